@@ -1,0 +1,119 @@
+"""Autoencoder evaluation and training in FP64 (Section III Stages 2-3, Eq. 5; Section IV-B).
+
+Dense model:  x = (f - mu) / sigma  (z-score per pixel, Section IV-C)
+              z = W2 relu(W1 x + b1) + b2                       (encoder, linear latent)
+              xhat = W4 relu(W3 z + b3) + b4,  fhat = sigma xhat + mu
+Tied linear model (the paper's own, Section IV-B): z = W x,  xhat = W^T z.
+Loss: MSE(X, Xhat), the mean over batch and pixels (Eq. 5).  Optimizer: Adam.
+Weights are stored [out][in] (y = x @ W.T + b).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def relu(x):
+    return np.maximum(x, 0.0)
+
+
+def norm_stats(F: np.ndarray, floor_rel: float = 1e-12):
+    """Per-pixel mean and population std over a batch (H, N); std floored at floor_rel*max std."""
+    X = np.asarray(F, np.float64).reshape(F.shape[0], -1)
+    mu = X.mean(axis=0)
+    sd = X.std(axis=0)
+    sd = np.maximum(sd, floor_rel * sd.max())
+    return mu, sd
+
+
+def _w(W, k):
+    return np.asarray(W[k], np.float64)
+
+
+def dense_encode(X: np.ndarray, W: dict) -> np.ndarray:
+    """X: normalised inputs (B, N) -> latent (B, L)."""
+    h1 = relu(X @ _w(W, "W1").T + _w(W, "b1"))
+    return h1 @ _w(W, "W2").T + _w(W, "b2")
+
+
+def dense_decode(Z: np.ndarray, W: dict) -> np.ndarray:
+    """Latent (B, L) -> normalised reconstruction (B, N)."""
+    h3 = relu(Z @ _w(W, "W3").T + _w(W, "b3"))
+    return h3 @ _w(W, "W4").T + _w(W, "b4")
+
+
+def normalize(F, mu, sd):
+    return (np.asarray(F, np.float64).reshape(F.shape[0], -1) - mu) / sd
+
+
+def denormalize(Xh, mu, sd):
+    return sd * Xh + mu
+
+
+def dense_forward_train(X: np.ndarray, W: dict):
+    """Full forward pass with the values the backward pass needs."""
+    a1 = X @ _w(W, "W1").T + _w(W, "b1")
+    h1 = relu(a1)
+    z = h1 @ _w(W, "W2").T + _w(W, "b2")
+    a3 = z @ _w(W, "W3").T + _w(W, "b3")
+    h3 = relu(a3)
+    xh = h3 @ _w(W, "W4").T + _w(W, "b4")
+    return dict(X=X, a1=a1, h1=h1, z=z, a3=a3, h3=h3, xh=xh)
+
+
+def mse(xh: np.ndarray, X: np.ndarray) -> float:
+    return float(np.mean((xh - X) ** 2))
+
+
+def dense_backward(cache: dict, W: dict) -> dict:
+    """Gradients of MSE(xhat, X) (mean over all B*N terms) w.r.t. every parameter."""
+    X, h1, z, h3, xh = cache["X"], cache["h1"], cache["z"], cache["h3"], cache["xh"]
+    B, N = X.shape
+    dxh = 2.0 * (xh - X) / (B * N)
+    g = {}
+    g["W4"] = dxh.T @ h3
+    g["b4"] = dxh.sum(axis=0)
+    dh3 = dxh @ _w(W, "W4")
+    da3 = dh3 * (cache["a3"] > 0)
+    g["W3"] = da3.T @ z
+    g["b3"] = da3.sum(axis=0)
+    dz = da3 @ _w(W, "W3")
+    g["W2"] = dz.T @ h1
+    g["b2"] = dz.sum(axis=0)
+    dh1 = dz @ _w(W, "W2")
+    da1 = dh1 * (cache["a1"] > 0)
+    g["W1"] = da1.T @ X
+    g["b1"] = da1.sum(axis=0)
+    return g
+
+
+def dense_loss(X: np.ndarray, W: dict) -> float:
+    return mse(dense_forward_train(X, W)["xh"], X)
+
+
+def tied_forward(X: np.ndarray, Wt: np.ndarray):
+    """The paper's tied linear AE: z = X W^T, xhat = z W (W is [L][N])."""
+    z = X @ Wt.T
+    return z, z @ Wt
+
+
+def tied_grad(X: np.ndarray, Wt: np.ndarray) -> np.ndarray:
+    z, xh = tied_forward(X, Wt)
+    B, N = X.shape
+    d = 2.0 * (xh - X) / (B * N)
+    # xhat = X W^T W: dL/dW = z^T d + (d W^T)^T X
+    return z.T @ d + (d @ Wt.T).T @ X
+
+
+def adam_step(params: dict, grads: dict, state: dict, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+    """One Adam update (Kingma & Ba) in place; `state` holds m, v and the step count t."""
+    t = state.get("t", 0) + 1
+    state["t"] = t
+    for k, gk in grads.items():
+        m = state.setdefault("m_" + k, np.zeros_like(gk))
+        v = state.setdefault("v_" + k, np.zeros_like(gk))
+        m[...] = b1 * m + (1 - b1) * gk
+        v[...] = b2 * v + (1 - b2) * gk * gk
+        mh = m / (1 - b1 ** t)
+        vh = v / (1 - b2 ** t)
+        params[k] = params[k] - lr * mh / (np.sqrt(vh) + eps)
+    return params

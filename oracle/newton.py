@@ -1,0 +1,153 @@
+"""QoI-restoring projection with Lagrange multipliers (Section III Stage 5, Eq. 6).
+
+Reading of the Stage-5 problem (the paper calls it a non-linear projection with a convex
+distance, linear moment constraints and a dual Newton method):
+
+    f_c = argmin_x  1/2 ||x - ft||^2   subject to  A x = b,  x >= 0
+
+with b the moments of the original histogram and ft the reconstruction.  Its dual
+theta(lam) = 1/2 ||x(lam) - ft||^2 + lam^T (A x(lam) - b), x(lam) = max(0, ft - A^T lam),
+is concave with gradient g = A x(lam) - b and Hessian -A diag(x > 0) A^T.  Eq. 6 is the
+Newton step on it with step size s: lam <- lam + s H^-1 g, H = A diag(x > 0) A^T.
+
+Stopping rule: |g_k| <= 1e-13 * (sum_j |A_kj| x_j + 1e-300) for every k.
+Round 1: s = 1, at most 50 updates (Section III Stage 5).  Round 2 (for histograms
+round 1 leaves unconverged): from the round-1 multipliers, either Armijo backtracking
+on theta (default) or the fixed step s = 0.01, both with at most 400 updates.  A
+histogram that still fails is stored verbatim.  A Cholesky pivot <= 1e-14 trace(H)
+counts as failure.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .grid import Grid
+
+GTOL = 1e-13
+PIVTOL = 1e-14
+ARMIJO_C = 1e-4
+ARMIJO_HALVINGS = 40
+
+
+def x_of(ft: np.ndarray, A: np.ndarray, lam: np.ndarray) -> np.ndarray:
+    return np.maximum(0.0, ft - A.T @ lam)
+
+
+def cholesky_solve(Hm: np.ndarray, g: np.ndarray):
+    """Solve Hm d = g for a 4x4 SPD matrix; None if a pivot is not clearly positive."""
+    n = Hm.shape[0]
+    tr = np.trace(Hm)
+    Lm = np.zeros_like(Hm)
+    for k in range(n):
+        piv = Hm[k, k] - np.dot(Lm[k, :k], Lm[k, :k])
+        if not (piv > PIVTOL * tr):
+            return None
+        Lm[k, k] = np.sqrt(piv)
+        for i in range(k + 1, n):
+            Lm[i, k] = (Hm[i, k] - np.dot(Lm[i, :k], Lm[k, :k])) / Lm[k, k]
+    y = np.zeros(n)
+    for i in range(n):
+        y[i] = (g[i] - np.dot(Lm[i, :i], y[:i])) / Lm[i, i]
+    d = np.zeros(n)
+    for i in range(n - 1, -1, -1):
+        d[i] = (y[i] - np.dot(Lm[i + 1:, i], d[i + 1:])) / Lm[i, i]
+    return d
+
+
+def theta(ft, A, b, lam):
+    x = x_of(ft, A, lam)
+    return 0.5 * np.dot(x - ft, x - ft) + np.dot(lam, A @ x - b)
+
+
+def converged(g, A, x):
+    sc = np.abs(A) @ x + 1e-300
+    return bool(np.all(np.abs(g) <= GTOL * sc))
+
+
+def newton_round(ft, A, b, lam, s, max_iter, mode):
+    """mode: 'fixed' (step s) or 'armijo'. Returns (lam, converged, updates)."""
+    lam = np.array(lam, np.float64)
+    for it in range(max_iter + 1):
+        x = x_of(ft, A, lam)
+        g = A @ x - b
+        if converged(g, A, x):
+            return lam, True, it
+        if it == max_iter:
+            return lam, False, it
+        m = x > 0
+        Hm = (A * m) @ A.T
+        d = cholesky_solve(Hm, g)
+        if d is None:
+            return lam, False, it
+        if mode == "fixed":
+            lam = lam + s * d
+        else:
+            t0 = theta(ft, A, b, lam)
+            gd = float(np.dot(g, d))
+            step = 1.0
+            for _ in range(ARMIJO_HALVINGS):
+                cand = lam + step * d
+                if theta(ft, A, b, cand) >= t0 + ARMIJO_C * step * gd:
+                    break
+                step *= 0.5
+            else:
+                return lam, False, it
+            lam = cand
+    return lam, False, max_iter
+
+
+def project(ft: np.ndarray, b: np.ndarray, g: Grid, s: float = 1.0, max_iter: int = 50,
+            max_iter2: int = 400, fallback: str = "backtrack", lam0=None):
+    """Project one reconstruction ft (n_perp, n_par) onto {A x = b, x >= 0}.
+
+    Returns dict(lam, x, status, iters): status 0 = round 1 converged, 1 = round 2
+    converged, 2 = failed (store verbatim).
+    """
+    A = g.A()
+    ftv = np.asarray(ft, np.float64).reshape(-1)
+    lam = np.zeros(4) if lam0 is None else np.asarray(lam0, np.float64)
+    lam1, ok, it1 = newton_round(ftv, A, b, lam, s, max_iter, "fixed")
+    if ok:
+        return dict(lam=lam1, x=x_of(ftv, A, lam1).reshape(ft.shape), status=0, iters=it1)
+    mode = "fixed" if fallback == "paper" else "armijo"
+    s2 = 0.01 if fallback == "paper" else 1.0
+    lam2, ok2, it2 = newton_round(ftv, A, b, lam1, s2, max_iter2, mode)
+    if ok2:
+        return dict(lam=lam2, x=x_of(ftv, A, lam2).reshape(ft.shape), status=1, iters=it1 + it2)
+    return dict(lam=np.zeros(4), x=None, status=2, iters=it1 + it2)
+
+
+def apply(ft: np.ndarray, lam: np.ndarray, g: Grid) -> np.ndarray:
+    """Decompression-side correction f_c = max(0, ft - A^T lam) for one histogram."""
+    return x_of(np.asarray(ft, np.float64).reshape(-1), g.A(), np.asarray(lam, np.float64)).reshape(ft.shape)
+
+
+def project_bruteforce(ft: np.ndarray, b: np.ndarray, g: Grid):
+    """Exact KKT point by enumerating every active set (tiny grids only).
+
+    For each set Z of cells fixed at zero, solve the equality-constrained projection on
+    the free cells and keep the candidate that is primal feasible (x >= 0) and dual
+    feasible (the multipliers of x >= 0 are >= 0).
+    """
+    A = g.A()
+    f = np.asarray(ft, np.float64).reshape(-1)
+    N = f.size
+    best = None
+    for mask in range(1 << N):
+        free = np.array([(mask >> k) & 1 == 0 for k in range(N)])
+        Af = A[:, free]
+        M = Af @ Af.T
+        if np.linalg.matrix_rank(M) < 4:
+            continue
+        lam = np.linalg.solve(M, Af @ f[free] - b)
+        x = np.zeros(N)
+        x[free] = f[free] - Af.T @ lam
+        if np.any(x[free] < -1e-12):
+            continue
+        mu = -(f[~free] - A[:, ~free].T @ lam)     # multipliers of x >= 0 on the fixed set
+        if np.any(mu < -1e-12):
+            continue
+        cand = (np.linalg.norm(x - f), x, lam)
+        if best is None or cand[0] < best[0]:
+            best = cand
+    return None if best is None else dict(x=best[1].reshape(ft.shape), lam=best[2])

@@ -1,0 +1,155 @@
+"""Compress / decompress of a batch of histograms (Section III, Fig. 1).
+
+Compress, per histogram (FP64):
+  1. widen the input; non-finite input or b0 <= 0 is stored verbatim;
+  2. b = A f (true moments, Eq. 1-4);
+  3. tau_h = tau ||f||_2 (relative L2) or tau sqrt(N) (max f - min f) (Eq. 7 per image);
+  4. z = encoder(f), codes = PQ(z), fhat = decoder(codebook[codes]) (Stages 2-3);
+     without a model fhat = 0 (the MGARD-only pipeline the paper compares against);
+  5. r = f - fhat; coded iff ||r||^2 > thr^2, thr = (1 - 2^-20) tau_h (Stage 4 selection);
+  6. coded: multilevel coefficients, bound bisection, record (Stage 4);
+  7. ft = fhat + rhat; Newton projection onto A x = b, x >= 0 (Stage 5);
+  8. outputs: codes, multipliers, flags, residual records.
+Decompress: fhat from the codes, rhat from the record, ft = fhat + rhat,
+f_c = max(0, ft - A^T lam); verbatim records are returned as stored.
+
+Flags: bit0 coder record, bit1 round-2 Newton used, bit2 verbatim record.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import ae, coder, newton, pq
+from .grid import Grid
+from .moments import moments
+
+FLAG_CODED, FLAG_ROUND2, FLAG_RAW = 1, 2, 4
+
+
+@dataclass
+class Params:
+    tau: float = 1e-3
+    tau_mode: str = "rel_l2"        # or "nrmse"
+    newton_s: float = 1.0
+    newton_max_iter: int = 50
+    newton_max_iter2: int = 400
+    fallback: str = "backtrack"     # or "paper" (s = 0.01)
+
+
+def tau_h(F64: np.ndarray, p: Params) -> np.ndarray:
+    H = F64.shape[0]
+    X = F64.reshape(H, -1)
+    if p.tau_mode == "nrmse":
+        return p.tau * math.sqrt(X.shape[1]) * (X.max(axis=1) - X.min(axis=1))
+    return np.array([p.tau * math.sqrt(math.fsum(x * x)) for x in X])
+
+
+def reconstruct_ae(codes: np.ndarray, C: np.ndarray, model: dict, shape) -> np.ndarray:
+    Zh = pq.decode(codes, C)
+    Xh = ae.dense_decode(Zh, model["W"])
+    return ae.denormalize(Xh, model["mu"], model["sd"]).reshape(shape)
+
+
+def compress(F: np.ndarray, g: Grid, model: dict | None, C: np.ndarray | None, p: Params,
+             fit_codebook: bool = False, bits: int = 8, sample_every: int = 16) -> dict:
+    H = F.shape[0]
+    F64 = np.asarray(F, np.float64).reshape(H, g.n_perp, g.n_par)
+    lay = coder.layout(g.n_par, g.n_perp)
+    finite = np.isfinite(F64).reshape(H, -1).all(axis=1)
+    Fz = np.where(finite[:, None, None], F64, 0.0)
+    b = moments(Fz, g)
+    th = tau_h(Fz, p)
+    L = model["W"]["W2"].shape[0] if model else 0
+    codes = np.zeros((H, L), np.uint8)
+    Z = None
+    if model is not None:
+        Z = ae.dense_encode(ae.normalize(Fz, model["mu"], model["sd"]), model["W"])
+        if fit_codebook:
+            C = pq.fit(Z, bits, sample_every)
+        codes = pq.encode(Z, C)
+        fhat = reconstruct_ae(codes, C, model, F64.shape)
+    else:
+        fhat = np.zeros_like(F64)
+    r = Fz - fhat
+    thr = coder.SEL_MARGIN * th
+    coded = coder.sumsq(r) > thr * thr
+    raw = ~finite | ~(b[:, 0] > 0) | (coded & ~(th > 0))
+    kstar = np.zeros(H, np.int64)
+    q = np.zeros(F64.shape, np.int64)
+    rhat = np.zeros_like(F64)
+    d0 = coder.delta0(th, lay)
+    act = coded & ~raw
+    if act.any():
+        d = coder.decompose(r[act], lay)
+        big = np.abs(d).reshape(d.shape[0], -1).max(axis=1) * (1.0 / d0[act]) >= coder.QMAX
+        idx = np.nonzero(act)[0]
+        raw[idx[big]] = True
+        act = coded & ~raw
+        keep = ~big
+        if keep.any():
+            ks, qs, rh = coder.bisect(r[act], d[keep], d0[act], thr[act], lay)
+            kstar[act], q[act], rhat[act] = ks, qs, rh
+    ft = fhat + rhat
+    lam = np.zeros((H, 4))
+    flags = np.zeros(H, np.uint8)
+    iters = np.zeros(H, np.int64)
+    fc = np.zeros_like(F64)
+    for h in range(H):
+        if raw[h]:
+            continue
+        res = newton.project(ft[h], b[h], g, p.newton_s, p.newton_max_iter, p.newton_max_iter2,
+                             p.fallback)
+        iters[h] = res["iters"]
+        if res["status"] >= 1:
+            flags[h] |= FLAG_ROUND2
+        if res["status"] == 2:
+            raw[h] = True
+            continue
+        lam[h] = res["lam"]
+        fc[h] = res["x"]
+    records = []
+    for h in range(H):
+        if raw[h]:
+            flags[h] = (flags[h] & FLAG_ROUND2) | FLAG_RAW
+            records.append(np.ascontiguousarray(np.asarray(F)[h]).tobytes())
+            fc[h] = F64[h]
+            lam[h] = 0.0
+        elif act[h]:
+            flags[h] |= FLAG_CODED
+            records.append(coder.pack(q[h], coder.ladder(d0[h:h + 1], kstar[h:h + 1])[0],
+                                      int(kstar[h]), lay))
+        else:
+            records.append(b"")
+    sizes = np.array([len(x) for x in records], np.uint64)
+    offsets = np.zeros(H + 1, np.uint64)
+    offsets[1:] = np.cumsum(sizes)
+    return dict(codes=codes, lam=lam, flags=flags, stream=b"".join(records), offsets=offsets,
+                codebook=C, b=b, tau_h=th, z=Z, fhat=fhat, rhat=rhat, ft=ft, fc=fc, kstar=kstar,
+                iters=iters)
+
+
+def decompress(comp: dict, g: Grid, model: dict | None, C: np.ndarray | None, H: int,
+               in_dtype=np.float32) -> np.ndarray:
+    lay = coder.layout(g.n_par, g.n_perp)
+    shape = (H, g.n_perp, g.n_par)
+    if model is not None:
+        fhat = reconstruct_ae(comp["codes"], C, model, shape)
+    else:
+        fhat = np.zeros(shape)
+    out = np.zeros(shape)
+    stream, off = comp["stream"], comp["offsets"]
+    for h in range(H):
+        rec = stream[int(off[h]):int(off[h + 1])]
+        fl = comp["flags"][h]
+        if fl & FLAG_RAW:
+            out[h] = np.frombuffer(rec, dtype=in_dtype).reshape(g.n_perp, g.n_par)
+            continue
+        ft = fhat[h].copy()
+        if fl & FLAG_CODED:
+            qh, Delta, _ = coder.unpack(rec, lay)
+            ft = fhat[h] + coder.reconstruct(qh[None], np.array([Delta]), lay)[0]
+        out[h] = newton.apply(ft, comp["lam"][h], g)
+    return out

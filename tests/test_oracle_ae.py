@@ -1,0 +1,109 @@
+"""Pins of the oracle's autoencoder (Section III Stages 2-3, Eq. 5): library routines,
+finite differences and the PCA optimum of a tied linear AE."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import ae
+from paper_2212_10733_amd import synth
+
+
+def small_weights(N=50, hidden=12, latent=4, seed=3):
+    W = synth.dense_ae_weights(N, hidden, latent, seed=seed)
+    rng = np.random.default_rng(seed)
+    for k in ("b1", "b2", "b3", "b4"):   # non-zero biases so they are exercised
+        W[k] = rng.normal(0, 0.1, W[k].shape).astype(np.float32)
+    return W
+
+
+def test_forward_matches_torch_linear():
+    W = small_weights()
+    X = np.random.default_rng(0).normal(size=(7, 50))
+    t = {k: torch.tensor(v, dtype=torch.float64) for k, v in W.items()}
+    x = torch.tensor(X)
+    h = torch.relu(torch.nn.functional.linear(x, t["W1"], t["b1"]))
+    z = torch.nn.functional.linear(h, t["W2"], t["b2"])
+    h3 = torch.relu(torch.nn.functional.linear(z, t["W3"], t["b3"]))
+    xh = torch.nn.functional.linear(h3, t["W4"], t["b4"])
+    assert np.allclose(ae.dense_encode(X, W), z.numpy(), rtol=1e-13, atol=1e-13)
+    assert np.allclose(ae.dense_decode(z.numpy(), W), xh.numpy(), rtol=1e-13, atol=1e-13)
+
+
+def test_backward_matches_autograd_and_finite_differences():
+    W = {k: v.astype(np.float64) for k, v in small_weights().items()}
+    X = np.random.default_rng(1).normal(size=(5, 50))
+    g = ae.dense_backward(ae.dense_forward_train(X, W), W)
+    t = {k: torch.tensor(v, requires_grad=True) for k, v in W.items()}
+    x = torch.tensor(X)
+    h = torch.relu(x @ t["W1"].T + t["b1"])
+    z = h @ t["W2"].T + t["b2"]
+    h3 = torch.relu(z @ t["W3"].T + t["b3"])
+    xh = h3 @ t["W4"].T + t["b4"]
+    torch.nn.functional.mse_loss(xh, x).backward()
+    for k in W:
+        assert np.allclose(g[k], t[k].grad.numpy(), rtol=1e-10, atol=1e-13), k
+    rng = np.random.default_rng(2)
+    eps = 1e-6
+    for k in W:
+        for _ in range(3):
+            idx = tuple(rng.integers(0, s) for s in W[k].shape)
+            Wp = {kk: vv.copy() for kk, vv in W.items()}
+            Wm = {kk: vv.copy() for kk, vv in W.items()}
+            Wp[k][idx] += eps
+            Wm[k][idx] -= eps
+            fd = (ae.dense_loss(X, Wp) - ae.dense_loss(X, Wm)) / (2 * eps)
+            assert fd == pytest.approx(g[k][idx], rel=1e-5, abs=1e-9), (k, idx)
+
+
+def test_tied_linear_ae_recovers_pca_subspace():
+    # Baldi & Hornik: the MSE optimum of a linear AE spans the top principal subspace.
+    rng = np.random.default_rng(4)
+    N, L, B = 20, 4, 400
+    basis, _ = np.linalg.qr(rng.normal(size=(N, L)))
+    X = (rng.normal(size=(B, L)) * np.array([3.0, 2.0, 1.5, 1.0])) @ basis.T
+    Wt = rng.normal(0, 0.1, size=(L, N))
+    params, state = {"W": Wt}, {}
+    for _ in range(4000):
+        ae.adam_step(params, {"W": ae.tied_grad(X, params["W"])}, state, lr=1e-2)
+    Q, _ = np.linalg.qr(params["W"].T)
+    s = np.linalg.svd(basis.T @ Q, compute_uv=False)
+    assert s.min() > 1 - 1e-6          # cosines of the principal angles
+    z, xh = ae.tied_forward(X, params["W"])
+    assert ae.mse(xh, X) < 1e-8
+
+
+def test_tied_grad_finite_differences():
+    rng = np.random.default_rng(5)
+    X = rng.normal(size=(6, 9))
+    Wt = rng.normal(size=(3, 9))
+    gr = ae.tied_grad(X, Wt)
+    loss = lambda W: ae.mse(ae.tied_forward(X, W)[1], X)
+    for idx in [(0, 0), (1, 4), (2, 8)]:
+        Wp, Wm = Wt.copy(), Wt.copy()
+        Wp[idx] += 1e-6
+        Wm[idx] -= 1e-6
+        assert (loss(Wp) - loss(Wm)) / 2e-6 == pytest.approx(gr[idx], rel=1e-6)
+
+
+def test_adam_matches_torch():
+    rng = np.random.default_rng(6)
+    p = {"w": rng.normal(size=(4, 3))}
+    tw = torch.tensor(p["w"].copy(), requires_grad=True)
+    opt = torch.optim.Adam([tw], lr=1e-3)
+    state = {}
+    for step in range(5):
+        gr = rng.normal(size=(4, 3))
+        ae.adam_step(p, {"w": gr}, state, lr=1e-3)
+        tw.grad = torch.tensor(gr)
+        opt.step()
+    assert np.allclose(p["w"], tw.detach().numpy(), rtol=1e-12, atol=1e-14)
+
+
+def test_norm_stats():
+    F = np.random.default_rng(7).random((100, 3, 4))
+    F[:, 0, 0] = 2.0                       # constant pixel -> floored std
+    mu, sd = ae.norm_stats(F)
+    X = F.reshape(100, -1)
+    assert np.allclose(mu, X.mean(0))
+    assert sd[0] == pytest.approx(1e-12 * X.std(0).max())
+    assert np.allclose(sd[1:], X.std(0)[1:])

@@ -1,0 +1,100 @@
+"""Whole-pipeline properties of the oracle (Section III): bound, QoIs, edge cases."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import coder, grid, moments, pipeline
+from paper_2212_10733_amd import synth
+
+
+def make_model(F, N=1521):
+    W = synth.dense_ae_weights(N)
+    mu, sd = oracle.ae.norm_stats(F)
+    return dict(W=W, mu=mu, sd=sd)
+
+
+def check_bound_and_qoi(F, out, comp, g, tau):
+    F64 = F.astype(np.float64)
+    err = np.sqrt(((out - F64) ** 2).sum((1, 2)))
+    th = comp["tau_h"]
+    raw = (comp["flags"] & pipeline.FLAG_RAW) != 0
+    assert np.all(err[~raw] <= th[~raw])
+    assert np.all(out[raw] == F64[raw])
+    q0 = moments.qoi(F64, g)
+    q1 = moments.qoi(out, g)
+    assert moments.qoi_rel_error(q0, q1, g).max() < 1e-10
+
+
+@pytest.mark.parametrize("use_model", [True, False])
+@pytest.mark.parametrize("tau", [1e-2, 1e-3])
+def test_roundtrip_bound_and_qoi(use_model, tau):
+    g = grid.make_grid()
+    F = synth.histograms(12, seed=1, dtype=np.float64)
+    model = make_model(F) if use_model else None
+    comp = pipeline.compress(F, g, model, None, pipeline.Params(tau=tau), fit_codebook=use_model,
+                             sample_every=1, bits=3)
+    out = pipeline.decompress(comp, g, model, comp["codebook"], 12, np.float64)
+    check_bound_and_qoi(F, out, comp, g, tau)
+    assert np.array_equal(out, comp["fc"])
+    assert int(comp["offsets"][-1]) == len(comp["stream"])
+
+
+def test_nrmse_mode_and_fp32_input():
+    g = grid.make_grid()
+    F = synth.histograms(6, seed=2, dtype=np.float32)
+    comp = pipeline.compress(F, g, None, None, pipeline.Params(tau=1e-3, tau_mode="nrmse"))
+    out = pipeline.decompress(comp, g, None, None, 6, np.float32)
+    check_bound_and_qoi(F, out, comp, g, 1e-3)
+    X = F.reshape(6, -1).astype(np.float64)
+    assert np.allclose(comp["tau_h"], 1e-3 * 39 * (X.max(1) - X.min(1)))
+
+
+def test_edge_cases_go_verbatim():
+    g = grid.make_grid()
+    F = synth.histograms(5, seed=3, dtype=np.float64)
+    F[0, 3, 4] = np.nan              # non-finite input
+    F[1] = 0.0                        # empty histogram (n = 0)
+    comp = pipeline.compress(F, g, None, None, pipeline.Params(tau=1e-3))
+    assert comp["flags"][0] == pipeline.FLAG_RAW and comp["flags"][1] == pipeline.FLAG_RAW
+    out = pipeline.decompress(comp, g, None, None, 5, np.float64)
+    assert np.isnan(out[0, 3, 4]) and np.all(out[1] == 0)
+    assert np.all(comp["flags"][2:] == pipeline.FLAG_CODED)
+
+
+def test_tau_zero_is_lossless():
+    g = grid.make_grid()
+    F = synth.histograms(3, seed=4, dtype=np.float64)
+    comp = pipeline.compress(F, g, None, None, pipeline.Params(tau=0.0))
+    assert np.all(comp["flags"] == pipeline.FLAG_RAW)
+    out = pipeline.decompress(comp, g, None, None, 3, np.float64)
+    assert np.array_equal(out, F)
+
+
+def test_forced_newton_failure_goes_round2_then_verbatim():
+    g = grid.make_grid()
+    F = synth.histograms(3, seed=5, dtype=np.float64)
+    comp = pipeline.compress(F, g, None, None, pipeline.Params(tau=1e-2, newton_max_iter=0, newton_max_iter2=0))
+    assert np.all(comp["flags"] == pipeline.FLAG_RAW | pipeline.FLAG_ROUND2)
+
+
+def test_uncoded_when_reconstruction_is_good():
+    g = grid.make_grid()
+    F = synth.histograms(4, seed=6, dtype=np.float64)
+    model = make_model(F)
+    comp = pipeline.compress(F, g, model, None, pipeline.Params(tau=100.0), fit_codebook=True,
+                             sample_every=1, bits=2)
+    assert np.all(comp["flags"] == 0) and len(comp["stream"]) == 0
+    out = pipeline.decompress(comp, g, model, comp["codebook"], 4, np.float64)
+    check_bound_and_qoi(F, out, comp, g, 100.0)
+
+
+def test_record_layout_in_stream():
+    g = grid.make_grid()
+    F = synth.histograms(3, seed=7, dtype=np.float64)
+    comp = pipeline.compress(F, g, None, None, pipeline.Params(tau=1e-3))
+    lay = coder.layout(39, 39)
+    for h in range(3):
+        rec = comp["stream"][int(comp["offsets"][h]):int(comp["offsets"][h + 1])]
+        q, Delta, k = coder.unpack(rec, lay)
+        assert k == comp["kstar"][h]
+        assert Delta == coder.ladder(coder.delta0(comp["tau_h"][h:h + 1], lay), np.array([k]))[0]
