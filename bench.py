@@ -1,0 +1,187 @@
+"""Throughput of the hybrid compressor's hot path on one MI355X.
+
+Workload (plain method at scale): 1,048,576 synthetic 39x39 FP32 histograms (6.38 GB),
+dense FP32 autoencoder 1521-128-16-128-1521 with seeded Xavier weights, 8-bit product
+quantizer fitted per batch on every 16th latent vector, per-histogram relative-L2 bound
+tau = 1e-3, FP64 residual coder and Newton QoI correction.  One step = one hcz_compress
+call (encode, codebook fit, quantize, decode, residual coding, Newton, stream assembly)
+with the input already resident in HBM.
+
+Prints one JSON line.  `--gpus N` with N > 1 is refused: this build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+PEAK_FP32_MFMA_TFLOPS = 157.3
+PEAK_FP64_VALU_TFLOPS = 78.6
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def residual_flops(N: int, H: int, coded: int, steps_per_coded: float, newton_passes: float) -> float:
+    """FP64 operations of the residual stage, FMA counted as 2 (per element
+    12 for the load pass, 10 for the decomposition, 15 per bisection step, 2 for packing,
+    26 per Newton pass)."""
+    per_elem = 12.0 * H + coded * (10.0 + 15.0 * steps_per_coded + 2.0) + 26.0 * newton_passes
+    return per_elem * N
+
+
+def cpu_baseline(F: np.ndarray, W: dict, mu, sd, tau: float, n: int) -> dict:
+    from threadpoolctl import threadpool_limits
+
+    import oracle
+    from oracle import grid, pipeline
+    g = grid.make_grid()
+    model = dict(W=W, mu=mu.astype(np.float64), sd=sd.astype(np.float64))
+    sample = F[:n]
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        pipeline.compress(sample, g, model, None, pipeline.Params(tau=tau), fit_codebook=True,
+                          bits=8, sample_every=16)
+        dt = time.perf_counter() - t0
+    return {"value": n / dt, "unit": "histograms/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {n} histograms of the same batch, full compress (encode, codebook fit on "
+                      f"every 16th, quantize, decode, coder, Newton), NumPy FP64, 1 thread, {dt:.1f} s"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--H", type=int, default=1 << 20)
+    ap.add_argument("--tau", type=float, default=1e-3)
+    ap.add_argument("--cpu-sample", type=int, default=768)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on exactly one GPU: the per-histogram path needs no communication, "
+              "and multi-GPU runs are not part of this build.", file=sys.stderr)
+        return 2
+
+    import torch
+
+    from paper_2212_10733_amd import hcz, synth
+
+    H = args.H
+    log(f"generating {H} histograms")
+    t0 = time.perf_counter()
+    F = synth.histograms(H, seed=synth.SEED_PLAIN_LARGE, dtype=np.float32)
+    W = synth.dense_ae_weights()
+    log(f"generated in {time.perf_counter() - t0:.1f} s")
+    x = torch.from_numpy(F).cuda()
+    # model preparation (outside the hot path): z-score statistics of the batch
+    xf = x.reshape(H, -1).double()
+    mu = xf.mean(0)
+    sd = xf.std(0, unbiased=False)
+    sd = torch.clamp(sd, min=1e-12 * sd.max().item())
+    mu, sd = mu.float().cpu().numpy(), sd.float().cpu().numpy()
+    del xf
+
+    ctx = hcz.Context(0)
+    plan = hcz.Plan(ctx)
+    model = hcz.Model(plan, W, mu, sd)
+    p = hcz.params(tau=args.tau, fit_codebook=True, sample_every=16)
+    cz = hcz.Compressor(plan, model, H, p, bits=8)
+    torch.cuda.synchronize()
+    log("warmup")
+    for _ in range(args.warmup):
+        cz.compress(x)
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    ctx.profile_read()
+    log(f"timing {args.steps} steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        comp = cz.compress(x)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    st = comp.stats()
+    ms_step = dt / args.steps * 1e3
+    value = H / (dt / args.steps)
+    log(f"{ms_step:.3f} ms/step, {value:.4g} hist/s")
+
+    # per-stage live timing (HIP events on the compress stream)
+    stage_ms = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in prof.items() if v[1]}
+    N = plan.N
+    coded = st["n_coded"]
+    steps_coded = 6.0
+    passes = st["newton_iters_total"] + (H - st["n_raw"])
+    ae_flops = 2.0 * H * N * 128 + 2.0 * H * 128 * 16
+    cands = {
+        "encode": ("mfma", ae_flops / 1e12, PEAK_FP32_MFMA_TFLOPS, "TFLOP/s"),
+        "decode": ("mfma", ae_flops / 1e12, PEAK_FP32_MFMA_TFLOPS, "TFLOP/s"),
+        "residual": ("alu", residual_flops(N, H, coded, steps_coded, passes) / 1e12, PEAK_FP64_VALU_TFLOPS, "TFLOP/s"),
+    }
+    dom = max(cands, key=lambda k: stage_ms.get(k, 0.0))
+    bound, work, peak, unit = cands[dom]
+    achieved = work / (stage_ms[dom] / 1e3)
+    roofline = {"bound": bound, "kernel": dom, "achieved": achieved, "peak": peak, "unit": unit,
+                "frac": achieved / peak, "traffic": None}
+    stream_bytes = st["stream_bytes"]
+    alg_bytes = H * (4 * N + 16 + 32 + 1 + 8) + stream_bytes
+    extra = {
+        "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
+        "stage_roofline": {k: {"bound": c[0], "achieved": c[1] / (stage_ms[k] / 1e3), "peak": c[2],
+                               "frac": c[1] / (stage_ms[k] / 1e3) / c[2]} for k, c in cands.items() if k in stage_ms},
+        "hbm_whole_step": {"alg_bytes": alg_bytes, "GB/s": alg_bytes / (dt / args.steps) / 1e9,
+                           "frac": alg_bytes / (dt / args.steps) / 1e9 / PEAK_HBM_GBS},
+        "coded_frac": coded / H, "raw": st["n_raw"], "round2": st["n_round2"],
+        "newton_mean_updates": st["newton_iters_total"] / max(1, H - st["n_raw"]),
+        "newton_max_updates": st["newton_max_iters"],
+        "stream_bytes": stream_bytes,
+        "compression_ratio": (H * N * 4) / (H * 16 + H * 32 + H + stream_bytes + 395265 * 4 + 16 * 256 * 4 + 44),
+    }
+    # QoI restoration and the bound, checked on the whole batch after the timed region
+    out = cz.decompress(comp, H, in_dtype=torch.float32, out_dtype=torch.float64)
+    _, q0, n0 = hcz.qoi(plan, x)
+    _, q1, _ = hcz.qoi(plan, out)
+    den = torch.stack([q0[:, 0].abs(), torch.maximum(q0[:, 1].abs(), q0[:, 3].abs().sqrt()),
+                       q0[:, 2].abs(), q0[:, 3].abs()], 1)
+    flags = comp.flags
+    ok = (flags & 4) == 0
+    qerr = ((q1 - q0).abs() / den)[ok].max().item()
+    dist = (out - x.double()).reshape(H, -1).norm(dim=1)
+    bound_ratio = (dist[ok] / (args.tau * n0[ok])).max().item()
+    extra["max_qoi_rel_err"] = qerr
+    extra["max_err_over_tau_h"] = bound_ratio
+    del out
+
+    cpu = None
+    if not args.no_cpu:
+        log(f"cpu baseline on {args.cpu_sample} histograms")
+        cpu = cpu_baseline(F, W, mu, sd, args.tau, args.cpu_sample)
+
+    line = {
+        "metric": "histograms/s (compress+QoI-correct)", "value": value, "unit": "histograms/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "fp32+fp64",
+        "data": "synthetic",
+        "config": {"workload": "plain method at scale: 1048576 x 39x39 FP32 histograms, dense FP32 AE "
+                               "1521-128-16 (Xavier), 8-bit PQ fitted per batch, tau=1e-3 rel-L2, FP64 coder + Newton",
+                   "H": H, "grid": "39x39", "tau": args.tau, "tau_mode": "rel_l2", "pq_bits": 8,
+                   "sample_every": 16},
+        "roofline": roofline, "cpu_baseline": cpu, **extra,
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,245 @@
+/*
+ * hcz.h - C ABI of libhcz, the MI355X (gfx950) implementation of the per-histogram hot
+ * path of the hybrid compressor of Banerjee et al., "Scalable Hybrid Learning Techniques
+ * for Scientific Data Compression" (arXiv 2212.10733).
+ *
+ * Pipeline (paper Section III, Fig. 1), per velocity-space histogram f[j][i]
+ * (j = v_perp row, i = v_par column):
+ *   moments b = A f                     (Section II, Eq. 1-4)
+ *   encode z = encoder((f - mu) / sigma) (Stages 2-3)
+ *   quantize codes = PQ(z)               (Stage 3, Section IV-E)
+ *   decode fhat = sigma decoder(C[codes]) + mu
+ *   residual r = f - fhat, coded under a per-histogram bound tau_h by a multilevel coder
+ *   with a bisection over its quantisation ladder (Stage 4)
+ *   Newton projection of ft = fhat + rhat onto {A x = b, x >= 0}; 4 multipliers lambda
+ *   per histogram (Stage 5, Eq. 6)
+ * Decompress rebuilds ft and applies f_c = max(0, ft - A^T lambda).
+ *
+ * Conventions
+ *   - Pointers are device pointers unless marked (host).  Every call that takes a
+ *     hipStream_t enqueues work on that stream and returns without synchronising,
+ *     except hcz_stats_read, which synchronises the stream.
+ *   - Buffers passed in are owned by the caller; the library never frees them.  Objects
+ *     created by hcz_*_create / hcz_model_load own device memory of their own and are
+ *     released by the matching destroy/free call.
+ *   - Every entry point returns an hcz_status.  Argument errors are detected before any
+ *     launch; a failed HIP call returns HCZ_EHIP.  hcz_last_error() gives the message of
+ *     the calling thread's last failure.  No C++ exception crosses this interface.
+ *   - Data-dependent outcomes (verbatim records, Newton fallbacks) are not errors: they
+ *     are reported in the per-histogram flags and in hcz_stats.
+ *   - A context is bound to one device; calls on one context may come from one host
+ *     thread at a time.  Calls that overlap on one stream are ordered by the stream.
+ */
+#ifndef HCZ_H
+#define HCZ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t* hcz_stream_t;   /* a hipStream_t; NULL = the null stream */
+
+typedef enum {
+  HCZ_OK = 0,
+  HCZ_EINVAL = -1,        /* bad argument (null pointer, size, mode, shape mismatch) */
+  HCZ_ENOMEM = -2,        /* library-owned allocation failed */
+  HCZ_EHIP = -3,          /* a HIP runtime call failed */
+  HCZ_EUNSUPPORTED = -4,  /* valid request this build does not implement */
+  HCZ_ECAPACITY = -5,     /* residual stream larger than the caller's capacity */
+  HCZ_EWORKSPACE = -6     /* workspace smaller than the size query returned */
+} hcz_status;
+
+enum { HCZ_F32 = 0, HCZ_F64 = 1 };                       /* element types */
+enum { HCZ_ARCH_DENSE = 1 };                              /* autoencoder architectures */
+enum { HCZ_TAU_REL_L2 = 0, HCZ_TAU_NRMSE = 1 };          /* tau_h = tau ||f||, tau sqrt(N)(max-min) */
+enum { HCZ_FALLBACK_BACKTRACK = 0, HCZ_FALLBACK_PAPER = 1 };
+enum { HCZ_FLAG_CODED = 1, HCZ_FLAG_ROUND2 = 2, HCZ_FLAG_RAW = 4 };
+
+typedef struct hcz_ctx hcz_ctx;
+typedef struct hcz_plan hcz_plan;
+typedef struct hcz_model hcz_model;
+
+/* Velocity grid (Section II).  v_par_i = vpar_lo + i (vpar_hi - vpar_lo)/(n_par - 1),
+ * likewise v_perp_j.  vol (host, [n_perp][n_par], copied) gives the cell volumes of
+ * Eq. 1-4; NULL means dv_par * dv_perp for every cell.  mass is m of Eq. 3-4.
+ * Supported sizes: 3 <= n_par, n_perp <= 128 and n_par * n_perp <= 4608. */
+typedef struct {
+  int32_t n_par, n_perp;
+  double vpar_lo, vpar_hi, vperp_lo, vperp_hi;
+  double mass;
+  const double* vol;
+} hcz_grid;
+
+/* Dense autoencoder N -> hidden -> latent -> hidden -> N, ReLU after each hidden layer,
+ * linear latent and output (Stage 2).  weights (host, FP32, copied) holds
+ * W1[hidden][N], b1[hidden], W2[latent][hidden], b2[latent], W3[hidden][latent],
+ * b3[hidden], W4[N][hidden], b4[N] back to back (y = x W^T + b).  norm_mean and
+ * norm_std (host, [N]) are the per-pixel z-score statistics (Section IV-C).
+ * Supported: hidden = 128, latent = 16. */
+typedef struct {
+  int32_t arch;
+  int32_t latent, hidden;
+  const float* weights;
+  const float* norm_mean;
+  const float* norm_std;
+} hcz_model_desc;
+
+/* Product-quantizer codebook (Section III Stage 3): centroids [latent][1 << bits]
+ * (device, FP32), sorted within each latent dimension.  1 <= bits <= 8. */
+typedef struct {
+  int32_t bits;
+  float* centroids;
+} hcz_codebook;
+
+/* Compression parameters.
+ * tau, tau_mode    per-histogram bound tau_h (tau >= 0; tau = 0 makes every histogram
+ *                  that needs a residual a verbatim record)
+ * newton_s         Eq. 6 step size of round 1 (paper default 1.0)
+ * newton_max_iter  round-1 update cap (paper: 50); newton_max_iter2: round-2 cap
+ * fallback         round 2: Armijo backtracking, or the fixed step 0.01
+ * fit_codebook     1: hcz_compress fits the codebook from the latents of every
+ *                  sample_every-th histogram before quantising and writes it to the
+ *                  codebook argument; 0: it uses the codebook given. */
+typedef struct {
+  double tau;
+  int32_t tau_mode;
+  double newton_s;
+  int32_t newton_max_iter;
+  int32_t newton_max_iter2;
+  int32_t fallback;
+  int32_t fit_codebook;
+  int32_t sample_every;
+} hcz_params;
+
+/* Run statistics, written to device memory by compress and read with hcz_stats_read. */
+typedef struct {
+  uint64_t n_hist, n_coded, n_round2, n_raw;
+  uint64_t stream_bytes;          /* bytes the residual stream needs */
+  uint64_t overflow;              /* 1 if stream_bytes > res_capacity (nothing written past it) */
+  uint64_t newton_max_iters;
+  uint64_t newton_iters_total;
+  uint64_t newton_iter_hist[64];  /* updates per histogram (last bin: >= 63) */
+  uint64_t kstar_hist[48];        /* chosen ladder index of coded histograms */
+} hcz_stats;
+
+/* Compressed batch.  codes [H][latent] (u8; unused without a model), lambda [H][4]
+ * (FP64), flags [H] (u8, HCZ_FLAG_*), res_offset [H+1] (u64, exclusive scan of record
+ * sizes), res_bytes [res_capacity] (records in histogram order), stats (device). */
+typedef struct {
+  uint8_t* codes;
+  double* lambda;
+  uint8_t* flags;
+  uint64_t* res_offset;
+  uint8_t* res_bytes;
+  uint64_t res_capacity;
+  hcz_stats* stats;
+} hcz_compressed;
+
+/* ---- context, plan, model ------------------------------------------------------- */
+
+/* Create a context on HIP device `device` (sets it current on the calling thread). */
+hcz_status hcz_create(int device, hcz_ctx** out);
+void hcz_destroy(hcz_ctx* ctx);
+/* Message of the calling thread's last failed call ("" if none); valid until the next call. */
+const char* hcz_last_error(void);
+/* Library version string, e.g. "hcz 0.1 gfx950". */
+const char* hcz_version(void);
+
+/* Device tables for one grid: basis phi_k of the four moments (Eq. 1-4; phi = 1,
+ * v_par/V_par, (v_perp/V_perp)^2, (v_par/V_par)^2 with V = the grid's half extent) and
+ * the multilevel node layout of the residual coder (Stage 4). */
+hcz_status hcz_plan_create(hcz_ctx* ctx, const hcz_grid* grid, hcz_plan** out);
+void hcz_plan_destroy(hcz_plan* plan);
+
+/* Copy an autoencoder to the device for `plan`'s grid (N = n_par * n_perp). */
+hcz_status hcz_model_load(hcz_plan* plan, const hcz_model_desc* desc, hcz_model** out);
+void hcz_model_free(hcz_model* model);
+
+/* ---- stages (each one step of Section III, callable on its own) ------------------- */
+
+/* Moments b[H][4] = A f and QoIs qoi[H][4] = (n, u_par, T_perp, T_par) (Eq. 1-4), and
+ * norm[H] = ||f||_2 (correctly rounded sum of the rounded squares).  hist: H histograms,
+ * element (h, j, i) at hist[h*hist_stride + j*row_stride + i] (elements); any output
+ * pointer may be NULL. */
+hcz_status hcz_qoi(const hcz_plan* plan, const void* hist, int32_t dtype, int64_t H,
+                   int64_t hist_stride, int64_t row_stride, double* b, double* qoi,
+                   double* norm, hcz_stream_t stream);
+
+/* Encoder (Stages 2-3): z[H][latent] (FP32) of the z-scored histograms. */
+hcz_status hcz_encode(const hcz_model* model, const void* hist, int32_t dtype, int64_t H,
+                      int64_t hist_stride, int64_t row_stride, float* z, hcz_stream_t stream);
+
+/* Codebook fit (Section IV-E): per latent dimension, 1-D k-means with k = 1 << bits on
+ * the rows z[s * sample_every], s = 0..ceil(n/sample_every)-1, of z[n][latent]; initial
+ * centroids at the (2c+1)/(2k) quantiles of the sorted sample; Lloyd updates until no
+ * assignment changes (at most 25); empty clusters keep their centroid.  Writes
+ * cb->centroids.  Workspace: hcz_codebook_fit_workspace. */
+hcz_status hcz_codebook_fit_workspace(int64_t n, int32_t latent, int64_t sample_every,
+                                      size_t* bytes);
+hcz_status hcz_codebook_fit(const float* z, int64_t n, int32_t latent, int64_t sample_every,
+                            hcz_codebook* cb, void* ws, size_t ws_bytes, hcz_stream_t stream);
+
+/* Quantize (Stage 3): codes[n][latent] = #{c : (C[d][c] + C[d][c+1]) / 2 < z[n][d]}
+ * (midpoints in FP64), the nearest centroid value with exact midpoints going low. */
+hcz_status hcz_quantize(const float* z, int64_t n, int32_t latent, const hcz_codebook* cb,
+                        uint8_t* codes, hcz_stream_t stream);
+
+/* Decode (Stage 3): fhat[H][N] (FP32, row-major [j][i]) = sigma * decoder(C[codes]) + mu. */
+hcz_status hcz_decode(const hcz_model* model, const uint8_t* codes, const hcz_codebook* cb,
+                      int64_t H, float* fhat, hcz_stream_t stream);
+
+/* Residual coding + QoI correction of H histograms against a given reconstruction
+ * (Stages 4-5): fhat [H][N] FP32 row-major, or NULL for fhat = 0 (the coder-only
+ * pipeline).  Fills out->lambda, flags, res_offset, res_bytes, stats (codes untouched).
+ * Workspace: hcz_compress_workspace. */
+hcz_status hcz_residual(const hcz_plan* plan, const hcz_params* params, const void* hist,
+                        int32_t dtype, int64_t H, int64_t hist_stride, int64_t row_stride,
+                        const float* fhat, hcz_compressed* out, void* ws, size_t ws_bytes,
+                        hcz_stream_t stream);
+
+/* ---- whole path --------------------------------------------------------------------- */
+
+/* Workspace bytes for hcz_compress / hcz_residual / hcz_decompress of H histograms. */
+hcz_status hcz_compress_workspace(const hcz_plan* plan, const hcz_model* model, int64_t H,
+                                  const hcz_params* params, size_t* bytes);
+hcz_status hcz_decompress_workspace(const hcz_plan* plan, const hcz_model* model, int64_t H,
+                                    size_t* bytes);
+
+/* Compress H histograms: encode, (fit and) quantize, decode, residual coding, Newton.
+ * model may be NULL (fhat = 0; cb unused).  The stream needs at most
+ * H * (header + 4 N) bytes for FP32 input (H * 8 N for FP64). */
+hcz_status hcz_compress(const hcz_plan* plan, const hcz_model* model, hcz_codebook* cb,
+                        const hcz_params* params, const void* hist, int32_t dtype, int64_t H,
+                        int64_t hist_stride, int64_t row_stride, hcz_compressed* out,
+                        void* ws, size_t ws_bytes, hcz_stream_t stream);
+
+/* Decompress (Section III, last paragraph): out[H][N] in out_dtype, row-major.
+ * in_dtype is the element type the batch was compressed from (verbatim records).
+ * A histogram whose record ends past in->res_capacity decodes to NaN. */
+hcz_status hcz_decompress(const hcz_plan* plan, const hcz_model* model,
+                          const hcz_codebook* cb, const hcz_compressed* in, int32_t in_dtype,
+                          int64_t H, void* out, int32_t out_dtype, void* ws, size_t ws_bytes,
+                          hcz_stream_t stream);
+
+/* Synchronise `stream`, copy the device stats to host_out (host); returns
+ * HCZ_ECAPACITY if the stream overflowed its capacity. */
+hcz_status hcz_stats_read(const hcz_stats* dev_stats, hcz_stats* host_out, hcz_stream_t stream);
+
+/* ---- stage timing ---------------------------------------------------------------------
+ * With profiling on, hcz_compress and hcz_decompress record a HIP event pair around every
+ * kernel stage, on the caller's stream.  hcz_profile_read waits for the recorded events
+ * and returns, per stage, the summed milliseconds (ms[HCZ_NSTAGES], host) and the number
+ * of calls (calls[HCZ_NSTAGES], host) since the previous read, then resets. */
+enum { HCZ_STAGE_ENCODE = 0, HCZ_STAGE_CODEBOOK, HCZ_STAGE_QUANTIZE, HCZ_STAGE_DECODE,
+       HCZ_STAGE_RESIDUAL, HCZ_STAGE_SCAN, HCZ_STAGE_COMPACT, HCZ_STAGE_STATS,
+       HCZ_STAGE_DECOMPRESS, HCZ_NSTAGES };
+hcz_status hcz_profile_enable(hcz_ctx* ctx, int enable);
+hcz_status hcz_profile_read(hcz_ctx* ctx, double* ms, int64_t* calls);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HCZ_H */

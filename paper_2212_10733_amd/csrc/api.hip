@@ -1,0 +1,690 @@
+// Host side of libhcz: argument validation, device tables of a grid (plan) and of a
+// model, workspace layout and the launch sequence of each C-ABI entry point.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "hcz_internal.h"
+
+using namespace hcz;
+
+namespace {
+
+thread_local std::string g_err;
+
+hcz_status fail(hcz_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+hcz_status hip_fail(hipError_t e, const char* what) {
+  return fail(HCZ_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HCZ_TRY(expr, what)                       \
+  do {                                            \
+    hipError_t e_ = (expr);                       \
+    if (e_ != hipSuccess) return hip_fail(e_, what); \
+  } while (0)
+
+size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+int nlevels_1d(int n) {
+  int m = n - 2, b = 0;
+  while (m > 0) { ++b; m >>= 1; }
+  return b;
+}
+
+}  // namespace
+
+// Stage timing: a ring of event sets; a set is folded into the totals when it is reused
+// or when the totals are read.
+struct ProfSet {
+  hipEvent_t ev[2 * HCZ_NSTAGES];
+  bool used[HCZ_NSTAGES];
+  bool live;
+};
+
+struct hcz_ctx {
+  int device;
+  bool prof = false;
+  std::vector<ProfSet> ring;
+  int head = 0;
+  ProfSet* cur = nullptr;
+  double acc_ms[HCZ_NSTAGES] = {};
+  int64_t acc_calls[HCZ_NSTAGES] = {};
+};
+
+namespace {
+
+void prof_fold(hcz_ctx* c, ProfSet& s) {
+  if (!s.live) return;
+  for (int k = 0; k < HCZ_NSTAGES; ++k) {
+    if (!s.used[k]) continue;
+    (void)hipEventSynchronize(s.ev[2 * k + 1]);
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, s.ev[2 * k], s.ev[2 * k + 1]) == hipSuccess) {
+      c->acc_ms[k] += ms;
+      c->acc_calls[k] += 1;
+    }
+    s.used[k] = false;
+  }
+  s.live = false;
+}
+
+// Start a new event set for one entry-point call (no-op when profiling is off).
+void prof_begin(hcz_ctx* c) {
+  c->cur = nullptr;
+  if (!c->prof || c->ring.empty()) return;
+  ProfSet& s = c->ring[c->head];
+  prof_fold(c, s);
+  c->head = (c->head + 1) % (int)c->ring.size();
+  s.live = true;
+  c->cur = &s;
+}
+
+struct StageTimer {
+  hcz_ctx* c;
+  int k;
+  hipStream_t st;
+  StageTimer(hcz_ctx* c_, int k_, hipStream_t st_) : c(c_), k(k_), st(st_) {
+    if (c->cur) (void)hipEventRecord(c->cur->ev[2 * k], st);
+  }
+  ~StageTimer() {
+    if (c->cur) {
+      (void)hipEventRecord(c->cur->ev[2 * k + 1], st);
+      c->cur->used[k] = true;
+    }
+  }
+};
+
+}  // namespace
+
+struct hcz_plan {
+  hcz_ctx* ctx;
+  GridDev G;
+  std::vector<void*> allocs;
+};
+
+struct hcz_model {
+  hcz_plan* plan;
+  ModelDev M;
+  std::vector<void*> allocs;
+};
+
+namespace {
+
+template <typename T>
+hcz_status upload(std::vector<void*>& allocs, const std::vector<T>& v, const T** out) {
+  void* p = nullptr;
+  const size_t bytes = std::max<size_t>(v.size() * sizeof(T), 16);
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) return fail(HCZ_ENOMEM, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+  allocs.push_back(p);
+  if (!v.empty()) {
+    e = hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
+  }
+  *out = (const T*)p;
+  return HCZ_OK;
+}
+
+void free_all(std::vector<void*>& allocs) {
+  for (void* p : allocs) (void)hipFree(p);
+  allocs.clear();
+}
+
+// Per-dimension level tables: lev(i) = the finest level whose node set
+// G_l = {multiples of 2^l} U {n-1} contains i (L at both ends), and the bracket of i in
+// G_{lev(i)+1} with its interpolation weight.
+struct DimTables {
+  std::vector<uint8_t> lev, a, b;
+  std::vector<double> s;
+};
+
+DimTables dim_tables(int n, int L) {
+  DimTables d;
+  d.lev.resize(n);
+  d.a.resize(n);
+  d.b.resize(n);
+  d.s.resize(n);
+  for (int i = 0; i < n; ++i) {
+    int lev;
+    if (i == 0 || i == n - 1) {
+      lev = L;
+    } else {
+      lev = 0;
+      while (((i >> (lev + 1)) << (lev + 1)) == i) ++lev;
+    }
+    d.lev[i] = (uint8_t)lev;
+    if (lev >= L) {
+      d.a[i] = d.b[i] = (uint8_t)i;
+      d.s[i] = 0.0;
+    } else {
+      const int l = lev + 1;
+      const int a = (i >> l) << l;
+      const int b = std::min(a + (1 << l), n - 1);
+      d.a[i] = (uint8_t)a;
+      d.b[i] = (uint8_t)b;
+      d.s[i] = (double)(i - a) / (double)(b - a);
+    }
+  }
+  return d;
+}
+
+bool in_set(int n, int l, int i) { return i == n - 1 || (i % (1 << l)) == 0; }
+
+hcz_status check_hist(const void* hist, int32_t dtype, int64_t H, int64_t hs, int64_t rs,
+                      const GridDev& G) {
+  if (H < 0) return fail(HCZ_EINVAL, "H = %lld < 0", (long long)H);
+  if (H > 0 && !hist) return fail(HCZ_EINVAL, "hist is NULL");
+  if (dtype != HCZ_F32 && dtype != HCZ_F64) return fail(HCZ_EINVAL, "dtype %d", dtype);
+  if (rs < G.n_par) return fail(HCZ_EINVAL, "row_stride %lld < n_par %d", (long long)rs, G.n_par);
+  if (H > 1 && hs < (int64_t)(G.n_perp - 1) * rs + G.n_par)
+    return fail(HCZ_EINVAL, "hist_stride %lld overlaps histograms", (long long)hs);
+  if (H > 0x7fffffffLL) return fail(HCZ_EINVAL, "H too large");
+  return HCZ_OK;
+}
+
+hcz_status check_params(const hcz_params* p) {
+  if (!p) return fail(HCZ_EINVAL, "params is NULL");
+  if (!(p->tau >= 0.0) || !std::isfinite(p->tau)) return fail(HCZ_EINVAL, "tau must be finite and >= 0");
+  if (p->tau_mode != HCZ_TAU_REL_L2 && p->tau_mode != HCZ_TAU_NRMSE) return fail(HCZ_EINVAL, "tau_mode");
+  if (!(p->newton_s > 0.0) || !std::isfinite(p->newton_s)) return fail(HCZ_EINVAL, "newton_s must be > 0");
+  if (p->newton_max_iter < 0 || p->newton_max_iter2 < 0) return fail(HCZ_EINVAL, "newton iteration caps must be >= 0");
+  if (p->fallback != HCZ_FALLBACK_BACKTRACK && p->fallback != HCZ_FALLBACK_PAPER) return fail(HCZ_EINVAL, "fallback");
+  if (p->fit_codebook && p->sample_every < 1) return fail(HCZ_EINVAL, "sample_every must be >= 1");
+  return HCZ_OK;
+}
+
+size_t slot_stride(const GridDev& G, int32_t dtype) {
+  const size_t coded = (size_t)G.hdr_bytes + 4 * (size_t)G.N;
+  const size_t raw = (size_t)G.N * (dtype == HCZ_F64 ? 8 : 4);
+  return (std::max(coded, raw) + 15) / 16 * 16;
+}
+
+struct WsLayout {
+  size_t z, fhat, sizes, kstar, iters, partial, slots, cbws, total;
+};
+
+WsLayout ws_layout(const GridDev& G, bool model, int64_t H, int32_t dtype, bool fit, int64_t every) {
+  WsLayout w{};
+  size_t o = 0;
+  w.z = o;      o += model ? align256((size_t)H * kLatent * 4) : 0;
+  w.fhat = o;   o += model ? align256((size_t)H * G.N * 4) : 0;
+  w.sizes = o;  o += align256((size_t)H * 8);
+  w.kstar = o;  o += align256((size_t)H);
+  w.iters = o;  o += align256((size_t)H * 2);
+  w.partial = o; o += align256(scan_partial_elems(H) * 8);
+  w.cbws = o;   o += (model && fit) ? align256(codebook_ws_bytes(H, kLatent, std::max<int64_t>(every, 1))) : 0;
+  w.slots = o;  o += align256((size_t)H * slot_stride(G, dtype));
+  w.total = o;
+  return w;
+}
+
+hcz_status set_device(const hcz_ctx* ctx) {
+  HCZ_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+  return HCZ_OK;
+}
+
+hcz_status check_cb(const hcz_codebook* cb) {
+  if (!cb || !cb->centroids) return fail(HCZ_EINVAL, "codebook or its centroids is NULL");
+  if (cb->bits < 1 || cb->bits > 8) return fail(HCZ_EINVAL, "codebook bits %d not in [1, 8]", cb->bits);
+  return HCZ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* hcz_last_error(void) { return g_err.c_str(); }
+const char* hcz_version(void) { return "hcz 0.1 gfx950"; }
+
+hcz_status hcz_create(int device, hcz_ctx** out) {
+  if (!out) return fail(HCZ_EINVAL, "out is NULL");
+  *out = nullptr;
+  int n = 0;
+  HCZ_TRY(hipGetDeviceCount(&n), "hipGetDeviceCount");
+  if (device < 0 || device >= n) return fail(HCZ_EINVAL, "device %d of %d", device, n);
+  HCZ_TRY(hipSetDevice(device), "hipSetDevice");
+  *out = new hcz_ctx{device};
+  return HCZ_OK;
+}
+
+void hcz_destroy(hcz_ctx* ctx) {
+  if (!ctx) return;
+  for (auto& set : ctx->ring)
+    for (auto& e : set.ev) (void)hipEventDestroy(e);
+  delete ctx;
+}
+
+hcz_status hcz_plan_create(hcz_ctx* ctx, const hcz_grid* g, hcz_plan** out) {
+  if (!ctx || !g || !out) return fail(HCZ_EINVAL, "NULL argument");
+  *out = nullptr;
+  const int np = g->n_par, nq = g->n_perp;
+  if (np < 3 || nq < 3 || np > kMaxDim || nq > kMaxDim || np * nq > kMaxN)
+    return fail(HCZ_EINVAL, "grid %d x %d outside 3..%d per side, %d cells", np, nq, kMaxDim, kMaxN);
+  if (!(g->vpar_hi > g->vpar_lo) || !(g->vperp_hi > g->vperp_lo) || !std::isfinite(g->vpar_lo) ||
+      !std::isfinite(g->vpar_hi) || !std::isfinite(g->vperp_lo) || !std::isfinite(g->vperp_hi))
+    return fail(HCZ_EINVAL, "velocity ranges must be finite with hi > lo");
+  if (!(g->mass > 0.0) || !std::isfinite(g->mass)) return fail(HCZ_EINVAL, "mass must be > 0");
+  hcz_status s = set_device(ctx);
+  if (s) return s;
+  const int N = np * nq;
+  const double dpar = (g->vpar_hi - g->vpar_lo) / (np - 1);
+  const double dperp = (g->vperp_hi - g->vperp_lo) / (nq - 1);
+  const double Vpar = std::max(std::fabs(g->vpar_lo), std::fabs(g->vpar_hi));
+  const double Vperp = std::max(std::fabs(g->vperp_lo), std::fabs(g->vperp_hi));
+  std::vector<double> apar(np), cperp(nq), vol(N);
+  for (int i = 0; i < np; ++i) apar[i] = (g->vpar_lo + i * dpar) / Vpar;
+  for (int j = 0; j < nq; ++j) {
+    const double c = (g->vperp_lo + j * dperp) / Vperp;
+    cperp[j] = c * c;
+  }
+  bool uniform = g->vol == nullptr;
+  for (int e = 0; e < N; ++e) {
+    vol[e] = g->vol ? g->vol[e] : dpar * dperp;
+    if (!(vol[e] > 0.0) || !std::isfinite(vol[e])) return fail(HCZ_EINVAL, "vol[%d] must be finite and > 0", e);
+  }
+  const int L = std::max(nlevels_1d(np), nlevels_1d(nq));
+  const int nlev = L + 1;
+  if (nlev > kMaxLev) return fail(HCZ_EUNSUPPORTED, "%d levels", nlev);
+  // packing order: coarsest node set first, then levels L..1, row-major within a group
+  std::vector<uint32_t> node;
+  node.reserve(N);
+  std::vector<int> gstart;
+  gstart.push_back(0);
+  for (int j = 0; j < nq; ++j)
+    for (int i = 0; i < np; ++i)
+      if (in_set(nq, L, j) && in_set(np, L, i)) node.push_back((uint32_t)i | ((uint32_t)j << 16));
+  gstart.push_back((int)node.size());
+  for (int l = L; l >= 1; --l) {
+    for (int j = 0; j < nq; ++j)
+      for (int i = 0; i < np; ++i) {
+        if (!in_set(nq, l - 1, j) || !in_set(np, l - 1, i)) continue;
+        if (in_set(nq, l, j) && in_set(np, l, i)) continue;
+        node.push_back((uint32_t)i | ((uint32_t)j << 16));
+      }
+    gstart.push_back((int)node.size());
+  }
+  if ((int)node.size() != N) return fail(HCZ_EINVAL, "internal: node layout has %zu of %d nodes", node.size(), N);
+  DimTables dp = dim_tables(np, L), dq = dim_tables(nq, L);
+  hcz_plan* P = new hcz_plan();
+  P->ctx = ctx;
+  GridDev& G = P->G;
+  G.n_par = np;
+  G.n_perp = nq;
+  G.N = N;
+  G.L = L;
+  G.nlev = nlev;
+  G.hdr_bytes = 8 * ((10 + nlev + 7) / 8);
+  G.uniform_vol = uniform ? 1 : 0;
+  for (int q = 0; q <= kMaxLev; ++q) G.gstart[q] = q < (int)gstart.size() ? gstart[q] : N;
+  G.vol0 = dpar * dperp;
+  G.sqrtN = std::sqrt((double)N);
+  G.den = std::sqrt((double)N) * (double)(L + 1);
+  G.Vpar = Vpar;
+  G.Vperp = Vperp;
+  G.mass = g->mass;
+  if ((s = upload(P->allocs, vol, &G.vol)) || (s = upload(P->allocs, apar, &G.apar)) ||
+      (s = upload(P->allocs, cperp, &G.cperp)) || (s = upload(P->allocs, node, &G.node_ij)) ||
+      (s = upload(P->allocs, dp.lev, &G.lev_par)) || (s = upload(P->allocs, dp.a, &G.a_par)) ||
+      (s = upload(P->allocs, dp.b, &G.b_par)) || (s = upload(P->allocs, dp.s, &G.s_par)) ||
+      (s = upload(P->allocs, dq.lev, &G.lev_perp)) || (s = upload(P->allocs, dq.a, &G.a_perp)) ||
+      (s = upload(P->allocs, dq.b, &G.b_perp)) || (s = upload(P->allocs, dq.s, &G.s_perp))) {
+    free_all(P->allocs);
+    delete P;
+    return s;
+  }
+  *out = P;
+  return HCZ_OK;
+}
+
+void hcz_plan_destroy(hcz_plan* plan) {
+  if (!plan) return;
+  free_all(plan->allocs);
+  delete plan;
+}
+
+hcz_status hcz_model_load(hcz_plan* plan, const hcz_model_desc* d, hcz_model** out) {
+  if (!plan || !d || !out) return fail(HCZ_EINVAL, "NULL argument");
+  *out = nullptr;
+  if (d->arch != HCZ_ARCH_DENSE) return fail(HCZ_EUNSUPPORTED, "arch %d", d->arch);
+  if (d->hidden != kHidden || d->latent != kLatent)
+    return fail(HCZ_EUNSUPPORTED, "dense model must be hidden %d, latent %d", kHidden, kLatent);
+  if (!d->weights || !d->norm_mean || !d->norm_std) return fail(HCZ_EINVAL, "weights or norm stats NULL");
+  hcz_status s = set_device(plan->ctx);
+  if (s) return s;
+  const int N = plan->G.N, Hd = kHidden, Ld = kLatent;
+  const int kpad = (N + 31) / 32 * 32, npad = (N + 127) / 128 * 128;
+  const float* w = d->weights;
+  const float *W1 = w, *b1 = W1 + (size_t)Hd * N, *W2 = b1 + Hd, *b2 = W2 + Ld * Hd, *W3 = b2 + Ld,
+              *b3 = W3 + Hd * Ld, *W4 = b3 + Hd, *b4 = W4 + (size_t)N * Hd;
+  std::vector<float> W1p((size_t)Hd * kpad, 0.0f), W4p((size_t)npad * Hd, 0.0f);
+  for (int r = 0; r < Hd; ++r)
+    for (int k = 0; k < N; ++k) W1p[(size_t)r * kpad + k] = W1[(size_t)r * N + k];
+  for (int c = 0; c < N; ++c)
+    for (int k = 0; k < Hd; ++k) W4p[(size_t)c * Hd + (k & 1) * 64 + (k >> 1)] = W4[(size_t)c * Hd + k];
+  std::vector<float> mu(d->norm_mean, d->norm_mean + N), sd(d->norm_std, d->norm_std + N), rsd(N);
+  for (int k = 0; k < N; ++k) {
+    if (!(sd[k] > 0.0f) || !std::isfinite(sd[k]) || !std::isfinite(mu[k]))
+      return fail(HCZ_EINVAL, "norm_std[%d] must be finite and > 0", k);
+    rsd[k] = 1.0f / sd[k];
+  }
+  hcz_model* m = new hcz_model();
+  m->plan = plan;
+  ModelDev& M = m->M;
+  M.N = N;
+  M.hidden = Hd;
+  M.latent = Ld;
+  M.kpad = kpad;
+  M.npad = npad;
+  std::vector<float> vb1(b1, b1 + Hd), vW2(W2, W2 + Ld * Hd), vb2(b2, b2 + Ld), vW3(W3, W3 + Hd * Ld),
+      vb3(b3, b3 + Hd), vb4(b4, b4 + N);
+  if ((s = upload(m->allocs, W1p, &M.W1p)) || (s = upload(m->allocs, vb1, &M.b1)) ||
+      (s = upload(m->allocs, vW2, &M.W2)) || (s = upload(m->allocs, vb2, &M.b2)) ||
+      (s = upload(m->allocs, vW3, &M.W3)) || (s = upload(m->allocs, vb3, &M.b3)) ||
+      (s = upload(m->allocs, W4p, &M.W4p)) || (s = upload(m->allocs, vb4, &M.b4)) ||
+      (s = upload(m->allocs, mu, &M.mu)) || (s = upload(m->allocs, rsd, &M.rsd)) ||
+      (s = upload(m->allocs, sd, &M.sd))) {
+    free_all(m->allocs);
+    delete m;
+    return s;
+  }
+  *out = m;
+  return HCZ_OK;
+}
+
+void hcz_model_free(hcz_model* m) {
+  if (!m) return;
+  free_all(m->allocs);
+  delete m;
+}
+
+hcz_status hcz_qoi(const hcz_plan* plan, const void* hist, int32_t dtype, int64_t H,
+                   int64_t hist_stride, int64_t row_stride, double* b, double* qoi, double* norm,
+                   hcz_stream_t stream) {
+  if (!plan) return fail(HCZ_EINVAL, "plan is NULL");
+  hcz_status s = check_hist(hist, dtype, H, hist_stride, row_stride, plan->G);
+  if (s) return s;
+  if ((s = set_device(plan->ctx))) return s;
+  HCZ_TRY(launch_qoi(plan->G, hist, dtype, H, hist_stride, row_stride, b, qoi, norm, (hipStream_t)stream), "qoi launch");
+  return HCZ_OK;
+}
+
+hcz_status hcz_encode(const hcz_model* model, const void* hist, int32_t dtype, int64_t H,
+                      int64_t hist_stride, int64_t row_stride, float* z, hcz_stream_t stream) {
+  if (!model) return fail(HCZ_EINVAL, "model is NULL");
+  hcz_status s = check_hist(hist, dtype, H, hist_stride, row_stride, model->plan->G);
+  if (s) return s;
+  if (H > 0 && !z) return fail(HCZ_EINVAL, "z is NULL");
+  if ((s = set_device(model->plan->ctx))) return s;
+  HCZ_TRY(launch_encode(model->M, hist, dtype, H, hist_stride, row_stride, model->plan->G.n_par, z,
+                        (hipStream_t)stream), "encode launch");
+  return HCZ_OK;
+}
+
+hcz_status hcz_codebook_fit_workspace(int64_t n, int32_t latent, int64_t sample_every, size_t* bytes) {
+  if (!bytes || n < 1 || latent < 1 || sample_every < 1) return fail(HCZ_EINVAL, "bad argument");
+  *bytes = codebook_ws_bytes(n, latent, sample_every);
+  return HCZ_OK;
+}
+
+hcz_status hcz_codebook_fit(const float* z, int64_t n, int32_t latent, int64_t sample_every,
+                            hcz_codebook* cb, void* ws, size_t ws_bytes, hcz_stream_t stream) {
+  if (!z || n < 1 || latent < 1 || latent > 65535 || sample_every < 1) return fail(HCZ_EINVAL, "bad argument");
+  hcz_status s = check_cb(cb);
+  if (s) return s;
+  if (!ws || ws_bytes < codebook_ws_bytes(n, latent, sample_every))
+    return fail(HCZ_EWORKSPACE, "workspace %zu < %zu", ws_bytes, codebook_ws_bytes(n, latent, sample_every));
+  HCZ_TRY(launch_codebook_fit(z, n, latent, sample_every, cb->bits, cb->centroids, ws, (hipStream_t)stream),
+          "codebook launch");
+  return HCZ_OK;
+}
+
+hcz_status hcz_quantize(const float* z, int64_t n, int32_t latent, const hcz_codebook* cb,
+                        uint8_t* codes, hcz_stream_t stream) {
+  if (n < 0 || latent < 1) return fail(HCZ_EINVAL, "bad size");
+  if (n > 0 && (!z || !codes)) return fail(HCZ_EINVAL, "NULL buffer");
+  hcz_status s = check_cb(cb);
+  if (s) return s;
+  HCZ_TRY(launch_quantize(z, n, latent, cb->centroids, cb->bits, codes, (hipStream_t)stream), "quantize launch");
+  return HCZ_OK;
+}
+
+hcz_status hcz_decode(const hcz_model* model, const uint8_t* codes, const hcz_codebook* cb,
+                      int64_t H, float* fhat, hcz_stream_t stream) {
+  if (!model) return fail(HCZ_EINVAL, "model is NULL");
+  if (H < 0) return fail(HCZ_EINVAL, "H < 0");
+  if (H > 0 && (!codes || !fhat)) return fail(HCZ_EINVAL, "NULL buffer");
+  hcz_status s = check_cb(cb);
+  if (s) return s;
+  if ((s = set_device(model->plan->ctx))) return s;
+  HCZ_TRY(launch_decode(model->M, codes, cb->centroids, cb->bits, H, fhat, (hipStream_t)stream), "decode launch");
+  return HCZ_OK;
+}
+
+hcz_status hcz_compress_workspace(const hcz_plan* plan, const hcz_model* model, int64_t H,
+                                  const hcz_params* params, size_t* bytes) {
+  if (!plan || !bytes || H < 0) return fail(HCZ_EINVAL, "bad argument");
+  const bool fit = params && params->fit_codebook;
+  const int64_t every = params ? std::max<int64_t>(params->sample_every, 1) : 1;
+  // sized for FP64 input, which needs the larger verbatim records
+  *bytes = ws_layout(plan->G, model != nullptr, H, HCZ_F64, fit, every).total;
+  return HCZ_OK;
+}
+
+hcz_status hcz_decompress_workspace(const hcz_plan* plan, const hcz_model* model, int64_t H, size_t* bytes) {
+  if (!plan || !bytes || H < 0) return fail(HCZ_EINVAL, "bad argument");
+  *bytes = model ? align256((size_t)H * plan->G.N * 4) : 0;
+  return HCZ_OK;
+}
+
+static hcz_status residual_impl(const hcz_plan* plan, const hcz_params* p, const void* hist,
+                                int32_t dtype, int64_t H, int64_t hs, int64_t rs, const float* fhat,
+                                hcz_compressed* out, uint8_t* ws, const WsLayout& L, hipStream_t st) {
+  const GridDev& G = plan->G;
+  ResidualArgs a{};
+  a.hist = hist;
+  a.dtype = dtype;
+  a.hs = hs;
+  a.rs = rs;
+  a.H = H;
+  a.fhat = fhat;
+  a.tau = p->tau;
+  a.tau_mode = p->tau_mode;
+  a.newton_s = p->newton_s;
+  a.max_iter = p->newton_max_iter;
+  a.max_iter2 = p->newton_max_iter2;
+  a.fallback = p->fallback;
+  a.lambda = out->lambda;
+  a.flags = out->flags;
+  a.sizes = (uint64_t*)(ws + L.sizes);
+  a.slots = ws + L.slots;
+  a.slot_stride = (long long)slot_stride(G, dtype);
+  a.kstar = ws + L.kstar;
+  a.iters = (uint16_t*)(ws + L.iters);
+  hcz_ctx* c = plan->ctx;
+  {
+    StageTimer tm(c, HCZ_STAGE_RESIDUAL, st);
+    HCZ_TRY(launch_residual(G, a, st), "residual launch");
+  }
+  {
+    StageTimer tm(c, HCZ_STAGE_SCAN, st);
+    HCZ_TRY(launch_scan(a.sizes, out->res_offset, H, (uint64_t*)(ws + L.partial), st), "scan launch");
+  }
+  {
+    StageTimer tm(c, HCZ_STAGE_COMPACT, st);
+    HCZ_TRY(launch_compact(a.slots, a.slot_stride, out->res_offset, a.sizes, H, out->res_bytes,
+                           out->res_capacity, st), "compact launch");
+  }
+  {
+    StageTimer tm(c, HCZ_STAGE_STATS, st);
+    HCZ_TRY(launch_stats(out->flags, a.kstar, a.iters, out->res_offset, H, out->res_capacity, out->stats, st),
+            "stats launch");
+  }
+  return HCZ_OK;
+}
+
+static hcz_status check_out(const hcz_compressed* out, int64_t H, bool codes) {
+  if (!out) return fail(HCZ_EINVAL, "out is NULL");
+  if (!out->res_offset || !out->stats) return fail(HCZ_EINVAL, "res_offset or stats is NULL");
+  if (H > 0 && (!out->lambda || !out->flags)) return fail(HCZ_EINVAL, "lambda or flags is NULL");
+  if (H > 0 && codes && !out->codes) return fail(HCZ_EINVAL, "codes is NULL");
+  if (out->res_capacity > 0 && !out->res_bytes) return fail(HCZ_EINVAL, "res_bytes is NULL");
+  return HCZ_OK;
+}
+
+hcz_status hcz_residual(const hcz_plan* plan, const hcz_params* params, const void* hist,
+                        int32_t dtype, int64_t H, int64_t hist_stride, int64_t row_stride,
+                        const float* fhat, hcz_compressed* out, void* ws, size_t ws_bytes,
+                        hcz_stream_t stream) {
+  if (!plan) return fail(HCZ_EINVAL, "plan is NULL");
+  hcz_status s;
+  if ((s = check_params(params)) || (s = check_hist(hist, dtype, H, hist_stride, row_stride, plan->G)) ||
+      (s = check_out(out, H, false)))
+    return s;
+  const WsLayout L = ws_layout(plan->G, false, H, dtype, false, 1);
+  if (!ws || ws_bytes < L.total) return fail(HCZ_EWORKSPACE, "workspace %zu < %zu", ws_bytes, L.total);
+  if ((s = set_device(plan->ctx))) return s;
+  prof_begin(plan->ctx);
+  return residual_impl(plan, params, hist, dtype, H, hist_stride, row_stride, fhat, out, (uint8_t*)ws, L,
+                       (hipStream_t)stream);
+}
+
+hcz_status hcz_compress(const hcz_plan* plan, const hcz_model* model, hcz_codebook* cb,
+                        const hcz_params* params, const void* hist, int32_t dtype, int64_t H,
+                        int64_t hist_stride, int64_t row_stride, hcz_compressed* out, void* ws,
+                        size_t ws_bytes, hcz_stream_t stream) {
+  if (!plan) return fail(HCZ_EINVAL, "plan is NULL");
+  if (model && model->plan->G.N != plan->G.N) return fail(HCZ_EINVAL, "model was loaded for another grid");
+  hcz_status s;
+  if ((s = check_params(params)) || (s = check_hist(hist, dtype, H, hist_stride, row_stride, plan->G)) ||
+      (s = check_out(out, H, model != nullptr)))
+    return s;
+  if (model && (s = check_cb(cb))) return s;
+  const bool fit = model && params->fit_codebook;
+  const WsLayout L = ws_layout(plan->G, model != nullptr, H, dtype, fit, params->sample_every);
+  if (!ws || ws_bytes < L.total) return fail(HCZ_EWORKSPACE, "workspace %zu < %zu", ws_bytes, L.total);
+  if ((s = set_device(plan->ctx))) return s;
+  hipStream_t st = (hipStream_t)stream;
+  uint8_t* w = (uint8_t*)ws;
+  const float* fhat = nullptr;
+  hcz_ctx* c = plan->ctx;
+  prof_begin(c);
+  if (model && H > 0) {
+    float* z = (float*)(w + L.z);
+    float* fh = (float*)(w + L.fhat);
+    {
+      StageTimer tm(c, HCZ_STAGE_ENCODE, st);
+      HCZ_TRY(launch_encode(model->M, hist, dtype, H, hist_stride, row_stride, plan->G.n_par, z, st), "encode launch");
+    }
+    if (fit) {
+      StageTimer tm(c, HCZ_STAGE_CODEBOOK, st);
+      HCZ_TRY(launch_codebook_fit(z, H, kLatent, params->sample_every, cb->bits, cb->centroids, w + L.cbws, st),
+              "codebook launch");
+    }
+    {
+      StageTimer tm(c, HCZ_STAGE_QUANTIZE, st);
+      HCZ_TRY(launch_quantize(z, H, kLatent, cb->centroids, cb->bits, out->codes, st), "quantize launch");
+    }
+    {
+      StageTimer tm(c, HCZ_STAGE_DECODE, st);
+      HCZ_TRY(launch_decode(model->M, out->codes, cb->centroids, cb->bits, H, fh, st), "decode launch");
+    }
+    fhat = fh;
+  }
+  return residual_impl(plan, params, hist, dtype, H, hist_stride, row_stride, fhat, out, w, L, st);
+}
+
+hcz_status hcz_decompress(const hcz_plan* plan, const hcz_model* model, const hcz_codebook* cb,
+                          const hcz_compressed* in, int32_t in_dtype, int64_t H, void* out,
+                          int32_t out_dtype, void* ws, size_t ws_bytes, hcz_stream_t stream) {
+  if (!plan || !in) return fail(HCZ_EINVAL, "NULL argument");
+  if (H < 0) return fail(HCZ_EINVAL, "H < 0");
+  if (in_dtype != HCZ_F32 && in_dtype != HCZ_F64) return fail(HCZ_EINVAL, "in_dtype");
+  if (out_dtype != HCZ_F32 && out_dtype != HCZ_F64) return fail(HCZ_EINVAL, "out_dtype");
+  if (H > 0 && (!out || !in->flags || !in->lambda || !in->res_offset)) return fail(HCZ_EINVAL, "NULL buffer");
+  if (in->res_capacity > 0 && !in->res_bytes) return fail(HCZ_EINVAL, "res_bytes is NULL");
+  if (model && model->plan->G.N != plan->G.N) return fail(HCZ_EINVAL, "model was loaded for another grid");
+  hcz_status s;
+  if (model && ((s = check_cb(cb)) || (H > 0 && !in->codes && (s = fail(HCZ_EINVAL, "codes is NULL")))))
+    return s;
+  const size_t need = model ? align256((size_t)H * plan->G.N * 4) : 0;
+  if (need && (!ws || ws_bytes < need)) return fail(HCZ_EWORKSPACE, "workspace %zu < %zu", ws_bytes, need);
+  if ((s = set_device(plan->ctx))) return s;
+  hipStream_t st = (hipStream_t)stream;
+  const float* fhat = nullptr;
+  hcz_ctx* c = plan->ctx;
+  prof_begin(c);
+  if (model && H > 0) {
+    StageTimer tm(c, HCZ_STAGE_DECODE, st);
+    HCZ_TRY(launch_decode(model->M, in->codes, cb->centroids, cb->bits, H, (float*)ws, st), "decode launch");
+    fhat = (const float*)ws;
+  }
+  DecompressArgs a{};
+  a.flags = in->flags;
+  a.lambda = in->lambda;
+  a.offsets = in->res_offset;
+  a.stream = in->res_bytes;
+  a.in_dtype = in_dtype;
+  a.H = H;
+  a.fhat = fhat;
+  a.out = out;
+  a.out_dtype = out_dtype;
+  a.capacity = in->res_capacity;
+  StageTimer tm(c, HCZ_STAGE_DECOMPRESS, st);
+  HCZ_TRY(launch_decompress(plan->G, a, st), "decompress launch");
+  return HCZ_OK;
+}
+
+hcz_status hcz_profile_enable(hcz_ctx* ctx, int enable) {
+  if (!ctx) return fail(HCZ_EINVAL, "ctx is NULL");
+  hcz_status s = set_device(ctx);
+  if (s) return s;
+  if (enable && ctx->ring.empty()) {
+    ctx->ring.resize(64);
+    for (auto& set : ctx->ring) {
+      set.live = false;
+      for (int k = 0; k < HCZ_NSTAGES; ++k) set.used[k] = false;
+      for (auto& e : set.ev) HCZ_TRY(hipEventCreate(&e), "hipEventCreate");
+    }
+  }
+  ctx->prof = enable != 0;
+  return HCZ_OK;
+}
+
+hcz_status hcz_profile_read(hcz_ctx* ctx, double* ms, int64_t* calls) {
+  if (!ctx || !ms || !calls) return fail(HCZ_EINVAL, "NULL argument");
+  hcz_status s = set_device(ctx);
+  if (s) return s;
+  for (auto& set : ctx->ring) prof_fold(ctx, set);
+  for (int k = 0; k < HCZ_NSTAGES; ++k) {
+    ms[k] = ctx->acc_ms[k];
+    calls[k] = ctx->acc_calls[k];
+    ctx->acc_ms[k] = 0.0;
+    ctx->acc_calls[k] = 0;
+  }
+  return HCZ_OK;
+}
+
+hcz_status hcz_stats_read(const hcz_stats* dev, hcz_stats* host_out, hcz_stream_t stream) {
+  if (!dev || !host_out) return fail(HCZ_EINVAL, "NULL argument");
+  HCZ_TRY(hipMemcpyAsync(host_out, dev, sizeof(hcz_stats), hipMemcpyDeviceToHost, (hipStream_t)stream),
+          "stats copy");
+  HCZ_TRY(hipStreamSynchronize((hipStream_t)stream), "stream sync");
+  if (host_out->overflow) return fail(HCZ_ECAPACITY, "residual stream needs %llu bytes",
+                                      (unsigned long long)host_out->stream_bytes);
+  return HCZ_OK;
+}
+
+}  // extern "C"

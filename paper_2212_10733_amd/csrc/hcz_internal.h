@@ -1,0 +1,292 @@
+// Internal declarations of libhcz: device-side grid tables, kernel argument blocks,
+// block reductions and the launch functions each kernel file exports to the host API.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/hcz.h"
+
+#pragma clang fp contract(off)
+
+namespace hcz {
+
+constexpr int kMaxDim = 128;        // largest n_par / n_perp of a grid
+constexpr int kMaxN = 4608;         // largest n_par * n_perp (keeps per-block LDS < 64 KB)
+constexpr int kMaxLev = 9;          // L + 1 for n <= 128 is at most 8
+constexpr int kLadder = 41;         // quantisation ladder k = 0..40
+constexpr int kHidden = 128;
+constexpr int kLatent = 16;
+
+// Selection / feasibility margin 1 - 2^-20 and ladder margin 2 (1 - 2^-19).
+constexpr double kSelMargin = 1.0 - 0x1p-20;
+constexpr double kLadderMargin = 2.0 * (1.0 - 0x1p-19);
+constexpr double kQMax = 1073741824.0;   // 2^30: larger integer coefficients go verbatim
+constexpr double kGTol = 1e-13;          // Newton stopping rule
+constexpr double kPivTol = 1e-14;        // Cholesky pivot test relative to trace(H)
+constexpr double kArmijoC = 1e-4;
+constexpr int kArmijoHalvings = 40;
+
+// Device copy of the grid: moment basis and the multilevel node layout.
+struct GridDev {
+  int n_par, n_perp, N, L, nlev, hdr_bytes, uniform_vol;
+  int gstart[kMaxLev + 1];     // coefficient groups in packing order, coarsest first
+  double vol0;                 // the cell volume when uniform
+  double sqrtN;                // sqrt(N)
+  double den;                  // sqrt(N) * (L + 1)
+  double Vpar, Vperp, mass;
+  const double* vol;           // [N] cell volumes (natural order e = j * n_par + i)
+  const double* apar;          // [n_par]  v_par / V_par
+  const double* cperp;         // [n_perp] (v_perp / V_perp)^2
+  const uint32_t* node_ij;     // [N] packing order -> i | j << 16
+  const uint8_t* lev_par;      // [n_par] finest level whose node set holds i (L at the ends)
+  const uint8_t* a_par;        // [n_par] lower bracket of i at level lev + 1
+  const uint8_t* b_par;        // [n_par] upper bracket
+  const double* s_par;         // [n_par] (i - a) / (b - a)
+  const uint8_t* lev_perp;
+  const uint8_t* a_perp;
+  const uint8_t* b_perp;
+  const double* s_perp;
+};
+
+struct ModelDev {
+  int N, hidden, latent, kpad;     // kpad: N rounded up to the encoder's K chunk
+  const float* W1p;                // [hidden][kpad] zero padded
+  const float* b1;
+  const float* W2;                 // [latent][hidden]
+  const float* b2;
+  const float* W3;                 // [hidden][latent]
+  const float* b3;
+  const float* W4p;                // [npad][hidden] rows >= N zero, k permuted for MFMA
+  const float* b4;                 // [N]
+  const float* mu;                 // [N]
+  const float* rsd;                // [N] 1 / sigma (encoder side)
+  const float* sd;                 // [N] sigma (decoder side)
+  int npad;
+};
+
+struct ResidualArgs {
+  const void* hist;
+  int dtype;
+  long long hs, rs, H;
+  const float* fhat;           // [H][N] or null
+  double tau;
+  int tau_mode;
+  double newton_s;
+  int max_iter, max_iter2, fallback;
+  double* lambda;              // [H][4]
+  uint8_t* flags;              // [H]
+  uint64_t* sizes;             // [H] record bytes
+  uint8_t* slots;              // [H][slot_stride] staging
+  long long slot_stride;
+  uint8_t* kstar;              // [H] 0xff if not coded
+  uint16_t* iters;             // [H]
+};
+
+struct DecompressArgs {
+  const uint8_t* flags;
+  const double* lambda;
+  const uint64_t* offsets;
+  const uint8_t* stream;
+  int in_dtype;
+  long long H;
+  const float* fhat;           // [H][N] or null
+  void* out;
+  int out_dtype;
+  uint64_t capacity;           // bytes of `stream`; records ending past it decode to NaN
+};
+
+// ---- double-double accumulation (exact TwoSum error terms) --------------------------
+struct dd { double hi, lo; };
+
+__device__ __forceinline__ dd two_sum(double a, double b) {
+  double s = a + b;
+  double bb = s - a;
+  double err = (a - (s - bb)) + (b - bb);
+  return {s, err};
+}
+__device__ __forceinline__ dd dd_add_d(dd a, double b) {
+  dd s = two_sum(a.hi, b);
+  s.lo += a.lo;
+  double hi = s.hi + s.lo;
+  double lo = s.lo - (hi - s.hi);
+  return {hi, lo};
+}
+__device__ __forceinline__ dd dd_add(dd a, dd b) {
+  dd s = two_sum(a.hi, b.hi);
+  s.lo += (a.lo + b.lo);
+  double hi = s.hi + s.lo;
+  double lo = s.lo - (hi - s.hi);
+  return {hi, lo};
+}
+
+// ---- wave / block reductions ----------------------------------------------------------
+// Butterflies with xor partners: each stage adds x_l + x_{l^k}, which both partners
+// compute identically (addition commutes exactly), so every lane ends with the same
+// bits and the order is fixed, i.e. results are run-to-run deterministic.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int k = 32; k >= 1; k >>= 1) v = v + __shfl_xor(v, k, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int k = 32; k >= 1; k >>= 1) v = fmax(v, __shfl_xor(v, k, 64));
+  return v;
+}
+__device__ __forceinline__ double wave_min(double v) {
+#pragma unroll
+  for (int k = 32; k >= 1; k >>= 1) v = fmin(v, __shfl_xor(v, k, 64));
+  return v;
+}
+__device__ __forceinline__ uint32_t wave_umax(uint32_t v) {
+#pragma unroll
+  for (int k = 32; k >= 1; k >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, k, 64));
+  return v;
+}
+__device__ __forceinline__ dd wave_dd(dd v) {
+#pragma unroll
+  for (int k = 32; k >= 1; k >>= 1) {
+    dd o{__shfl_xor(v.hi, k, 64), __shfl_xor(v.lo, k, 64)};
+    v = dd_add(v, o);
+  }
+  return v;
+}
+
+// Sum K doubles over the block; every thread gets the same result.  `red` needs
+// NT/64 * K doubles of LDS.  Contains two barriers.
+template <int NT, int K>
+__device__ __forceinline__ void block_sum(double (&v)[K], double* red) {
+  constexpr int NW = NT / 64;
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] = wave_sum(v[k]);
+  if (l == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) red[w * K + k] = v[k];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    double s = red[k];
+#pragma unroll
+    for (int q = 1; q < NW; ++q) s = s + red[q * K + k];
+    v[k] = s;
+  }
+  __syncthreads();
+}
+
+template <int NT>
+__device__ __forceinline__ double block_max(double v, double* red) {
+  constexpr int NW = NT / 64;
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  v = wave_max(v);
+  if (l == 0) red[w] = v;
+  __syncthreads();
+  double s = red[0];
+#pragma unroll
+  for (int q = 1; q < NW; ++q) s = fmax(s, red[q]);
+  __syncthreads();
+  return s;
+}
+
+template <int NT>
+__device__ __forceinline__ dd block_dd(dd v, double* red) {
+  constexpr int NW = NT / 64;
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  v = wave_dd(v);
+  if (l == 0) { red[2 * w] = v.hi; red[2 * w + 1] = v.lo; }
+  __syncthreads();
+  dd s{red[0], red[1]};
+#pragma unroll
+  for (int q = 1; q < NW; ++q) s = dd_add(s, dd{red[2 * q], red[2 * q + 1]});
+  __syncthreads();
+  return s;
+}
+
+// ---- multilevel interpolation ----------------------------------------------------------
+// Per node of the decomposition: the four corner offsets of its interpolation cell and
+// the weights s (along v_par) and t (along v_perp).  A node on a coarse line has the two
+// corners of that line repeated and weight 0 across it; the bilinear formula then
+// reduces exactly to the linear one.
+struct Interp {
+  uint16_t e00, e10, e01, e11;
+  double s, t;
+};
+
+__device__ __forceinline__ Interp make_interp(const GridDev& G, int i, int j) {
+  const int li = G.lev_par[i], lj = G.lev_perp[j];
+  int ia = i, ib = i, ja = j, jb = j;
+  double s = 0.0, t = 0.0;
+  if (li <= lj) { ia = G.a_par[i]; ib = G.b_par[i]; s = G.s_par[i]; }
+  if (lj <= li) { ja = G.a_perp[j]; jb = G.b_perp[j]; t = G.s_perp[j]; }
+  Interp r;
+  r.e00 = (uint16_t)(ja * G.n_par + ia);
+  r.e10 = (uint16_t)(ja * G.n_par + ib);
+  r.e01 = (uint16_t)(jb * G.n_par + ia);
+  r.e11 = (uint16_t)(jb * G.n_par + ib);
+  r.s = s;
+  r.t = t;
+  return r;
+}
+
+// p0 = y00 + s (y10 - y00), p1 = y01 + s (y11 - y01), P = p0 + t (p1 - p0), unfused.
+__device__ __forceinline__ double predict(const double* y, const Interp& c) {
+  const double y00 = y[c.e00], y10 = y[c.e10], y01 = y[c.e01], y11 = y[c.e11];
+  const double p0 = __dadd_rn(y00, __dmul_rn(c.s, __dsub_rn(y10, y00)));
+  const double p1 = __dadd_rn(y01, __dmul_rn(c.s, __dsub_rn(y11, y01)));
+  return __dadd_rn(p0, __dmul_rn(c.t, __dsub_rn(p1, p0)));
+}
+
+// 2^(m/4), m = 0..3, correctly rounded.
+__device__ __forceinline__ double ladder_c(int m) {
+  return m == 0 ? 1.0 : (m == 1 ? 0x1.306fe0a31b715p+0 : (m == 2 ? 0x1.6a09e667f3bcdp+0 : 0x1.ae89f995ad3adp+0));
+}
+__device__ __forceinline__ double ladder(double d0, int k) {
+  return __dmul_rn(ldexp(d0, k >> 2), ladder_c(k & 3));
+}
+
+// Per-cell constraint coefficients vol * phi_k and the correction A^T lambda, in one
+// fixed order shared by compression and decompression.
+struct Aphi { double a0, a1, a2, a3; };
+__device__ __forceinline__ Aphi make_aphi(const GridDev& G, int e, int i, int j) {
+  const double v = G.uniform_vol ? G.vol0 : G.vol[e];
+  const double ap = G.apar[i];
+  Aphi r;
+  r.a0 = v;
+  r.a1 = __dmul_rn(v, ap);
+  r.a2 = __dmul_rn(v, G.cperp[j]);
+  r.a3 = __dmul_rn(r.a1, ap);
+  return r;
+}
+__device__ __forceinline__ double correction(const Aphi& A, const double (&lam)[4]) {
+  double c = __dmul_rn(lam[0], A.a0);
+  c = __dadd_rn(c, __dmul_rn(lam[1], A.a1));
+  c = __dadd_rn(c, __dmul_rn(lam[2], A.a2));
+  return __dadd_rn(c, __dmul_rn(lam[3], A.a3));
+}
+
+// ---- launch functions (defined in the kernel files) -----------------------------------
+hipError_t launch_qoi(const GridDev& G, const void* hist, int dtype, long long H, long long hs,
+                      long long rs, double* b, double* qoi, double* norm, hipStream_t st);
+hipError_t launch_residual(const GridDev& G, const ResidualArgs& a, hipStream_t st);
+hipError_t launch_decompress(const GridDev& G, const DecompressArgs& a, hipStream_t st);
+hipError_t launch_scan(const uint64_t* sizes, uint64_t* offsets, long long H, uint64_t* partial,
+                       hipStream_t st);
+size_t scan_partial_elems(long long H);
+hipError_t launch_compact(const uint8_t* slots, long long slot_stride, const uint64_t* offsets,
+                          const uint64_t* sizes, long long H, uint8_t* out, uint64_t capacity,
+                          hipStream_t st);
+hipError_t launch_stats(const uint8_t* flags, const uint8_t* kstar, const uint16_t* iters,
+                        const uint64_t* offsets, long long H, uint64_t capacity, hcz_stats* stats,
+                        hipStream_t st);
+hipError_t launch_encode(const ModelDev& M, const void* hist, int dtype, long long H, long long hs,
+                         long long rs, int n_par, float* z, hipStream_t st);
+hipError_t launch_decode(const ModelDev& M, const uint8_t* codes, const float* centroids, int bits,
+                         long long H, float* fhat, hipStream_t st);
+hipError_t launch_quantize(const float* z, long long n, int latent, const float* centroids,
+                           int bits, uint8_t* codes, hipStream_t st);
+size_t codebook_ws_bytes(long long n, int latent, long long every);
+hipError_t launch_codebook_fit(const float* z, long long n, int latent, long long every, int bits,
+                               float* centroids, void* ws, hipStream_t st);
+
+}  // namespace hcz

@@ -1,0 +1,269 @@
+// Dense autoencoder evaluation on FP32 matrix cores (Section III Stages 2-3) and the
+// product-quantizer encoder (Stage 3).
+//
+// Encoder: a workgroup takes a tile of 128 histograms and computes
+//   H1 = relu(X W1^T + b1)   [128 x 128], K = N streamed in chunks of 32 through LDS,
+//   z  = H1 W2^T + b2        [128 x 16] on the vector ALUs,
+// where X = (f - mu) / sigma is formed while loading.  Each of the four waves owns a
+// 64 x 64 block of H1 made of 2 x 2 v_mfma_f32_32x32x2f32 tiles.  LDS rows are stored
+// with k permuted (k -> (k & 1) * 16 + k / 2) so that a lane's 16 operands for one chunk
+// are contiguous (four ds_read_b128).
+// Decoder: Zhat = C[codes] -> H3 = relu(Zhat W3^T + b3) (vector ALUs) ->
+//   fhat = sigma (H3 W4^T + b4) + mu, with H3 in LDS (k permuted) and W4 pre-permuted in
+//   device memory, output columns in blocks of 128.  The decoder's arithmetic does not
+//   depend on the launch: compression and decompression run this same kernel and get the
+//   same bits.
+#include "hcz_internal.h"
+
+namespace hcz {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kTile = 128;   // histograms per workgroup
+constexpr int kKc = 32;      // encoder K chunk
+constexpr int kPitch = 36;   // LDS pitch (floats) of an encoder operand row
+constexpr int kHPitch = 132; // LDS pitch of H1 / H3 rows
+
+__device__ __forceinline__ f32x16 mfma32(float a, float b, f32x16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+}
+
+template <typename TIn, bool CONTIG>
+__global__ __launch_bounds__(256, 2) void k_encode(ModelDev M, const TIn* hist, long long H,
+                                                   long long hs, long long rs, int n_par, float* z) {
+  // union: {As, Bs} during the K loop, H1 afterwards
+  __shared__ __attribute__((aligned(16))) float smem[kTile * kHPitch];
+  __shared__ __attribute__((aligned(16))) float W2t[kHidden * kLatent];
+  float* As = smem;
+  float* Bs = smem + kTile * kPitch;
+  const int t = threadIdx.x, w = t >> 6, l = t & 63;
+  const long long h0 = (long long)blockIdx.x * kTile;
+  const int wr = (w >> 1) * 64, wc = (w & 1) * 64;
+  const int li = l & 31, lh = l >> 5;
+  for (int q = t; q < kHidden * kLatent; q += 256) {
+    const int o = q / kHidden, c = q % kHidden;
+    W2t[c * kLatent + o] = M.W2[q];
+  }
+  f32x16 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.0f;
+
+  const int lk = t & 31, lr = t >> 5;
+  const int kp = (lk & 1) * 16 + (lk >> 1);
+  float ra[16], rb[16];
+  const int nchunk = M.kpad / kKc;
+  auto gload = [&](int c) {
+    const int k = c * kKc + lk;
+    const bool kin = k < M.N;
+    const float mu = kin ? M.mu[k] : 0.0f;
+    const float rsd = kin ? M.rsd[k] : 0.0f;
+    const long long koff = CONTIG ? (long long)k : (long long)(k / n_par) * rs + (k % n_par);
+#pragma unroll
+    for (int it = 0; it < 16; ++it) {
+      const int row = it * 8 + lr;
+      const long long h = h0 + row;
+      float v = 0.0f;
+      if (kin && h < H) {
+        float fv = (float)hist[h * hs + koff];
+        if (!isfinite(fv)) fv = 0.0f;
+        v = (fv - mu) * rsd;
+      }
+      ra[it] = v;
+      rb[it] = M.W1p[(long long)row * M.kpad + k];
+    }
+  };
+  gload(0);
+  for (int c = 0; c < nchunk; ++c) {
+#pragma unroll
+    for (int it = 0; it < 16; ++it) {
+      As[(it * 8 + lr) * kPitch + kp] = ra[it];
+      Bs[(it * 8 + lr) * kPitch + kp] = rb[it];
+    }
+    __syncthreads();
+    if (c + 1 < nchunk) gload(c + 1);
+    f32x4 av[2][4], bv[2][4];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const f32x4* pa = (const f32x4*)&As[(wr + q * 32 + li) * kPitch + lh * 16];
+      const f32x4* pb = (const f32x4*)&Bs[(wc + q * 32 + li) * kPitch + lh * 16];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) { av[q][u] = pa[u]; bv[q][u] = pb[u]; }
+    }
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+          acc[a][b] = mfma32(av[a][s >> 2][s & 3], bv[b][s >> 2][s & 3], acc[a][b]);
+    }
+    __syncthreads();
+  }
+  // epilogue 1: H1 = relu(acc + b1) into LDS
+  float* H1 = smem;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const int col = wc + b * 32 + li;
+      const float bias = M.b1[col];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = wr + a * 32 + 8 * (r >> 2) + 4 * lh + (r & 3);
+        H1[row * kHPitch + col] = fmaxf(acc[a][b][r] + bias, 0.0f);
+      }
+    }
+  __syncthreads();
+  // layer 2 on the vector ALUs: 8 latent outputs per thread
+  const int row = t >> 1, o0 = (t & 1) * 8;
+  float s[8];
+#pragma unroll
+  for (int o = 0; o < 8; ++o) s[o] = M.b2[o0 + o];
+  for (int c = 0; c < kHidden; ++c) {
+    const float hv = H1[row * kHPitch + c];
+    const f32x4 w0 = *(const f32x4*)&W2t[c * kLatent + o0];
+    const f32x4 w1 = *(const f32x4*)&W2t[c * kLatent + o0 + 4];
+#pragma unroll
+    for (int o = 0; o < 4; ++o) {
+      s[o] = fmaf(hv, w0[o], s[o]);
+      s[o + 4] = fmaf(hv, w1[o], s[o + 4]);
+    }
+  }
+  const long long h = h0 + row;
+  if (h < H) {
+#pragma unroll
+    for (int o = 0; o < 8; ++o) z[h * kLatent + o0 + o] = s[o];
+  }
+}
+
+__global__ __launch_bounds__(256, 2) void k_decode(ModelDev M, const uint8_t* codes,
+                                                   const float* centroids, int kcb, long long H,
+                                                   float* fhat) {
+  __shared__ __attribute__((aligned(16))) float H3[kTile * kHPitch];
+  __shared__ float Zh[kTile * kLatent];
+  const int t = threadIdx.x, w = t >> 6, l = t & 63;
+  const long long h0 = (long long)blockIdx.x * kTile;
+  const int li = l & 31, lh = l >> 5;
+  for (int q = t; q < kTile * kLatent; q += 256) {
+    const int row = q / kLatent, d = q % kLatent;
+    const long long h = h0 + row;
+    Zh[q] = (h < H) ? centroids[d * kcb + min((int)codes[h * kLatent + d], kcb - 1)] : 0.0f;
+  }
+  __syncthreads();
+  // H3 = relu(Zhat W3^T + b3), stored with k permuted: c -> (c & 1) * 64 + c / 2
+  {
+    const int c = t & 127;
+    float w3[kLatent];
+#pragma unroll
+    for (int d = 0; d < kLatent; ++d) w3[d] = M.W3[c * kLatent + d];
+    const float b3 = M.b3[c];
+    const int cp = (c & 1) * 64 + (c >> 1);
+    for (int row = t >> 7; row < kTile; row += 2) {
+      float s = b3;
+#pragma unroll
+      for (int d = 0; d < kLatent; ++d) s = fmaf(Zh[row * kLatent + d], w3[d], s);
+      H3[row * kHPitch + cp] = fmaxf(s, 0.0f);
+    }
+  }
+  __syncthreads();
+  const int wr = (w >> 1) * 64;
+  for (int nb = 0; nb < M.npad; nb += 128) {
+    const int wc = nb + (w & 1) * 64;
+    f32x16 acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.0f;
+#pragma unroll 1
+    for (int quarter = 0; quarter < 4; ++quarter) {
+      f32x4 av[2][4], bv[2][4];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const f32x4* pa = (const f32x4*)&H3[(wr + q * 32 + li) * kHPitch + lh * 64 + quarter * 16];
+        const f32x4* pb = (const f32x4*)&M.W4p[(long long)(wc + q * 32 + li) * kHidden + lh * 64 + quarter * 16];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) { av[q][u] = pa[u]; bv[q][u] = pb[u]; }
+      }
+#pragma unroll
+      for (int s = 0; s < 16; ++s)
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b)
+            acc[a][b] = mfma32(av[a][s >> 2][s & 3], bv[b][s >> 2][s & 3], acc[a][b]);
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        const int col = wc + b * 32 + li;
+        if (col >= M.N) continue;
+        const float b4 = M.b4[col], sd = M.sd[col], mu = M.mu[col];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int row = wr + a * 32 + 8 * (r >> 2) + 4 * lh + (r & 3);
+          const long long h = h0 + row;
+          if (h < H) fhat[h * M.N + col] = fmaf(sd, acc[a][b][r] + b4, mu);
+        }
+      }
+  }
+}
+
+// code = #{c : (C_c + C_{c+1}) / 2 < z} with the midpoints in FP64: a lower bound search.
+__global__ __launch_bounds__(256) void k_quantize(const float* z, long long n, int latent,
+                                                  const float* centroids, int kcb, uint8_t* codes) {
+  const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (q >= n * latent) return;
+  const int d = (int)(q % latent);
+  const float* C = centroids + (long long)d * kcb;
+  const double zv = (double)z[q];
+  int lo = 0, hi = kcb - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    const double beta = ((double)C[mid] + (double)C[mid + 1]) * 0.5;
+    if (beta < zv) lo = mid + 1;
+    else hi = mid;
+  }
+  codes[q] = (uint8_t)lo;
+}
+
+hipError_t launch_encode(const ModelDev& M, const void* hist, int dtype, long long H, long long hs,
+                         long long rs, int n_par, float* z, hipStream_t st) {
+  if (H <= 0) return hipSuccess;
+  const bool contig = rs == n_par;
+  dim3 grid((unsigned)((H + kTile - 1) / kTile)), block(256);
+  if (dtype == HCZ_F32) {
+    if (contig) hipLaunchKernelGGL((k_encode<float, true>), grid, block, 0, st, M, (const float*)hist, H, hs, rs, n_par, z);
+    else hipLaunchKernelGGL((k_encode<float, false>), grid, block, 0, st, M, (const float*)hist, H, hs, rs, n_par, z);
+  } else {
+    if (contig) hipLaunchKernelGGL((k_encode<double, true>), grid, block, 0, st, M, (const double*)hist, H, hs, rs, n_par, z);
+    else hipLaunchKernelGGL((k_encode<double, false>), grid, block, 0, st, M, (const double*)hist, H, hs, rs, n_par, z);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_decode(const ModelDev& M, const uint8_t* codes, const float* centroids, int bits,
+                         long long H, float* fhat, hipStream_t st) {
+  if (H <= 0) return hipSuccess;
+  dim3 grid((unsigned)((H + kTile - 1) / kTile)), block(256);
+  hipLaunchKernelGGL(k_decode, grid, block, 0, st, M, codes, centroids, 1 << bits, H, fhat);
+  return hipGetLastError();
+}
+
+hipError_t launch_quantize(const float* z, long long n, int latent, const float* centroids,
+                           int bits, uint8_t* codes, hipStream_t st) {
+  const long long tot = n * latent;
+  if (tot <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_quantize, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, z, n, latent,
+                     centroids, 1 << bits, codes);
+  return hipGetLastError();
+}
+
+}  // namespace hcz

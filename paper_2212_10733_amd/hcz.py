@@ -1,0 +1,389 @@
+"""ctypes binding of libhcz (C ABI in include/hcz.h), with torch tensors for device memory.
+
+Every function here marshals arguments and calls the library; all compute runs in the
+HIP kernels.  Import fails loudly if the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhcz.so")
+
+F32, F64 = 0, 1
+ARCH_DENSE = 1
+TAU_REL_L2, TAU_NRMSE = 0, 1
+FALLBACK_BACKTRACK, FALLBACK_PAPER = 0, 1
+FLAG_CODED, FLAG_ROUND2, FLAG_RAW = 1, 2, 4
+HIDDEN, LATENT = 128, 16
+
+STATUS = {0: "HCZ_OK", -1: "HCZ_EINVAL", -2: "HCZ_ENOMEM", -3: "HCZ_EHIP",
+          -4: "HCZ_EUNSUPPORTED", -5: "HCZ_ECAPACITY", -6: "HCZ_EWORKSPACE"}
+
+
+class HczError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Grid(C.Structure):
+    _fields_ = [("n_par", C.c_int32), ("n_perp", C.c_int32), ("vpar_lo", C.c_double),
+                ("vpar_hi", C.c_double), ("vperp_lo", C.c_double), ("vperp_hi", C.c_double),
+                ("mass", C.c_double), ("vol", C.POINTER(C.c_double))]
+
+
+class ModelDesc(C.Structure):
+    _fields_ = [("arch", C.c_int32), ("latent", C.c_int32), ("hidden", C.c_int32),
+                ("weights", C.POINTER(C.c_float)), ("norm_mean", C.POINTER(C.c_float)),
+                ("norm_std", C.POINTER(C.c_float))]
+
+
+class Codebook(C.Structure):
+    _fields_ = [("bits", C.c_int32), ("centroids", C.c_void_p)]
+
+
+class Params(C.Structure):
+    _fields_ = [("tau", C.c_double), ("tau_mode", C.c_int32), ("newton_s", C.c_double),
+                ("newton_max_iter", C.c_int32), ("newton_max_iter2", C.c_int32),
+                ("fallback", C.c_int32), ("fit_codebook", C.c_int32), ("sample_every", C.c_int32)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("n_hist", C.c_uint64), ("n_coded", C.c_uint64), ("n_round2", C.c_uint64),
+                ("n_raw", C.c_uint64), ("stream_bytes", C.c_uint64), ("overflow", C.c_uint64),
+                ("newton_max_iters", C.c_uint64), ("newton_iters_total", C.c_uint64),
+                ("newton_iter_hist", C.c_uint64 * 64), ("kstar_hist", C.c_uint64 * 48)]
+
+    def as_dict(self) -> dict:
+        d = {k: getattr(self, k) for k, _ in self._fields_[:8]}
+        d["newton_iter_hist"] = list(self.newton_iter_hist)
+        d["kstar_hist"] = list(self.kstar_hist)
+        return d
+
+
+class CompressedC(C.Structure):
+    _fields_ = [("codes", C.c_void_p), ("lambda_", C.c_void_p), ("flags", C.c_void_p),
+                ("res_offset", C.c_void_p), ("res_bytes", C.c_void_p),
+                ("res_capacity", C.c_uint64), ("stats", C.c_void_p)]
+
+
+def _load() -> C.CDLL:
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2212_10733_amd.build` "
+                          "(there is no CPU fallback)")
+    lib = C.CDLL(LIB_PATH)
+    vp, i32, i64, sz = C.c_void_p, C.c_int32, C.c_int64, C.c_size_t
+    sig = {
+        "hcz_create": [C.c_int, C.POINTER(vp)],
+        "hcz_plan_create": [vp, C.POINTER(Grid), C.POINTER(vp)],
+        "hcz_model_load": [vp, C.POINTER(ModelDesc), C.POINTER(vp)],
+        "hcz_qoi": [vp, vp, i32, i64, i64, i64, vp, vp, vp, vp],
+        "hcz_encode": [vp, vp, i32, i64, i64, i64, vp, vp],
+        "hcz_codebook_fit_workspace": [i64, i32, i64, C.POINTER(sz)],
+        "hcz_codebook_fit": [vp, i64, i32, i64, C.POINTER(Codebook), vp, sz, vp],
+        "hcz_quantize": [vp, i64, i32, C.POINTER(Codebook), vp, vp],
+        "hcz_decode": [vp, vp, C.POINTER(Codebook), i64, vp, vp],
+        "hcz_residual": [vp, C.POINTER(Params), vp, i32, i64, i64, i64, vp, C.POINTER(CompressedC), vp, sz, vp],
+        "hcz_compress_workspace": [vp, vp, i64, C.POINTER(Params), C.POINTER(sz)],
+        "hcz_decompress_workspace": [vp, vp, i64, C.POINTER(sz)],
+        "hcz_compress": [vp, vp, C.POINTER(Codebook), C.POINTER(Params), vp, i32, i64, i64, i64,
+                         C.POINTER(CompressedC), vp, sz, vp],
+        "hcz_decompress": [vp, vp, C.POINTER(Codebook), C.POINTER(CompressedC), i32, i64, vp, i32, vp, sz, vp],
+        "hcz_stats_read": [vp, C.POINTER(Stats), vp],
+        "hcz_profile_enable": [vp, C.c_int],
+        "hcz_profile_read": [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = C.c_int
+    for name in ("hcz_destroy", "hcz_plan_destroy", "hcz_model_free"):
+        getattr(lib, name).argtypes = [vp]
+        getattr(lib, name).restype = None
+    lib.hcz_last_error.restype = C.c_char_p
+    lib.hcz_version.restype = C.c_char_p
+    return lib
+
+
+LIB = _load()
+
+# Every symbol the C header declares (checked by the CPU tests).
+EXPORTS = ["hcz_create", "hcz_destroy", "hcz_last_error", "hcz_version", "hcz_plan_create",
+           "hcz_plan_destroy", "hcz_model_load", "hcz_model_free", "hcz_qoi", "hcz_encode",
+           "hcz_codebook_fit_workspace", "hcz_codebook_fit", "hcz_quantize", "hcz_decode",
+           "hcz_residual", "hcz_compress_workspace", "hcz_decompress_workspace", "hcz_compress",
+           "hcz_decompress", "hcz_stats_read", "hcz_profile_enable", "hcz_profile_read"]
+
+STAGES = ["encode", "codebook", "quantize", "decode", "residual", "scan", "compact", "stats", "decompress"]
+
+
+def _check(status: int) -> None:
+    if status != 0:
+        raise HczError(status, LIB.hcz_last_error().decode())
+
+
+def _ptr(t: torch.Tensor | None):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dtype_code(t: torch.Tensor) -> int:
+    if t.dtype == torch.float32:
+        return F32
+    if t.dtype == torch.float64:
+        return F64
+    raise TypeError(f"histograms must be float32 or float64, not {t.dtype}")
+
+
+def _strides(hist: torch.Tensor):
+    if hist.dim() != 3:
+        raise ValueError("hist must be (H, n_perp, n_par)")
+    if hist.stride(2) != 1:
+        raise ValueError("the v_par axis must be contiguous")
+    return hist.shape[0], hist.stride(0), hist.stride(1)
+
+
+class Context:
+    def __init__(self, device: int = 0):
+        h = C.c_void_p()
+        _check(LIB.hcz_create(device, C.byref(h)))
+        self.h = h
+        self.device = device
+
+    def profile(self, enable: bool = True) -> None:
+        _check(LIB.hcz_profile_enable(self.h, int(enable)))
+
+    def profile_read(self) -> dict:
+        """{stage: (total ms, calls)} since the last read (waits for the recorded events)."""
+        ms = (C.c_double * len(STAGES))()
+        calls = (C.c_int64 * len(STAGES))()
+        _check(LIB.hcz_profile_read(self.h, ms, calls))
+        return {s: (ms[i], calls[i]) for i, s in enumerate(STAGES)}
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            LIB.hcz_destroy(self.h)
+            self.h = None
+
+
+class Plan:
+    """Device tables of one velocity grid."""
+
+    def __init__(self, ctx: Context, n_par=39, n_perp=39, vpar=(-4.0, 4.0), vperp=(0.0, 4.0),
+                 mass=1.0, vol: np.ndarray | None = None):
+        self.ctx = ctx
+        self.n_par, self.n_perp = n_par, n_perp
+        self.N = n_par * n_perp
+        self._vol = None if vol is None else np.ascontiguousarray(vol, np.float64).reshape(-1)
+        g = Grid(n_par, n_perp, vpar[0], vpar[1], vperp[0], vperp[1], mass,
+                 None if self._vol is None else self._vol.ctypes.data_as(C.POINTER(C.c_double)))
+        h = C.c_void_p()
+        _check(LIB.hcz_plan_create(ctx.h, C.byref(g), C.byref(h)))
+        self.h = h
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            LIB.hcz_plan_destroy(self.h)
+            self.h = None
+
+
+def pack_dense_weights(W: dict) -> np.ndarray:
+    return np.concatenate([np.ascontiguousarray(W[k], np.float32).ravel()
+                           for k in ("W1", "b1", "W2", "b2", "W3", "b3", "W4", "b4")])
+
+
+class Model:
+    """A dense autoencoder copied to the device for one plan."""
+
+    def __init__(self, plan: Plan, W: dict, mu: np.ndarray, sd: np.ndarray):
+        self.plan = plan
+        blob = pack_dense_weights(W)
+        mu = np.ascontiguousarray(mu, np.float32)
+        sd = np.ascontiguousarray(sd, np.float32)
+        fp = C.POINTER(C.c_float)
+        d = ModelDesc(ARCH_DENSE, LATENT, HIDDEN, blob.ctypes.data_as(fp), mu.ctypes.data_as(fp),
+                      sd.ctypes.data_as(fp))
+        h = C.c_void_p()
+        _check(LIB.hcz_model_load(plan.h, C.byref(d), C.byref(h)))
+        self.h = h
+        self.latent = LATENT
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            LIB.hcz_model_free(self.h)
+            self.h = None
+
+
+def params(tau=1e-3, tau_mode=TAU_REL_L2, newton_s=1.0, newton_max_iter=50, newton_max_iter2=400,
+           fallback=FALLBACK_BACKTRACK, fit_codebook=False, sample_every=16) -> Params:
+    return Params(tau, tau_mode, newton_s, newton_max_iter, newton_max_iter2, fallback,
+                  int(fit_codebook), sample_every)
+
+
+@dataclass
+class Compressed:
+    codes: torch.Tensor        # (H, latent) uint8
+    lam: torch.Tensor          # (H, 4) float64
+    flags: torch.Tensor        # (H,) uint8
+    offsets: torch.Tensor      # (H + 1,) int64 (u64 bits)
+    stream: torch.Tensor       # (capacity,) uint8
+    stats_dev: torch.Tensor    # sizeof(hcz_stats) bytes
+
+    def cstruct(self) -> CompressedC:
+        return CompressedC(self.codes.data_ptr(), self.lam.data_ptr(), self.flags.data_ptr(),
+                           self.offsets.data_ptr(), self.stream.data_ptr(), self.stream.numel(),
+                           self.stats_dev.data_ptr())
+
+    def stats(self) -> dict:
+        s = Stats()
+        st = LIB.hcz_stats_read(C.c_void_p(self.stats_dev.data_ptr()), C.byref(s), _stream())
+        d = s.as_dict()
+        if st not in (0, -5):
+            _check(st)
+        return d
+
+    def stream_bytes(self) -> bytes:
+        n = int(self.offsets[-1].item())
+        return bytes(self.stream[:n].cpu().numpy().tobytes())
+
+
+def alloc_compressed(H: int, N: int, device, latent=LATENT, capacity: int | None = None,
+                     in_bytes: int = 4) -> Compressed:
+    if capacity is None:
+        capacity = H * (24 + in_bytes * N)
+    return Compressed(
+        codes=torch.zeros((H, latent), dtype=torch.uint8, device=device),
+        lam=torch.zeros((H, 4), dtype=torch.float64, device=device),
+        flags=torch.zeros(H, dtype=torch.uint8, device=device),
+        offsets=torch.zeros(H + 1, dtype=torch.int64, device=device),
+        stream=torch.empty(max(capacity, 16), dtype=torch.uint8, device=device),
+        stats_dev=torch.zeros(C.sizeof(Stats), dtype=torch.uint8, device=device),
+    )
+
+
+def workspace(nbytes: int, device) -> torch.Tensor:
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+# ---- stage entry points --------------------------------------------------------------
+
+def qoi(plan: Plan, hist: torch.Tensor):
+    H, hs, rs = _strides(hist)
+    dev = hist.device
+    b = torch.empty((H, 4), dtype=torch.float64, device=dev)
+    q = torch.empty((H, 4), dtype=torch.float64, device=dev)
+    n = torch.empty(H, dtype=torch.float64, device=dev)
+    _check(LIB.hcz_qoi(plan.h, _ptr(hist), _dtype_code(hist), H, hs, rs, _ptr(b), _ptr(q), _ptr(n), _stream()))
+    return b, q, n
+
+
+def encode(model: Model, hist: torch.Tensor) -> torch.Tensor:
+    H, hs, rs = _strides(hist)
+    z = torch.empty((H, model.latent), dtype=torch.float32, device=hist.device)
+    _check(LIB.hcz_encode(model.h, _ptr(hist), _dtype_code(hist), H, hs, rs, _ptr(z), _stream()))
+    return z
+
+
+def codebook_fit(z: torch.Tensor, bits: int = 8, sample_every: int = 1) -> torch.Tensor:
+    z = z.contiguous()
+    n, L = z.shape
+    nbytes = C.c_size_t()
+    _check(LIB.hcz_codebook_fit_workspace(n, L, sample_every, C.byref(nbytes)))
+    ws = workspace(nbytes.value, z.device)
+    cent = torch.empty((L, 1 << bits), dtype=torch.float32, device=z.device)
+    cb = Codebook(bits, cent.data_ptr())
+    _check(LIB.hcz_codebook_fit(_ptr(z), n, L, sample_every, C.byref(cb), _ptr(ws), ws.numel(), _stream()))
+    return cent
+
+
+def _cb(centroids: torch.Tensor) -> Codebook:
+    k = centroids.shape[1]
+    bits = int(k).bit_length() - 1
+    if 1 << bits != k:
+        raise ValueError("codebook size must be a power of two")
+    return Codebook(bits, centroids.data_ptr())
+
+
+def quantize(z: torch.Tensor, centroids: torch.Tensor) -> torch.Tensor:
+    z = z.contiguous()
+    n, L = z.shape
+    codes = torch.empty((n, L), dtype=torch.uint8, device=z.device)
+    cb = _cb(centroids)
+    _check(LIB.hcz_quantize(_ptr(z), n, L, C.byref(cb), _ptr(codes), _stream()))
+    return codes
+
+
+def decode(model: Model, codes: torch.Tensor, centroids: torch.Tensor) -> torch.Tensor:
+    H = codes.shape[0]
+    out = torch.empty((H, model.plan.n_perp, model.plan.n_par), dtype=torch.float32, device=codes.device)
+    cb = _cb(centroids)
+    _check(LIB.hcz_decode(model.h, _ptr(codes.contiguous()), C.byref(cb), H, _ptr(out), _stream()))
+    return out
+
+
+def residual(plan: Plan, p: Params, hist: torch.Tensor, fhat: torch.Tensor | None,
+             capacity: int | None = None) -> Compressed:
+    H, hs, rs = _strides(hist)
+    nbytes = C.c_size_t()
+    _check(LIB.hcz_compress_workspace(plan.h, None, H, C.byref(p), C.byref(nbytes)))
+    ws = workspace(nbytes.value, hist.device)
+    out = alloc_compressed(H, plan.N, hist.device, capacity=capacity, in_bytes=hist.element_size())
+    cs = out.cstruct()
+    fh = None if fhat is None else fhat.contiguous()
+    _check(LIB.hcz_residual(plan.h, C.byref(p), _ptr(hist), _dtype_code(hist), H, hs, rs, _ptr(fh),
+                            C.byref(cs), _ptr(ws), ws.numel(), _stream()))
+    out._ws = ws
+    return out
+
+
+# ---- whole path ------------------------------------------------------------------------
+
+class Compressor:
+    """Preallocated compress/decompress for batches of up to H histograms (no allocation per call)."""
+
+    def __init__(self, plan: Plan, model: Model | None, H: int, p: Params, bits: int = 8,
+                 in_dtype=torch.float32, capacity: int | None = None, device="cuda"):
+        self.plan, self.model, self.H, self.p = plan, model, H, p
+        nbytes = C.c_size_t()
+        _check(LIB.hcz_compress_workspace(plan.h, None if model is None else model.h, H, C.byref(p),
+                                          C.byref(nbytes)))
+        self.ws = workspace(nbytes.value, device)
+        _check(LIB.hcz_decompress_workspace(plan.h, None if model is None else model.h, H, C.byref(nbytes)))
+        self.dws = workspace(nbytes.value, device)
+        esz = 4 if in_dtype == torch.float32 else 8
+        self.out = alloc_compressed(H, plan.N, device, capacity=capacity, in_bytes=esz)
+        self.centroids = torch.zeros((LATENT, 1 << bits), dtype=torch.float32, device=device)
+        self.bits = bits
+
+    def compress(self, hist: torch.Tensor) -> Compressed:
+        H, hs, rs = _strides(hist)
+        if H > self.H:
+            raise ValueError("batch larger than the compressor was sized for")
+        cb = Codebook(self.bits, self.centroids.data_ptr())
+        cs = self.out.cstruct()
+        _check(LIB.hcz_compress(self.plan.h, None if self.model is None else self.model.h, C.byref(cb),
+                                C.byref(self.p), _ptr(hist), _dtype_code(hist), H, hs, rs, C.byref(cs),
+                                _ptr(self.ws), self.ws.numel(), _stream()))
+        return self.out
+
+    def decompress(self, comp: Compressed, H: int, in_dtype=torch.float32,
+                   out_dtype=torch.float64) -> torch.Tensor:
+        out = torch.empty((H, self.plan.n_perp, self.plan.n_par), dtype=out_dtype, device=comp.lam.device)
+        return self.decompress_into(comp, H, out, in_dtype)
+
+    def decompress_into(self, comp: Compressed, H: int, out: torch.Tensor, in_dtype=torch.float32):
+        cb = Codebook(self.bits, self.centroids.data_ptr())
+        cs = comp.cstruct()
+        _check(LIB.hcz_decompress(self.plan.h, None if self.model is None else self.model.h, C.byref(cb),
+                                  C.byref(cs), F32 if in_dtype == torch.float32 else F64, H, _ptr(out),
+                                  _dtype_code(out), _ptr(self.dws), self.dws.numel(), _stream()))
+        return out

@@ -1,0 +1,327 @@
+"""Stage parity of the HIP path against the oracle on identical seeded inputs (GPU).
+
+Each stage gets its inputs from the generator, never from another GPU stage, so the
+oracle never consumes HIP output.  Integer results are compared bit for bit; floating
+point within tolerances stated next to each comparison.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import coder, grid, moments, pipeline, pq
+from paper_2212_10733_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def H():
+    from paper_2212_10733_amd import hcz
+    return hcz
+
+
+@pytest.fixture(scope="module")
+def ctx(H):
+    return H.Context(0)
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+def to_dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+# ---- moments / QoIs -------------------------------------------------------------------------
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("shape,vol", [((39, 39), None), ((39, 39), "jacobian"), ((33, 37), None), ((65, 65), None)])
+def test_qoi_parity(H, ctx, dtype, shape, vol):
+    n_perp, n_par = shape
+    say("qoi", dtype.__name__, shape, vol)
+    g = grid.make_grid(n_par, n_perp, vol=vol)
+    plan = H.Plan(ctx, n_par, n_perp, vol=None if vol is None else g.vol)
+    F = synth.histograms(300, n_par, n_perp, seed=21, dtype=dtype)
+    b, q, nrm = H.qoi(plan, to_dev(F))
+    torch.cuda.synchronize()
+    b, q, nrm = b.cpu().numpy(), q.cpu().numpy(), nrm.cpu().numpy()
+    bo = moments.moments(F, g)
+    assert np.allclose(b, bo, rtol=1e-13, atol=1e-15 * np.abs(bo).max())
+    assert np.allclose(q, moments.qoi_from_moments(bo, g), rtol=1e-12, atol=1e-14)
+    # ||f|| is the correctly rounded sqrt of the correctly rounded sum of rounded squares
+    X = F.reshape(300, -1).astype(np.float64)
+    ref = np.array([math.sqrt(math.fsum(x * x)) for x in X])
+    assert np.array_equal(nrm, ref)
+
+
+# ---- quantizer -------------------------------------------------------------------------------
+
+def test_quantize_bit_exact(H, ctx):
+    say("quantize")
+    Z = synth.latents(5000, 16, seed=22)
+    C = synth.sorted_codebook(16, 8, seed=23)
+    C[3, 10] = C[3, 11]                      # duplicate centroid
+    beta = (C[:, :-1].astype(np.float64) + C[:, 1:]) * 0.5
+    exact = beta.astype(np.float32).astype(np.float64) == beta
+    Z[:40, 5] = beta[5][exact[5]][:40].astype(np.float32) if exact[5].sum() >= 40 else Z[:40, 5]
+    Z[40, :] = np.nan
+    Z[41, :] = np.inf
+    Z[42, :] = -np.inf
+    got = H.quantize(to_dev(Z), to_dev(C)).cpu().numpy()
+    assert np.array_equal(got, pq.encode(Z, C))
+
+
+@pytest.mark.parametrize("n,bits,every", [(4096, 8, 1), (20000, 4, 16), (777, 6, 3), (100, 8, 1)])
+def test_codebook_fit(H, ctx, n, bits, every):
+    say("codebook", n, bits, every)
+    Z = synth.latents(n, 16, seed=24)
+    got = H.codebook_fit(to_dev(Z), bits, every).cpu().numpy()
+    ref = pq.fit(Z, bits, every)
+    scale = np.abs(Z).max()
+    # same Lloyd path: centroids agree to FP32 rounding of means summed in different orders
+    close = np.isclose(got, ref, rtol=0, atol=4 * np.finfo(np.float32).eps * scale)
+    assert close.mean() > 0.999, close.mean()
+    assert np.all(np.diff(got, axis=1) >= 0)
+
+
+# ---- autoencoder -----------------------------------------------------------------------------
+
+def dense_model(H, plan, F, seed=0):
+    W = synth.dense_ae_weights(plan.N, seed=seed)
+    rng = np.random.default_rng(seed + 100)
+    for k in ("b1", "b2", "b3", "b4"):
+        W[k] = rng.normal(0, 0.05, W[k].shape).astype(np.float32)
+    mu, sd = oracle.ae.norm_stats(F)
+    return W, mu.astype(np.float32), sd.astype(np.float32), H.Model(plan, W, mu, sd)
+
+
+@pytest.mark.parametrize("Hn,dtype,shape", [(300, np.float32, (39, 39)), (129, np.float64, (39, 39)),
+                                            (1000, np.float32, (33, 33)), (50, np.float32, (65, 65))])
+def test_encode_parity(H, ctx, Hn, dtype, shape):
+    n_perp, n_par = shape
+    say("encode", Hn, dtype.__name__, shape)
+    plan = H.Plan(ctx, n_par, n_perp)
+    F = synth.histograms(Hn, n_par, n_perp, seed=25, dtype=dtype)
+    W, mu, sd, model = dense_model(H, plan, F)
+    z = H.encode(model, to_dev(F)).cpu().numpy()
+    X = (F.reshape(Hn, -1).astype(np.float32).astype(np.float64) - mu) / sd
+    zo = oracle.ae.dense_encode(X, W)
+    # FP32 products and sums over K = N terms: error ~ sqrt(K) eps32 sum|terms|
+    h1 = np.maximum(X @ W["W1"].T.astype(np.float64) + W["b1"], 0)
+    mag = np.abs(h1) @ np.abs(W["W2"].T.astype(np.float64)) + (np.abs(X) @ np.abs(W["W1"].T.astype(np.float64))).max() * 0.01
+    assert np.all(np.abs(z - zo) <= 5e-5 * (mag + 1e-3)), np.abs(z - zo).max()
+
+
+@pytest.mark.parametrize("Hn,shape", [(300, (39, 39)), (1000, (33, 33)), (50, (65, 65))])
+def test_decode_parity(H, ctx, Hn, shape):
+    n_perp, n_par = shape
+    say("decode", Hn, shape)
+    plan = H.Plan(ctx, n_par, n_perp)
+    F = synth.histograms(64, n_par, n_perp, seed=26, dtype=np.float32)
+    W, mu, sd, model = dense_model(H, plan, F)
+    C = synth.sorted_codebook(16, 8, seed=27)
+    codes = synth.codes(Hn, 16, 8, seed=28)
+    fh = H.decode(model, to_dev(codes), to_dev(C)).cpu().numpy().reshape(Hn, -1)
+    Zh = pq.decode(codes, C)
+    ref = oracle.ae.denormalize(oracle.ae.dense_decode(Zh, W), mu.astype(np.float64), sd.astype(np.float64))
+    h3 = np.maximum(Zh @ W["W3"].T.astype(np.float64) + W["b3"], 0)
+    mag = sd * (np.abs(h3) @ np.abs(W["W4"].T.astype(np.float64)) + np.abs(W["b4"])) + np.abs(mu)
+    assert np.all(np.abs(fh - ref) <= 2e-5 * mag + 1e-30), np.abs(fh - ref).max()
+
+
+# ---- residual coder + Newton -------------------------------------------------------------------
+
+def oracle_residual(F, fhat, g, p):
+    """Oracle compress with a given reconstruction (the coder-only pipeline when fhat is None)."""
+    class _M:   # pipeline hook: a fixed reconstruction instead of the autoencoder
+        pass
+    Hn = F.shape[0]
+    F64 = F.astype(np.float64)
+    lay = coder.layout(g.n_par, g.n_perp)
+    fh = np.zeros_like(F64) if fhat is None else fhat.astype(np.float64)
+    finite = np.isfinite(F64).reshape(Hn, -1).all(axis=1)
+    Fz = np.where(finite[:, None, None], F64, 0.0)
+    b = moments.moments(Fz, g)
+    th = pipeline.tau_h(Fz, p)
+    r = Fz - fh
+    thr = coder.SEL_MARGIN * th
+    rr = coder.sumsq(r)
+    coded = rr > thr * thr
+    raw = ~finite | ~(b[:, 0] > 0) | (coded & ~(th > 0))
+    out = dict(flags=np.zeros(Hn, np.uint8), lam=np.zeros((Hn, 4)), records=[], kstar=np.full(Hn, 255),
+               margin=np.full(Hn, np.inf), iters=np.zeros(Hn, int))
+    d0 = coder.delta0(th, lay)
+    for h in range(Hn):
+        rec = b""
+        if not raw[h] and coded[h]:
+            d = coder.decompose(r[h:h + 1], lay)
+            if np.abs(d).max() * (1.0 / d0[h]) >= coder.QMAX:
+                raw[h] = True
+            else:
+                ks, q, rh = coder.bisect(r[h:h + 1], d, d0[h:h + 1], thr[h:h + 1], lay)
+                out["kstar"][h] = ks[0]
+                rec = coder.pack(q[0], coder.ladder(d0[h:h + 1], ks)[0], int(ks[0]), lay)
+                # distance of every feasibility decision on the search path from its threshold
+                m = abs(rr[h] - thr[h] ** 2) / thr[h] ** 2
+                lo, hi = 0, coder.NLADDER
+                while hi - lo > 1:
+                    mid = (lo + hi) // 2
+                    Dk = coder.ladder(d0[h:h + 1], np.array([mid]))
+                    qq = coder.quantize(d, Dk)
+                    e2 = coder.sumsq(r[h:h + 1] - coder.reconstruct(qq, Dk, lay))[0]
+                    m = min(m, abs(e2 - thr[h] ** 2) / thr[h] ** 2)
+                    lo, hi = (mid, hi) if e2 <= thr[h] ** 2 else (lo, mid)
+                out["margin"][h] = m
+                fh[h] = fh[h] + rh[0]
+        elif not raw[h]:
+            out["margin"][h] = abs(rr[h] - thr[h] ** 2) / max(thr[h] ** 2, 1e-300)
+        flag = 0
+        if not raw[h]:
+            res = oracle.newton.project(fh[h], b[h], g, p.newton_s, p.newton_max_iter, p.newton_max_iter2, p.fallback)
+            out["iters"][h] = res["iters"]
+            if res["status"] >= 1:
+                flag |= pipeline.FLAG_ROUND2
+            if res["status"] == 2:
+                raw[h] = True
+            else:
+                out["lam"][h] = res["lam"]
+                flag |= pipeline.FLAG_CODED if coded[h] else 0
+        if raw[h]:
+            flag = (flag & pipeline.FLAG_ROUND2) | pipeline.FLAG_RAW
+            rec = np.ascontiguousarray(F[h]).tobytes()
+            out["kstar"][h] = 255
+        out["flags"][h] = flag
+        out["records"].append(rec)
+    out["raw"] = raw
+    out["b"] = b
+    out["tau_h"] = th
+    return out
+
+
+def compare_residual(H, plan, g, F, fhat, p, hp, near_tie=1e-9):
+    Hn = F.shape[0]
+    comp = H.residual(plan, hp, to_dev(F), None if fhat is None else to_dev(fhat))
+    torch.cuda.synchronize()
+    flags = comp.flags.cpu().numpy()
+    lam = comp.lam.cpu().numpy()
+    off = comp.offsets.cpu().numpy().astype(np.uint64)
+    stream = comp.stream_bytes()
+    st = comp.stats()
+    ref = oracle_residual(F, fhat, g, p)
+    sure = ref["margin"] > near_tie          # decisions that rounding order cannot flip
+    assert np.array_equal(flags[sure], ref["flags"][sure])
+    assert (~sure).sum() <= max(1, Hn // 1000)
+    nrec_equal = 0
+    for h in np.nonzero(sure)[0]:
+        rec = stream[int(off[h]):int(off[h + 1])]
+        assert rec == ref["records"][h], (h, len(rec), len(ref["records"][h]))
+        nrec_equal += 1
+    assert int(off[-1]) == len(stream) == st["stream_bytes"]
+    ok = sure & ~ref["raw"]
+    scale = np.abs(ref["lam"][ok]).max() if ok.any() else 1.0
+    assert np.allclose(lam[ok], ref["lam"][ok], rtol=1e-7, atol=1e-9 * scale)
+    assert st["n_hist"] == Hn
+    assert st["n_coded"] == int((flags & 1).sum()) and st["n_raw"] == int(((flags & 4) != 0).sum())
+    return comp, ref, nrec_equal
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+@pytest.mark.parametrize("Hn", [257, 64])
+def test_residual_bit_exact_with_reconstruction(H, ctx, dtype, Hn):
+    say("residual", dtype.__name__, Hn)
+    g = grid.make_grid()
+    plan = H.Plan(ctx)
+    F = synth.histograms(Hn, seed=29, dtype=dtype)
+    rel = np.geomspace(1e-5, 1e-1, Hn)
+    fhat = synth.perturbed(F, rel, seed=30, dtype=np.float32)
+    p = pipeline.Params(tau=1e-3)
+    comp, ref, n = compare_residual(H, plan, g, F, fhat, p, H.params(tau=1e-3))
+    coded = (comp.flags.cpu().numpy() & 1) != 0
+    assert 0 < coded.sum() < Hn                  # both kinds present
+
+
+@pytest.mark.parametrize("shape,vol", [((39, 39), None), ((33, 33), None), ((49, 49), "jacobian"),
+                                       ((65, 65), None), ((37, 33), None), ((3, 3), None), ((12, 5), None)])
+@pytest.mark.parametrize("tau", [1e-2, 1e-4])
+def test_residual_coder_only_grids(H, ctx, shape, vol, tau):
+    n_perp, n_par = shape
+    say("coder-only", shape, vol, tau)
+    g = grid.make_grid(n_par, n_perp, vol=vol)
+    plan = H.Plan(ctx, n_par, n_perp, vol=None if vol is None else g.vol)
+    F = synth.histograms(67, n_par, n_perp, seed=31, dtype=np.float32)
+    compare_residual(H, plan, g, F, None, pipeline.Params(tau=tau), H.params(tau=tau))
+
+
+def test_residual_nrmse_mode_and_edge_cases(H, ctx):
+    say("edge cases")
+    g = grid.make_grid()
+    plan = H.Plan(ctx)
+    F = synth.histograms(40, seed=32, dtype=np.float32)
+    F[0, 2, 3] = np.nan
+    F[1] = 0.0
+    F[2, 5, 5] = np.inf
+    F[3] = 0.0
+    F[3, 10, 10] = 1.0            # single cell: singular Hessian after a large perturbation
+    fhat = synth.perturbed(F, 0.02, seed=33)
+    fhat[3] = 0.0
+    fhat[3, 12, 12] = 1.0
+    p = pipeline.Params(tau=1e-3, tau_mode="nrmse")
+    comp, ref, _ = compare_residual(H, plan, g, F, np.nan_to_num(fhat), p, H.params(tau=1e-3, tau_mode=H.TAU_NRMSE))
+    flags = comp.flags.cpu().numpy()
+    assert flags[0] & 4 and flags[1] & 4 and flags[2] & 4 and flags[3] & 4
+
+
+def test_residual_tau_zero_and_forced_fallbacks(H, ctx):
+    g = grid.make_grid()
+    plan = H.Plan(ctx)
+    F = synth.histograms(20, seed=34, dtype=np.float32)
+    say("tau=0")
+    compare_residual(H, plan, g, F, None, pipeline.Params(tau=0.0), H.params(tau=0.0))
+    say("max_iter=0")
+    p = pipeline.Params(tau=1e-2, newton_max_iter=0, newton_max_iter2=0)
+    comp, _, _ = compare_residual(H, plan, g, F, None, p, H.params(tau=1e-2, newton_max_iter=0, newton_max_iter2=0))
+    assert np.all(comp.flags.cpu().numpy() == 6)
+    say("paper fallback")
+    p = pipeline.Params(tau=1e-2, newton_max_iter=1, newton_max_iter2=400, fallback="paper")
+    compare_residual(H, plan, g, F, None, p, H.params(tau=1e-2, newton_max_iter=1, fallback=H.FALLBACK_PAPER))
+
+
+def test_residual_overflow_capacity(H, ctx):
+    say("capacity")
+    plan = H.Plan(ctx)
+    F = synth.histograms(16, seed=35, dtype=np.float32)
+    comp = H.residual(plan, H.params(tau=1e-3), to_dev(F), None, capacity=1000)
+    with pytest.raises(H.HczError) as e:
+        import ctypes
+        s = H.Stats()
+        st = H.LIB.hcz_stats_read(ctypes.c_void_p(comp.stats_dev.data_ptr()), ctypes.byref(s), None)
+        H._check(st)
+    assert e.value.status == -5
+    assert s.overflow == 1 and s.stream_bytes > 1000
+
+
+# ---- decompression ------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_decompress_reads_oracle_stream(H, ctx, dtype):
+    """The GPU decompressor rebuilds the oracle's own compressed stream (coder-only pipeline)."""
+    say("decompress oracle stream", dtype.__name__)
+    g = grid.make_grid()
+    plan = H.Plan(ctx)
+    F = synth.histograms(50, seed=36, dtype=dtype)
+    F[7, 1, 1] = np.nan
+    comp = pipeline.compress(F, g, None, None, pipeline.Params(tau=1e-3))
+    ref = pipeline.decompress(comp, g, None, None, 50, dtype)
+    cmp_ = H.alloc_compressed(50, plan.N, "cuda", capacity=len(comp["stream"]) + 16)
+    cmp_.flags.copy_(torch.from_numpy(comp["flags"]))
+    cmp_.lam.copy_(torch.from_numpy(comp["lam"]))
+    cmp_.offsets.copy_(torch.from_numpy(comp["offsets"].astype(np.int64)))
+    cmp_.stream[:len(comp["stream"])].copy_(torch.frombuffer(bytearray(comp["stream"]), dtype=torch.uint8))
+    cz = H.Compressor(plan, None, 50, H.params(), in_dtype=torch.float32 if dtype == np.float32 else torch.float64)
+    out = cz.decompress(cmp_, 50, in_dtype=torch.float32 if dtype == np.float32 else torch.float64).cpu().numpy()
+    both_nan = np.isnan(out) & np.isnan(ref)
+    assert np.all(both_nan | np.isclose(out, ref, rtol=1e-13, atol=1e-15 * np.nanmax(np.abs(ref))))
