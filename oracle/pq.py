@@ -23,9 +23,13 @@ def midpoints(C: np.ndarray) -> np.ndarray:
 
 
 def assign_1d(z: np.ndarray, C: np.ndarray) -> np.ndarray:
-    """#{c : beta_c < z} for every z (C sorted, FP64)."""
+    """#{c : beta_c < z} for every z (C sorted, so the midpoints are sorted and a left
+    binary search returns exactly that count)."""
     beta = midpoints(C)
-    return (beta[None, :] < np.asarray(z, np.float64)[:, None]).sum(axis=1)
+    z = np.asarray(z, np.float64)
+    a = np.searchsorted(beta, z, side="left")
+    a[np.isnan(z)] = 0            # no midpoint is below NaN
+    return a
 
 
 def fit_1d(sample: np.ndarray, k: int, max_iter: int = 25):
@@ -39,10 +43,8 @@ def fit_1d(sample: np.ndarray, k: int, max_iter: int = 25):
         a = assign_1d(s, C)
         if prev is not None and np.array_equal(a, prev):
             break
-        for c in range(k):
-            mem = s[a == c]
-            if mem.size:
-                C[c] = mem.mean()
+        for c in np.unique(a):
+            C[c] = s[a == c].mean()
         prev = a
         updates += 1
     return C, updates

@@ -1,0 +1,203 @@
+"""End-to-end parity of hcz_compress / hcz_decompress against the oracle (GPU).
+
+Both sides start from the same generator output and model.  The autoencoder runs in FP32
+on the GPU and FP64 in the oracle, so codes may differ only where the oracle's latent sits
+within the stated tolerance of a midpoint (counted, bounded); the bound and the QoIs must
+hold on the GPU's own output for every histogram.  In the coder-only pipeline (no model)
+every record must match the oracle's bit for bit, also at the full 2^20 batch.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import grid, moments, pipeline, pq
+from paper_2212_10733_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def H():
+    from paper_2212_10733_amd import hcz
+    return hcz
+
+
+@pytest.fixture(scope="module")
+def ctx(H):
+    return H.Context(0)
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+def check_roundtrip(F, out, flags, tau, g, qtol=1e-10):
+    F64 = F.astype(np.float64)
+    Hn = F.shape[0]
+    th = pipeline.tau_h(F64, pipeline.Params(tau=tau))
+    raw = (flags & 4) != 0
+    dist = np.sqrt(((out - F64) ** 2).reshape(Hn, -1).sum(1))
+    assert np.all(dist[~raw] <= th[~raw]), (dist[~raw] / th[~raw]).max()
+    assert np.array_equal(out[raw], F64[raw])
+    q0 = moments.qoi(F64, g)
+    q1 = moments.qoi(out, g)
+    err = moments.qoi_rel_error(q0, q1, g)[~raw]
+    assert err.max() < qtol, err.max()
+    return dist, th
+
+
+def near_tie_codes(z_or, C_or, C_gpu, tol):
+    """Mask of (h, d) where the oracle latent lies within tol of a midpoint of either codebook."""
+    near = np.zeros(z_or.shape, bool)
+    for C in (C_or, C_gpu):
+        beta = pq.midpoints(C)
+        for d in range(z_or.shape[1]):
+            idx = np.searchsorted(beta[d], z_or[:, d])
+            lo = np.abs(z_or[:, d] - beta[d][np.clip(idx - 1, 0, beta.shape[1] - 1)])
+            hi = np.abs(z_or[:, d] - beta[d][np.clip(idx, 0, beta.shape[1] - 1)])
+            near[:, d] |= np.minimum(lo, hi) <= tol[d]
+    return near
+
+
+@pytest.mark.parametrize("Hn,dtype,every,bits", [(256, np.float64, 1, 8), (3001, np.float32, 16, 8),
+                                                 (1000, np.float32, 4, 4)])
+def test_compress_with_model(H, ctx, Hn, dtype, every, bits):
+    say("e2e model", Hn, dtype.__name__, every, bits)
+    g = grid.make_grid()
+    F = synth.histograms(Hn, seed=synth.SEED_PLAIN_SMALL, dtype=dtype)
+    W = synth.dense_ae_weights()
+    mu, sd = oracle.ae.norm_stats(F)
+    mu, sd = mu.astype(np.float32), sd.astype(np.float32)
+    plan = H.Plan(ctx)
+    model = H.Model(plan, W, mu, sd)
+    tdt = torch.float64 if dtype == np.float64 else torch.float32
+    cz = H.Compressor(plan, model, Hn, H.params(tau=1e-3, fit_codebook=True, sample_every=every), bits=bits, in_dtype=tdt)
+    x = torch.from_numpy(F).cuda()
+    comp = cz.compress(x)
+    out = cz.decompress(comp, Hn, in_dtype=tdt).cpu().numpy()
+    st = comp.stats()
+    flags = comp.flags.cpu().numpy()
+    codes = comp.codes.cpu().numpy()
+    Cg = cz.centroids.cpu().numpy()
+    check_roundtrip(F, out, flags, 1e-3, g)
+    assert st["n_hist"] == Hn and st["overflow"] == 0
+    # oracle pipeline on the same inputs
+    model_o = dict(W=W, mu=mu.astype(np.float64), sd=sd.astype(np.float64))
+    ref = pipeline.compress(F, g, model_o, None, pipeline.Params(tau=1e-3), fit_codebook=True,
+                            bits=bits, sample_every=every)
+    Co = ref["codebook"]
+    rng_z = np.abs(ref["z"]).max(axis=0) + 1.0
+    assert np.allclose(Cg, Co, rtol=0, atol=1e-4 * rng_z.max())
+    tol = 2e-5 * rng_z + np.abs(Cg - Co).max(axis=1)
+    near = near_tie_codes(ref["z"], Co, Cg, tol)
+    diff = codes != ref["codes"]
+    assert not np.any(diff & ~near), np.argwhere(diff & ~near)[:5]
+    assert diff.sum() <= max(2, 1e-3 * diff.size)
+    # the same histograms need a residual (decisions far from the threshold)
+    assert abs(int((flags & 1).sum()) - int((ref["flags"] & 1).sum())) <= max(1, Hn // 500)
+    # residual sizes agree in aggregate (the reconstructions differ by FP32 rounding only)
+    assert abs(st["stream_bytes"] - len(ref["stream"])) <= 0.01 * len(ref["stream"]) + 64
+
+
+def test_compress_without_model_bit_exact(H, ctx):
+    say("e2e coder-only")
+    g = grid.make_grid()
+    F = synth.histograms(700, seed=41, dtype=np.float32)
+    plan = H.Plan(ctx)
+    cz = H.Compressor(plan, None, 700, H.params(tau=1e-3))
+    comp = cz.compress(torch.from_numpy(F).cuda())
+    out = cz.decompress(comp, 700).cpu().numpy()
+    ref = pipeline.compress(F, g, None, None, pipeline.Params(tau=1e-3))
+    assert comp.stream_bytes() == ref["stream"]
+    assert np.array_equal(comp.offsets.cpu().numpy().astype(np.uint64), ref["offsets"])
+    assert np.array_equal(comp.flags.cpu().numpy(), ref["flags"])
+    assert np.allclose(out, ref["fc"], rtol=1e-12, atol=1e-14 * np.abs(F).max())
+    check_roundtrip(F, out, comp.flags.cpu().numpy(), 1e-3, g)
+
+
+def test_determinism_and_empty_batch(H, ctx):
+    say("determinism")
+    F = synth.histograms(500, seed=42, dtype=np.float32)
+    W = synth.dense_ae_weights()
+    mu, sd = oracle.ae.norm_stats(F)
+    plan = H.Plan(ctx)
+    model = H.Model(plan, W, mu, sd)
+    x = torch.from_numpy(F).cuda()
+    res = []
+    for _ in range(2):
+        cz = H.Compressor(plan, model, 500, H.params(tau=1e-3, fit_codebook=True, sample_every=2))
+        c = cz.compress(x)
+        res.append((c.codes.cpu().numpy(), c.lam.cpu().numpy(), c.stream_bytes(), cz.centroids.cpu().numpy(),
+                    cz.decompress(c, 500).cpu().numpy()))
+    for a, b in zip(res[0], res[1]):
+        if isinstance(a, bytes):
+            assert a == b
+        else:
+            assert np.array_equal(a, b)
+    say("empty batch")
+    cz = H.Compressor(plan, model, 4, H.params(tau=1e-3))
+    c = cz.compress(x[:0])
+    assert c.stats()["n_hist"] == 0 and int(c.offsets[0].item()) == 0
+
+
+@pytest.mark.parametrize("with_model", [False, True])
+def test_full_scale_batch(H, ctx, with_model):
+    """2^20 histograms of 39x39 FP32, the configuration the benchmark times."""
+    Hn = 1 << 20
+    say("full scale", "model" if with_model else "coder-only", Hn)
+    g = grid.make_grid()
+    F = synth.histograms(Hn, seed=synth.SEED_PLAIN_LARGE, dtype=np.float32)
+    plan = H.Plan(ctx)
+    W = synth.dense_ae_weights()
+    model = model_o = None
+    if with_model:
+        x = torch.from_numpy(F).cuda()
+        mu, sd = oracle.ae.norm_stats(F[::16])
+        mu, sd = mu.astype(np.float32), sd.astype(np.float32)
+        model = H.Model(plan, W, mu, sd)
+        model_o = dict(W=W, mu=mu.astype(np.float64), sd=sd.astype(np.float64))
+    else:
+        x = torch.from_numpy(F).cuda()
+    cz = H.Compressor(plan, model, Hn, H.params(tau=1e-3, fit_codebook=with_model, sample_every=16))
+    comp = cz.compress(x)
+    st = comp.stats()
+    assert st["n_hist"] == Hn and st["overflow"] == 0
+    out = cz.decompress(comp, Hn)
+    # bound and QoIs on every histogram, evaluated on the device from the GPU's own output
+    _, q0, n0 = H.qoi(plan, x)
+    _, q1, _ = H.qoi(plan, out)
+    ok = (comp.flags & 4) == 0
+    dist = (out - x.double()).reshape(Hn, -1).norm(dim=1)
+    assert bool(((dist <= 1e-3 * n0) | ~ok).all())
+    den = torch.stack([q0[:, 0].abs(), torch.maximum(q0[:, 1].abs(), q0[:, 3].abs().sqrt()),
+                       q0[:, 2].abs(), q0[:, 3].abs()], 1)
+    assert ((q1 - q0).abs() / den)[ok].max().item() < 1e-10
+    rng = np.random.default_rng(43)
+    sample = np.sort(rng.choice(Hn, 128, replace=False))
+    off = comp.offsets.cpu().numpy().astype(np.int64)
+    flags = comp.flags.cpu().numpy()
+    if not with_model:
+        ref = pipeline.compress(F[sample], g, None, None, pipeline.Params(tau=1e-3))
+        stream = comp.stream
+        for k, h in enumerate(sample):
+            rec = bytes(stream[off[h]:off[h + 1]].cpu().numpy().tobytes())
+            assert rec == ref["stream"][int(ref["offsets"][k]):int(ref["offsets"][k + 1])], h
+        assert np.array_equal(flags[sample], ref["flags"])
+        lam = comp.lam.cpu().numpy()[sample]
+        assert np.allclose(lam, ref["lam"], rtol=1e-7, atol=1e-9 * np.abs(ref["lam"]).max())
+    else:
+        # codebook: the oracle fits it on the oracle's latents of the same every-16th sample
+        Zs = oracle.ae.dense_encode(oracle.ae.normalize(F[::16], model_o["mu"], model_o["sd"]), W)
+        Co = pq.fit(Zs, 8, 1)
+        Cg = cz.centroids.cpu().numpy()
+        rng_z = np.abs(Zs).max(axis=0) + 1.0
+        close = np.isclose(Cg, Co, rtol=0, atol=1e-4 * rng_z[:, None])
+        assert close.mean() > 0.99, close.mean()
+        zs = oracle.ae.dense_encode(oracle.ae.normalize(F[sample], model_o["mu"], model_o["sd"]), W)
+        codes_o = pq.encode(zs, Co)
+        codes = comp.codes.cpu().numpy()[sample]
+        tol = 2e-5 * rng_z + np.abs(Cg - Co).max(axis=1)
+        near = near_tie_codes(zs, Co, Cg, tol)
+        diff = codes != codes_o
+        assert not np.any(diff & ~near)

@@ -113,3 +113,13 @@ def test_paper_size_accounting():
     w = gold["tied_ae_weight_bytes"]
     Wt = np.zeros((w["latent"], w["n_perp"] * w["n_par"]), np.float32)
     assert Wt.nbytes == w["bytes"]
+
+
+def test_assignment_is_the_midpoint_count():
+    # the binary search equals the literal count #{c : beta_c < z}, NaN counting none
+    rng = np.random.default_rng(9)
+    C = np.sort(rng.normal(size=64))
+    C[10] = C[11]
+    beta = pq.midpoints(C)
+    z = np.concatenate([rng.normal(size=2000), beta, [np.inf, -np.inf, np.nan]])
+    assert np.array_equal(pq.assign_1d(z, C), (beta[None, :] < z[:, None]).sum(axis=1))
