@@ -228,6 +228,38 @@ hcz_status hcz_decompress(const hcz_plan* plan, const hcz_model* model,
  * HCZ_ECAPACITY if the stream overflowed its capacity. */
 hcz_status hcz_stats_read(const hcz_stats* dev_stats, hcz_stats* host_out, hcz_stream_t stream);
 
+/* ---- autoencoder training (Section III Stage 2, Eq. 5; Section IV-B) -------------------
+ * The dense model of hcz_model_desc, trained with these kernels from torch.autograd.
+ * params / grad: FP32 device vectors in the hcz_model_desc weights layout
+ * (hcz_ae_param_count elements).  x: z-scored inputs [B][N] (device, FP32).
+ * hcz_ae_forward writes z [B][latent], xhat [B][N] and the activations the backward
+ * pass needs into `saved` (hcz_ae_saved_bytes; also the backward's scratch).
+ * hcz_ae_backward takes dL/dz (or NULL for 0) and dL/dxhat and writes dL/dparams to
+ * grad and, if dx is not NULL, dL/dx [B][N].  Every product runs on FP32 matrix cores
+ * with a fixed reduction order (no atomics). */
+hcz_status hcz_ae_param_count(int32_t N, int64_t* count);
+hcz_status hcz_ae_saved_bytes(int32_t N, int64_t B, size_t* bytes);
+hcz_status hcz_ae_forward(int32_t N, const float* params, const float* x, int64_t B, float* z,
+                          float* xhat, void* saved, size_t saved_bytes, hcz_stream_t stream);
+hcz_status hcz_ae_backward(int32_t N, const float* params, const float* x, int64_t B,
+                           const float* dz, const float* dxhat, void* saved, size_t saved_bytes,
+                           float* grad, float* dx, hcz_stream_t stream);
+/* MSE of Eq. 5: *loss (device) = mean((xhat - x)^2) over n values; dxhat (or NULL) =
+ * 2 (xhat - x) / n.  Workspace: hcz_mse_workspace bytes. */
+hcz_status hcz_mse_workspace(size_t* bytes);
+hcz_status hcz_mse(const float* xhat, const float* x, int64_t n, float* loss, float* dxhat,
+                   void* ws, size_t ws_bytes, hcz_stream_t stream);
+/* One Adam update (Kingma & Ba) of n parameters in place; step counts from 1. */
+hcz_status hcz_adam_step(float* params, const float* grad, float* m, float* v, int64_t n,
+                         double lr, double beta1, double beta2, double eps, int64_t step,
+                         hcz_stream_t stream);
+/* Per-pixel z-score statistics (Section IV-C): mean and population std over H
+ * histograms (FP64 two-pass), std floored at 1e-12 * max std; written as FP32 [N]. */
+hcz_status hcz_norm_stats_workspace(const hcz_plan* plan, int64_t H, size_t* bytes);
+hcz_status hcz_norm_stats(const hcz_plan* plan, const void* hist, int32_t dtype, int64_t H,
+                          int64_t hist_stride, int64_t row_stride, float* mean, float* std,
+                          void* ws, size_t ws_bytes, hcz_stream_t stream);
+
 /* ---- stage timing ---------------------------------------------------------------------
  * With profiling on, hcz_compress and hcz_decompress record a HIP event pair around every
  * kernel stage, on the caller's stream.  hcz_profile_read waits for the recorded events

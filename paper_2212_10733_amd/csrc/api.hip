@@ -647,6 +647,146 @@ hcz_status hcz_decompress(const hcz_plan* plan, const hcz_model* model, const hc
   return HCZ_OK;
 }
 
+// ---- training ------------------------------------------------------------------------
+namespace {
+struct AeOffsets {
+  size_t W1, b1, W2, b2, W3, b3, W4, b4, total;
+};
+AeOffsets ae_offsets(int N) {
+  AeOffsets o{};
+  size_t p = 0;
+  o.W1 = p; p += (size_t)kHidden * N;
+  o.b1 = p; p += kHidden;
+  o.W2 = p; p += (size_t)kLatent * kHidden;
+  o.b2 = p; p += kLatent;
+  o.W3 = p; p += (size_t)kHidden * kLatent;
+  o.b3 = p; p += kHidden;
+  o.W4 = p; p += (size_t)N * kHidden;
+  o.b4 = p; p += N;
+  o.total = p;
+  return o;
+}
+size_t ae_saved_floats(long long B) { return (size_t)B * (3 * kHidden + kHidden + kLatent); }
+}  // namespace
+
+hcz_status hcz_ae_param_count(int32_t N, int64_t* count) {
+  if (!count || N < 1 || N > kMaxN) return fail(HCZ_EINVAL, "bad argument");
+  *count = (int64_t)ae_offsets(N).total;
+  return HCZ_OK;
+}
+
+hcz_status hcz_ae_saved_bytes(int32_t N, int64_t B, size_t* bytes) {
+  if (!bytes || N < 1 || N > kMaxN || B < 0) return fail(HCZ_EINVAL, "bad argument");
+  *bytes = ae_saved_floats(B) * sizeof(float);
+  return HCZ_OK;
+}
+
+hcz_status hcz_ae_forward(int32_t N, const float* params, const float* x, int64_t B, float* z,
+                          float* xhat, void* saved, size_t saved_bytes, hcz_stream_t stream) {
+  if (N < 1 || N > kMaxN || B < 0) return fail(HCZ_EINVAL, "bad size");
+  if (B == 0) return HCZ_OK;
+  if (!params || !x || !z || !xhat || !saved) return fail(HCZ_EINVAL, "NULL buffer");
+  if (saved_bytes < ae_saved_floats(B) * sizeof(float)) return fail(HCZ_EWORKSPACE, "saved buffer too small");
+  const AeOffsets o = ae_offsets(N);
+  hipStream_t st = (hipStream_t)stream;
+  float* h1 = (float*)saved;
+  float* h3 = h1 + (size_t)B * kHidden;
+  const int Hd = kHidden, Ld = kLatent;
+  HCZ_TRY(launch_gemm(x, N, 1, params + o.W1, 1, N, h1, Hd, B, Hd, N, 1.f, 0.f, params + o.b1, 1, st), "gemm");
+  HCZ_TRY(launch_gemm(h1, Hd, 1, params + o.W2, 1, Hd, z, Ld, B, Ld, Hd, 1.f, 0.f, params + o.b2, 0, st), "gemm");
+  HCZ_TRY(launch_gemm(z, Ld, 1, params + o.W3, 1, Ld, h3, Hd, B, Hd, Ld, 1.f, 0.f, params + o.b3, 1, st), "gemm");
+  HCZ_TRY(launch_gemm(h3, Hd, 1, params + o.W4, 1, Hd, xhat, N, B, N, Hd, 1.f, 0.f, params + o.b4, 0, st), "gemm");
+  return HCZ_OK;
+}
+
+hcz_status hcz_ae_backward(int32_t N, const float* params, const float* x, int64_t B,
+                           const float* dz_in, const float* dxh, void* saved, size_t saved_bytes,
+                           float* grad, float* dx, hcz_stream_t stream) {
+  if (N < 1 || N > kMaxN || B < 0) return fail(HCZ_EINVAL, "bad size");
+  if (!params || !grad) return fail(HCZ_EINVAL, "NULL buffer");
+  if (B > 0 && (!x || !dxh || !saved)) return fail(HCZ_EINVAL, "NULL buffer");
+  if (saved_bytes < ae_saved_floats(B) * sizeof(float)) return fail(HCZ_EWORKSPACE, "saved buffer too small");
+  const AeOffsets o = ae_offsets(N);
+  hipStream_t st = (hipStream_t)stream;
+  const int Hd = kHidden, Ld = kLatent;
+  float* h1 = (float*)saved;
+  float* h3 = h1 + (size_t)B * Hd;
+  float* d3 = h3 + (size_t)B * Hd;      // dL/d(pre-activation 3), [B][Hd]
+  float* d1 = d3 + (size_t)B * Hd;      // dL/d(pre-activation 1), [B][Hd]
+  float* dz = d1 + (size_t)B * Hd;      // dL/dz, [B][Ld]
+  // z is needed for dW3: recompute it from h1 (cheap) into dz's slot first
+  HCZ_TRY(launch_gemm(h1, Hd, 1, params + o.W2, 1, Hd, dz, Ld, B, Ld, Hd, 1.f, 0.f, params + o.b2, 0, st), "gemm");
+  // output layer
+  HCZ_TRY(launch_gemm(dxh, 1, N, h3, Hd, 1, grad + o.W4, Hd, N, Hd, B, 1.f, 0.f, nullptr, 0, st), "gemm dW4");
+  HCZ_TRY(launch_colsum(dxh, B, N, grad + o.b4, st), "colsum");
+  HCZ_TRY(launch_gemm(dxh, N, 1, params + o.W4, Hd, 1, d3, Hd, B, Hd, N, 1.f, 0.f, nullptr, 0, st), "gemm dh3");
+  HCZ_TRY(launch_relu_mask(d3, h3, (long long)B * Hd, st), "relu mask");
+  // decoder input layer: dW3 = d3^T z
+  HCZ_TRY(launch_gemm(d3, 1, Hd, dz, Ld, 1, grad + o.W3, Ld, Hd, Ld, B, 1.f, 0.f, nullptr, 0, st), "gemm dW3");
+  HCZ_TRY(launch_colsum(d3, B, Hd, grad + o.b3, st), "colsum");
+  // dz = d3 W3 (+ dz_in)
+  if (dz_in) {
+    HCZ_TRY(hipMemcpyAsync(dz, dz_in, (size_t)B * Ld * sizeof(float), hipMemcpyDeviceToDevice, st), "copy dz");
+    HCZ_TRY(launch_gemm(d3, Hd, 1, params + o.W3, Ld, 1, dz, Ld, B, Ld, Hd, 1.f, 1.f, nullptr, 0, st), "gemm dz");
+  } else {
+    HCZ_TRY(launch_gemm(d3, Hd, 1, params + o.W3, Ld, 1, dz, Ld, B, Ld, Hd, 1.f, 0.f, nullptr, 0, st), "gemm dz");
+  }
+  // encoder output layer
+  HCZ_TRY(launch_gemm(dz, 1, Ld, h1, Hd, 1, grad + o.W2, Hd, Ld, Hd, B, 1.f, 0.f, nullptr, 0, st), "gemm dW2");
+  HCZ_TRY(launch_colsum(dz, B, Ld, grad + o.b2, st), "colsum");
+  HCZ_TRY(launch_gemm(dz, Ld, 1, params + o.W2, Hd, 1, d1, Hd, B, Hd, Ld, 1.f, 0.f, nullptr, 0, st), "gemm dh1");
+  HCZ_TRY(launch_relu_mask(d1, h1, (long long)B * Hd, st), "relu mask");
+  // encoder input layer
+  HCZ_TRY(launch_gemm(d1, 1, Hd, x, N, 1, grad + o.W1, N, Hd, N, B, 1.f, 0.f, nullptr, 0, st), "gemm dW1");
+  HCZ_TRY(launch_colsum(d1, B, Hd, grad + o.b1, st), "colsum");
+  if (dx) HCZ_TRY(launch_gemm(d1, Hd, 1, params + o.W1, N, 1, dx, N, B, N, Hd, 1.f, 0.f, nullptr, 0, st), "gemm dx");
+  return HCZ_OK;
+}
+
+hcz_status hcz_mse_workspace(size_t* bytes) {
+  if (!bytes) return fail(HCZ_EINVAL, "NULL argument");
+  *bytes = mse_ws_bytes();
+  return HCZ_OK;
+}
+
+hcz_status hcz_mse(const float* xhat, const float* x, int64_t n, float* loss, float* dxhat, void* ws,
+                   size_t ws_bytes, hcz_stream_t stream) {
+  if (n < 1 || !xhat || !x || !loss) return fail(HCZ_EINVAL, "bad argument");
+  if (!ws || ws_bytes < mse_ws_bytes()) return fail(HCZ_EWORKSPACE, "workspace too small");
+  HCZ_TRY(launch_mse(xhat, x, n, loss, dxhat, ws, (hipStream_t)stream), "mse");
+  return HCZ_OK;
+}
+
+hcz_status hcz_adam_step(float* params, const float* grad, float* m, float* v, int64_t n, double lr,
+                         double beta1, double beta2, double eps, int64_t step, hcz_stream_t stream) {
+  if (n < 0 || step < 1 || !(lr > 0) || !(beta1 >= 0 && beta1 < 1) || !(beta2 >= 0 && beta2 < 1) || !(eps > 0))
+    return fail(HCZ_EINVAL, "bad Adam argument");
+  if (n > 0 && (!params || !grad || !m || !v)) return fail(HCZ_EINVAL, "NULL buffer");
+  HCZ_TRY(launch_adam(params, grad, m, v, n, lr, beta1, beta2, eps, step, (hipStream_t)stream), "adam");
+  return HCZ_OK;
+}
+
+hcz_status hcz_norm_stats_workspace(const hcz_plan* plan, int64_t H, size_t* bytes) {
+  if (!plan || !bytes || H < 1) return fail(HCZ_EINVAL, "bad argument");
+  *bytes = norm_stats_ws_bytes(H, plan->G.N);
+  return HCZ_OK;
+}
+
+hcz_status hcz_norm_stats(const hcz_plan* plan, const void* hist, int32_t dtype, int64_t H,
+                          int64_t hist_stride, int64_t row_stride, float* mean, float* sd, void* ws,
+                          size_t ws_bytes, hcz_stream_t stream) {
+  if (!plan) return fail(HCZ_EINVAL, "plan is NULL");
+  if (H < 1) return fail(HCZ_EINVAL, "H must be >= 1");
+  hcz_status s = check_hist(hist, dtype, H, hist_stride, row_stride, plan->G);
+  if (s) return s;
+  if (!mean || !sd) return fail(HCZ_EINVAL, "NULL output");
+  if (!ws || ws_bytes < norm_stats_ws_bytes(H, plan->G.N)) return fail(HCZ_EWORKSPACE, "workspace too small");
+  if ((s = set_device(plan->ctx))) return s;
+  HCZ_TRY(launch_norm_stats(hist, dtype, H, hist_stride, row_stride, plan->G.n_par, plan->G.N, mean, sd, ws,
+                            (hipStream_t)stream), "norm stats");
+  return HCZ_OK;
+}
+
 hcz_status hcz_profile_enable(hcz_ctx* ctx, int enable) {
   if (!ctx) return fail(HCZ_EINVAL, "ctx is NULL");
   hcz_status s = set_device(ctx);

@@ -286,6 +286,19 @@ hipError_t launch_decode(const ModelDev& M, const uint8_t* codes, const float* c
 hipError_t launch_quantize(const float* z, long long n, int latent, const float* centroids,
                            int bits, uint8_t* codes, hipStream_t st);
 size_t codebook_ws_bytes(long long n, int latent, long long every);
+hipError_t launch_gemm(const float* A, long long sam, long long sak, const float* B, long long sbk,
+                       long long sbn, float* C, long long scm, long long M, long long Nc, long long K,
+                       float alpha, float beta, const float* bias, int relu, hipStream_t st);
+hipError_t launch_relu_mask(float* d, const float* h, long long n, hipStream_t st);
+hipError_t launch_colsum(const float* D, long long M, long long Nc, float* out, hipStream_t st);
+size_t mse_ws_bytes();
+hipError_t launch_mse(const float* xh, const float* x, long long n, float* loss, float* dxh, void* ws,
+                      hipStream_t st);
+hipError_t launch_adam(float* p, const float* g, float* m, float* v, long long n, double lr, double b1,
+                       double b2, double eps, long long step, hipStream_t st);
+size_t norm_stats_ws_bytes(long long H, int N);
+hipError_t launch_norm_stats(const void* hist, int dtype, long long H, long long hs, long long rs, int n_par,
+                             int N, float* mean, float* sd, void* ws, hipStream_t st);
 hipError_t launch_codebook_fit(const float* z, long long n, int latent, long long every, int bits,
                                float* centroids, void* ws, hipStream_t st);
 

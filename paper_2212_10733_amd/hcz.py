@@ -96,6 +96,15 @@ def _load() -> C.CDLL:
                          C.POINTER(CompressedC), vp, sz, vp],
         "hcz_decompress": [vp, vp, C.POINTER(Codebook), C.POINTER(CompressedC), i32, i64, vp, i32, vp, sz, vp],
         "hcz_stats_read": [vp, C.POINTER(Stats), vp],
+        "hcz_ae_param_count": [i32, C.POINTER(i64)],
+        "hcz_ae_saved_bytes": [i32, i64, C.POINTER(sz)],
+        "hcz_ae_forward": [i32, vp, vp, i64, vp, vp, vp, sz, vp],
+        "hcz_ae_backward": [i32, vp, vp, i64, vp, vp, vp, sz, vp, vp, vp],
+        "hcz_mse_workspace": [C.POINTER(sz)],
+        "hcz_mse": [vp, vp, i64, vp, vp, vp, sz, vp],
+        "hcz_adam_step": [vp, vp, vp, vp, i64, C.c_double, C.c_double, C.c_double, C.c_double, i64, vp],
+        "hcz_norm_stats_workspace": [vp, i64, C.POINTER(sz)],
+        "hcz_norm_stats": [vp, vp, i32, i64, i64, i64, vp, vp, vp, sz, vp],
         "hcz_profile_enable": [vp, C.c_int],
         "hcz_profile_read": [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)],
     }
@@ -118,7 +127,9 @@ EXPORTS = ["hcz_create", "hcz_destroy", "hcz_last_error", "hcz_version", "hcz_pl
            "hcz_plan_destroy", "hcz_model_load", "hcz_model_free", "hcz_qoi", "hcz_encode",
            "hcz_codebook_fit_workspace", "hcz_codebook_fit", "hcz_quantize", "hcz_decode",
            "hcz_residual", "hcz_compress_workspace", "hcz_decompress_workspace", "hcz_compress",
-           "hcz_decompress", "hcz_stats_read", "hcz_profile_enable", "hcz_profile_read"]
+           "hcz_decompress", "hcz_stats_read", "hcz_profile_enable", "hcz_profile_read",
+           "hcz_ae_param_count", "hcz_ae_saved_bytes", "hcz_ae_forward", "hcz_ae_backward",
+           "hcz_mse_workspace", "hcz_mse", "hcz_adam_step", "hcz_norm_stats_workspace", "hcz_norm_stats"]
 
 STAGES = ["encode", "codebook", "quantize", "decode", "residual", "scan", "compact", "stats", "decompress"]
 
@@ -387,3 +398,16 @@ class Compressor:
                                   C.byref(cs), F32 if in_dtype == torch.float32 else F64, H, _ptr(out),
                                   _dtype_code(out), _ptr(self.dws), self.dws.numel(), _stream()))
         return out
+
+
+def norm_stats(plan: Plan, hist: torch.Tensor):
+    """Per-pixel z-score statistics (mean, std) of a batch, as FP32 numpy arrays."""
+    H, hs, rs = _strides(hist)
+    nbytes = C.c_size_t()
+    _check(LIB.hcz_norm_stats_workspace(plan.h, H, C.byref(nbytes)))
+    ws = workspace(nbytes.value, hist.device)
+    mu = torch.empty(plan.N, dtype=torch.float32, device=hist.device)
+    sd = torch.empty(plan.N, dtype=torch.float32, device=hist.device)
+    _check(LIB.hcz_norm_stats(plan.h, _ptr(hist), _dtype_code(hist), H, hs, rs, _ptr(mu), _ptr(sd),
+                              _ptr(ws), ws.numel(), _stream()))
+    return mu, sd

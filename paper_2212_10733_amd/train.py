@@ -1,0 +1,139 @@
+"""Training of the dense autoencoder with the library's own kernels (Section III Stage 2,
+Eq. 5; Section IV-B: Adam, z-scored inputs, a random sampler).
+
+`DenseAE.apply(x, params)` is a torch.autograd.Function whose forward and backward are
+hcz_ae_forward / hcz_ae_backward; `mse` wraps hcz_mse; `Trainer` runs Adam
+(hcz_adam_step) over a device-resident training set.  torch provides memory, the random
+permutation of the sampler and the autograd bookkeeping only.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import hcz
+from .hcz import LIB, _check, _ptr, _stream
+
+KEYS = ("W1", "b1", "W2", "b2", "W3", "b3", "W4", "b4")
+
+
+def param_count(N: int) -> int:
+    n = C.c_int64()
+    _check(LIB.hcz_ae_param_count(N, C.byref(n)))
+    return n.value
+
+
+def shapes(N: int, hidden=hcz.HIDDEN, latent=hcz.LATENT):
+    return dict(W1=(hidden, N), b1=(hidden,), W2=(latent, hidden), b2=(latent,), W3=(hidden, latent),
+                b3=(hidden,), W4=(N, hidden), b4=(N,))
+
+
+def pack(W: dict, device="cuda") -> torch.Tensor:
+    return torch.from_numpy(hcz.pack_dense_weights(W)).to(device)
+
+
+def unpack(p: torch.Tensor, N: int) -> dict:
+    out, o = {}, 0
+    flat = p.detach().cpu().numpy()
+    for k, s in shapes(N).items():
+        n = int(np.prod(s))
+        out[k] = flat[o:o + n].reshape(s).copy()
+        o += n
+    return out
+
+
+class DenseAE(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, x: torch.Tensor, params: torch.Tensor):
+        x = x.contiguous()
+        B, N = x.shape
+        nbytes = C.c_size_t()
+        _check(LIB.hcz_ae_saved_bytes(N, B, C.byref(nbytes)))
+        saved = torch.empty(max(nbytes.value, 4) // 4, dtype=torch.float32, device=x.device)
+        z = torch.empty((B, hcz.LATENT), dtype=torch.float32, device=x.device)
+        xh = torch.empty((B, N), dtype=torch.float32, device=x.device)
+        _check(LIB.hcz_ae_forward(N, _ptr(params), _ptr(x), B, _ptr(z), _ptr(xh), _ptr(saved),
+                                  saved.numel() * 4, _stream()))
+        ctx.save_for_backward(x, params, saved)
+        return z, xh
+
+    @staticmethod
+    def backward(ctx, dz, dxh):
+        x, params, saved = ctx.saved_tensors
+        B, N = x.shape
+        grad = torch.empty_like(params)
+        dx = torch.empty_like(x) if ctx.needs_input_grad[0] else None
+        dz = None if dz is None else dz.contiguous()
+        if dxh is None:
+            dxh = torch.zeros_like(x)
+        _check(LIB.hcz_ae_backward(N, _ptr(params), _ptr(x), B, _ptr(dz), _ptr(dxh.contiguous()), _ptr(saved),
+                                   saved.numel() * 4, _ptr(grad), _ptr(dx), _stream()))
+        return dx, grad
+
+
+class MSE(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, xh: torch.Tensor, x: torch.Tensor):
+        nbytes = C.c_size_t()
+        _check(LIB.hcz_mse_workspace(C.byref(nbytes)))
+        ws = torch.empty(nbytes.value, dtype=torch.uint8, device=x.device)
+        loss = torch.empty((), dtype=torch.float32, device=x.device)
+        dxh = torch.empty_like(xh)
+        _check(LIB.hcz_mse(_ptr(xh.contiguous()), _ptr(x.contiguous()), xh.numel(), _ptr(loss), _ptr(dxh),
+                           _ptr(ws), ws.numel(), _stream()))
+        ctx.save_for_backward(dxh)
+        return loss
+
+    @staticmethod
+    def backward(ctx, g):
+        (dxh,) = ctx.saved_tensors
+        return dxh * g, None
+
+
+def mse(xh, x):
+    return MSE.apply(xh, x)
+
+
+class Trainer:
+    """Adam on the packed parameter vector with hcz_adam_step (FP32 master weights)."""
+
+    def __init__(self, params: torch.Tensor, lr=1e-3, betas=(0.9, 0.999), eps=1e-8):
+        self.p = params.detach().clone().contiguous()
+        self.m = torch.zeros_like(self.p)
+        self.v = torch.zeros_like(self.p)
+        self.lr, self.betas, self.eps = lr, betas, eps
+        self.step_count = 0
+
+    def step(self, grad: torch.Tensor) -> None:
+        self.step_count += 1
+        _check(LIB.hcz_adam_step(_ptr(self.p), _ptr(grad.contiguous()), _ptr(self.m), _ptr(self.v),
+                                 self.p.numel(), self.lr, self.betas[0], self.betas[1], self.eps,
+                                 self.step_count, _stream()))
+
+    def train_step(self, xb: torch.Tensor) -> torch.Tensor:
+        p = self.p.detach().requires_grad_(True)
+        _, xh = DenseAE.apply(xb, p)
+        loss = mse(xh, xb)
+        loss.backward()
+        self.step(p.grad)
+        return loss.detach()
+
+    def fit(self, X: torch.Tensor, epochs: int, batch: int = 1024, seed: int = 0, log=None) -> list:
+        """X: z-scored training set [n][N] on the device; random sampler without replacement."""
+        g = torch.Generator(device=X.device)
+        g.manual_seed(seed)
+        losses = []
+        n = X.shape[0]
+        for ep in range(epochs):
+            perm = torch.randperm(n, generator=g, device=X.device)
+            tot = torch.zeros((), dtype=torch.float64, device=X.device)
+            nb = 0
+            for s in range(0, n - batch + 1, batch):
+                tot += self.train_step(X[perm[s:s + batch]])
+                nb += 1
+            losses.append((tot / max(nb, 1)).item())
+            if log:
+                log(f"epoch {ep + 1}: loss {losses[-1]:.5f}")
+        return losses

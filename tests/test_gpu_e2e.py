@@ -91,9 +91,12 @@ def test_compress_with_model(H, ctx, Hn, dtype, every, bits):
     assert np.allclose(Cg, Co, rtol=0, atol=1e-4 * rng_z.max())
     tol = 2e-5 * rng_z + np.abs(Cg - Co).max(axis=1)
     near = near_tie_codes(ref["z"], Co, Cg, tol)
-    diff = codes != ref["codes"]
-    assert not np.any(diff & ~near), np.argwhere(diff & ~near)[:5]
-    assert diff.sum() <= max(2, 1e-3 * diff.size)
+    # a sample smaller than the codebook leaves duplicate centroids, whose indices may
+    # differ while the dequantized values agree: compare what is unique, the values
+    d = np.arange(16)[None, :]
+    vdiff = np.abs(Cg[d, codes] - Co[d, ref["codes"]]) > tol[None, :]
+    assert not np.any(vdiff & ~near), np.argwhere(vdiff & ~near)[:5]
+    assert vdiff.sum() <= max(2, 1e-3 * vdiff.size)
     # the same histograms need a residual (decisions far from the threshold)
     assert abs(int((flags & 1).sum()) - int((ref["flags"] & 1).sum())) <= max(1, Hn // 500)
     # residual sizes agree in aggregate (the reconstructions differ by FP32 rounding only)

@@ -1,0 +1,152 @@
+"""The learned part on the GPU: the dense autoencoder's hand-written forward/backward
+kernels against the oracle (FP64) and central finite differences, Adam, the z-score
+statistics, and what training buys in compression (GPU)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import grid, moments
+from paper_2212_10733_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def T():
+    from paper_2212_10733_amd import hcz, train
+    return hcz, train
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+def weights(N, seed=5):
+    W = synth.dense_ae_weights(N, seed=seed)
+    rng = np.random.default_rng(seed)
+    for k in ("b1", "b2", "b3", "b4"):
+        W[k] = rng.normal(0, 0.05, W[k].shape).astype(np.float32)
+    return W
+
+
+def inputs(B, N, seed=6):
+    F = synth.histograms(B, seed=seed, dtype=np.float32).reshape(B, -1)[:, :N]
+    mu, sd = oracle.ae.norm_stats(F)
+    return ((F - mu) / sd).astype(np.float32)
+
+
+@pytest.mark.parametrize("B", [64, 200])
+def test_forward_backward_parity(T, B):
+    hcz, train = T
+    N = 1521
+    say("ae fwd/bwd", B)
+    W = weights(N)
+    X = inputs(B, N)
+    p = train.pack(W).requires_grad_(True)
+    x = torch.from_numpy(X).cuda()
+    z, xh = train.DenseAE.apply(x, p)
+    loss = train.mse(xh, x)
+    loss.backward()
+    torch.cuda.synchronize()
+    W64 = {k: v.astype(np.float64) for k, v in W.items()}
+    cache = oracle.ae.dense_forward_train(X.astype(np.float64), W64)
+    assert np.allclose(z.detach().cpu().numpy(), cache["z"], rtol=1e-4, atol=1e-4 * np.abs(cache["z"]).max())
+    assert np.allclose(xh.detach().cpu().numpy(), cache["xh"], rtol=1e-4, atol=1e-4 * np.abs(cache["xh"]).max())
+    assert loss.item() == pytest.approx(oracle.ae.mse(cache["xh"], X.astype(np.float64)), rel=1e-5)
+    g_or = oracle.ae.dense_backward(cache, W64)
+    g = train.unpack(p.grad, N)
+    for k in train.KEYS:
+        scale = np.abs(g_or[k]).max() + 1e-30
+        err = np.abs(g[k] - g_or[k]).max() / scale
+        assert err < 2e-4, (k, err)
+    # central finite differences of the FP64 loss at sampled coordinates
+    rng = np.random.default_rng(7)
+    for k in train.KEYS:
+        for _ in range(2):
+            idx = tuple(rng.integers(0, s) for s in W64[k].shape)
+            Wp = {kk: vv.copy() for kk, vv in W64.items()}
+            Wm = {kk: vv.copy() for kk, vv in W64.items()}
+            h = 1e-4 * max(1.0, abs(W64[k][idx]))
+            Wp[k][idx] += h
+            Wm[k][idx] -= h
+            fd = (oracle.ae.dense_loss(X.astype(np.float64), Wp) - oracle.ae.dense_loss(X.astype(np.float64), Wm)) / (2 * h)
+            assert g[k][idx] == pytest.approx(fd, rel=2e-3, abs=2e-4 * (np.abs(g_or[k]).max() + 1e-12)), (k, idx)
+
+
+def test_latent_and_input_gradients(T):
+    hcz, train = T
+    say("dz / dx")
+    N, B = 1521, 48
+    W = weights(N, seed=8)
+    X = inputs(B, N, seed=9)
+    dz = np.random.default_rng(10).normal(size=(B, 16)).astype(np.float32)
+    p = train.pack(W).requires_grad_(True)
+    x = torch.from_numpy(X).cuda().requires_grad_(True)
+    z, xh = train.DenseAE.apply(x, p)
+    ((z * torch.from_numpy(dz).cuda()).sum() + train.mse(xh, x.detach())).backward()
+    # reference: torch autograd on the CPU in FP64 (library routine)
+    t = {k: torch.tensor(v, dtype=torch.float64, requires_grad=True) for k, v in W.items()}
+    xt = torch.tensor(X, dtype=torch.float64, requires_grad=True)
+    h1 = torch.relu(xt @ t["W1"].T + t["b1"])
+    zt = h1 @ t["W2"].T + t["b2"]
+    xht = torch.relu(zt @ t["W3"].T + t["b3"]) @ t["W4"].T + t["b4"]
+    ((zt * torch.tensor(dz, dtype=torch.float64)).sum() + ((xht - xt.detach()) ** 2).mean()).backward()
+    assert np.allclose(x.grad.cpu().numpy(), xt.grad.numpy(), rtol=1e-3, atol=2e-4 * np.abs(xt.grad.numpy()).max())
+    g = train.unpack(p.grad, N)
+    for k in train.KEYS:
+        ref = t[k].grad.numpy()
+        assert np.abs(g[k] - ref).max() <= 2e-4 * (np.abs(ref).max() + 1e-30), k
+
+
+def test_adam_and_norm_stats(T):
+    hcz, train = T
+    say("adam")
+    rng = np.random.default_rng(11)
+    p0 = rng.normal(size=5000).astype(np.float32)
+    tr = train.Trainer(torch.from_numpy(p0).cuda(), lr=1e-2)
+    params = {"w": p0.astype(np.float64)}
+    state = {}
+    for _ in range(5):
+        gr = rng.normal(size=5000).astype(np.float32)
+        tr.step(torch.from_numpy(gr).cuda())
+        oracle.ae.adam_step(params, {"w": gr.astype(np.float64)}, state, lr=1e-2)
+    assert np.allclose(tr.p.cpu().numpy(), params["w"], rtol=1e-5, atol=1e-6)
+    say("norm stats")
+    ctx = hcz.Context(0)
+    plan = hcz.Plan(ctx)
+    F = synth.histograms(1000, seed=12, dtype=np.float32)
+    F[:, 0, 0] = 0.5                      # a constant pixel gets the floored std
+    mu, sd = hcz.norm_stats(plan, torch.from_numpy(F).cuda())
+    mo, so = oracle.ae.norm_stats(F)
+    assert np.allclose(mu.cpu().numpy(), mo, rtol=1e-6, atol=1e-12)
+    assert np.allclose(sd.cpu().numpy(), so, rtol=1e-5, atol=1e-18)
+
+
+def test_training_reduces_loss_and_residuals(T):
+    hcz, train = T
+    say("training")
+    ctx = hcz.Context(0)
+    plan = hcz.Plan(ctx)
+    Ftr = torch.from_numpy(synth.histograms(16384, seed=synth.SEED_TRAIN, dtype=np.float32)).cuda()
+    Fte = torch.from_numpy(synth.histograms(4096, seed=synth.SEED_HELDOUT, dtype=np.float32)).cuda()
+    mu, sd = hcz.norm_stats(plan, Ftr)
+    X = ((Ftr.reshape(16384, -1) - mu) / sd).contiguous()
+    W0 = synth.dense_ae_weights()
+    tr = train.Trainer(train.pack(W0), lr=1e-3)
+    losses = tr.fit(X, epochs=8, batch=1024)
+    assert losses[-1] < 0.5 * losses[0]
+    res = {}
+    for name, W in (("untrained", W0), ("trained", train.unpack(tr.p, 1521))):
+        model = hcz.Model(plan, W, mu.cpu().numpy(), sd.cpu().numpy())
+        cz = hcz.Compressor(plan, model, 4096, hcz.params(tau=1e-2, fit_codebook=True, sample_every=1))
+        c = cz.compress(Fte)
+        st = c.stats()
+        res[name] = (st["n_coded"], st["stream_bytes"])
+        out = cz.decompress(c, 4096).cpu().numpy()
+        g = grid.make_grid()
+        F = Fte.cpu().numpy().astype(np.float64)
+        q0, q1 = moments.qoi(F, g), moments.qoi(out, g)
+        assert moments.qoi_rel_error(q0, q1, g).max() < 1e-10
+    assert res["trained"][0] < res["untrained"][0]
+    assert res["trained"][1] < res["untrained"][1]
