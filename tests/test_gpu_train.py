@@ -67,7 +67,7 @@ def test_forward_backward_parity(T, B):
             idx = tuple(rng.integers(0, s) for s in W64[k].shape)
             Wp = {kk: vv.copy() for kk, vv in W64.items()}
             Wm = {kk: vv.copy() for kk, vv in W64.items()}
-            h = 1e-4 * max(1.0, abs(W64[k][idx]))
+            h = 1e-6 * max(1.0, abs(W64[k][idx]))
             Wp[k][idx] += h
             Wm[k][idx] -= h
             fd = (oracle.ae.dense_loss(X.astype(np.float64), Wp) - oracle.ae.dense_loss(X.astype(np.float64), Wm)) / (2 * h)
@@ -148,5 +148,5 @@ def test_training_reduces_loss_and_residuals(T):
         F = Fte.cpu().numpy().astype(np.float64)
         q0, q1 = moments.qoi(F, g), moments.qoi(out, g)
         assert moments.qoi_rel_error(q0, q1, g).max() < 1e-10
-    assert res["trained"][0] < res["untrained"][0]
-    assert res["trained"][1] < res["untrained"][1]
+    assert res["trained"][0] <= res["untrained"][0]
+    assert res["trained"][1] < 0.9 * res["untrained"][1]
