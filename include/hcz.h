@@ -56,11 +56,13 @@ enum { HCZ_F32 = 0, HCZ_F64 = 1 };                       /* element types */
 enum { HCZ_ARCH_DENSE = 1 };                              /* autoencoder architectures */
 enum { HCZ_TAU_REL_L2 = 0, HCZ_TAU_NRMSE = 1 };          /* tau_h = tau ||f||, tau sqrt(N)(max-min) */
 enum { HCZ_FALLBACK_BACKTRACK = 0, HCZ_FALLBACK_PAPER = 1 };
-enum { HCZ_FLAG_CODED = 1, HCZ_FLAG_ROUND2 = 2, HCZ_FLAG_RAW = 4 };
+enum { HCZ_FLAG_CODED = 1, HCZ_FLAG_ROUND2 = 2, HCZ_FLAG_RAW = 4, HCZ_FLAG_WARM_REJECTED = 8 };
+enum { HCZ_WARM_COLD = 0, HCZ_WARM_MLP = 1 };
 
 typedef struct hcz_ctx hcz_ctx;
 typedef struct hcz_plan hcz_plan;
 typedef struct hcz_model hcz_model;
+typedef struct hcz_mlp hcz_mlp;
 
 /* Velocity grid (Section II).  v_par_i = vpar_lo + i (vpar_hi - vpar_lo)/(n_par - 1),
  * likewise v_perp_j.  vol (host, [n_perp][n_par], copied) gives the cell volumes of
@@ -102,7 +104,11 @@ typedef struct {
  * fallback         round 2: Armijo backtracking, or the fixed step 0.01
  * fit_codebook     1: hcz_compress fits the codebook from the latents of every
  *                  sample_every-th histogram before quantising and writes it to the
- *                  codebook argument; 0: it uses the codebook given. */
+ *                  codebook argument; 0: it uses the codebook given.
+ * warm_start, mlp  HCZ_WARM_MLP: round 1 of the Newton solve starts from the warm-start
+ *                  network's multipliers (hcz_compress with a model only); the start is
+ *                  rejected, and the solve restarts cold, if its first Newton step makes
+ *                  max_k |g_k| / sum_j |A_kj| x_j grow (flag HCZ_FLAG_WARM_REJECTED). */
 typedef struct {
   double tau;
   int32_t tau_mode;
@@ -112,6 +118,8 @@ typedef struct {
   int32_t fallback;
   int32_t fit_codebook;
   int32_t sample_every;
+  int32_t warm_start;
+  const hcz_mlp* mlp;
 } hcz_params;
 
 /* Run statistics, written to device memory by compress and read with hcz_stats_read. */
@@ -193,12 +201,13 @@ hcz_status hcz_decode(const hcz_model* model, const uint8_t* codes, const hcz_co
 
 /* Residual coding + QoI correction of H histograms against a given reconstruction
  * (Stages 4-5): fhat [H][N] FP32 row-major, or NULL for fhat = 0 (the coder-only
- * pipeline).  Fills out->lambda, flags, res_offset, res_bytes, stats (codes untouched).
- * Workspace: hcz_compress_workspace. */
+ * pipeline); lam0 [H][4] (FP64) warm-start multipliers or NULL (params->warm_start is
+ * not used here).  Fills out->lambda, flags, res_offset, res_bytes, stats (codes
+ * untouched).  Workspace: hcz_compress_workspace. */
 hcz_status hcz_residual(const hcz_plan* plan, const hcz_params* params, const void* hist,
                         int32_t dtype, int64_t H, int64_t hist_stride, int64_t row_stride,
-                        const float* fhat, hcz_compressed* out, void* ws, size_t ws_bytes,
-                        hcz_stream_t stream);
+                        const float* fhat, const double* lam0, hcz_compressed* out, void* ws,
+                        size_t ws_bytes, hcz_stream_t stream);
 
 /* ---- whole path --------------------------------------------------------------------- */
 
@@ -260,6 +269,27 @@ hcz_status hcz_norm_stats(const hcz_plan* plan, const void* hist, int32_t dtype,
                           int64_t hist_stride, int64_t row_stride, float* mean, float* std,
                           void* ws, size_t ws_bytes, hcz_stream_t stream);
 
+/* ---- warm-start network (learned addition to Section III Stage 5) ----------------------
+ * lam0 = scale * (W3 relu(W2 relu(W1 zhat + b1) + b2) + b3), 16 -> 64 -> 64 -> 4, with
+ * zhat the dequantised latent.  params (host for hcz_mlp_load, device for training):
+ * W1[64][16], b1[64], W2[64][64], b2[64], W3[4][64], b3[4] back to back (5,508 FP32);
+ * scale (host) [4].  Training entry points mirror the autoencoder's: saved holds the
+ * activations (hcz_mlp_saved_bytes), grad receives dL/dparams for dL/dout given. */
+hcz_status hcz_mlp_load(hcz_ctx* ctx, const float* params, const double* scale, hcz_mlp** out);
+void hcz_mlp_free(hcz_mlp* mlp);
+hcz_status hcz_mlp_param_count(int64_t* count);
+hcz_status hcz_mlp_saved_bytes(int64_t B, size_t* bytes);
+hcz_status hcz_mlp_forward(const float* params, const float* z, int64_t B, float* out, void* saved,
+                           size_t saved_bytes, hcz_stream_t stream);
+hcz_status hcz_mlp_backward(const float* params, const float* z, int64_t B, const float* dout,
+                            void* saved, size_t saved_bytes, float* grad, hcz_stream_t stream);
+/* Dequantise codes [n][latent] with a codebook: z[n][d] = C[d][code[n][d]] (FP32). */
+hcz_status hcz_dequantize(const uint8_t* codes, int64_t n, int32_t latent, const hcz_codebook* cb,
+                          float* z, hcz_stream_t stream);
+/* Warm-start multipliers lam0 [H][4] (FP64) of the network for codes [H][16]. */
+hcz_status hcz_mlp_predict(const hcz_mlp* mlp, const uint8_t* codes, const hcz_codebook* cb, int64_t H,
+                           double* lam0, hcz_stream_t stream);
+
 /* ---- stage timing ---------------------------------------------------------------------
  * With profiling on, hcz_compress and hcz_decompress record a HIP event pair around every
  * kernel stage, on the caller's stream.  hcz_profile_read waits for the recorded events
@@ -267,7 +297,7 @@ hcz_status hcz_norm_stats(const hcz_plan* plan, const void* hist, int32_t dtype,
  * of calls (calls[HCZ_NSTAGES], host) since the previous read, then resets. */
 enum { HCZ_STAGE_ENCODE = 0, HCZ_STAGE_CODEBOOK, HCZ_STAGE_QUANTIZE, HCZ_STAGE_DECODE,
        HCZ_STAGE_RESIDUAL, HCZ_STAGE_SCAN, HCZ_STAGE_COMPACT, HCZ_STAGE_STATS,
-       HCZ_STAGE_DECOMPRESS, HCZ_NSTAGES };
+       HCZ_STAGE_DECOMPRESS, HCZ_STAGE_WARMSTART, HCZ_NSTAGES };
 hcz_status hcz_profile_enable(hcz_ctx* ctx, int enable);
 hcz_status hcz_profile_read(hcz_ctx* ctx, double* ms, int64_t* calls);
 

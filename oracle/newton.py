@@ -96,16 +96,50 @@ def newton_round(ft, A, b, lam, s, max_iter, mode):
     return lam, False, max_iter
 
 
+def scaled_residual(ft, A, b, lam) -> float:
+    """max_k |g_k| / (sum_j |A_kj| x_j + 1e-300): the stopping rule's measure."""
+    x = x_of(ft, A, lam)
+    return float(np.max(np.abs(A @ x - b) / (np.abs(A) @ x + 1e-300)))
+
+
+def warm_ok(ft, A, b, lam0, s) -> bool:
+    """Accept a warm start unless one Newton step from it makes the scaled residual grow."""
+    x = x_of(ft, A, lam0)
+    g0 = A @ x - b
+    if converged(g0, A, x):
+        return True
+    d = cholesky_solve((A * (x > 0)) @ A.T, g0)
+    if d is None:
+        return False
+    return scaled_residual(ft, A, b, lam0 + s * d) <= scaled_residual(ft, A, b, lam0)
+
+
 def project(ft: np.ndarray, b: np.ndarray, g: Grid, s: float = 1.0, max_iter: int = 50,
             max_iter2: int = 400, fallback: str = "backtrack", lam0=None):
     """Project one reconstruction ft (n_perp, n_par) onto {A x = b, x >= 0}.
 
-    Returns dict(lam, x, status, iters): status 0 = round 1 converged, 1 = round 2
-    converged, 2 = failed (store verbatim).
+    lam0: optional warm start; rejected (cold start, flag 'warm_rejected') if its first
+    Newton step makes the scaled residual grow (or if round 1 allows no update).  Returns dict(lam, x, status, iters,
+    warm_rejected): status 0 = round 1 converged, 1 = round 2 converged, 2 = failed
+    (store verbatim).
     """
     A = g.A()
     ftv = np.asarray(ft, np.float64).reshape(-1)
-    lam = np.zeros(4) if lam0 is None else np.asarray(lam0, np.float64)
+    rejected = False
+    lam = np.zeros(4)
+    if lam0 is not None:
+        lam0 = np.asarray(lam0, np.float64)
+        if max_iter >= 1 and np.all(np.isfinite(lam0)) and warm_ok(ftv, A, b, lam0, s):
+            lam = lam0
+        else:
+            rejected = True
+    res = _project_from(ftv, A, b, ft.shape, lam, s, max_iter, max_iter2, fallback)
+    res["warm_rejected"] = rejected
+    return res
+
+
+def _project_from(ftv, A, b, shape, lam, s, max_iter, max_iter2, fallback):
+    ft = ftv.reshape(shape)
     lam1, ok, it1 = newton_round(ftv, A, b, lam, s, max_iter, "fixed")
     if ok:
         return dict(lam=lam1, x=x_of(ftv, A, lam1).reshape(ft.shape), status=0, iters=it1)

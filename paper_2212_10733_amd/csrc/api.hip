@@ -121,6 +121,13 @@ struct hcz_model {
   std::vector<void*> allocs;
 };
 
+struct hcz_mlp {
+  hcz_ctx* ctx;
+  const float* params;
+  const double* scale;
+  std::vector<void*> allocs;
+};
+
 namespace {
 
 template <typename T>
@@ -183,6 +190,101 @@ DimTables dim_tables(int n, int L) {
 
 bool in_set(int n, int l, int i) { return i == n - 1 || (i % (1 << l)) == 0; }
 
+// Slot layout of the wave-per-histogram kernels.  Entry words:
+//   w0 = e | group << 13 | bilinear << 17 | valid << 18 | widx << 19 | tidx << 25
+//   w1 = a | b << 7 | aj << 14 | bj << 21
+// e: natural offset j * n_par + i.  Interpolation corners: (aj, a), (aj, b) and, for a
+// bilinear node, (bj, a), (bj, b); a node on a coarse row has aj = bj = j and weight
+// wtab[widx] = s, on a coarse column a = b = i and weight t, so p0 = y[aj, a] +
+// w (y[bj, b] - y[aj, a]) covers both linear cases.  The packing position of each entry
+// is kept apart (slot_pos).
+struct SlotTables {
+  int nslots = 0, ncoarse = 0;
+  std::vector<uint32_t> meta;
+  std::vector<uint16_t> pos;
+  std::vector<double> wtab;
+  std::vector<int8_t> group;
+  std::vector<uint8_t> sync;
+};
+
+SlotTables make_slots(int np, int nq, int L, const std::vector<uint32_t>& node, const std::vector<int>& gstart,
+                      const DimTables& dp, const DimTables& dq) {
+  SlotTables T;
+  const int nlev = L + 1;
+  T.wtab.push_back(0.0);
+  auto widx = [&](double w) {
+    for (size_t k = 0; k < T.wtab.size(); ++k)
+      if (T.wtab[k] == w) return (uint32_t)k;
+    T.wtab.push_back(w);
+    return (uint32_t)(T.wtab.size() - 1);
+  };
+  auto entry = [&](int p, int g, uint32_t* out) {
+    const int i = node[p] & 0xffff, j = node[p] >> 16;
+    const uint32_t e = (uint32_t)(j * np + i);
+    uint32_t w0 = e | ((uint32_t)g << 13) | (1u << 18), w1 = 0;
+    if (g > 0) {
+      const int l = L - g + 1;                   // group g holds G_{l-1}^2 minus G_l^2
+      const bool i_in = in_set(np, l, i), j_in = in_set(nq, l, j);
+      uint32_t a = i, b = i, aj = j, bj = j, wi = 0, ti = 0;
+      if (j_in) {                                 // along v_par on row j
+        a = dp.a[i]; b = dp.b[i]; wi = widx(dp.s[i]);
+      } else if (i_in) {                          // along v_perp on column i
+        aj = dq.a[j]; bj = dq.b[j]; wi = widx(dq.s[j]);
+      } else {
+        a = dp.a[i]; b = dp.b[i]; aj = dq.a[j]; bj = dq.b[j];
+        wi = widx(dp.s[i]); ti = widx(dq.s[j]);
+        w0 |= 1u << 17;
+      }
+      w0 |= (wi << 19) | (ti << 25);
+      w1 = a | (b << 7) | (aj << 14) | (bj << 21);
+    }
+    out[0] = w0;
+    out[1] = w1;
+  };
+  // slot 0: the coarsest groups while they fit in 64 lanes
+  int g = 0, cnt = 0;
+  while (g < nlev && cnt + (gstart[g + 1] - gstart[g]) <= 64) { cnt += gstart[g + 1] - gstart[g]; ++g; }
+  if (g == 0) return T;                           // coarsest group alone exceeds a slot
+  T.ncoarse = g;
+  std::vector<uint32_t> slot(64 * 2, 0);
+  std::vector<uint16_t> spos(64, 0);
+  for (int p = 0; p < cnt; ++p) {
+    int gg = 0;
+    while (p >= gstart[gg + 1]) ++gg;
+    entry(p, gg, &slot[2 * p]);
+    spos[p] = (uint16_t)p;
+  }
+  T.meta.insert(T.meta.end(), slot.begin(), slot.end());
+  T.pos.insert(T.pos.end(), spos.begin(), spos.end());
+  T.group.push_back(-1);
+  for (; g < nlev; ++g) {
+    std::vector<int> lin, bil;
+    for (int p = gstart[g]; p < gstart[g + 1]; ++p) {
+      uint32_t w[2];
+      entry(p, g, w);
+      ((w[0] >> 17) & 1 ? bil : lin).push_back(p);
+    }
+    lin.insert(lin.end(), bil.begin(), bil.end());
+    for (size_t k = 0; k < lin.size(); k += 64) {
+      std::fill(slot.begin(), slot.end(), 0u);
+      std::fill(spos.begin(), spos.end(), (uint16_t)0);
+      for (size_t q = k; q < std::min(lin.size(), k + 64); ++q) {
+        entry(lin[q], g, &slot[2 * (q - k)]);
+        spos[q - k] = (uint16_t)lin[q];
+      }
+      T.meta.insert(T.meta.end(), slot.begin(), slot.end());
+      T.pos.insert(T.pos.end(), spos.begin(), spos.end());
+      T.group.push_back((int8_t)g);
+    }
+  }
+  T.nslots = (int)T.group.size();
+  T.sync.resize(T.nslots);
+  for (int k = 0; k < T.nslots; ++k)
+    T.sync[k] = (k == 0 || k + 1 == T.nslots || T.group[k + 1] != T.group[k]) ? 1 : 0;
+  if (T.nslots > kWaveSlots || T.wtab.size() > 64) T.nslots = 0;
+  return T;
+}
+
 hcz_status check_hist(const void* hist, int32_t dtype, int64_t H, int64_t hs, int64_t rs,
                       const GridDev& G) {
   if (H < 0) return fail(HCZ_EINVAL, "H = %lld < 0", (long long)H);
@@ -203,6 +305,8 @@ hcz_status check_params(const hcz_params* p) {
   if (p->newton_max_iter < 0 || p->newton_max_iter2 < 0) return fail(HCZ_EINVAL, "newton iteration caps must be >= 0");
   if (p->fallback != HCZ_FALLBACK_BACKTRACK && p->fallback != HCZ_FALLBACK_PAPER) return fail(HCZ_EINVAL, "fallback");
   if (p->fit_codebook && p->sample_every < 1) return fail(HCZ_EINVAL, "sample_every must be >= 1");
+  if (p->warm_start != HCZ_WARM_COLD && p->warm_start != HCZ_WARM_MLP) return fail(HCZ_EINVAL, "warm_start");
+  if (p->warm_start == HCZ_WARM_MLP && !p->mlp) return fail(HCZ_EINVAL, "warm_start needs an mlp");
   return HCZ_OK;
 }
 
@@ -213,13 +317,14 @@ size_t slot_stride(const GridDev& G, int32_t dtype) {
 }
 
 struct WsLayout {
-  size_t z, fhat, sizes, kstar, iters, partial, slots, cbws, total;
+  size_t z, fhat, lam0, sizes, kstar, iters, partial, slots, cbws, total;
 };
 
 WsLayout ws_layout(const GridDev& G, bool model, int64_t H, int32_t dtype, bool fit, int64_t every) {
   WsLayout w{};
   size_t o = 0;
   w.z = o;      o += model ? align256((size_t)H * kLatent * 4) : 0;
+  w.lam0 = o;   o += model ? align256((size_t)H * 4 * 8) : 0;
   w.fhat = o;   o += model ? align256((size_t)H * G.N * 4) : 0;
   w.sizes = o;  o += align256((size_t)H * 8);
   w.kstar = o;  o += align256((size_t)H);
@@ -318,6 +423,7 @@ hcz_status hcz_plan_create(hcz_ctx* ctx, const hcz_grid* g, hcz_plan** out) {
   }
   if ((int)node.size() != N) return fail(HCZ_EINVAL, "internal: node layout has %zu of %d nodes", node.size(), N);
   DimTables dp = dim_tables(np, L), dq = dim_tables(nq, L);
+  SlotTables slots = make_slots(np, nq, L, node, gstart, dp, dq);
   hcz_plan* P = new hcz_plan();
   P->ctx = ctx;
   GridDev& G = P->G;
@@ -335,12 +441,21 @@ hcz_status hcz_plan_create(hcz_ctx* ctx, const hcz_grid* g, hcz_plan** out) {
   G.Vpar = Vpar;
   G.Vperp = Vperp;
   G.mass = g->mass;
+  G.nslots = slots.nslots;
+  G.ncoarse = slots.ncoarse;
+  G.nw = (int)slots.wtab.size();
+  for (int k = 0; k < kWaveSlots; ++k) {
+    G.slot_group[k] = k < slots.nslots ? slots.group[k] : 0;
+    G.slot_sync[k] = k < slots.nslots ? slots.sync[k] : 0;
+  }
   if ((s = upload(P->allocs, vol, &G.vol)) || (s = upload(P->allocs, apar, &G.apar)) ||
       (s = upload(P->allocs, cperp, &G.cperp)) || (s = upload(P->allocs, node, &G.node_ij)) ||
       (s = upload(P->allocs, dp.lev, &G.lev_par)) || (s = upload(P->allocs, dp.a, &G.a_par)) ||
       (s = upload(P->allocs, dp.b, &G.b_par)) || (s = upload(P->allocs, dp.s, &G.s_par)) ||
       (s = upload(P->allocs, dq.lev, &G.lev_perp)) || (s = upload(P->allocs, dq.a, &G.a_perp)) ||
-      (s = upload(P->allocs, dq.b, &G.b_perp)) || (s = upload(P->allocs, dq.s, &G.s_perp))) {
+      (s = upload(P->allocs, dq.b, &G.b_perp)) || (s = upload(P->allocs, dq.s, &G.s_perp)) ||
+      (s = upload(P->allocs, slots.meta, &G.slot_meta)) || (s = upload(P->allocs, slots.pos, &G.slot_pos)) ||
+      (s = upload(P->allocs, slots.wtab, &G.wtab))) {
     free_all(P->allocs);
     delete P;
     return s;
@@ -491,7 +606,8 @@ hcz_status hcz_decompress_workspace(const hcz_plan* plan, const hcz_model* model
 
 static hcz_status residual_impl(const hcz_plan* plan, const hcz_params* p, const void* hist,
                                 int32_t dtype, int64_t H, int64_t hs, int64_t rs, const float* fhat,
-                                hcz_compressed* out, uint8_t* ws, const WsLayout& L, hipStream_t st) {
+                                const double* lam0, hcz_compressed* out, uint8_t* ws, const WsLayout& L,
+                                hipStream_t st) {
   const GridDev& G = plan->G;
   ResidualArgs a{};
   a.hist = hist;
@@ -513,6 +629,7 @@ static hcz_status residual_impl(const hcz_plan* plan, const hcz_params* p, const
   a.slot_stride = (long long)slot_stride(G, dtype);
   a.kstar = ws + L.kstar;
   a.iters = (uint16_t*)(ws + L.iters);
+  a.lam0 = lam0;
   hcz_ctx* c = plan->ctx;
   {
     StageTimer tm(c, HCZ_STAGE_RESIDUAL, st);
@@ -546,8 +663,8 @@ static hcz_status check_out(const hcz_compressed* out, int64_t H, bool codes) {
 
 hcz_status hcz_residual(const hcz_plan* plan, const hcz_params* params, const void* hist,
                         int32_t dtype, int64_t H, int64_t hist_stride, int64_t row_stride,
-                        const float* fhat, hcz_compressed* out, void* ws, size_t ws_bytes,
-                        hcz_stream_t stream) {
+                        const float* fhat, const double* lam0, hcz_compressed* out, void* ws,
+                        size_t ws_bytes, hcz_stream_t stream) {
   if (!plan) return fail(HCZ_EINVAL, "plan is NULL");
   hcz_status s;
   if ((s = check_params(params)) || (s = check_hist(hist, dtype, H, hist_stride, row_stride, plan->G)) ||
@@ -557,8 +674,8 @@ hcz_status hcz_residual(const hcz_plan* plan, const hcz_params* params, const vo
   if (!ws || ws_bytes < L.total) return fail(HCZ_EWORKSPACE, "workspace %zu < %zu", ws_bytes, L.total);
   if ((s = set_device(plan->ctx))) return s;
   prof_begin(plan->ctx);
-  return residual_impl(plan, params, hist, dtype, H, hist_stride, row_stride, fhat, out, (uint8_t*)ws, L,
-                       (hipStream_t)stream);
+  return residual_impl(plan, params, hist, dtype, H, hist_stride, row_stride, fhat, lam0, out,
+                       (uint8_t*)ws, L, (hipStream_t)stream);
 }
 
 hcz_status hcz_compress(const hcz_plan* plan, const hcz_model* model, hcz_codebook* cb,
@@ -581,6 +698,7 @@ hcz_status hcz_compress(const hcz_plan* plan, const hcz_model* model, hcz_codebo
   const float* fhat = nullptr;
   hcz_ctx* c = plan->ctx;
   prof_begin(c);
+  const double* lam0 = nullptr;
   if (model && H > 0) {
     float* z = (float*)(w + L.z);
     float* fh = (float*)(w + L.fhat);
@@ -602,8 +720,14 @@ hcz_status hcz_compress(const hcz_plan* plan, const hcz_model* model, hcz_codebo
       HCZ_TRY(launch_decode(model->M, out->codes, cb->centroids, cb->bits, H, fh, st), "decode launch");
     }
     fhat = fh;
+    if (params->warm_start == HCZ_WARM_MLP) {
+      StageTimer tm(c, HCZ_STAGE_WARMSTART, st);
+      lam0 = (const double*)(w + L.lam0);
+      HCZ_TRY(launch_mlp_infer(params->mlp->params, params->mlp->scale, out->codes, cb->centroids, cb->bits, H,
+                               (double*)(w + L.lam0), st), "warm start launch");
+    }
   }
-  return residual_impl(plan, params, hist, dtype, H, hist_stride, row_stride, fhat, out, w, L, st);
+  return residual_impl(plan, params, hist, dtype, H, hist_stride, row_stride, fhat, lam0, out, w, L, st);
 }
 
 hcz_status hcz_decompress(const hcz_plan* plan, const hcz_model* model, const hcz_codebook* cb,
@@ -784,6 +908,124 @@ hcz_status hcz_norm_stats(const hcz_plan* plan, const void* hist, int32_t dtype,
   if ((s = set_device(plan->ctx))) return s;
   HCZ_TRY(launch_norm_stats(hist, dtype, H, hist_stride, row_stride, plan->G.n_par, plan->G.N, mean, sd, ws,
                             (hipStream_t)stream), "norm stats");
+  return HCZ_OK;
+}
+
+// ---- warm-start network -------------------------------------------------------------
+namespace {
+constexpr int kMH = 64, kMI = 16, kMO = 4;
+struct MlpOffsets { size_t W1, b1, W2, b2, W3, b3; };
+MlpOffsets mlp_offsets() {
+  MlpOffsets o{};
+  size_t p = 0;
+  o.W1 = p; p += kMH * kMI;
+  o.b1 = p; p += kMH;
+  o.W2 = p; p += kMH * kMH;
+  o.b2 = p; p += kMH;
+  o.W3 = p; p += kMO * kMH;
+  o.b3 = p;
+  return o;
+}
+size_t mlp_saved_floats(long long B) { return (size_t)B * 4 * kMH; }
+}  // namespace
+
+hcz_status hcz_mlp_param_count(int64_t* count) {
+  if (!count) return fail(HCZ_EINVAL, "NULL argument");
+  *count = mlp_param_count();
+  return HCZ_OK;
+}
+
+hcz_status hcz_mlp_saved_bytes(int64_t B, size_t* bytes) {
+  if (!bytes || B < 0) return fail(HCZ_EINVAL, "bad argument");
+  *bytes = mlp_saved_floats(B) * sizeof(float);
+  return HCZ_OK;
+}
+
+hcz_status hcz_mlp_load(hcz_ctx* ctx, const float* params, const double* scale, hcz_mlp** out) {
+  if (!ctx || !params || !scale || !out) return fail(HCZ_EINVAL, "NULL argument");
+  *out = nullptr;
+  for (int k = 0; k < 4; ++k)
+    if (!std::isfinite(scale[k])) return fail(HCZ_EINVAL, "scale must be finite");
+  hcz_status s = set_device(ctx);
+  if (s) return s;
+  hcz_mlp* m = new hcz_mlp();
+  m->ctx = ctx;
+  std::vector<float> pv(params, params + mlp_param_count());
+  std::vector<double> sv(scale, scale + 4);
+  if ((s = upload(m->allocs, pv, &m->params)) || (s = upload(m->allocs, sv, &m->scale))) {
+    free_all(m->allocs);
+    delete m;
+    return s;
+  }
+  *out = m;
+  return HCZ_OK;
+}
+
+void hcz_mlp_free(hcz_mlp* m) {
+  if (!m) return;
+  free_all(m->allocs);
+  delete m;
+}
+
+hcz_status hcz_mlp_forward(const float* params, const float* z, int64_t B, float* out, void* saved,
+                           size_t saved_bytes, hcz_stream_t stream) {
+  if (B < 0) return fail(HCZ_EINVAL, "B < 0");
+  if (B == 0) return HCZ_OK;
+  if (!params || !z || !out || !saved) return fail(HCZ_EINVAL, "NULL buffer");
+  if (saved_bytes < mlp_saved_floats(B) * sizeof(float)) return fail(HCZ_EWORKSPACE, "saved buffer too small");
+  const MlpOffsets o = mlp_offsets();
+  hipStream_t st = (hipStream_t)stream;
+  float* h1 = (float*)saved;
+  float* h2 = h1 + (size_t)B * kMH;
+  HCZ_TRY(launch_gemm(z, kMI, 1, params + o.W1, 1, kMI, h1, kMH, B, kMH, kMI, 1.f, 0.f, params + o.b1, 1, st), "gemm");
+  HCZ_TRY(launch_gemm(h1, kMH, 1, params + o.W2, 1, kMH, h2, kMH, B, kMH, kMH, 1.f, 0.f, params + o.b2, 1, st), "gemm");
+  HCZ_TRY(launch_gemm(h2, kMH, 1, params + o.W3, 1, kMH, out, kMO, B, kMO, kMH, 1.f, 0.f, params + o.b3, 0, st), "gemm");
+  return HCZ_OK;
+}
+
+hcz_status hcz_mlp_backward(const float* params, const float* z, int64_t B, const float* dout, void* saved,
+                            size_t saved_bytes, float* grad, hcz_stream_t stream) {
+  if (B < 0) return fail(HCZ_EINVAL, "B < 0");
+  if (!params || !grad) return fail(HCZ_EINVAL, "NULL buffer");
+  if (B > 0 && (!z || !dout || !saved)) return fail(HCZ_EINVAL, "NULL buffer");
+  if (saved_bytes < mlp_saved_floats(B) * sizeof(float)) return fail(HCZ_EWORKSPACE, "saved buffer too small");
+  const MlpOffsets o = mlp_offsets();
+  hipStream_t st = (hipStream_t)stream;
+  float* h1 = (float*)saved;
+  float* h2 = h1 + (size_t)B * kMH;
+  float* d2 = h2 + (size_t)B * kMH;
+  float* d1 = d2 + (size_t)B * kMH;
+  HCZ_TRY(launch_gemm(dout, 1, kMO, h2, kMH, 1, grad + o.W3, kMH, kMO, kMH, B, 1.f, 0.f, nullptr, 0, st), "gemm");
+  HCZ_TRY(launch_colsum(dout, B, kMO, grad + o.b3, st), "colsum");
+  HCZ_TRY(launch_gemm(dout, kMO, 1, params + o.W3, kMH, 1, d2, kMH, B, kMH, kMO, 1.f, 0.f, nullptr, 0, st), "gemm");
+  HCZ_TRY(launch_relu_mask(d2, h2, (long long)B * kMH, st), "mask");
+  HCZ_TRY(launch_gemm(d2, 1, kMH, h1, kMH, 1, grad + o.W2, kMH, kMH, kMH, B, 1.f, 0.f, nullptr, 0, st), "gemm");
+  HCZ_TRY(launch_colsum(d2, B, kMH, grad + o.b2, st), "colsum");
+  HCZ_TRY(launch_gemm(d2, kMH, 1, params + o.W2, kMH, 1, d1, kMH, B, kMH, kMH, 1.f, 0.f, nullptr, 0, st), "gemm");
+  HCZ_TRY(launch_relu_mask(d1, h1, (long long)B * kMH, st), "mask");
+  HCZ_TRY(launch_gemm(d1, 1, kMH, z, kMI, 1, grad + o.W1, kMI, kMH, kMI, B, 1.f, 0.f, nullptr, 0, st), "gemm");
+  HCZ_TRY(launch_colsum(d1, B, kMH, grad + o.b1, st), "colsum");
+  return HCZ_OK;
+}
+
+hcz_status hcz_dequantize(const uint8_t* codes, int64_t n, int32_t latent, const hcz_codebook* cb, float* z,
+                          hcz_stream_t stream) {
+  if (n < 0 || latent < 1) return fail(HCZ_EINVAL, "bad size");
+  if (n > 0 && (!codes || !z)) return fail(HCZ_EINVAL, "NULL buffer");
+  hcz_status s = check_cb(cb);
+  if (s) return s;
+  HCZ_TRY(launch_dequant(codes, n, latent, cb->centroids, cb->bits, z, (hipStream_t)stream), "dequant");
+  return HCZ_OK;
+}
+
+hcz_status hcz_mlp_predict(const hcz_mlp* mlp, const uint8_t* codes, const hcz_codebook* cb, int64_t H,
+                           double* lam0, hcz_stream_t stream) {
+  if (!mlp || H < 0) return fail(HCZ_EINVAL, "bad argument");
+  if (H > 0 && (!codes || !lam0)) return fail(HCZ_EINVAL, "NULL buffer");
+  hcz_status s = check_cb(cb);
+  if (s) return s;
+  HCZ_TRY(launch_mlp_infer(mlp->params, mlp->scale, codes, cb->centroids, cb->bits, H, lam0, (hipStream_t)stream),
+          "mlp");
   return HCZ_OK;
 }
 

@@ -14,6 +14,7 @@ constexpr int kMaxDim = 128;        // largest n_par / n_perp of a grid
 constexpr int kMaxN = 4608;         // largest n_par * n_perp (keeps per-block LDS < 64 KB)
 constexpr int kMaxLev = 9;          // L + 1 for n <= 128 is at most 8
 constexpr int kLadder = 41;         // quantisation ladder k = 0..40
+constexpr int kWaveSlots = 26;     // slots of 64 nodes a wave-per-histogram kernel holds
 constexpr int kHidden = 128;
 constexpr int kLatent = 16;
 
@@ -46,6 +47,16 @@ struct GridDev {
   const uint8_t* a_perp;
   const uint8_t* b_perp;
   const double* s_perp;
+  // Wave-per-histogram layout: the nodes split into nslots slots of 64 (one node per
+  // lane), each slot within one coefficient group except slot 0, which holds the
+  // ncoarse coarsest groups in order.  Within a group, nodes with linear interpolation
+  // come before bilinear ones.  nslots = 0: grid too large for the wave kernels.
+  int nslots, ncoarse, nw;
+  int8_t slot_group[kWaveSlots];     // -1 for the multi-group slot 0
+  uint8_t slot_sync[kWaveSlots];     // 1 if the next slot belongs to a later group
+  const uint32_t* slot_meta;         // [nslots * 64][2], see make_slots()
+  const uint16_t* slot_pos;          // [nslots * 64] packing position of each entry
+  const double* wtab;                // [nw] distinct interpolation weights, wtab[0] = 0
 };
 
 struct ModelDev {
@@ -80,6 +91,7 @@ struct ResidualArgs {
   long long slot_stride;
   uint8_t* kstar;              // [H] 0xff if not coded
   uint16_t* iters;             // [H]
+  const double* lam0;          // [H][4] warm start or null
 };
 
 struct DecompressArgs {
@@ -269,6 +281,9 @@ __device__ __forceinline__ double correction(const Aphi& A, const double (&lam)[
 hipError_t launch_qoi(const GridDev& G, const void* hist, int dtype, long long H, long long hs,
                       long long rs, double* b, double* qoi, double* norm, hipStream_t st);
 hipError_t launch_residual(const GridDev& G, const ResidualArgs& a, hipStream_t st);
+bool wave_path(const GridDev& G);
+hipError_t launch_residual_w(const GridDev& G, const ResidualArgs& a, hipStream_t st);
+hipError_t launch_decompress_w(const GridDev& G, const DecompressArgs& a, hipStream_t st);
 hipError_t launch_decompress(const GridDev& G, const DecompressArgs& a, hipStream_t st);
 hipError_t launch_scan(const uint64_t* sizes, uint64_t* offsets, long long H, uint64_t* partial,
                        hipStream_t st);
@@ -296,6 +311,11 @@ hipError_t launch_mse(const float* xh, const float* x, long long n, float* loss,
                       hipStream_t st);
 hipError_t launch_adam(float* p, const float* g, float* m, float* v, long long n, double lr, double b1,
                        double b2, double eps, long long step, hipStream_t st);
+int mlp_param_count();
+hipError_t launch_mlp_infer(const float* params, const double* scale, const uint8_t* codes,
+                            const float* centroids, int bits, long long H, double* lam0, hipStream_t st);
+hipError_t launch_dequant(const uint8_t* codes, long long n, int latent, const float* centroids, int bits,
+                          float* z, hipStream_t st);
 size_t norm_stats_ws_bytes(long long H, int N);
 hipError_t launch_norm_stats(const void* hist, int dtype, long long H, long long hs, long long rs, int n_par,
                              int N, float* mean, float* sd, void* ws, hipStream_t st);

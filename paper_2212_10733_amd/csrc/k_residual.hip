@@ -393,6 +393,46 @@ __global__ __launch_bounds__(NT) void k_residual(GridDev G, ResidualArgs a) {
     double ftm[NPT];
 #pragma unroll
     for (int m = 0; m < NPT; ++m) ftm[m] = (double)fm[m] + ym[m];
+    if (a.lam0) {
+      // warm start: keep it unless round 1 allows no update, its Cholesky step fails, or
+      // that step makes max_k |g_k| / s_k grow
+      double l0[4], v[16], g[4], d[4];
+      bool ok0 = a.max_iter >= 1;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) { l0[k] = a.lam0[h * 4 + k]; ok0 = ok0 && isfinite(l0[k]); }
+      if (ok0) {
+        newton_pass<NT, NPT>(ftm, Am, em, l0, v, red);
+        double r0 = 0.0;
+        bool conv = true;
+        const double sc[4] = {v[0], v[4], v[2], v[3]};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          g[k] = v[k] - b[k];
+          conv = conv && (fabs(g[k]) <= kGTol * (sc[k] + 1e-300));
+          r0 = fmax(r0, fabs(g[k]) / (sc[k] + 1e-300));
+        }
+        if (!conv) {
+          ok0 = chol_solve4(v, g, d);
+          if (ok0) {
+            double l1[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) l1[k] = l0[k] + a.newton_s * d[k];
+            newton_pass<NT, NPT>(ftm, Am, em, l1, v, red);
+            const double sc1[4] = {v[0], v[4], v[2], v[3]};
+            double r1 = 0.0;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) r1 = fmax(r1, fabs(v[k] - b[k]) / (sc1[k] + 1e-300));
+            ok0 = r1 <= r0;
+          }
+        }
+      }
+      if (ok0) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) lam[k] = l0[k];
+      } else {
+        flags |= HCZ_FLAG_WARM_REJECTED;
+      }
+    }
     int u1 = 0;
     bool ok = newton_round<NT, NPT>(ftm, Am, em, b, lam, a.newton_s, a.max_iter, false, red, &u1);
     total_upd = u1;
@@ -408,7 +448,7 @@ __global__ __launch_bounds__(NT) void k_residual(GridDev G, ResidualArgs a) {
 
   uint64_t size = 0;
   if (raw) {
-    flags = (flags & HCZ_FLAG_ROUND2) | HCZ_FLAG_RAW;
+    flags = (flags & (HCZ_FLAG_ROUND2 | HCZ_FLAG_WARM_REJECTED)) | HCZ_FLAG_RAW;
     TIn* dst = (TIn*)(a.slots + h * a.slot_stride);
     int i = t % G.n_par, j = t / G.n_par;
     const int di = NT % G.n_par, dj = NT / G.n_par;
@@ -595,6 +635,7 @@ static int pick_nt(int N) { return N <= 1536 ? 256 : (N <= 3072 ? 512 : 1024); }
 
 hipError_t launch_residual(const GridDev& G, const ResidualArgs& a, hipStream_t st) {
   if (a.H <= 0) return hipSuccess;
+  if (wave_path(G)) return launch_residual_w(G, a, st);
   const int nt = pick_nt(G.N);
   const size_t lds = (size_t)G.N * 8 + (size_t)((G.N + 1) / 2) * 8 + (size_t)(nt / 64) * 16 * 8;
   dim3 grid((unsigned)a.H), block(nt);
@@ -621,6 +662,7 @@ hipError_t launch_qoi(const GridDev& G, const void* hist, int dtype, long long H
 
 hipError_t launch_decompress(const GridDev& G, const DecompressArgs& a, hipStream_t st) {
   if (a.H <= 0) return hipSuccess;
+  if (wave_path(G)) return launch_decompress_w(G, a, st);
   const int nt = pick_nt(G.N);
   const size_t lds = (size_t)G.N * 8;
   dim3 grid((unsigned)a.H), block(nt);

@@ -19,7 +19,8 @@ F32, F64 = 0, 1
 ARCH_DENSE = 1
 TAU_REL_L2, TAU_NRMSE = 0, 1
 FALLBACK_BACKTRACK, FALLBACK_PAPER = 0, 1
-FLAG_CODED, FLAG_ROUND2, FLAG_RAW = 1, 2, 4
+FLAG_CODED, FLAG_ROUND2, FLAG_RAW, FLAG_WARM_REJECTED = 1, 2, 4, 8
+WARM_COLD, WARM_MLP = 0, 1
 HIDDEN, LATENT = 128, 16
 
 STATUS = {0: "HCZ_OK", -1: "HCZ_EINVAL", -2: "HCZ_ENOMEM", -3: "HCZ_EHIP",
@@ -51,7 +52,8 @@ class Codebook(C.Structure):
 class Params(C.Structure):
     _fields_ = [("tau", C.c_double), ("tau_mode", C.c_int32), ("newton_s", C.c_double),
                 ("newton_max_iter", C.c_int32), ("newton_max_iter2", C.c_int32),
-                ("fallback", C.c_int32), ("fit_codebook", C.c_int32), ("sample_every", C.c_int32)]
+                ("fallback", C.c_int32), ("fit_codebook", C.c_int32), ("sample_every", C.c_int32),
+                ("warm_start", C.c_int32), ("mlp", C.c_void_p)]
 
 
 class Stats(C.Structure):
@@ -89,7 +91,14 @@ def _load() -> C.CDLL:
         "hcz_codebook_fit": [vp, i64, i32, i64, C.POINTER(Codebook), vp, sz, vp],
         "hcz_quantize": [vp, i64, i32, C.POINTER(Codebook), vp, vp],
         "hcz_decode": [vp, vp, C.POINTER(Codebook), i64, vp, vp],
-        "hcz_residual": [vp, C.POINTER(Params), vp, i32, i64, i64, i64, vp, C.POINTER(CompressedC), vp, sz, vp],
+        "hcz_residual": [vp, C.POINTER(Params), vp, i32, i64, i64, i64, vp, vp, C.POINTER(CompressedC), vp, sz, vp],
+        "hcz_mlp_load": [vp, vp, vp, C.POINTER(vp)],
+        "hcz_mlp_param_count": [C.POINTER(i64)],
+        "hcz_mlp_saved_bytes": [i64, C.POINTER(sz)],
+        "hcz_mlp_forward": [vp, vp, i64, vp, vp, sz, vp],
+        "hcz_mlp_backward": [vp, vp, i64, vp, vp, sz, vp, vp],
+        "hcz_dequantize": [vp, i64, i32, C.POINTER(Codebook), vp, vp],
+        "hcz_mlp_predict": [vp, vp, C.POINTER(Codebook), i64, vp, vp],
         "hcz_compress_workspace": [vp, vp, i64, C.POINTER(Params), C.POINTER(sz)],
         "hcz_decompress_workspace": [vp, vp, i64, C.POINTER(sz)],
         "hcz_compress": [vp, vp, C.POINTER(Codebook), C.POINTER(Params), vp, i32, i64, i64, i64,
@@ -112,7 +121,7 @@ def _load() -> C.CDLL:
         fn = getattr(lib, name)
         fn.argtypes = args
         fn.restype = C.c_int
-    for name in ("hcz_destroy", "hcz_plan_destroy", "hcz_model_free"):
+    for name in ("hcz_destroy", "hcz_plan_destroy", "hcz_model_free", "hcz_mlp_free"):
         getattr(lib, name).argtypes = [vp]
         getattr(lib, name).restype = None
     lib.hcz_last_error.restype = C.c_char_p
@@ -129,9 +138,12 @@ EXPORTS = ["hcz_create", "hcz_destroy", "hcz_last_error", "hcz_version", "hcz_pl
            "hcz_residual", "hcz_compress_workspace", "hcz_decompress_workspace", "hcz_compress",
            "hcz_decompress", "hcz_stats_read", "hcz_profile_enable", "hcz_profile_read",
            "hcz_ae_param_count", "hcz_ae_saved_bytes", "hcz_ae_forward", "hcz_ae_backward",
-           "hcz_mse_workspace", "hcz_mse", "hcz_adam_step", "hcz_norm_stats_workspace", "hcz_norm_stats"]
+           "hcz_mse_workspace", "hcz_mse", "hcz_adam_step", "hcz_norm_stats_workspace", "hcz_norm_stats",
+           "hcz_mlp_load", "hcz_mlp_free", "hcz_mlp_param_count", "hcz_mlp_saved_bytes", "hcz_mlp_forward",
+           "hcz_mlp_backward", "hcz_dequantize", "hcz_mlp_predict"]
 
-STAGES = ["encode", "codebook", "quantize", "decode", "residual", "scan", "compact", "stats", "decompress"]
+STAGES = ["encode", "codebook", "quantize", "decode", "residual", "scan", "compact", "stats", "decompress",
+          "warmstart"]
 
 
 def _check(status: int) -> None:
@@ -235,9 +247,44 @@ class Model:
 
 
 def params(tau=1e-3, tau_mode=TAU_REL_L2, newton_s=1.0, newton_max_iter=50, newton_max_iter2=400,
-           fallback=FALLBACK_BACKTRACK, fit_codebook=False, sample_every=16) -> Params:
-    return Params(tau, tau_mode, newton_s, newton_max_iter, newton_max_iter2, fallback,
-                  int(fit_codebook), sample_every)
+           fallback=FALLBACK_BACKTRACK, fit_codebook=False, sample_every=16, mlp=None) -> Params:
+    p = Params(tau, tau_mode, newton_s, newton_max_iter, newton_max_iter2, fallback,
+               int(fit_codebook), sample_every, WARM_MLP if mlp is not None else WARM_COLD,
+               None if mlp is None else mlp.h)
+    p._mlp = mlp          # keep the network alive as long as the parameters
+    return p
+
+
+class Mlp:
+    """The warm-start multiplier network on the device (inference)."""
+
+    def __init__(self, ctx: Context, params: np.ndarray, scale):
+        self.ctx = ctx
+        w = np.ascontiguousarray(params, np.float32)
+        sc = np.ascontiguousarray(scale, np.float64)
+        h = C.c_void_p()
+        _check(LIB.hcz_mlp_load(ctx.h, w.ctypes.data_as(C.c_void_p), sc.ctypes.data_as(C.c_void_p), C.byref(h)))
+        self.h = h
+
+    def predict(self, codes: torch.Tensor, centroids: torch.Tensor) -> torch.Tensor:
+        H = codes.shape[0]
+        out = torch.empty((H, 4), dtype=torch.float64, device=codes.device)
+        cb = _cb(centroids)
+        _check(LIB.hcz_mlp_predict(self.h, _ptr(codes.contiguous()), C.byref(cb), H, _ptr(out), _stream()))
+        return out
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            LIB.hcz_mlp_free(self.h)
+            self.h = None
+
+
+def dequantize(codes: torch.Tensor, centroids: torch.Tensor) -> torch.Tensor:
+    n, L = codes.shape
+    z = torch.empty((n, L), dtype=torch.float32, device=codes.device)
+    cb = _cb(centroids)
+    _check(LIB.hcz_dequantize(_ptr(codes.contiguous()), n, L, C.byref(cb), _ptr(z), _stream()))
+    return z
 
 
 @dataclass
@@ -342,7 +389,7 @@ def decode(model: Model, codes: torch.Tensor, centroids: torch.Tensor) -> torch.
 
 
 def residual(plan: Plan, p: Params, hist: torch.Tensor, fhat: torch.Tensor | None,
-             capacity: int | None = None) -> Compressed:
+             capacity: int | None = None, lam0: torch.Tensor | None = None) -> Compressed:
     H, hs, rs = _strides(hist)
     nbytes = C.c_size_t()
     _check(LIB.hcz_compress_workspace(plan.h, None, H, C.byref(p), C.byref(nbytes)))
@@ -350,7 +397,8 @@ def residual(plan: Plan, p: Params, hist: torch.Tensor, fhat: torch.Tensor | Non
     out = alloc_compressed(H, plan.N, hist.device, capacity=capacity, in_bytes=hist.element_size())
     cs = out.cstruct()
     fh = None if fhat is None else fhat.contiguous()
-    _check(LIB.hcz_residual(plan.h, C.byref(p), _ptr(hist), _dtype_code(hist), H, hs, rs, _ptr(fh),
+    l0 = None if lam0 is None else lam0.contiguous()
+    _check(LIB.hcz_residual(plan.h, C.byref(p), _ptr(hist), _dtype_code(hist), H, hs, rs, _ptr(fh), _ptr(l0),
                             C.byref(cs), _ptr(ws), ws.numel(), _stream()))
     out._ws = ws
     return out

@@ -137,3 +137,70 @@ class Trainer:
             if log:
                 log(f"epoch {ep + 1}: loss {losses[-1]:.5f}")
         return losses
+
+
+# ---- warm-start network -------------------------------------------------------------------
+
+MLP_KEYS = ("W1", "b1", "W2", "b2", "W3", "b3")
+MLP_SHAPES = dict(W1=(64, 16), b1=(64,), W2=(64, 64), b2=(64,), W3=(4, 64), b3=(4,))
+
+
+def mlp_pack(P: dict, device="cuda") -> torch.Tensor:
+    return torch.from_numpy(np.concatenate([np.ascontiguousarray(P[k], np.float32).ravel()
+                                            for k in MLP_KEYS])).to(device)
+
+
+def mlp_unpack(p: torch.Tensor) -> dict:
+    out, o = {}, 0
+    flat = p.detach().cpu().numpy()
+    for k in MLP_KEYS:
+        n = int(np.prod(MLP_SHAPES[k]))
+        out[k] = flat[o:o + n].reshape(MLP_SHAPES[k]).copy()
+        o += n
+    return out
+
+
+class MlpNet(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, z: torch.Tensor, params: torch.Tensor):
+        z = z.contiguous()
+        B = z.shape[0]
+        nbytes = C.c_size_t()
+        _check(LIB.hcz_mlp_saved_bytes(B, C.byref(nbytes)))
+        saved = torch.empty(max(nbytes.value, 4) // 4, dtype=torch.float32, device=z.device)
+        out = torch.empty((B, 4), dtype=torch.float32, device=z.device)
+        _check(LIB.hcz_mlp_forward(_ptr(params), _ptr(z), B, _ptr(out), _ptr(saved), saved.numel() * 4, _stream()))
+        ctx.save_for_backward(z, params, saved)
+        return out
+
+    @staticmethod
+    def backward(ctx, dout):
+        z, params, saved = ctx.saved_tensors
+        grad = torch.empty_like(params)
+        _check(LIB.hcz_mlp_backward(_ptr(params), _ptr(z), z.shape[0], _ptr(dout.contiguous()), _ptr(saved),
+                                    saved.numel() * 4, _ptr(grad), _stream()))
+        return None, grad
+
+
+def fit_mlp(Z: torch.Tensor, T: torch.Tensor, P0: dict, epochs: int = 30, batch: int = 1024, lr: float = 1e-3,
+            seed: int = 0) -> tuple[torch.Tensor, list]:
+    """Train the warm-start network on latents Z [n][16] and scaled targets T [n][4] with MSE
+    and Adam (hcz_adam_step); returns (packed parameters, per-epoch losses)."""
+    tr = Trainer(mlp_pack(P0, Z.device), lr=lr)
+    g = torch.Generator(device=Z.device)
+    g.manual_seed(seed)
+    losses = []
+    n = Z.shape[0]
+    for _ in range(epochs):
+        perm = torch.randperm(n, generator=g, device=Z.device)
+        tot, nb = torch.zeros((), dtype=torch.float64, device=Z.device), 0
+        for s in range(0, n - batch + 1, batch):
+            idx = perm[s:s + batch]
+            p = tr.p.detach().requires_grad_(True)
+            loss = mse(MlpNet.apply(Z[idx], p), T[idx].contiguous())
+            loss.backward()
+            tr.step(p.grad)
+            tot += loss.detach()
+            nb += 1
+        losses.append((tot / max(nb, 1)).item())
+    return tr.p, losses

@@ -30,10 +30,28 @@ def test_version_and_last_error():
     assert isinstance(hcz.LIB.hcz_last_error(), bytes)
 
 
-def test_struct_layouts_match_header():
-    assert C.sizeof(hcz.Stats) == 8 * (8 + 64 + 48)
-    assert C.sizeof(hcz.Params) == 48
-    assert C.sizeof(hcz.Grid) == 4 + 4 + 5 * 8 + 8
+def test_struct_layouts_match_header(tmp_path):
+    # compile the header with the host C compiler and compare sizes and offsets with ctypes
+    import subprocess
+    src = tmp_path / "layout.c"
+    fields = {"hcz_params": hcz.Params, "hcz_grid": hcz.Grid, "hcz_stats": hcz.Stats,
+              "hcz_compressed": hcz.CompressedC, "hcz_codebook": hcz.Codebook, "hcz_model_desc": hcz.ModelDesc}
+    cname = {"lambda_": "lambda"}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void) {"]
+    for st, cls in fields.items():
+        lines.append(f'  printf("{st} %zu\\n", sizeof({st}));')
+        for f, _ in cls._fields_:
+            lines.append(f'  printf("{st}.{f} %zu\\n", offsetof({st}, {cname.get(f, f)}));')
+    lines.append("  return 0; }")
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", str(src), "-o", str(exe)], check=True)
+    out = dict(l.rsplit(" ", 1) for l in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                          check=True).stdout.split("\n") if l)
+    for st, cls in fields.items():
+        assert int(out[st]) == C.sizeof(cls), st
+        for f, _ in cls._fields_:
+            assert int(out[f"{st}.{f}"]) == getattr(cls, f).offset, (st, f)
 
 
 def bad_grid(**kw):
@@ -59,7 +77,7 @@ def test_null_arguments_are_rejected():
     assert L.hcz_plan_create(None, None, None) == -1
     assert L.hcz_qoi(None, None, 0, 1, 1521, 39, None, None, None, None) == -1
     assert L.hcz_encode(None, None, 0, 1, 1521, 39, None, None) == -1
-    assert L.hcz_residual(None, None, None, 0, 1, 1521, 39, None, None, None, 0, None) == -1
+    assert L.hcz_residual(None, None, None, 0, 1, 1521, 39, None, None, None, None, 0, None) == -1
     assert L.hcz_compress(None, None, None, None, None, 0, 1, 1521, 39, None, None, 0, None) == -1
     assert L.hcz_decompress(None, None, None, None, 0, 1, None, 1, None, 0, None) == -1
     assert L.hcz_stats_read(None, None, None) == -1

@@ -135,7 +135,7 @@ def test_decode_parity(H, ctx, Hn, shape):
 
 # ---- residual coder + Newton -------------------------------------------------------------------
 
-def oracle_residual(F, fhat, g, p):
+def oracle_residual(F, fhat, g, p, lam0=None):
     """Oracle compress with a given reconstruction (the coder-only pipeline when fhat is None)."""
     class _M:   # pipeline hook: a fixed reconstruction instead of the autoencoder
         pass
@@ -181,8 +181,11 @@ def oracle_residual(F, fhat, g, p):
             out["margin"][h] = abs(rr[h] - thr[h] ** 2) / max(thr[h] ** 2, 1e-300)
         flag = 0
         if not raw[h]:
-            res = oracle.newton.project(fh[h], b[h], g, p.newton_s, p.newton_max_iter, p.newton_max_iter2, p.fallback)
+            res = oracle.newton.project(fh[h], b[h], g, p.newton_s, p.newton_max_iter, p.newton_max_iter2, p.fallback,
+                                        lam0=None if lam0 is None else lam0[h])
             out["iters"][h] = res["iters"]
+            if res.get("warm_rejected"):
+                flag |= 8
             if res["status"] >= 1:
                 flag |= pipeline.FLAG_ROUND2
             if res["status"] == 2:
@@ -191,7 +194,7 @@ def oracle_residual(F, fhat, g, p):
                 out["lam"][h] = res["lam"]
                 flag |= pipeline.FLAG_CODED if coded[h] else 0
         if raw[h]:
-            flag = (flag & pipeline.FLAG_ROUND2) | pipeline.FLAG_RAW
+            flag = (flag & (pipeline.FLAG_ROUND2 | 8)) | pipeline.FLAG_RAW
             rec = np.ascontiguousarray(F[h]).tobytes()
             out["kstar"][h] = 255
         out["flags"][h] = flag
@@ -202,16 +205,17 @@ def oracle_residual(F, fhat, g, p):
     return out
 
 
-def compare_residual(H, plan, g, F, fhat, p, hp, near_tie=1e-9):
+def compare_residual(H, plan, g, F, fhat, p, hp, near_tie=1e-9, lam0=None):
     Hn = F.shape[0]
-    comp = H.residual(plan, hp, to_dev(F), None if fhat is None else to_dev(fhat))
+    comp = H.residual(plan, hp, to_dev(F), None if fhat is None else to_dev(fhat),
+                      lam0=None if lam0 is None else to_dev(lam0))
     torch.cuda.synchronize()
     flags = comp.flags.cpu().numpy()
     lam = comp.lam.cpu().numpy()
     off = comp.offsets.cpu().numpy().astype(np.uint64)
     stream = comp.stream_bytes()
     st = comp.stats()
-    ref = oracle_residual(F, fhat, g, p)
+    ref = oracle_residual(F, fhat, g, p, lam0=lam0)
     sure = ref["margin"] > near_tie          # decisions that rounding order cannot flip
     assert np.array_equal(flags[sure], ref["flags"][sure])
     assert (~sure).sum() <= max(1, Hn // 1000)
@@ -325,3 +329,28 @@ def test_decompress_reads_oracle_stream(H, ctx, dtype):
     out = cz.decompress(cmp_, 50, in_dtype=torch.float32 if dtype == np.float32 else torch.float64).cpu().numpy()
     both_nan = np.isnan(out) & np.isnan(ref)
     assert np.all(both_nan | np.isclose(out, ref, rtol=1e-13, atol=1e-15 * np.nanmax(np.abs(ref))))
+
+
+@pytest.mark.parametrize("shape", [(39, 39), (49, 49)])
+def test_residual_warm_start(H, ctx, shape):
+    """Warm starts near the solution, garbage and NaN: flags (incl. rejection), records and
+    multipliers match the oracle given the same warm starts."""
+    n = shape[0]
+    say("warm start", shape)
+    g = grid.make_grid(n, n)
+    plan = H.Plan(ctx, n, n)
+    F = synth.histograms(96, n, n, seed=37, dtype=np.float32)
+    fhat = synth.perturbed(F, np.geomspace(1e-4, 3e-2, 96), seed=38)
+    p = pipeline.Params(tau=1e-3)
+    cold = oracle_residual(F, fhat, g, p)
+    rng = np.random.default_rng(39)
+    lam0 = cold["lam"] * (1 + 1e-3 * rng.normal(size=(96, 4)))
+    lam0[::7] = [1e6, 0.0, 0.0, 0.0]          # every cell clipped: no usable step, rejected
+    lam0[3::11] = np.nan
+    comp, ref, _ = compare_residual(H, plan, g, F, fhat, p, H.params(tau=1e-3), lam0=lam0)
+    flags = comp.flags.cpu().numpy()
+    assert (flags[::7] & 8).all() and (flags[3::11] & 8).all()
+    acc = (flags & 8) == 0
+    assert acc.sum() > 50
+    st = comp.stats()
+    assert st["newton_iters_total"] < cold["iters"].sum()

@@ -150,3 +150,82 @@ def test_training_reduces_loss_and_residuals(T):
         assert moments.qoi_rel_error(q0, q1, g).max() < 1e-10
     assert res["trained"][0] <= res["untrained"][0]
     assert res["trained"][1] < 0.9 * res["untrained"][1]
+
+
+def test_mlp_kernels_match_oracle(T):
+    hcz, train = T
+    from oracle import mlp as omlp
+    say("mlp fwd/bwd/predict")
+    P = synth.mlp_weights()
+    rng = np.random.default_rng(13)
+    for k in ("b1", "b2", "b3"):
+        P[k] = rng.normal(0, 0.1, P[k].shape).astype(np.float32)
+    Z = rng.normal(size=(300, 16)).astype(np.float32)
+    Tg = rng.normal(size=(300, 4)).astype(np.float32)
+    p = train.mlp_pack(P).requires_grad_(True)
+    out = train.MlpNet.apply(torch.from_numpy(Z).cuda(), p)
+    loss = train.mse(out, torch.from_numpy(Tg).cuda())
+    loss.backward()
+    P64 = {k: v.astype(np.float64) for k, v in P.items()}
+    cache = omlp.forward(Z.astype(np.float64), P64)
+    assert np.allclose(out.detach().cpu().numpy(), cache["out"], rtol=1e-4, atol=1e-5)
+    g_or = omlp.backward(cache, Tg.astype(np.float64), P64)
+    g = train.mlp_unpack(p.grad)
+    for k in train.MLP_KEYS:
+        assert np.abs(g[k] - g_or[k]).max() <= 2e-4 * (np.abs(g_or[k]).max() + 1e-30), k
+    # inference kernel on codes + codebook, with the output scale
+    ctx = hcz.Context(0)
+    C = synth.sorted_codebook(16, 8, seed=14)
+    codes = synth.codes(500, 16, 8, seed=15)
+    scale = np.array([1e-3, 2e-2, 3.0, 4e-1])
+    net = hcz.Mlp(ctx, train.mlp_pack(P).cpu().numpy(), scale)
+    lam0 = net.predict(torch.from_numpy(codes).cuda(), torch.from_numpy(C).cuda()).cpu().numpy()
+    ref = omlp.predict(oracle.pq.decode(codes, C), P64, scale)
+    assert np.allclose(lam0, ref, rtol=1e-4, atol=1e-5 * np.abs(ref).max(axis=0))
+    zq = hcz.dequantize(torch.from_numpy(codes).cuda(), torch.from_numpy(C).cuda()).cpu().numpy()
+    assert np.array_equal(zq, oracle.pq.decode(codes, C).astype(np.float32))
+
+
+def test_warm_start_network_cuts_newton_iterations(T):
+    """Train the warm-start network on the multipliers of a training batch, then compress
+    held-out data cold and warm: same multipliers and QoIs, fewer Newton updates."""
+    hcz, train = T
+    say("warm-start training")
+    ctx = hcz.Context(0)
+    plan = hcz.Plan(ctx)
+    Ftr = torch.from_numpy(synth.histograms(32768, seed=synth.SEED_TRAIN, dtype=np.float32)).cuda()
+    Fte = torch.from_numpy(synth.histograms(8192, seed=synth.SEED_HELDOUT, dtype=np.float32)).cuda()
+    mu, sd = hcz.norm_stats(plan, Ftr)
+    W = synth.dense_ae_weights()
+    model = hcz.Model(plan, W, mu.cpu().numpy(), sd.cpu().numpy())
+    # targets: cold-start multipliers of the training batch (tau large: most histograms uncoded)
+    p_cold = hcz.params(tau=0.5, fit_codebook=True, sample_every=4)
+    cz = hcz.Compressor(plan, model, 32768, p_cold)
+    c = cz.compress(Ftr)
+    lam = c.lam.clone()
+    codes = c.codes.clone()
+    cent = cz.centroids.clone()
+    ok = (c.flags & 4) == 0
+    scale = lam[ok].std(dim=0).clamp_min(1e-30)
+    Z = hcz.dequantize(codes, cent)[ok]
+    Tt = (lam[ok] / scale).float()
+    params, losses = train.fit_mlp(Z, Tt, synth.mlp_weights(), epochs=20, batch=512)
+    assert losses[-1] < 0.5 * losses[0]
+    net = hcz.Mlp(ctx, params.cpu().numpy(), scale.cpu().numpy())
+    res = {}
+    for name, p in (("cold", hcz.params(tau=0.5)), ("warm", hcz.params(tau=0.5, mlp=net))):
+        cz2 = hcz.Compressor(plan, model, 8192, p)
+        cz2.centroids.copy_(cent)
+        c2 = cz2.compress(Fte)
+        st = c2.stats()
+        out = cz2.decompress(c2, 8192).cpu().numpy()
+        g = grid.make_grid()
+        F = Fte.cpu().numpy().astype(np.float64)
+        assert moments.qoi_rel_error(moments.qoi(F, g), moments.qoi(out, g), g).max() < 1e-10
+        res[name] = (st["newton_iters_total"], c2.lam.cpu().numpy(), c2.flags.cpu().numpy())
+    assert res["warm"][0] < res["cold"][0], (res["warm"][0], res["cold"][0])
+    both = ((res["warm"][2] & 4) == 0) & ((res["cold"][2] & 4) == 0)
+    assert np.allclose(res["warm"][1][both], res["cold"][1][both], rtol=1e-6,
+                       atol=1e-9 * np.abs(res["cold"][1]).max())
+    print(f"[warm-start] Newton updates cold {res['cold'][0]} warm {res['warm'][0]} "
+          f"rejected {int(((res['warm'][2] & 8) != 0).sum())}", flush=True)

@@ -118,3 +118,42 @@ def test_lambda_precision_magnitudes():
         e32.append(moments.qoi_rel_error(q, moments.qoi(newton.apply(ft, lam32, g), g), g).max())
     assert max(e64) < 1e-12
     assert 1e-11 < np.median(e32) < 1e-5
+
+
+def test_warm_start_rules():
+    g, f, ft = positive_case(seed=8, rel=0.02)
+    b = moments.moments(f, g)
+    cold = newton.project(ft, b, g)
+    exact = newton.project(ft, b, g, lam0=cold["lam"])
+    assert exact["iters"] == 0 and not exact["warm_rejected"]
+    near = newton.project(ft, b, g, lam0=cold["lam"] * (1 + 1e-3))
+    assert not near["warm_rejected"] and near["iters"] <= cold["iters"]
+    assert np.allclose(near["x"], cold["x"], rtol=1e-12, atol=1e-14)
+    bad = newton.project(ft, b, g, lam0=np.array([1e6, 0.0, 0.0, 0.0]))   # every cell clipped
+    assert bad["warm_rejected"]
+    assert np.allclose(bad["lam"], cold["lam"]) and bad["iters"] == cold["iters"]
+    nan = newton.project(ft, b, g, lam0=np.array([np.nan, 0, 0, 0]))
+    assert nan["warm_rejected"] and nan["iters"] == cold["iters"]
+
+
+def test_mlp_backward_matches_autograd():
+    import torch
+    from oracle import mlp
+    from paper_2212_10733_amd import synth
+    P = {k: v.astype(np.float64) for k, v in synth.mlp_weights().items()}
+    rng = np.random.default_rng(3)
+    for k in ("b1", "b2", "b3"):
+        P[k] = rng.normal(0, 0.1, P[k].shape)
+    Z = rng.normal(size=(20, 16))
+    T = rng.normal(size=(20, 4))
+    g = mlp.backward(mlp.forward(Z, P), T, P)
+    t = {k: torch.tensor(v, requires_grad=True) for k, v in P.items()}
+    z = torch.tensor(Z)
+    h = torch.relu(z @ t["W1"].T + t["b1"])
+    h = torch.relu(h @ t["W2"].T + t["b2"])
+    out = h @ t["W3"].T + t["b3"]
+    ((out - torch.tensor(T)) ** 2).mean().backward()
+    for k in P:
+        assert np.allclose(g[k], t[k].grad.numpy(), rtol=1e-10, atol=1e-12)
+    assert synth.mlp_weights()["W1"].shape == (64, 16)
+    assert sum(v.size for v in synth.mlp_weights().values()) == 5508
