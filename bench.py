@@ -57,6 +57,88 @@ def cpu_baseline(F: np.ndarray, W: dict, mu, sd, tau: float, n: int) -> dict:
                       f"every 16th, quantize, decode, coder, Newton), NumPy FP64, 1 thread, {dt:.1f} s"}
 
 
+def time_compress(cz, x, steps):
+    import torch
+    cz.compress(x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        comp = cz.compress(x)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps, comp
+
+
+def other_forms(hcz, plan, ctx, x, F, W, args, plain_value, plain_stats) -> dict:
+    """The same batch and tau through (a) the coder-only pipeline and (b) the learned form:
+    the autoencoder trained by the library's kernels on held-apart synthetic histograms,
+    plus the warm-start network trained on the training batch's multipliers."""
+    import torch
+
+    from paper_2212_10733_amd import synth, train
+    H = x.shape[0]
+    out = {}
+    log("form: coder-only")
+    cz = hcz.Compressor(plan, None, H, hcz.params(tau=args.tau))
+    dt, comp = time_compress(cz, x, 3)
+    s = comp.stats()
+    out["coder_only"] = {"value": H / dt, "ms_per_step": dt * 1e3, "coded_frac": s["n_coded"] / H,
+                         "stream_bytes": s["stream_bytes"], "newton_mean_updates": s["newton_iters_total"] / H}
+    del cz, comp
+    log(f"form: learned (train {args.epochs} epochs on {args.train_hist})")
+    Ftr = torch.from_numpy(synth.histograms(args.train_hist, seed=synth.SEED_TRAIN, dtype=np.float32)).cuda()
+    mu, sd = hcz.norm_stats(plan, Ftr)
+    X = ((Ftr.reshape(args.train_hist, -1) - mu) / sd).contiguous()
+    t0 = time.perf_counter()
+    tr = train.Trainer(train.pack(W), lr=1e-3)
+    losses = tr.fit(X, epochs=args.epochs, batch=1024)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    del X
+    Wt = train.unpack(tr.p, plan.N)
+    model = hcz.Model(plan, Wt, mu.cpu().numpy(), sd.cpu().numpy())
+    # warm-start network: targets are the training batch's cold multipliers
+    czt = hcz.Compressor(plan, model, args.train_hist, hcz.params(tau=args.tau, fit_codebook=True, sample_every=16))
+    ct = czt.compress(Ftr)
+    ok = (ct.flags & 4) == 0
+    scale = ct.lam[ok].std(dim=0).clamp_min(1e-30)
+    Z = hcz.dequantize(ct.codes, czt.centroids)[ok]
+    T = (ct.lam[ok] / scale).float()
+    t0 = time.perf_counter()
+    pm, mlosses = train.fit_mlp(Z, T, synth.mlp_weights(), epochs=10, batch=1024)
+    torch.cuda.synchronize()
+    t_mlp = time.perf_counter() - t0
+    net = hcz.Mlp(ctx, pm.cpu().numpy(), scale.cpu().numpy())
+    del czt, ct, Ftr, Z, T
+    res = {}
+    for name, p in (("cold", hcz.params(tau=args.tau, fit_codebook=True, sample_every=16)),
+                    ("warm", hcz.params(tau=args.tau, fit_codebook=True, sample_every=16, mlp=net))):
+        cz = hcz.Compressor(plan, model, H, p)
+        dt, comp = time_compress(cz, x, 3)
+        s = comp.stats()
+        res[name] = {"value": H / dt, "ms_per_step": dt * 1e3, "coded_frac": s["n_coded"] / H,
+                     "stream_bytes": s["stream_bytes"], "newton_mean_updates": s["newton_iters_total"] / H,
+                     "newton_max_updates": s["newton_max_iters"], "raw": s["n_raw"],
+                     "warm_rejected": int(((comp.flags & 8) != 0).sum().item())}
+        if name == "warm":
+            o = cz.decompress(comp, H)
+            _, q0, n0 = hcz.qoi(plan, x)
+            _, q1, _ = hcz.qoi(plan, o)
+            okk = (comp.flags & 4) == 0
+            den = torch.stack([q0[:, 0].abs(), torch.maximum(q0[:, 1].abs(), q0[:, 3].abs().sqrt()),
+                               q0[:, 2].abs(), q0[:, 3].abs()], 1)
+            res[name]["max_qoi_rel_err"] = ((q1 - q0).abs() / den)[okk].max().item()
+            res[name]["max_err_over_tau_h"] = ((o - x.double()).reshape(H, -1).norm(dim=1)[okk]
+                                               / (args.tau * n0[okk])).max().item()
+            del o
+        del cz, comp
+    out["learned"] = {"train_seconds": t_train, "train_loss_first_last": [losses[0], losses[-1]],
+                      "mlp_train_seconds": t_mlp, "mlp_loss_first_last": [mlosses[0], mlosses[-1]],
+                      "cold_start": res["cold"], "warm_start": res["warm"],
+                      "untrained_plain": {"value": plain_value, "coded_frac": plain_stats["n_coded"] / H,
+                                          "stream_bytes": plain_stats["stream_bytes"]}}
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -64,8 +146,11 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--H", type=int, default=1 << 20)
     ap.add_argument("--tau", type=float, default=1e-3)
-    ap.add_argument("--cpu-sample", type=int, default=768)
+    ap.add_argument("--cpu-sample", type=int, default=8192)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-forms", action="store_true", help="skip the coder-only and learned forms")
+    ap.add_argument("--train-hist", type=int, default=262144)
+    ap.add_argument("--epochs", type=int, default=20)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on exactly one GPU: the per-histogram path needs no communication, "
@@ -163,6 +248,10 @@ def main() -> int:
     extra["max_err_over_tau_h"] = bound_ratio
     del out
 
+    forms = {}
+    if not args.no_forms:
+        forms = other_forms(hcz, plan, ctx, x, F, W, args, value, st)
+
     cpu = None
     if not args.no_cpu:
         log(f"cpu baseline on {args.cpu_sample} histograms")
@@ -177,7 +266,7 @@ def main() -> int:
                                "1521-128-16 (Xavier), 8-bit PQ fitted per batch, tau=1e-3 rel-L2, FP64 coder + Newton",
                    "H": H, "grid": "39x39", "tau": args.tau, "tau_mode": "rel_l2", "pq_bits": 8,
                    "sample_every": 16},
-        "roofline": roofline, "cpu_baseline": cpu, **extra,
+        "roofline": roofline, "cpu_baseline": cpu, **extra, "forms": forms,
     }
     print(json.dumps(line), flush=True)
     return 0

@@ -13,7 +13,9 @@ Compress, per histogram (FP64):
 Decompress: fhat from the codes, rhat from the record, ft = fhat + rhat,
 f_c = max(0, ft - A^T lam); verbatim records are returned as stored.
 
-Flags: bit0 coder record, bit1 round-2 Newton used, bit2 verbatim record.
+Flags: bit0 coder record, bit1 round-2 Newton used, bit2 verbatim record, bit3 warm
+start rejected.  An optional warm-start network (oracle.mlp) seeds the Newton solve from
+the dequantised latent; the projection keeps cold start as fallback and judge.
 """
 from __future__ import annotations
 
@@ -22,11 +24,11 @@ from dataclasses import dataclass
 
 import numpy as np
 
-from . import ae, coder, newton, pq
+from . import ae, coder, mlp as mlp_net, newton, pq
 from .grid import Grid
 from .moments import moments
 
-FLAG_CODED, FLAG_ROUND2, FLAG_RAW = 1, 2, 4
+FLAG_CODED, FLAG_ROUND2, FLAG_RAW, FLAG_WARM_REJECTED = 1, 2, 4, 8
 
 
 @dataclass
@@ -54,7 +56,9 @@ def reconstruct_ae(codes: np.ndarray, C: np.ndarray, model: dict, shape) -> np.n
 
 
 def compress(F: np.ndarray, g: Grid, model: dict | None, C: np.ndarray | None, p: Params,
-             fit_codebook: bool = False, bits: int = 8, sample_every: int = 16) -> dict:
+             fit_codebook: bool = False, bits: int = 8, sample_every: int = 16,
+             warm: tuple | None = None) -> dict:
+    """warm: optional (network parameters, scale) of the warm-start network (needs a model)."""
     H = F.shape[0]
     F64 = np.asarray(F, np.float64).reshape(H, g.n_perp, g.n_par)
     lay = coder.layout(g.n_par, g.n_perp)
@@ -97,12 +101,17 @@ def compress(F: np.ndarray, g: Grid, model: dict | None, C: np.ndarray | None, p
     flags = np.zeros(H, np.uint8)
     iters = np.zeros(H, np.int64)
     fc = np.zeros_like(F64)
+    lam0 = None
+    if warm is not None and model is not None:
+        lam0 = mlp_net.predict(pq.decode(codes, C), warm[0], warm[1])
     for h in range(H):
         if raw[h]:
             continue
         res = newton.project(ft[h], b[h], g, p.newton_s, p.newton_max_iter, p.newton_max_iter2,
-                             p.fallback)
+                             p.fallback, lam0=None if lam0 is None else lam0[h])
         iters[h] = res["iters"]
+        if res.get("warm_rejected"):
+            flags[h] |= FLAG_WARM_REJECTED
         if res["status"] >= 1:
             flags[h] |= FLAG_ROUND2
         if res["status"] == 2:
@@ -113,7 +122,7 @@ def compress(F: np.ndarray, g: Grid, model: dict | None, C: np.ndarray | None, p
     records = []
     for h in range(H):
         if raw[h]:
-            flags[h] = (flags[h] & FLAG_ROUND2) | FLAG_RAW
+            flags[h] = (flags[h] & (FLAG_ROUND2 | FLAG_WARM_REJECTED)) | FLAG_RAW
             records.append(np.ascontiguousarray(np.asarray(F)[h]).tobytes())
             fc[h] = F64[h]
             lam[h] = 0.0

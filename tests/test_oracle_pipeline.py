@@ -98,3 +98,18 @@ def test_record_layout_in_stream():
         q, Delta, k = coder.unpack(rec, lay)
         assert k == comp["kstar"][h]
         assert Delta == coder.ladder(coder.delta0(comp["tau_h"][h:h + 1], lay), np.array([k]))[0]
+
+
+def test_warm_start_network_keeps_the_solution():
+    from oracle import mlp
+    g = grid.make_grid()
+    F = synth.histograms(10, seed=8, dtype=np.float64)
+    model = make_model(F)
+    cold = pipeline.compress(F, g, model, None, pipeline.Params(tau=0.5), fit_codebook=True,
+                             sample_every=1, bits=3)
+    P = synth.mlp_weights()
+    warm = pipeline.compress(F, g, model, None, pipeline.Params(tau=0.5), fit_codebook=True,
+                             sample_every=1, bits=3, warm=(P, np.abs(cold["lam"]).max(axis=0)))
+    ok = (cold["flags"] & pipeline.FLAG_RAW) == 0
+    assert np.allclose(warm["fc"][ok], cold["fc"][ok], rtol=1e-10, atol=1e-13)
+    assert warm["stream"] == cold["stream"]
