@@ -104,7 +104,7 @@ def other_forms(hcz, plan, ctx, x, F, W, args, plain_value, plain_stats) -> dict
     Z = hcz.dequantize(ct.codes, czt.centroids)[ok]
     T = (ct.lam[ok] / scale).float()
     t0 = time.perf_counter()
-    pm, mlosses = train.fit_mlp(Z, T, synth.mlp_weights(), epochs=10, batch=1024)
+    pm, mlosses = train.fit_mlp(Z, T, synth.mlp_weights(), epochs=10, batch=512, lr=3e-3)
     torch.cuda.synchronize()
     t_mlp = time.perf_counter() - t0
     net = hcz.Mlp(ctx, pm.cpu().numpy(), scale.cpu().numpy())

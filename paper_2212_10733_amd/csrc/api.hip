@@ -285,6 +285,42 @@ SlotTables make_slots(int np, int nq, int L, const std::vector<uint32_t>& node, 
   return T;
 }
 
+// Every index the wave kernels take from the slot tables must stay inside its buffer: the
+// natural offset below N and each node once, corners inside the grid and strictly coarser
+// than the node, weight indices inside wtab, packing positions inside the node's group.
+bool slots_valid(const SlotTables& T, int np, int nq, int N, int nlev, const std::vector<uint32_t>& node,
+                 const std::vector<int>& gstart) {
+  if (T.nslots == 0) return true;
+  if (T.meta.size() != (size_t)T.nslots * 128 || T.pos.size() != (size_t)T.nslots * 64) return false;
+  std::vector<int> grp(N, -1);
+  for (int g = 0; g < nlev; ++g)
+    for (int p = gstart[g]; p < gstart[g + 1]; ++p) grp[(node[p] >> 16) * np + (node[p] & 0xffff)] = g;
+  std::vector<uint8_t> seen(N, 0);
+  for (int s = 0; s < T.nslots; ++s)
+    for (int l = 0; l < 64; ++l) {
+      const uint32_t w0 = T.meta[(size_t)(s * 64 + l) * 2], w1 = T.meta[(size_t)(s * 64 + l) * 2 + 1];
+      if (!((w0 >> 18) & 1u)) {
+        if (w0 || w1) return false;
+        continue;
+      }
+      const int e = (int)(w0 & 0x1fff), g = (int)((w0 >> 13) & 0xf);
+      if (e >= N || seen[e] || g >= nlev || grp[e] != g) return false;
+      if (s == 0 ? g >= T.ncoarse : g != T.group[s]) return false;
+      seen[e] = 1;
+      const int p = T.pos[(size_t)s * 64 + l];
+      if (p < gstart[g] || p >= gstart[g + 1] || (int)((node[p] >> 16) * np + (node[p] & 0xffff)) != e) return false;
+      if (g == 0) continue;
+      const int a = w1 & 0x7f, b = (w1 >> 7) & 0x7f, aj = (w1 >> 14) & 0x7f, bj = (w1 >> 21) & 0x7f;
+      const size_t wi = (w0 >> 19) & 0x3f, ti = (w0 >> 25) & 0x3f;
+      if (a >= np || b >= np || aj >= nq || bj >= nq || wi >= T.wtab.size() || ti >= T.wtab.size()) return false;
+      for (int c : {aj * np + a, aj * np + b, bj * np + a, bj * np + b})
+        if (grp[c] >= g) return false;
+    }
+  for (int e = 0; e < N; ++e)
+    if (!seen[e]) return false;
+  return true;
+}
+
 hcz_status check_hist(const void* hist, int32_t dtype, int64_t H, int64_t hs, int64_t rs,
                       const GridDev& G) {
   if (H < 0) return fail(HCZ_EINVAL, "H = %lld < 0", (long long)H);
@@ -424,6 +460,8 @@ hcz_status hcz_plan_create(hcz_ctx* ctx, const hcz_grid* g, hcz_plan** out) {
   if ((int)node.size() != N) return fail(HCZ_EINVAL, "internal: node layout has %zu of %d nodes", node.size(), N);
   DimTables dp = dim_tables(np, L), dq = dim_tables(nq, L);
   SlotTables slots = make_slots(np, nq, L, node, gstart, dp, dq);
+  if (!slots_valid(slots, np, nq, N, nlev, node, gstart))
+    return fail(HCZ_EINVAL, "internal: slot tables for %dx%d failed their check", np, nq);
   hcz_plan* P = new hcz_plan();
   P->ctx = ctx;
   GridDev& G = P->G;

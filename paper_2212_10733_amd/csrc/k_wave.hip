@@ -429,7 +429,12 @@ __device__ __forceinline__ int newton_w(const GridDev& G, const double* ft, cons
   return 2;
 }
 
-__host__ __device__ __forceinline__ size_t wave_lds_doubles(int N) { return (size_t)N + (size_t)(N + 1) / 2; }
+// Dynamic LDS of the wave kernels, in doubles: s_a [kMaxDim], s_c [kMaxDim], s_w [64],
+// then (compression only) the node metadata, nslots * 64 entries of two words = one
+// double each, then one N-double buffer per wave.  Kernels and launchers both take the
+// offsets from here.
+constexpr int kLdsTables = 2 * kMaxDim + 64;
+__host__ __device__ __forceinline__ size_t lds_meta_doubles(int nslots) { return (size_t)nslots * 64; }
 
 // Per-grid scalars that are indexed at run time go to LDS (indexing them inside the
 // by-value kernel argument would force a private copy of the whole argument).
@@ -453,10 +458,10 @@ __global__ __launch_bounds__(256, 2) void k_residual_w(GridDev G, ResidualArgs a
   double* s_a = smem;                    // [128]
   double* s_c = smem + kMaxDim;          // [128]
   double* s_w = smem + 2 * kMaxDim;      // [64]
-  uint2* meta = (uint2*)(smem + 2 * kMaxDim + 64);                 // [nslots * 64]
+  uint2* meta = (uint2*)(smem + kLdsTables);                       // [nslots * 64]
   const int N = G.N;
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  double* y = smem + 2 * kMaxDim + 64 + (size_t)G.nslots * 32 + (size_t)N * wv;
+  double* y = smem + kLdsTables + lds_meta_doubles(G.nslots) + (size_t)N * wv;
   uint32_t* words = (uint32_t*)y;        // payload words reuse the buffer once ft is read
   for (int k = threadIdx.x; k < G.n_par; k += 256) s_a[k] = G.apar[k];
   for (int k = threadIdx.x; k < G.n_perp; k += 256) s_c[k] = G.cperp[k];
@@ -734,7 +739,7 @@ __global__ __launch_bounds__(256, 2) void k_decompress_w(GridDev G, DecompressAr
   double* s_w = smem + 2 * kMaxDim;
   const int N = G.N;
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  double* y = smem + 2 * kMaxDim + 64 + (size_t)N * wv;
+  double* y = smem + kLdsTables + (size_t)N * wv;
   for (int k = threadIdx.x; k < G.n_par; k += 256) s_a[k] = G.apar[k];
   for (int k = threadIdx.x; k < G.n_perp; k += 256) s_c[k] = G.cperp[k];
   for (int k = threadIdx.x; k < G.nw; k += 256) s_w[k] = G.wtab[k];
@@ -847,8 +852,8 @@ __global__ __launch_bounds__(256, 2) void k_decompress_w(GridDev G, DecompressAr
 // ---- launchers ----------------------------------------------------------------------------
 
 static size_t lds_bytes(const GridDev& G, bool with_meta) {
-  const size_t meta = with_meta ? (size_t)G.nslots * 32 : 0;   // nslots * 64 uint2 = doubles
-  return (2 * kMaxDim + 64 + meta + (size_t)G.N * kWPB) * sizeof(double);
+  const size_t meta = with_meta ? lds_meta_doubles(G.nslots) : 0;
+  return (kLdsTables + meta + (size_t)G.N * kWPB) * sizeof(double);
 }
 
 bool wave_path(const GridDev& G) { return G.nslots > 0 && G.nslots <= kWaveSlots; }
