@@ -190,27 +190,35 @@ DimTables dim_tables(int n, int L) {
 
 bool in_set(int n, int l, int i) { return i == n - 1 || (i % (1 << l)) == 0; }
 
-// Slot layout of the wave-per-histogram kernels.  Entry words:
-//   w0 = e | group << 13 | bilinear << 17 | valid << 18 | widx << 19 | tidx << 25
-//   w1 = a | b << 7 | aj << 14 | bj << 21
-// e: natural offset j * n_par + i.  Interpolation corners: (aj, a), (aj, b) and, for a
-// bilinear node, (bj, a), (bj, b); a node on a coarse row has aj = bj = j and weight
-// wtab[widx] = s, on a coarse column a = b = i and weight t, so p0 = y[aj, a] +
-// w (y[bj, b] - y[aj, a]) covers both linear cases.  The packing position of each entry
-// is kept apart (slot_pos).
+// Slot layout of the wave-per-histogram kernels.  An entry is three words; offsets are
+// bytes into a wave's FP64 buffer, which holds the histogram in natural order
+// (e = j * n_par + i) followed by one zero cell at N:
+//   w0 = off(e) | off(c00) << 16
+//   w1 = off(c10) | off(c01) << 16
+//   w2 = off(c11) | widx << 16 | tidx << 22 | group << 28
+// A linear slot predicts y(c00) + s (y(c10) - y(c00)) with s = wtab[widx], the two
+// corners lying on the node's coarse row or column.  A four-corner slot interpolates the
+// rows (c00, c10) and (c01, c11) with s, then between the two with t = wtab[tidx]; its
+// linear nodes take a degenerate form with the same bits as the linear one (a row node
+// repeats its two corners with t = 0, a column node doubles each of its two corners with
+// s = 0).  Padding lanes point every offset at the zero cell, with wtab[0] = 0 and
+// group 15.  The packing position of each entry is kept apart (slot_pos).
 struct SlotTables {
   int nslots = 0, ncoarse = 0;
   std::vector<uint32_t> meta;
   std::vector<uint16_t> pos;
   std::vector<double> wtab;
   std::vector<int8_t> group;
-  std::vector<uint8_t> sync;
+  uint32_t bil = 0, sync = 0, keep = 0;
 };
+
+constexpr uint32_t kPadGroup = 15;
 
 SlotTables make_slots(int np, int nq, int L, const std::vector<uint32_t>& node, const std::vector<int>& gstart,
                       const DimTables& dp, const DimTables& dq) {
   SlotTables T;
   const int nlev = L + 1;
+  const uint32_t zero = (uint32_t)(np * nq) * 8u;
   T.wtab.push_back(0.0);
   auto widx = [&](double w) {
     for (size_t k = 0; k < T.wtab.size(); ++k)
@@ -218,103 +226,135 @@ SlotTables make_slots(int np, int nq, int L, const std::vector<uint32_t>& node, 
     T.wtab.push_back(w);
     return (uint32_t)(T.wtab.size() - 1);
   };
-  auto entry = [&](int p, int g, uint32_t* out) {
+  auto off = [&](int i, int j) { return (uint32_t)(j * np + i) * 8u; };
+  auto pad = [&](uint32_t* w) {
+    w[0] = zero | zero << 16;
+    w[1] = zero | zero << 16;
+    w[2] = zero | kPadGroup << 28;
+  };
+  // kind of the node at packing position p in group g: 0 coarsest, 1 row, 2 column, 3 bilinear
+  auto kind = [&](int p, int g) {
+    if (g == 0) return 0;
     const int i = node[p] & 0xffff, j = node[p] >> 16;
-    const uint32_t e = (uint32_t)(j * np + i);
-    uint32_t w0 = e | ((uint32_t)g << 13) | (1u << 18), w1 = 0;
-    if (g > 0) {
-      const int l = L - g + 1;                   // group g holds G_{l-1}^2 minus G_l^2
-      const bool i_in = in_set(np, l, i), j_in = in_set(nq, l, j);
-      uint32_t a = i, b = i, aj = j, bj = j, wi = 0, ti = 0;
-      if (j_in) {                                 // along v_par on row j
-        a = dp.a[i]; b = dp.b[i]; wi = widx(dp.s[i]);
-      } else if (i_in) {                          // along v_perp on column i
-        aj = dq.a[j]; bj = dq.b[j]; wi = widx(dq.s[j]);
-      } else {
-        a = dp.a[i]; b = dp.b[i]; aj = dq.a[j]; bj = dq.b[j];
+    const int l = L - g + 1;                       // group g holds G_{l-1}^2 minus G_l^2
+    if (in_set(nq, l, j)) return 1;
+    if (in_set(np, l, i)) return 2;
+    return 3;
+  };
+  auto entry = [&](int p, int g, bool four, uint32_t* w) {
+    const int i = node[p] & 0xffff, j = node[p] >> 16;
+    uint32_t c00 = zero, c10 = zero, c01 = zero, c11 = zero, wi = 0, ti = 0;
+    switch (kind(p, g)) {
+      case 1:                                      // along v_par on row j
+        c00 = off(dp.a[i], j); c10 = off(dp.b[i], j); wi = widx(dp.s[i]);
+        if (four) { c01 = c00; c11 = c10; }
+        break;
+      case 2:                                      // along v_perp on column i
+        if (four) {
+          c00 = c10 = off(i, dq.a[j]); c01 = c11 = off(i, dq.b[j]); ti = widx(dq.s[j]);
+        } else {
+          c00 = off(i, dq.a[j]); c10 = off(i, dq.b[j]); wi = widx(dq.s[j]);
+        }
+        break;
+      case 3:
+        c00 = off(dp.a[i], dq.a[j]); c10 = off(dp.b[i], dq.a[j]);
+        c01 = off(dp.a[i], dq.b[j]); c11 = off(dp.b[i], dq.b[j]);
         wi = widx(dp.s[i]); ti = widx(dq.s[j]);
-        w0 |= 1u << 17;
-      }
-      w0 |= (wi << 19) | (ti << 25);
-      w1 = a | (b << 7) | (aj << 14) | (bj << 21);
+        break;
+      default:
+        break;
     }
-    out[0] = w0;
-    out[1] = w1;
+    w[0] = off(i, j) | c00 << 16;
+    w[1] = c10 | c01 << 16;
+    w[2] = c11 | wi << 16 | ti << 22 | (uint32_t)g << 28;
   };
   // slot 0: the coarsest groups while they fit in 64 lanes
   int g = 0, cnt = 0;
   while (g < nlev && cnt + (gstart[g + 1] - gstart[g]) <= 64) { cnt += gstart[g + 1] - gstart[g]; ++g; }
   if (g == 0) return T;                           // coarsest group alone exceeds a slot
   T.ncoarse = g;
-  std::vector<uint32_t> slot(64 * 2, 0);
-  std::vector<uint16_t> spos(64, 0);
+  std::vector<uint32_t> slot(64 * 3);
+  std::vector<uint16_t> spos(64);
+  for (int l = 0; l < 64; ++l) pad(&slot[3 * l]);
+  std::fill(spos.begin(), spos.end(), (uint16_t)0);
   for (int p = 0; p < cnt; ++p) {
     int gg = 0;
     while (p >= gstart[gg + 1]) ++gg;
-    entry(p, gg, &slot[2 * p]);
+    entry(p, gg, true, &slot[3 * p]);
     spos[p] = (uint16_t)p;
   }
   T.meta.insert(T.meta.end(), slot.begin(), slot.end());
   T.pos.insert(T.pos.end(), spos.begin(), spos.end());
   T.group.push_back(-1);
+  std::vector<bool> four;
+  four.push_back(true);
   for (; g < nlev; ++g) {
     std::vector<int> lin, bil;
-    for (int p = gstart[g]; p < gstart[g + 1]; ++p) {
-      uint32_t w[2];
-      entry(p, g, w);
-      ((w[0] >> 17) & 1 ? bil : lin).push_back(p);
-    }
+    for (int p = gstart[g]; p < gstart[g + 1]; ++p) (kind(p, g) == 3 ? bil : lin).push_back(p);
+    const size_t nlin = lin.size();
     lin.insert(lin.end(), bil.begin(), bil.end());
     for (size_t k = 0; k < lin.size(); k += 64) {
-      std::fill(slot.begin(), slot.end(), 0u);
+      const size_t kend = std::min(lin.size(), k + 64);
+      const bool f4 = kend > nlin;                // the slot holds a bilinear node
+      for (int l = 0; l < 64; ++l) pad(&slot[3 * l]);
       std::fill(spos.begin(), spos.end(), (uint16_t)0);
-      for (size_t q = k; q < std::min(lin.size(), k + 64); ++q) {
-        entry(lin[q], g, &slot[2 * (q - k)]);
+      for (size_t q = k; q < kend; ++q) {
+        entry(lin[q], g, f4, &slot[3 * (q - k)]);
         spos[q - k] = (uint16_t)lin[q];
       }
       T.meta.insert(T.meta.end(), slot.begin(), slot.end());
       T.pos.insert(T.pos.end(), spos.begin(), spos.end());
       T.group.push_back((int8_t)g);
+      four.push_back(f4);
     }
   }
   T.nslots = (int)T.group.size();
-  T.sync.resize(T.nslots);
-  for (int k = 0; k < T.nslots; ++k)
-    T.sync[k] = (k == 0 || k + 1 == T.nslots || T.group[k + 1] != T.group[k]) ? 1 : 0;
-  if (T.nslots > kWaveSlots || T.wtab.size() > 64) T.nslots = 0;
+  if (T.nslots > kWaveSlots || T.wtab.size() > 64 || np * nq * 8 + 8 > 65535) {
+    T.nslots = 0;
+    return T;
+  }
+  for (int k = 0; k < T.nslots; ++k) {
+    if (four[k]) T.bil |= 1u << k;
+    if (k == 0 || k + 1 == T.nslots || T.group[k + 1] != T.group[k]) T.sync |= 1u << k;
+    if (k == 0 || T.group[k] < nlev - 1) T.keep |= 1u << k;
+  }
   return T;
 }
 
-// Every index the wave kernels take from the slot tables must stay inside its buffer: the
-// natural offset below N and each node once, corners inside the grid and strictly coarser
-// than the node, weight indices inside wtab, packing positions inside the node's group.
+// Every offset the wave kernels take from the slot tables must stay inside the wave's
+// buffer: the node's own cell below N and each node once, corners inside the grid (or
+// the zero cell) and in strictly coarser groups, weight indices inside wtab, packing
+// positions inside the node's group.
 bool slots_valid(const SlotTables& T, int np, int nq, int N, int nlev, const std::vector<uint32_t>& node,
                  const std::vector<int>& gstart) {
   if (T.nslots == 0) return true;
-  if (T.meta.size() != (size_t)T.nslots * 128 || T.pos.size() != (size_t)T.nslots * 64) return false;
-  std::vector<int> grp(N, -1);
+  if (T.meta.size() != (size_t)T.nslots * 192 || T.pos.size() != (size_t)T.nslots * 64) return false;
+  const uint32_t zero = (uint32_t)N * 8u;
+  std::vector<int> grp(N + 1, -1);
   for (int g = 0; g < nlev; ++g)
     for (int p = gstart[g]; p < gstart[g + 1]; ++p) grp[(node[p] >> 16) * np + (node[p] & 0xffff)] = g;
   std::vector<uint8_t> seen(N, 0);
   for (int s = 0; s < T.nslots; ++s)
     for (int l = 0; l < 64; ++l) {
-      const uint32_t w0 = T.meta[(size_t)(s * 64 + l) * 2], w1 = T.meta[(size_t)(s * 64 + l) * 2 + 1];
-      if (!((w0 >> 18) & 1u)) {
-        if (w0 || w1) return false;
+      const uint32_t* w = &T.meta[(size_t)(s * 64 + l) * 3];
+      const uint32_t oe = w[0] & 0xffff, o[4] = {w[0] >> 16, w[1] & 0xffff, w[1] >> 16, w[2] & 0xffff};
+      const uint32_t wi = (w[2] >> 16) & 63, ti = (w[2] >> 22) & 63, g = w[2] >> 28;
+      for (uint32_t v : {oe, o[0], o[1], o[2], o[3]})
+        if (v % 8 || v > zero) return false;
+      if (wi >= T.wtab.size() || ti >= T.wtab.size()) return false;
+      if (oe == zero) {                            // padding lane
+        if (g != kPadGroup || o[0] != zero || o[1] != zero || o[2] != zero || o[3] != zero) return false;
         continue;
       }
-      const int e = (int)(w0 & 0x1fff), g = (int)((w0 >> 13) & 0xf);
-      if (e >= N || seen[e] || g >= nlev || grp[e] != g) return false;
-      if (s == 0 ? g >= T.ncoarse : g != T.group[s]) return false;
+      const int e = (int)(oe / 8);
+      if (seen[e] || (int)g >= nlev || grp[e] != (int)g) return false;
+      if (s == 0 ? (int)g >= T.ncoarse : (int)g != T.group[s]) return false;
       seen[e] = 1;
       const int p = T.pos[(size_t)s * 64 + l];
       if (p < gstart[g] || p >= gstart[g + 1] || (int)((node[p] >> 16) * np + (node[p] & 0xffff)) != e) return false;
-      if (g == 0) continue;
-      const int a = w1 & 0x7f, b = (w1 >> 7) & 0x7f, aj = (w1 >> 14) & 0x7f, bj = (w1 >> 21) & 0x7f;
-      const size_t wi = (w0 >> 19) & 0x3f, ti = (w0 >> 25) & 0x3f;
-      if (a >= np || b >= np || aj >= nq || bj >= nq || wi >= T.wtab.size() || ti >= T.wtab.size()) return false;
-      for (int c : {aj * np + a, aj * np + b, bj * np + a, bj * np + b})
-        if (grp[c] >= g) return false;
+      for (uint32_t v : o)
+        if (v != zero && grp[v / 8] >= (int)g) return false;
+      if (g == 0 && (o[0] != zero || o[1] != zero || o[2] != zero || o[3] != zero)) return false;
     }
   for (int e = 0; e < N; ++e)
     if (!seen[e]) return false;
@@ -482,10 +522,10 @@ hcz_status hcz_plan_create(hcz_ctx* ctx, const hcz_grid* g, hcz_plan** out) {
   G.nslots = slots.nslots;
   G.ncoarse = slots.ncoarse;
   G.nw = (int)slots.wtab.size();
-  for (int k = 0; k < kWaveSlots; ++k) {
-    G.slot_group[k] = k < slots.nslots ? slots.group[k] : 0;
-    G.slot_sync[k] = k < slots.nslots ? slots.sync[k] : 0;
-  }
+  for (int k = 0; k < kWaveSlots; ++k) G.slot_group[k] = k < slots.nslots ? slots.group[k] : 0;
+  G.slot_bil = slots.bil;
+  G.slot_sync = slots.sync;
+  G.slot_keep = slots.keep;
   if ((s = upload(P->allocs, vol, &G.vol)) || (s = upload(P->allocs, apar, &G.apar)) ||
       (s = upload(P->allocs, cperp, &G.cperp)) || (s = upload(P->allocs, node, &G.node_ij)) ||
       (s = upload(P->allocs, dp.lev, &G.lev_par)) || (s = upload(P->allocs, dp.a, &G.a_par)) ||

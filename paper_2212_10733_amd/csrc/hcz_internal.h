@@ -53,8 +53,10 @@ struct GridDev {
   // come before bilinear ones.  nslots = 0: grid too large for the wave kernels.
   int nslots, ncoarse, nw;
   int8_t slot_group[kWaveSlots];     // -1 for the multi-group slot 0
-  uint8_t slot_sync[kWaveSlots];     // 1 if the next slot belongs to a later group
-  const uint32_t* slot_meta;         // [nslots * 64][2], see make_slots()
+  uint32_t slot_bil;                 // bit s: slot s uses the four-corner form
+  uint32_t slot_sync;                // bit s: the next slot belongs to a later group
+  uint32_t slot_keep;                // bit s: later groups read slot s (not the finest group)
+  const uint32_t* slot_meta;         // [nslots * 64][3], see make_slots()
   const uint16_t* slot_pos;          // [nslots * 64] packing position of each entry
   const double* wtab;                // [nw] distinct interpolation weights, wtab[0] = 0
 };
@@ -106,6 +108,12 @@ struct DecompressArgs {
   int out_dtype;
   uint64_t capacity;           // bytes of `stream`; records ending past it decode to NaN
 };
+
+// Quantised coefficient Dk * q, q = rint(d / Dk) taken as an integer: rint of a small
+// negative value is -0, which the integer turns into +0.
+__device__ __forceinline__ double qdelta(double Dk, double d, double inv) {
+  return __dmul_rn(Dk, __dadd_rn(rint(__dmul_rn(d, inv)), 0.0));
+}
 
 // ---- double-double accumulation (exact TwoSum error terms) --------------------------
 struct dd { double hi, lo; };

@@ -36,7 +36,7 @@ __device__ double recompose_err(const GridDev& G, double* buf, double* red, cons
 #pragma unroll
     for (int m = 0; m < NPT; ++m) {
       if (gm[m] == g) {
-        const double dq = __dmul_rn(Dk, rint(__dmul_rn(dm[m], inv)));
+        const double dq = qdelta(Dk, dm[m], inv);
         const double y = (g == 0) ? dq : __dadd_rn(dq, predict(buf, cm[m]));
         buf[em[m]] = y;
         y_out[m] = y;

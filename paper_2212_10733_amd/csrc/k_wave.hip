@@ -1,15 +1,20 @@
 // Wave-per-histogram residual coding, Newton projection and decompression (Section III
 // Stages 4-5 and decompression), for grids whose nodes fit in kWaveSlots slots of 64.
 //
-// Each 64-lane wave owns one histogram; a workgroup of four waves shares only the small
-// per-grid tables in LDS, so after the first barrier no block-wide synchronisation is
-// needed.  Lane l holds, per slot, one node of the multilevel decomposition (residual r
-// and coefficient d in registers, interpolation cell in packed form).  A per-wave FP64
-// buffer in LDS carries the values the recomposition reads from coarser groups; since a
-// wave's LDS operations complete in order, a compiler fence between groups is all the
-// ordering needed.  Reductions are DPP butterflies within the wave with the result taken
-// from lane 63, so every lane sees the same bits and runs repeat bitwise.
-// The Newton projection runs in natural element order (lane l, elements l + 64 m).
+// One 64-lane wave owns one histogram; a workgroup of four waves shares the per-grid
+// tables in LDS, so after the first barrier no block-wide synchronisation is needed.
+// Each wave keeps its histogram in an FP64 LDS buffer in natural order
+// (e = j * n_par + i) followed by one zero cell.  Two lane layouts use it:
+//  - node slots (decomposition, recomposition, packing): per slot, lane l holds one
+//    node of the multilevel decomposition, its residual and coefficient in registers
+//    and its interpolation corners as byte offsets into the buffer; padding lanes read
+//    and write the zero cell, so no lane ever branches on its own node;
+//  - columns (loading, moments, Newton, output): lane l walks grid column i = l (and
+//    l + 64) down the rows, so a_i stays in a register, c_j is one broadcast read per
+//    row, and the sums over a column are combined with powers of a_i only once.
+// A wave's LDS operations complete in order, so a compiler fence between coefficient
+// groups is all the ordering needed.  Reductions are DPP butterflies with the result
+// read from lane 63, so every lane sees the same bits and runs repeat bitwise.
 #include "hcz_internal.h"
 
 namespace hcz {
@@ -97,171 +102,207 @@ __device__ __forceinline__ dd wdd(dd v) {
   return dd{lane63(v.hi), lane63(v.lo)};
 }
 
-// ---- node arithmetic --------------------------------------------------------------------
+// ---- tables and layout -----------------------------------------------------------------
 
-struct Node {
-  uint32_t w0, w1;
+// Dynamic LDS, in doubles: s_w [64] interpolation weights, s_cc [2 kMaxDim] (c_j, c_j^2)
+// pairs, then the slot entries as nslots * 64 uint2 (words 0-1) followed by nslots * 64
+// uint32 (word 2), then one (N + 1)-double buffer per wave.
+constexpr int kLdsTables = 64 + 2 * kMaxDim;
+__host__ __device__ __forceinline__ size_t lds_meta_doubles(int nslots) { return (size_t)nslots * 96; }
+__host__ __device__ __forceinline__ size_t lds_bytes_w(const GridDev& G) {
+  return (kLdsTables + lds_meta_doubles(G.nslots) + (size_t)(G.N + 1) * kWPB) * sizeof(double);
+}
+
+struct WaveLds {
+  double* s_w;
+  double* s_cc;
+  const uint2* m01;
+  const uint32_t* m2;
+  char* yb;          // this wave's buffer (byte addressed)
 };
-__device__ __forceinline__ int n_e(const Node& n) { return n.w0 & 0x1fff; }
-__device__ __forceinline__ int n_g(const Node& n) { return (n.w0 >> 13) & 0xf; }
-__device__ __forceinline__ bool n_bil(const Node& n) { return (n.w0 >> 17) & 1u; }
-__device__ __forceinline__ bool n_valid(const Node& n) { return (n.w0 >> 18) & 1u; }
 
-// Interpolated value at a node from y, in the fixed unfused order of the coder.
-__device__ __forceinline__ double predict_n(const double* y, const double* wt, const Node& n, int np) {
-  const int a = n.w1 & 0x7f, b = (n.w1 >> 7) & 0x7f, aj = (n.w1 >> 14) & 0x7f, bj = (n.w1 >> 21) & 0x7f;
-  const double s = wt[(n.w0 >> 19) & 0x3f];
-  if (!n_bil(n)) {
-    const double y0 = y[aj * np + a], y1 = y[bj * np + b];
-    return __dadd_rn(y0, __dmul_rn(s, __dsub_rn(y1, y0)));
+__device__ __forceinline__ WaveLds setup_lds(const GridDev& G, double* smem, int wv) {
+  WaveLds L;
+  L.s_w = smem;
+  L.s_cc = smem + 64;
+  uint2* m01 = (uint2*)(smem + kLdsTables);
+  uint32_t* m2 = (uint32_t*)(m01 + (size_t)G.nslots * 64);
+  const int t = threadIdx.x;
+  for (int k = t; k < G.nw; k += 256) L.s_w[k] = G.wtab[k];
+  for (int k = t; k < G.n_perp; k += 256) {
+    const double c = G.cperp[k];
+    L.s_cc[2 * k] = c;
+    L.s_cc[2 * k + 1] = c * c;
   }
-  const double y00 = y[aj * np + a], y10 = y[aj * np + b], y01 = y[bj * np + a], y11 = y[bj * np + b];
-  const double t = wt[(n.w0 >> 25) & 0x3f];
+  for (int k = t; k < G.nslots * 64; k += 256) {
+    m01[k] = make_uint2(G.slot_meta[3 * k], G.slot_meta[3 * k + 1]);
+    m2[k] = G.slot_meta[3 * k + 2];
+  }
+  L.m01 = m01;
+  L.m2 = m2;
+  double* y = smem + kLdsTables + lds_meta_doubles(G.nslots) + (size_t)(G.N + 1) * wv;
+  if (t < 256) y[G.N] = 0.0;      // every wave's zero cell (lane 0 of each wave)
+  L.yb = (char*)y;
+  return L;
+}
+
+__device__ __forceinline__ double ldy(const char* yb, uint32_t off) { return *(const double*)(yb + off); }
+__device__ __forceinline__ void sty(char* yb, uint32_t off, double v) { *(double*)(yb + off) = v; }
+
+// Interpolated value of a node from its corners, in the fixed unfused order of the coder
+// (two-corner form unless FOUR).
+template <bool FOUR>
+__device__ __forceinline__ double predict_w(const WaveLds& L, uint2 m, uint32_t m2) {
+  const double y00 = ldy(L.yb, m.x >> 16), y10 = ldy(L.yb, m.y & 0xffffu);
+  const double s = L.s_w[(m2 >> 16) & 63u];
   const double p0 = __dadd_rn(y00, __dmul_rn(s, __dsub_rn(y10, y00)));
+  if (!FOUR) return p0;
+  const double y01 = ldy(L.yb, m.y >> 16), y11 = ldy(L.yb, m2 & 0xffffu);
+  const double t = L.s_w[(m2 >> 22) & 63u];
   const double p1 = __dadd_rn(y01, __dmul_rn(s, __dsub_rn(y11, y01)));
   return __dadd_rn(p0, __dmul_rn(t, __dsub_rn(p1, p0)));
 }
 
-// Hide a value from loop-invariant code motion: without this the compiler hoists every
-// node's decoded corners and weights out of the bisection and Newton loops, which
-// multiplies the live registers and spills.
-__device__ __forceinline__ Node opaque(Node n) {
-  asm volatile("" : "+v"(n.w0), "+v"(n.w1));
-  return n;
-}
-__device__ __forceinline__ int opaque_i(int v) {
-  asm volatile("" : "+v"(v));
-  return v;
+__device__ __forceinline__ bool bit(uint32_t mask, int s) { return (mask >> s) & 1u; }
+
+// The per-slot masks, kept as plain scalars: without the opaque copy the compiler hoists
+// every slot's test out of the bisection loop as a lane mask and spills them.
+struct SlotMasks {
+  uint32_t bil, keep, sync;
+};
+__device__ __forceinline__ SlotMasks slot_masks(const GridDev& G) {
+  SlotMasks m{G.slot_bil, G.slot_keep, G.slot_sync};
+  asm volatile("" : "+s"(m.bil), "+s"(m.keep), "+s"(m.sync));
+  return m;
 }
 
-// y = dq + P (or dq on the coarsest group), stored at the node's offset.
-__device__ __forceinline__ double recompose_node(double* y, const double* wt, const Node& n, double dq, int np) {
-  const double v = n_g(n) == 0 ? dq : __dadd_rn(dq, predict_n(y, wt, n, np));
-  y[n_e(n)] = v;
-  return v;
-}
-
-// Correction A^T lam at one cell: vol * (lam0 + lam1 a + lam2 c + lam3 a^2), one fixed
-// order for compression and decompression.
-__device__ __forceinline__ double corr_cell(const double (&lam)[4], double vol, double a, double c) {
-  double p = fma(lam[3], a, lam[1]);
-  p = fma(p, a, lam[0]);
-  p = fma(lam[2], c, p);
-  return vol * p;
-}
-
-// Recompose every node at step Dk (1/Dk = inv) into y; returns sum (r - y)^2 over the
-// histogram (same value in all lanes).  Slots after the first are independent within a
-// group; a fence separates groups.
-template <int NS>
-__device__ __forceinline__ double recompose_all(const GridDev& G, double* y, const double* wt, const uint2* meta,
-                                const int* ssync, const double (&dm)[NS], const double (&rm)[NS], double Dk,
-                                double inv) {
+// Recompose every node with quantised values dq(s) into the buffer (slots of the finest
+// group only when STORE_ALL) and return sum (rm - y)^2 over the histogram.  DQ(s) gives
+// the lane's quantised coefficient of slot s.
+template <int NS, bool STORE_ALL, typename DQ>
+__device__ __forceinline__ double recompose_w(const GridDev& G, const WaveLds& L, const double (&rm)[NS], DQ dqf) {
   const int lane = threadIdx.x & 63;
-  auto nd_at = [&](int s) { const uint2 v = meta[s * 64 + lane]; return Node{v.x, v.y}; };
+  const SlotMasks sm = slot_masks(G);
   double acc = 0.0;
-  for (int g = 0; g < G.ncoarse; ++g) {
-    const Node n0 = nd_at(0);
-    if (n_valid(n0) && n_g(n0) == g) {
-      const double v = recompose_node(y, wt, n0, __dmul_rn(Dk, rint(__dmul_rn(dm[0], inv))), G.n_par);
-      const double e = rm[0] - v;
-      acc = fma(e, e, acc);
+  {
+    const uint2 m = L.m01[lane];
+    const uint32_t m2 = L.m2[lane];
+    const int g0 = (int)(m2 >> 28);
+    const double dq = dqf(0);
+    for (int g = 0; g < G.ncoarse; ++g) {
+      if (g0 == g) {
+        const double v = g == 0 ? dq : __dadd_rn(dq, predict_w<true>(L, m, m2));
+        sty(L.yb, m.x & 0xffffu, v);
+        const double e = rm[0] - v;
+        acc = fma(e, e, acc);
+      }
+      wave_sync();
     }
-    wave_sync();
   }
-  // Slots of one group read only coarser groups, so the stores of a batch of slots can
-  // wait until every load of the batch is issued; batches end at group boundaries.
-  constexpr int BATCH = 4;
 #pragma unroll
-  for (int s0 = 1; s0 < NS; s0 += BATCH) {
-    double v[BATCH];
-    int ev[BATCH];
-#pragma unroll
-    for (int q = 0; q < BATCH; ++q) {
-      const int s = s0 + q;
-      ev[q] = -1;
-      v[q] = 0.0;
-      const Node n = (s < NS && s < G.nslots) ? nd_at(s) : Node{0u, 0u};
-      if (n_valid(n)) {
-        const double dq = __dmul_rn(Dk, rint(__dmul_rn(dm[s], inv)));
-        v[q] = __dadd_rn(dq, predict_n(y, wt, n, G.n_par));
-        ev[q] = n_e(n);
-      }
-      // a group boundary inside the batch: store what is computed so far first
-      if (s < NS && s < G.nslots && ssync[s]) {
-#pragma unroll
-        for (int r = 0; r <= q; ++r)
-          if (ev[r] >= 0) { y[ev[r]] = v[r]; ev[r] = -2 - ev[r]; }
-        wave_sync();
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < BATCH; ++q) {
-      const int s = s0 + q;
-      if (s < NS && s < G.nslots) {
-        if (ev[q] >= 0) y[ev[q]] = v[q];
-        if (ev[q] != -1) {
-          const double e = rm[s] - v[q];
-          acc = fma(e, e, acc);
-        }
-      }
+  for (int s = 1; s < NS; ++s) {
+    if (s < G.nslots) {
+      const uint2 m = L.m01[s * 64 + lane];
+      const uint32_t m2 = L.m2[s * 64 + lane];
+      const double dq = dqf(s);
+      const double v = __dadd_rn(dq, bit(sm.bil, s) ? predict_w<true>(L, m, m2) : predict_w<false>(L, m, m2));
+      if (STORE_ALL || bit(sm.keep, s)) sty(L.yb, m.x & 0xffffu, v);
+      const double e = rm[s] - v;
+      acc = fma(e, e, acc);
+      if (bit(sm.sync, s)) wave_sync();
     }
   }
   return wsum(acc);
 }
 
-// Newton statistics at lam over the lane's natural-order elements (uniform vol factored
-// out: v[0..3] = sum phi_k x, v[4] = sum |phi_1| x, v[5..14] = sum_{x>0} phi_k phi_l,
-// v[15] = ||x - ft||^2; all scaled back by vol / vol^2 before return).
-__device__ __forceinline__ void newton_stats(const GridDev& G, const double* ft, const double* s_a, const double* s_c,
-                             const double (&lam)[4], double (&v)[16]) {
+// ---- column walks ---------------------------------------------------------------------
+
+// Lane l visits columns i = l, l + 64 (< n_par): begin(i), then body(i, j, off) for every
+// row j, off the byte offset of (j, i) in the wave buffer, then fold(i).
+template <typename BEGIN, typename BODY, typename FOLD>
+__device__ __forceinline__ void for_columns(const GridDev& G, BEGIN begin, BODY body, FOLD fold) {
   const int lane = threadIdx.x & 63;
+  const uint32_t rowb = (uint32_t)G.n_par * 8u;
+  for (int i = lane; i < G.n_par; i += 64) {
+    begin(i);
+    uint32_t off = (uint32_t)i * 8u;
+#pragma unroll 4
+    for (int j = 0; j < G.n_perp; ++j) {
+      body(i, j, off);
+      off += rowb;
+    }
+    fold(i);
+  }
+}
+
+// Newton statistics at lam (Section III Stage 5): v[0..3] = A x, v[4] = sum |A_1| x,
+// v[5..14] = A diag(x > 0) A^T (upper triangle, row-major), v[15] = ||x - ft||^2 when
+// THETA, x = max(0, ft - A^T lam) with ft in the wave buffer.  Per column, sums over the
+// rows of x, c x and (on active cells) w^2, w^2 c, w^2 c^2 are formed first, then
+// weighted by the column's powers of a.  The correction per cell is
+// vol * ((lam3 a + lam1) a + lam0 + lam2 c), one fixed order for compression and
+// decompression.
+template <bool UVOL, bool THETA>
+__device__ __forceinline__ void newton_stats_w(const GridDev& G, const WaveLds& L, const double (&lam)[4],
+                                               double (&v)[16]) {
 #pragma unroll
   for (int k = 0; k < 16; ++k) v[k] = 0.0;
-  int i = lane % G.n_par, j = lane / G.n_par;
-  const int di = 64 % G.n_par, dj = 64 / G.n_par;
-#pragma unroll 2
-  for (int e = lane; e < G.N; e += 64) {
-    const double a = s_a[i], c = s_c[j];
-    const double vol = G.uniform_vol ? G.vol0 : G.vol[e];
-    const double fte = ft[e];
-    const double x = fmax(0.0, fte - corr_cell(lam, vol, a, c));
-    const double w = G.uniform_vol ? 1.0 : vol;
-    const double wx = w * x;
-    const double ax = a * wx;
-    v[0] += wx;
-    v[1] += ax;
-    v[2] = fma(c, wx, v[2]);
-    v[3] = fma(a, ax, v[3]);
-    v[4] = fma(fabs(a), wx, v[4]);
+  double sx, sxc, h0, hc, hcc, s2;
+  double pa = 0.0;
+  auto begin = [&](int i) {
+    const double a = G.apar[i];
+    pa = fma(fma(lam[3], a, lam[1]), a, lam[0]);
+    sx = sxc = h0 = hc = hcc = s2 = 0.0;
+  };
+  auto body = [&](int i, int j, uint32_t off) {
+    const double c = L.s_cc[2 * j], c2 = L.s_cc[2 * j + 1];
+    const double w = UVOL ? G.vol0 : G.vol[j * G.n_par + i];
+    const double ft = ldy(L.yb, off);
+    const double x = fmax(0.0, ft - w * fma(lam[2], c, pa));
+    const double wx = UVOL ? x : w * x;
+    sx += wx;
+    sxc = fma(c, wx, sxc);
     if (x > 0.0) {
-      const double w2 = w * w;
-      const double wa = w2 * a, wc = w2 * c, wa2 = wa * a;
-      v[5] += w2;
-      v[6] += wa;
-      v[7] += wc;
-      v[8] += wa2;
-      v[9] += wa2;
-      v[10] = fma(wa, c, v[10]);
-      v[11] = fma(wa2, a, v[11]);
-      v[12] = fma(wc, c, v[12]);
-      v[13] = fma(wa2, c, v[13]);
-      v[14] = fma(wa2, a * a, v[14]);
+      const double w2 = UVOL ? 1.0 : w * w;
+      h0 += w2;
+      hc = fma(w2, c, hc);
+      hcc = fma(w2, c2, hcc);
     }
-    const double dx = x - fte;
-    v[15] = fma(dx, dx, v[15]);
-    i += di;
-    j += dj;
-    if (i >= G.n_par) { i -= G.n_par; ++j; }
-  }
+    if (THETA) {
+      const double dx = x - ft;
+      s2 = fma(dx, dx, s2);
+    }
+  };
+  auto fold = [&](int i) {
+    const double a = G.apar[i], a2 = a * a;
+    v[0] += sx;
+    v[1] = fma(a, sx, v[1]);
+    v[2] += sxc;
+    v[3] = fma(a2, sx, v[3]);
+    v[4] = fma(fabs(a), sx, v[4]);
+    v[5] += h0;
+    v[6] = fma(a, h0, v[6]);
+    v[7] += hc;
+    v[8] = fma(a2, h0, v[8]);
+    v[10] = fma(a, hc, v[10]);
+    v[11] = fma(a2 * a, h0, v[11]);
+    v[12] += hcc;
+    v[13] = fma(a2, hc, v[13]);
+    v[14] = fma(a2 * a2, h0, v[14]);
+    v[15] += s2;
+  };
+  for_columns(G, begin, body, fold);
 #pragma unroll
-  for (int k = 0; k < 16; ++k) v[k] = wsum(v[k]);
-  if (G.uniform_vol) {
-    const double s1 = G.vol0, s2 = G.vol0 * G.vol0;
+  for (int k = 0; k < 15; ++k)
+    if (k != 9) v[k] = wsum(v[k]);
+  v[9] = v[8];
+  v[15] = THETA ? wsum(v[15]) : 0.0;
+  if (UVOL) {
+    const double s1 = G.vol0, s2v = G.vol0 * G.vol0;
 #pragma unroll
     for (int k = 0; k < 5; ++k) v[k] *= s1;
 #pragma unroll
-    for (int k = 5; k < 15; ++k) v[k] *= s2;
+    for (int k = 5; k < 15; ++k) v[k] *= s2v;
   }
 }
 
@@ -314,15 +355,16 @@ __device__ __forceinline__ bool chol4(const double (&v)[16], const double (&g)[4
   return true;
 }
 
-// Both Newton rounds in one loop with a single pass site (the unrolled pass is large):
-// round 1 takes fixed steps s1 for up to max1 updates; if it does not converge, round 2
-// continues from its multipliers with fixed steps s2 or, with armijo2, Armijo
-// backtracking on theta, for up to max2 updates.  An accepted Armijo candidate's pass is
-// also the next iterate's pass (same multipliers, same values).  Returns 0 (round 1
-// converged), 1 (round 2 converged) or 2 (failed); *upd counts the updates.
-__device__ __forceinline__ int newton_w(const GridDev& G, const double* ft, const double* s_a, const double* s_c,
-                        const double (&b)[4], double (&lam)[4], double s1, int max1, double s2, int max2,
-                        bool armijo2, int* upd, bool have_init, const double (&lam_init)[4], bool* rejected) {
+// Both Newton rounds in one loop with a single pass site: round 1 takes fixed steps s1
+// for up to max1 updates; if it does not converge, round 2 continues from its
+// multipliers with fixed steps s2 or, with armijo2, Armijo backtracking on theta, for up
+// to max2 updates.  An accepted Armijo candidate's pass is also the next iterate's pass
+// (same multipliers, same values).  Returns 0 (round 1 converged), 1 (round 2
+// converged) or 2 (failed); *upd counts the updates.
+template <bool UVOL>
+__device__ __forceinline__ int newton_w(const GridDev& G, const WaveLds& L, const double (&b)[4], double (&lam)[4],
+                                        double s1, int max1, double s2, int max2, bool armijo2, int* upd,
+                                        bool have_init, const double (&lam_init)[4], bool* rejected) {
   int round = 0, it = 0, total = 0, halvings = 0;
   bool trial = false;
   // warm start: lam begins at lam_init; it is dropped (cold restart) if round 1 allows no
@@ -344,8 +386,8 @@ __device__ __forceinline__ int newton_w(const GridDev& G, const double* ft, cons
   double t0 = 0.0, gd = 0.0, step = 1.0;
   double v[16];
   for (;;) {
-    newton_stats(G, ft, s_a, s_c, cand, v);
-    const bool armijo = round == 1 && armijo2;
+    if (round == 1 && armijo2) newton_stats_w<UVOL, true>(G, L, cand, v);
+    else newton_stats_w<UVOL, false>(G, L, cand, v);
     if (trial) {
       if (theta_w(v, cand, b) >= t0 + kArmijoC * step * gd) {
 #pragma unroll
@@ -402,9 +444,8 @@ __device__ __forceinline__ int newton_w(const GridDev& G, const double* ft, cons
       it = 0;
 #pragma unroll
       for (int k = 0; k < 4; ++k) cand[k] = lam[k];
-      // the pass at lam is v already: redo the checks for round 2 without a new pass
-      const int cap2 = max2;
-      if (it == cap2 || !chol4(v, g, d)) break;
+      if (armijo2) continue;     // round 2 needs theta at lam: one pass with it
+      if (it == max2 || !chol4(v, g, d)) break;
     }
     if (round == 1 && armijo2) {
       t0 = theta_w(v, lam, b);
@@ -423,114 +464,74 @@ __device__ __forceinline__ int newton_w(const GridDev& G, const double* ft, cons
       ++it;
       ++total;
     }
-    (void)armijo;
   }
   *upd = total;
   return 2;
 }
 
-// Dynamic LDS of the wave kernels, in doubles: s_a [kMaxDim], s_c [kMaxDim], s_w [64],
-// then (compression only) the node metadata, nslots * 64 entries of two words = one
-// double each, then one N-double buffer per wave.  Kernels and launchers both take the
-// offsets from here.
-constexpr int kLdsTables = 2 * kMaxDim + 64;
-__host__ __device__ __forceinline__ size_t lds_meta_doubles(int nslots) { return (size_t)nslots * 64; }
-
-// Per-grid scalars that are indexed at run time go to LDS (indexing them inside the
-// by-value kernel argument would force a private copy of the whole argument).
-__device__ __forceinline__ void load_small_tables(const GridDev& G, int* gs, int* sg, int* ss) {
-  const int t = threadIdx.x;
-  if (t <= kMaxLev) gs[t] = t <= G.nlev ? G.gstart[t] : G.N;
-  if (t < kWaveSlots) {
-    sg[t] = G.slot_group[t];
-    ss[t] = G.slot_sync[t];
-  }
-}
-
 // ---- compression ------------------------------------------------------------------------
 
-template <typename TIn, int NS>
+template <typename TIn, bool UVOL, int NS>
 __global__ __launch_bounds__(256, 2) void k_residual_w(GridDev G, ResidualArgs a) {
   extern __shared__ double smem[];
   __shared__ uint32_t s_gmax[kWPB][kMaxLev], s_width[kWPB][kMaxLev], s_base[kWPB][kMaxLev];
   __shared__ int s_gstart[kMaxLev + 1];
-  __shared__ int s_sgroup[kWaveSlots], s_ssync[kWaveSlots];
-  double* s_a = smem;                    // [128]
-  double* s_c = smem + kMaxDim;          // [128]
-  double* s_w = smem + 2 * kMaxDim;      // [64]
-  uint2* meta = (uint2*)(smem + kLdsTables);                       // [nslots * 64]
+  __shared__ int s_sgroup[kWaveSlots];
   const int N = G.N;
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  double* y = smem + kLdsTables + lds_meta_doubles(G.nslots) + (size_t)N * wv;
-  uint32_t* words = (uint32_t*)y;        // payload words reuse the buffer once ft is read
-  for (int k = threadIdx.x; k < G.n_par; k += 256) s_a[k] = G.apar[k];
-  for (int k = threadIdx.x; k < G.n_perp; k += 256) s_c[k] = G.cperp[k];
-  for (int k = threadIdx.x; k < G.nw; k += 256) s_w[k] = G.wtab[k];
-  for (int k = threadIdx.x; k < G.nslots * 64; k += 256)
-    meta[k] = make_uint2(G.slot_meta[2 * k], G.slot_meta[2 * k + 1]);
-  load_small_tables(G, s_gstart, s_sgroup, s_ssync);
+  const WaveLds L = setup_lds(G, smem, wv);
+  if (threadIdx.x <= kMaxLev) s_gstart[threadIdx.x] = threadIdx.x <= G.nlev ? G.gstart[threadIdx.x] : N;
+  if (threadIdx.x < kWaveSlots) s_sgroup[threadIdx.x] = G.slot_group[threadIdx.x];
   __syncthreads();
   const long long h = (long long)blockIdx.x * kWPB + wv;
   if (h >= a.H) return;
   const TIn* f = (const TIn*)a.hist + h * a.hs;
   const float* fhp = a.fhat ? a.fhat + h * (long long)N : nullptr;
+  uint32_t* words = (uint32_t*)L.yb;     // payload words borrow the buffer before the last recomposition
 
-  // ---- natural-order pass: residual into LDS, moments, norms, range ----
+  // ---- column pass: residual into the buffer, moments, norms, range ----
   dd ff{0.0, 0.0};
   double rr = 0.0, m0 = 0.0, m1 = 0.0, m2 = 0.0, m3 = 0.0, fmx = -INFINITY, fmnn = -INFINITY;
   bool bad = false;
   {
-    // issue every load of the histogram before using any (one round trip of latency)
-    TIn fr[NS];
-    float hr[NS];
-    {
-      int i = lane % G.n_par, j = lane / G.n_par;
-      const int di = 64 % G.n_par, dj = 64 / G.n_par;
-#pragma unroll
-      for (int m = 0; m < NS; ++m) {
-        const int e = lane + 64 * m;
-        fr[m] = (TIn)0;
-        hr[m] = 0.0f;
-        if (e < N) {
-          fr[m] = f[(long long)j * a.rs + i];
-          if (fhp) hr[m] = fhp[e];
-        }
-        i += di;
-        j += dj;
-        if (i >= G.n_par) { i -= G.n_par; ++j; }
-      }
-    }
-    int i = lane % G.n_par, j = lane / G.n_par;
-    const int di = 64 % G.n_par, dj = 64 / G.n_par;
-#pragma unroll
-    for (int m = 0; m < NS; ++m) {
-      const int e = lane + 64 * m;
-      if (e < N) {
-        const double fv = (double)fr[m];
-        const double r = fv - (double)hr[m];
-        y[e] = r;
-        ff = dd_add_d(ff, fv * fv);
-        rr = fma(r, r, rr);
-        const double w = G.uniform_vol ? fv : G.vol[e] * fv;
-        const double av = s_a[i];
-        const double wa = w * av;
-        m0 += w;
-        m1 += wa;
-        m2 = fma(s_c[j], w, m2);
-        m3 = fma(av, wa, m3);
-        bad |= !isfinite(fv);
-        fmx = fmax(fmx, fv);
-        fmnn = fmax(fmnn, -fv);
-      }
-      i += di;
-      j += dj;
-      if (i >= G.n_par) { i -= G.n_par; ++j; }
-    }
+    double sf = 0.0, sfc = 0.0;
+    auto body = [&](int i, int j, uint32_t off) {
+      const double fv = (double)f[(long long)j * a.rs + i];
+      const double hv = fhp ? (double)fhp[j * G.n_par + i] : 0.0;
+      const double r = fv - hv;
+      sty(L.yb, off, r);
+      // ||f||^2 in double-double: the products are rounded as in a plain FP64 sum of
+      // squares, the sum is carried with TwoSum error terms
+      const double p = fv * fv;
+      const double hi = ff.hi + p;
+      const double bb = hi - ff.hi;
+      ff.lo += (ff.hi - (hi - bb)) + (p - bb);
+      ff.hi = hi;
+      rr = fma(r, r, rr);
+      const double w = UVOL ? fv : G.vol[j * G.n_par + i] * fv;
+      sf += w;
+      sfc = fma(L.s_cc[2 * j], w, sfc);
+      bad |= !isfinite(fv);
+      fmx = fmax(fmx, fv);
+      fmnn = fmax(fmnn, -fv);
+    };
+    auto fold = [&](int i) {
+      const double av = G.apar[i];
+      m0 += sf;
+      m1 = fma(av, sf, m1);
+      m2 += sfc;
+      m3 = fma(av * av, sf, m3);
+    };
+    for_columns(G, [&](int) { sf = sfc = 0.0; }, body, fold);
+  }
+  {
+    const double hi = ff.hi + ff.lo;
+    ff = dd{hi, ff.lo - (hi - ff.hi)};
   }
   ff = wdd(ff);
   rr = wsum(rr);
   double b[4] = {wsum(m0), wsum(m1), wsum(m2), wsum(m3)};
-  if (G.uniform_vol) {
+  if (UVOL) {
 #pragma unroll
     for (int k = 0; k < 4; ++k) b[k] *= G.vol0;
   }
@@ -549,33 +550,37 @@ __global__ __launch_bounds__(256, 2) void k_residual_w(GridDev G, ResidualArgs a
   int kst = 0xff;
   uint32_t rec_bytes = 0;
   // ft = fhat + rhat (rhat = 0 when not coded), written over the buffer in natural order
-  bool ft_ready = false;
   auto load_ft = [&](bool with_r) {
-    float hr[NS];
-#pragma unroll
-    for (int m = 0; m < NS; ++m) {
-      const int e = lane + 64 * m;
-      hr[m] = (fhp && e < N) ? fhp[e] : 0.0f;
-    }
-#pragma unroll
-    for (int m = 0; m < NS; ++m) {
-      const int e = lane + 64 * m;
-      if (e < N) y[e] = (double)hr[m] + (with_r ? y[e] : 0.0);
-    }
+    for_columns(
+        G, [](int) {},
+        [&](int i, int j, uint32_t off) {
+          const double hv = fhp ? (double)fhp[j * G.n_par + i] : 0.0;
+          sty(L.yb, off, with_r ? hv + ldy(L.yb, off) : hv);
+        },
+        [](int) {});
     wave_sync();
   };
-  auto nd_at = [&](int s) { const uint2 v = meta[s * 64 + lane]; return Node{v.x, v.y}; };
+  bool ft_ready = false;
   if (coded && !raw) {
+    // coefficients: d = r - P(r) over the residual itself (no node is rewritten here)
     double dm[NS], rm[NS];
     double mx = 0.0;
+    {
+      const uint2 m = L.m01[lane];
+      const uint32_t mm2 = L.m2[lane];
+      rm[0] = ldy(L.yb, m.x & 0xffffu);
+      dm[0] = (mm2 >> 28) == 0 ? rm[0] : __dsub_rn(rm[0], predict_w<true>(L, m, mm2));
+      mx = fabs(dm[0]);
+    }
 #pragma unroll
-    for (int s = 0; s < NS; ++s) {
+    for (int s = 1; s < NS; ++s) {
       dm[s] = 0.0;
       rm[s] = 0.0;
-      const Node n = s < G.nslots ? nd_at(s) : Node{0u, 0u};
-      if (n_valid(n)) {
-        rm[s] = y[n_e(n)];
-        dm[s] = n_g(n) == 0 ? rm[s] : __dsub_rn(rm[s], predict_n(y, s_w, n, G.n_par));
+      if (s < G.nslots) {
+        const uint2 m = L.m01[s * 64 + lane];
+        const uint32_t mm2 = L.m2[s * 64 + lane];
+        rm[s] = ldy(L.yb, m.x & 0xffffu);
+        dm[s] = __dsub_rn(rm[s], bit(G.slot_bil, s) ? predict_w<true>(L, m, mm2) : predict_w<false>(L, m, mm2));
         mx = fmax(mx, fabs(dm[s]));
       }
     }
@@ -588,34 +593,39 @@ __global__ __launch_bounds__(256, 2) void k_residual_w(GridDev G, ResidualArgs a
       while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
         const double Dk = ladder(d0, mid);
-        const double e2 = recompose_all<NS>(G, y, s_w, meta, s_ssync, dm, rm, Dk, 1.0 / Dk);
+        const double inv = 1.0 / Dk;
+        const double e2 = recompose_w<NS, false>(G, L, rm, [&](int s) { return qdelta(Dk, dm[s], inv); });
         if (e2 <= thr2) lo = mid;
         else hi = mid;
       }
       kst = lo;
       const double Dk = ladder(d0, kst);
       const double inv = 1.0 / Dk;
-      // zigzag integers, per-group widths (packing first: the payload words borrow the
-      // buffer, which the final recomposition then fills with rhat)
+      // zigzag integers and per-group widths; the payload words borrow the buffer, which
+      // the final recomposition then fills with rhat
       if (lane < kMaxLev) s_gmax[wv][lane] = 0u;
       wave_sync();
       auto zz = [&](double d) -> uint32_t {
         const int q = (int)rint(__dmul_rn(d, inv));
         return ((uint32_t)q << 1) ^ (uint32_t)(q >> 31);
       };
+      const uint32_t zero_off = (uint32_t)N * 8u;
       // slot 0 may mix groups: reduce each of its groups separately
-      const Node nd0 = nd_at(0);
-      const uint32_t u0 = n_valid(nd0) ? zz(dm[0]) : 0u;
-      for (int g = 0; g < G.ncoarse; ++g) {
-        const uint32_t v = wumax((n_valid(nd0) && n_g(nd0) == g) ? u0 : 0u);
-        if (lane == 0) s_gmax[wv][g] = max(s_gmax[wv][g], v);
+      {
+        const uint32_t mm2 = L.m2[lane];
+        const int g0 = (int)(mm2 >> 28);
+        const uint32_t u0 = zz(dm[0]);
+        for (int g = 0; g < G.ncoarse; ++g) {
+          const uint32_t v = wumax(g0 == g ? u0 : 0u);
+          if (lane == 0) s_gmax[wv][g] = max(s_gmax[wv][g], v);
+        }
       }
       uint32_t cur = 0u;
 #pragma unroll
       for (int s = 1; s < NS; ++s) {
         if (s < G.nslots) {
-          if (n_valid(nd_at(s))) cur = max(cur, zz(dm[s]));
-          if (s_ssync[s]) {
+          cur = max(cur, zz(dm[s]));          // padding lanes hold d = 0
+          if (bit(G.slot_sync, s)) {
             const uint32_t v = wumax(cur);
             if (lane == 0) {
               const int g = s_sgroup[s];
@@ -638,16 +648,18 @@ __global__ __launch_bounds__(256, 2) void k_residual_w(GridDev G, ResidualArgs a
       wave_sync();
 #pragma unroll
       for (int s = 0; s < NS; ++s) {
-        const Node n = s < G.nslots ? nd_at(s) : Node{0u, 0u};
-        if (n_valid(n)) {
-          const int g = n_g(n);
-          const uint32_t wdt = s_width[wv][g];
-          if (wdt != 0) {
-            const int p = G.slot_pos[(size_t)s * 64 + lane];
-            const uint32_t pos = s_base[wv][g] + (uint32_t)(p - s_gstart[g]) * wdt;
-            const uint64_t v = (uint64_t)zz(dm[s]) << (pos & 31u);
-            atomicOr(&words[pos >> 5], (uint32_t)v);
-            if ((pos & 31u) + wdt > 32u) atomicOr(&words[(pos >> 5) + 1], (uint32_t)(v >> 32));
+        if (s < G.nslots) {
+          const uint32_t eo = L.m01[s * 64 + lane].x & 0xffffu;
+          const int g = s == 0 ? (int)(L.m2[lane] >> 28) : s_sgroup[s];
+          if (eo != zero_off) {
+            const uint32_t wdt = s_width[wv][g];
+            if (wdt != 0) {
+              const int p = G.slot_pos[(size_t)s * 64 + lane];
+              const uint32_t pos = s_base[wv][g] + (uint32_t)(p - s_gstart[g]) * wdt;
+              const uint64_t v = (uint64_t)zz(dm[s]) << (pos & 31u);
+              atomicOr(&words[pos >> 5], (uint32_t)v);
+              if ((pos & 31u) + wdt > 32u) atomicOr(&words[(pos >> 5) + 1], (uint32_t)(v >> 32));
+            }
           }
         }
       }
@@ -670,14 +682,16 @@ __global__ __launch_bounds__(256, 2) void k_residual_w(GridDev G, ResidualArgs a
       for (uint32_t k = lane; k < nwords; k += 64) pw[k] = words[k];
       rec_bytes = (uint32_t)G.hdr_bytes + 4u * nwords;
       wave_sync();
-      recompose_all<NS>(G, y, s_w, meta, s_ssync, dm, rm, Dk, inv);   // rhat at k* now in y
+      if (lane == 0) sty(L.yb, zero_off, 0.0);     // the words may have reached the zero cell
+      wave_sync();
+      recompose_w<NS, true>(G, L, rm, [&](int s) { return qdelta(Dk, dm[s], inv); });
       wave_sync();
       load_ft(true);                                          // ft = fhat + rhat
       ft_ready = true;
     }
   }
 
-  // ---- Newton projection in natural order ----
+  // ---- Newton projection ----
   double lam[4] = {0.0, 0.0, 0.0, 0.0};
   int flags = 0, total_upd = 0;
   if (!raw) {
@@ -689,8 +703,8 @@ __global__ __launch_bounds__(256, 2) void k_residual_w(GridDev G, ResidualArgs a
       for (int k = 0; k < 4; ++k) l0[k] = a.lam0[h * 4 + k];
     }
     bool rejected = false;
-    const int st = newton_w(G, y, s_a, s_c, b, lam, a.newton_s, a.max_iter, paper ? 0.01 : 1.0,
-                            a.max_iter2, !paper, &total_upd, a.lam0 != nullptr, l0, &rejected);
+    const int st = newton_w<UVOL>(G, L, b, lam, a.newton_s, a.max_iter, paper ? 0.01 : 1.0, a.max_iter2, !paper,
+                                  &total_upd, a.lam0 != nullptr, l0, &rejected);
     if (rejected) flags |= HCZ_FLAG_WARM_REJECTED;
     if (st >= 1) flags |= HCZ_FLAG_ROUND2;
     if (st == 2) raw = true;
@@ -700,14 +714,9 @@ __global__ __launch_bounds__(256, 2) void k_residual_w(GridDev G, ResidualArgs a
   if (raw) {
     flags = (flags & (HCZ_FLAG_ROUND2 | HCZ_FLAG_WARM_REJECTED)) | HCZ_FLAG_RAW;
     TIn* dst = (TIn*)(a.slots + h * a.slot_stride);
-    int i = lane % G.n_par, j = lane / G.n_par;
-    const int di = 64 % G.n_par, dj = 64 / G.n_par;
-    for (int e = lane; e < N; e += 64) {
-      dst[e] = f[(long long)j * a.rs + i];
-      i += di;
-      j += dj;
-      if (i >= G.n_par) { i -= G.n_par; ++j; }
-    }
+    for_columns(
+        G, [](int) {}, [&](int i, int j, uint32_t) { dst[j * G.n_par + i] = f[(long long)j * a.rs + i]; },
+        [](int) {});
     size = (uint64_t)N * sizeof(TIn);
     kst = 0xff;
   } else if (coded) {
@@ -728,22 +737,17 @@ __global__ __launch_bounds__(256, 2) void k_residual_w(GridDev G, ResidualArgs a
 
 __device__ __forceinline__ uint32_t ld32w(const uint8_t* p) { return *(const uint32_t*)p; }
 
-template <typename TIn, typename TOut, int NS>
+template <typename TIn, typename TOut, bool UVOL, int NS>
 __global__ __launch_bounds__(256, 2) void k_decompress_w(GridDev G, DecompressArgs a) {
   extern __shared__ double smem[];
   __shared__ uint32_t s_width[kWPB][kMaxLev], s_base[kWPB][kMaxLev];
   __shared__ int s_gstart[kMaxLev + 1];
-  __shared__ int s_sgroup[kWaveSlots], s_ssync[kWaveSlots];
-  double* s_a = smem;
-  double* s_c = smem + kMaxDim;
-  double* s_w = smem + 2 * kMaxDim;
+  __shared__ int s_sgroup[kWaveSlots];
   const int N = G.N;
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  double* y = smem + kLdsTables + (size_t)N * wv;
-  for (int k = threadIdx.x; k < G.n_par; k += 256) s_a[k] = G.apar[k];
-  for (int k = threadIdx.x; k < G.n_perp; k += 256) s_c[k] = G.cperp[k];
-  for (int k = threadIdx.x; k < G.nw; k += 256) s_w[k] = G.wtab[k];
-  load_small_tables(G, s_gstart, s_sgroup, s_ssync);
+  const WaveLds L = setup_lds(G, smem, wv);
+  if (threadIdx.x <= kMaxLev) s_gstart[threadIdx.x] = threadIdx.x <= G.nlev ? G.gstart[threadIdx.x] : N;
+  if (threadIdx.x < kWaveSlots) s_sgroup[threadIdx.x] = G.slot_group[threadIdx.x];
   __syncthreads();
   const long long h = (long long)blockIdx.x * kWPB + wv;
   if (h >= a.H) return;
@@ -785,17 +789,16 @@ __global__ __launch_bounds__(256, 2) void k_decompress_w(GridDev G, DecompressAr
     }
     wave_sync();
     const uint8_t* payload = rec + G.hdr_bytes;
-    Node nd[NS];
-    double dq[NS];
+    const uint32_t zero_off = (uint32_t)N * 8u;
+    double dq[NS], rm[NS];
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
-      nd[s] = Node{0u, 0u};
       dq[s] = 0.0;
+      rm[s] = 0.0;
       if (s < G.nslots) {
-        const uint32_t* mp = G.slot_meta + ((size_t)s * 64 + lane) * 2;
-        nd[s] = Node{mp[0], mp[1]};
-        if (n_valid(nd[s])) {
-          const int g = n_g(nd[s]);
+        const uint32_t eo = L.m01[s * 64 + lane].x & 0xffffu;
+        const int g = s == 0 ? (int)(L.m2[lane] >> 28) : s_sgroup[s];
+        if (eo != zero_off) {
           const uint32_t wdt = s_width[wv][g];
           uint32_t u = 0;
           if (wdt) {
@@ -811,74 +814,57 @@ __global__ __launch_bounds__(256, 2) void k_decompress_w(GridDev G, DecompressAr
         }
       }
     }
-    // recomposition in the compressor's order
-    for (int g = 0; g < G.ncoarse; ++g) {
-      if (n_valid(nd[0]) && n_g(nd[0]) == g) recompose_node(y, s_w, nd[0], dq[0], G.n_par);
-      wave_sync();
-    }
-#pragma unroll
-    for (int s = 1; s < NS; ++s) {
-      if (s < G.nslots) {
-        if (n_valid(nd[s])) recompose_node(y, s_w, nd[s], dq[s], G.n_par);
-        if (s_ssync[s]) wave_sync();
-      }
-    }
+    recompose_w<NS, true>(G, L, rm, [&](int s) { return dq[s]; });
   }
   double lam[4];
 #pragma unroll
   for (int k = 0; k < 4; ++k) lam[k] = a.lambda[h * 4 + k];
-  float hr[NS];
-#pragma unroll
-  for (int m = 0; m < NS; ++m) {
-    const int e = lane + 64 * m;
-    hr[m] = (fhp && e < N) ? fhp[e] : 0.0f;
-  }
-  int i = lane % G.n_par, j = lane / G.n_par;
-  const int di = 64 % G.n_par, dj = 64 / G.n_par;
-#pragma unroll
-  for (int m = 0; m < NS; ++m) {
-    const int e = lane + 64 * m;
-    if (e < N) {
-      const double ft = (double)hr[m] + (coded ? y[e] : 0.0);
-      const double vol = G.uniform_vol ? G.vol0 : G.vol[e];
-      out[e] = (TOut)fmax(0.0, ft - corr_cell(lam, vol, s_a[i], s_c[j]));
-    }
-    i += di;
-    j += dj;
-    if (i >= G.n_par) { i -= G.n_par; ++j; }
-  }
+  double pa = 0.0;
+  for_columns(
+      G,
+      [&](int i) {
+        const double av = G.apar[i];
+        pa = fma(fma(lam[3], av, lam[1]), av, lam[0]);
+      },
+      [&](int i, int j, uint32_t off) {
+        const double hv = fhp ? (double)fhp[j * G.n_par + i] : 0.0;
+        const double ft = coded ? hv + ldy(L.yb, off) : hv;
+        const double w = UVOL ? G.vol0 : G.vol[j * G.n_par + i];
+        out[j * G.n_par + i] = (TOut)fmax(0.0, ft - w * fma(lam[2], L.s_cc[2 * j], pa));
+      },
+      [](int) {});
 }
 
 // ---- launchers ----------------------------------------------------------------------------
-
-static size_t lds_bytes(const GridDev& G, bool with_meta) {
-  const size_t meta = with_meta ? lds_meta_doubles(G.nslots) : 0;
-  return (kLdsTables + meta + (size_t)G.N * kWPB) * sizeof(double);
-}
 
 bool wave_path(const GridDev& G) { return G.nslots > 0 && G.nslots <= kWaveSlots; }
 
 hipError_t launch_residual_w(const GridDev& G, const ResidualArgs& a, hipStream_t st) {
   if (a.H <= 0) return hipSuccess;
   dim3 grid((unsigned)((a.H + kWPB - 1) / kWPB)), block(64 * kWPB);
-  const size_t lds = lds_bytes(G, true);
-  if (a.dtype == HCZ_F32)
-    hipLaunchKernelGGL((k_residual_w<float, kWaveSlots>), grid, block, lds, st, G, a);
-  else
-    hipLaunchKernelGGL((k_residual_w<double, kWaveSlots>), grid, block, lds, st, G, a);
+  const size_t lds = lds_bytes_w(G);
+#define HCZ_RW(T, U) hipLaunchKernelGGL((k_residual_w<T, U, kWaveSlots>), grid, block, lds, st, G, a)
+  if (a.dtype == HCZ_F32) {
+    if (G.uniform_vol) HCZ_RW(float, true); else HCZ_RW(float, false);
+  } else {
+    if (G.uniform_vol) HCZ_RW(double, true); else HCZ_RW(double, false);
+  }
+#undef HCZ_RW
   return hipGetLastError();
 }
 
 hipError_t launch_decompress_w(const GridDev& G, const DecompressArgs& a, hipStream_t st) {
   if (a.H <= 0) return hipSuccess;
   dim3 grid((unsigned)((a.H + kWPB - 1) / kWPB)), block(64 * kWPB);
-  const size_t lds = lds_bytes(G, false);
-#define HCZ_DW(TI, TO) hipLaunchKernelGGL((k_decompress_w<TI, TO, kWaveSlots>), grid, block, lds, st, G, a)
+  const size_t lds = lds_bytes_w(G);
+#define HCZ_DW(TI, TO, U) hipLaunchKernelGGL((k_decompress_w<TI, TO, U, kWaveSlots>), grid, block, lds, st, G, a)
+#define HCZ_DW2(TI, TO) do { if (G.uniform_vol) HCZ_DW(TI, TO, true); else HCZ_DW(TI, TO, false); } while (0)
   if (a.in_dtype == HCZ_F32) {
-    if (a.out_dtype == HCZ_F64) HCZ_DW(float, double); else HCZ_DW(float, float);
+    if (a.out_dtype == HCZ_F64) HCZ_DW2(float, double); else HCZ_DW2(float, float);
   } else {
-    if (a.out_dtype == HCZ_F64) HCZ_DW(double, double); else HCZ_DW(double, float);
+    if (a.out_dtype == HCZ_F64) HCZ_DW2(double, double); else HCZ_DW2(double, float);
   }
+#undef HCZ_DW2
 #undef HCZ_DW
   return hipGetLastError();
 }
