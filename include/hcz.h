@@ -162,6 +162,15 @@ const char* hcz_version(void);
 hcz_status hcz_plan_create(hcz_ctx* ctx, const hcz_grid* grid, hcz_plan** out);
 void hcz_plan_destroy(hcz_plan* plan);
 
+/* Which per-histogram kernels serve `plan`'s grid (host only, no GPU work):
+   HCZ_PATH_BLOCK one workgroup per histogram (grids too large for one wave),
+   HCZ_PATH_WAVE one wave per histogram with the slot structure read at run time,
+   HCZ_PATH_WAVE_FIXED one wave per histogram with a slot structure compiled in
+   (the 39 x 39 grid with uniform cell volumes).  Results are identical on every path.
+   Errors: HCZ_EINVAL for a NULL argument. */
+enum { HCZ_PATH_BLOCK = 0, HCZ_PATH_WAVE = 1, HCZ_PATH_WAVE_FIXED = 2 };
+hcz_status hcz_plan_path(const hcz_plan* plan, int32_t* path);
+
 /* Copy an autoencoder to the device for `plan`'s grid (N = n_par * n_perp). */
 hcz_status hcz_model_load(hcz_plan* plan, const hcz_model_desc* desc, hcz_model** out);
 void hcz_model_free(hcz_model* model);

@@ -542,6 +542,12 @@ hcz_status hcz_plan_create(hcz_ctx* ctx, const hcz_grid* g, hcz_plan** out) {
   return HCZ_OK;
 }
 
+hcz_status hcz_plan_path(const hcz_plan* plan, int32_t* path) {
+  if (!plan || !path) return fail(HCZ_EINVAL, "NULL argument");
+  *path = wave_fixed_path(plan->G) ? HCZ_PATH_WAVE_FIXED : wave_path(plan->G) ? HCZ_PATH_WAVE : HCZ_PATH_BLOCK;
+  return HCZ_OK;
+}
+
 void hcz_plan_destroy(hcz_plan* plan) {
   if (!plan) return;
   free_all(plan->allocs);

@@ -290,6 +290,7 @@ hipError_t launch_qoi(const GridDev& G, const void* hist, int dtype, long long H
                       long long rs, double* b, double* qoi, double* norm, hipStream_t st);
 hipError_t launch_residual(const GridDev& G, const ResidualArgs& a, hipStream_t st);
 bool wave_path(const GridDev& G);
+bool wave_fixed_path(const GridDev& G);
 hipError_t launch_residual_w(const GridDev& G, const ResidualArgs& a, hipStream_t st);
 hipError_t launch_decompress_w(const GridDev& G, const DecompressArgs& a, hipStream_t st);
 hipError_t launch_decompress(const GridDev& G, const DecompressArgs& a, hipStream_t st);

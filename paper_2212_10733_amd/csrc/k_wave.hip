@@ -176,11 +176,91 @@ __device__ __forceinline__ SlotMasks slot_masks(const GridDev& G) {
   return m;
 }
 
+// Slot structure of a grid: read from the plan at run time (any grid), or fixed at
+// compile time for a grid whose tables match, which lets every per-slot choice fold away
+// and batches of slots issue their LDS reads together.
+struct ShapeDyn {
+  static constexpr bool fixed = false;
+  static constexpr int NS = kWaveSlots, NCO = 0;
+  static constexpr uint32_t BIL = 0, SYNC = 0, KEEP = 0;
+};
+// 39 x 39 (the velocity grid of the paper's data): slot 0 holds groups 0-3, slots 1-2
+// group 4, slots 3-7 group 5 and slots 8-25 the finest group.
+struct Shape39 {
+  static constexpr bool fixed = true;
+  static constexpr int NS = 26, NCO = 4;
+  static constexpr uint32_t BIL = 0x3f800c7u, SYNC = 0x2000085u, KEEP = 0xffu;
+};
+template <class SH>
+__host__ __device__ constexpr bool shape_matches(const GridDev& G) {
+  return !SH::fixed || (G.nslots == SH::NS && G.ncoarse == SH::NCO && G.slot_bil == SH::BIL &&
+                        G.slot_sync == SH::SYNC && G.slot_keep == SH::KEEP);
+}
+template <class SH> __device__ __forceinline__ int nslots_of(const GridDev& G) { return SH::fixed ? SH::NS : G.nslots; }
+template <class SH> __device__ __forceinline__ int ncoarse_of(const GridDev& G) { return SH::fixed ? SH::NCO : G.ncoarse; }
+template <class SH> __device__ __forceinline__ bool bil_of(const GridDev& G, int s) {
+  return SH::fixed ? bit(SH::BIL, s) : bit(G.slot_bil, s);
+}
+template <class SH> __device__ __forceinline__ bool sync_of(const GridDev& G, int s) {
+  return SH::fixed ? bit(SH::SYNC, s) : bit(G.slot_sync, s);
+}
+
+constexpr int kBatch = 4;   // slots whose LDS reads issue together (fixed shapes)
+
+// End of the batch that starts at slot s: at most kBatch slots, closed by a group end.
+template <class SH>
+constexpr int batch_end(int s) {
+  int e = s;
+  while (e < SH::NS && e - s < kBatch) {
+    ++e;
+    if ((SH::SYNC >> (e - 1)) & 1u) break;
+  }
+  return e;
+}
+
+// Slots [S, E) of one group: every entry and corner read first, then values, stores
+// and errors.  Nothing in the batch reads what the batch writes.
+template <class SH, int S, int E, bool STORE_ALL, typename DQ>
+__device__ __forceinline__ void batch_fixed(const WaveLds& L, const double (&rm)[SH::NS], DQ& dqf, double& acc) {
+  const int lane = threadIdx.x & 63;
+  constexpr int B = E - S;
+  uint2 m[B];
+  uint32_t m2[B];
+#pragma unroll
+  for (int k = 0; k < B; ++k) {
+    m[k] = L.m01[(S + k) * 64 + lane];
+    m2[k] = L.m2[(S + k) * 64 + lane];
+  }
+  double v[B];
+#pragma unroll
+  for (int k = 0; k < B; ++k)
+    v[k] = __dadd_rn(dqf(S + k), bit(SH::BIL, S + k) ? predict_w<true>(L, m[k], m2[k])
+                                                      : predict_w<false>(L, m[k], m2[k]));
+#pragma unroll
+  for (int k = 0; k < B; ++k) {
+    if (STORE_ALL || bit(SH::KEEP, S + k)) sty(L.yb, m[k].x & 0xffffu, v[k]);
+    const double e = rm[S + k] - v[k];
+    acc = fma(e, e, acc);
+  }
+}
+
+template <class SH, int S, bool STORE_ALL, typename DQ>
+__device__ __forceinline__ void slots_fixed(const WaveLds& L, const double (&rm)[SH::NS], DQ& dqf, double& acc) {
+  if constexpr (S < SH::NS) {
+    constexpr int E = batch_end<SH>(S);
+    batch_fixed<SH, S, E, STORE_ALL>(L, rm, dqf, acc);
+    if constexpr (((SH::SYNC >> (E - 1)) & 1u) != 0) wave_sync();
+    slots_fixed<SH, E, STORE_ALL>(L, rm, dqf, acc);
+  }
+}
+
 // Recompose every node with quantised values dq(s) into the buffer (slots of the finest
 // group only when STORE_ALL) and return sum (rm - y)^2 over the histogram.  DQ(s) gives
 // the lane's quantised coefficient of slot s.
-template <int NS, bool STORE_ALL, typename DQ>
-__device__ __forceinline__ double recompose_w(const GridDev& G, const WaveLds& L, const double (&rm)[NS], DQ dqf) {
+template <class SH, bool STORE_ALL, typename DQ>
+__device__ __forceinline__ double recompose_w(const GridDev& G, const WaveLds& L, const double (&rm)[SH::NS],
+                                              DQ dqf) {
+  constexpr int NS = SH::NS;
   const int lane = threadIdx.x & 63;
   const SlotMasks sm = slot_masks(G);
   double acc = 0.0;
@@ -189,7 +269,7 @@ __device__ __forceinline__ double recompose_w(const GridDev& G, const WaveLds& L
     const uint32_t m2 = L.m2[lane];
     const int g0 = (int)(m2 >> 28);
     const double dq = dqf(0);
-    for (int g = 0; g < G.ncoarse; ++g) {
+    for (int g = 0; g < ncoarse_of<SH>(G); ++g) {
       if (g0 == g) {
         const double v = g == 0 ? dq : __dadd_rn(dq, predict_w<true>(L, m, m2));
         sty(L.yb, m.x & 0xffffu, v);
@@ -199,23 +279,55 @@ __device__ __forceinline__ double recompose_w(const GridDev& G, const WaveLds& L
       wave_sync();
     }
   }
+  if constexpr (SH::fixed) {
+    slots_fixed<SH, 1, STORE_ALL>(L, rm, dqf, acc);
+  } else {
 #pragma unroll
-  for (int s = 1; s < NS; ++s) {
-    if (s < G.nslots) {
-      const uint2 m = L.m01[s * 64 + lane];
-      const uint32_t m2 = L.m2[s * 64 + lane];
-      const double dq = dqf(s);
-      const double v = __dadd_rn(dq, bit(sm.bil, s) ? predict_w<true>(L, m, m2) : predict_w<false>(L, m, m2));
-      if (STORE_ALL || bit(sm.keep, s)) sty(L.yb, m.x & 0xffffu, v);
-      const double e = rm[s] - v;
-      acc = fma(e, e, acc);
-      if (bit(sm.sync, s)) wave_sync();
+    for (int s = 1; s < NS; ++s) {
+      if (s < G.nslots) {
+        const uint2 m = L.m01[s * 64 + lane];
+        const uint32_t m2 = L.m2[s * 64 + lane];
+        const double dq = dqf(s);
+        const double v = __dadd_rn(dq, bit(sm.bil, s) ? predict_w<true>(L, m, m2) : predict_w<false>(L, m, m2));
+        if (STORE_ALL || bit(sm.keep, s)) sty(L.yb, m.x & 0xffffu, v);
+        const double e = rm[s] - v;
+        acc = fma(e, e, acc);
+        if (bit(sm.sync, s)) wave_sync();
+      }
     }
   }
   return wsum(acc);
 }
 
 // ---- column walks ---------------------------------------------------------------------
+
+constexpr int kRowChunk = 40;   // rows whose global loads a lane issues together
+
+// As for_columns, with load(i, j) issued for a chunk of rows before body(i, j, off, v)
+// runs on them, so a column costs one memory round trip per chunk.
+template <typename BEGIN, typename LOAD, typename BODY, typename FOLD>
+__device__ __forceinline__ void for_columns_pre(const GridDev& G, BEGIN begin, LOAD load, BODY body, FOLD fold) {
+  const int lane = threadIdx.x & 63;
+  const uint32_t rowb = (uint32_t)G.n_par * 8u;
+  using V = decltype(load(0, 0));
+  for (int i = lane; i < G.n_par; i += 64) {
+    begin(i);
+    uint32_t off = (uint32_t)i * 8u;
+    for (int j0 = 0; j0 < G.n_perp; j0 += kRowChunk) {
+      V v[kRowChunk];
+#pragma unroll
+      for (int k = 0; k < kRowChunk; ++k)
+        if (j0 + k < G.n_perp) v[k] = load(i, j0 + k);
+#pragma unroll
+      for (int k = 0; k < kRowChunk; ++k)
+        if (j0 + k < G.n_perp) {
+          body(i, j0 + k, off, v[k]);
+          off += rowb;
+        }
+    }
+    fold(i);
+  }
+}
 
 // Lane l visits columns i = l, l + 64 (< n_par): begin(i), then body(i, j, off) for every
 // row j, off the byte offset of (j, i) in the wave buffer, then fold(i).
@@ -471,8 +583,9 @@ __device__ __forceinline__ int newton_w(const GridDev& G, const WaveLds& L, cons
 
 // ---- compression ------------------------------------------------------------------------
 
-template <typename TIn, bool UVOL, int NS>
+template <typename TIn, bool UVOL, class SH>
 __global__ __launch_bounds__(256, 2) void k_residual_w(GridDev G, ResidualArgs a) {
+  constexpr int NS = SH::NS;
   extern __shared__ double smem[];
   __shared__ uint32_t s_gmax[kWPB][kMaxLev], s_width[kWPB][kMaxLev], s_base[kWPB][kMaxLev];
   __shared__ int s_gstart[kMaxLev + 1];
@@ -495,9 +608,16 @@ __global__ __launch_bounds__(256, 2) void k_residual_w(GridDev G, ResidualArgs a
   bool bad = false;
   {
     double sf = 0.0, sfc = 0.0;
-    auto body = [&](int i, int j, uint32_t off) {
-      const double fv = (double)f[(long long)j * a.rs + i];
-      const double hv = fhp ? (double)fhp[j * G.n_par + i] : 0.0;
+    struct FH {
+      TIn f;
+      float h;
+    };
+    auto load = [&](int i, int j) {
+      return FH{f[(long long)j * a.rs + i], fhp ? fhp[j * G.n_par + i] : 0.0f};
+    };
+    auto body = [&](int i, int j, uint32_t off, FH ld) {
+      const double fv = (double)ld.f;
+      const double hv = (double)ld.h;
       const double r = fv - hv;
       sty(L.yb, off, r);
       // ||f||^2 in double-double: the products are rounded as in a plain FP64 sum of
@@ -522,7 +642,7 @@ __global__ __launch_bounds__(256, 2) void k_residual_w(GridDev G, ResidualArgs a
       m2 += sfc;
       m3 = fma(av * av, sf, m3);
     };
-    for_columns(G, [&](int) { sf = sfc = 0.0; }, body, fold);
+    for_columns_pre(G, [&](int) { sf = sfc = 0.0; }, load, body, fold);
   }
   {
     const double hi = ff.hi + ff.lo;
@@ -551,10 +671,10 @@ __global__ __launch_bounds__(256, 2) void k_residual_w(GridDev G, ResidualArgs a
   uint32_t rec_bytes = 0;
   // ft = fhat + rhat (rhat = 0 when not coded), written over the buffer in natural order
   auto load_ft = [&](bool with_r) {
-    for_columns(
-        G, [](int) {},
-        [&](int i, int j, uint32_t off) {
-          const double hv = fhp ? (double)fhp[j * G.n_par + i] : 0.0;
+    for_columns_pre(
+        G, [](int) {}, [&](int i, int j) { return fhp ? fhp[j * G.n_par + i] : 0.0f; },
+        [&](int, int, uint32_t off, float h) {
+          const double hv = (double)h;
           sty(L.yb, off, with_r ? hv + ldy(L.yb, off) : hv);
         },
         [](int) {});
@@ -576,11 +696,11 @@ __global__ __launch_bounds__(256, 2) void k_residual_w(GridDev G, ResidualArgs a
     for (int s = 1; s < NS; ++s) {
       dm[s] = 0.0;
       rm[s] = 0.0;
-      if (s < G.nslots) {
+      if (s < nslots_of<SH>(G)) {
         const uint2 m = L.m01[s * 64 + lane];
         const uint32_t mm2 = L.m2[s * 64 + lane];
         rm[s] = ldy(L.yb, m.x & 0xffffu);
-        dm[s] = __dsub_rn(rm[s], bit(G.slot_bil, s) ? predict_w<true>(L, m, mm2) : predict_w<false>(L, m, mm2));
+        dm[s] = __dsub_rn(rm[s], bil_of<SH>(G, s) ? predict_w<true>(L, m, mm2) : predict_w<false>(L, m, mm2));
         mx = fmax(mx, fabs(dm[s]));
       }
     }
@@ -594,7 +714,7 @@ __global__ __launch_bounds__(256, 2) void k_residual_w(GridDev G, ResidualArgs a
         const int mid = (lo + hi) >> 1;
         const double Dk = ladder(d0, mid);
         const double inv = 1.0 / Dk;
-        const double e2 = recompose_w<NS, false>(G, L, rm, [&](int s) { return qdelta(Dk, dm[s], inv); });
+        const double e2 = recompose_w<SH, false>(G, L, rm, [&](int s) { return qdelta(Dk, dm[s], inv); });
         if (e2 <= thr2) lo = mid;
         else hi = mid;
       }
@@ -615,7 +735,7 @@ __global__ __launch_bounds__(256, 2) void k_residual_w(GridDev G, ResidualArgs a
         const uint32_t mm2 = L.m2[lane];
         const int g0 = (int)(mm2 >> 28);
         const uint32_t u0 = zz(dm[0]);
-        for (int g = 0; g < G.ncoarse; ++g) {
+        for (int g = 0; g < ncoarse_of<SH>(G); ++g) {
           const uint32_t v = wumax(g0 == g ? u0 : 0u);
           if (lane == 0) s_gmax[wv][g] = max(s_gmax[wv][g], v);
         }
@@ -623,9 +743,9 @@ __global__ __launch_bounds__(256, 2) void k_residual_w(GridDev G, ResidualArgs a
       uint32_t cur = 0u;
 #pragma unroll
       for (int s = 1; s < NS; ++s) {
-        if (s < G.nslots) {
+        if (s < nslots_of<SH>(G)) {
           cur = max(cur, zz(dm[s]));          // padding lanes hold d = 0
-          if (bit(G.slot_sync, s)) {
+          if (sync_of<SH>(G, s)) {
             const uint32_t v = wumax(cur);
             if (lane == 0) {
               const int g = s_sgroup[s];
@@ -648,7 +768,7 @@ __global__ __launch_bounds__(256, 2) void k_residual_w(GridDev G, ResidualArgs a
       wave_sync();
 #pragma unroll
       for (int s = 0; s < NS; ++s) {
-        if (s < G.nslots) {
+        if (s < nslots_of<SH>(G)) {
           const uint32_t eo = L.m01[s * 64 + lane].x & 0xffffu;
           const int g = s == 0 ? (int)(L.m2[lane] >> 28) : s_sgroup[s];
           if (eo != zero_off) {
@@ -684,7 +804,7 @@ __global__ __launch_bounds__(256, 2) void k_residual_w(GridDev G, ResidualArgs a
       wave_sync();
       if (lane == 0) sty(L.yb, zero_off, 0.0);     // the words may have reached the zero cell
       wave_sync();
-      recompose_w<NS, true>(G, L, rm, [&](int s) { return qdelta(Dk, dm[s], inv); });
+      recompose_w<SH, true>(G, L, rm, [&](int s) { return qdelta(Dk, dm[s], inv); });
       wave_sync();
       load_ft(true);                                          // ft = fhat + rhat
       ft_ready = true;
@@ -737,8 +857,9 @@ __global__ __launch_bounds__(256, 2) void k_residual_w(GridDev G, ResidualArgs a
 
 __device__ __forceinline__ uint32_t ld32w(const uint8_t* p) { return *(const uint32_t*)p; }
 
-template <typename TIn, typename TOut, bool UVOL, int NS>
+template <typename TIn, typename TOut, bool UVOL, class SH>
 __global__ __launch_bounds__(256, 2) void k_decompress_w(GridDev G, DecompressArgs a) {
+  constexpr int NS = SH::NS;
   extern __shared__ double smem[];
   __shared__ uint32_t s_width[kWPB][kMaxLev], s_base[kWPB][kMaxLev];
   __shared__ int s_gstart[kMaxLev + 1];
@@ -795,7 +916,7 @@ __global__ __launch_bounds__(256, 2) void k_decompress_w(GridDev G, DecompressAr
     for (int s = 0; s < NS; ++s) {
       dq[s] = 0.0;
       rm[s] = 0.0;
-      if (s < G.nslots) {
+      if (s < nslots_of<SH>(G)) {
         const uint32_t eo = L.m01[s * 64 + lane].x & 0xffffu;
         const int g = s == 0 ? (int)(L.m2[lane] >> 28) : s_sgroup[s];
         if (eo != zero_off) {
@@ -814,20 +935,21 @@ __global__ __launch_bounds__(256, 2) void k_decompress_w(GridDev G, DecompressAr
         }
       }
     }
-    recompose_w<NS, true>(G, L, rm, [&](int s) { return dq[s]; });
+    recompose_w<SH, true>(G, L, rm, [&](int s) { return dq[s]; });
   }
   double lam[4];
 #pragma unroll
   for (int k = 0; k < 4; ++k) lam[k] = a.lambda[h * 4 + k];
   double pa = 0.0;
-  for_columns(
+  for_columns_pre(
       G,
       [&](int i) {
         const double av = G.apar[i];
         pa = fma(fma(lam[3], av, lam[1]), av, lam[0]);
       },
-      [&](int i, int j, uint32_t off) {
-        const double hv = fhp ? (double)fhp[j * G.n_par + i] : 0.0;
+      [&](int i, int j) { return fhp ? fhp[j * G.n_par + i] : 0.0f; },
+      [&](int i, int j, uint32_t off, float h) {
+        const double hv = (double)h;
         const double ft = coded ? hv + ldy(L.yb, off) : hv;
         const double w = UVOL ? G.vol0 : G.vol[j * G.n_par + i];
         out[j * G.n_par + i] = (TOut)fmax(0.0, ft - w * fma(lam[2], L.s_cc[2 * j], pa));
@@ -838,17 +960,23 @@ __global__ __launch_bounds__(256, 2) void k_decompress_w(GridDev G, DecompressAr
 // ---- launchers ----------------------------------------------------------------------------
 
 bool wave_path(const GridDev& G) { return G.nslots > 0 && G.nslots <= kWaveSlots; }
+bool wave_fixed_path(const GridDev& G) { return wave_path(G) && G.uniform_vol && shape_matches<Shape39>(G); }
 
 hipError_t launch_residual_w(const GridDev& G, const ResidualArgs& a, hipStream_t st) {
   if (a.H <= 0) return hipSuccess;
   dim3 grid((unsigned)((a.H + kWPB - 1) / kWPB)), block(64 * kWPB);
   const size_t lds = lds_bytes_w(G);
-#define HCZ_RW(T, U) hipLaunchKernelGGL((k_residual_w<T, U, kWaveSlots>), grid, block, lds, st, G, a)
-  if (a.dtype == HCZ_F32) {
-    if (G.uniform_vol) HCZ_RW(float, true); else HCZ_RW(float, false);
-  } else {
-    if (G.uniform_vol) HCZ_RW(double, true); else HCZ_RW(double, false);
-  }
+  const bool s39 = wave_fixed_path(G);
+#define HCZ_RW(T, U, SH) hipLaunchKernelGGL((k_residual_w<T, U, SH>), grid, block, lds, st, G, a)
+#define HCZ_RW2(T)                                     \
+  do {                                                  \
+    if (s39) HCZ_RW(T, true, Shape39);                  \
+    else if (G.uniform_vol) HCZ_RW(T, true, ShapeDyn);  \
+    else HCZ_RW(T, false, ShapeDyn);                    \
+  } while (0)
+  if (a.dtype == HCZ_F32) HCZ_RW2(float);
+  else HCZ_RW2(double);
+#undef HCZ_RW2
 #undef HCZ_RW
   return hipGetLastError();
 }
@@ -857,8 +985,14 @@ hipError_t launch_decompress_w(const GridDev& G, const DecompressArgs& a, hipStr
   if (a.H <= 0) return hipSuccess;
   dim3 grid((unsigned)((a.H + kWPB - 1) / kWPB)), block(64 * kWPB);
   const size_t lds = lds_bytes_w(G);
-#define HCZ_DW(TI, TO, U) hipLaunchKernelGGL((k_decompress_w<TI, TO, U, kWaveSlots>), grid, block, lds, st, G, a)
-#define HCZ_DW2(TI, TO) do { if (G.uniform_vol) HCZ_DW(TI, TO, true); else HCZ_DW(TI, TO, false); } while (0)
+  const bool s39 = wave_fixed_path(G);
+#define HCZ_DW(TI, TO, U, SH) hipLaunchKernelGGL((k_decompress_w<TI, TO, U, SH>), grid, block, lds, st, G, a)
+#define HCZ_DW2(TI, TO)                                       \
+  do {                                                         \
+    if (s39) HCZ_DW(TI, TO, true, Shape39);                    \
+    else if (G.uniform_vol) HCZ_DW(TI, TO, true, ShapeDyn);    \
+    else HCZ_DW(TI, TO, false, ShapeDyn);                      \
+  } while (0)
   if (a.in_dtype == HCZ_F32) {
     if (a.out_dtype == HCZ_F64) HCZ_DW2(float, double); else HCZ_DW2(float, float);
   } else {

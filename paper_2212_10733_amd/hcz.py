@@ -114,6 +114,7 @@ def _load() -> C.CDLL:
         "hcz_adam_step": [vp, vp, vp, vp, i64, C.c_double, C.c_double, C.c_double, C.c_double, i64, vp],
         "hcz_norm_stats_workspace": [vp, i64, C.POINTER(sz)],
         "hcz_norm_stats": [vp, vp, i32, i64, i64, i64, vp, vp, vp, sz, vp],
+        "hcz_plan_path": [vp, C.POINTER(i32)],
         "hcz_profile_enable": [vp, C.c_int],
         "hcz_profile_read": [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)],
     }
@@ -133,7 +134,7 @@ LIB = _load()
 
 # Every symbol the C header declares (checked by the CPU tests).
 EXPORTS = ["hcz_create", "hcz_destroy", "hcz_last_error", "hcz_version", "hcz_plan_create",
-           "hcz_plan_destroy", "hcz_model_load", "hcz_model_free", "hcz_qoi", "hcz_encode",
+           "hcz_plan_destroy", "hcz_plan_path", "hcz_model_load", "hcz_model_free", "hcz_qoi", "hcz_encode",
            "hcz_codebook_fit_workspace", "hcz_codebook_fit", "hcz_quantize", "hcz_decode",
            "hcz_residual", "hcz_compress_workspace", "hcz_decompress_workspace", "hcz_compress",
            "hcz_decompress", "hcz_stats_read", "hcz_profile_enable", "hcz_profile_read",
@@ -212,6 +213,15 @@ class Plan:
         h = C.c_void_p()
         _check(LIB.hcz_plan_create(ctx.h, C.byref(g), C.byref(h)))
         self.h = h
+
+    PATHS = {0: "block", 1: "wave", 2: "wave_fixed"}
+
+    @property
+    def path(self) -> str:
+        """Kernel family serving this grid: 'block', 'wave' or 'wave_fixed'."""
+        v = C.c_int32()
+        _check(LIB.hcz_plan_path(self.h, C.byref(v)))
+        return self.PATHS[v.value]
 
     def __del__(self):
         if getattr(self, "h", None):

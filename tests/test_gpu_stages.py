@@ -248,8 +248,20 @@ def test_residual_bit_exact_with_reconstruction(H, ctx, dtype, Hn):
     assert 0 < coded.sum() < Hn                  # both kinds present
 
 
-@pytest.mark.parametrize("shape,vol", [((39, 39), None), ((33, 33), None), ((49, 49), "jacobian"),
-                                       ((65, 65), None), ((37, 33), None), ((3, 3), None), ((12, 5), None)])
+def test_plan_paths(H, ctx):
+    """Which kernel family serves a grid; every path is checked bit-exact below."""
+    say("plan paths")
+    cases = [((39, 39), None, "wave_fixed"), ((39, 39), "jacobian", "wave"), ((33, 37), None, "wave"),
+             ((3, 3), None, "wave"), ((65, 65), None, "block"), ((49, 49), "jacobian", "block")]
+    for (n_perp, n_par), vol, want in cases:
+        g = grid.make_grid(n_par, n_perp, vol=vol)
+        plan = H.Plan(ctx, n_par, n_perp, vol=None if vol is None else g.vol)
+        assert plan.path == want, ((n_perp, n_par), vol, plan.path)
+
+
+@pytest.mark.parametrize("shape,vol", [((39, 39), None), ((39, 39), "jacobian"), ((33, 33), None),
+                                       ((49, 49), "jacobian"), ((65, 65), None), ((37, 33), None), ((3, 3), None),
+                                       ((12, 5), None)])
 @pytest.mark.parametrize("tau", [1e-2, 1e-4])
 def test_residual_coder_only_grids(H, ctx, shape, vol, tau):
     n_perp, n_par = shape
