@@ -202,7 +202,8 @@ bool in_set(int n, int l, int i) { return i == n - 1 || (i % (1 << l)) == 0; }
 // linear nodes take a degenerate form with the same bits as the linear one (a row node
 // repeats its two corners with t = 0, a column node doubles each of its two corners with
 // s = 0).  Padding lanes point every offset at the zero cell, with wtab[0] = 0 and
-// group 15.  The packing position of each entry is kept apart (slot_pos).
+// group 15.  The packing position of each entry is kept apart (its rank within the
+// group goes to the device as slot_rank).
 struct SlotTables {
   int nslots = 0, ncoarse = 0;
   std::vector<uint32_t> meta;
@@ -522,6 +523,12 @@ hcz_status hcz_plan_create(hcz_ctx* ctx, const hcz_grid* g, hcz_plan** out) {
   G.nslots = slots.nslots;
   G.ncoarse = slots.ncoarse;
   G.nw = (int)slots.wtab.size();
+  // packing rank of each entry within its group (0 for padding lanes)
+  std::vector<uint16_t> rank(slots.pos.size(), 0);
+  for (size_t k = 0; k < rank.size(); ++k) {
+    const uint32_t w0 = slots.meta[3 * k], w2 = slots.meta[3 * k + 2];
+    if ((w0 & 0xffffu) != (uint32_t)N * 8u) rank[k] = (uint16_t)(slots.pos[k] - gstart[w2 >> 28]);
+  }
   for (int k = 0; k < kWaveSlots; ++k) G.slot_group[k] = k < slots.nslots ? slots.group[k] : 0;
   G.slot_bil = slots.bil;
   G.slot_sync = slots.sync;
@@ -532,7 +539,7 @@ hcz_status hcz_plan_create(hcz_ctx* ctx, const hcz_grid* g, hcz_plan** out) {
       (s = upload(P->allocs, dp.b, &G.b_par)) || (s = upload(P->allocs, dp.s, &G.s_par)) ||
       (s = upload(P->allocs, dq.lev, &G.lev_perp)) || (s = upload(P->allocs, dq.a, &G.a_perp)) ||
       (s = upload(P->allocs, dq.b, &G.b_perp)) || (s = upload(P->allocs, dq.s, &G.s_perp)) ||
-      (s = upload(P->allocs, slots.meta, &G.slot_meta)) || (s = upload(P->allocs, slots.pos, &G.slot_pos)) ||
+      (s = upload(P->allocs, slots.meta, &G.slot_meta)) || (s = upload(P->allocs, rank, &G.slot_rank)) ||
       (s = upload(P->allocs, slots.wtab, &G.wtab))) {
     free_all(P->allocs);
     delete P;

@@ -57,7 +57,7 @@ struct GridDev {
   uint32_t slot_sync;                // bit s: the next slot belongs to a later group
   uint32_t slot_keep;                // bit s: later groups read slot s (not the finest group)
   const uint32_t* slot_meta;         // [nslots * 64][3], see make_slots()
-  const uint16_t* slot_pos;          // [nslots * 64] packing position of each entry
+  const uint16_t* slot_rank;         // [nslots * 64] packing rank of each entry within its group
   const double* wtab;                // [nw] distinct interpolation weights, wtab[0] = 0
 };
 

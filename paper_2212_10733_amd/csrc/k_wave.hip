@@ -105,10 +105,10 @@ __device__ __forceinline__ dd wdd(dd v) {
 // ---- tables and layout -----------------------------------------------------------------
 
 // Dynamic LDS, in doubles: s_w [64] interpolation weights, s_cc [2 kMaxDim] (c_j, c_j^2)
-// pairs, then the slot entries as nslots * 64 uint2 (words 0-1) followed by nslots * 64
-// uint32 (word 2), then one (N + 1)-double buffer per wave.
+// pairs, then the slot entries as nslots * 64 uint2 (words 0-1), nslots * 64 uint32
+// (word 2) and nslots * 64 uint16 packing ranks, then one (N + 1)-double buffer per wave.
 constexpr int kLdsTables = 64 + 2 * kMaxDim;
-__host__ __device__ __forceinline__ size_t lds_meta_doubles(int nslots) { return (size_t)nslots * 96; }
+__host__ __device__ __forceinline__ size_t lds_meta_doubles(int nslots) { return (size_t)nslots * 112; }
 __host__ __device__ __forceinline__ size_t lds_bytes_w(const GridDev& G) {
   return (kLdsTables + lds_meta_doubles(G.nslots) + (size_t)(G.N + 1) * kWPB) * sizeof(double);
 }
@@ -118,6 +118,7 @@ struct WaveLds {
   double* s_cc;
   const uint2* m01;
   const uint32_t* m2;
+  const uint16_t* rk;
   char* yb;          // this wave's buffer (byte addressed)
 };
 
@@ -127,6 +128,7 @@ __device__ __forceinline__ WaveLds setup_lds(const GridDev& G, double* smem, int
   L.s_cc = smem + 64;
   uint2* m01 = (uint2*)(smem + kLdsTables);
   uint32_t* m2 = (uint32_t*)(m01 + (size_t)G.nslots * 64);
+  uint16_t* rk = (uint16_t*)(m2 + (size_t)G.nslots * 64);
   const int t = threadIdx.x;
   for (int k = t; k < G.nw; k += 256) L.s_w[k] = G.wtab[k];
   for (int k = t; k < G.n_perp; k += 256) {
@@ -137,13 +139,45 @@ __device__ __forceinline__ WaveLds setup_lds(const GridDev& G, double* smem, int
   for (int k = t; k < G.nslots * 64; k += 256) {
     m01[k] = make_uint2(G.slot_meta[3 * k], G.slot_meta[3 * k + 1]);
     m2[k] = G.slot_meta[3 * k + 2];
+    rk[k] = G.slot_rank[k];
   }
   L.m01 = m01;
   L.m2 = m2;
+  L.rk = rk;
   double* y = smem + kLdsTables + lds_meta_doubles(G.nslots) + (size_t)(G.N + 1) * wv;
   if (t < 256) y[G.N] = 0.0;      // every wave's zero cell (lane 0 of each wave)
   L.yb = (char*)y;
   return L;
+}
+
+// A wave's copy of the slot entries in registers (read once from LDS).
+template <int NS>
+struct SlotRegs {
+  uint2 m[NS];
+  uint32_t m2[NS];
+};
+// Entry words hidden from loop-invariant code motion: otherwise every slot's decoded
+// addresses are hoisted out of the bisection loop and the registers spill.
+__device__ __forceinline__ uint2 opaque2(uint2 m) {
+  asm volatile("" : "+v"(m.x), "+v"(m.y));
+  return m;
+}
+__device__ __forceinline__ uint32_t opaque1(uint32_t m) {
+  asm volatile("" : "+v"(m));
+  return m;
+}
+template <class SH>
+__device__ __forceinline__ void load_slot_regs(const GridDev& G, const WaveLds& L, SlotRegs<SH::NS>& R) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int s = 0; s < SH::NS; ++s) {
+    R.m[s] = make_uint2(0u, 0u);
+    R.m2[s] = 0u;
+    if (SH::fixed || s < G.nslots) {
+      R.m[s] = L.m01[s * 64 + lane];
+      R.m2[s] = L.m2[s * 64 + lane];
+    }
+  }
 }
 
 __device__ __forceinline__ double ldy(const char* yb, uint32_t off) { return *(const double*)(yb + off); }
@@ -221,36 +255,36 @@ constexpr int batch_end(int s) {
 // Slots [S, E) of one group: every entry and corner read first, then values, stores
 // and errors.  Nothing in the batch reads what the batch writes.
 template <class SH, int S, int E, bool STORE_ALL, typename DQ>
-__device__ __forceinline__ void batch_fixed(const WaveLds& L, const double (&rm)[SH::NS], DQ& dqf, double& acc) {
-  const int lane = threadIdx.x & 63;
+__device__ __forceinline__ void batch_fixed(const WaveLds& L, const SlotRegs<SH::NS>& R, const double (&rm)[SH::NS],
+                                            DQ& dqf, double& acc) {
   constexpr int B = E - S;
+  double v[B], r[B];
   uint2 m[B];
-  uint32_t m2[B];
 #pragma unroll
   for (int k = 0; k < B; ++k) {
-    m[k] = L.m01[(S + k) * 64 + lane];
-    m2[k] = L.m2[(S + k) * 64 + lane];
+    m[k] = opaque2(R.m[S + k]);
+    const uint32_t m2 = opaque1(R.m2[S + k]);
+    v[k] = __dadd_rn(dqf(S + k), bit(SH::BIL, S + k) ? predict_w<true>(L, m[k], m2) : predict_w<false>(L, m[k], m2));
+    // a slot no later group reads keeps its residual in the buffer while the bisection
+    // runs, which saves its register copy
+    r[k] = bit(SH::KEEP, S + k) ? rm[S + k] : ldy(L.yb, m[k].x & 0xffffu);
   }
-  double v[B];
-#pragma unroll
-  for (int k = 0; k < B; ++k)
-    v[k] = __dadd_rn(dqf(S + k), bit(SH::BIL, S + k) ? predict_w<true>(L, m[k], m2[k])
-                                                      : predict_w<false>(L, m[k], m2[k]));
 #pragma unroll
   for (int k = 0; k < B; ++k) {
     if (STORE_ALL || bit(SH::KEEP, S + k)) sty(L.yb, m[k].x & 0xffffu, v[k]);
-    const double e = rm[S + k] - v[k];
+    const double e = r[k] - v[k];
     acc = fma(e, e, acc);
   }
 }
 
 template <class SH, int S, bool STORE_ALL, typename DQ>
-__device__ __forceinline__ void slots_fixed(const WaveLds& L, const double (&rm)[SH::NS], DQ& dqf, double& acc) {
+__device__ __forceinline__ void slots_fixed(const WaveLds& L, const SlotRegs<SH::NS>& R, const double (&rm)[SH::NS],
+                                            DQ& dqf, double& acc) {
   if constexpr (S < SH::NS) {
     constexpr int E = batch_end<SH>(S);
-    batch_fixed<SH, S, E, STORE_ALL>(L, rm, dqf, acc);
+    batch_fixed<SH, S, E, STORE_ALL>(L, R, rm, dqf, acc);
     if constexpr (((SH::SYNC >> (E - 1)) & 1u) != 0) wave_sync();
-    slots_fixed<SH, E, STORE_ALL>(L, rm, dqf, acc);
+    slots_fixed<SH, E, STORE_ALL>(L, R, rm, dqf, acc);
   }
 }
 
@@ -258,15 +292,14 @@ __device__ __forceinline__ void slots_fixed(const WaveLds& L, const double (&rm)
 // group only when STORE_ALL) and return sum (rm - y)^2 over the histogram.  DQ(s) gives
 // the lane's quantised coefficient of slot s.
 template <class SH, bool STORE_ALL, typename DQ>
-__device__ __forceinline__ double recompose_w(const GridDev& G, const WaveLds& L, const double (&rm)[SH::NS],
-                                              DQ dqf) {
+__device__ __forceinline__ double recompose_w(const GridDev& G, const WaveLds& L, const SlotRegs<SH::NS>& R,
+                                              const double (&rm)[SH::NS], DQ dqf) {
   constexpr int NS = SH::NS;
-  const int lane = threadIdx.x & 63;
   const SlotMasks sm = slot_masks(G);
   double acc = 0.0;
   {
-    const uint2 m = L.m01[lane];
-    const uint32_t m2 = L.m2[lane];
+    const uint2 m = opaque2(R.m[0]);
+    const uint32_t m2 = opaque1(R.m2[0]);
     const int g0 = (int)(m2 >> 28);
     const double dq = dqf(0);
     for (int g = 0; g < ncoarse_of<SH>(G); ++g) {
@@ -280,13 +313,13 @@ __device__ __forceinline__ double recompose_w(const GridDev& G, const WaveLds& L
     }
   }
   if constexpr (SH::fixed) {
-    slots_fixed<SH, 1, STORE_ALL>(L, rm, dqf, acc);
+    slots_fixed<SH, 1, STORE_ALL>(L, R, rm, dqf, acc);
   } else {
 #pragma unroll
     for (int s = 1; s < NS; ++s) {
       if (s < G.nslots) {
-        const uint2 m = L.m01[s * 64 + lane];
-        const uint32_t m2 = L.m2[s * 64 + lane];
+        const uint2 m = opaque2(R.m[s]);
+        const uint32_t m2 = opaque1(R.m2[s]);
         const double dq = dqf(s);
         const double v = __dadd_rn(dq, bit(sm.bil, s) ? predict_w<true>(L, m, m2) : predict_w<false>(L, m, m2));
         if (STORE_ALL || bit(sm.keep, s)) sty(L.yb, m.x & 0xffffu, v);
@@ -347,75 +380,132 @@ __device__ __forceinline__ void for_columns(const GridDev& G, BEGIN begin, BODY 
   }
 }
 
-// Newton statistics at lam (Section III Stage 5): v[0..3] = A x, v[4] = sum |A_1| x,
-// v[5..14] = A diag(x > 0) A^T (upper triangle, row-major), v[15] = ||x - ft||^2 when
-// THETA, x = max(0, ft - A^T lam) with ft in the wave buffer.  Per column, sums over the
-// rows of x, c x and (on active cells) w^2, w^2 c, w^2 c^2 are formed first, then
-// weighted by the column's powers of a.  The correction per cell is
+// Activity masks of a Newton pass: bit (j & 31) of word 4 cb + j / 32 says whether cell
+// (j, i = lane + 64 cb) has x > 0.  The Hessian depends on nothing else.
+constexpr int kColBlocks = (kMaxDim + 63) / 64, kRowWords = (kMaxDim + 31) / 32;
+constexpr int kMaskWords = kColBlocks * kRowWords;
+
+// One Newton pass at lam (Section III Stage 5): v[0..3] = A x, v[4] = sum |A_1| x and,
+// when THETA, v[15] = ||x - ft||^2, with x = max(0, ft - A^T lam) and ft in the wave
+// buffer; am gets the activity masks.  Per column the row sums of w x and c w x come
+// first and are then weighted by the column's powers of a.  The correction per cell is
 // vol * ((lam3 a + lam1) a + lam0 + lam2 c), one fixed order for compression and
 // decompression.
 template <bool UVOL, bool THETA>
-__device__ __forceinline__ void newton_stats_w(const GridDev& G, const WaveLds& L, const double (&lam)[4],
-                                               double (&v)[16]) {
+__device__ __forceinline__ void newton_pass_w(const GridDev& G, const WaveLds& L, const double (&lam)[4],
+                                              double (&v)[16], uint32_t (&am)[kMaskWords]) {
+  const int lane = threadIdx.x & 63;
+  double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0, v4 = 0.0, v15 = 0.0;
+  const uint32_t rowb = (uint32_t)G.n_par * 8u;
 #pragma unroll
-  for (int k = 0; k < 16; ++k) v[k] = 0.0;
-  double sx, sxc, h0, hc, hcc, s2;
-  double pa = 0.0;
-  auto begin = [&](int i) {
-    const double a = G.apar[i];
-    pa = fma(fma(lam[3], a, lam[1]), a, lam[0]);
-    sx = sxc = h0 = hc = hcc = s2 = 0.0;
-  };
-  auto body = [&](int i, int j, uint32_t off) {
-    const double c = L.s_cc[2 * j], c2 = L.s_cc[2 * j + 1];
-    const double w = UVOL ? G.vol0 : G.vol[j * G.n_par + i];
-    const double ft = ldy(L.yb, off);
-    const double x = fmax(0.0, ft - w * fma(lam[2], c, pa));
-    const double wx = UVOL ? x : w * x;
-    sx += wx;
-    sxc = fma(c, wx, sxc);
-    if (x > 0.0) {
-      const double w2 = UVOL ? 1.0 : w * w;
-      h0 += w2;
-      hc = fma(w2, c, hc);
-      hcc = fma(w2, c2, hcc);
+  for (int cb = 0; cb < kColBlocks; ++cb) {
+    const int i = lane + 64 * cb;
+    const bool col = i < G.n_par;
+    const double a = col ? G.apar[i] : 0.0;
+    const double pa = fma(fma(lam[3], a, lam[1]), a, lam[0]);
+    double sx = 0.0, sxc = 0.0, s2 = 0.0;
+    uint32_t off = (uint32_t)i * 8u;
+#pragma unroll
+    for (int jw = 0; jw < kRowWords; ++jw) {
+      uint32_t bits = 0;
+      if (64 * cb < G.n_par && 32 * jw < G.n_perp) {
+        const int jend = min(32, G.n_perp - 32 * jw);
+        if (col) {
+#pragma unroll 4
+          for (int jj = 0; jj < jend; ++jj) {
+            const int j = 32 * jw + jj;
+            const double c = L.s_cc[2 * j];
+            const double w = UVOL ? G.vol0 : G.vol[j * G.n_par + i];
+            const double ft = ldy(L.yb, off);
+            const double x = fmax(0.0, ft - w * fma(lam[2], c, pa));
+            const double wx = UVOL ? x : w * x;
+            sx += wx;
+            sxc = fma(c, wx, sxc);
+            bits |= (x > 0.0 ? 1u : 0u) << jj;
+            if (THETA) {
+              const double dx = x - ft;
+              s2 = fma(dx, dx, s2);
+            }
+            off += rowb;
+          }
+        }
+      }
+      am[cb * kRowWords + jw] = bits;
     }
-    if (THETA) {
-      const double dx = x - ft;
-      s2 = fma(dx, dx, s2);
-    }
-  };
-  auto fold = [&](int i) {
-    const double a = G.apar[i], a2 = a * a;
-    v[0] += sx;
-    v[1] = fma(a, sx, v[1]);
-    v[2] += sxc;
-    v[3] = fma(a2, sx, v[3]);
-    v[4] = fma(fabs(a), sx, v[4]);
-    v[5] += h0;
-    v[6] = fma(a, h0, v[6]);
-    v[7] += hc;
-    v[8] = fma(a2, h0, v[8]);
-    v[10] = fma(a, hc, v[10]);
-    v[11] = fma(a2 * a, h0, v[11]);
-    v[12] += hcc;
-    v[13] = fma(a2, hc, v[13]);
-    v[14] = fma(a2 * a2, h0, v[14]);
-    v[15] += s2;
-  };
-  for_columns(G, begin, body, fold);
-#pragma unroll
-  for (int k = 0; k < 15; ++k)
-    if (k != 9) v[k] = wsum(v[k]);
-  v[9] = v[8];
-  v[15] = THETA ? wsum(v[15]) : 0.0;
-  if (UVOL) {
-    const double s1 = G.vol0, s2v = G.vol0 * G.vol0;
-#pragma unroll
-    for (int k = 0; k < 5; ++k) v[k] *= s1;
-#pragma unroll
-    for (int k = 5; k < 15; ++k) v[k] *= s2v;
+    v0 += sx;
+    v1 = fma(a, sx, v1);
+    v2 += sxc;
+    v3 = fma(a * a, sx, v3);
+    v4 = fma(fabs(a), sx, v4);
+    v15 += s2;
   }
+  v[0] = wsum(v0);
+  v[1] = wsum(v1);
+  v[2] = wsum(v2);
+  v[3] = wsum(v3);
+  v[4] = wsum(v4);
+  v[15] = THETA ? wsum(v15) : 0.0;
+  if (UVOL) {
+#pragma unroll
+    for (int k = 0; k < 5; ++k) v[k] *= G.vol0;
+  }
+}
+
+// Newton Hessian A diag(x > 0) A^T from the activity masks into v[5..14] (upper
+// triangle, row-major): per column the row sums of w^2, w^2 c and w^2 c^2 over active
+// cells, then the column's powers of a.
+template <bool UVOL>
+__device__ __forceinline__ void newton_hess_w(const GridDev& G, const WaveLds& L, const uint32_t (&am)[kMaskWords],
+                                              double (&v)[16]) {
+  const int lane = threadIdx.x & 63;
+  double h[10];
+#pragma unroll
+  for (int k = 0; k < 10; ++k) h[k] = 0.0;
+#pragma unroll
+  for (int cb = 0; cb < kColBlocks; ++cb) {
+    const int i = lane + 64 * cb;
+    const bool col = i < G.n_par;
+    const double a = col ? G.apar[i] : 0.0, a2 = a * a;
+    double h0 = 0.0, hc = 0.0, hcc = 0.0;
+#pragma unroll
+    for (int jw = 0; jw < kRowWords; ++jw) {
+      const uint32_t bits = am[cb * kRowWords + jw];
+      if (64 * cb < G.n_par && 32 * jw < G.n_perp && col) {
+        const int jend = min(32, G.n_perp - 32 * jw);
+        if (UVOL) h0 += (double)__popc(bits);
+#pragma unroll 4
+        for (int jj = 0; jj < jend; ++jj) {
+          if ((bits >> jj) & 1u) {
+            const int j = 32 * jw + jj;
+            const double c = L.s_cc[2 * j], c2 = L.s_cc[2 * j + 1];
+            if (UVOL) {
+              hc += c;
+              hcc += c2;
+            } else {
+              const double w = G.vol[j * G.n_par + i], w2 = w * w;
+              h0 += w2;
+              hc = fma(w2, c, hc);
+              hcc = fma(w2, c2, hcc);
+            }
+          }
+        }
+      }
+    }
+    h[0] += h0;
+    h[1] = fma(a, h0, h[1]);
+    h[2] += hc;
+    h[3] = fma(a2, h0, h[3]);
+    h[5] = fma(a, hc, h[5]);
+    h[6] = fma(a2 * a, h0, h[6]);
+    h[7] += hcc;
+    h[8] = fma(a2, hc, h[8]);
+    h[9] = fma(a2 * a2, h0, h[9]);
+  }
+  const double s2v = UVOL ? G.vol0 * G.vol0 : 1.0;
+#pragma unroll
+  for (int k = 0; k < 10; ++k)
+    if (k != 4) v[5 + k] = wsum(h[k]) * s2v;
+  v[9] = v[8];
 }
 
 __device__ __forceinline__ double theta_w(const double (&v)[16], const double (&lam)[4], const double (&b)[4]) {
@@ -434,6 +524,7 @@ __device__ __forceinline__ bool chol4(const double (&v)[16], const double (&g)[4
   Hm[2][1] = Hm[1][2]; Hm[3][1] = Hm[1][3]; Hm[3][2] = Hm[2][3];
   const double tr = ((Hm[0][0] + Hm[1][1]) + Hm[2][2]) + Hm[3][3];
   double Lm[4][4] = {};
+  double rl[4];
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     double piv = Hm[k][k];
@@ -441,12 +532,13 @@ __device__ __forceinline__ bool chol4(const double (&v)[16], const double (&g)[4
     for (int q = 0; q < k; ++q) piv = piv - Lm[k][q] * Lm[k][q];
     if (!(piv > kPivTol * tr)) return false;
     Lm[k][k] = sqrt(piv);
+    rl[k] = 1.0 / Lm[k][k];
 #pragma unroll
     for (int i = k + 1; i < 4; ++i) {
       double s = Hm[i][k];
 #pragma unroll
       for (int q = 0; q < k; ++q) s = s - Lm[i][q] * Lm[k][q];
-      Lm[i][k] = s / Lm[k][k];
+      Lm[i][k] = s * rl[k];
     }
   }
   double y[4];
@@ -455,14 +547,14 @@ __device__ __forceinline__ bool chol4(const double (&v)[16], const double (&g)[4
     double s = g[i];
 #pragma unroll
     for (int q = 0; q < i; ++q) s = s - Lm[i][q] * y[q];
-    y[i] = s / Lm[i][i];
+    y[i] = s * rl[i];
   }
 #pragma unroll
   for (int i = 3; i >= 0; --i) {
     double s = y[i];
 #pragma unroll
     for (int q = i + 1; q < 4; ++q) s = s - Lm[q][i] * d[q];
-    d[i] = s / Lm[i][i];
+    d[i] = s * rl[i];
   }
   return true;
 }
@@ -497,9 +589,28 @@ __device__ __forceinline__ int newton_w(const GridDev& G, const WaveLds& L, cons
   double d[4] = {0.0, 0.0, 0.0, 0.0};
   double t0 = 0.0, gd = 0.0, step = 1.0;
   double v[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) v[k] = 0.0;
+  // the Hessian in v[5..14] belongs to the activity masks hm; it is rebuilt only when a
+  // step is taken from a pass whose masks differ
+  uint32_t am[kMaskWords], hm[kMaskWords];
+  bool have_h = false;
+#pragma unroll
+  for (int k = 0; k < kMaskWords; ++k) hm[k] = 0u;
+  auto hessian = [&]() {
+    bool same = have_h;
+#pragma unroll
+    for (int k = 0; k < kMaskWords; ++k) same = same && am[k] == hm[k];
+    if (__ballot(!same) != 0) {
+      newton_hess_w<UVOL>(G, L, am, v);
+#pragma unroll
+      for (int k = 0; k < kMaskWords; ++k) hm[k] = am[k];
+      have_h = true;
+    }
+  };
   for (;;) {
-    if (round == 1 && armijo2) newton_stats_w<UVOL, true>(G, L, cand, v);
-    else newton_stats_w<UVOL, false>(G, L, cand, v);
+    if (round == 1 && armijo2) newton_pass_w<UVOL, true>(G, L, cand, v, am);
+    else newton_pass_w<UVOL, false>(G, L, cand, v, am);
     if (trial) {
       if (theta_w(v, cand, b) >= t0 + kArmijoC * step * gd) {
 #pragma unroll
@@ -542,7 +653,11 @@ __device__ __forceinline__ int newton_w(const GridDev& G, const WaveLds& L, cons
     *upd = total;
     if (conv) return round;
     const int cap = round == 0 ? max1 : max2;
-    bool fail_round = it == cap || !chol4(v, g, d);
+    bool fail_round = it == cap;
+    if (!fail_round) {
+      hessian();
+      fail_round = !chol4(v, g, d);
+    }
     if (fail_round && warm && round == 0 && it == 0) {
       warm = false;                // no usable step at the warm start
       *rejected = true;
@@ -557,7 +672,9 @@ __device__ __forceinline__ int newton_w(const GridDev& G, const WaveLds& L, cons
 #pragma unroll
       for (int k = 0; k < 4; ++k) cand[k] = lam[k];
       if (armijo2) continue;     // round 2 needs theta at lam: one pass with it
-      if (it == max2 || !chol4(v, g, d)) break;
+      if (it == max2) break;
+      hessian();
+      if (!chol4(v, g, d)) break;
     }
     if (round == 1 && armijo2) {
       t0 = theta_w(v, lam, b);
@@ -683,11 +800,13 @@ __global__ __launch_bounds__(256, 2) void k_residual_w(GridDev G, ResidualArgs a
   bool ft_ready = false;
   if (coded && !raw) {
     // coefficients: d = r - P(r) over the residual itself (no node is rewritten here)
+    SlotRegs<NS> R;
+    load_slot_regs<SH>(G, L, R);
     double dm[NS], rm[NS];
     double mx = 0.0;
     {
-      const uint2 m = L.m01[lane];
-      const uint32_t mm2 = L.m2[lane];
+      const uint2 m = R.m[0];
+      const uint32_t mm2 = R.m2[0];
       rm[0] = ldy(L.yb, m.x & 0xffffu);
       dm[0] = (mm2 >> 28) == 0 ? rm[0] : __dsub_rn(rm[0], predict_w<true>(L, m, mm2));
       mx = fabs(dm[0]);
@@ -697,8 +816,8 @@ __global__ __launch_bounds__(256, 2) void k_residual_w(GridDev G, ResidualArgs a
       dm[s] = 0.0;
       rm[s] = 0.0;
       if (s < nslots_of<SH>(G)) {
-        const uint2 m = L.m01[s * 64 + lane];
-        const uint32_t mm2 = L.m2[s * 64 + lane];
+        const uint2 m = R.m[s];
+        const uint32_t mm2 = R.m2[s];
         rm[s] = ldy(L.yb, m.x & 0xffffu);
         dm[s] = __dsub_rn(rm[s], bil_of<SH>(G, s) ? predict_w<true>(L, m, mm2) : predict_w<false>(L, m, mm2));
         mx = fmax(mx, fabs(dm[s]));
@@ -714,7 +833,7 @@ __global__ __launch_bounds__(256, 2) void k_residual_w(GridDev G, ResidualArgs a
         const int mid = (lo + hi) >> 1;
         const double Dk = ladder(d0, mid);
         const double inv = 1.0 / Dk;
-        const double e2 = recompose_w<SH, false>(G, L, rm, [&](int s) { return qdelta(Dk, dm[s], inv); });
+        const double e2 = recompose_w<SH, false>(G, L, R, rm, [&](int s) { return qdelta(Dk, dm[s], inv); });
         if (e2 <= thr2) lo = mid;
         else hi = mid;
       }
@@ -732,7 +851,7 @@ __global__ __launch_bounds__(256, 2) void k_residual_w(GridDev G, ResidualArgs a
       const uint32_t zero_off = (uint32_t)N * 8u;
       // slot 0 may mix groups: reduce each of its groups separately
       {
-        const uint32_t mm2 = L.m2[lane];
+        const uint32_t mm2 = R.m2[0];
         const int g0 = (int)(mm2 >> 28);
         const uint32_t u0 = zz(dm[0]);
         for (int g = 0; g < ncoarse_of<SH>(G); ++g) {
@@ -769,13 +888,12 @@ __global__ __launch_bounds__(256, 2) void k_residual_w(GridDev G, ResidualArgs a
 #pragma unroll
       for (int s = 0; s < NS; ++s) {
         if (s < nslots_of<SH>(G)) {
-          const uint32_t eo = L.m01[s * 64 + lane].x & 0xffffu;
-          const int g = s == 0 ? (int)(L.m2[lane] >> 28) : s_sgroup[s];
+          const uint32_t eo = R.m[s].x & 0xffffu;
+          const int g = s == 0 ? (int)(R.m2[0] >> 28) : s_sgroup[s];
           if (eo != zero_off) {
             const uint32_t wdt = s_width[wv][g];
             if (wdt != 0) {
-              const int p = G.slot_pos[(size_t)s * 64 + lane];
-              const uint32_t pos = s_base[wv][g] + (uint32_t)(p - s_gstart[g]) * wdt;
+              const uint32_t pos = s_base[wv][g] + (uint32_t)L.rk[s * 64 + lane] * wdt;
               const uint64_t v = (uint64_t)zz(dm[s]) << (pos & 31u);
               atomicOr(&words[pos >> 5], (uint32_t)v);
               if ((pos & 31u) + wdt > 32u) atomicOr(&words[(pos >> 5) + 1], (uint32_t)(v >> 32));
@@ -804,9 +922,31 @@ __global__ __launch_bounds__(256, 2) void k_residual_w(GridDev G, ResidualArgs a
       wave_sync();
       if (lane == 0) sty(L.yb, zero_off, 0.0);     // the words may have reached the zero cell
       wave_sync();
-      recompose_w<SH, true>(G, L, rm, [&](int s) { return qdelta(Dk, dm[s], inv); });
+      // fhat for ft = fhat + rhat: issued before the last recomposition so that its
+      // latency hides behind it (one column per lane when the grid allows)
+      const bool pre = G.n_par <= 64 && G.n_perp <= kRowChunk;
+      float fh[kRowChunk];
+      if (pre) {
+#pragma unroll
+        for (int k = 0; k < kRowChunk; ++k)
+          fh[k] = (fhp && lane < G.n_par && k < G.n_perp) ? fhp[k * G.n_par + lane] : 0.0f;
+      }
+      recompose_w<SH, true>(G, L, R, rm, [&](int s) { return qdelta(Dk, dm[s], inv); });   // rhat at k*
       wave_sync();
-      load_ft(true);                                          // ft = fhat + rhat
+      if (pre) {
+        if (lane < G.n_par) {
+#pragma unroll
+          for (int k = 0; k < kRowChunk; ++k) {
+            if (k < G.n_perp) {
+              const uint32_t off = (uint32_t)(k * G.n_par + lane) * 8u;
+              sty(L.yb, off, (double)fh[k] + ldy(L.yb, off));
+            }
+          }
+        }
+        wave_sync();
+      } else {
+        load_ft(true);                                        // ft = fhat + rhat
+      }
       ft_ready = true;
     }
   }
@@ -911,20 +1051,21 @@ __global__ __launch_bounds__(256, 2) void k_decompress_w(GridDev G, DecompressAr
     wave_sync();
     const uint8_t* payload = rec + G.hdr_bytes;
     const uint32_t zero_off = (uint32_t)N * 8u;
+    SlotRegs<NS> R;
+    load_slot_regs<SH>(G, L, R);
     double dq[NS], rm[NS];
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
       dq[s] = 0.0;
       rm[s] = 0.0;
       if (s < nslots_of<SH>(G)) {
-        const uint32_t eo = L.m01[s * 64 + lane].x & 0xffffu;
-        const int g = s == 0 ? (int)(L.m2[lane] >> 28) : s_sgroup[s];
+        const uint32_t eo = R.m[s].x & 0xffffu;
+        const int g = s == 0 ? (int)(R.m2[0] >> 28) : s_sgroup[s];
         if (eo != zero_off) {
           const uint32_t wdt = s_width[wv][g];
           uint32_t u = 0;
           if (wdt) {
-            const int p = G.slot_pos[(size_t)s * 64 + lane];
-            const uint32_t pos = s_base[wv][g] + (uint32_t)(p - s_gstart[g]) * wdt;
+            const uint32_t pos = s_base[wv][g] + (uint32_t)L.rk[s * 64 + lane] * wdt;
             const uint32_t wi = pos >> 5, sh = pos & 31u;
             uint64_t v = ld32w(payload + 4 * wi);
             if (sh + wdt > 32u) v |= (uint64_t)ld32w(payload + 4 * (wi + 1)) << 32;
@@ -935,7 +1076,7 @@ __global__ __launch_bounds__(256, 2) void k_decompress_w(GridDev G, DecompressAr
         }
       }
     }
-    recompose_w<SH, true>(G, L, rm, [&](int s) { return dq[s]; });
+    recompose_w<SH, true>(G, L, R, rm, [&](int s) { return dq[s]; });
   }
   double lam[4];
 #pragma unroll
