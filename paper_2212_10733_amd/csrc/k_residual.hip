@@ -523,6 +523,7 @@ __global__ __launch_bounds__(NT) void k_decompress(GridDev G, DecompressArgs a) 
   const int N = G.N;
   double* buf = smem;
   __shared__ uint32_t s_width[kMaxLev], s_base[kMaxLev];
+  __shared__ int s_corrupt;
   const int t = threadIdx.x;
   const long long h = blockIdx.x;
   const int fl = a.flags[h];
@@ -557,12 +558,21 @@ __global__ __launch_bounds__(NT) void k_decompress(GridDev G, DecompressArgs a) 
     __syncthreads();
     if (t == 0) {
       uint32_t nb = 0;
+      bool corrupt = false;
       for (int g = 0; g < G.nlev; ++g) {
         s_base[g] = nb;
         nb += (uint32_t)(G.gstart[g + 1] - G.gstart[g]) * s_width[g];
+        corrupt = corrupt || s_width[g] > 32u;
       }
+      // a header that does not fit its record decodes to NaN rather than reading past it
+      s_corrupt = corrupt || (uint64_t)G.hdr_bytes + 4ull * (((uint64_t)nb + 31u) >> 5) >
+                                 a.offsets[h + 1] - a.offsets[h];
     }
     __syncthreads();
+    if (s_corrupt) {
+      for (int e = t; e < N; e += NT) out[e] = (TOut)NAN;
+      return;
+    }
   }
   const uint8_t* payload = rec + G.hdr_bytes;
   double lam[4];

@@ -238,6 +238,19 @@ template <class SH> __device__ __forceinline__ bool bil_of(const GridDev& G, int
 template <class SH> __device__ __forceinline__ bool sync_of(const GridDev& G, int s) {
   return SH::fixed ? bit(SH::SYNC, s) : bit(G.slot_sync, s);
 }
+// Coefficient group of slot s >= 1: the coarse groups of slot 0, then one more per group
+// end before s.
+template <class SH> __device__ __forceinline__ int group_of_slot(const GridDev& G, int s) {
+  const uint32_t sync = SH::fixed ? SH::SYNC : G.slot_sync;
+  return ncoarse_of<SH>(G) + __popc(sync & ((1u << s) - 1u) & ~1u);
+}
+// x[g] for a group index known to be below kMaxLev (unrolled select, no indexed registers)
+__device__ __forceinline__ uint32_t pick(const uint32_t (&x)[kMaxLev], int g) {
+  uint32_t r = 0u;
+#pragma unroll
+  for (int q = 0; q < kMaxLev; ++q) r = g == q ? x[q] : r;
+  return r;
+}
 
 constexpr int kBatch = 4;   // slots whose LDS reads issue together (fixed shapes)
 
@@ -380,65 +393,65 @@ __device__ __forceinline__ void for_columns(const GridDev& G, BEGIN begin, BODY 
   }
 }
 
-// Activity masks of a Newton pass: bit (j & 31) of word 4 cb + j / 32 says whether cell
-// (j, i = lane + 64 cb) has x > 0.  The Hessian depends on nothing else.
-constexpr int kColBlocks = (kMaxDim + 63) / 64, kRowWords = (kMaxDim + 31) / 32;
-constexpr int kMaskWords = kColBlocks * kRowWords;
-
 // One Newton pass at lam (Section III Stage 5): v[0..3] = A x, v[4] = sum |A_1| x and,
 // when THETA, v[15] = ||x - ft||^2, with x = max(0, ft - A^T lam) and ft in the wave
-// buffer; am gets the activity masks.  Per column the row sums of w x and c w x come
-// first and are then weighted by the column's powers of a.  The correction per cell is
-// vol * ((lam3 a + lam1) a + lam0 + lam2 c), one fixed order for compression and
-// decompression.
+// buffer.  The Hessian A diag(x > 0) A^T is left as this lane's share in hh[10] (upper
+// triangle, row-major, without the duplicate (1,1) = (0,3) entry); hess_reduce() sums it
+// only when a step is taken.  Per column the row sums of w x, c w x and, on active
+// cells, w^2, w^2 c, w^2 c^2 come first and are then weighted by the column's powers of
+// a.  The correction per cell is vol * ((lam3 a + lam1) a + lam0 + lam2 c), one fixed
+// order for compression and decompression.
 template <bool UVOL, bool THETA>
 __device__ __forceinline__ void newton_pass_w(const GridDev& G, const WaveLds& L, const double (&lam)[4],
-                                              double (&v)[16], uint32_t (&am)[kMaskWords]) {
-  const int lane = threadIdx.x & 63;
+                                              double (&v)[16], double (&hh)[9]) {
   double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0, v4 = 0.0, v15 = 0.0;
-  const uint32_t rowb = (uint32_t)G.n_par * 8u;
 #pragma unroll
-  for (int cb = 0; cb < kColBlocks; ++cb) {
-    const int i = lane + 64 * cb;
-    const bool col = i < G.n_par;
-    const double a = col ? G.apar[i] : 0.0;
-    const double pa = fma(fma(lam[3], a, lam[1]), a, lam[0]);
-    double sx = 0.0, sxc = 0.0, s2 = 0.0;
-    uint32_t off = (uint32_t)i * 8u;
-#pragma unroll
-    for (int jw = 0; jw < kRowWords; ++jw) {
-      uint32_t bits = 0;
-      if (64 * cb < G.n_par && 32 * jw < G.n_perp) {
-        const int jend = min(32, G.n_perp - 32 * jw);
-        if (col) {
-#pragma unroll 4
-          for (int jj = 0; jj < jend; ++jj) {
-            const int j = 32 * jw + jj;
-            const double c = L.s_cc[2 * j];
-            const double w = UVOL ? G.vol0 : G.vol[j * G.n_par + i];
-            const double ft = ldy(L.yb, off);
-            const double x = fmax(0.0, ft - w * fma(lam[2], c, pa));
-            const double wx = UVOL ? x : w * x;
-            sx += wx;
-            sxc = fma(c, wx, sxc);
-            bits |= (x > 0.0 ? 1u : 0u) << jj;
-            if (THETA) {
-              const double dx = x - ft;
-              s2 = fma(dx, dx, s2);
-            }
-            off += rowb;
-          }
-        }
-      }
-      am[cb * kRowWords + jw] = bits;
+  for (int k = 0; k < 9; ++k) hh[k] = 0.0;
+  double sx, sxc, h0, hc, hcc, s2;
+  double pa = 0.0;
+  auto begin = [&](int i) {
+    const double a = G.apar[i];
+    pa = fma(fma(lam[3], a, lam[1]), a, lam[0]);
+    sx = sxc = h0 = hc = hcc = s2 = 0.0;
+  };
+  auto body = [&](int i, int j, uint32_t off) {
+    const double c = L.s_cc[2 * j], c2 = L.s_cc[2 * j + 1];
+    const double w = UVOL ? G.vol0 : G.vol[j * G.n_par + i];
+    const double ft = ldy(L.yb, off);
+    const double x = fmax(0.0, ft - w * fma(lam[2], c, pa));
+    const double wx = UVOL ? x : w * x;
+    sx += wx;
+    sxc = fma(c, wx, sxc);
+    if (x > 0.0) {
+      const double w2 = UVOL ? 1.0 : w * w;
+      h0 += w2;
+      hc = fma(w2, c, hc);
+      hcc = fma(w2, c2, hcc);
     }
+    if (THETA) {
+      const double dx = x - ft;
+      s2 = fma(dx, dx, s2);
+    }
+  };
+  auto fold = [&](int i) {
+    const double a = G.apar[i], a2 = a * a;
     v0 += sx;
     v1 = fma(a, sx, v1);
     v2 += sxc;
-    v3 = fma(a * a, sx, v3);
+    v3 = fma(a2, sx, v3);
     v4 = fma(fabs(a), sx, v4);
     v15 += s2;
-  }
+    hh[0] += h0;
+    hh[1] = fma(a, h0, hh[1]);
+    hh[2] += hc;
+    hh[3] = fma(a2, h0, hh[3]);
+    hh[4] = fma(a, hc, hh[4]);
+    hh[5] = fma(a2 * a, h0, hh[5]);
+    hh[6] += hcc;
+    hh[7] = fma(a2, hc, hh[7]);
+    hh[8] = fma(a2 * a2, h0, hh[8]);
+  };
+  for_columns(G, begin, body, fold);
   v[0] = wsum(v0);
   v[1] = wsum(v1);
   v[2] = wsum(v2);
@@ -451,60 +464,13 @@ __device__ __forceinline__ void newton_pass_w(const GridDev& G, const WaveLds& L
   }
 }
 
-// Newton Hessian A diag(x > 0) A^T from the activity masks into v[5..14] (upper
-// triangle, row-major): per column the row sums of w^2, w^2 c and w^2 c^2 over active
-// cells, then the column's powers of a.
+// The pass's Hessian shares summed into v[5..14].
 template <bool UVOL>
-__device__ __forceinline__ void newton_hess_w(const GridDev& G, const WaveLds& L, const uint32_t (&am)[kMaskWords],
-                                              double (&v)[16]) {
-  const int lane = threadIdx.x & 63;
-  double h[10];
-#pragma unroll
-  for (int k = 0; k < 10; ++k) h[k] = 0.0;
-#pragma unroll
-  for (int cb = 0; cb < kColBlocks; ++cb) {
-    const int i = lane + 64 * cb;
-    const bool col = i < G.n_par;
-    const double a = col ? G.apar[i] : 0.0, a2 = a * a;
-    double h0 = 0.0, hc = 0.0, hcc = 0.0;
-#pragma unroll
-    for (int jw = 0; jw < kRowWords; ++jw) {
-      const uint32_t bits = am[cb * kRowWords + jw];
-      if (64 * cb < G.n_par && 32 * jw < G.n_perp && col) {
-        const int jend = min(32, G.n_perp - 32 * jw);
-        if (UVOL) h0 += (double)__popc(bits);
-#pragma unroll 4
-        for (int jj = 0; jj < jend; ++jj) {
-          if ((bits >> jj) & 1u) {
-            const int j = 32 * jw + jj;
-            const double c = L.s_cc[2 * j], c2 = L.s_cc[2 * j + 1];
-            if (UVOL) {
-              hc += c;
-              hcc += c2;
-            } else {
-              const double w = G.vol[j * G.n_par + i], w2 = w * w;
-              h0 += w2;
-              hc = fma(w2, c, hc);
-              hcc = fma(w2, c2, hcc);
-            }
-          }
-        }
-      }
-    }
-    h[0] += h0;
-    h[1] = fma(a, h0, h[1]);
-    h[2] += hc;
-    h[3] = fma(a2, h0, h[3]);
-    h[5] = fma(a, hc, h[5]);
-    h[6] = fma(a2 * a, h0, h[6]);
-    h[7] += hcc;
-    h[8] = fma(a2, hc, h[8]);
-    h[9] = fma(a2 * a2, h0, h[9]);
-  }
+__device__ __forceinline__ void hess_reduce(const GridDev& G, const double (&hh)[9], double (&v)[16]) {
   const double s2v = UVOL ? G.vol0 * G.vol0 : 1.0;
+  constexpr int dst[9] = {5, 6, 7, 8, 10, 11, 12, 13, 14};
 #pragma unroll
-  for (int k = 0; k < 10; ++k)
-    if (k != 4) v[5 + k] = wsum(h[k]) * s2v;
+  for (int k = 0; k < 9; ++k) v[dst[k]] = wsum(hh[k]) * s2v;
   v[9] = v[8];
 }
 
@@ -591,26 +557,11 @@ __device__ __forceinline__ int newton_w(const GridDev& G, const WaveLds& L, cons
   double v[16];
 #pragma unroll
   for (int k = 0; k < 16; ++k) v[k] = 0.0;
-  // the Hessian in v[5..14] belongs to the activity masks hm; it is rebuilt only when a
-  // step is taken from a pass whose masks differ
-  uint32_t am[kMaskWords], hm[kMaskWords];
-  bool have_h = false;
-#pragma unroll
-  for (int k = 0; k < kMaskWords; ++k) hm[k] = 0u;
-  auto hessian = [&]() {
-    bool same = have_h;
-#pragma unroll
-    for (int k = 0; k < kMaskWords; ++k) same = same && am[k] == hm[k];
-    if (__ballot(!same) != 0) {
-      newton_hess_w<UVOL>(G, L, am, v);
-#pragma unroll
-      for (int k = 0; k < kMaskWords; ++k) hm[k] = am[k];
-      have_h = true;
-    }
-  };
+  double hh[9];
+  auto hessian = [&]() { hess_reduce<UVOL>(G, hh, v); };
   for (;;) {
-    if (round == 1 && armijo2) newton_pass_w<UVOL, true>(G, L, cand, v, am);
-    else newton_pass_w<UVOL, false>(G, L, cand, v, am);
+    if (round == 1 && armijo2) newton_pass_w<UVOL, true>(G, L, cand, v, hh);
+    else newton_pass_w<UVOL, false>(G, L, cand, v, hh);
     if (trial) {
       if (theta_w(v, cand, b) >= t0 + kArmijoC * step * gd) {
 #pragma unroll
@@ -704,14 +655,9 @@ template <typename TIn, bool UVOL, class SH>
 __global__ __launch_bounds__(256, 2) void k_residual_w(GridDev G, ResidualArgs a) {
   constexpr int NS = SH::NS;
   extern __shared__ double smem[];
-  __shared__ uint32_t s_gmax[kWPB][kMaxLev], s_width[kWPB][kMaxLev], s_base[kWPB][kMaxLev];
-  __shared__ int s_gstart[kMaxLev + 1];
-  __shared__ int s_sgroup[kWaveSlots];
   const int N = G.N;
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const WaveLds L = setup_lds(G, smem, wv);
-  if (threadIdx.x <= kMaxLev) s_gstart[threadIdx.x] = threadIdx.x <= G.nlev ? G.gstart[threadIdx.x] : N;
-  if (threadIdx.x < kWaveSlots) s_sgroup[threadIdx.x] = G.slot_group[threadIdx.x];
   __syncthreads();
   const long long h = (long long)blockIdx.x * kWPB + wv;
   if (h >= a.H) return;
@@ -840,24 +786,22 @@ __global__ __launch_bounds__(256, 2) void k_residual_w(GridDev G, ResidualArgs a
       kst = lo;
       const double Dk = ladder(d0, kst);
       const double inv = 1.0 / Dk;
-      // zigzag integers and per-group widths; the payload words borrow the buffer, which
-      // the final recomposition then fills with rhat
-      if (lane < kMaxLev) s_gmax[wv][lane] = 0u;
-      wave_sync();
+      // zigzag integers and per-group widths (wave-uniform, in registers); the payload
+      // words borrow the buffer, which the final recomposition then fills with rhat
       auto zz = [&](double d) -> uint32_t {
         const int q = (int)rint(__dmul_rn(d, inv));
         return ((uint32_t)q << 1) ^ (uint32_t)(q >> 31);
       };
       const uint32_t zero_off = (uint32_t)N * 8u;
-      // slot 0 may mix groups: reduce each of its groups separately
+      uint32_t gmx[kMaxLev];
+#pragma unroll
+      for (int g = 0; g < kMaxLev; ++g) gmx[g] = 0u;
+      const int g0 = (int)(R.m2[0] >> 28);     // slot 0 may mix groups: one maximum each
       {
-        const uint32_t mm2 = R.m2[0];
-        const int g0 = (int)(mm2 >> 28);
         const uint32_t u0 = zz(dm[0]);
-        for (int g = 0; g < ncoarse_of<SH>(G); ++g) {
-          const uint32_t v = wumax(g0 == g ? u0 : 0u);
-          if (lane == 0) s_gmax[wv][g] = max(s_gmax[wv][g], v);
-        }
+#pragma unroll
+        for (int g = 0; g < kMaxLev; ++g)
+          if (g < ncoarse_of<SH>(G)) gmx[g] = wumax(g0 == g ? u0 : 0u);
       }
       uint32_t cur = 0u;
 #pragma unroll
@@ -866,38 +810,39 @@ __global__ __launch_bounds__(256, 2) void k_residual_w(GridDev G, ResidualArgs a
           cur = max(cur, zz(dm[s]));          // padding lanes hold d = 0
           if (sync_of<SH>(G, s)) {
             const uint32_t v = wumax(cur);
-            if (lane == 0) {
-              const int g = s_sgroup[s];
-              s_gmax[wv][g] = max(s_gmax[wv][g], v);
-            }
+            const int g = group_of_slot<SH>(G, s);
+#pragma unroll
+            for (int q = 0; q < kMaxLev; ++q)
+              if (q == g) gmx[q] = max(gmx[q], v);
             cur = 0u;
           }
         }
       }
-      wave_sync();
+      uint32_t wd[kMaxLev], bs[kMaxLev];
       uint32_t nbits = 0;
-      for (int g = 0; g < G.nlev; ++g) {
-        const uint32_t mxu = s_gmax[wv][g];
-        const uint32_t wdt = mxu ? 32u - (uint32_t)__clz(mxu) : 0u;
-        if (lane == 0) { s_width[wv][g] = wdt; s_base[wv][g] = nbits; }
-        nbits += (uint32_t)(s_gstart[g + 1] - s_gstart[g]) * wdt;
+#pragma unroll
+      for (int g = 0; g < kMaxLev; ++g) {
+        wd[g] = (g < G.nlev && gmx[g]) ? 32u - (uint32_t)__clz(gmx[g]) : 0u;
+        bs[g] = nbits;
+        if (g < G.nlev) nbits += (uint32_t)(G.gstart[g + 1] - G.gstart[g]) * wd[g];
       }
       const uint32_t nwords = (nbits + 31u) >> 5;
+      uint32_t rk[NS];
+#pragma unroll
+      for (int s = 0; s < NS; ++s) rk[s] = s < nslots_of<SH>(G) ? (uint32_t)L.rk[s * 64 + lane] : 0u;
       for (uint32_t k = lane; k < nwords; k += 64) words[k] = 0u;
       wave_sync();
 #pragma unroll
       for (int s = 0; s < NS; ++s) {
         if (s < nslots_of<SH>(G)) {
           const uint32_t eo = R.m[s].x & 0xffffu;
-          const int g = s == 0 ? (int)(R.m2[0] >> 28) : s_sgroup[s];
-          if (eo != zero_off) {
-            const uint32_t wdt = s_width[wv][g];
-            if (wdt != 0) {
-              const uint32_t pos = s_base[wv][g] + (uint32_t)L.rk[s * 64 + lane] * wdt;
-              const uint64_t v = (uint64_t)zz(dm[s]) << (pos & 31u);
-              atomicOr(&words[pos >> 5], (uint32_t)v);
-              if ((pos & 31u) + wdt > 32u) atomicOr(&words[(pos >> 5) + 1], (uint32_t)(v >> 32));
-            }
+          const int g = s == 0 ? g0 : group_of_slot<SH>(G, s);
+          const uint32_t wdt = pick(wd, g), base = pick(bs, g);
+          if (eo != zero_off && wdt != 0) {
+            const uint32_t pos = base + rk[s] * wdt;
+            const uint64_t v = (uint64_t)zz(dm[s]) << (pos & 31u);
+            atomicOr(&words[pos >> 5], (uint32_t)v);
+            if ((pos & 31u) + wdt > 32u) atomicOr(&words[(pos >> 5) + 1], (uint32_t)(v >> 32));
           }
         }
       }
@@ -908,10 +853,13 @@ __global__ __launch_bounds__(256, 2) void k_residual_w(GridDev G, ResidualArgs a
         hp[0] = (uint64_t)__double_as_longlong(Dk);
         uint64_t w1 = (uint64_t)(uint32_t)kst | ((uint64_t)(uint32_t)G.nlev << 8);
         uint64_t w2 = 0;
-        for (int g = 0; g < G.nlev; ++g) {
+#pragma unroll
+        for (int g = 0; g < kMaxLev; ++g) {
           const int byte = 10 + g;
-          if (byte < 16) w1 |= (uint64_t)s_width[wv][g] << (8 * (byte - 8));
-          else w2 |= (uint64_t)s_width[wv][g] << (8 * (byte - 16));
+          if (g < G.nlev) {
+            if (byte < 16) w1 |= (uint64_t)wd[g] << (8 * (byte - 8));
+            else w2 |= (uint64_t)wd[g] << (8 * (byte - 16));
+          }
         }
         hp[1] = w1;
         if (G.hdr_bytes > 16) hp[2] = w2;
@@ -926,10 +874,14 @@ __global__ __launch_bounds__(256, 2) void k_residual_w(GridDev G, ResidualArgs a
       // latency hides behind it (one column per lane when the grid allows)
       const bool pre = G.n_par <= 64 && G.n_perp <= kRowChunk;
       float fh[kRowChunk];
-      if (pre) {
+      if (pre && fhp) {
+        // clamped indices keep every load in bounds and unconditional, so all issue at once
+        const int ic = min(lane, G.n_par - 1);
 #pragma unroll
-        for (int k = 0; k < kRowChunk; ++k)
-          fh[k] = (fhp && lane < G.n_par && k < G.n_perp) ? fhp[k * G.n_par + lane] : 0.0f;
+        for (int k = 0; k < kRowChunk; ++k) fh[k] = fhp[min(k, G.n_perp - 1) * G.n_par + ic];
+      } else {
+#pragma unroll
+        for (int k = 0; k < kRowChunk; ++k) fh[k] = 0.0f;
       }
       recompose_w<SH, true>(G, L, R, rm, [&](int s) { return qdelta(Dk, dm[s], inv); });   // rhat at k*
       wave_sync();
@@ -1001,14 +953,9 @@ template <typename TIn, typename TOut, bool UVOL, class SH>
 __global__ __launch_bounds__(256, 2) void k_decompress_w(GridDev G, DecompressArgs a) {
   constexpr int NS = SH::NS;
   extern __shared__ double smem[];
-  __shared__ uint32_t s_width[kWPB][kMaxLev], s_base[kWPB][kMaxLev];
-  __shared__ int s_gstart[kMaxLev + 1];
-  __shared__ int s_sgroup[kWaveSlots];
   const int N = G.N;
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const WaveLds L = setup_lds(G, smem, wv);
-  if (threadIdx.x <= kMaxLev) s_gstart[threadIdx.x] = threadIdx.x <= G.nlev ? G.gstart[threadIdx.x] : N;
-  if (threadIdx.x < kWaveSlots) s_sgroup[threadIdx.x] = G.slot_group[threadIdx.x];
   __syncthreads();
   const long long h = (long long)blockIdx.x * kWPB + wv;
   if (h >= a.H) return;
@@ -1039,16 +986,24 @@ __global__ __launch_bounds__(256, 2) void k_decompress_w(GridDev G, DecompressAr
   if (coded) {
     const uint64_t lo = ld32w(rec), hi = ld32w(rec + 4);
     const double Delta = __longlong_as_double((long long)(lo | (hi << 32)));
-    if (lane == 0) {
-      uint32_t nb = 0;
-      for (int g = 0; g < G.nlev; ++g) {
-        const uint32_t wdt = rec[10 + g];
-        s_width[wv][g] = wdt;
-        s_base[wv][g] = nb;
-        nb += (uint32_t)(s_gstart[g + 1] - s_gstart[g]) * wdt;
-      }
+    // per-group widths from the header and their bit offsets (wave-uniform)
+    uint32_t wd[kMaxLev], bs[kMaxLev];
+    uint32_t nb = 0;
+#pragma unroll
+    for (int g = 0; g < kMaxLev; ++g) {
+      wd[g] = g < G.nlev ? (uint32_t)rec[10 + g] : 0u;
+      bs[g] = nb;
+      if (g < G.nlev) nb += (uint32_t)(G.gstart[g + 1] - G.gstart[g]) * wd[g];
     }
-    wave_sync();
+    // a header that does not fit its record (widths above 32 bits, or more payload than
+    // the record holds) decodes to NaN rather than reading past the record
+    bool corrupt = (uint64_t)G.hdr_bytes + 4ull * (((uint64_t)nb + 31u) >> 5) > a.offsets[h + 1] - a.offsets[h];
+#pragma unroll
+    for (int g = 0; g < kMaxLev; ++g) corrupt = corrupt || wd[g] > 32u;
+    if (corrupt) {
+      for (int e = lane; e < N; e += 64) out[e] = (TOut)NAN;
+      return;
+    }
     const uint8_t* payload = rec + G.hdr_bytes;
     const uint32_t zero_off = (uint32_t)N * 8u;
     SlotRegs<NS> R;
@@ -1060,12 +1015,12 @@ __global__ __launch_bounds__(256, 2) void k_decompress_w(GridDev G, DecompressAr
       rm[s] = 0.0;
       if (s < nslots_of<SH>(G)) {
         const uint32_t eo = R.m[s].x & 0xffffu;
-        const int g = s == 0 ? (int)(R.m2[0] >> 28) : s_sgroup[s];
+        const int g = s == 0 ? (int)(R.m2[0] >> 28) : group_of_slot<SH>(G, s);
+        const uint32_t wdt = pick(wd, g), base = pick(bs, g);
         if (eo != zero_off) {
-          const uint32_t wdt = s_width[wv][g];
           uint32_t u = 0;
           if (wdt) {
-            const uint32_t pos = s_base[wv][g] + (uint32_t)L.rk[s * 64 + lane] * wdt;
+            const uint32_t pos = base + (uint32_t)L.rk[s * 64 + lane] * wdt;
             const uint32_t wi = pos >> 5, sh = pos & 31u;
             uint64_t v = ld32w(payload + 4 * wi);
             if (sh + wdt > 32u) v |= (uint64_t)ld32w(payload + 4 * (wi + 1)) << 32;

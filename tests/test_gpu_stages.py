@@ -343,6 +343,35 @@ def test_decompress_reads_oracle_stream(H, ctx, dtype):
     assert np.all(both_nan | np.isclose(out, ref, rtol=1e-13, atol=1e-15 * np.nanmax(np.abs(ref))))
 
 
+@pytest.mark.parametrize("shape", [(39, 39), (65, 65)])
+def test_decompress_rejects_corrupt_headers(H, ctx, shape):
+    """A record whose header claims more payload than the record holds (or a width above 32
+    bits) decodes to NaN; the records around it decode as before."""
+    n = shape[0]
+    say("corrupt headers", shape)
+    g = grid.make_grid(n, n)
+    plan = H.Plan(ctx, n, n)
+    F = synth.histograms(6, n, n, seed=40, dtype=np.float32)
+    comp = pipeline.compress(F, g, None, None, pipeline.Params(tau=1e-3))
+    assert np.all(comp["flags"] & 1)
+    lay = oracle.coder.layout(n, n)
+    stream = bytearray(comp["stream"])
+    off = comp["offsets"].astype(np.int64)
+    stream[off[1] + 10] = 40                                  # width above 32 bits
+    stream[off[3] + 10 + lay.nlev - 1] += 8                   # finest group: payload past the record
+    ref = pipeline.decompress(comp, g, None, None, 6)
+    cmp_ = H.alloc_compressed(6, plan.N, "cuda", capacity=len(stream))
+    cmp_.flags.copy_(torch.from_numpy(comp["flags"]))
+    cmp_.lam.copy_(torch.from_numpy(comp["lam"]))
+    cmp_.offsets.copy_(torch.from_numpy(off))
+    cmp_.stream.copy_(torch.frombuffer(stream, dtype=torch.uint8))
+    cz = H.Compressor(plan, None, 6, H.params())
+    out = cz.decompress(cmp_, 6).cpu().numpy()
+    assert np.all(np.isnan(out[[1, 3]]))
+    ok = [0, 2, 4, 5]
+    assert np.allclose(out[ok], ref[ok], rtol=1e-13, atol=1e-15 * np.abs(ref).max())
+
+
 @pytest.mark.parametrize("shape", [(39, 39), (49, 49)])
 def test_residual_warm_start(H, ctx, shape):
     """Warm starts near the solution, garbage and NaN: flags (incl. rejection), records and
