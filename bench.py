@@ -32,11 +32,62 @@ def log(*a):
 
 
 def residual_flops(N: int, H: int, coded: int, steps_per_coded: float, newton_passes: float) -> float:
-    """FP64 operations of the residual stage, FMA counted as 2 (per element
-    12 for the load pass, 10 for the decomposition, 15 per bisection step, 2 for packing,
-    26 per Newton pass)."""
-    per_elem = 12.0 * H + coded * (10.0 + 15.0 * steps_per_coded + 2.0) + 26.0 * newton_passes
-    return per_elem * N
+    """FP64 operations the residual stage's method needs, FMA counted as 2, per grid cell:
+    13 for the load pass (residual, two squared norms, four moments), per coded histogram
+    5 for the decomposition, 12 per bisection step (quantise, interpolate, add, error),
+    2 for packing and 10 for the final recomposition with ft = fhat + rhat, and 10 per
+    Newton pass (correction, clip, two moment sums, Hessian terms on active cells)."""
+    per_cell = 13.0 * H + coded * (5.0 + 12.0 * steps_per_coded + 2.0 + 10.0) + 10.0 * newton_passes
+    return per_cell * N
+
+
+def bisection_steps(kstar_hist) -> float:
+    """Mean number of bound evaluations of the bisection over the 41-step ladder: each
+    final step k* has exactly one search path."""
+    def steps(k):
+        lo, hi, n = 0, 41, 0
+        while hi - lo > 1:
+            mid = (lo + hi) >> 1
+            n += 1
+            if mid <= k:
+                lo = mid
+            else:
+                hi = mid
+        return n
+    tot = sum(kstar_hist)
+    return sum(c * steps(k) for k, c in enumerate(kstar_hist)) / tot if tot else 0.0
+
+
+def _sha256(paths) -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for p in paths:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+RESIDUAL_SOURCES = ["paper_2212_10733_amd/csrc/k_wave.hip", "paper_2212_10733_amd/csrc/hcz_internal.h"]
+
+
+def residual_traffic(H: int):
+    """HBM bytes of one residual launch from the committed counter summary, scaled to H,
+    or None when the kernel sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "residual_wave_hbm_counters.md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if line.startswith("- ") and ":" in line:
+            k, v = line[2:].split(":", 1)
+            vals[k.strip()] = v.strip().strip("`")
+    try:
+        if vals["kernel source sha256"] != _sha256(RESIDUAL_SOURCES):
+            return None
+        per_hist = float(vals["calibrated fetch bytes per histogram"]) + float(vals["calibrated write bytes per histogram"])
+    except (KeyError, ValueError):
+        return None
+    return per_hist * H
 
 
 def cpu_baseline(F: np.ndarray, W: dict, mu, sd, tau: float, n: int) -> dict:
@@ -219,7 +270,7 @@ def main() -> int:
     stage_ms = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in prof.items() if v[1]}
     N = plan.N
     coded = st["n_coded"]
-    steps_coded = 6.0
+    steps_coded = bisection_steps(st["kstar_hist"])
     passes = st["newton_iters_total"] + (H - st["n_raw"])
     ae_flops = 2.0 * H * N * 128 + 2.0 * H * 128 * 16
     cands = {
@@ -231,7 +282,7 @@ def main() -> int:
     bound, work, peak, unit = cands[dom]
     achieved = work / (stage_ms[dom] / 1e3)
     roofline = {"bound": bound, "kernel": dom, "achieved": achieved, "peak": peak, "unit": unit,
-                "frac": achieved / peak, "traffic": None}
+                "frac": achieved / peak, "traffic": residual_traffic(H) if dom == "residual" else None}
     stream_bytes = st["stream_bytes"]
     alg_bytes = H * (4 * N + 16 + 32 + 1 + 8) + stream_bytes
     extra = {
