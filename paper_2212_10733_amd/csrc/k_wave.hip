@@ -215,20 +215,20 @@ __device__ __forceinline__ SlotMasks slot_masks(const GridDev& G) {
 // and batches of slots issue their LDS reads together.
 struct ShapeDyn {
   static constexpr bool fixed = false;
-  static constexpr int NS = kWaveSlots, NCO = 0;
+  static constexpr int NS = kWaveSlots, NCO = 0, NP = 0, NQ = 0;
   static constexpr uint32_t BIL = 0, SYNC = 0, KEEP = 0;
 };
 // 39 x 39 (the velocity grid of the paper's data): slot 0 holds groups 0-3, slots 1-2
 // group 4, slots 3-7 group 5 and slots 8-25 the finest group.
 struct Shape39 {
   static constexpr bool fixed = true;
-  static constexpr int NS = 26, NCO = 4;
+  static constexpr int NS = 26, NCO = 4, NP = 39, NQ = 39;
   static constexpr uint32_t BIL = 0x3f800c7u, SYNC = 0x2000085u, KEEP = 0xffu;
 };
 template <class SH>
 __host__ __device__ constexpr bool shape_matches(const GridDev& G) {
-  return !SH::fixed || (G.nslots == SH::NS && G.ncoarse == SH::NCO && G.slot_bil == SH::BIL &&
-                        G.slot_sync == SH::SYNC && G.slot_keep == SH::KEEP);
+  return !SH::fixed || (G.nslots == SH::NS && G.ncoarse == SH::NCO && G.n_par == SH::NP && G.n_perp == SH::NQ &&
+                        G.slot_bil == SH::BIL && G.slot_sync == SH::SYNC && G.slot_keep == SH::KEEP);
 }
 template <class SH> __device__ __forceinline__ int nslots_of(const GridDev& G) { return SH::fixed ? SH::NS : G.nslots; }
 template <class SH> __device__ __forceinline__ int ncoarse_of(const GridDev& G) { return SH::fixed ? SH::NCO : G.ncoarse; }
@@ -317,7 +317,9 @@ __device__ __forceinline__ double recompose_w(const GridDev& G, const WaveLds& L
     const double dq = dqf(0);
     for (int g = 0; g < ncoarse_of<SH>(G); ++g) {
       if (g0 == g) {
-        const double v = g == 0 ? dq : __dadd_rn(dq, predict_w<true>(L, m, m2));
+        // the coarsest values are dq itself: +0 for a quantised zero as in the oracle
+        // (elsewhere dq + P already has the bits of +0 + P: P is never -0)
+        const double v = g == 0 ? __dadd_rn(dq, 0.0) : __dadd_rn(dq, predict_w<true>(L, m, m2));
         sty(L.yb, m.x & 0xffffu, v);
         const double e = rm[0] - v;
         acc = fma(e, e, acc);
@@ -401,7 +403,7 @@ __device__ __forceinline__ void for_columns(const GridDev& G, BEGIN begin, BODY 
 // cells, w^2, w^2 c, w^2 c^2 come first and are then weighted by the column's powers of
 // a.  The correction per cell is vol * ((lam3 a + lam1) a + lam0 + lam2 c), one fixed
 // order for compression and decompression.
-template <bool UVOL, bool THETA>
+template <class SH, bool UVOL, bool THETA>
 __device__ __forceinline__ void newton_pass_w(const GridDev& G, const WaveLds& L, const double (&lam)[4],
                                               double (&v)[16], double (&hh)[9]) {
   double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0, v4 = 0.0, v15 = 0.0;
@@ -422,12 +424,12 @@ __device__ __forceinline__ void newton_pass_w(const GridDev& G, const WaveLds& L
     const double wx = UVOL ? x : w * x;
     sx += wx;
     sxc = fma(c, wx, sxc);
-    if (x > 0.0) {
-      const double w2 = UVOL ? 1.0 : w * w;
-      h0 += w2;
-      hc = fma(w2, c, hc);
-      hcc = fma(w2, c2, hcc);
-    }
+    // Hessian terms on active cells, as a 0/1 weight (exact: products with 0 or 1)
+    const double act = x > 0.0 ? 1.0 : 0.0;
+    const double w2 = UVOL ? act : act * (w * w);
+    h0 += w2;
+    hc = fma(w2, c, hc);
+    hcc = fma(w2, c2, hcc);
     if (THETA) {
       const double dx = x - ft;
       s2 = fma(dx, dx, s2);
@@ -451,7 +453,18 @@ __device__ __forceinline__ void newton_pass_w(const GridDev& G, const WaveLds& L
     hh[7] = fma(a2, hc, hh[7]);
     hh[8] = fma(a2 * a2, h0, hh[8]);
   };
-  for_columns(G, begin, body, fold);
+  if constexpr (SH::fixed && SH::NP <= 64) {
+    // one column per lane, every row offset a compile-time constant
+    const int i = threadIdx.x & 63;
+    if (i < SH::NP) {
+      begin(i);
+#pragma unroll
+      for (int j = 0; j < SH::NQ; ++j) body(i, j, (uint32_t)(j * SH::NP + i) * 8u);
+      fold(i);
+    }
+  } else {
+    for_columns(G, begin, body, fold);
+  }
   v[0] = wsum(v0);
   v[1] = wsum(v1);
   v[2] = wsum(v2);
@@ -531,7 +544,7 @@ __device__ __forceinline__ bool chol4(const double (&v)[16], const double (&g)[4
 // to max2 updates.  An accepted Armijo candidate's pass is also the next iterate's pass
 // (same multipliers, same values).  Returns 0 (round 1 converged), 1 (round 2
 // converged) or 2 (failed); *upd counts the updates.
-template <bool UVOL>
+template <class SH, bool UVOL>
 __device__ __forceinline__ int newton_w(const GridDev& G, const WaveLds& L, const double (&b)[4], double (&lam)[4],
                                         double s1, int max1, double s2, int max2, bool armijo2, int* upd,
                                         bool have_init, const double (&lam_init)[4], bool* rejected) {
@@ -560,8 +573,8 @@ __device__ __forceinline__ int newton_w(const GridDev& G, const WaveLds& L, cons
   double hh[9];
   auto hessian = [&]() { hess_reduce<UVOL>(G, hh, v); };
   for (;;) {
-    if (round == 1 && armijo2) newton_pass_w<UVOL, true>(G, L, cand, v, hh);
-    else newton_pass_w<UVOL, false>(G, L, cand, v, hh);
+    if (round == 1 && armijo2) newton_pass_w<SH, UVOL, true>(G, L, cand, v, hh);
+    else newton_pass_w<SH, UVOL, false>(G, L, cand, v, hh);
     if (trial) {
       if (theta_w(v, cand, b) >= t0 + kArmijoC * step * gd) {
 #pragma unroll
@@ -779,7 +792,7 @@ __global__ __launch_bounds__(256, 2) void k_residual_w(GridDev G, ResidualArgs a
         const int mid = (lo + hi) >> 1;
         const double Dk = ladder(d0, mid);
         const double inv = 1.0 / Dk;
-        const double e2 = recompose_w<SH, false>(G, L, R, rm, [&](int s) { return qdelta(Dk, dm[s], inv); });
+        const double e2 = recompose_w<SH, false>(G, L, R, rm, [&](int s) { return __dmul_rn(Dk, rint(__dmul_rn(dm[s], inv))); });
         if (e2 <= thr2) lo = mid;
         else hi = mid;
       }
@@ -883,7 +896,7 @@ __global__ __launch_bounds__(256, 2) void k_residual_w(GridDev G, ResidualArgs a
 #pragma unroll
         for (int k = 0; k < kRowChunk; ++k) fh[k] = 0.0f;
       }
-      recompose_w<SH, true>(G, L, R, rm, [&](int s) { return qdelta(Dk, dm[s], inv); });   // rhat at k*
+      recompose_w<SH, true>(G, L, R, rm, [&](int s) { return __dmul_rn(Dk, rint(__dmul_rn(dm[s], inv))); });   // rhat at k*
       wave_sync();
       if (pre) {
         if (lane < G.n_par) {
@@ -915,7 +928,7 @@ __global__ __launch_bounds__(256, 2) void k_residual_w(GridDev G, ResidualArgs a
       for (int k = 0; k < 4; ++k) l0[k] = a.lam0[h * 4 + k];
     }
     bool rejected = false;
-    const int st = newton_w<UVOL>(G, L, b, lam, a.newton_s, a.max_iter, paper ? 0.01 : 1.0, a.max_iter2, !paper,
+    const int st = newton_w<SH, UVOL>(G, L, b, lam, a.newton_s, a.max_iter, paper ? 0.01 : 1.0, a.max_iter2, !paper,
                                   &total_upd, a.lam0 != nullptr, l0, &rejected);
     if (rejected) flags |= HCZ_FLAG_WARM_REJECTED;
     if (st >= 1) flags |= HCZ_FLAG_ROUND2;
