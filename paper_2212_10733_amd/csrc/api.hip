@@ -210,7 +210,7 @@ struct SlotTables {
   std::vector<uint16_t> pos;
   std::vector<double> wtab;
   std::vector<int8_t> group;
-  uint32_t bil = 0, sync = 0, keep = 0;
+  uint32_t bil = 0, sync = 0, keep = 0, half = 0;
 };
 
 constexpr uint32_t kPadGroup = 15;
@@ -315,6 +315,15 @@ SlotTables make_slots(int np, int nq, int L, const std::vector<uint32_t>& node, 
     return T;
   }
   for (int k = 0; k < T.nslots; ++k) {
+    // every node of the slot interpolates with weight(s) exactly 1/2 (padding lanes read
+    // the zero cell, where any weight gives 0)
+    bool half = true;
+    for (int l = 0; l < 64; ++l) {
+      const uint32_t* w = &T.meta[(size_t)(k * 64 + l) * 3];
+      if ((w[0] & 0xffffu) == zero || (w[2] >> 28) == 0) continue;
+      half = half && T.wtab[(w[2] >> 16) & 63] == 0.5 && (!four[k] || T.wtab[(w[2] >> 22) & 63] == 0.5);
+    }
+    if (half && k > 0) T.half |= 1u << k;
     if (four[k]) T.bil |= 1u << k;
     if (k == 0 || k + 1 == T.nslots || T.group[k + 1] != T.group[k]) T.sync |= 1u << k;
     if (k == 0 || T.group[k] < nlev - 1) T.keep |= 1u << k;
@@ -533,6 +542,7 @@ hcz_status hcz_plan_create(hcz_ctx* ctx, const hcz_grid* g, hcz_plan** out) {
   G.slot_bil = slots.bil;
   G.slot_sync = slots.sync;
   G.slot_keep = slots.keep;
+  G.slot_half = slots.half;
   if ((s = upload(P->allocs, vol, &G.vol)) || (s = upload(P->allocs, apar, &G.apar)) ||
       (s = upload(P->allocs, cperp, &G.cperp)) || (s = upload(P->allocs, node, &G.node_ij)) ||
       (s = upload(P->allocs, dp.lev, &G.lev_par)) || (s = upload(P->allocs, dp.a, &G.a_par)) ||

@@ -56,6 +56,7 @@ struct GridDev {
   uint32_t slot_bil;                 // bit s: slot s uses the four-corner form
   uint32_t slot_sync;                // bit s: the next slot belongs to a later group
   uint32_t slot_keep;                // bit s: later groups read slot s (not the finest group)
+  uint32_t slot_half;                // bit s: every weight of slot s is exactly 1/2
   const uint32_t* slot_meta;         // [nslots * 64][3], see make_slots()
   const uint16_t* slot_rank;         // [nslots * 64] packing rank of each entry within its group
   const double* wtab;                // [nw] distinct interpolation weights, wtab[0] = 0

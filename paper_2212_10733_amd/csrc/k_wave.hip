@@ -185,14 +185,14 @@ __device__ __forceinline__ void sty(char* yb, uint32_t off, double v) { *(double
 
 // Interpolated value of a node from its corners, in the fixed unfused order of the coder
 // (two-corner form unless FOUR).
-template <bool FOUR>
+template <bool FOUR, bool HALF = false>
 __device__ __forceinline__ double predict_w(const WaveLds& L, uint2 m, uint32_t m2) {
   const double y00 = ldy(L.yb, m.x >> 16), y10 = ldy(L.yb, m.y & 0xffffu);
-  const double s = L.s_w[(m2 >> 16) & 63u];
+  const double s = HALF ? 0.5 : L.s_w[(m2 >> 16) & 63u];
   const double p0 = __dadd_rn(y00, __dmul_rn(s, __dsub_rn(y10, y00)));
   if (!FOUR) return p0;
   const double y01 = ldy(L.yb, m.y >> 16), y11 = ldy(L.yb, m2 & 0xffffu);
-  const double t = L.s_w[(m2 >> 22) & 63u];
+  const double t = HALF ? 0.5 : L.s_w[(m2 >> 22) & 63u];
   const double p1 = __dadd_rn(y01, __dmul_rn(s, __dsub_rn(y11, y01)));
   return __dadd_rn(p0, __dmul_rn(t, __dsub_rn(p1, p0)));
 }
@@ -216,19 +216,20 @@ __device__ __forceinline__ SlotMasks slot_masks(const GridDev& G) {
 struct ShapeDyn {
   static constexpr bool fixed = false;
   static constexpr int NS = kWaveSlots, NCO = 0, NP = 0, NQ = 0;
-  static constexpr uint32_t BIL = 0, SYNC = 0, KEEP = 0;
+  static constexpr uint32_t BIL = 0, SYNC = 0, KEEP = 0, HALF = 0;
 };
 // 39 x 39 (the velocity grid of the paper's data): slot 0 holds groups 0-3, slots 1-2
 // group 4, slots 3-7 group 5 and slots 8-25 the finest group.
 struct Shape39 {
   static constexpr bool fixed = true;
   static constexpr int NS = 26, NCO = 4, NP = 39, NQ = 39;
-  static constexpr uint32_t BIL = 0x3f800c7u, SYNC = 0x2000085u, KEEP = 0xffu;
+  static constexpr uint32_t BIL = 0x3f800c7u, SYNC = 0x2000085u, KEEP = 0xffu, HALF = 0x3f7ffb8u;
 };
 template <class SH>
 __host__ __device__ constexpr bool shape_matches(const GridDev& G) {
   return !SH::fixed || (G.nslots == SH::NS && G.ncoarse == SH::NCO && G.n_par == SH::NP && G.n_perp == SH::NQ &&
-                        G.slot_bil == SH::BIL && G.slot_sync == SH::SYNC && G.slot_keep == SH::KEEP);
+                        G.slot_bil == SH::BIL && G.slot_sync == SH::SYNC && G.slot_keep == SH::KEEP &&
+                        G.slot_half == SH::HALF);
 }
 template <class SH> __device__ __forceinline__ int nslots_of(const GridDev& G) { return SH::fixed ? SH::NS : G.nslots; }
 template <class SH> __device__ __forceinline__ int ncoarse_of(const GridDev& G) { return SH::fixed ? SH::NCO : G.ncoarse; }
@@ -250,6 +251,14 @@ __device__ __forceinline__ uint32_t pick(const uint32_t (&x)[kMaxLev], int g) {
 #pragma unroll
   for (int q = 0; q < kMaxLev; ++q) r = g == q ? x[q] : r;
   return r;
+}
+
+// Prediction for slot s of a fixed shape: the slot's form and (when every weight is 1/2)
+// its weights are compile-time constants after unrolling.
+template <class SH>
+__device__ __forceinline__ double predict_s(const WaveLds& L, int s, uint2 m, uint32_t m2) {
+  if (bit(SH::BIL, s)) return bit(SH::HALF, s) ? predict_w<true, true>(L, m, m2) : predict_w<true>(L, m, m2);
+  return bit(SH::HALF, s) ? predict_w<false, true>(L, m, m2) : predict_w<false>(L, m, m2);
 }
 
 constexpr int kBatch = 4;   // slots whose LDS reads issue together (fixed shapes)
@@ -277,7 +286,7 @@ __device__ __forceinline__ void batch_fixed(const WaveLds& L, const SlotRegs<SH:
   for (int k = 0; k < B; ++k) {
     m[k] = opaque2(R.m[S + k]);
     const uint32_t m2 = opaque1(R.m2[S + k]);
-    v[k] = __dadd_rn(dqf(S + k), bit(SH::BIL, S + k) ? predict_w<true>(L, m[k], m2) : predict_w<false>(L, m[k], m2));
+    v[k] = __dadd_rn(dqf(S + k), predict_s<SH>(L, S + k, m[k], m2));
     // a slot no later group reads keeps its residual in the buffer while the bisection
     // runs, which saves its register copy
     r[k] = bit(SH::KEEP, S + k) ? rm[S + k] : ldy(L.yb, m[k].x & 0xffffu);
@@ -664,15 +673,43 @@ __device__ __forceinline__ int newton_w(const GridDev& G, const WaveLds& L, cons
 
 // ---- compression ------------------------------------------------------------------------
 
+// One histogram's column for this lane, loaded ahead of its use (fixed shapes).
+template <typename TIn, class SH>
+struct PreRows {
+  TIn f[SH::fixed ? SH::NQ : 1];
+  float h[SH::fixed ? SH::NQ : 1];
+};
+// Every lane loads, clamped to a valid histogram and column (the extra values are unused).
+template <typename TIn, class SH>
+__device__ __forceinline__ void pre_load(PreRows<TIn, SH>& P, const GridDev& G, const ResidualArgs& a, long long h) {
+  const int i = min(threadIdx.x & 63, SH::NP - 1);
+  const long long hc = min(h, a.H - 1);
+  const TIn* f = (const TIn*)a.hist + hc * a.hs;
+#pragma unroll
+  for (int j = 0; j < SH::NQ; ++j) P.f[j] = f[(long long)j * a.rs + i];
+  if (a.fhat) {
+    const float* fhp = a.fhat + hc * (long long)G.N;
+#pragma unroll
+    for (int j = 0; j < SH::NQ; ++j) P.h[j] = fhp[j * SH::NP + i];
+  } else {
+#pragma unroll
+    for (int j = 0; j < SH::NQ; ++j) P.h[j] = 0.0f;
+  }
+}
+
+// One wave per histogram.  With a fixed shape the wave's column of the histogram is
+// loaded before the workgroup stages its tables, so both latencies overlap.
 template <typename TIn, bool UVOL, class SH>
 __global__ __launch_bounds__(256, 2) void k_residual_w(GridDev G, ResidualArgs a) {
   constexpr int NS = SH::NS;
   extern __shared__ double smem[];
   const int N = G.N;
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const long long h = (long long)blockIdx.x * kWPB + wv;
+  PreRows<TIn, SH> P;
+  if constexpr (SH::fixed) pre_load(P, G, a, h);
   const WaveLds L = setup_lds(G, smem, wv);
   __syncthreads();
-  const long long h = (long long)blockIdx.x * kWPB + wv;
   if (h >= a.H) return;
   const TIn* f = (const TIn*)a.hist + h * a.hs;
   const float* fhp = a.fhat ? a.fhat + h * (long long)N : nullptr;
@@ -718,7 +755,15 @@ __global__ __launch_bounds__(256, 2) void k_residual_w(GridDev G, ResidualArgs a
       m2 += sfc;
       m3 = fma(av * av, sf, m3);
     };
-    for_columns_pre(G, [&](int) { sf = sfc = 0.0; }, load, body, fold);
+    if constexpr (SH::fixed) {
+      if (lane < SH::NP) {
+#pragma unroll
+        for (int j = 0; j < SH::NQ; ++j) body(lane, j, (uint32_t)(j * SH::NP + lane) * 8u, FH{P.f[j], P.h[j]});
+        fold(lane);
+      }
+    } else {
+      for_columns_pre(G, [&](int) { sf = sfc = 0.0; }, load, body, fold);
+    }
   }
   {
     const double hi = ff.hi + ff.lo;
@@ -778,7 +823,8 @@ __global__ __launch_bounds__(256, 2) void k_residual_w(GridDev G, ResidualArgs a
         const uint2 m = R.m[s];
         const uint32_t mm2 = R.m2[s];
         rm[s] = ldy(L.yb, m.x & 0xffffu);
-        dm[s] = __dsub_rn(rm[s], bil_of<SH>(G, s) ? predict_w<true>(L, m, mm2) : predict_w<false>(L, m, mm2));
+        if constexpr (SH::fixed) dm[s] = __dsub_rn(rm[s], predict_s<SH>(L, s, m, mm2));
+        else dm[s] = __dsub_rn(rm[s], bil_of<SH>(G, s) ? predict_w<true>(L, m, mm2) : predict_w<false>(L, m, mm2));
         mx = fmax(mx, fabs(dm[s]));
       }
     }
@@ -1073,9 +1119,9 @@ bool wave_fixed_path(const GridDev& G) { return wave_path(G) && G.uniform_vol &&
 
 hipError_t launch_residual_w(const GridDev& G, const ResidualArgs& a, hipStream_t st) {
   if (a.H <= 0) return hipSuccess;
+  const bool s39 = wave_fixed_path(G);
   dim3 grid((unsigned)((a.H + kWPB - 1) / kWPB)), block(64 * kWPB);
   const size_t lds = lds_bytes_w(G);
-  const bool s39 = wave_fixed_path(G);
 #define HCZ_RW(T, U, SH) hipLaunchKernelGGL((k_residual_w<T, U, SH>), grid, block, lds, st, G, a)
 #define HCZ_RW2(T)                                     \
   do {                                                  \
