@@ -141,6 +141,141 @@ __global__ __launch_bounds__(256, 2) void k_encode(ModelDev M, const TIn* hist, 
   }
 }
 
+// Encoder for contiguous FP32 histograms without LDS staging in the K loop: lane
+// (li, kh) of a wave owns rows wr + 32 q + li and feeds the matrix core the 16
+// consecutive k = 32 c + 16 kh + s (s = 0..15) of chunk c, loaded straight from memory
+// (one run of 64 bytes per row and operand), so each v_mfma_f32_32x32x2f32 step sums the
+// pair k = 32 c + s, 32 c + 16 + s.  The next chunk's operands are loaded while the
+// current one is multiplied; no barrier is needed until the epilogue.  mu and 1/sigma
+// sit in LDS (zero beyond N), and a chunk reaching past N reads element by element.
+typedef float f32x4u __attribute__((ext_vector_type(4), aligned(4)));
+
+__global__ __launch_bounds__(256, 2) void k_encode_d(ModelDev M, const float* hist, long long H, long long hs,
+                                                     float* z) {
+  __shared__ __attribute__((aligned(16))) float smem[kTile * kHPitch];   // mu / rsd, then H1
+  __shared__ __attribute__((aligned(16))) float W2t[kHidden * kLatent];
+  const int t = threadIdx.x, w = t >> 6, l = t & 63;
+  const long long h0 = (long long)blockIdx.x * kTile;
+  const int wr = (w >> 1) * 64, wc = (w & 1) * 64;
+  const int li = l & 31, kh = l >> 5;
+  const int N = M.N, kpad = M.kpad;
+  float* s_mu = smem;
+  float* s_rsd = smem + kpad;
+  for (int k = t; k < kpad; k += 256) {
+    s_mu[k] = k < N ? M.mu[k] : 0.0f;
+    s_rsd[k] = k < N ? M.rsd[k] : 0.0f;
+  }
+  for (int q = t; q < kHidden * kLatent; q += 256) {
+    const int o = q / kHidden, c = q % kHidden;
+    W2t[c * kLatent + o] = M.W2[q];
+  }
+  __syncthreads();
+  const float* arow[2];
+  const float* brow[2];
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const long long r = min(h0 + wr + q * 32 + li, H - 1);     // rows past H repeat the last one
+    arow[q] = hist + r * hs + kh * 16;
+    brow[q] = M.W1p + (long long)(wc + q * 32 + li) * kpad + kh * 16;
+  }
+  f32x16 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.0f;
+  const int nfull = N / kKc, nchunk = kpad / kKc;
+  f32x4u ra[2][4], rb[2][4];
+  auto gload = [&](int c) {
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        ra[q][u] = *(const f32x4u*)(arow[q] + c * kKc + 4 * u);
+        rb[q][u] = *(const f32x4u*)(brow[q] + c * kKc + 4 * u);
+      }
+  };
+  auto gload_tail = [&](int c) {            // k may reach N: element by element
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int k = c * kKc + kh * 16 + 4 * u + e;
+          ra[q][u][e] = k < N ? arow[q][c * kKc + 4 * u + e] : 0.0f;
+        }
+        rb[q][u] = *(const f32x4u*)(brow[q] + c * kKc + 4 * u);
+      }
+  };
+  if (nfull > 0) gload(0);
+  else gload_tail(0);
+  for (int c = 0; c < nchunk; ++c) {
+    // normalise this chunk's A operands: (f - mu) / sigma, non-finite inputs as 0
+    float av[2][16], bv[2][16];
+    const f32x4* pm = (const f32x4*)(s_mu + c * kKc + kh * 16);
+    const f32x4* pr = (const f32x4*)(s_rsd + c * kKc + kh * 16);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const f32x4 mu4 = pm[u], rs4 = pr[u];
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          float fv = ra[q][u][e];
+          if (!isfinite(fv)) fv = 0.0f;
+          av[q][4 * u + e] = (fv - mu4[e]) * rs4[e];
+          bv[q][4 * u + e] = rb[q][u][e];
+        }
+    }
+    if (c + 1 < nfull) gload(c + 1);
+    else if (c + 1 < nchunk) gload_tail(c + 1);
+#pragma unroll
+    for (int s2 = 0; s2 < 16; ++s2)
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = mfma32(av[a][s2], bv[b][s2], acc[a][b]);
+  }
+  __syncthreads();
+  // epilogue 1: H1 = relu(acc + b1) into LDS
+  float* H1 = smem;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const int col = wc + b * 32 + li;
+      const float bias = M.b1[col];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = wr + a * 32 + 8 * (r >> 2) + 4 * kh + (r & 3);
+        H1[row * kHPitch + col] = fmaxf(acc[a][b][r] + bias, 0.0f);
+      }
+    }
+  __syncthreads();
+  // layer 2 on the vector ALUs: 8 latent outputs per thread
+  const int row = t >> 1, o0 = (t & 1) * 8;
+  float sacc[8];
+#pragma unroll
+  for (int o = 0; o < 8; ++o) sacc[o] = M.b2[o0 + o];
+  for (int c = 0; c < kHidden; ++c) {
+    const float hv = H1[row * kHPitch + c];
+    const f32x4 w0 = *(const f32x4*)&W2t[c * kLatent + o0];
+    const f32x4 w1 = *(const f32x4*)&W2t[c * kLatent + o0 + 4];
+#pragma unroll
+    for (int o = 0; o < 4; ++o) {
+      sacc[o] = fmaf(hv, w0[o], sacc[o]);
+      sacc[o + 4] = fmaf(hv, w1[o], sacc[o + 4]);
+    }
+  }
+  const long long h = h0 + row;
+  if (h < H) {
+#pragma unroll
+    for (int o = 0; o < 8; ++o) z[h * kLatent + o0 + o] = sacc[o];
+  }
+}
+
 __global__ __launch_bounds__(256, 2) void k_decode(ModelDev M, const uint8_t* codes,
                                                    const float* centroids, int kcb, long long H,
                                                    float* fhat) {
@@ -240,7 +375,9 @@ hipError_t launch_encode(const ModelDev& M, const void* hist, int dtype, long lo
   const bool contig = rs == n_par;
   dim3 grid((unsigned)((H + kTile - 1) / kTile)), block(256);
   if (dtype == HCZ_F32) {
-    if (contig) hipLaunchKernelGGL((k_encode<float, true>), grid, block, 0, st, M, (const float*)hist, H, hs, rs, n_par, z);
+    if (contig && (size_t)M.kpad * 2 <= (size_t)kTile * kHPitch)
+      hipLaunchKernelGGL(k_encode_d, grid, block, 0, st, M, (const float*)hist, H, hs, z);
+    else if (contig) hipLaunchKernelGGL((k_encode<float, true>), grid, block, 0, st, M, (const float*)hist, H, hs, rs, n_par, z);
     else hipLaunchKernelGGL((k_encode<float, false>), grid, block, 0, st, M, (const float*)hist, H, hs, rs, n_par, z);
   } else {
     if (contig) hipLaunchKernelGGL((k_encode<double, true>), grid, block, 0, st, M, (const double*)hist, H, hs, rs, n_par, z);
