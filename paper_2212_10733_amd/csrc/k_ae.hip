@@ -307,6 +307,19 @@ __global__ __launch_bounds__(256, 2) void k_decode(ModelDev M, const uint8_t* co
   }
   __syncthreads();
   const int wr = (w >> 1) * 64;
+  // the weights of the next (column block, quarter) step are loaded from memory while the
+  // current one is multiplied; the H3 operands come from LDS
+  f32x4 av[2][4], bv[2][4], bn[2][4];
+  auto bload = [&](int nb, int quarter, f32x4 (&B)[2][4]) {
+    const int wc = nb + (w & 1) * 64;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const f32x4* pb = (const f32x4*)&M.W4p[(long long)(wc + q * 32 + li) * kHidden + lh * 64 + quarter * 16];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) B[q][u] = pb[u];
+    }
+  };
+  bload(0, 0, bv);
   for (int nb = 0; nb < M.npad; nb += 128) {
     const int wc = nb + (w & 1) * 64;
     f32x16 acc[2][2];
@@ -318,13 +331,12 @@ __global__ __launch_bounds__(256, 2) void k_decode(ModelDev M, const uint8_t* co
         for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.0f;
 #pragma unroll 1
     for (int quarter = 0; quarter < 4; ++quarter) {
-      f32x4 av[2][4], bv[2][4];
+      if (quarter < 3 || nb + 128 < M.npad) bload(quarter < 3 ? nb : nb + 128, (quarter + 1) & 3, bn);
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
         const f32x4* pa = (const f32x4*)&H3[(wr + q * 32 + li) * kHPitch + lh * 64 + quarter * 16];
-        const f32x4* pb = (const f32x4*)&M.W4p[(long long)(wc + q * 32 + li) * kHidden + lh * 64 + quarter * 16];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) { av[q][u] = pa[u]; bv[q][u] = pb[u]; }
+        for (int u = 0; u < 4; ++u) av[q][u] = pa[u];
       }
 #pragma unroll
       for (int s = 0; s < 16; ++s)
@@ -333,6 +345,10 @@ __global__ __launch_bounds__(256, 2) void k_decode(ModelDev M, const uint8_t* co
 #pragma unroll
           for (int b = 0; b < 2; ++b)
             acc[a][b] = mfma32(av[a][s >> 2][s & 3], bv[b][s >> 2][s & 3], acc[a][b]);
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) bv[q][u] = bn[q][u];
     }
 #pragma unroll
     for (int a = 0; a < 2; ++a)
