@@ -56,7 +56,8 @@ enum { HCZ_F32 = 0, HCZ_F64 = 1 };                       /* element types */
 enum { HCZ_ARCH_DENSE = 1 };                              /* autoencoder architectures */
 enum { HCZ_TAU_REL_L2 = 0, HCZ_TAU_NRMSE = 1 };          /* tau_h = tau ||f||, tau sqrt(N)(max-min) */
 enum { HCZ_FALLBACK_BACKTRACK = 0, HCZ_FALLBACK_PAPER = 1 };
-enum { HCZ_FLAG_CODED = 1, HCZ_FLAG_ROUND2 = 2, HCZ_FLAG_RAW = 4, HCZ_FLAG_WARM_REJECTED = 8 };
+enum { HCZ_FLAG_CODED = 1, HCZ_FLAG_ROUND2 = 2, HCZ_FLAG_RAW = 4, HCZ_FLAG_WARM_REJECTED = 8,
+       HCZ_FLAG_NOCLIP = 16 };
 enum { HCZ_WARM_COLD = 0, HCZ_WARM_MLP = 1 };
 
 typedef struct hcz_ctx hcz_ctx;
@@ -108,7 +109,14 @@ typedef struct {
  * warm_start, mlp  HCZ_WARM_MLP: round 1 of the Newton solve starts from the warm-start
  *                  network's multipliers (hcz_compress with a model only); the start is
  *                  rejected, and the solve restarts cold, if its first Newton step makes
- *                  max_k |g_k| / sum_j |A_kj| x_j grow (flag HCZ_FLAG_WARM_REJECTED). */
+ *                  max_k |g_k| / sum_j |A_kj| x_j grow (flag HCZ_FLAG_WARM_REJECTED).
+ * lambda_fp32      1: store the multipliers as FP32 (the paper's float multipliers,
+ *                  Section I and Fig. 7: QoIs to about 1e-8 instead of 1e-14); the
+ *                  compressed batch's lambda_fp32 must say the same.
+ * no_positivity    1: the correction drops x >= 0 and becomes the orthogonal projection
+ *                  onto {A x = b}, f_c = f~ - A^T lam with (A A^T) lam = A f~ - b (one
+ *                  Newton step; flag HCZ_FLAG_NOCLIP); 0: the Stage-5 projection onto
+ *                  {A x = b, x >= 0}. */
 typedef struct {
   double tau;
   int32_t tau_mode;
@@ -120,6 +128,8 @@ typedef struct {
   int32_t sample_every;
   int32_t warm_start;
   const hcz_mlp* mlp;
+  int32_t lambda_fp32;
+  int32_t no_positivity;
 } hcz_params;
 
 /* Run statistics, written to device memory by compress and read with hcz_stats_read. */
@@ -134,16 +144,18 @@ typedef struct {
 } hcz_stats;
 
 /* Compressed batch.  codes [H][latent] (u8; unused without a model), lambda [H][4]
- * (FP64), flags [H] (u8, HCZ_FLAG_*), res_offset [H+1] (u64, exclusive scan of record
- * sizes), res_bytes [res_capacity] (records in histogram order), stats (device). */
+ * (FP64, or FP32 when lambda_fp32 = 1), flags [H] (u8, HCZ_FLAG_*), res_offset [H+1]
+ * (u64, exclusive scan of record sizes), res_bytes [res_capacity] (records in histogram
+ * order), stats (device). */
 typedef struct {
   uint8_t* codes;
-  double* lambda;
+  void* lambda;
   uint8_t* flags;
   uint64_t* res_offset;
   uint8_t* res_bytes;
   uint64_t res_capacity;
   hcz_stats* stats;
+  int32_t lambda_fp32;
 } hcz_compressed;
 
 /* ---- context, plan, model ------------------------------------------------------- */

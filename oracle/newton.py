@@ -11,7 +11,9 @@ is concave with gradient g = A x(lam) - b and Hessian -A diag(x > 0) A^T.  Eq. 6
 Newton step on it with step size s: lam <- lam + s H^-1 g, H = A diag(x > 0) A^T.
 
 Stopping rule: |g_k| <= 1e-13 * (sum_j |A_kj| x_j + 1e-300) for every k.
-Round 1: s = 1, at most 50 updates (Section III Stage 5).  Round 2 (for histograms
+Round 1: s = 1, at most 50 updates (Section III Stage 5).
+Without positivity (an alternative reading, `project_linear`) the correction is the
+orthogonal projection onto {A x = b}, whose multipliers solve (A A^T) lam = A ft - b.  Round 2 (for histograms
 round 1 leaves unconverged): from the round-1 multipliers, either Armijo backtracking
 on theta (default) or the fixed step s = 0.01, both with at most 400 updates.  A
 histogram that still fails is stored verbatim.  A Cholesky pivot <= 1e-14 trace(H)
@@ -114,8 +116,17 @@ def warm_ok(ft, A, b, lam0, s) -> bool:
     return scaled_residual(ft, A, b, lam0 + s * d) <= scaled_residual(ft, A, b, lam0)
 
 
+def project_linear(ft: np.ndarray, b: np.ndarray, g: Grid):
+    """Reading without positivity: the orthogonal projection of ft onto {A x = b},
+    x = ft - A^T lam with (A A^T) lam = A ft - b (the plain definition, one solve)."""
+    A = g.A()
+    ftv = np.asarray(ft, np.float64).reshape(-1)
+    lam = np.linalg.solve(A @ A.T, A @ ftv - b)
+    return dict(lam=lam, x=(ftv - A.T @ lam).reshape(np.shape(ft)), status=0, iters=1, warm_rejected=False)
+
+
 def project(ft: np.ndarray, b: np.ndarray, g: Grid, s: float = 1.0, max_iter: int = 50,
-            max_iter2: int = 400, fallback: str = "backtrack", lam0=None):
+            max_iter2: int = 400, fallback: str = "backtrack", lam0=None, positivity: bool = True):
     """Project one reconstruction ft (n_perp, n_par) onto {A x = b, x >= 0}.
 
     lam0: optional warm start; rejected (cold start, flag 'warm_rejected') if its first
@@ -123,6 +134,8 @@ def project(ft: np.ndarray, b: np.ndarray, g: Grid, s: float = 1.0, max_iter: in
     warm_rejected): status 0 = round 1 converged, 1 = round 2 converged, 2 = failed
     (store verbatim).
     """
+    if not positivity:
+        return project_linear(ft, b, g)
     A = g.A()
     ftv = np.asarray(ft, np.float64).reshape(-1)
     rejected = False
@@ -151,9 +164,14 @@ def _project_from(ftv, A, b, shape, lam, s, max_iter, max_iter2, fallback):
     return dict(lam=np.zeros(4), x=None, status=2, iters=it1 + it2)
 
 
-def apply(ft: np.ndarray, lam: np.ndarray, g: Grid) -> np.ndarray:
-    """Decompression-side correction f_c = max(0, ft - A^T lam) for one histogram."""
-    return x_of(np.asarray(ft, np.float64).reshape(-1), g.A(), np.asarray(lam, np.float64)).reshape(ft.shape)
+def apply(ft: np.ndarray, lam: np.ndarray, g: Grid, positivity: bool = True) -> np.ndarray:
+    """Decompression-side correction f_c = max(0, ft - A^T lam) (or ft - A^T lam without
+    positivity) for one histogram."""
+    ftv = np.asarray(ft, np.float64).reshape(-1)
+    lam = np.asarray(lam, np.float64)
+    if not positivity:
+        return (ftv - g.A().T @ lam).reshape(ft.shape)
+    return x_of(ftv, g.A(), lam).reshape(ft.shape)
 
 
 def project_bruteforce(ft: np.ndarray, b: np.ndarray, g: Grid):

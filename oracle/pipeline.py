@@ -14,7 +14,8 @@ Decompress: fhat from the codes, rhat from the record, ft = fhat + rhat,
 f_c = max(0, ft - A^T lam); verbatim records are returned as stored.
 
 Flags: bit0 coder record, bit1 round-2 Newton used, bit2 verbatim record, bit3 warm
-start rejected.  An optional warm-start network (oracle.mlp) seeds the Newton solve from
+start rejected, bit4 correction without positivity.  Multipliers can be stored as FP32
+(the paper's float multipliers, Section I and Fig. 7).  An optional warm-start network (oracle.mlp) seeds the Newton solve from
 the dequantised latent; the projection keeps cold start as fallback and judge.
 """
 from __future__ import annotations
@@ -28,7 +29,7 @@ from . import ae, coder, mlp as mlp_net, newton, pq
 from .grid import Grid
 from .moments import moments
 
-FLAG_CODED, FLAG_ROUND2, FLAG_RAW, FLAG_WARM_REJECTED = 1, 2, 4, 8
+FLAG_CODED, FLAG_ROUND2, FLAG_RAW, FLAG_WARM_REJECTED, FLAG_NOCLIP = 1, 2, 4, 8, 16
 
 
 @dataclass
@@ -39,6 +40,8 @@ class Params:
     newton_max_iter: int = 50
     newton_max_iter2: int = 400
     fallback: str = "backtrack"     # or "paper" (s = 0.01)
+    lambda_fp32: bool = False       # store the multipliers as FP32
+    positivity: bool = True         # False: projection onto {A x = b} only
 
 
 def tau_h(F64: np.ndarray, p: Params) -> np.ndarray:
@@ -108,7 +111,7 @@ def compress(F: np.ndarray, g: Grid, model: dict | None, C: np.ndarray | None, p
         if raw[h]:
             continue
         res = newton.project(ft[h], b[h], g, p.newton_s, p.newton_max_iter, p.newton_max_iter2,
-                             p.fallback, lam0=None if lam0 is None else lam0[h])
+                             p.fallback, lam0=None if lam0 is None else lam0[h], positivity=p.positivity)
         iters[h] = res["iters"]
         if res.get("warm_rejected"):
             flags[h] |= FLAG_WARM_REJECTED
@@ -119,6 +122,8 @@ def compress(F: np.ndarray, g: Grid, model: dict | None, C: np.ndarray | None, p
             continue
         lam[h] = res["lam"]
         fc[h] = res["x"]
+        if not p.positivity:
+            flags[h] |= FLAG_NOCLIP
     records = []
     for h in range(H):
         if raw[h]:
@@ -135,6 +140,8 @@ def compress(F: np.ndarray, g: Grid, model: dict | None, C: np.ndarray | None, p
     sizes = np.array([len(x) for x in records], np.uint64)
     offsets = np.zeros(H + 1, np.uint64)
     offsets[1:] = np.cumsum(sizes)
+    if p.lambda_fp32:
+        lam = lam.astype(np.float32)
     return dict(codes=codes, lam=lam, flags=flags, stream=b"".join(records), offsets=offsets,
                 codebook=C, b=b, tau_h=th, z=Z, fhat=fhat, rhat=rhat, ft=ft, fc=fc, kstar=kstar,
                 iters=iters)
@@ -160,5 +167,6 @@ def decompress(comp: dict, g: Grid, model: dict | None, C: np.ndarray | None, H:
         if fl & FLAG_CODED:
             qh, Delta, _ = coder.unpack(rec, lay)
             ft = fhat[h] + coder.reconstruct(qh[None], np.array([Delta]), lay)[0]
-        out[h] = newton.apply(ft, comp["lam"][h], g)
+        out[h] = newton.apply(ft, np.asarray(comp["lam"][h], np.float64), g,
+                              positivity=not comp["flags"][h] & FLAG_NOCLIP)
     return out

@@ -393,6 +393,8 @@ hcz_status check_params(const hcz_params* p) {
   if (p->fit_codebook && p->sample_every < 1) return fail(HCZ_EINVAL, "sample_every must be >= 1");
   if (p->warm_start != HCZ_WARM_COLD && p->warm_start != HCZ_WARM_MLP) return fail(HCZ_EINVAL, "warm_start");
   if (p->warm_start == HCZ_WARM_MLP && !p->mlp) return fail(HCZ_EINVAL, "warm_start needs an mlp");
+  if (p->lambda_fp32 != 0 && p->lambda_fp32 != 1) return fail(HCZ_EINVAL, "lambda_fp32 must be 0 or 1");
+  if (p->no_positivity != 0 && p->no_positivity != 1) return fail(HCZ_EINVAL, "no_positivity must be 0 or 1");
   return HCZ_OK;
 }
 
@@ -724,6 +726,8 @@ static hcz_status residual_impl(const hcz_plan* plan, const hcz_params* p, const
   a.max_iter2 = p->newton_max_iter2;
   a.fallback = p->fallback;
   a.lambda = out->lambda;
+  a.lambda_fp32 = p->lambda_fp32;
+  a.no_positivity = p->no_positivity;
   a.flags = out->flags;
   a.sizes = (uint64_t*)(ws + L.sizes);
   a.slots = ws + L.slots;
@@ -757,6 +761,7 @@ static hcz_status check_out(const hcz_compressed* out, int64_t H, bool codes) {
   if (!out) return fail(HCZ_EINVAL, "out is NULL");
   if (!out->res_offset || !out->stats) return fail(HCZ_EINVAL, "res_offset or stats is NULL");
   if (H > 0 && (!out->lambda || !out->flags)) return fail(HCZ_EINVAL, "lambda or flags is NULL");
+  if (out->lambda_fp32 != 0 && out->lambda_fp32 != 1) return fail(HCZ_EINVAL, "lambda_fp32 must be 0 or 1");
   if (H > 0 && codes && !out->codes) return fail(HCZ_EINVAL, "codes is NULL");
   if (out->res_capacity > 0 && !out->res_bytes) return fail(HCZ_EINVAL, "res_bytes is NULL");
   return HCZ_OK;
@@ -771,6 +776,7 @@ hcz_status hcz_residual(const hcz_plan* plan, const hcz_params* params, const vo
   if ((s = check_params(params)) || (s = check_hist(hist, dtype, H, hist_stride, row_stride, plan->G)) ||
       (s = check_out(out, H, false)))
     return s;
+  if (out->lambda_fp32 != params->lambda_fp32) return fail(HCZ_EINVAL, "out->lambda_fp32 differs from params");
   const WsLayout L = ws_layout(plan->G, false, H, dtype, false, 1);
   if (!ws || ws_bytes < L.total) return fail(HCZ_EWORKSPACE, "workspace %zu < %zu", ws_bytes, L.total);
   if ((s = set_device(plan->ctx))) return s;
@@ -789,6 +795,7 @@ hcz_status hcz_compress(const hcz_plan* plan, const hcz_model* model, hcz_codebo
   if ((s = check_params(params)) || (s = check_hist(hist, dtype, H, hist_stride, row_stride, plan->G)) ||
       (s = check_out(out, H, model != nullptr)))
     return s;
+  if (out->lambda_fp32 != params->lambda_fp32) return fail(HCZ_EINVAL, "out->lambda_fp32 differs from params");
   if (model && (s = check_cb(cb))) return s;
   const bool fit = model && params->fit_codebook;
   const WsLayout L = ws_layout(plan->G, model != nullptr, H, dtype, fit, params->sample_every);
@@ -839,6 +846,7 @@ hcz_status hcz_decompress(const hcz_plan* plan, const hcz_model* model, const hc
   if (in_dtype != HCZ_F32 && in_dtype != HCZ_F64) return fail(HCZ_EINVAL, "in_dtype");
   if (out_dtype != HCZ_F32 && out_dtype != HCZ_F64) return fail(HCZ_EINVAL, "out_dtype");
   if (H > 0 && (!out || !in->flags || !in->lambda || !in->res_offset)) return fail(HCZ_EINVAL, "NULL buffer");
+  if (in->lambda_fp32 != 0 && in->lambda_fp32 != 1) return fail(HCZ_EINVAL, "lambda_fp32 must be 0 or 1");
   if (in->res_capacity > 0 && !in->res_bytes) return fail(HCZ_EINVAL, "res_bytes is NULL");
   if (model && model->plan->G.N != plan->G.N) return fail(HCZ_EINVAL, "model was loaded for another grid");
   hcz_status s;
@@ -859,6 +867,7 @@ hcz_status hcz_decompress(const hcz_plan* plan, const hcz_model* model, const hc
   DecompressArgs a{};
   a.flags = in->flags;
   a.lambda = in->lambda;
+  a.lambda_fp32 = in->lambda_fp32;
   a.offsets = in->res_offset;
   a.stream = in->res_bytes;
   a.in_dtype = in_dtype;

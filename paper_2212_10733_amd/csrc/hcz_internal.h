@@ -87,7 +87,9 @@ struct ResidualArgs {
   int tau_mode;
   double newton_s;
   int max_iter, max_iter2, fallback;
-  double* lambda;              // [H][4]
+  void* lambda;                // [H][4] FP64, or FP32 when lambda_fp32
+  int lambda_fp32;
+  int no_positivity;           // 1: projection onto {A x = b} only (flag HCZ_FLAG_NOCLIP)
   uint8_t* flags;              // [H]
   uint64_t* sizes;             // [H] record bytes
   uint8_t* slots;              // [H][slot_stride] staging
@@ -99,7 +101,8 @@ struct ResidualArgs {
 
 struct DecompressArgs {
   const uint8_t* flags;
-  const double* lambda;
+  const void* lambda;          // FP64, or FP32 when lambda_fp32
+  int lambda_fp32;
   const uint64_t* offsets;
   const uint8_t* stream;
   int in_dtype;

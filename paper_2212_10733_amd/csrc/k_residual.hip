@@ -58,22 +58,30 @@ __device__ double recompose_err(const GridDev& G, double* buf, double* red, cons
 
 // Newton statistics of one pass at multipliers lam: v[0..3] = A x, v[4] = sum |A_1| x,
 // v[5..14] = A diag(x > 0) A^T (upper triangle, row-major), v[15] = ||x - ft||^2.
+// With pos = false (the projection onto {A x = b} alone) x may be negative: v[16..18]
+// then hold sum A_k |x| for k = 0, 2, 3 and v[4] sum |A_1| |x|, the stopping rule's scales.
+constexpr int kNv = 19;
 template <int NT, int NPT>
 __device__ void newton_pass(const double (&ftm)[NPT], const Aphi (&Am)[NPT], const int (&em)[NPT],
-                            const double (&lam)[4], double (&v)[16], double* red) {
+                            const double (&lam)[4], double (&v)[kNv], double* red, bool pos) {
 #pragma unroll
-  for (int k = 0; k < 16; ++k) v[k] = 0.0;
+  for (int k = 0; k < kNv; ++k) v[k] = 0.0;
 #pragma unroll
   for (int m = 0; m < NPT; ++m) {
     if (em[m] < 0) continue;
     const Aphi& A = Am[m];
-    const double x = fmax(0.0, ftm[m] - correction(A, lam));
+    const double y = ftm[m] - correction(A, lam);
+    const double x = pos ? fmax(0.0, y) : y;
+    const double xa = fabs(x);
     v[0] = fma(A.a0, x, v[0]);
     v[1] = fma(A.a1, x, v[1]);
     v[2] = fma(A.a2, x, v[2]);
     v[3] = fma(A.a3, x, v[3]);
-    v[4] = fma(fabs(A.a1), x, v[4]);
-    if (x > 0.0) {
+    v[4] = fma(fabs(A.a1), xa, v[4]);
+    v[16] = fma(A.a0, xa, v[16]);
+    v[17] = fma(A.a2, xa, v[17]);
+    v[18] = fma(A.a3, xa, v[18]);
+    if (!pos || x > 0.0) {
       v[5] = fma(A.a0, A.a0, v[5]);
       v[6] = fma(A.a0, A.a1, v[6]);
       v[7] = fma(A.a0, A.a2, v[7]);
@@ -88,11 +96,19 @@ __device__ void newton_pass(const double (&ftm)[NPT], const Aphi (&Am)[NPT], con
     const double dx = x - ftm[m];
     v[15] = fma(dx, dx, v[15]);
   }
-  block_sum<NT, 16>(v, red);
+  block_sum<NT, kNv>(v, red);
+}
+
+// Scales sum_j |A_kj| x_j of the stopping rule from a pass.
+__device__ __forceinline__ void pass_scales(const double (&v)[kNv], bool pos, double (&sc)[4]) {
+  sc[0] = pos ? v[0] : v[16];
+  sc[1] = v[4];
+  sc[2] = pos ? v[2] : v[17];
+  sc[3] = pos ? v[3] : v[18];
 }
 
 // theta(lam) = 1/2 ||x - ft||^2 + lam^T (A x - b) from a pass's statistics.
-__device__ __forceinline__ double theta_of(const double (&v)[16], const double (&lam)[4],
+__device__ __forceinline__ double theta_of(const double (&v)[kNv], const double (&lam)[4],
                                            const double (&b)[4]) {
   double t = 0.5 * v[15];
 #pragma unroll
@@ -101,7 +117,7 @@ __device__ __forceinline__ double theta_of(const double (&v)[16], const double (
 }
 
 // Solve H d = g by Cholesky; false if a pivot is not > kPivTol * trace(H).
-__device__ __forceinline__ bool chol_solve4(const double (&v)[16], const double (&g)[4],
+__device__ __forceinline__ bool chol_solve4(const double (&v)[kNv], const double (&g)[4],
                                             double (&d)[4]) {
   double Hm[4][4];
   Hm[0][0] = v[5]; Hm[0][1] = v[6]; Hm[0][2] = v[7]; Hm[0][3] = v[8];
@@ -149,14 +165,15 @@ __device__ __forceinline__ bool chol_solve4(const double (&v)[16], const double 
 template <int NT, int NPT>
 __device__ bool newton_round(const double (&ftm)[NPT], const Aphi (&Am)[NPT], const int (&em)[NPT],
                              const double (&b)[4], double (&lam)[4], double s, int max_iter,
-                             bool armijo, double* red, int* upd) {
-  double v[16];
+                             bool armijo, double* red, int* upd, bool pos) {
+  double v[kNv];
   for (int it = 0; it <= max_iter; ++it) {
-    newton_pass<NT, NPT>(ftm, Am, em, lam, v, red);
+    newton_pass<NT, NPT>(ftm, Am, em, lam, v, red, pos);
     double g[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) g[k] = v[k] - b[k];
-    const double sc[4] = {v[0], v[4], v[2], v[3]};
+    double sc[4];
+    pass_scales(v, pos, sc);
     bool conv = true;
 #pragma unroll
     for (int k = 0; k < 4; ++k) conv = conv && (fabs(g[k]) <= kGTol * (sc[k] + 1e-300));
@@ -177,8 +194,8 @@ __device__ bool newton_round(const double (&ftm)[NPT], const Aphi (&Am)[NPT], co
       for (int q = 0; q < kArmijoHalvings; ++q) {
 #pragma unroll
         for (int k = 0; k < 4; ++k) cand[k] = lam[k] + step * d[k];
-        double w[16];
-        newton_pass<NT, NPT>(ftm, Am, em, cand, w, red);
+        double w[kNv];
+        newton_pass<NT, NPT>(ftm, Am, em, cand, w, red, pos);
         if (theta_of(w, cand, b) >= t0 + kArmijoC * step * gd) { ok = true; break; }
         step *= 0.5;
       }
@@ -212,7 +229,7 @@ __global__ __launch_bounds__(NT) void k_residual(GridDev G, ResidualArgs a) {
   double* buf = smem;                                  // [N] residual, then reconstruction
   float* fh = (float*)(smem + N);                      // [N] reconstruction, then payload words
   uint32_t* words = (uint32_t*)fh;
-  double* red = smem + N + (N + 1) / 2;                // [NT/64 * 16]
+  double* red = smem + N + (N + 1) / 2;                // [NT/64 * kNv]
   __shared__ uint32_t s_width[kMaxLev], s_base[kMaxLev];
   const int t = threadIdx.x;
   const long long h = blockIdx.x;
@@ -396,15 +413,17 @@ __global__ __launch_bounds__(NT) void k_residual(GridDev G, ResidualArgs a) {
     if (a.lam0) {
       // warm start: keep it unless round 1 allows no update, its Cholesky step fails, or
       // that step makes max_k |g_k| / s_k grow
-      double l0[4], v[16], g[4], d[4];
+      double l0[4], v[kNv], g[4], d[4];
+      const bool pos = !a.no_positivity;
       bool ok0 = a.max_iter >= 1;
 #pragma unroll
       for (int k = 0; k < 4; ++k) { l0[k] = a.lam0[h * 4 + k]; ok0 = ok0 && isfinite(l0[k]); }
       if (ok0) {
-        newton_pass<NT, NPT>(ftm, Am, em, l0, v, red);
+        newton_pass<NT, NPT>(ftm, Am, em, l0, v, red, pos);
         double r0 = 0.0;
         bool conv = true;
-        const double sc[4] = {v[0], v[4], v[2], v[3]};
+        double sc[4];
+        pass_scales(v, pos, sc);
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
           g[k] = v[k] - b[k];
@@ -417,8 +436,9 @@ __global__ __launch_bounds__(NT) void k_residual(GridDev G, ResidualArgs a) {
             double l1[4];
 #pragma unroll
             for (int k = 0; k < 4; ++k) l1[k] = l0[k] + a.newton_s * d[k];
-            newton_pass<NT, NPT>(ftm, Am, em, l1, v, red);
-            const double sc1[4] = {v[0], v[4], v[2], v[3]};
+            newton_pass<NT, NPT>(ftm, Am, em, l1, v, red, pos);
+            double sc1[4];
+            pass_scales(v, pos, sc1);
             double r1 = 0.0;
 #pragma unroll
             for (int k = 0; k < 4; ++k) r1 = fmax(r1, fabs(v[k] - b[k]) / (sc1[k] + 1e-300));
@@ -434,16 +454,19 @@ __global__ __launch_bounds__(NT) void k_residual(GridDev G, ResidualArgs a) {
       }
     }
     int u1 = 0;
-    bool ok = newton_round<NT, NPT>(ftm, Am, em, b, lam, a.newton_s, a.max_iter, false, red, &u1);
+    bool ok = newton_round<NT, NPT>(ftm, Am, em, b, lam, a.newton_s, a.max_iter, false, red, &u1,
+                                    !a.no_positivity);
     total_upd = u1;
     if (!ok) {
       flags |= HCZ_FLAG_ROUND2;
       int u2 = 0;
       const bool paper = a.fallback == HCZ_FALLBACK_PAPER;
-      ok = newton_round<NT, NPT>(ftm, Am, em, b, lam, paper ? 0.01 : 1.0, a.max_iter2, !paper, red, &u2);
+      ok = newton_round<NT, NPT>(ftm, Am, em, b, lam, paper ? 0.01 : 1.0, a.max_iter2, !paper, red, &u2,
+                                 !a.no_positivity);
       total_upd += u2;
       if (!ok) raw = true;
     }
+    if (!raw && a.no_positivity) flags |= HCZ_FLAG_NOCLIP;
   }
 
   uint64_t size = 0;
@@ -466,7 +489,11 @@ __global__ __launch_bounds__(NT) void k_residual(GridDev G, ResidualArgs a) {
   }
   if (t == 0) {
 #pragma unroll
-    for (int k = 0; k < 4; ++k) a.lambda[h * 4 + k] = raw ? 0.0 : lam[k];
+    for (int k = 0; k < 4; ++k) {
+      const double lv = raw ? 0.0 : lam[k];
+      if (a.lambda_fp32) ((float*)a.lambda)[h * 4 + k] = (float)lv;
+      else ((double*)a.lambda)[h * 4 + k] = lv;
+    }
     a.flags[h] = (uint8_t)flags;
     a.sizes[h] = size;
     a.kstar[h] = (uint8_t)kst;
@@ -577,7 +604,9 @@ __global__ __launch_bounds__(NT) void k_decompress(GridDev G, DecompressArgs a) 
   const uint8_t* payload = rec + G.hdr_bytes;
   double lam[4];
 #pragma unroll
-  for (int k = 0; k < 4; ++k) lam[k] = a.lambda[h * 4 + k];
+  for (int k = 0; k < 4; ++k)
+    lam[k] = a.lambda_fp32 ? (double)((const float*)a.lambda)[h * 4 + k] : ((const double*)a.lambda)[h * 4 + k];
+  const bool clip = (fl & HCZ_FLAG_NOCLIP) == 0;
   int em[NPT], gm[NPT];
   Interp cm[NPT];
   double dq[NPT], ym[NPT];
@@ -630,7 +659,8 @@ __global__ __launch_bounds__(NT) void k_decompress(GridDev G, DecompressArgs a) 
     const float fv = fhp ? fhp[e] : 0.0f;
     const double ft = (double)fv + ym[m];
     const Aphi A = make_aphi(G, e, i, j);
-    ym[m] = fmax(0.0, ft - correction(A, lam));
+    const double y = ft - correction(A, lam);
+    ym[m] = clip ? fmax(0.0, y) : y;
   }
   __syncthreads();
 #pragma unroll
@@ -647,7 +677,7 @@ hipError_t launch_residual(const GridDev& G, const ResidualArgs& a, hipStream_t 
   if (a.H <= 0) return hipSuccess;
   if (wave_path(G)) return launch_residual_w(G, a, st);
   const int nt = pick_nt(G.N);
-  const size_t lds = (size_t)G.N * 8 + (size_t)((G.N + 1) / 2) * 8 + (size_t)(nt / 64) * 16 * 8;
+  const size_t lds = (size_t)G.N * 8 + (size_t)((G.N + 1) / 2) * 8 + (size_t)(nt / 64) * kNv * 8;
   dim3 grid((unsigned)a.H), block(nt);
 #define HCZ_RES(NT, T) hipLaunchKernelGGL((k_residual<NT, 6, T>), grid, block, lds, st, G, a)
   if (a.dtype == HCZ_F32) {

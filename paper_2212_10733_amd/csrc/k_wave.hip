@@ -412,29 +412,35 @@ __device__ __forceinline__ void for_columns(const GridDev& G, BEGIN begin, BODY 
 // cells, w^2, w^2 c, w^2 c^2 come first and are then weighted by the column's powers of
 // a.  The correction per cell is vol * ((lam3 a + lam1) a + lam0 + lam2 c), one fixed
 // order for compression and decompression.
-template <class SH, bool UVOL, bool THETA>
+template <class SH, bool UVOL, bool THETA, bool POS>
 __device__ __forceinline__ void newton_pass_w(const GridDev& G, const WaveLds& L, const double (&lam)[4],
-                                              double (&v)[16], double (&hh)[9]) {
-  double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0, v4 = 0.0, v15 = 0.0;
+                                              double (&v)[16], double (&sc)[4], double (&hh)[9]) {
+  double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0, v4 = 0.0, v15 = 0.0, c0 = 0.0, c2 = 0.0, c3 = 0.0;
 #pragma unroll
   for (int k = 0; k < 9; ++k) hh[k] = 0.0;
-  double sx, sxc, h0, hc, hcc, s2;
+  double sx, sxc, sxa, sxca, h0, hc, hcc, s2;
   double pa = 0.0;
   auto begin = [&](int i) {
     const double a = G.apar[i];
     pa = fma(fma(lam[3], a, lam[1]), a, lam[0]);
-    sx = sxc = h0 = hc = hcc = s2 = 0.0;
+    sx = sxc = sxa = sxca = h0 = hc = hcc = s2 = 0.0;
   };
   auto body = [&](int i, int j, uint32_t off) {
     const double c = L.s_cc[2 * j], c2 = L.s_cc[2 * j + 1];
     const double w = UVOL ? G.vol0 : G.vol[j * G.n_par + i];
     const double ft = ldy(L.yb, off);
-    const double x = fmax(0.0, ft - w * fma(lam[2], c, pa));
+    const double y = ft - w * fma(lam[2], c, pa);
+    const double x = POS ? fmax(0.0, y) : y;
     const double wx = UVOL ? x : w * x;
     sx += wx;
     sxc = fma(c, wx, sxc);
+    if (!POS) {                      // the stopping rule's scales use |x| when x may be negative
+      const double wxa = fabs(wx);
+      sxa += wxa;
+      sxca = fma(c, wxa, sxca);
+    }
     // Hessian terms on active cells, as a 0/1 weight (exact: products with 0 or 1)
-    const double act = x > 0.0 ? 1.0 : 0.0;
+    const double act = (!POS || x > 0.0) ? 1.0 : 0.0;
     const double w2 = UVOL ? act : act * (w * w);
     h0 += w2;
     hc = fma(w2, c, hc);
@@ -450,8 +456,13 @@ __device__ __forceinline__ void newton_pass_w(const GridDev& G, const WaveLds& L
     v1 = fma(a, sx, v1);
     v2 += sxc;
     v3 = fma(a2, sx, v3);
-    v4 = fma(fabs(a), sx, v4);
+    v4 = fma(fabs(a), POS ? sx : sxa, v4);
     v15 += s2;
+    if (!POS) {
+      c0 += sxa;
+      c2 += sxca;
+      c3 = fma(a2, sxa, c3);
+    }
     hh[0] += h0;
     hh[1] = fma(a, h0, hh[1]);
     hh[2] += hc;
@@ -483,6 +494,19 @@ __device__ __forceinline__ void newton_pass_w(const GridDev& G, const WaveLds& L
   if (UVOL) {
 #pragma unroll
     for (int k = 0; k < 5; ++k) v[k] *= G.vol0;
+  }
+  // scales sum_j |A_kj| x_j of the stopping rule (every A entry but k = 1 is >= 0)
+  if (POS) {
+    sc[0] = v[0];
+    sc[1] = v[4];
+    sc[2] = v[2];
+    sc[3] = v[3];
+  } else {
+    const double s1 = UVOL ? G.vol0 : 1.0;
+    sc[0] = wsum(c0) * s1;
+    sc[1] = v[4];
+    sc[2] = wsum(c2) * s1;
+    sc[3] = wsum(c3) * s1;
   }
 }
 
@@ -553,7 +577,7 @@ __device__ __forceinline__ bool chol4(const double (&v)[16], const double (&g)[4
 // to max2 updates.  An accepted Armijo candidate's pass is also the next iterate's pass
 // (same multipliers, same values).  Returns 0 (round 1 converged), 1 (round 2
 // converged) or 2 (failed); *upd counts the updates.
-template <class SH, bool UVOL>
+template <class SH, bool UVOL, bool POS>
 __device__ __forceinline__ int newton_w(const GridDev& G, const WaveLds& L, const double (&b)[4], double (&lam)[4],
                                         double s1, int max1, double s2, int max2, bool armijo2, int* upd,
                                         bool have_init, const double (&lam_init)[4], bool* rejected) {
@@ -579,11 +603,11 @@ __device__ __forceinline__ int newton_w(const GridDev& G, const WaveLds& L, cons
   double v[16];
 #pragma unroll
   for (int k = 0; k < 16; ++k) v[k] = 0.0;
-  double hh[9];
+  double hh[9], sc[4];
   auto hessian = [&]() { hess_reduce<UVOL>(G, hh, v); };
   for (;;) {
-    if (round == 1 && armijo2) newton_pass_w<SH, UVOL, true>(G, L, cand, v, hh);
-    else newton_pass_w<SH, UVOL, false>(G, L, cand, v, hh);
+    if (round == 1 && armijo2) newton_pass_w<SH, UVOL, true, POS>(G, L, cand, v, sc, hh);
+    else newton_pass_w<SH, UVOL, false, POS>(G, L, cand, v, sc, hh);
     if (trial) {
       if (theta_w(v, cand, b) >= t0 + kArmijoC * step * gd) {
 #pragma unroll
@@ -603,7 +627,6 @@ __device__ __forceinline__ int newton_w(const GridDev& G, const WaveLds& L, cons
     double g[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) g[k] = v[k] - b[k];
-    const double sc[4] = {v[0], v[4], v[2], v[3]};
     bool conv = true;
     double rs = 0.0;
 #pragma unroll
@@ -974,11 +997,15 @@ __global__ __launch_bounds__(256, 2) void k_residual_w(GridDev G, ResidualArgs a
       for (int k = 0; k < 4; ++k) l0[k] = a.lam0[h * 4 + k];
     }
     bool rejected = false;
-    const int st = newton_w<SH, UVOL>(G, L, b, lam, a.newton_s, a.max_iter, paper ? 0.01 : 1.0, a.max_iter2, !paper,
-                                  &total_upd, a.lam0 != nullptr, l0, &rejected);
+    const int st = a.no_positivity
+                       ? newton_w<SH, UVOL, false>(G, L, b, lam, a.newton_s, a.max_iter, paper ? 0.01 : 1.0,
+                                                   a.max_iter2, !paper, &total_upd, a.lam0 != nullptr, l0, &rejected)
+                       : newton_w<SH, UVOL, true>(G, L, b, lam, a.newton_s, a.max_iter, paper ? 0.01 : 1.0,
+                                                  a.max_iter2, !paper, &total_upd, a.lam0 != nullptr, l0, &rejected);
     if (rejected) flags |= HCZ_FLAG_WARM_REJECTED;
     if (st >= 1) flags |= HCZ_FLAG_ROUND2;
     if (st == 2) raw = true;
+    if (!raw && a.no_positivity) flags |= HCZ_FLAG_NOCLIP;
   }
 
   uint64_t size = 0;
@@ -996,7 +1023,11 @@ __global__ __launch_bounds__(256, 2) void k_residual_w(GridDev G, ResidualArgs a
   }
   if (lane == 0) {
 #pragma unroll
-    for (int k = 0; k < 4; ++k) a.lambda[h * 4 + k] = raw ? 0.0 : lam[k];
+    for (int k = 0; k < 4; ++k) {
+      const double lv = raw ? 0.0 : lam[k];
+      if (a.lambda_fp32) ((float*)a.lambda)[h * 4 + k] = (float)lv;
+      else ((double*)a.lambda)[h * 4 + k] = lv;
+    }
     a.flags[h] = (uint8_t)flags;
     a.sizes[h] = size;
     a.kstar[h] = (uint8_t)kst;
@@ -1094,7 +1125,9 @@ __global__ __launch_bounds__(256, 2) void k_decompress_w(GridDev G, DecompressAr
   }
   double lam[4];
 #pragma unroll
-  for (int k = 0; k < 4; ++k) lam[k] = a.lambda[h * 4 + k];
+  for (int k = 0; k < 4; ++k)
+    lam[k] = a.lambda_fp32 ? (double)((const float*)a.lambda)[h * 4 + k] : ((const double*)a.lambda)[h * 4 + k];
+  const bool clip = (fl & HCZ_FLAG_NOCLIP) == 0;
   double pa = 0.0;
   for_columns_pre(
       G,
@@ -1107,7 +1140,8 @@ __global__ __launch_bounds__(256, 2) void k_decompress_w(GridDev G, DecompressAr
         const double hv = (double)h;
         const double ft = coded ? hv + ldy(L.yb, off) : hv;
         const double w = UVOL ? G.vol0 : G.vol[j * G.n_par + i];
-        out[j * G.n_par + i] = (TOut)fmax(0.0, ft - w * fma(lam[2], L.s_cc[2 * j], pa));
+        const double y = ft - w * fma(lam[2], L.s_cc[2 * j], pa);
+        out[j * G.n_par + i] = (TOut)(clip ? fmax(0.0, y) : y);
       },
       [](int) {});
 }

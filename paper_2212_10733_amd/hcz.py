@@ -53,7 +53,8 @@ class Params(C.Structure):
     _fields_ = [("tau", C.c_double), ("tau_mode", C.c_int32), ("newton_s", C.c_double),
                 ("newton_max_iter", C.c_int32), ("newton_max_iter2", C.c_int32),
                 ("fallback", C.c_int32), ("fit_codebook", C.c_int32), ("sample_every", C.c_int32),
-                ("warm_start", C.c_int32), ("mlp", C.c_void_p)]
+                ("warm_start", C.c_int32), ("mlp", C.c_void_p), ("lambda_fp32", C.c_int32),
+                ("no_positivity", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -72,7 +73,7 @@ class Stats(C.Structure):
 class CompressedC(C.Structure):
     _fields_ = [("codes", C.c_void_p), ("lambda_", C.c_void_p), ("flags", C.c_void_p),
                 ("res_offset", C.c_void_p), ("res_bytes", C.c_void_p),
-                ("res_capacity", C.c_uint64), ("stats", C.c_void_p)]
+                ("res_capacity", C.c_uint64), ("stats", C.c_void_p), ("lambda_fp32", C.c_int32)]
 
 
 def _load() -> C.CDLL:
@@ -257,10 +258,11 @@ class Model:
 
 
 def params(tau=1e-3, tau_mode=TAU_REL_L2, newton_s=1.0, newton_max_iter=50, newton_max_iter2=400,
-           fallback=FALLBACK_BACKTRACK, fit_codebook=False, sample_every=16, mlp=None) -> Params:
+           fallback=FALLBACK_BACKTRACK, fit_codebook=False, sample_every=16, mlp=None, lambda_fp32=False,
+           no_positivity=False) -> Params:
     p = Params(tau, tau_mode, newton_s, newton_max_iter, newton_max_iter2, fallback,
                int(fit_codebook), sample_every, WARM_MLP if mlp is not None else WARM_COLD,
-               None if mlp is None else mlp.h)
+               None if mlp is None else mlp.h, int(lambda_fp32), int(no_positivity))
     p._mlp = mlp          # keep the network alive as long as the parameters
     return p
 
@@ -300,7 +302,7 @@ def dequantize(codes: torch.Tensor, centroids: torch.Tensor) -> torch.Tensor:
 @dataclass
 class Compressed:
     codes: torch.Tensor        # (H, latent) uint8
-    lam: torch.Tensor          # (H, 4) float64
+    lam: torch.Tensor          # (H, 4) float64, or float32 for FP32 multipliers
     flags: torch.Tensor        # (H,) uint8
     offsets: torch.Tensor      # (H + 1,) int64 (u64 bits)
     stream: torch.Tensor       # (capacity,) uint8
@@ -309,7 +311,7 @@ class Compressed:
     def cstruct(self) -> CompressedC:
         return CompressedC(self.codes.data_ptr(), self.lam.data_ptr(), self.flags.data_ptr(),
                            self.offsets.data_ptr(), self.stream.data_ptr(), self.stream.numel(),
-                           self.stats_dev.data_ptr())
+                           self.stats_dev.data_ptr(), int(self.lam.dtype == torch.float32))
 
     def stats(self) -> dict:
         s = Stats()
@@ -325,12 +327,12 @@ class Compressed:
 
 
 def alloc_compressed(H: int, N: int, device, latent=LATENT, capacity: int | None = None,
-                     in_bytes: int = 4) -> Compressed:
+                     in_bytes: int = 4, lambda_fp32: bool = False) -> Compressed:
     if capacity is None:
         capacity = H * (24 + in_bytes * N)
     return Compressed(
         codes=torch.zeros((H, latent), dtype=torch.uint8, device=device),
-        lam=torch.zeros((H, 4), dtype=torch.float64, device=device),
+        lam=torch.zeros((H, 4), dtype=torch.float32 if lambda_fp32 else torch.float64, device=device),
         flags=torch.zeros(H, dtype=torch.uint8, device=device),
         offsets=torch.zeros(H + 1, dtype=torch.int64, device=device),
         stream=torch.empty(max(capacity, 16), dtype=torch.uint8, device=device),
@@ -404,7 +406,8 @@ def residual(plan: Plan, p: Params, hist: torch.Tensor, fhat: torch.Tensor | Non
     nbytes = C.c_size_t()
     _check(LIB.hcz_compress_workspace(plan.h, None, H, C.byref(p), C.byref(nbytes)))
     ws = workspace(nbytes.value, hist.device)
-    out = alloc_compressed(H, plan.N, hist.device, capacity=capacity, in_bytes=hist.element_size())
+    out = alloc_compressed(H, plan.N, hist.device, capacity=capacity, in_bytes=hist.element_size(),
+                           lambda_fp32=bool(p.lambda_fp32))
     cs = out.cstruct()
     fh = None if fhat is None else fhat.contiguous()
     l0 = None if lam0 is None else lam0.contiguous()
@@ -429,7 +432,8 @@ class Compressor:
         _check(LIB.hcz_decompress_workspace(plan.h, None if model is None else model.h, H, C.byref(nbytes)))
         self.dws = workspace(nbytes.value, device)
         esz = 4 if in_dtype == torch.float32 else 8
-        self.out = alloc_compressed(H, plan.N, device, capacity=capacity, in_bytes=esz)
+        self.out = alloc_compressed(H, plan.N, device, capacity=capacity, in_bytes=esz,
+                                    lambda_fp32=bool(p.lambda_fp32))
         self.centroids = torch.zeros((LATENT, 1 << bits), dtype=torch.float32, device=device)
         self.bits = bits
 

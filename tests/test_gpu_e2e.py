@@ -119,6 +119,38 @@ def test_compress_without_model_bit_exact(H, ctx):
     check_roundtrip(F, out, comp.flags.cpu().numpy(), 1e-3, g)
 
 
+@pytest.mark.parametrize("lambda_fp32,no_positivity", [(True, False), (False, True)])
+def test_stage5_variants_end_to_end(H, ctx, lambda_fp32, no_positivity):
+    """Compress and decompress with FP32 multipliers or without positivity: the stream is
+    the oracle's byte for byte, the bound holds, and the QoIs are restored to the
+    variant's accuracy (FP32 multipliers: about 1e-8, Section I)."""
+    say("e2e stage-5 variant", lambda_fp32, no_positivity)
+    g = grid.make_grid()
+    F = synth.histograms(300, seed=45, dtype=np.float32)
+    plan = H.Plan(ctx)
+    hp = H.params(tau=1e-3, lambda_fp32=lambda_fp32, no_positivity=no_positivity)
+    cz = H.Compressor(plan, None, 300, hp)
+    comp = cz.compress(torch.from_numpy(F).cuda())
+    out = cz.decompress(comp, 300).cpu().numpy()
+    p = pipeline.Params(tau=1e-3, lambda_fp32=lambda_fp32, positivity=not no_positivity)
+    ref = pipeline.compress(F, g, None, None, p)
+    assert comp.stream_bytes() == ref["stream"]
+    assert np.array_equal(comp.flags.cpu().numpy(), ref["flags"])
+    refout = pipeline.decompress(ref, g, None, None, 300)
+    assert np.allclose(out, refout, rtol=1e-6, atol=1e-9 * np.abs(F).max())
+    raw = (ref["flags"] & 4) != 0
+    F64 = F.astype(np.float64)
+    th = pipeline.tau_h(F64, p)
+    dist = np.sqrt(((out - F64) ** 2).reshape(300, -1).sum(1))
+    assert np.all(dist[~raw] <= th[~raw])
+    err = moments.qoi_rel_error(moments.qoi(F64, g), moments.qoi(out, g), g)[~raw].max(axis=1)
+    if lambda_fp32:
+        assert 1e-11 < np.median(err) < 1e-5
+    else:
+        assert err.max() < 1e-10
+        assert (out < 0).any()
+
+
 def test_determinism_and_empty_batch(H, ctx):
     say("determinism")
     F = synth.histograms(500, seed=42, dtype=np.float32)

@@ -182,7 +182,7 @@ def oracle_residual(F, fhat, g, p, lam0=None):
         flag = 0
         if not raw[h]:
             res = oracle.newton.project(fh[h], b[h], g, p.newton_s, p.newton_max_iter, p.newton_max_iter2, p.fallback,
-                                        lam0=None if lam0 is None else lam0[h])
+                                        lam0=None if lam0 is None else lam0[h], positivity=p.positivity)
             out["iters"][h] = res["iters"]
             if res.get("warm_rejected"):
                 flag |= 8
@@ -193,6 +193,7 @@ def oracle_residual(F, fhat, g, p, lam0=None):
             else:
                 out["lam"][h] = res["lam"]
                 flag |= pipeline.FLAG_CODED if coded[h] else 0
+                flag |= 0 if p.positivity else pipeline.FLAG_NOCLIP
         if raw[h]:
             flag = (flag & (pipeline.FLAG_ROUND2 | 8)) | pipeline.FLAG_RAW
             rec = np.ascontiguousarray(F[h]).tobytes()
@@ -341,6 +342,32 @@ def test_decompress_reads_oracle_stream(H, ctx, dtype):
     out = cz.decompress(cmp_, 50, in_dtype=torch.float32 if dtype == np.float32 else torch.float64).cpu().numpy()
     both_nan = np.isnan(out) & np.isnan(ref)
     assert np.all(both_nan | np.isclose(out, ref, rtol=1e-13, atol=1e-15 * np.nanmax(np.abs(ref))))
+
+
+@pytest.mark.parametrize("shape", [(39, 39), (33, 37), (65, 65)])
+def test_residual_stage5_variants(H, ctx, shape):
+    """Correction without positivity: flags (bit 4), records and multipliers equal the
+    oracle's closed form.  FP32 multipliers: the FP64 solution rounded (one FP32 ulp)."""
+    n_perp, n_par = shape
+    say("stage-5 variants", shape)
+    g = grid.make_grid(n_par, n_perp)
+    plan = H.Plan(ctx, n_par, n_perp)
+    F = synth.histograms(96, n_par, n_perp, seed=43, dtype=np.float32)
+    fhat = synth.perturbed(F, np.geomspace(1e-4, 5e-2, 96), seed=44)
+    p = pipeline.Params(tau=1e-3, positivity=False)
+    comp, ref, _ = compare_residual(H, plan, g, F, fhat, p, H.params(tau=1e-3, no_positivity=True))
+    flags = comp.flags.cpu().numpy()
+    raw = (flags & 4) != 0
+    assert np.all((flags[~raw] & 16) != 0) and not np.any(flags[raw] & 16)
+    p32 = pipeline.Params(tau=1e-3)
+    c32 = H.residual(plan, H.params(tau=1e-3, lambda_fp32=True), to_dev(F), to_dev(fhat))
+    assert c32.lam.dtype == torch.float32
+    ref = oracle_residual(F, fhat, g, p32)
+    lam32 = c32.lam.cpu().numpy()
+    ok = ~ref["raw"]
+    want = ref["lam"][ok].astype(np.float32)
+    ulp = np.spacing(np.abs(want)).astype(np.float64)
+    assert np.all(np.abs(lam32[ok].astype(np.float64) - want.astype(np.float64)) <= ulp)
 
 
 @pytest.mark.parametrize("shape", [(39, 39), (65, 65)])

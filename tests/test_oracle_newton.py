@@ -157,3 +157,30 @@ def test_mlp_backward_matches_autograd():
         assert np.allclose(g[k], t[k].grad.numpy(), rtol=1e-10, atol=1e-12)
     assert synth.mlp_weights()["W1"].shape == (64, 16)
     assert sum(v.size for v in synth.mlp_weights().values()) == 5508
+
+
+def test_projection_without_positivity():
+    """project_linear: A x = b, x - ft orthogonal to the null space of A (an SVD basis,
+    not the normal equations the oracle solves), negative values kept, and equal to the
+    Stage-5 projection when no cell reaches zero."""
+    g = grid.make_grid()
+    F = synth.histograms(4, seed=21, dtype=np.float64)
+    rng = np.random.default_rng(22)
+    A = g.A()
+    _, _, Vt = np.linalg.svd(A)
+    Z = Vt[4:].T                                  # orthonormal basis of null(A)
+    for f in F:
+        ft = f + 0.05 * f.max() * rng.normal(size=f.shape)     # plenty of negative cells
+        b = moments.moments(f, g)
+        res = newton.project_linear(ft, b, g)
+        x = res["x"].reshape(-1)
+        assert np.allclose(A @ x, b, rtol=1e-12, atol=1e-14 * np.abs(b).max())
+        assert np.abs(Z.T @ (x - ft.reshape(-1))).max() < 1e-12 * np.abs(ft).max()
+        assert (x < 0).any()
+        assert np.allclose(newton.apply(ft, res["lam"], g, positivity=False), res["x"], rtol=0, atol=1e-15)
+    g, f, ft = positive_case(seed=23)
+    b = moments.moments(f, g)
+    lin = newton.project_linear(ft, b, g)
+    pos = newton.project(ft, b, g)
+    assert np.all(lin["x"] > 0)
+    assert np.allclose(lin["lam"], pos["lam"], rtol=1e-10, atol=1e-14)

@@ -113,3 +113,27 @@ def test_warm_start_network_keeps_the_solution():
     ok = (cold["flags"] & pipeline.FLAG_RAW) == 0
     assert np.allclose(warm["fc"][ok], cold["fc"][ok], rtol=1e-10, atol=1e-13)
     assert warm["stream"] == cold["stream"]
+
+
+@pytest.mark.parametrize("lambda_fp32,positivity", [(True, True), (False, False), (True, False)])
+def test_stage5_variants_roundtrip(lambda_fp32, positivity):
+    """FP32 multipliers (the paper's float storage: QoIs to ~1e-8 rather than ~1e-14) and
+    the correction without positivity (flag bit 4): the bound holds on every histogram."""
+    g = grid.make_grid()
+    F = synth.histograms(24, seed=24, dtype=np.float64)
+    p = pipeline.Params(tau=1e-3, lambda_fp32=lambda_fp32, positivity=positivity)
+    comp = pipeline.compress(F, g, None, None, p)
+    assert comp["lam"].dtype == (np.float32 if lambda_fp32 else np.float64)
+    raw = (comp["flags"] & pipeline.FLAG_RAW) != 0
+    assert np.all(((comp["flags"] & pipeline.FLAG_NOCLIP) != 0) == (~raw & (not positivity)))
+    out = pipeline.decompress(comp, g, None, None, 24, np.float64)
+    th = pipeline.tau_h(F, p)
+    dist = np.sqrt(((out - F) ** 2).reshape(24, -1).sum(1))
+    assert np.all(dist[~raw] <= th[~raw])
+    err = moments.qoi_rel_error(moments.qoi(F, g), moments.qoi(out, g), g)[~raw].max(axis=1)
+    if lambda_fp32:
+        assert 1e-11 < np.median(err) < 1e-5
+    else:
+        assert err.max() < 1e-11
+    if not positivity:
+        assert (out < 0).any()                     # negative values survive without positivity
