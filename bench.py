@@ -119,6 +119,36 @@ def time_compress(cz, x, steps):
     return (time.perf_counter() - t0) / steps, comp
 
 
+def tau_sweep(hcz, plan, model, x, args) -> dict:
+    """The plain form at the other bounds of the workload's tau set: throughput, coded
+    fraction p, stream size, compression ratio, QoI error and the bound on the batch."""
+    import torch
+    H = x.shape[0]
+    N = plan.N
+    out = {}
+    _, q0, n0 = hcz.qoi(plan, x)
+    den = torch.stack([q0[:, 0].abs(), torch.maximum(q0[:, 1].abs(), q0[:, 3].abs().sqrt()),
+                       q0[:, 2].abs(), q0[:, 3].abs()], 1)
+    for tau in (1e-2, 1e-4):
+        log(f"tau sweep: {tau}")
+        cz = hcz.Compressor(plan, model, H, hcz.params(tau=tau, fit_codebook=True, sample_every=16))
+        dt, comp = time_compress(cz, x, 3)
+        s = comp.stats()
+        o = cz.decompress(comp, H)
+        _, q1, _ = hcz.qoi(plan, o)
+        ok = (comp.flags & 4) == 0
+        stored = H * 16 + H * 32 + H + s["stream_bytes"] + 395265 * 4 + 16 * 256 * 4 + 44
+        out[f"{tau:g}"] = {
+            "value": H / dt, "ms_per_step": dt * 1e3, "coded_frac": s["n_coded"] / H, "raw": s["n_raw"],
+            "stream_bytes": s["stream_bytes"], "compression_ratio": H * N * 4 / stored,
+            "newton_mean_updates": s["newton_iters_total"] / max(1, H - s["n_raw"]),
+            "max_qoi_rel_err": ((q1 - q0).abs() / den)[ok].max().item(),
+            "max_err_over_tau_h": ((o - x.double()).reshape(H, -1).norm(dim=1)[ok] / (tau * n0[ok])).max().item(),
+        }
+        del cz, comp, o
+    return out
+
+
 def other_forms(hcz, plan, ctx, x, F, W, args, plain_value, plain_stats) -> dict:
     """The same batch and tau through (a) the coder-only pipeline and (b) the learned form:
     the autoencoder trained by the library's kernels on held-apart synthetic histograms,
@@ -314,7 +344,8 @@ def main() -> int:
 
     forms = {}
     if not args.no_forms:
-        forms = other_forms(hcz, plan, ctx, x, F, W, args, value, st)
+        forms["tau_sweep"] = tau_sweep(hcz, plan, model, x, args)
+        forms.update(other_forms(hcz, plan, ctx, x, F, W, args, value, st))
 
     cpu = None
     if not args.no_cpu:
