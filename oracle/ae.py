@@ -117,3 +117,56 @@ def adam_step(params: dict, grads: dict, state: dict, lr=1e-3, b1=0.9, b2=0.999,
         vh = v / (1 - b2 ** t)
         params[k] = params[k] - lr * mh / (np.sqrt(vh) + eps)
     return params
+
+
+# ---- BF16 form (matrix-core operands rounded to bfloat16, sums in higher precision) ----
+#
+# The dense model again, with the two large products taking bfloat16 operands: the
+# encoder's input x and W1, the decoder's hidden h3 and W4.  Where a rounding to bfloat16
+# decides a value, it is taken from the FP32 value the kernel forms (the rule for
+# decisions made in floating point): x = (f - mu) * (1/sigma) in FP32, h3 by the FP32
+# fused multiply-add chain b3 + sum_d zhat_d W3_cd in order d = 0..15.  The products of
+# bfloat16 values are exact in FP64 and are summed there.
+
+def bf16(x) -> np.ndarray:
+    """Round FP32 values to the nearest bfloat16 (ties to even), returned as FP32.
+    Finite inputs only."""
+    u = np.ascontiguousarray(x, np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32)
+
+
+def fma32(a, b, c) -> np.ndarray:
+    """FP32 fused multiply-add round(a b + c): the product of two FP32 values is exact in
+    FP64, and the FP64 sum is rounded to FP32 (a second rounding that can only matter
+    when the FP64 sum ties two FP32 values, which the tests' margins exclude)."""
+    return (np.float64(a) * np.float64(b) + np.float64(c)).astype(np.float32)
+
+
+def bf16_encode_input(F32: np.ndarray, mu32: np.ndarray, rsd32: np.ndarray) -> np.ndarray:
+    """x = (f - mu) * rsd in FP32 (non-finite inputs as 0), rounded to bfloat16."""
+    f = np.where(np.isfinite(F32), F32, np.float32(0)).astype(np.float32)
+    return bf16((f - mu32.astype(np.float32)) * rsd32.astype(np.float32))
+
+
+def dense_encode_bf16(F32: np.ndarray, mu32, rsd32, W: dict) -> np.ndarray:
+    """Latents of the BF16 form: h1 = relu(bf16(x) bf16(W1)^T + b1), z = h1 W2^T + b2."""
+    H = F32.shape[0]
+    xb = bf16_encode_input(F32.reshape(H, -1), mu32, rsd32).astype(np.float64)
+    w1 = bf16(np.asarray(W["W1"], np.float32)).astype(np.float64)
+    h1 = relu(xb @ w1.T + np.asarray(W["b1"], np.float64))
+    return h1 @ np.asarray(W["W2"], np.float64).T + np.asarray(W["b2"], np.float64)
+
+
+def dense_decode_bf16(Zh: np.ndarray, W: dict, mu, sd) -> np.ndarray:
+    """fhat of the BF16 form: h3 by the FP32 FMA chain, rounded to bfloat16, then
+    sigma (bf16(h3) bf16(W4)^T + b4) + mu."""
+    W3 = np.asarray(W["W3"], np.float32)
+    h3 = np.broadcast_to(np.asarray(W["b3"], np.float32), (Zh.shape[0], W3.shape[0])).astype(np.float32)
+    Z32 = np.asarray(Zh, np.float32)
+    for d in range(W3.shape[1]):
+        h3 = fma32(Z32[:, d:d + 1], W3[None, :, d], h3)
+    h3b = bf16(np.maximum(h3, np.float32(0))).astype(np.float64)
+    w4 = bf16(np.asarray(W["W4"], np.float32)).astype(np.float64)
+    y = h3b @ w4.T + np.asarray(W["b4"], np.float64)
+    return np.asarray(sd, np.float64) * y + np.asarray(mu, np.float64)

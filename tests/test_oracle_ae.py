@@ -107,3 +107,54 @@ def test_norm_stats():
     assert np.allclose(mu, X.mean(0))
     assert sd[0] == pytest.approx(1e-12 * X.std(0).max())
     assert np.allclose(sd[1:], X.std(0)[1:])
+
+
+def test_bf16_rounding_matches_torch_and_ties():
+    import torch
+    rng = np.random.default_rng(31)
+    x = (rng.standard_normal(20000) * 10.0 ** rng.integers(-20, 20, 20000)).astype(np.float32)
+    want = torch.from_numpy(x).to(torch.bfloat16).to(torch.float32).numpy()
+    assert np.array_equal(ae.bf16(x), want)
+    # exact ties: 1 + 2^-8 sits halfway between 1 and 1 + 2^-7 and goes to the even 1;
+    # 1 + 3 * 2^-8 goes up to 1 + 2^-6
+    t = np.array([1 + 2.0 ** -8, 1 + 3 * 2.0 ** -8, -(1 + 2.0 ** -8)], np.float32)
+    assert np.array_equal(ae.bf16(t), np.array([1.0, 1 + 2.0 ** -6, -1.0], np.float32))
+
+
+def test_fma32_is_a_single_rounding():
+    """Against exact rational arithmetic: the nearest FP32 value to a b + c (ties to
+    even), found among the neighbours of the FP64 result."""
+    from fractions import Fraction
+    rng = np.random.default_rng(32)
+    a, b, c = (rng.standard_normal(3000).astype(np.float32) * np.float32(s) for s in (1.0, 3.0, 0.5))
+    got = ae.fma32(a, b, c)
+    for k in range(len(a)):
+        exact = Fraction(float(a[k])) * Fraction(float(b[k])) + Fraction(float(c[k]))
+        x0 = np.float32(float(exact))
+        cands = [np.nextafter(x0, np.float32(-np.inf)), x0, np.nextafter(x0, np.float32(np.inf))]
+        dist = [abs(Fraction(float(v)) - exact) for v in cands]
+        best = min(dist)
+        ties = [v for v, d in zip(cands, dist) if d == best]
+        want = ties[0] if len(ties) == 1 else [v for v in ties if (np.float32(v).view(np.uint32) & 1) == 0][0]
+        assert got[k] == want, (k, got[k], want)
+
+
+def test_bf16_form_is_close_to_the_fp64_model():
+    """The BF16 form differs from the FP64 model by about the bfloat16 rounding of its
+    operands (2^-9 relative per operand), and equals it when every operand is already a
+    bfloat16 value."""
+    F = synth.histograms(64, seed=33, dtype=np.float32)
+    W = synth.dense_ae_weights()
+    mu, sd = ae.norm_stats(F.astype(np.float64))
+    mu32, sd32 = mu.astype(np.float32), sd.astype(np.float32)
+    rsd32 = (np.float32(1) / sd32).astype(np.float32)
+    z16 = ae.dense_encode_bf16(F, mu32, rsd32, W)
+    z64 = ae.dense_encode(ae.normalize(F.astype(np.float64), mu, sd), W)
+    rel = np.abs(z16 - z64).max() / np.abs(z64).max()
+    assert 1e-5 < rel < 2e-2
+    # operands already in bfloat16: the form reduces to the exact model on them
+    Wb = {k: ae.bf16(np.asarray(v, np.float32)).astype(np.float64) for k, v in W.items()}
+    Wb32 = {k: v.astype(np.float32) for k, v in Wb.items()}
+    xb = ae.bf16_encode_input(F.reshape(64, -1), mu32, rsd32)
+    zb = ae.dense_encode_bf16(F, mu32, rsd32, Wb32)
+    assert np.allclose(zb, ae.dense_encode(xb.astype(np.float64), Wb), rtol=1e-12, atol=1e-12)
