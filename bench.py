@@ -149,6 +149,47 @@ def tau_sweep(hcz, plan, model, x, args) -> dict:
     return out
 
 
+def bf16_form(hcz, plan, ctx, x, W, args) -> dict:
+    """The plain workload with the autoencoder's two large products on bfloat16 operands
+    (FP32 accumulation): throughput, per-stage times with the encoder's and decoder's HBM
+    rates (4N bytes read, resp. written, per histogram), p, stream size, QoI error, bound."""
+    import torch
+    H, N = x.shape[0], plan.N
+    xf = x.reshape(H, -1).double()
+    mu, sd = xf.mean(0), xf.std(0, unbiased=False)
+    sd = torch.clamp(sd, min=1e-12 * sd.max().item())
+    mu, sd = mu.float().cpu().numpy(), sd.float().cpu().numpy()
+    del xf
+    model = hcz.Model(plan, W, mu, sd, compute="bf16")
+    cz = hcz.Compressor(plan, model, H, hcz.params(tau=args.tau, fit_codebook=True, sample_every=16))
+    cz.compress(x)
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    ctx.profile_read()
+    dt, comp = time_compress(cz, x, 3)
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    stage_ms = {k: v[0] / v[1] for k, v in prof.items() if v[1]}
+    s = comp.stats()
+    o = cz.decompress(comp, H)
+    _, q0, n0 = hcz.qoi(plan, x)
+    _, q1, _ = hcz.qoi(plan, o)
+    ok = (comp.flags & 4) == 0
+    den = torch.stack([q0[:, 0].abs(), torch.maximum(q0[:, 1].abs(), q0[:, 3].abs().sqrt()),
+                       q0[:, 2].abs(), q0[:, 3].abs()], 1)
+    res = {"value": H / dt, "ms_per_step": dt * 1e3, "coded_frac": s["n_coded"] / H,
+           "stream_bytes": s["stream_bytes"], "raw": s["n_raw"],
+           "newton_mean_updates": s["newton_iters_total"] / max(1, H - s["n_raw"]),
+           "max_qoi_rel_err": ((q1 - q0).abs() / den)[ok].max().item(),
+           "max_err_over_tau_h": ((o - x.double()).reshape(H, -1).norm(dim=1)[ok] / (args.tau * n0[ok])).max().item(),
+           "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()}}
+    for k in ("encode", "decode"):
+        if k in stage_ms:
+            res[f"{k}_hbm_GBps"] = H * 4 * N / (stage_ms[k] / 1e3) / 1e9
+    del cz, comp, o, model
+    return res
+
+
 def other_forms(hcz, plan, ctx, x, F, W, args, plain_value, plain_stats) -> dict:
     """The same batch and tau through (a) the coder-only pipeline and (b) the learned form:
     the autoencoder trained by the library's kernels on held-apart synthetic histograms,
@@ -158,13 +199,19 @@ def other_forms(hcz, plan, ctx, x, F, W, args, plain_value, plain_stats) -> dict
     from paper_2212_10733_amd import synth, train
     H = x.shape[0]
     out = {}
-    log("form: coder-only")
-    cz = hcz.Compressor(plan, None, H, hcz.params(tau=args.tau))
-    dt, comp = time_compress(cz, x, 3)
-    s = comp.stats()
-    out["coder_only"] = {"value": H / dt, "ms_per_step": dt * 1e3, "coded_frac": s["n_coded"] / H,
-                         "stream_bytes": s["stream_bytes"], "newton_mean_updates": s["newton_iters_total"] / H}
-    del cz, comp
+    if "coder" in args.forms:
+        log("form: coder-only")
+        cz = hcz.Compressor(plan, None, H, hcz.params(tau=args.tau))
+        dt, comp = time_compress(cz, x, 3)
+        s = comp.stats()
+        out["coder_only"] = {"value": H / dt, "ms_per_step": dt * 1e3, "coded_frac": s["n_coded"] / H,
+                             "stream_bytes": s["stream_bytes"], "newton_mean_updates": s["newton_iters_total"] / H}
+        del cz, comp
+    if "bf16" in args.forms:
+        log("form: BF16 autoencoder")
+        out["bf16_ae"] = bf16_form(hcz, plan, ctx, x, W, args)
+    if "learned" not in args.forms:
+        return out
     log(f"form: learned (train {args.epochs} epochs on {args.train_hist})")
     Ftr = torch.from_numpy(synth.histograms(args.train_hist, seed=synth.SEED_TRAIN, dtype=np.float32)).cuda()
     mu, sd = hcz.norm_stats(plan, Ftr)
@@ -230,6 +277,9 @@ def main() -> int:
     ap.add_argument("--cpu-sample", type=int, default=8192)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the coder-only and learned forms")
+    ap.add_argument("--forms", default="tau,coder,bf16,learned",
+                    help="comma list of the other forms to run: tau (sweep), coder (coder-only), "
+                         "bf16 (BF16 autoencoder), learned")
     ap.add_argument("--train-hist", type=int, default=262144)
     ap.add_argument("--epochs", type=int, default=20)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -344,7 +394,8 @@ def main() -> int:
 
     forms = {}
     if not args.no_forms:
-        forms["tau_sweep"] = tau_sweep(hcz, plan, model, x, args)
+        if "tau" in args.forms:
+            forms["tau_sweep"] = tau_sweep(hcz, plan, model, x, args)
         forms.update(other_forms(hcz, plan, ctx, x, F, W, args, value, st))
 
     cpu = None

@@ -54,6 +54,7 @@ typedef enum {
 
 enum { HCZ_F32 = 0, HCZ_F64 = 1 };                       /* element types */
 enum { HCZ_ARCH_DENSE = 1 };                              /* autoencoder architectures */
+enum { HCZ_COMPUTE_FP32 = 0, HCZ_COMPUTE_BF16 = 1 };      /* autoencoder arithmetic */
 enum { HCZ_TAU_REL_L2 = 0, HCZ_TAU_NRMSE = 1 };          /* tau_h = tau ||f||, tau sqrt(N)(max-min) */
 enum { HCZ_FALLBACK_BACKTRACK = 0, HCZ_FALLBACK_PAPER = 1 };
 enum { HCZ_FLAG_CODED = 1, HCZ_FLAG_ROUND2 = 2, HCZ_FLAG_RAW = 4, HCZ_FLAG_WARM_REJECTED = 8,
@@ -81,13 +82,22 @@ typedef struct {
  * W1[hidden][N], b1[hidden], W2[latent][hidden], b2[latent], W3[hidden][latent],
  * b3[hidden], W4[N][hidden], b4[N] back to back (y = x W^T + b).  norm_mean and
  * norm_std (host, [N]) are the per-pixel z-score statistics (Section IV-C).
- * Supported: hidden = 128, latent = 16. */
+ * Supported: hidden = 128, latent = 16.
+ * compute: HCZ_COMPUTE_FP32 evaluates both products on FP32 matrix cores.
+ *   HCZ_COMPUTE_BF16 (an arithmetic form of this library, not the paper's) gives the two
+ *   large products bfloat16 operands with FP32 accumulation: x = (f - mean) * (1 / std)
+ *   formed in FP32 (FP64 input rounded to FP32 first) and rounded to nearest-even
+ *   bfloat16 against W1 rounded at load; h3 = relu(b3 + sum_d zhat_d W3[:, d]) as FP32
+ *   fused multiply-adds in order d = 0..15, rounded likewise, against W4 rounded at load.
+ *   The 128 -> latent and latent -> 128 layers stay FP32.  Compression and decompression
+ *   evaluate the decoder with the same kernel, so they agree bit for bit either way. */
 typedef struct {
   int32_t arch;
   int32_t latent, hidden;
   const float* weights;
   const float* norm_mean;
   const float* norm_std;
+  int32_t compute;
 } hcz_model_desc;
 
 /* Product-quantizer codebook (Section III Stage 3): centroids [latent][1 << bits]

@@ -137,10 +137,20 @@ def bf16(x) -> np.ndarray:
 
 
 def fma32(a, b, c) -> np.ndarray:
-    """FP32 fused multiply-add round(a b + c): the product of two FP32 values is exact in
-    FP64, and the FP64 sum is rounded to FP32 (a second rounding that can only matter
-    when the FP64 sum ties two FP32 values, which the tests' margins exclude)."""
-    return (np.float64(a) * np.float64(b) + np.float64(c)).astype(np.float32)
+    """FP32 fused multiply-add: a b + c rounded once to the nearest FP32 value (ties to
+    even).  The product of two FP32 values is exact in FP64; the FP64 sum s and its
+    rounding error e (Knuth's two-sum) hold a b + c exactly.  Rounding s to FP32 is right
+    unless s sits exactly halfway between two FP32 values, where the sign of e decides."""
+    p = np.float64(a) * np.float64(b)
+    c = np.asarray(c, np.float64)
+    s = p + c
+    bb = s - p
+    e = (p - (s - bb)) + (c - bb)
+    r = s.astype(np.float32)
+    other = np.nextafter(r, np.where(s > r, np.float32(np.inf), np.float32(-np.inf))).astype(np.float32)
+    mid = (np.float64(r) != s) & ((np.float64(r) + np.float64(other)) * 0.5 == s)
+    up = np.where(e > 0, np.maximum(r, other), np.minimum(r, other))
+    return np.where(mid & (e != 0), up, r).astype(np.float32)
 
 
 def bf16_encode_input(F32: np.ndarray, mu32: np.ndarray, rsd32: np.ndarray) -> np.ndarray:

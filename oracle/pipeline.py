@@ -52,8 +52,25 @@ def tau_h(F64: np.ndarray, p: Params) -> np.ndarray:
     return np.array([p.tau * math.sqrt(math.fsum(x * x)) for x in X])
 
 
+def _bf16(model: dict) -> bool:
+    """model["compute"] == "bf16" selects the BF16 form of the autoencoder (bfloat16
+    operands for the two large products); the default is the FP64 model."""
+    return model.get("compute", "fp64") == "bf16"
+
+
+def encode_ae(F64: np.ndarray, model: dict) -> np.ndarray:
+    if _bf16(model):
+        sd32 = np.asarray(model["sd"], np.float32)
+        return ae.dense_encode_bf16(F64.astype(np.float32), np.asarray(model["mu"], np.float32),
+                                    np.float32(1) / sd32, model["W"])
+    return ae.dense_encode(ae.normalize(F64, model["mu"], model["sd"]), model["W"])
+
+
 def reconstruct_ae(codes: np.ndarray, C: np.ndarray, model: dict, shape) -> np.ndarray:
     Zh = pq.decode(codes, C)
+    if _bf16(model):
+        return ae.dense_decode_bf16(Zh, model["W"], np.asarray(model["mu"], np.float32),
+                                    np.asarray(model["sd"], np.float32)).reshape(shape)
     Xh = ae.dense_decode(Zh, model["W"])
     return ae.denormalize(Xh, model["mu"], model["sd"]).reshape(shape)
 
@@ -73,7 +90,7 @@ def compress(F: np.ndarray, g: Grid, model: dict | None, C: np.ndarray | None, p
     codes = np.zeros((H, L), np.uint8)
     Z = None
     if model is not None:
-        Z = ae.dense_encode(ae.normalize(Fz, model["mu"], model["sd"]), model["W"])
+        Z = encode_ae(Fz, model)
         if fit_codebook:
             C = pq.fit(Z, bits, sample_every)
         codes = pq.encode(Z, C)

@@ -573,6 +573,14 @@ void hcz_plan_destroy(hcz_plan* plan) {
   delete plan;
 }
 
+// nearest-even bfloat16 of a finite or infinite FP32 value (NaN keeps a quiet NaN)
+static uint16_t bf16_rne(float x) {
+  uint32_t u;
+  std::memcpy(&u, &x, 4);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40);
+  return (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+
 hcz_status hcz_model_load(hcz_plan* plan, const hcz_model_desc* d, hcz_model** out) {
   if (!plan || !d || !out) return fail(HCZ_EINVAL, "NULL argument");
   *out = nullptr;
@@ -580,6 +588,8 @@ hcz_status hcz_model_load(hcz_plan* plan, const hcz_model_desc* d, hcz_model** o
   if (d->hidden != kHidden || d->latent != kLatent)
     return fail(HCZ_EUNSUPPORTED, "dense model must be hidden %d, latent %d", kHidden, kLatent);
   if (!d->weights || !d->norm_mean || !d->norm_std) return fail(HCZ_EINVAL, "weights or norm stats NULL");
+  if (d->compute != HCZ_COMPUTE_FP32 && d->compute != HCZ_COMPUTE_BF16)
+    return fail(HCZ_EINVAL, "compute %d", d->compute);
   hcz_status s = set_device(plan->ctx);
   if (s) return s;
   const int N = plan->G.N, Hd = kHidden, Ld = kLatent;
@@ -606,8 +616,22 @@ hcz_status hcz_model_load(hcz_plan* plan, const hcz_model_desc* d, hcz_model** o
   M.latent = Ld;
   M.kpad = kpad;
   M.npad = npad;
+  M.bf16 = d->compute == HCZ_COMPUTE_BF16;
   std::vector<float> vb1(b1, b1 + Hd), vW2(W2, W2 + Ld * Hd), vb2(b2, b2 + Ld), vW3(W3, W3 + Hd * Ld),
       vb3(b3, b3 + Hd), vb4(b4, b4 + N);
+  if (M.bf16) {
+    // BF16 form: W1 and W4 rounded to nearest-even bfloat16, natural k order
+    std::vector<uint16_t> W1b((size_t)Hd * kpad, 0), W4b((size_t)npad * Hd, 0);
+    for (int r = 0; r < Hd; ++r)
+      for (int k = 0; k < N; ++k) W1b[(size_t)r * kpad + k] = bf16_rne(W1[(size_t)r * N + k]);
+    for (int c = 0; c < N; ++c)
+      for (int k = 0; k < Hd; ++k) W4b[(size_t)c * Hd + k] = bf16_rne(W4[(size_t)c * Hd + k]);
+    if ((s = upload(m->allocs, W1b, &M.W1b)) || (s = upload(m->allocs, W4b, &M.W4b))) {
+      free_all(m->allocs);
+      delete m;
+      return s;
+    }
+  }
   if ((s = upload(m->allocs, W1p, &M.W1p)) || (s = upload(m->allocs, vb1, &M.b1)) ||
       (s = upload(m->allocs, vW2, &M.W2)) || (s = upload(m->allocs, vb2, &M.b2)) ||
       (s = upload(m->allocs, vW3, &M.W3)) || (s = upload(m->allocs, vb3, &M.b3)) ||

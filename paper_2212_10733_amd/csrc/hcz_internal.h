@@ -76,6 +76,9 @@ struct ModelDev {
   const float* rsd;                // [N] 1 / sigma (encoder side)
   const float* sd;                 // [N] sigma (decoder side)
   int npad;
+  int bf16;                        // 1: the BF16 form (W1b, W4b below)
+  const uint16_t* W1b;             // [hidden][kpad] bfloat16 of W1, zero padded
+  const uint16_t* W4b;             // [npad][hidden] bfloat16 of W4, rows >= N zero
 };
 
 struct ResidualArgs {

@@ -367,6 +367,252 @@ __global__ __launch_bounds__(256, 2) void k_decode(ModelDev M, const uint8_t* co
   }
 }
 
+// ---- BF16 form --------------------------------------------------------------------------
+// The two large products take bfloat16 operands on v_mfma_f32_32x32x16_bf16 with FP32
+// accumulation: the encoder's x = (f - mu) * (1/sigma), formed in FP32 and rounded to
+// nearest-even bfloat16, against W1 rounded at load; the decoder's h3 (the same FP32
+// fused multiply-add chain as the FP32 form, then ReLU) rounded likewise, against W4.
+// Operand layout of the 32x32x16 instruction: lane l supplies row (or column) l % 32 and
+// eight consecutive k of the sixteen, starting at 8 (l / 32).  The encoder streams K in
+// chunks of 32: lane half kh holds k in [32c + 16kh, 32c + 16kh + 16), the first eight for
+// the chunk's first instruction and the rest for its second, read straight from memory.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+constexpr int kBPitch = 136;  // LDS pitch (bfloat16) of the decoder's H3 rows
+
+__device__ __forceinline__ f32x16 mfma_bf16(bf16x8 a, bf16x8 b, f32x16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+}
+
+// VEC: FP32 input with contiguous rows, loaded 16 bytes at a time.  Otherwise elements are
+// loaded one by one through an LDS table of their offsets (FP64 input is rounded to FP32).
+template <typename TIn, bool VEC>
+__global__ __launch_bounds__(256, 2) void k_encode_b(ModelDev M, const TIn* hist, long long H, long long hs,
+                                                     long long rs, int n_par, float* z) {
+  __shared__ __attribute__((aligned(16))) float smem[kTile * kHPitch];   // mu / rsd / offsets, then H1
+  __shared__ __attribute__((aligned(16))) float W2t[kHidden * kLatent];
+  const int t = threadIdx.x, w = t >> 6, l = t & 63;
+  const long long h0 = (long long)blockIdx.x * kTile;
+  const int wr = (w >> 1) * 64, wc = (w & 1) * 64;
+  const int li = l & 31, kh = l >> 5;
+  const int N = M.N, kpad = M.kpad;
+  float* s_mu = smem;
+  float* s_rsd = smem + kpad;
+  int* s_off = (int*)(smem + 2 * kpad);
+  for (int k = t; k < kpad; k += 256) {
+    s_mu[k] = k < N ? M.mu[k] : 0.0f;
+    s_rsd[k] = k < N ? M.rsd[k] : 0.0f;
+    if (!VEC) s_off[k] = k < N ? (int)((k / n_par) * rs + k % n_par) : 0;
+  }
+  for (int q = t; q < kHidden * kLatent; q += 256) {
+    const int o = q / kHidden, c = q % kHidden;
+    W2t[c * kLatent + o] = M.W2[q];
+  }
+  __syncthreads();
+  const TIn* arow[2];
+  const __bf16* brow[2];
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const long long r = min(h0 + wr + q * 32 + li, H - 1);     // rows past H repeat the last one
+    arow[q] = hist + r * hs;
+    brow[q] = (const __bf16*)M.W1b + (long long)(wc + q * 32 + li) * kpad + kh * 16;
+  }
+  f32x16 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.0f;
+  const int nfull = VEC ? N / kKc : 0, nchunk = kpad / kKc;
+  float ra[2][16];
+  bf16x8 rb[2][2];
+  auto bload = [&](int c) {
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+      for (int s = 0; s < 2; ++s) rb[q][s] = *(const bf16x8*)(brow[q] + c * kKc + 8 * s);
+  };
+  auto gload = [&](int c) {               // 16 in-range k per row
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const f32x4u v = *(const f32x4u*)((const float*)arow[q] + c * kKc + kh * 16 + 4 * u);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) ra[q][4 * u + e] = v[e];
+      }
+    bload(c);
+  };
+  auto gload_elem = [&](int c) {          // k may reach N, or rows are strided
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const int k = c * kKc + kh * 16 + j;
+        ra[q][j] = k < N ? (float)arow[q][VEC ? k : s_off[k]] : 0.0f;
+      }
+    bload(c);
+  };
+  if (nfull > 0) gload(0);
+  else gload_elem(0);
+  for (int c = 0; c < nchunk; ++c) {
+    // this chunk's operands: (f - mu) / sigma in FP32, non-finite inputs as 0, to bfloat16
+    bf16x8 a8[2][2], b8[2][2];
+    const f32x4* pm = (const f32x4*)(s_mu + c * kKc + kh * 16);
+    const f32x4* pr = (const f32x4*)(s_rsd + c * kKc + kh * 16);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const f32x4 mu4 = pm[u], rs4 = pr[u];
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          float fv = ra[q][4 * u + e];
+          if (!isfinite(fv)) fv = 0.0f;
+          a8[q][u >> 1][4 * (u & 1) + e] = (__bf16)((fv - mu4[e]) * rs4[e]);
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+      for (int s = 0; s < 2; ++s) b8[q][s] = rb[q][s];
+    if (c + 1 < nfull) gload(c + 1);
+    else if (c + 1 < nchunk) gload_elem(c + 1);
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = mfma_bf16(a8[a][s], b8[b][s], acc[a][b]);
+  }
+  __syncthreads();
+  // epilogue 1: H1 = relu(acc + b1) into LDS
+  float* H1 = smem;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const int col = wc + b * 32 + li;
+      const float bias = M.b1[col];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = wr + a * 32 + 8 * (r >> 2) + 4 * kh + (r & 3);
+        H1[row * kHPitch + col] = fmaxf(acc[a][b][r] + bias, 0.0f);
+      }
+    }
+  __syncthreads();
+  // layer 2 on the vector ALUs in FP32: 8 latent outputs per thread
+  const int row = t >> 1, o0 = (t & 1) * 8;
+  float sacc[8];
+#pragma unroll
+  for (int o = 0; o < 8; ++o) sacc[o] = M.b2[o0 + o];
+  for (int c = 0; c < kHidden; ++c) {
+    const float hv = H1[row * kHPitch + c];
+    const f32x4 w0 = *(const f32x4*)&W2t[c * kLatent + o0];
+    const f32x4 w1 = *(const f32x4*)&W2t[c * kLatent + o0 + 4];
+#pragma unroll
+    for (int o = 0; o < 4; ++o) {
+      sacc[o] = fmaf(hv, w0[o], sacc[o]);
+      sacc[o + 4] = fmaf(hv, w1[o], sacc[o + 4]);
+    }
+  }
+  const long long h = h0 + row;
+  if (h < H) {
+#pragma unroll
+    for (int o = 0; o < 8; ++o) z[h * kLatent + o0 + o] = sacc[o];
+  }
+}
+
+// Decoder of the BF16 form: H3 in LDS as bfloat16 rows in natural k order, W4 as
+// bfloat16 [npad][hidden] in device memory; K = 128 in two halves of four instructions,
+// the next half's weights loaded while the current half is multiplied.
+__global__ __launch_bounds__(256, 2) void k_decode_b(ModelDev M, const uint8_t* codes,
+                                                     const float* centroids, int kcb, long long H,
+                                                     float* fhat) {
+  __shared__ __attribute__((aligned(16))) __bf16 H3[kTile * kBPitch];
+  __shared__ float Zh[kTile * kLatent];
+  const int t = threadIdx.x, w = t >> 6, l = t & 63;
+  const long long h0 = (long long)blockIdx.x * kTile;
+  const int li = l & 31, kh = l >> 5;
+  for (int q = t; q < kTile * kLatent; q += 256) {
+    const int row = q / kLatent, d = q % kLatent;
+    const long long h = h0 + row;
+    Zh[q] = (h < H) ? centroids[d * kcb + min((int)codes[h * kLatent + d], kcb - 1)] : 0.0f;
+  }
+  __syncthreads();
+  {
+    const int c = t & 127;
+    float w3[kLatent];
+#pragma unroll
+    for (int d = 0; d < kLatent; ++d) w3[d] = M.W3[c * kLatent + d];
+    const float b3 = M.b3[c];
+    for (int row = t >> 7; row < kTile; row += 2) {
+      float s = b3;
+#pragma unroll
+      for (int d = 0; d < kLatent; ++d) s = fmaf(Zh[row * kLatent + d], w3[d], s);
+      H3[row * kBPitch + c] = (__bf16)fmaxf(s, 0.0f);
+    }
+  }
+  __syncthreads();
+  const int wr = (w >> 1) * 64;
+  const __bf16* W4b = (const __bf16*)M.W4b;
+  bf16x8 bv[2][4], bn[2][4];
+  auto bload = [&](int nb, int half, bf16x8 (&B)[2][4]) {
+    const int wc = nb + (w & 1) * 64;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const __bf16* pb = W4b + (long long)(wc + q * 32 + li) * kHidden + half * 64 + kh * 8;
+#pragma unroll
+      for (int s = 0; s < 4; ++s) B[q][s] = *(const bf16x8*)(pb + 16 * s);
+    }
+  };
+  bload(0, 0, bv);
+  for (int nb = 0; nb < M.npad; nb += 128) {
+    const int wc = nb + (w & 1) * 64;
+    f32x16 acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.0f;
+#pragma unroll 1
+    for (int half = 0; half < 2; ++half) {
+      if (half == 0) bload(nb, 1, bn);
+      else if (nb + 128 < M.npad) bload(nb + 128, 0, bn);
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        bf16x8 av[2];
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+          av[q] = *(const bf16x8*)&H3[(wr + q * 32 + li) * kBPitch + half * 64 + 16 * s + kh * 8];
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b) acc[a][b] = mfma_bf16(av[a], bv[b][s], acc[a][b]);
+      }
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int s = 0; s < 4; ++s) bv[q][s] = bn[q][s];
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        const int col = wc + b * 32 + li;
+        if (col >= M.N) continue;
+        const float b4 = M.b4[col], sd = M.sd[col], mu = M.mu[col];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int row = wr + a * 32 + 8 * (r >> 2) + 4 * kh + (r & 3);
+          const long long h = h0 + row;
+          if (h < H) fhat[h * M.N + col] = fmaf(sd, acc[a][b][r] + b4, mu);
+        }
+      }
+  }
+}
+
 // code = #{c : (C_c + C_{c+1}) / 2 < z} with the midpoints in FP64: a lower bound search.
 __global__ __launch_bounds__(256) void k_quantize(const float* z, long long n, int latent,
                                                   const float* centroids, int kcb, uint8_t* codes) {
@@ -390,7 +636,14 @@ hipError_t launch_encode(const ModelDev& M, const void* hist, int dtype, long lo
   if (H <= 0) return hipSuccess;
   const bool contig = rs == n_par;
   dim3 grid((unsigned)((H + kTile - 1) / kTile)), block(256);
-  if (dtype == HCZ_F32) {
+  if (M.bf16) {
+    if (dtype == HCZ_F32 && contig)
+      hipLaunchKernelGGL((k_encode_b<float, true>), grid, block, 0, st, M, (const float*)hist, H, hs, rs, n_par, z);
+    else if (dtype == HCZ_F32)
+      hipLaunchKernelGGL((k_encode_b<float, false>), grid, block, 0, st, M, (const float*)hist, H, hs, rs, n_par, z);
+    else
+      hipLaunchKernelGGL((k_encode_b<double, false>), grid, block, 0, st, M, (const double*)hist, H, hs, rs, n_par, z);
+  } else if (dtype == HCZ_F32) {
     if (contig && (size_t)M.kpad * 2 <= (size_t)kTile * kHPitch)
       hipLaunchKernelGGL(k_encode_d, grid, block, 0, st, M, (const float*)hist, H, hs, z);
     else if (contig) hipLaunchKernelGGL((k_encode<float, true>), grid, block, 0, st, M, (const float*)hist, H, hs, rs, n_par, z);
@@ -406,7 +659,8 @@ hipError_t launch_decode(const ModelDev& M, const uint8_t* codes, const float* c
                          long long H, float* fhat, hipStream_t st) {
   if (H <= 0) return hipSuccess;
   dim3 grid((unsigned)((H + kTile - 1) / kTile)), block(256);
-  hipLaunchKernelGGL(k_decode, grid, block, 0, st, M, codes, centroids, 1 << bits, H, fhat);
+  if (M.bf16) hipLaunchKernelGGL(k_decode_b, grid, block, 0, st, M, codes, centroids, 1 << bits, H, fhat);
+  else hipLaunchKernelGGL(k_decode, grid, block, 0, st, M, codes, centroids, 1 << bits, H, fhat);
   return hipGetLastError();
 }
 

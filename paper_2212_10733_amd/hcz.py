@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libhcz.so")
 
 F32, F64 = 0, 1
 ARCH_DENSE = 1
+COMPUTE_FP32, COMPUTE_BF16 = 0, 1
 TAU_REL_L2, TAU_NRMSE = 0, 1
 FALLBACK_BACKTRACK, FALLBACK_PAPER = 0, 1
 FLAG_CODED, FLAG_ROUND2, FLAG_RAW, FLAG_WARM_REJECTED = 1, 2, 4, 8
@@ -42,7 +43,7 @@ class Grid(C.Structure):
 class ModelDesc(C.Structure):
     _fields_ = [("arch", C.c_int32), ("latent", C.c_int32), ("hidden", C.c_int32),
                 ("weights", C.POINTER(C.c_float)), ("norm_mean", C.POINTER(C.c_float)),
-                ("norm_std", C.POINTER(C.c_float))]
+                ("norm_std", C.POINTER(C.c_float)), ("compute", C.c_int32)]
 
 
 class Codebook(C.Structure):
@@ -238,14 +239,17 @@ def pack_dense_weights(W: dict) -> np.ndarray:
 class Model:
     """A dense autoencoder copied to the device for one plan."""
 
-    def __init__(self, plan: Plan, W: dict, mu: np.ndarray, sd: np.ndarray):
+    def __init__(self, plan: Plan, W: dict, mu: np.ndarray, sd: np.ndarray, compute: str = "fp32"):
+        if compute not in ("fp32", "bf16"):
+            raise ValueError(f"compute must be 'fp32' or 'bf16', not {compute!r}")
         self.plan = plan
+        self.compute = compute
         blob = pack_dense_weights(W)
         mu = np.ascontiguousarray(mu, np.float32)
         sd = np.ascontiguousarray(sd, np.float32)
         fp = C.POINTER(C.c_float)
         d = ModelDesc(ARCH_DENSE, LATENT, HIDDEN, blob.ctypes.data_as(fp), mu.ctypes.data_as(fp),
-                      sd.ctypes.data_as(fp))
+                      sd.ctypes.data_as(fp), COMPUTE_BF16 if compute == "bf16" else COMPUTE_FP32)
         h = C.c_void_p()
         _check(LIB.hcz_model_load(plan.h, C.byref(d), C.byref(h)))
         self.h = h

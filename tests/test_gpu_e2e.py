@@ -60,17 +60,20 @@ def near_tie_codes(z_or, C_or, C_gpu, tol):
     return near
 
 
-@pytest.mark.parametrize("Hn,dtype,every,bits", [(256, np.float64, 1, 8), (3001, np.float32, 16, 8),
-                                                 (1000, np.float32, 4, 4)])
-def test_compress_with_model(H, ctx, Hn, dtype, every, bits):
-    say("e2e model", Hn, dtype.__name__, every, bits)
+@pytest.mark.parametrize("Hn,dtype,every,bits,compute", [(256, np.float64, 1, 8, "fp32"), (3001, np.float32, 16, 8, "fp32"),
+                                                         (1000, np.float32, 4, 4, "fp32"), (3001, np.float32, 16, 8, "bf16"),
+                                                         (256, np.float64, 1, 8, "bf16")])
+def test_compress_with_model(H, ctx, Hn, dtype, every, bits, compute):
+    """compute = "bf16": the BF16 form on both sides (the oracle forms the same bfloat16
+    operands and sums in FP64), with the same tolerances as the FP32 form."""
+    say("e2e model", Hn, dtype.__name__, every, bits, compute)
     g = grid.make_grid()
     F = synth.histograms(Hn, seed=synth.SEED_PLAIN_SMALL, dtype=dtype)
     W = synth.dense_ae_weights()
     mu, sd = oracle.ae.norm_stats(F)
     mu, sd = mu.astype(np.float32), sd.astype(np.float32)
     plan = H.Plan(ctx)
-    model = H.Model(plan, W, mu, sd)
+    model = H.Model(plan, W, mu, sd, compute=compute)
     tdt = torch.float64 if dtype == np.float64 else torch.float32
     cz = H.Compressor(plan, model, Hn, H.params(tau=1e-3, fit_codebook=True, sample_every=every), bits=bits, in_dtype=tdt)
     x = torch.from_numpy(F).cuda()
@@ -83,7 +86,8 @@ def test_compress_with_model(H, ctx, Hn, dtype, every, bits):
     check_roundtrip(F, out, flags, 1e-3, g)
     assert st["n_hist"] == Hn and st["overflow"] == 0
     # oracle pipeline on the same inputs
-    model_o = dict(W=W, mu=mu.astype(np.float64), sd=sd.astype(np.float64))
+    model_o = dict(W=W, mu=mu.astype(np.float64), sd=sd.astype(np.float64),
+                   compute="bf16" if compute == "bf16" else "fp64")
     ref = pipeline.compress(F, g, model_o, None, pipeline.Params(tau=1e-3), fit_codebook=True,
                             bits=bits, sample_every=every)
     Co = ref["codebook"]

@@ -133,6 +133,74 @@ def test_decode_parity(H, ctx, Hn, shape):
     assert np.all(np.abs(fh - ref) <= 2e-5 * mag + 1e-30), np.abs(fh - ref).max()
 
 
+def bf16_model(H, plan, F, seed=0):
+    W, mu, sd, _ = dense_model(H, plan, F, seed)
+    return W, mu, sd, H.Model(plan, W, mu, sd, compute="bf16")
+
+
+@pytest.mark.parametrize("Hn,dtype,shape,pad", [(300, np.float32, (39, 39), 0), (129, np.float64, (39, 39), 0),
+                                                (1000, np.float32, (33, 33), 0), (70, np.float32, (39, 39), 3),
+                                                (50, np.float32, (65, 65), 0)])
+def test_encode_parity_bf16(H, ctx, Hn, dtype, shape, pad):
+    """BF16 form: the oracle forms the same bfloat16 operands (FP32 z-score, nearest-even
+    rounding), so the two sides differ only in how the products are summed: FP32
+    accumulation on the matrix cores against FP64 in the oracle.  Bound: about 100 FP32
+    roundings of the running sum per output of layer 1 (K/16 accumulations plus the
+    instruction's own), propagated through the FP32 layer 2."""
+    n_perp, n_par = shape
+    say("encode bf16", Hn, dtype.__name__, shape, "row pad", pad)
+    plan = H.Plan(ctx, n_par, n_perp)
+    F = synth.histograms(Hn, n_par, n_perp, seed=29, dtype=dtype)
+    F[3, 2, 5] = np.nan                        # a non-finite element enters as 0
+    W, mu, sd, model = bf16_model(H, plan, F[4:])
+    x = to_dev(F)
+    if pad:                                    # rows with a stride beyond n_par
+        xp = torch.zeros((Hn, n_perp, n_par + pad), dtype=x.dtype, device=x.device)
+        xp[:, :, :n_par] = x
+        x = xp[:, :, :n_par]
+    z = H.encode(model, x).cpu().numpy()
+    rsd = np.float32(1) / sd
+    zo = oracle.ae.dense_encode_bf16(F.astype(np.float32), mu, rsd, W)
+    xb = oracle.ae.bf16_encode_input(F.reshape(Hn, -1).astype(np.float32), mu, rsd).astype(np.float64)
+    w1 = oracle.ae.bf16(W["W1"]).astype(np.float64)
+    s1 = np.abs(xb) @ np.abs(w1.T) + np.abs(W["b1"])
+    h1 = np.maximum(xb @ w1.T + W["b1"], 0)
+    w2 = np.abs(W["W2"].astype(np.float64)).T
+    eps = 2.0 ** -24
+    bound = 120 * eps * (s1 @ w2) + 140 * eps * (np.abs(h1) @ w2 + np.abs(W["b2"]))
+    err = np.abs(z - zo)
+    assert np.all(err <= bound), (err / bound).max()
+    # against the FP32 form: the bfloat16 operands move z by about 2^-9 of the terms
+    z32 = H.encode(H.Model(plan, W, mu, sd), x).cpu().numpy()
+    assert np.abs(z - z32).max() > 100 * np.abs(err).max()
+
+
+@pytest.mark.parametrize("Hn,shape", [(300, (39, 39)), (1000, (33, 33)), (50, (65, 65))])
+def test_decode_parity_bf16(H, ctx, Hn, shape):
+    """BF16 form: h3 is the same FP32 fused multiply-add chain on both sides (the oracle's
+    FMA is exact), so its bfloat16 operands agree bit for bit; the output differs by FP32
+    accumulation over K = 128 and the two roundings of sigma (y + b4) + mu."""
+    n_perp, n_par = shape
+    say("decode bf16", Hn, shape)
+    plan = H.Plan(ctx, n_par, n_perp)
+    F = synth.histograms(64, n_par, n_perp, seed=30, dtype=np.float32)
+    W, mu, sd, model = bf16_model(H, plan, F)
+    C = synth.sorted_codebook(16, 8, seed=31)
+    codes = synth.codes(Hn, 16, 8, seed=32)
+    fh = H.decode(model, to_dev(codes), to_dev(C)).cpu().numpy().reshape(Hn, -1)
+    Zh = pq.decode(codes, C)
+    ref = oracle.ae.dense_decode_bf16(Zh, W, mu, sd)
+    w3 = W["W3"].astype(np.float64)
+    h3 = np.maximum(Zh @ w3.T + W["b3"], 0)
+    mag = np.abs(sd) * (np.abs(h3) @ np.abs(oracle.ae.bf16(W["W4"]).astype(np.float64).T) * 1.01
+                        + np.abs(W["b4"])) + np.abs(mu)
+    err = np.abs(fh - ref)
+    assert np.all(err <= 40 * 2.0 ** -24 * mag), (err / mag).max()
+    # decoding twice gives the same bits (compress and decompress share this kernel)
+    fh2 = H.decode(model, to_dev(codes), to_dev(C)).cpu().numpy().reshape(Hn, -1)
+    assert np.array_equal(fh, fh2)
+
+
 # ---- residual coder + Newton -------------------------------------------------------------------
 
 def oracle_residual(F, fhat, g, p, lam0=None):

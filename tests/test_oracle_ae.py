@@ -127,7 +127,16 @@ def test_fma32_is_a_single_rounding():
     from fractions import Fraction
     rng = np.random.default_rng(32)
     a, b, c = (rng.standard_normal(3000).astype(np.float32) * np.float32(s) for s in (1.0, 3.0, 0.5))
+    # cases where the FP64 sum ties two FP32 values and only the discarded tail decides:
+    # a b + c = 1 + 2^-24 + 2^-60 (must round up to 1 + 2^-23, not to the even 1) and
+    # 1 + 3 2^-24 - 2^-60 (must round down to 1 + 2^-23, not to the even 1 + 2^-22); and
+    # the exact tie 1 + 2^-24 (to the even 1)
+    t = 2.0 ** -18
+    a = np.concatenate([a, np.float32([-(1 - t) * 2.0 ** -24, (1 - t) * 2.0 ** -24, 1 + 2.0 ** -12])])
+    b = np.concatenate([b, np.float32([1 + t, 1 + t, 1 + 2.0 ** -12])])
+    c = np.concatenate([c, np.float32([1 + 2.0 ** -23, 1 + 2.0 ** -23, -(2.0 ** -11)])])
     got = ae.fma32(a, b, c)
+    assert list(got[-3:]) == [np.float32(1 + 2.0 ** -23), np.float32(1 + 2.0 ** -23), np.float32(1.0)]
     for k in range(len(a)):
         exact = Fraction(float(a[k])) * Fraction(float(b[k])) + Fraction(float(c[k]))
         x0 = np.float32(float(exact))

@@ -137,3 +137,23 @@ def test_stage5_variants_roundtrip(lambda_fp32, positivity):
         assert err.max() < 1e-11
     if not positivity:
         assert (out < 0).any()                     # negative values survive without positivity
+
+
+def test_bf16_form_roundtrip():
+    """The BF16 autoencoder form changes only the reconstruction fhat: the bound and the
+    QoIs hold as in the FP64 form, decompression rebuilds the compressor's f_c exactly,
+    and the reconstruction stays within a few bfloat16 roundings of the FP64 model's."""
+    g = grid.make_grid()
+    F = synth.histograms(16, seed=27, dtype=np.float32)
+    model = make_model(F.astype(np.float64))
+    m16 = dict(model, compute="bf16")
+    comp = pipeline.compress(F, g, m16, None, pipeline.Params(tau=1e-3), fit_codebook=True,
+                             sample_every=1, bits=3)
+    out = pipeline.decompress(comp, g, m16, comp["codebook"], 16, np.float32)
+    check_bound_and_qoi(F, out, comp, g, 1e-3)
+    assert np.array_equal(out, comp["fc"])
+    C = comp["codebook"]
+    f16 = pipeline.reconstruct_ae(comp["codes"], C, m16, F.shape)
+    f64 = pipeline.reconstruct_ae(comp["codes"], C, model, F.shape)
+    scale = np.abs(f64).max()
+    assert 1e-6 * scale < np.abs(f16 - f64).max() < 3e-2 * scale
