@@ -190,6 +190,50 @@ def bf16_form(hcz, plan, ctx, x, W, args) -> dict:
     return res
 
 
+def incremental_form(hcz, plan, H, W, args, steps=4, planes=8) -> dict:
+    """Incremental training (Section IV-C) on a drifting synthetic series: at every step a
+    batch of planes x nodes = H / 4 histograms (262,144 at H = 2^20), training rows chosen
+    one per node (column-random-index: 32,768), the model of step 0 trained from
+    scratch for --epochs, every later step either continued from the previous model for 2
+    epochs or trained from scratch for --epochs.  Reported per step: training seconds, final
+    training loss, and the residual stream of the whole batch at tau (what the model buys)."""
+    import torch
+
+    from paper_2212_10733_amd import synth, train
+    nodes = max(1024, H // 4 // planes)
+    n = planes * nodes
+    res = []
+    prev = None
+    for t in range(steps):
+        F = torch.from_numpy(synth.series(t, planes, nodes)).cuda()
+        sel = torch.from_numpy(train.colrandind(planes, nodes, seed=t)).cuda()
+        Fs = F.reshape(n, -1)[sel]
+        mu, sd = hcz.norm_stats(plan, Fs.reshape(nodes, plan.n_perp, plan.n_par))
+        X = ((Fs - mu) / sd).contiguous()
+        row = {"step": t}
+        runs = [("scratch", train.pack(W), args.epochs)]
+        if prev is not None:
+            runs.insert(0, ("incremental", prev, 2))
+        for name, p0, ep in runs:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            tr, losses = train.incremental(p0, X, epochs=ep, batch=1024)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            model = hcz.Model(plan, train.unpack(tr.p, plan.N), mu.cpu().numpy(), sd.cpu().numpy())
+            cz = hcz.Compressor(plan, model, n, hcz.params(tau=args.tau, fit_codebook=True, sample_every=16))
+            s = cz.compress(F).stats()
+            row[name] = {"epochs": ep, "train_seconds": dt, "final_loss": losses[-1],
+                         "coded_frac": s["n_coded"] / n, "stream_bytes_per_hist": s["stream_bytes"] / n}
+            if name == "incremental" or prev is None:
+                nxt = tr.p
+            del cz, model
+        prev = nxt
+        res.append(row)
+        del F, Fs, X
+    return {"planes": planes, "nodes": nodes, "train_rows_per_step": nodes, "steps": res}
+
+
 def other_forms(hcz, plan, ctx, x, F, W, args, plain_value, plain_stats) -> dict:
     """The same batch and tau through (a) the coder-only pipeline and (b) the learned form:
     the autoencoder trained by the library's kernels on held-apart synthetic histograms,
@@ -210,6 +254,9 @@ def other_forms(hcz, plan, ctx, x, F, W, args, plain_value, plain_stats) -> dict
     if "bf16" in args.forms:
         log("form: BF16 autoencoder")
         out["bf16_ae"] = bf16_form(hcz, plan, ctx, x, W, args)
+    if "incremental" in args.forms:
+        log("form: incremental training series")
+        out["incremental"] = incremental_form(hcz, plan, x.shape[0], W, args)
     if "learned" not in args.forms:
         return out
     log(f"form: learned (train {args.epochs} epochs on {args.train_hist})")
@@ -277,9 +324,9 @@ def main() -> int:
     ap.add_argument("--cpu-sample", type=int, default=8192)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the coder-only and learned forms")
-    ap.add_argument("--forms", default="tau,coder,bf16,learned",
+    ap.add_argument("--forms", default="tau,coder,bf16,incremental,learned",
                     help="comma list of the other forms to run: tau (sweep), coder (coder-only), "
-                         "bf16 (BF16 autoencoder), learned")
+                         "bf16 (BF16 autoencoder), incremental (training series), learned")
     ap.add_argument("--train-hist", type=int, default=262144)
     ap.add_argument("--epochs", type=int, default=20)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",

@@ -34,6 +34,7 @@ SEED_PLAIN_LARGE = 2      # 2^20 histograms, FP32 (also the precision form)
 SEED_TRAIN = 3
 SEED_HELDOUT = 4
 SEED_BATCHED = 5
+SEED_SERIES = 11          # drifting series for incremental training: seed SEED_SERIES + t
 
 
 def _axis(lo: float, hi: float, n: int) -> np.ndarray:
@@ -42,8 +43,11 @@ def _axis(lo: float, hi: float, n: int) -> np.ndarray:
 
 def histograms(H: int, n_par: int = 39, n_perp: int = 39, seed: int = SEED_PLAIN_SMALL,
                dtype=np.float32, vpar=(-4.0, 4.0), vperp=(0.0, 4.0),
-               threads: int | None = None, out: np.ndarray | None = None) -> np.ndarray:
-    """Return H synthetic histograms, shape (H, n_perp, n_par), in `dtype`."""
+               threads: int | None = None, out: np.ndarray | None = None,
+               shift: tuple = (0.0, 0.0)) -> np.ndarray:
+    """Return H synthetic histograms, shape (H, n_perp, n_par), in `dtype`.
+    shift: (dpar, dperp) added to every bump centre after the draws (the same random
+    numbers, so shift = (0, 0) is the unshifted batch): a drifting series of batches."""
     if out is None:
         out = np.empty((H, n_perp, n_par), dtype=dtype)
     xs = _axis(vpar[0], vpar[1], n_par)
@@ -60,6 +64,8 @@ def histograms(H: int, n_par: int = 39, n_perp: int = 39, seed: int = SEED_PLAIN
         K = rng.integers(1, 4, size=n)
         cpar = rng.uniform(-2.0, 2.0, size=(n, 3))
         cperp = rng.uniform(0.0, 2.0, size=(n, 3))
+        cpar = cpar + shift[0]
+        cperp = cperp + shift[1]
         spar = rng.uniform(0.3, 1.2, size=(n, 3))
         sperp = rng.uniform(0.3, 1.2, size=(n, 3))
         w = rng.uniform(0.2, 1.0, size=(n, 3))
@@ -147,3 +153,15 @@ def perturbed(f: np.ndarray, rel: np.ndarray | float, seed: int = 9,
 def codes(n: int, L: int = 16, bits: int = 8, seed: int = 10) -> np.ndarray:
     rng = np.random.Generator(np.random.PCG64(seed))
     return rng.integers(0, 1 << bits, size=(n, L), dtype=np.uint8)
+
+
+def series_shift(t: int) -> tuple:
+    """Drift of the bump centres at step t of the synthetic series (velocity units)."""
+    return (0.15 * t, 0.05 * t)
+
+
+def series(t: int, planes: int, nodes: int, n_par: int = 39, n_perp: int = 39, dtype=np.float32) -> np.ndarray:
+    """Step t of a drifting series: planes x nodes histograms, histogram (r, m) at row
+    r * nodes + m (r: plane, m: mesh node), bump centres moved by series_shift(t)."""
+    return histograms(planes * nodes, n_par, n_perp, seed=SEED_SERIES + t, dtype=dtype,
+                      shift=series_shift(t))

@@ -139,6 +139,28 @@ class Trainer:
         return losses
 
 
+# ---- data selection and incremental training (Section IV-C) --------------------------------
+
+def colrandind(planes: int, nodes: int, seed: int = 0) -> np.ndarray:
+    """Training rows chosen like the paper's column-random-index scheme (Section IV-C,
+    Fig. 5): the batch holds planes x nodes histograms (row r * nodes + m); for every mesh
+    node m one plane r_m is drawn uniformly, giving `nodes` rows, one per node, in node
+    order.  The draw is NumPy PCG64 with the given seed."""
+    if planes < 1 or nodes < 0:
+        raise ValueError("planes >= 1 and nodes >= 0")
+    r = np.random.Generator(np.random.PCG64(seed)).integers(0, planes, size=nodes)
+    return r.astype(np.int64) * nodes + np.arange(nodes, dtype=np.int64)
+
+
+def incremental(params: torch.Tensor, X: torch.Tensor, epochs: int = 2, batch: int = 1024, lr: float = 1e-3,
+                seed: int = 0) -> tuple:
+    """Incremental training (Section IV-C): continue a model trained on an earlier batch
+    with `epochs` passes over the current batch's z-scored rows X, with fresh Adam moments.
+    Returns (Trainer, per-epoch losses)."""
+    tr = Trainer(params, lr=lr)
+    return tr, tr.fit(X, epochs=epochs, batch=batch, seed=seed)
+
+
 # ---- warm-start network -------------------------------------------------------------------
 
 MLP_KEYS = ("W1", "b1", "W2", "b2", "W3", "b3")

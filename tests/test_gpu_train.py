@@ -231,3 +231,52 @@ def test_warm_start_network_cuts_newton_iterations(T):
                        atol=1e-9 * np.abs(res["cold"][1]).max())
     print(f"[warm-start] Newton updates cold {res['cold'][0]} warm {res['warm'][0]} "
           f"rejected {int(((res['warm'][2] & 8) != 0).sum())}", flush=True)
+
+
+def test_incremental_training(T):
+    """Incremental training (Section IV-C) on a drifting series: a model trained on step 0
+    and continued for 2 epochs on step 1 (rows chosen one per mesh node, column-random-
+    index style) fits step 1 better than before the update and better than 2 epochs from
+    scratch; its first update is the oracle's Adam step from the same weights."""
+    hcz, train = T
+    say("incremental training")
+    ctx = hcz.Context(0)
+    plan = hcz.Plan(ctx)
+    planes, nodes = 4, 4096
+    sets = []
+    for t in range(2):
+        F = torch.from_numpy(synth.series(t, planes, nodes)).cuda()
+        Fs = F.reshape(planes * nodes, -1)[torch.from_numpy(train.colrandind(planes, nodes, seed=t)).cuda()]
+        mu, sd = hcz.norm_stats(plan, Fs.reshape(nodes, 39, 39))
+        sets.append(((Fs - mu) / sd).contiguous())
+    X0, X1 = sets
+    W0 = synth.dense_ae_weights()
+    tr0 = train.Trainer(train.pack(W0), lr=1e-3)
+    tr0.fit(X0, epochs=8, batch=256)
+
+    def loss_of(p, X):
+        with torch.no_grad():
+            _, xh = train.DenseAE.apply(X, p)
+            return train.mse(xh, X).item()
+
+    before = loss_of(tr0.p, X1)
+    tri, li = train.incremental(tr0.p, X1, epochs=2, batch=256)
+    trs, ls = train.incremental(train.pack(W0), X1, epochs=2, batch=256)
+    after, scratch = loss_of(tri.p, X1), loss_of(trs.p, X1)
+    assert after < before and after < 0.8 * scratch, (before, after, scratch)
+    # parity of the first incremental update against the oracle (FP64 gradient, Adam)
+    xb = X1[:256].contiguous()
+    tr = train.Trainer(tr0.p, lr=1e-3)
+    tr.train_step(xb)
+    P0 = train.unpack(tr0.p, 1521)
+    P1 = train.unpack(tr.p, 1521)
+    W64 = {k: v.astype(np.float64) for k, v in P0.items()}
+    cache = oracle.ae.dense_forward_train(xb.cpu().numpy().astype(np.float64), W64)
+    g = oracle.ae.dense_backward(cache, W64)
+    ref = oracle.ae.adam_step(dict(W64), g, {}, lr=1e-3)
+    for k in train.KEYS:
+        sure = np.abs(g[k]) > 1e-3 * np.abs(g[k]).max()     # the FP32 gradient has the same sign
+        d = np.abs(P1[k].astype(np.float64) - ref[k])[sure]
+        # the step is lr g / (|g| + eps): within 0.5 % of lr where the sign is sure
+        tol = 5e-6 + 4 * np.finfo(np.float32).eps * np.abs(W64[k][sure])
+        assert np.all(d <= tol), (k, (d / tol).max())
