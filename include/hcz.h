@@ -126,7 +126,11 @@ typedef struct {
  * no_positivity    1: the correction drops x >= 0 and becomes the orthogonal projection
  *                  onto {A x = b}, f_c = f~ - A^T lam with (A A^T) lam = A f~ - b (one
  *                  Newton step; flag HCZ_FLAG_NOCLIP); 0: the Stage-5 projection onto
- *                  {A x = b, x >= 0}. */
+ *                  {A x = b, x >= 0}.
+ * tau_hist         NULL: every histogram uses tau.  Otherwise (device, FP64, [H]) histogram
+ *                  h uses tau_hist[h] in place of tau (tau is then not read): per-subdomain
+ *                  bounds in one call, see hcz_segment_tau.  A negative, infinite or NaN
+ *                  entry makes that histogram a verbatim record. */
 typedef struct {
   double tau;
   int32_t tau_mode;
@@ -140,6 +144,7 @@ typedef struct {
   const hcz_mlp* mlp;
   int32_t lambda_fp32;
   int32_t no_positivity;
+  const double* tau_hist;
 } hcz_params;
 
 /* Run statistics, written to device memory by compress and read with hcz_stats_read. */
@@ -156,7 +161,9 @@ typedef struct {
 /* Compressed batch.  codes [H][latent] (u8; unused without a model), lambda [H][4]
  * (FP64, or FP32 when lambda_fp32 = 1), flags [H] (u8, HCZ_FLAG_*), res_offset [H+1]
  * (u64, exclusive scan of record sizes), res_bytes [res_capacity] (records in histogram
- * order), stats (device). */
+ * order), stats (device).  t_done: NULL, or (device, u64, [H]) the device wall clock
+ * (hcz_wall_clock_hz ticks per second) at which the residual stage finished histogram h,
+ * for per-subdomain completion times (hcz_segment_max, hcz_timestamp). */
 typedef struct {
   uint8_t* codes;
   void* lambda;
@@ -166,6 +173,7 @@ typedef struct {
   uint64_t res_capacity;
   hcz_stats* stats;
   int32_t lambda_fp32;
+  uint64_t* t_done;
 } hcz_compressed;
 
 /* ---- context, plan, model ------------------------------------------------------- */
@@ -267,6 +275,24 @@ hcz_status hcz_decompress(const hcz_plan* plan, const hcz_model* model,
 /* Synchronise `stream`, copy the device stats to host_out (host); returns
  * HCZ_ECAPACITY if the stream overflowed its capacity. */
 hcz_status hcz_stats_read(const hcz_stats* dev_stats, hcz_stats* host_out, hcz_stream_t stream);
+
+/* ---- batches of subdomains (one call per grid size, per-subdomain bounds) -----------
+ * A batch of nseg subdomains laid out back to back: subdomain s holds histograms
+ * [seg_start[s], seg_start[s+1]) (device, i64, [nseg+1], non-decreasing, seg_start[0] = 0,
+ * seg_start[nseg] = H).  Entries out of that order are clamped to [0, H], so no access
+ * leaves the arrays; the results are then unspecified.  nseg >= 1. */
+
+/* tau_hist[h] = seg_tau[s] for seg_start[s] <= h < seg_start[s+1] (device arrays). */
+hcz_status hcz_segment_tau(const int64_t* seg_start, const double* seg_tau, int32_t nseg, int64_t H,
+                           double* tau_hist, hcz_stream_t stream);
+/* seg_max[s] = max of t[h] over subdomain s (0 for an empty one): with hcz_compressed.t_done
+ * the moment the subdomain's last histogram finished. */
+hcz_status hcz_segment_max(const int64_t* seg_start, int32_t nseg, int64_t H, const uint64_t* t,
+                           uint64_t* seg_max, hcz_stream_t stream);
+/* *dst = the device wall clock when the stream reaches this call (device, u64). */
+hcz_status hcz_timestamp(uint64_t* dst, hcz_stream_t stream);
+/* Ticks per second of the device wall clock of HIP device `device`. */
+hcz_status hcz_wall_clock_hz(int device, double* hz);
 
 /* ---- autoencoder training (Section III Stage 2, Eq. 5; Section IV-B) -------------------
  * The dense model of hcz_model_desc, trained with these kernels from torch.autograd.

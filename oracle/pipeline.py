@@ -44,12 +44,19 @@ class Params:
     positivity: bool = True         # False: projection onto {A x = b} only
 
 
+def tau_of(H: int, p: Params) -> np.ndarray:
+    """The bound of every histogram: p.tau is one value for the batch or one per histogram
+    (subdomains of a batch with their own bounds)."""
+    return np.broadcast_to(np.asarray(p.tau, np.float64), (H,))
+
+
 def tau_h(F64: np.ndarray, p: Params) -> np.ndarray:
     H = F64.shape[0]
     X = F64.reshape(H, -1)
+    tau = tau_of(H, p)
     if p.tau_mode == "nrmse":
-        return p.tau * math.sqrt(X.shape[1]) * (X.max(axis=1) - X.min(axis=1))
-    return np.array([p.tau * math.sqrt(math.fsum(x * x)) for x in X])
+        return tau * math.sqrt(X.shape[1]) * (X.max(axis=1) - X.min(axis=1))
+    return np.array([t * math.sqrt(math.fsum(x * x)) for t, x in zip(tau, X)])
 
 
 def _bf16(model: dict) -> bool:
@@ -100,7 +107,8 @@ def compress(F: np.ndarray, g: Grid, model: dict | None, C: np.ndarray | None, p
     r = Fz - fhat
     thr = coder.SEL_MARGIN * th
     coded = coder.sumsq(r) > thr * thr
-    raw = ~finite | ~(b[:, 0] > 0) | (coded & ~(th > 0))
+    tau = tau_of(H, p)
+    raw = ~finite | ~(b[:, 0] > 0) | (coded & ~(th > 0)) | ~(np.isfinite(tau) & (tau >= 0))
     kstar = np.zeros(H, np.int64)
     q = np.zeros(F64.shape, np.int64)
     rhat = np.zeros_like(F64)

@@ -1,0 +1,74 @@
+"""Batches of subdomains of uneven sizes over several velocity grids, each subdomain with
+its own bound (the paper's per-rank subdomains of the mesh, Section III-A, compressed
+together on one device).
+
+The subdomains of one grid size are laid out back to back and compressed by one
+hcz_compress call with per-histogram bounds (hcz_segment_tau expands the per-subdomain
+tau); every grid size has its own plan, model and codebook.  The residual stage stamps the
+device wall clock as each histogram finishes, and hcz_segment_max turns those stamps into
+per-subdomain completion times.  Allocation happens at construction; compress() only
+launches.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import hcz
+
+
+class SubdomainBatch:
+    def __init__(self, plans: dict, models: dict, layout: list, bits: int = 8, sample_every: int = 16,
+                 device="cuda", **param_kw):
+        """plans / models: grid key -> Plan / Model (or None: the coder-only pipeline);
+        layout: [(grid key, count, tau)] in batch order."""
+        self.layout = list(layout)
+        self.keys = [k for k in plans if any(g == k for g, _, _ in self.layout)]
+        self.groups = {}
+        for k in self.keys:
+            idx = [i for i, (g, _, _) in enumerate(self.layout) if g == k]
+            counts = np.array([self.layout[i][1] for i in idx], np.int64)
+            start = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+            H = int(start[-1])
+            tau_buf = torch.empty(max(H, 1), dtype=torch.float64, device=device)
+            p = hcz.params(tau_hist=tau_buf, fit_codebook=models.get(k) is not None, sample_every=sample_every,
+                           **param_kw)
+            self.groups[k] = dict(
+                index=idx, H=H, start_host=start,
+                start=torch.from_numpy(start).to(device),
+                tau=torch.tensor([self.layout[i][2] for i in idx], dtype=torch.float64, device=device),
+                tau_buf=tau_buf, params=p,
+                cz=hcz.Compressor(plans[k], models.get(k), max(H, 1), p, bits=bits, device=device,
+                                  timestamps=True))
+        self.t0 = torch.zeros(1, dtype=torch.int64, device=device)
+        self.done = {}
+
+    def compress(self, inputs: dict) -> dict:
+        """inputs: grid key -> (H_k, n_perp, n_par) tensor of that grid's subdomains, back to
+        back in layout order.  Returns grid key -> Compressed (the compressor's buffers)."""
+        out = {}
+        hcz._check(hcz.LIB.hcz_timestamp(hcz._ptr(self.t0), hcz._stream()))
+        for k in self.keys:
+            g = self.groups[k]
+            if g["H"] == 0:
+                continue
+            hcz._check(hcz.LIB.hcz_segment_tau(hcz._ptr(g["start"]), hcz._ptr(g["tau"]), len(g["index"]), g["H"],
+                                               hcz._ptr(g["tau_buf"]), hcz._stream()))
+            comp = g["cz"].compress(inputs[k])
+            self.done[k] = hcz.segment_max(g["start"], comp.t_done)
+            out[k] = comp
+        return out
+
+    def completion_seconds(self) -> np.ndarray:
+        """Seconds from the start of the last compress() to each subdomain's last histogram
+        leaving the residual stage, in layout order (synchronises)."""
+        hz = hcz.wall_clock_hz(torch.cuda.current_device())
+        t0 = int(self.t0.item())
+        res = np.zeros(len(self.layout))
+        for k, d in self.done.items():
+            res[self.groups[k]["index"]] = (d.cpu().numpy() - t0) / hz
+        return res
+
+    def decompress(self, comps: dict, in_dtype=torch.float32) -> dict:
+        return {k: self.groups[k]["cz"].decompress(c, self.groups[k]["H"], in_dtype=in_dtype)
+                for k, c in comps.items()}

@@ -385,7 +385,8 @@ hcz_status check_hist(const void* hist, int32_t dtype, int64_t H, int64_t hs, in
 
 hcz_status check_params(const hcz_params* p) {
   if (!p) return fail(HCZ_EINVAL, "params is NULL");
-  if (!(p->tau >= 0.0) || !std::isfinite(p->tau)) return fail(HCZ_EINVAL, "tau must be finite and >= 0");
+  if (!p->tau_hist && (!(p->tau >= 0.0) || !std::isfinite(p->tau)))
+    return fail(HCZ_EINVAL, "tau must be finite and >= 0");
   if (p->tau_mode != HCZ_TAU_REL_L2 && p->tau_mode != HCZ_TAU_NRMSE) return fail(HCZ_EINVAL, "tau_mode");
   if (!(p->newton_s > 0.0) || !std::isfinite(p->newton_s)) return fail(HCZ_EINVAL, "newton_s must be > 0");
   if (p->newton_max_iter < 0 || p->newton_max_iter2 < 0) return fail(HCZ_EINVAL, "newton iteration caps must be >= 0");
@@ -703,6 +704,38 @@ hcz_status hcz_quantize(const float* z, int64_t n, int32_t latent, const hcz_cod
   return HCZ_OK;
 }
 
+hcz_status hcz_segment_tau(const int64_t* seg_start, const double* seg_tau, int32_t nseg, int64_t H,
+                           double* tau_hist, hcz_stream_t stream) {
+  if (nseg < 1 || H < 0) return fail(HCZ_EINVAL, "nseg must be >= 1 and H >= 0");
+  if (!seg_start || !seg_tau || (H > 0 && !tau_hist)) return fail(HCZ_EINVAL, "NULL buffer");
+  HCZ_TRY(launch_segment_tau(seg_start, seg_tau, nseg, H, tau_hist, (hipStream_t)stream), "segment launch");
+  return HCZ_OK;
+}
+
+hcz_status hcz_segment_max(const int64_t* seg_start, int32_t nseg, int64_t H, const uint64_t* t,
+                           uint64_t* seg_max, hcz_stream_t stream) {
+  if (nseg < 1 || H < 0) return fail(HCZ_EINVAL, "nseg must be >= 1 and H >= 0");
+  if (!seg_start || !seg_max || (H > 0 && !t)) return fail(HCZ_EINVAL, "NULL buffer");
+  HCZ_TRY(launch_segment_max(seg_start, nseg, H, t, seg_max, (hipStream_t)stream), "segment launch");
+  return HCZ_OK;
+}
+
+hcz_status hcz_timestamp(uint64_t* dst, hcz_stream_t stream) {
+  if (!dst) return fail(HCZ_EINVAL, "NULL buffer");
+  HCZ_TRY(launch_timestamp(dst, (hipStream_t)stream), "timestamp launch");
+  return HCZ_OK;
+}
+
+hcz_status hcz_wall_clock_hz(int device, double* hz) {
+  if (!hz) return fail(HCZ_EINVAL, "NULL argument");
+  int khz = 0;
+  hipError_t e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device);
+  if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute");
+  if (khz <= 0) return fail(HCZ_EUNSUPPORTED, "device reports no wall clock rate");
+  *hz = 1e3 * khz;
+  return HCZ_OK;
+}
+
 hcz_status hcz_decode(const hcz_model* model, const uint8_t* codes, const hcz_codebook* cb,
                       int64_t H, float* fhat, hcz_stream_t stream) {
   if (!model) return fail(HCZ_EINVAL, "model is NULL");
@@ -744,6 +777,7 @@ static hcz_status residual_impl(const hcz_plan* plan, const hcz_params* p, const
   a.H = H;
   a.fhat = fhat;
   a.tau = p->tau;
+  a.tau_hist = p->tau_hist;
   a.tau_mode = p->tau_mode;
   a.newton_s = p->newton_s;
   a.max_iter = p->newton_max_iter;
@@ -759,6 +793,7 @@ static hcz_status residual_impl(const hcz_plan* plan, const hcz_params* p, const
   a.kstar = ws + L.kstar;
   a.iters = (uint16_t*)(ws + L.iters);
   a.lam0 = lam0;
+  a.t_done = (unsigned long long*)out->t_done;
   hcz_ctx* c = plan->ctx;
   {
     StageTimer tm(c, HCZ_STAGE_RESIDUAL, st);

@@ -3,6 +3,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <cfloat>
 
 #include "../../include/hcz.h"
 
@@ -100,6 +101,8 @@ struct ResidualArgs {
   uint8_t* kstar;              // [H] 0xff if not coded
   uint16_t* iters;             // [H]
   const double* lam0;          // [H][4] warm start or null
+  const double* tau_hist;      // [H] per-histogram tau, or null (tau for all)
+  unsigned long long* t_done;  // [H] wall clock at the end of each histogram, or null
 };
 
 struct DecompressArgs {
@@ -307,6 +310,11 @@ size_t scan_partial_elems(long long H);
 hipError_t launch_compact(const uint8_t* slots, long long slot_stride, const uint64_t* offsets,
                           const uint64_t* sizes, long long H, uint8_t* out, uint64_t capacity,
                           hipStream_t st);
+hipError_t launch_segment_tau(const int64_t* start, const double* tau, int nseg, long long H, double* out,
+                              hipStream_t st);
+hipError_t launch_segment_max(const int64_t* start, int nseg, long long H, const uint64_t* t, uint64_t* out,
+                              hipStream_t st);
+hipError_t launch_timestamp(uint64_t* dst, hipStream_t st);
 hipError_t launch_stats(const uint8_t* flags, const uint8_t* kstar, const uint16_t* iters,
                         const uint64_t* offsets, long long H, uint64_t capacity, hcz_stats* stats,
                         hipStream_t st);

@@ -269,11 +269,12 @@ __global__ __launch_bounds__(NT) void k_residual(GridDev G, ResidualArgs a) {
   fmx = block_max<NT>(fmx, red);
   fmnn = block_max<NT>(fmnn, red);
   const double b[4] = {acc[1], acc[2], acc[3], acc[4]};
-  const double tau_h = (a.tau_mode == HCZ_TAU_NRMSE) ? (a.tau * G.sqrtN) * (fmx - (-fmnn))
-                                                     : a.tau * sqrt(ff.hi + ff.lo);
+  const double tau = a.tau_hist ? a.tau_hist[h] : a.tau;
+  const double tau_h = (a.tau_mode == HCZ_TAU_NRMSE) ? (tau * G.sqrtN) * (fmx - (-fmnn))
+                                                     : tau * sqrt(ff.hi + ff.lo);
   const double thr = kSelMargin * tau_h;
   const double thr2 = thr * thr;
-  bool raw = (acc[5] > 0.0) || !(b[0] > 0.0);
+  bool raw = (acc[5] > 0.0) || !(b[0] > 0.0) || !(tau >= 0.0 && tau <= DBL_MAX);
   const bool coded = acc[0] > thr2;
   if (coded && !(tau_h > 0.0)) raw = true;
 
@@ -498,6 +499,7 @@ __global__ __launch_bounds__(NT) void k_residual(GridDev G, ResidualArgs a) {
     a.sizes[h] = size;
     a.kstar[h] = (uint8_t)kst;
     a.iters[h] = (uint16_t)min(total_upd, 65535);
+    if (a.t_done) a.t_done[h] = wall_clock64();
   }
 }
 

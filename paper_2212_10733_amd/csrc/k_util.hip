@@ -177,4 +177,59 @@ hipError_t launch_stats(const uint8_t* flags, const uint8_t* kstar, const uint16
   return hipGetLastError();
 }
 
+
+// ---- batches of subdomains -----------------------------------------------------------------
+
+// tau_hist[h] = seg_tau[s] with s the last segment whose start is <= h (starts clamped)
+__global__ __launch_bounds__(256) void k_segment_tau(const int64_t* start, const double* tau, int nseg,
+                                                     long long H, double* out) {
+  const long long h = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (h >= H) return;
+  int lo = 0, hi = nseg - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (start[mid] <= h) lo = mid;
+    else hi = mid - 1;
+  }
+  out[h] = tau[lo];
+}
+
+// one workgroup per segment: the maximum of t over its histograms
+__global__ __launch_bounds__(256) void k_segment_max(const int64_t* start, long long H, const uint64_t* t,
+                                                     uint64_t* out) {
+  __shared__ uint64_t red[256];
+  const int s = blockIdx.x;
+  const long long lo = min(max(start[s], (int64_t)0), (int64_t)H);
+  const long long hi = min(max(start[s + 1], (int64_t)lo), (int64_t)H);
+  uint64_t m = 0;
+  for (long long h = lo + threadIdx.x; h < hi; h += 256) m = max(m, t[h]);
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] = max(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[s] = red[0];
+}
+
+__global__ void k_timestamp(uint64_t* dst) { *dst = wall_clock64(); }
+
+hipError_t launch_segment_tau(const int64_t* start, const double* tau, int nseg, long long H, double* out,
+                              hipStream_t st) {
+  if (H <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_segment_tau, dim3((unsigned)((H + 255) / 256)), dim3(256), 0, st, start, tau, nseg, H, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_segment_max(const int64_t* start, int nseg, long long H, const uint64_t* t, uint64_t* out,
+                              hipStream_t st) {
+  hipLaunchKernelGGL(k_segment_max, dim3((unsigned)nseg), dim3(256), 0, st, start, H, t, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_timestamp(uint64_t* dst, hipStream_t st) {
+  hipLaunchKernelGGL(k_timestamp, dim3(1), dim3(1), 0, st, dst);
+  return hipGetLastError();
+}
+
 }  // namespace hcz

@@ -802,11 +802,12 @@ __global__ __launch_bounds__(256, 2) void k_residual_w(GridDev G, ResidualArgs a
   fmx = wmax(fmx);
   fmnn = wmax(fmnn);
   bad = __ballot(bad) != 0;
-  const double tau_h = (a.tau_mode == HCZ_TAU_NRMSE) ? (a.tau * G.sqrtN) * (fmx - (-fmnn))
-                                                     : a.tau * sqrt(ff.hi + ff.lo);
+  const double tau = a.tau_hist ? a.tau_hist[h] : a.tau;
+  const double tau_h = (a.tau_mode == HCZ_TAU_NRMSE) ? (tau * G.sqrtN) * (fmx - (-fmnn))
+                                                     : tau * sqrt(ff.hi + ff.lo);
   const double thr = kSelMargin * tau_h;
   const double thr2 = thr * thr;
-  bool raw = bad || !(b[0] > 0.0);
+  bool raw = bad || !(b[0] > 0.0) || !(tau >= 0.0 && tau <= DBL_MAX);
   const bool coded = rr > thr2;
   if (coded && !(tau_h > 0.0)) raw = true;
   wave_sync();
@@ -1032,6 +1033,7 @@ __global__ __launch_bounds__(256, 2) void k_residual_w(GridDev G, ResidualArgs a
     a.sizes[h] = size;
     a.kstar[h] = (uint8_t)kst;
     a.iters[h] = (uint16_t)min(total_upd, 65535);
+    if (a.t_done) a.t_done[h] = wall_clock64();
   }
 }
 

@@ -55,7 +55,7 @@ class Params(C.Structure):
                 ("newton_max_iter", C.c_int32), ("newton_max_iter2", C.c_int32),
                 ("fallback", C.c_int32), ("fit_codebook", C.c_int32), ("sample_every", C.c_int32),
                 ("warm_start", C.c_int32), ("mlp", C.c_void_p), ("lambda_fp32", C.c_int32),
-                ("no_positivity", C.c_int32)]
+                ("no_positivity", C.c_int32), ("tau_hist", C.c_void_p)]
 
 
 class Stats(C.Structure):
@@ -74,7 +74,8 @@ class Stats(C.Structure):
 class CompressedC(C.Structure):
     _fields_ = [("codes", C.c_void_p), ("lambda_", C.c_void_p), ("flags", C.c_void_p),
                 ("res_offset", C.c_void_p), ("res_bytes", C.c_void_p),
-                ("res_capacity", C.c_uint64), ("stats", C.c_void_p), ("lambda_fp32", C.c_int32)]
+                ("res_capacity", C.c_uint64), ("stats", C.c_void_p), ("lambda_fp32", C.c_int32),
+                ("t_done", C.c_void_p)]
 
 
 def _load() -> C.CDLL:
@@ -119,6 +120,10 @@ def _load() -> C.CDLL:
         "hcz_plan_path": [vp, C.POINTER(i32)],
         "hcz_profile_enable": [vp, C.c_int],
         "hcz_profile_read": [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)],
+        "hcz_segment_tau": [vp, vp, i32, i64, vp, vp],
+        "hcz_segment_max": [vp, i32, i64, vp, vp, vp],
+        "hcz_timestamp": [vp, vp],
+        "hcz_wall_clock_hz": [C.c_int, C.POINTER(C.c_double)],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -143,7 +148,8 @@ EXPORTS = ["hcz_create", "hcz_destroy", "hcz_last_error", "hcz_version", "hcz_pl
            "hcz_ae_param_count", "hcz_ae_saved_bytes", "hcz_ae_forward", "hcz_ae_backward",
            "hcz_mse_workspace", "hcz_mse", "hcz_adam_step", "hcz_norm_stats_workspace", "hcz_norm_stats",
            "hcz_mlp_load", "hcz_mlp_free", "hcz_mlp_param_count", "hcz_mlp_saved_bytes", "hcz_mlp_forward",
-           "hcz_mlp_backward", "hcz_dequantize", "hcz_mlp_predict"]
+           "hcz_mlp_backward", "hcz_dequantize", "hcz_mlp_predict", "hcz_segment_tau", "hcz_segment_max",
+           "hcz_timestamp", "hcz_wall_clock_hz"]
 
 STAGES = ["encode", "codebook", "quantize", "decode", "residual", "scan", "compact", "stats", "decompress",
           "warmstart"]
@@ -263,11 +269,18 @@ class Model:
 
 def params(tau=1e-3, tau_mode=TAU_REL_L2, newton_s=1.0, newton_max_iter=50, newton_max_iter2=400,
            fallback=FALLBACK_BACKTRACK, fit_codebook=False, sample_every=16, mlp=None, lambda_fp32=False,
-           no_positivity=False) -> Params:
+           no_positivity=False, tau_hist: torch.Tensor | None = None) -> Params:
+    """tau_hist: optional per-histogram bounds (device, float64, one per histogram), used in
+    place of tau."""
+    if tau_hist is not None and (tau_hist.dtype != torch.float64 or not tau_hist.is_cuda
+                                 or not tau_hist.is_contiguous()):
+        raise ValueError("tau_hist must be a contiguous float64 device tensor")
     p = Params(tau, tau_mode, newton_s, newton_max_iter, newton_max_iter2, fallback,
                int(fit_codebook), sample_every, WARM_MLP if mlp is not None else WARM_COLD,
-               None if mlp is None else mlp.h, int(lambda_fp32), int(no_positivity))
-    p._mlp = mlp          # keep the network alive as long as the parameters
+               None if mlp is None else mlp.h, int(lambda_fp32), int(no_positivity),
+               None if tau_hist is None else tau_hist.data_ptr())
+    p._mlp = mlp          # keep the network and the bounds alive as long as the parameters
+    p._tau_hist = tau_hist
     return p
 
 
@@ -311,11 +324,13 @@ class Compressed:
     offsets: torch.Tensor      # (H + 1,) int64 (u64 bits)
     stream: torch.Tensor       # (capacity,) uint8
     stats_dev: torch.Tensor    # sizeof(hcz_stats) bytes
+    t_done: torch.Tensor | None = None   # (H,) int64 (u64 bits): wall clock per histogram
 
     def cstruct(self) -> CompressedC:
         return CompressedC(self.codes.data_ptr(), self.lam.data_ptr(), self.flags.data_ptr(),
                            self.offsets.data_ptr(), self.stream.data_ptr(), self.stream.numel(),
-                           self.stats_dev.data_ptr(), int(self.lam.dtype == torch.float32))
+                           self.stats_dev.data_ptr(), int(self.lam.dtype == torch.float32),
+                           None if self.t_done is None else self.t_done.data_ptr())
 
     def stats(self) -> dict:
         s = Stats()
@@ -331,10 +346,11 @@ class Compressed:
 
 
 def alloc_compressed(H: int, N: int, device, latent=LATENT, capacity: int | None = None,
-                     in_bytes: int = 4, lambda_fp32: bool = False) -> Compressed:
+                     in_bytes: int = 4, lambda_fp32: bool = False, timestamps: bool = False) -> Compressed:
     if capacity is None:
         capacity = H * (24 + in_bytes * N)
     return Compressed(
+        t_done=torch.zeros(H, dtype=torch.int64, device=device) if timestamps else None,
         codes=torch.zeros((H, latent), dtype=torch.uint8, device=device),
         lam=torch.zeros((H, 4), dtype=torch.float32 if lambda_fp32 else torch.float64, device=device),
         flags=torch.zeros(H, dtype=torch.uint8, device=device),
@@ -427,7 +443,7 @@ class Compressor:
     """Preallocated compress/decompress for batches of up to H histograms (no allocation per call)."""
 
     def __init__(self, plan: Plan, model: Model | None, H: int, p: Params, bits: int = 8,
-                 in_dtype=torch.float32, capacity: int | None = None, device="cuda"):
+                 in_dtype=torch.float32, capacity: int | None = None, device="cuda", timestamps: bool = False):
         self.plan, self.model, self.H, self.p = plan, model, H, p
         nbytes = C.c_size_t()
         _check(LIB.hcz_compress_workspace(plan.h, None if model is None else model.h, H, C.byref(p),
@@ -437,7 +453,7 @@ class Compressor:
         self.dws = workspace(nbytes.value, device)
         esz = 4 if in_dtype == torch.float32 else 8
         self.out = alloc_compressed(H, plan.N, device, capacity=capacity, in_bytes=esz,
-                                    lambda_fp32=bool(p.lambda_fp32))
+                                    lambda_fp32=bool(p.lambda_fp32), timestamps=timestamps)
         self.centroids = torch.zeros((LATENT, 1 << bits), dtype=torch.float32, device=device)
         self.bits = bits
 
@@ -477,3 +493,38 @@ def norm_stats(plan: Plan, hist: torch.Tensor):
     _check(LIB.hcz_norm_stats(plan.h, _ptr(hist), _dtype_code(hist), H, hs, rs, _ptr(mu), _ptr(sd),
                               _ptr(ws), ws.numel(), _stream()))
     return mu, sd
+
+
+# ---- batches of subdomains --------------------------------------------------------------
+
+def segment_tau(seg_start: torch.Tensor, seg_tau: torch.Tensor, H: int) -> torch.Tensor:
+    """Per-histogram bounds of a batch of subdomains: histogram h of subdomain s (rows
+    seg_start[s] .. seg_start[s+1]-1) gets seg_tau[s]."""
+    nseg = seg_tau.numel()
+    if seg_start.dtype != torch.int64 or seg_start.numel() != nseg + 1 or seg_tau.dtype != torch.float64:
+        raise ValueError("seg_start: int64 [nseg+1], seg_tau: float64 [nseg]")
+    out = torch.empty(H, dtype=torch.float64, device=seg_tau.device)
+    _check(LIB.hcz_segment_tau(_ptr(seg_start.contiguous()), _ptr(seg_tau.contiguous()), nseg, H, _ptr(out),
+                               _stream()))
+    return out
+
+
+def segment_max(seg_start: torch.Tensor, t: torch.Tensor) -> torch.Tensor:
+    """Per-subdomain maximum of a per-histogram u64 array (int64 bits), e.g. t_done."""
+    nseg = seg_start.numel() - 1
+    out = torch.empty(nseg, dtype=torch.int64, device=t.device)
+    _check(LIB.hcz_segment_max(_ptr(seg_start.contiguous()), nseg, t.numel(), _ptr(t), _ptr(out), _stream()))
+    return out
+
+
+def timestamp(device="cuda") -> torch.Tensor:
+    """A one-element int64 tensor set to the device wall clock when the stream gets there."""
+    out = torch.zeros(1, dtype=torch.int64, device=device)
+    _check(LIB.hcz_timestamp(_ptr(out), _stream()))
+    return out
+
+
+def wall_clock_hz(device: int = 0) -> float:
+    hz = C.c_double()
+    _check(LIB.hcz_wall_clock_hz(device, C.byref(hz)))
+    return hz.value

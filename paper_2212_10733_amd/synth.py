@@ -165,3 +165,17 @@ def series(t: int, planes: int, nodes: int, n_par: int = 39, n_perp: int = 39, d
     r * nodes + m (r: plane, m: mesh node), bump centres moved by series_shift(t)."""
     return histograms(planes * nodes, n_par, n_perp, seed=SEED_SERIES + t, dtype=dtype,
                       shift=series_shift(t))
+
+
+BATCH_GRIDS = (33, 39, 49, 65)
+
+
+def subdomains(n: int = 512, seed: int = SEED_BATCHED, count_range=(500, 20000), tau_range=(1e-4, 1e-2),
+               grids=BATCH_GRIDS) -> list:
+    """Layout of a batch of uneven subdomains: for each, (grid size g of a g x g grid,
+    histogram count, tau), counts and tau log-uniform over their ranges, grids uniform."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    g = rng.integers(0, len(grids), size=n)
+    c = np.exp(rng.uniform(math.log(count_range[0]), math.log(count_range[1]), size=n)).astype(np.int64)
+    t = np.exp(rng.uniform(math.log(tau_range[0]), math.log(tau_range[1]), size=n))
+    return [(int(grids[g[i]]), int(c[i]), float(t[i])) for i in range(n)]

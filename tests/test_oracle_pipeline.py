@@ -157,3 +157,27 @@ def test_bf16_form_roundtrip():
     f64 = pipeline.reconstruct_ae(comp["codes"], C, model, F.shape)
     scale = np.abs(f64).max()
     assert 1e-6 * scale < np.abs(f16 - f64).max() < 3e-2 * scale
+
+
+def test_per_histogram_tau_is_the_scalar_form_per_subdomain():
+    """Subdomains with their own bounds in one batch: every histogram's record, flags and
+    multipliers are those of compressing its subdomain alone with the scalar bound; a
+    negative or NaN bound stores the histogram verbatim."""
+    g = grid.make_grid(33, 33)
+    F = synth.histograms(30, 33, 33, seed=28, dtype=np.float32)
+    counts, taus = [7, 0, 11, 4, 8], [1e-2, 5e-3, 1e-4, -1.0, np.nan]
+    tau = np.repeat(taus, counts)
+    comp = pipeline.compress(F, g, None, None, pipeline.Params(tau=tau))
+    start = np.concatenate([[0], np.cumsum(counts)])
+    for s, t in enumerate(taus):
+        lo, hi = start[s], start[s + 1]
+        if hi == lo:
+            continue
+        if not (t >= 0):
+            assert np.all(comp["flags"][lo:hi] == pipeline.FLAG_RAW)
+            assert np.array_equal(comp["fc"][lo:hi], F[lo:hi].astype(np.float64))
+            continue
+        one = pipeline.compress(F[lo:hi], g, None, None, pipeline.Params(tau=t))
+        assert np.array_equal(comp["flags"][lo:hi], one["flags"])
+        assert np.array_equal(comp["lam"][lo:hi], one["lam"])
+        assert comp["stream"][comp["offsets"][lo]:comp["offsets"][hi]] == one["stream"]
