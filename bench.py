@@ -190,6 +190,54 @@ def bf16_form(hcz, plan, ctx, x, W, args) -> dict:
     return res
 
 
+def batched_form(hcz, ctx, args, n_sub=512, reps=3) -> dict:
+    """512 subdomains of uneven sizes (log-uniform 500..20,000 histograms) on 33x33, 39x39,
+    49x49 and 65x65 grids, each with its own tau (log-uniform 1e-4..1e-2): one plan, dense
+    FP32 model (Xavier, z-score statistics of its grid's histograms) and per-batch codebook
+    per grid size.  Reported: whole-batch throughput (histograms/s and input GB/s), and the
+    per-subdomain completion time (residual stage done) p50/p99 of the last repetition."""
+    import torch
+
+    from paper_2212_10733_amd import batched, synth
+    layout = synth.subdomains(n_sub)
+    plans, models, inputs = {}, {}, {}
+    nbytes = 0
+    for n in synth.BATCH_GRIDS:
+        Hn = sum(c for g, c, _ in layout if g == n)
+        plans[n] = hcz.Plan(ctx, n, n)
+        F = synth.histograms(Hn, n, n, seed=synth.SEED_BATCHED * 100 + n, dtype=np.float32)
+        x = torch.from_numpy(F).cuda()
+        del F
+        mu, sd = hcz.norm_stats(plans[n], x)
+        models[n] = hcz.Model(plans[n], synth.dense_ae_weights(n * n), mu.cpu().numpy(), sd.cpu().numpy())
+        inputs[n] = x
+        nbytes += x.numel() * 4
+    Htot = sum(c for _, c, _ in layout)
+    sb = batched.SubdomainBatch(plans, models, layout)
+    sb.compress(inputs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        comps = sb.compress(inputs)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    done = sb.completion_seconds()
+    live = np.array([c > 0 for _, c, _ in layout])
+    st = {k: c.stats() for k, c in comps.items()}
+    res = {"subdomains": n_sub, "histograms": Htot, "input_bytes": nbytes, "value": Htot / dt,
+           "unit": "histograms/s", "ms_per_step": dt * 1e3, "input_GBps": nbytes / dt / 1e9,
+           "completion_ms_p50": float(np.percentile(done[live], 50) * 1e3),
+           "completion_ms_p99": float(np.percentile(done[live], 99) * 1e3),
+           "completion_ms_max": float(done[live].max() * 1e3),
+           "per_grid": {f"{k}x{k}": {"histograms": sb.groups[k]["H"], "coded_frac": s["n_coded"] / max(1, s["n_hist"]),
+                                     "raw": s["n_raw"], "stream_bytes": s["stream_bytes"],
+                                     "newton_mean_updates": s["newton_iters_total"] / max(1, s["n_hist"] - s["n_raw"])}
+                        for k, s in st.items()}}
+    del sb, comps, inputs, models, plans
+    torch.cuda.empty_cache()
+    return res
+
+
 def incremental_form(hcz, plan, H, W, args, steps=4, planes=8) -> dict:
     """Incremental training (Section IV-C) on a drifting synthetic series: at every step a
     batch of planes x nodes = H / 4 histograms (262,144 at H = 2^20), training rows chosen
@@ -254,6 +302,9 @@ def other_forms(hcz, plan, ctx, x, F, W, args, plain_value, plain_stats) -> dict
     if "bf16" in args.forms:
         log("form: BF16 autoencoder")
         out["bf16_ae"] = bf16_form(hcz, plan, ctx, x, W, args)
+    if "batched" in args.forms:
+        log("form: batched uneven subdomains")
+        out["batched"] = batched_form(hcz, ctx, args)
     if "incremental" in args.forms:
         log("form: incremental training series")
         out["incremental"] = incremental_form(hcz, plan, x.shape[0], W, args)
@@ -324,9 +375,10 @@ def main() -> int:
     ap.add_argument("--cpu-sample", type=int, default=8192)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the coder-only and learned forms")
-    ap.add_argument("--forms", default="tau,coder,bf16,incremental,learned",
+    ap.add_argument("--forms", default="tau,coder,bf16,batched,incremental,learned",
                     help="comma list of the other forms to run: tau (sweep), coder (coder-only), "
-                         "bf16 (BF16 autoencoder), incremental (training series), learned")
+                         "bf16 (BF16 autoencoder), batched (uneven subdomains on four grids), "
+                         "incremental (training series), learned")
     ap.add_argument("--train-hist", type=int, default=262144)
     ap.add_argument("--epochs", type=int, default=20)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",

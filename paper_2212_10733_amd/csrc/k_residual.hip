@@ -25,21 +25,19 @@ __device__ __forceinline__ int group_of(const GridDev& G, int p) {
   return g;
 }
 
-// Recompose the reconstruction of all owned nodes for step size Dk (1/Dk = inv) and
-// return the block-wide sum of (r - y)^2.  y_out gets the owned nodes' values.
+// Recompose the reconstruction of all owned nodes for step size Dk (1/Dk = inv) into buf
+// (natural order) and return the block-wide sum of (r - y)^2.
 template <int NT, int NPT>
 __device__ double recompose_err(const GridDev& G, double* buf, double* red, const int (&gm)[NPT],
                                 const int (&em)[NPT], const Interp (&cm)[NPT],
                                 const double (&dm)[NPT], const double (&rm)[NPT], double Dk,
-                                double inv, double (&y_out)[NPT]) {
+                                double inv) {
   for (int g = 0; g < G.nlev; ++g) {
 #pragma unroll
     for (int m = 0; m < NPT; ++m) {
       if (gm[m] == g) {
         const double dq = qdelta(Dk, dm[m], inv);
-        const double y = (g == 0) ? dq : __dadd_rn(dq, predict(buf, cm[m]));
-        buf[em[m]] = y;
-        y_out[m] = y;
+        buf[em[m]] = (g == 0) ? dq : __dadd_rn(dq, predict(buf, cm[m]));
       }
     }
     __syncthreads();
@@ -48,7 +46,7 @@ __device__ double recompose_err(const GridDev& G, double* buf, double* red, cons
 #pragma unroll
   for (int m = 0; m < NPT; ++m) {
     if (em[m] >= 0) {
-      const double e = rm[m] - y_out[m];
+      const double e = rm[m] - buf[em[m]];
       s[0] = fma(e, e, s[0]);
     }
   }
@@ -61,16 +59,21 @@ __device__ double recompose_err(const GridDev& G, double* buf, double* red, cons
 // With pos = false (the projection onto {A x = b} alone) x may be negative: v[16..18]
 // then hold sum A_k |x| for k = 0, 2, 3 and v[4] sum |A_1| |x|, the stopping rule's scales.
 constexpr int kNv = 19;
-template <int NT, int NPT>
-__device__ void newton_pass(const double (&ftm)[NPT], const Aphi (&Am)[NPT], const int (&em)[NPT],
-                            const double (&lam)[4], double (&v)[kNv], double* red, bool pos) {
+// ft: the reconstruction f^ + r^ in LDS, natural order; thread t takes cells t, t + NT, ...
+template <int NT>
+__device__ void newton_pass(const GridDev& G, const double* ft, const double (&lam)[4], double (&v)[kNv],
+                            double* red, bool pos) {
 #pragma unroll
   for (int k = 0; k < kNv; ++k) v[k] = 0.0;
-#pragma unroll
-  for (int m = 0; m < NPT; ++m) {
-    if (em[m] < 0) continue;
-    const Aphi& A = Am[m];
-    const double y = ftm[m] - correction(A, lam);
+  int i = (int)threadIdx.x % G.n_par, j = (int)threadIdx.x / G.n_par;
+  const int di = NT % G.n_par, dj = NT / G.n_par;
+  for (int e = threadIdx.x; e < G.N; e += NT) {
+    const Aphi A = make_aphi(G, e, i, j);
+    const double fte = ft[e];
+    i += di;
+    j += dj;
+    if (i >= G.n_par) { i -= G.n_par; ++j; }
+    const double y = fte - correction(A, lam);
     const double x = pos ? fmax(0.0, y) : y;
     const double xa = fabs(x);
     v[0] = fma(A.a0, x, v[0]);
@@ -93,7 +96,7 @@ __device__ void newton_pass(const double (&ftm)[NPT], const Aphi (&Am)[NPT], con
       v[13] = fma(A.a2, A.a3, v[13]);
       v[14] = fma(A.a3, A.a3, v[14]);
     }
-    const double dx = x - ftm[m];
+    const double dx = x - fte;
     v[15] = fma(dx, dx, v[15]);
   }
   block_sum<NT, kNv>(v, red);
@@ -162,13 +165,12 @@ __device__ __forceinline__ bool chol_solve4(const double (&v)[kNv], const double
 
 // One Newton round (Eq. 6).  armijo = false: lam += s d; true: backtracking on theta.
 // Returns true when the stopping rule holds; *upd counts the updates made.
-template <int NT, int NPT>
-__device__ bool newton_round(const double (&ftm)[NPT], const Aphi (&Am)[NPT], const int (&em)[NPT],
-                             const double (&b)[4], double (&lam)[4], double s, int max_iter,
-                             bool armijo, double* red, int* upd, bool pos) {
+template <int NT>
+__device__ bool newton_round(const GridDev& G, const double* ft, const double (&b)[4], double (&lam)[4],
+                             double s, int max_iter, bool armijo, double* red, int* upd, bool pos) {
   double v[kNv];
   for (int it = 0; it <= max_iter; ++it) {
-    newton_pass<NT, NPT>(ftm, Am, em, lam, v, red, pos);
+    newton_pass<NT>(G, ft, lam, v, red, pos);
     double g[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) g[k] = v[k] - b[k];
@@ -195,7 +197,7 @@ __device__ bool newton_round(const double (&ftm)[NPT], const Aphi (&Am)[NPT], co
 #pragma unroll
         for (int k = 0; k < 4; ++k) cand[k] = lam[k] + step * d[k];
         double w[kNv];
-        newton_pass<NT, NPT>(ftm, Am, em, cand, w, red, pos);
+        newton_pass<NT>(G, ft, cand, w, red, pos);
         if (theta_of(w, cand, b) >= t0 + kArmijoC * step * gd) { ok = true; break; }
         step *= 0.5;
       }
@@ -281,17 +283,13 @@ __global__ __launch_bounds__(NT) void k_residual(GridDev G, ResidualArgs a) {
   // ---- owned nodes ---------------------------------------------------------------
   int em[NPT], gm[NPT];
   Interp cm[NPT];
-  double rm[NPT], ym[NPT];
-  float fm[NPT];
-  Aphi Am[NPT];
+  double rm[NPT];
 #pragma unroll
   for (int m = 0; m < NPT; ++m) {
     const int p = t + NT * m;
     em[m] = -1;
     gm[m] = 99;
-    ym[m] = 0.0;
     rm[m] = 0.0;
-    fm[m] = 0.0f;
     if (p < N) {
       const uint32_t ij = G.node_ij[p];
       const int i = ij & 0xffff, j = ij >> 16;
@@ -299,15 +297,14 @@ __global__ __launch_bounds__(NT) void k_residual(GridDev G, ResidualArgs a) {
       gm[m] = group_of(G, p);
       cm[m] = make_interp(G, i, j);
       rm[m] = buf[em[m]];
-      fm[m] = fh[em[m]];
-      Am[m] = make_aphi(G, em[m], i, j);
     }
   }
 
   int kst = 0xff;
   uint32_t rec_bytes = 0;
+  bool have_y = false;          // buf holds the recomposition at ladder index kst
+  double dm[NPT];
   if (coded && !raw) {
-    double dm[NPT];
     double mx = 0.0;
 #pragma unroll
     for (int m = 0; m < NPT; ++m) {
@@ -321,28 +318,33 @@ __global__ __launch_bounds__(NT) void k_residual(GridDev G, ResidualArgs a) {
     const double d0 = (kLadderMargin * tau_h) / G.den;
     if (mx * (1.0 / d0) >= kQMax) raw = true;
     if (!raw) {
-      int lo = 0, hi = kLadder;
-      bool have = false;
-      double yc[NPT];
+      int lo = 0, hi = kLadder, at = -1;
       while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
         const double Dk = ladder(d0, mid);
-        const double e2 = recompose_err<NT, NPT>(G, buf, red, gm, em, cm, dm, rm, Dk, 1.0 / Dk, yc);
-        if (e2 <= thr2) {
-          lo = mid;
-          have = true;
-#pragma unroll
-          for (int m = 0; m < NPT; ++m) ym[m] = yc[m];
-        } else {
-          hi = mid;
-        }
-      }
-      if (!have) {
-        const double Dk = ladder(d0, 0);
-        recompose_err<NT, NPT>(G, buf, red, gm, em, cm, dm, rm, Dk, 1.0 / Dk, ym);
+        const double e2 = recompose_err<NT, NPT>(G, buf, red, gm, em, cm, dm, rm, Dk, 1.0 / Dk);
+        at = mid;
+        if (e2 <= thr2) lo = mid;
+        else hi = mid;
       }
       kst = lo;
+      if (at != kst) {
+        const double Dk = ladder(d0, kst);
+        recompose_err<NT, NPT>(G, buf, red, gm, em, cm, dm, rm, Dk, 1.0 / Dk);
+      }
+      have_y = true;
+    }
+  }
+
+  // ft = f^ + r^ (r^ = 0 without a record) in natural order, before the record's words reuse
+  // the f^ array
+  for (int e = t; e < N; e += NT) buf[e] = (double)fh[e] + (have_y ? buf[e] : 0.0);
+  __syncthreads();
+
+  if (have_y) {
+    {
       // ---- record: header + zigzag integers, group widths, LSB-first bit packing ----
+      const double d0 = (kLadderMargin * tau_h) / G.den;
       const double Dk = ladder(d0, kst);
       const double inv = 1.0 / Dk;
       uint32_t um[NPT];
@@ -408,9 +410,7 @@ __global__ __launch_bounds__(NT) void k_residual(GridDev G, ResidualArgs a) {
   double lam[4] = {0.0, 0.0, 0.0, 0.0};
   int flags = 0, total_upd = 0;
   if (!raw) {
-    double ftm[NPT];
-#pragma unroll
-    for (int m = 0; m < NPT; ++m) ftm[m] = (double)fm[m] + ym[m];
+    const double* ft = buf;
     if (a.lam0) {
       // warm start: keep it unless round 1 allows no update, its Cholesky step fails, or
       // that step makes max_k |g_k| / s_k grow
@@ -420,7 +420,7 @@ __global__ __launch_bounds__(NT) void k_residual(GridDev G, ResidualArgs a) {
 #pragma unroll
       for (int k = 0; k < 4; ++k) { l0[k] = a.lam0[h * 4 + k]; ok0 = ok0 && isfinite(l0[k]); }
       if (ok0) {
-        newton_pass<NT, NPT>(ftm, Am, em, l0, v, red, pos);
+        newton_pass<NT>(G, ft, l0, v, red, pos);
         double r0 = 0.0;
         bool conv = true;
         double sc[4];
@@ -437,7 +437,7 @@ __global__ __launch_bounds__(NT) void k_residual(GridDev G, ResidualArgs a) {
             double l1[4];
 #pragma unroll
             for (int k = 0; k < 4; ++k) l1[k] = l0[k] + a.newton_s * d[k];
-            newton_pass<NT, NPT>(ftm, Am, em, l1, v, red, pos);
+            newton_pass<NT>(G, ft, l1, v, red, pos);
             double sc1[4];
             pass_scales(v, pos, sc1);
             double r1 = 0.0;
@@ -455,15 +455,13 @@ __global__ __launch_bounds__(NT) void k_residual(GridDev G, ResidualArgs a) {
       }
     }
     int u1 = 0;
-    bool ok = newton_round<NT, NPT>(ftm, Am, em, b, lam, a.newton_s, a.max_iter, false, red, &u1,
-                                    !a.no_positivity);
+    bool ok = newton_round<NT>(G, ft, b, lam, a.newton_s, a.max_iter, false, red, &u1, !a.no_positivity);
     total_upd = u1;
     if (!ok) {
       flags |= HCZ_FLAG_ROUND2;
       int u2 = 0;
       const bool paper = a.fallback == HCZ_FALLBACK_PAPER;
-      ok = newton_round<NT, NPT>(ftm, Am, em, b, lam, paper ? 0.01 : 1.0, a.max_iter2, !paper, red, &u2,
-                                 !a.no_positivity);
+      ok = newton_round<NT>(G, ft, b, lam, paper ? 0.01 : 1.0, a.max_iter2, !paper, red, &u2, !a.no_positivity);
       total_upd += u2;
       if (!ok) raw = true;
     }
@@ -678,14 +676,15 @@ static int pick_nt(int N) { return N <= 1536 ? 256 : (N <= 3072 ? 512 : 1024); }
 hipError_t launch_residual(const GridDev& G, const ResidualArgs& a, hipStream_t st) {
   if (a.H <= 0) return hipSuccess;
   if (wave_path(G)) return launch_residual_w(G, a, st);
-  const int nt = pick_nt(G.N);
+  // nodes per thread: 256 x 6 up to 1536 nodes, then 512 x 5 (2560) and 512 x 9 (4608)
+  const int nt = G.N <= 1536 ? 256 : 512;
   const size_t lds = (size_t)G.N * 8 + (size_t)((G.N + 1) / 2) * 8 + (size_t)(nt / 64) * kNv * 8;
   dim3 grid((unsigned)a.H), block(nt);
-#define HCZ_RES(NT, T) hipLaunchKernelGGL((k_residual<NT, 6, T>), grid, block, lds, st, G, a)
+#define HCZ_RES(NT, NPT, T) hipLaunchKernelGGL((k_residual<NT, NPT, T>), grid, block, lds, st, G, a)
   if (a.dtype == HCZ_F32) {
-    if (nt == 256) HCZ_RES(256, float); else if (nt == 512) HCZ_RES(512, float); else HCZ_RES(1024, float);
+    if (G.N <= 1536) HCZ_RES(256, 6, float); else if (G.N <= 2560) HCZ_RES(512, 5, float); else HCZ_RES(512, 9, float);
   } else {
-    if (nt == 256) HCZ_RES(256, double); else if (nt == 512) HCZ_RES(512, double); else HCZ_RES(1024, double);
+    if (G.N <= 1536) HCZ_RES(256, 6, double); else if (G.N <= 2560) HCZ_RES(512, 5, double); else HCZ_RES(512, 9, double);
   }
 #undef HCZ_RES
   return hipGetLastError();
