@@ -10,6 +10,7 @@ FP64 (plus `math.fsum` for correctly rounded moment sums), written from the pape
   ae        dense / tied-linear autoencoder forward+backward, MSE, Adam, z-score
                                                                   (Section III Stage 2-3, Eq. 5;
                                                                    Section IV-B)
+  conv      convolutional autoencoder for 39 x 39 grids, BF16 form (Section III Stage 2)
   pq        per-dimension product-quantizer fit (1-D k-means) and encode
                                                                   (Section III Stage 3, IV-E)
   coder     multilevel residual coder with bound bisection        (Section III Stage 4)
@@ -23,4 +24,4 @@ Where the paper defers to works that are not available (the exact Stage-5 object
 MGARD coefficients, the PQ initialisation), the oracle follows a stated reading; its
 agreement with the paper's own outputs is unpinned.
 """
-from . import grid, moments, ae, pq, coder, newton, pipeline, metrics  # noqa: F401
+from . import grid, moments, ae, conv, pq, coder, newton, pipeline, metrics  # noqa: F401

@@ -179,3 +179,29 @@ def subdomains(n: int = 512, seed: int = SEED_BATCHED, count_range=(500, 20000),
     c = np.exp(rng.uniform(math.log(count_range[0]), math.log(count_range[1]), size=n)).astype(np.int64)
     t = np.exp(rng.uniform(math.log(tau_range[0]), math.log(tau_range[1]), size=n))
     return [(int(grids[g[i]]), int(c[i]), float(t[i])) for i in range(n)]
+
+
+CONV_SHAPES = dict(c1w=(32, 1, 3, 3), c1b=(32,), c2w=(64, 32, 3, 3), c2b=(64,), fw=(16, 6400), fb=(16,),
+                   dw=(6400, 16), db=(6400,), t1w=(64, 32, 3, 3), t1b=(32,), t2w=(32, 1, 3, 3), t2b=(1,))
+CONV_KEYS = tuple(CONV_SHAPES)
+
+
+def conv_ae_weights(seed: int = SEED_WEIGHTS) -> dict:
+    """Xavier-uniform weights of the convolutional autoencoder for 39 x 39 grids:
+    conv 3x3 1->32 and 32->64 (stride 2, padding 1: 39 -> 20 -> 10), dense 6400 -> 16;
+    decoder dense 16 -> 6400, transposed conv 64 -> 32 (stride 2, padding 1, output
+    padding 1: 10 -> 20) and 32 -> 1 (stride 2, padding 1: 20 -> 39).  Shapes as in
+    CONV_SHAPES (conv weights [out][in][ky][kx], transposed conv [in][out][ky][kx], dense
+    [out][in]); fan sizes count the 3 x 3 window.  Biases are zero.  Draw order: c1w, c2w,
+    fw, dw, t1w, t2w from one PCG64 stream."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = {}
+    for k, s in CONV_SHAPES.items():
+        if len(s) == 1:
+            out[k] = np.zeros(s, np.float32)
+            continue
+        rf = s[2] * s[3] if len(s) == 4 else 1
+        fan_sum = (s[0] + s[1]) * rf
+        a = math.sqrt(6.0 / fan_sum)
+        out[k] = rng.uniform(-a, a, size=s).astype(np.float32)
+    return out
