@@ -53,7 +53,7 @@ typedef enum {
 } hcz_status;
 
 enum { HCZ_F32 = 0, HCZ_F64 = 1 };                       /* element types */
-enum { HCZ_ARCH_DENSE = 1 };                              /* autoencoder architectures */
+enum { HCZ_ARCH_DENSE = 1, HCZ_ARCH_CONV = 2 };           /* autoencoder architectures */
 enum { HCZ_COMPUTE_FP32 = 0, HCZ_COMPUTE_BF16 = 1 };      /* autoencoder arithmetic */
 enum { HCZ_TAU_REL_L2 = 0, HCZ_TAU_NRMSE = 1 };          /* tau_h = tau ||f||, tau sqrt(N)(max-min) */
 enum { HCZ_FALLBACK_BACKTRACK = 0, HCZ_FALLBACK_PAPER = 1 };
@@ -90,7 +90,20 @@ typedef struct {
  *   bfloat16 against W1 rounded at load; h3 = relu(b3 + sum_d zhat_d W3[:, d]) as FP32
  *   fused multiply-adds in order d = 0..15, rounded likewise, against W4 rounded at load.
  *   The 128 -> latent and latent -> 128 layers stay FP32.  Compression and decompression
- *   evaluate the decoder with the same kernel, so they agree bit for bit either way. */
+ *   evaluate the decoder with the same kernel, so they agree bit for bit either way.
+ * arch = HCZ_ARCH_CONV: the convolutional autoencoder of 39 x 39 grids (latent 16,
+ *   compute = HCZ_COMPUTE_BF16; hidden is ignored).  weights (host, FP32) holds, back to
+ *   back: c1w[32][1][3][3], c1b[32], c2w[64][32][3][3], c2b[64], fw[16][6400], fb[16],
+ *   dw[6400][16], db[6400], t1w[64][32][3][3], t1b[32], t2w[32][1][3][3], t2b[1]
+ *   (248,785 values).  Encoder: relu(conv1) 3x3 1 -> 32 stride 2 padding 1 (39 -> 20),
+ *   relu(conv2) 32 -> 64 (20 -> 10), z = fw h2 + fb with h2 flattened channel-major;
+ *   decoder: hd = relu(dw zhat + db) as 64 x 10 x 10, relu(transposed conv) 64 -> 32
+ *   stride 2 padding 1 output padding 1 (10 -> 20), transposed conv 32 -> 1 (20 -> 39),
+ *   fhat = std * y + mean.  conv1 and the decoder's dense layer are FP32 fused
+ *   multiply-add chains (conv1 over the in-range taps in row-major order, the dense layer
+ *   over d = 0..15); their ReLU outputs and the weights of conv2 and of the first
+ *   transposed conv are rounded to nearest-even bfloat16 for the matrix cores (FP32
+ *   accumulation); the rest is FP32.  Other grids or compute forms: HCZ_EUNSUPPORTED. */
 typedef struct {
   int32_t arch;
   int32_t latent, hidden;

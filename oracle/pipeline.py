@@ -25,7 +25,7 @@ from dataclasses import dataclass
 
 import numpy as np
 
-from . import ae, coder, mlp as mlp_net, newton, pq
+from . import ae, coder, conv, mlp as mlp_net, newton, pq
 from .grid import Grid
 from .moments import moments
 
@@ -66,6 +66,10 @@ def _bf16(model: dict) -> bool:
 
 
 def encode_ae(F64: np.ndarray, model: dict) -> np.ndarray:
+    if model.get("arch", "dense") == "conv":
+        sd32 = np.asarray(model["sd"], np.float32)
+        return conv.encode_bf16(F64.astype(np.float32), np.asarray(model["mu"], np.float32),
+                                np.float32(1) / sd32, model["W"])
     if _bf16(model):
         sd32 = np.asarray(model["sd"], np.float32)
         return ae.dense_encode_bf16(F64.astype(np.float32), np.asarray(model["mu"], np.float32),
@@ -75,6 +79,9 @@ def encode_ae(F64: np.ndarray, model: dict) -> np.ndarray:
 
 def reconstruct_ae(codes: np.ndarray, C: np.ndarray, model: dict, shape) -> np.ndarray:
     Zh = pq.decode(codes, C)
+    if model.get("arch", "dense") == "conv":
+        return conv.decode_bf16(Zh, model["W"], np.asarray(model["mu"], np.float32),
+                                np.asarray(model["sd"], np.float32)).reshape(shape)
     if _bf16(model):
         return ae.dense_decode_bf16(Zh, model["W"], np.asarray(model["mu"], np.float32),
                                     np.asarray(model["sd"], np.float32)).reshape(shape)
@@ -93,7 +100,7 @@ def compress(F: np.ndarray, g: Grid, model: dict | None, C: np.ndarray | None, p
     Fz = np.where(finite[:, None, None], F64, 0.0)
     b = moments(Fz, g)
     th = tau_h(Fz, p)
-    L = model["W"]["W2"].shape[0] if model else 0
+    L = (model["W"]["fw"] if model.get("arch") == "conv" else model["W"]["W2"]).shape[0] if model else 0
     codes = np.zeros((H, L), np.uint8)
     Z = None
     if model is not None:

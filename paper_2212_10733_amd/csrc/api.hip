@@ -582,9 +582,62 @@ static uint16_t bf16_rne(float x) {
   return (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
 }
 
+static hcz_status conv_model_load(hcz_plan* plan, const hcz_model_desc* d, hcz_model** out) {
+  if (plan->G.n_par != 39 || plan->G.n_perp != 39)
+    return fail(HCZ_EUNSUPPORTED, "the convolutional model needs a 39 x 39 grid");
+  if (d->latent != kLatent) return fail(HCZ_EUNSUPPORTED, "convolutional model must have latent %d", kLatent);
+  if (d->compute != HCZ_COMPUTE_BF16) return fail(HCZ_EUNSUPPORTED, "the convolutional model runs in the BF16 form");
+  if (!d->weights || !d->norm_mean || !d->norm_std) return fail(HCZ_EINVAL, "weights or norm stats NULL");
+  hcz_status s = set_device(plan->ctx);
+  if (s) return s;
+  const int N = 1521;
+  std::vector<float> mu(d->norm_mean, d->norm_mean + N), sd(d->norm_std, d->norm_std + N), rsd(N);
+  for (int k = 0; k < N; ++k) {
+    if (!(sd[k] > 0.0f) || !std::isfinite(sd[k]) || !std::isfinite(mu[k]))
+      return fail(HCZ_EINVAL, "norm_std[%d] must be finite and > 0", k);
+    rsd[k] = 1.0f / sd[k];
+  }
+  const float* w = d->weights;
+  const float *c1w = w, *c1b = c1w + 288, *c2w = c1b + 32, *c2b = c2w + 18432, *fw = c2b + 64,
+              *fb = fw + 102400, *dw = fb + 16, *db = dw + 102400, *t1w = db + 6400, *t1b = t1w + 18432,
+              *t2w = t1b + 32, *t2b = t2w + 288;
+  // matrix-core operands: bfloat16, [tap][out][in]
+  std::vector<uint16_t> c2(9 * 64 * 32), t1(9 * 32 * 64);
+  for (int co = 0; co < 64; ++co)
+    for (int ci = 0; ci < 32; ++ci)
+      for (int tap = 0; tap < 9; ++tap) c2[(tap * 64 + co) * 32 + ci] = bf16_rne(c2w[(co * 32 + ci) * 9 + tap]);
+  for (int ci = 0; ci < 64; ++ci)
+    for (int co = 0; co < 32; ++co)
+      for (int tap = 0; tap < 9; ++tap) t1[(tap * 32 + co) * 64 + ci] = bf16_rne(t1w[(ci * 32 + co) * 9 + tap]);
+  hcz_model* m = new hcz_model();
+  m->plan = plan;
+  ModelDev& M = m->M;
+  M.N = N;
+  M.hidden = 0;
+  M.latent = kLatent;
+  M.arch = HCZ_ARCH_CONV;
+  M.bf16 = 1;
+  auto vec = [](const float* p, size_t n) { return std::vector<float>(p, p + n); };
+  if ((s = upload(m->allocs, vec(c1w, 288), &M.c1w)) || (s = upload(m->allocs, vec(c1b, 32), &M.c1b)) ||
+      (s = upload(m->allocs, c2, &M.c2w)) || (s = upload(m->allocs, vec(c2b, 64), &M.c2b)) ||
+      (s = upload(m->allocs, vec(fw, 102400), &M.fw)) || (s = upload(m->allocs, vec(fb, 16), &M.fb)) ||
+      (s = upload(m->allocs, vec(dw, 102400), &M.dw)) || (s = upload(m->allocs, vec(db, 6400), &M.db)) ||
+      (s = upload(m->allocs, t1, &M.t1w)) || (s = upload(m->allocs, vec(t1b, 32), &M.t1b)) ||
+      (s = upload(m->allocs, vec(t2w, 288), &M.t2w)) || (s = upload(m->allocs, vec(t2b, 1), &M.t2b)) ||
+      (s = upload(m->allocs, mu, &M.mu)) || (s = upload(m->allocs, rsd, &M.rsd)) ||
+      (s = upload(m->allocs, sd, &M.sd))) {
+    free_all(m->allocs);
+    delete m;
+    return s;
+  }
+  *out = m;
+  return HCZ_OK;
+}
+
 hcz_status hcz_model_load(hcz_plan* plan, const hcz_model_desc* d, hcz_model** out) {
   if (!plan || !d || !out) return fail(HCZ_EINVAL, "NULL argument");
   *out = nullptr;
+  if (d->arch == HCZ_ARCH_CONV) return conv_model_load(plan, d, out);
   if (d->arch != HCZ_ARCH_DENSE) return fail(HCZ_EUNSUPPORTED, "arch %d", d->arch);
   if (d->hidden != kHidden || d->latent != kLatent)
     return fail(HCZ_EUNSUPPORTED, "dense model must be hidden %d, latent %d", kHidden, kLatent);
@@ -618,6 +671,7 @@ hcz_status hcz_model_load(hcz_plan* plan, const hcz_model_desc* d, hcz_model** o
   M.kpad = kpad;
   M.npad = npad;
   M.bf16 = d->compute == HCZ_COMPUTE_BF16;
+  M.arch = HCZ_ARCH_DENSE;
   std::vector<float> vb1(b1, b1 + Hd), vW2(W2, W2 + Ld * Hd), vb2(b2, b2 + Ld), vW3(W3, W3 + Hd * Ld),
       vb3(b3, b3 + Hd), vb4(b4, b4 + N);
   if (M.bf16) {

@@ -80,6 +80,20 @@ struct ModelDev {
   int bf16;                        // 1: the BF16 form (W1b, W4b below)
   const uint16_t* W1b;             // [hidden][kpad] bfloat16 of W1, zero padded
   const uint16_t* W4b;             // [npad][hidden] bfloat16 of W4, rows >= N zero
+  // convolutional model (39 x 39 grids), arch == HCZ_ARCH_CONV
+  int arch;
+  const float* c1w;                // [32][9]
+  const float* c1b;                // [32]
+  const uint16_t* c2w;             // bfloat16 [tap][64 out][32 in]
+  const float* c2b;                // [64]
+  const float* fw;                 // [16][6400]
+  const float* fb;                 // [16]
+  const float* dw;                 // [6400][16]
+  const float* db;                 // [6400]
+  const uint16_t* t1w;             // bfloat16 [tap][32 out][64 in]
+  const float* t1b;                // [32]
+  const float* t2w;                // [32][9]
+  const float* t2b;                // [1]
 };
 
 struct ResidualArgs {
@@ -322,6 +336,10 @@ hipError_t launch_encode(const ModelDev& M, const void* hist, int dtype, long lo
                          long long rs, int n_par, float* z, hipStream_t st);
 hipError_t launch_decode(const ModelDev& M, const uint8_t* codes, const float* centroids, int bits,
                          long long H, float* fhat, hipStream_t st);
+hipError_t launch_conv_encode(const ModelDev& M, const void* hist, int dtype, long long H, long long hs,
+                              long long rs, float* z, hipStream_t st);
+hipError_t launch_conv_decode(const ModelDev& M, const uint8_t* codes, const float* centroids, int bits,
+                              long long H, float* fhat, hipStream_t st);
 hipError_t launch_quantize(const float* z, long long n, int latent, const float* centroids,
                            int bits, uint8_t* codes, hipStream_t st);
 size_t codebook_ws_bytes(long long n, int latent, long long every);

@@ -634,6 +634,7 @@ __global__ __launch_bounds__(256) void k_quantize(const float* z, long long n, i
 hipError_t launch_encode(const ModelDev& M, const void* hist, int dtype, long long H, long long hs,
                          long long rs, int n_par, float* z, hipStream_t st) {
   if (H <= 0) return hipSuccess;
+  if (M.arch == HCZ_ARCH_CONV) return launch_conv_encode(M, hist, dtype, H, hs, rs, z, st);
   const bool contig = rs == n_par;
   dim3 grid((unsigned)((H + kTile - 1) / kTile)), block(256);
   if (M.bf16) {
@@ -658,6 +659,7 @@ hipError_t launch_encode(const ModelDev& M, const void* hist, int dtype, long lo
 hipError_t launch_decode(const ModelDev& M, const uint8_t* codes, const float* centroids, int bits,
                          long long H, float* fhat, hipStream_t st) {
   if (H <= 0) return hipSuccess;
+  if (M.arch == HCZ_ARCH_CONV) return launch_conv_decode(M, codes, centroids, bits, H, fhat, st);
   dim3 grid((unsigned)((H + kTile - 1) / kTile)), block(256);
   if (M.bf16) hipLaunchKernelGGL(k_decode_b, grid, block, 0, st, M, codes, centroids, 1 << bits, H, fhat);
   else hipLaunchKernelGGL(k_decode, grid, block, 0, st, M, codes, centroids, 1 << bits, H, fhat);

@@ -16,7 +16,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhcz.so")
 
 F32, F64 = 0, 1
-ARCH_DENSE = 1
+ARCH_DENSE, ARCH_CONV = 1, 2
+CONV_KEYS = ("c1w", "c1b", "c2w", "c2b", "fw", "fb", "dw", "db", "t1w", "t1b", "t2w", "t2b")
 COMPUTE_FP32, COMPUTE_BF16 = 0, 1
 TAU_REL_L2, TAU_NRMSE = 0, 1
 FALLBACK_BACKTRACK, FALLBACK_PAPER = 0, 1
@@ -245,16 +246,26 @@ def pack_dense_weights(W: dict) -> np.ndarray:
 class Model:
     """A dense autoencoder copied to the device for one plan."""
 
-    def __init__(self, plan: Plan, W: dict, mu: np.ndarray, sd: np.ndarray, compute: str = "fp32"):
+    def __init__(self, plan: Plan, W: dict, mu: np.ndarray, sd: np.ndarray, compute: str = "fp32",
+                 arch: str = "dense"):
+        """arch "dense" (W1..b4) or "conv" (the convolutional model of 39 x 39 grids, keys
+        CONV_KEYS, compute "bf16" only)."""
         if compute not in ("fp32", "bf16"):
             raise ValueError(f"compute must be 'fp32' or 'bf16', not {compute!r}")
+        if arch not in ("dense", "conv"):
+            raise ValueError(f"arch must be 'dense' or 'conv', not {arch!r}")
         self.plan = plan
         self.compute = compute
-        blob = pack_dense_weights(W)
+        self.arch = arch
+        if arch == "conv":
+            blob = np.concatenate([np.ascontiguousarray(W[k], np.float32).ravel() for k in CONV_KEYS])
+        else:
+            blob = pack_dense_weights(W)
         mu = np.ascontiguousarray(mu, np.float32)
         sd = np.ascontiguousarray(sd, np.float32)
         fp = C.POINTER(C.c_float)
-        d = ModelDesc(ARCH_DENSE, LATENT, HIDDEN, blob.ctypes.data_as(fp), mu.ctypes.data_as(fp),
+        d = ModelDesc(ARCH_CONV if arch == "conv" else ARCH_DENSE, LATENT, HIDDEN, blob.ctypes.data_as(fp),
+                      mu.ctypes.data_as(fp),
                       sd.ctypes.data_as(fp), COMPUTE_BF16 if compute == "bf16" else COMPUTE_FP32)
         h = C.c_void_p()
         _check(LIB.hcz_model_load(plan.h, C.byref(d), C.byref(h)))

@@ -181,3 +181,18 @@ def test_per_histogram_tau_is_the_scalar_form_per_subdomain():
         assert np.array_equal(comp["flags"][lo:hi], one["flags"])
         assert np.array_equal(comp["lam"][lo:hi], one["lam"])
         assert comp["stream"][comp["offsets"][lo]:comp["offsets"][hi]] == one["stream"]
+
+
+def test_conv_model_roundtrip():
+    """The convolutional model (BF16 form) in the pipeline: bound, QoIs and exact
+    decompression as with the dense model."""
+    g = grid.make_grid()
+    F = synth.histograms(10, seed=29, dtype=np.float32)
+    mu, sd = oracle.ae.norm_stats(F.astype(np.float64))
+    model = dict(arch="conv", W=synth.conv_ae_weights(), mu=mu, sd=sd)
+    comp = pipeline.compress(F, g, model, None, pipeline.Params(tau=1e-3), fit_codebook=True,
+                             sample_every=1, bits=3)
+    assert comp["codes"].shape == (10, 16)
+    out = pipeline.decompress(comp, g, model, comp["codebook"], 10, np.float32)
+    check_bound_and_qoi(F, out, comp, g, 1e-3)
+    assert np.array_equal(out, comp["fc"])
