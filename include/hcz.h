@@ -58,7 +58,7 @@ enum { HCZ_COMPUTE_FP32 = 0, HCZ_COMPUTE_BF16 = 1 };      /* autoencoder arithme
 enum { HCZ_TAU_REL_L2 = 0, HCZ_TAU_NRMSE = 1 };          /* tau_h = tau ||f||, tau sqrt(N)(max-min) */
 enum { HCZ_FALLBACK_BACKTRACK = 0, HCZ_FALLBACK_PAPER = 1 };
 enum { HCZ_FLAG_CODED = 1, HCZ_FLAG_ROUND2 = 2, HCZ_FLAG_RAW = 4, HCZ_FLAG_WARM_REJECTED = 8,
-       HCZ_FLAG_NOCLIP = 16 };
+       HCZ_FLAG_NOCLIP = 16, HCZ_FLAG_KL = 32 };
 enum { HCZ_WARM_COLD = 0, HCZ_WARM_MLP = 1 };
 
 typedef struct hcz_ctx hcz_ctx;
@@ -103,7 +103,10 @@ typedef struct {
  *   multiply-add chains (conv1 over the in-range taps in row-major order, the dense layer
  *   over d = 0..15); their ReLU outputs and the weights of conv2 and of the first
  *   transposed conv are rounded to nearest-even bfloat16 for the matrix cores (FP32
- *   accumulation); the rest is FP32.  Other grids or compute forms: HCZ_EUNSUPPORTED. */
+ *   accumulation); the rest is FP32.  Other grids or compute forms: HCZ_EUNSUPPORTED.
+ *   The model owns a 419 MB device scratch buffer through which encode and decode pass
+ *   their intermediate layer in chunks of 16,384 histograms: calls that use one
+ *   convolutional model must not overlap (calls ordered on one stream are fine). */
 typedef struct {
   int32_t arch;
   int32_t latent, hidden;
@@ -140,6 +143,13 @@ typedef struct {
  *                  onto {A x = b}, f_c = f~ - A^T lam with (A A^T) lam = A f~ - b (one
  *                  Newton step; flag HCZ_FLAG_NOCLIP); 0: the Stage-5 projection onto
  *                  {A x = b, x >= 0}.
+ * kl               1: the KL (I-divergence) reading of Stage 5 first: f_c = argmin
+ *                  sum x log(x / ft) - x + ft subject to A x = b over the cells with ft > 0,
+ *                  i.e. f_c = max(ft, 0) exp(-A^T lam), solved by the same Newton rounds on
+ *                  its dual.  It is not non-expansive, so it is kept (flag HCZ_FLAG_KL) only
+ *                  where ||f - f_c|| <= (1 - 2^-20) tau_h; elsewhere the histogram gets the
+ *                  L2 projection.  Runs on the workgroup-per-histogram kernel for every grid.
+ *                  Not combined with no_positivity or a warm start (HCZ_EINVAL).
  * tau_hist         NULL: every histogram uses tau.  Otherwise (device, FP64, [H]) histogram
  *                  h uses tau_hist[h] in place of tau (tau is then not read): per-subdomain
  *                  bounds in one call, see hcz_segment_tau.  A negative, infinite or NaN
@@ -158,6 +168,7 @@ typedef struct {
   int32_t lambda_fp32;
   int32_t no_positivity;
   const double* tau_hist;
+  int32_t kl;
 } hcz_params;
 
 /* Run statistics, written to device memory by compress and read with hcz_stats_read. */

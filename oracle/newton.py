@@ -125,6 +125,70 @@ def project_linear(ft: np.ndarray, b: np.ndarray, g: Grid):
     return dict(lam=lam, x=(ftv - A.T @ lam).reshape(np.shape(ft)), status=0, iters=1, warm_rejected=False)
 
 
+# ---- KL / I-divergence reading of the correction -------------------------------------------
+#
+#     f_c = argmin_x  sum_j x_j log(x_j / ft_j) - x_j + ft_j   subject to  A x = b
+#
+# over the cells where ft_j > 0 (the others stay 0).  Stationarity gives the multiplicative
+# form x(lam) = ft+ exp(-A^T lam), ft+ = max(ft, 0).  The dual
+# D(lam) = -sum_j x_j(lam) - lam^T b is concave with gradient g = A x(lam) - b and Hessian
+# -A diag(x) A^T, so the Newton step is lam <- lam + s H^-1 g with H = A diag(x) A^T; the
+# stopping rule, rounds and Armijo backtracking (on D) are those of the L2 reading.
+
+def x_kl(ft: np.ndarray, A: np.ndarray, lam: np.ndarray) -> np.ndarray:
+    return np.maximum(ft, 0.0) * np.exp(-(A.T @ lam))
+
+
+def dual_kl(ft, A, b, lam) -> float:
+    return -float(np.sum(x_kl(ft, A, lam))) - float(np.dot(lam, b))
+
+
+def newton_round_kl(ft, A, b, lam, s, max_iter, mode):
+    """As newton_round, for the KL reading.  Returns (lam, converged, updates)."""
+    lam = np.array(lam, np.float64)
+    for it in range(max_iter + 1):
+        x = x_kl(ft, A, lam)
+        g = A @ x - b
+        if converged(g, A, x):
+            return lam, True, it
+        if it == max_iter:
+            return lam, False, it
+        d = cholesky_solve((A * x) @ A.T, g)
+        if d is None:
+            return lam, False, it
+        if mode == "fixed":
+            lam = lam + s * d
+        else:
+            t0 = dual_kl(ft, A, b, lam)
+            gd = float(np.dot(g, d))
+            step = 1.0
+            for _ in range(ARMIJO_HALVINGS):
+                cand = lam + step * d
+                if dual_kl(ft, A, b, cand) >= t0 + ARMIJO_C * step * gd:
+                    break
+                step *= 0.5
+            else:
+                return lam, False, it
+            lam = cand
+    return lam, False, max_iter
+
+
+def project_kl(ft: np.ndarray, b: np.ndarray, g: Grid, s: float = 1.0, max_iter: int = 50,
+               max_iter2: int = 400, fallback: str = "backtrack"):
+    """KL reading: dict(lam, x, status, iters, warm_rejected) as project()."""
+    A = g.A()
+    ftv = np.asarray(ft, np.float64).reshape(-1)
+    lam1, ok, it1 = newton_round_kl(ftv, A, b, np.zeros(4), s, max_iter, "fixed")
+    if ok:
+        return dict(lam=lam1, x=x_kl(ftv, A, lam1).reshape(np.shape(ft)), status=0, iters=it1, warm_rejected=False)
+    mode = "fixed" if fallback == "paper" else "armijo"
+    lam2, ok2, it2 = newton_round_kl(ftv, A, b, lam1, 0.01 if fallback == "paper" else 1.0, max_iter2, mode)
+    if ok2:
+        return dict(lam=lam2, x=x_kl(ftv, A, lam2).reshape(np.shape(ft)), status=1, iters=it1 + it2,
+                    warm_rejected=False)
+    return dict(lam=np.zeros(4), x=None, status=2, iters=it1 + it2, warm_rejected=False)
+
+
 def project(ft: np.ndarray, b: np.ndarray, g: Grid, s: float = 1.0, max_iter: int = 50,
             max_iter2: int = 400, fallback: str = "backtrack", lam0=None, positivity: bool = True):
     """Project one reconstruction ft (n_perp, n_par) onto {A x = b, x >= 0}.
@@ -164,11 +228,13 @@ def _project_from(ftv, A, b, shape, lam, s, max_iter, max_iter2, fallback):
     return dict(lam=np.zeros(4), x=None, status=2, iters=it1 + it2)
 
 
-def apply(ft: np.ndarray, lam: np.ndarray, g: Grid, positivity: bool = True) -> np.ndarray:
+def apply(ft: np.ndarray, lam: np.ndarray, g: Grid, positivity: bool = True, kl: bool = False) -> np.ndarray:
     """Decompression-side correction f_c = max(0, ft - A^T lam) (or ft - A^T lam without
-    positivity) for one histogram."""
+    positivity, or max(ft, 0) exp(-A^T lam) in the KL reading) for one histogram."""
     ftv = np.asarray(ft, np.float64).reshape(-1)
     lam = np.asarray(lam, np.float64)
+    if kl:
+        return x_kl(ftv, g.A(), lam).reshape(ft.shape)
     if not positivity:
         return (ftv - g.A().T @ lam).reshape(ft.shape)
     return x_of(ftv, g.A(), lam).reshape(ft.shape)

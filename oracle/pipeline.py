@@ -14,7 +14,7 @@ Decompress: fhat from the codes, rhat from the record, ft = fhat + rhat,
 f_c = max(0, ft - A^T lam); verbatim records are returned as stored.
 
 Flags: bit0 coder record, bit1 round-2 Newton used, bit2 verbatim record, bit3 warm
-start rejected, bit4 correction without positivity.  Multipliers can be stored as FP32
+start rejected, bit4 correction without positivity, bit5 KL correction.  Multipliers can be stored as FP32
 (the paper's float multipliers, Section I and Fig. 7).  An optional warm-start network (oracle.mlp) seeds the Newton solve from
 the dequantised latent; the projection keeps cold start as fallback and judge.
 """
@@ -29,7 +29,7 @@ from . import ae, coder, conv, mlp as mlp_net, newton, pq
 from .grid import Grid
 from .moments import moments
 
-FLAG_CODED, FLAG_ROUND2, FLAG_RAW, FLAG_WARM_REJECTED, FLAG_NOCLIP = 1, 2, 4, 8, 16
+FLAG_CODED, FLAG_ROUND2, FLAG_RAW, FLAG_WARM_REJECTED, FLAG_NOCLIP, FLAG_KL = 1, 2, 4, 8, 16, 32
 
 
 @dataclass
@@ -42,6 +42,7 @@ class Params:
     fallback: str = "backtrack"     # or "paper" (s = 0.01)
     lambda_fp32: bool = False       # store the multipliers as FP32
     positivity: bool = True         # False: projection onto {A x = b} only
+    kl: bool = False                # True: the KL / I-divergence correction (multiplicative)
 
 
 def tau_of(H: int, p: Params) -> np.ndarray:
@@ -142,8 +143,15 @@ def compress(F: np.ndarray, g: Grid, model: dict | None, C: np.ndarray | None, p
     for h in range(H):
         if raw[h]:
             continue
-        res = newton.project(ft[h], b[h], g, p.newton_s, p.newton_max_iter, p.newton_max_iter2,
-                             p.fallback, lam0=None if lam0 is None else lam0[h], positivity=p.positivity)
+        kl = False
+        if p.kl:
+            # the KL correction is not non-expansive: it is kept only where it keeps the bound,
+            # elsewhere the histogram gets the L2 projection
+            res = newton.project_kl(ft[h], b[h], g, p.newton_s, p.newton_max_iter, p.newton_max_iter2, p.fallback)
+            kl = res["status"] < 2 and coder.sumsq(Fz[h:h + 1] - res["x"][None])[0] <= thr[h] * thr[h]
+        if not kl:
+            res = newton.project(ft[h], b[h], g, p.newton_s, p.newton_max_iter, p.newton_max_iter2,
+                                 p.fallback, lam0=None if lam0 is None else lam0[h], positivity=p.positivity)
         iters[h] = res["iters"]
         if res.get("warm_rejected"):
             flags[h] |= FLAG_WARM_REJECTED
@@ -156,6 +164,8 @@ def compress(F: np.ndarray, g: Grid, model: dict | None, C: np.ndarray | None, p
         fc[h] = res["x"]
         if not p.positivity:
             flags[h] |= FLAG_NOCLIP
+        if kl:
+            flags[h] |= FLAG_KL
     records = []
     for h in range(H):
         if raw[h]:
@@ -200,5 +210,5 @@ def decompress(comp: dict, g: Grid, model: dict | None, C: np.ndarray | None, H:
             qh, Delta, _ = coder.unpack(rec, lay)
             ft = fhat[h] + coder.reconstruct(qh[None], np.array([Delta]), lay)[0]
         out[h] = newton.apply(ft, np.asarray(comp["lam"][h], np.float64), g,
-                              positivity=not comp["flags"][h] & FLAG_NOCLIP)
+                              positivity=not comp["flags"][h] & FLAG_NOCLIP, kl=bool(comp["flags"][h] & FLAG_KL))
     return out

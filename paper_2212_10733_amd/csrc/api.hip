@@ -396,6 +396,9 @@ hcz_status check_params(const hcz_params* p) {
   if (p->warm_start == HCZ_WARM_MLP && !p->mlp) return fail(HCZ_EINVAL, "warm_start needs an mlp");
   if (p->lambda_fp32 != 0 && p->lambda_fp32 != 1) return fail(HCZ_EINVAL, "lambda_fp32 must be 0 or 1");
   if (p->no_positivity != 0 && p->no_positivity != 1) return fail(HCZ_EINVAL, "no_positivity must be 0 or 1");
+  if (p->kl != 0 && p->kl != 1) return fail(HCZ_EINVAL, "kl must be 0 or 1");
+  if (p->kl && (p->no_positivity || p->warm_start != HCZ_WARM_COLD))
+    return fail(HCZ_EINVAL, "kl is not combined with no_positivity or a warm start");
   return HCZ_OK;
 }
 
@@ -630,6 +633,18 @@ static hcz_status conv_model_load(hcz_plan* plan, const hcz_model_desc* d, hcz_m
     delete m;
     return s;
   }
+  {
+    void* p = nullptr;
+    const size_t bytes = (size_t)kConvChunk * 6400 * sizeof(float);
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+      free_all(m->allocs);
+      delete m;
+      return fail(HCZ_ENOMEM, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+    }
+    m->allocs.push_back(p);
+    M.scratch = (float*)p;
+  }
   *out = m;
   return HCZ_OK;
 }
@@ -840,6 +855,7 @@ static hcz_status residual_impl(const hcz_plan* plan, const hcz_params* p, const
   a.lambda = out->lambda;
   a.lambda_fp32 = p->lambda_fp32;
   a.no_positivity = p->no_positivity;
+  a.kl = p->kl;
   a.flags = out->flags;
   a.sizes = (uint64_t*)(ws + L.sizes);
   a.slots = ws + L.slots;

@@ -94,7 +94,9 @@ struct ModelDev {
   const float* t1b;                // [32]
   const float* t2w;                // [32][9]
   const float* t2b;                // [1]
+  float* scratch;                  // [kConvChunk][6400] FP32, owned by the model
 };
+constexpr int kConvChunk = 16384;  // histograms per pass of the convolutional model
 
 struct ResidualArgs {
   const void* hist;
@@ -108,6 +110,7 @@ struct ResidualArgs {
   void* lambda;                // [H][4] FP64, or FP32 when lambda_fp32
   int lambda_fp32;
   int no_positivity;           // 1: projection onto {A x = b} only (flag HCZ_FLAG_NOCLIP)
+  int kl;                      // 1: KL correction where it keeps the bound (flag HCZ_FLAG_KL)
   uint8_t* flags;              // [H]
   uint64_t* sizes;             // [H] record bytes
   uint8_t* slots;              // [H][slot_stride] staging

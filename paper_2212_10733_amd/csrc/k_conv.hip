@@ -16,6 +16,8 @@
 // parity class: an output cell of parity (cy, cx) receives 1, 2 or 4 taps, K = taps x 64;
 // ReLU(acc + b) in FP32 to LDS [y][x][channel]; the transposed conv2 (32 -> 1) on the
 // vector ALUs; fhat = sigma y + mu.
+#include <algorithm>
+
 #include "hcz_internal.h"
 
 namespace hcz {
@@ -27,25 +29,40 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 constexpr int kCP1 = 40;   // LDS pitch (bfloat16) of a conv1 output cell (32 channels)
 constexpr int kCPD = 72;   // LDS pitch (bfloat16) of a decoder hidden cell (64 channels)
 constexpr int kCP3 = 33;   // LDS pitch (floats) of a transposed-conv1 output cell (32 channels)
+constexpr int kConvGrid = 1024;  // workgroups of the looping decoder kernel
 
 __device__ __forceinline__ f32x16 mfma_bf16c(bf16x8 a, bf16x8 b, f32x16 c) {
   return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
 }
 
+// One workgroup per histogram (an LDS footprint of 41 KB lets three share a CU).
 template <typename TIn>
 __global__ __launch_bounds__(256, 2) void k_conv_enc(ModelDev M, const TIn* hist, long long hs, long long rs,
-                                                     float* z) {
+                                                     float* h2out) {
   __shared__ float xs[39 * 39];
   __shared__ __attribute__((aligned(16))) __bf16 h1p[21 * 21 * kCP1];   // later: h2 (6400 floats)
   float* h2s = (float*)h1p;
   const int t = threadIdx.x, w = t >> 6, l = t & 63;
+  const int li = l & 31, kh = l >> 5;
+  const __bf16* W2 = (const __bf16*)M.c2w;
   const long long h = blockIdx.x;
   const TIn* f = hist + h * hs;
-  for (int e = t; e < 1521; e += 256) {
-    const int j = e / 39, i = e - 39 * j;
-    float fv = (float)f[j * rs + i];
-    if (!isfinite(fv)) fv = 0.0f;
-    xs[e] = (fv - M.mu[e]) * M.rsd[e];
+  {
+    // all loads first (6 per thread), then the stores: one memory round trip
+    float fv[6], mv[6], rv[6];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      const int e = min(t + 256 * q, 1520);
+      const int j = e / 39, i = e - 39 * j;
+      fv[q] = (float)f[j * rs + i];
+      mv[q] = M.mu[e];
+      rv[q] = M.rsd[e];
+    }
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      const int e = t + 256 * q;
+      if (e < 1521) xs[e] = ((isfinite(fv[q]) ? fv[q] : 0.0f) - mv[q]) * rv[q];
+    }
   }
   // zero border of the conv1 output (row 0 and column 0 of the padded layout)
   for (int q = t; q < 41 * 32; q += 256) {
@@ -80,98 +97,177 @@ __global__ __launch_bounds__(256, 2) void k_conv_enc(ModelDev M, const TIn* hist
   }
   __syncthreads();
   // conv2 on matrix cores: wave w owns output positions 32 w .. 32 w + 31
-  const int li = l & 31, kh = l >> 5;
   const int P = min(32 * w + li, 99);
   const int oy2 = P / 10, ox2 = P - 10 * oy2;
-  const __bf16* W2 = (const __bf16*)M.c2w;
   f32x16 acc[2];
 #pragma unroll
-  for (int n = 0; n < 2; ++n)
+  for (int nt = 0; nt < 2; ++nt)
 #pragma unroll
-    for (int r = 0; r < 16; ++r) acc[n][r] = 0.0f;
-#pragma unroll 3
+    for (int r = 0; r < 16; ++r) acc[nt][r] = 0.0f;
+#pragma unroll
   for (int tap = 0; tap < 9; ++tap) {
     const int ky = tap / 3, kx = tap - 3 * ky;
     const __bf16* arow = &h1p[((2 * oy2 + ky) * 21 + (2 * ox2 + kx)) * kCP1];
 #pragma unroll
     for (int half = 0; half < 2; ++half) {
-      const int ci0 = 16 * half + 8 * kh;
-      const bf16x8 a = *(const bf16x8*)(arow + ci0);
+      const bf16x8 a = *(const bf16x8*)(arow + 16 * half + 8 * kh);
 #pragma unroll
-      for (int n = 0; n < 2; ++n) {
-        const bf16x8 b = *(const bf16x8*)(W2 + ((long long)(tap * 64 + 32 * n + li)) * 32 + ci0);
-        acc[n] = mfma_bf16c(a, b, acc[n]);
-      }
+      for (int nt = 0; nt < 2; ++nt)
+        acc[nt] = mfma_bf16c(a, *(const bf16x8*)(W2 + ((long long)(tap * 64 + 32 * nt + li)) * 32 + 16 * half + 8 * kh),
+                             acc[nt]);
     }
   }
   __syncthreads();          // every wave is done reading h1p before h2 overwrites it
 #pragma unroll
-  for (int n = 0; n < 2; ++n) {
-    const int co = 32 * n + li;
+  for (int nt = 0; nt < 2; ++nt) {
+    const int co = 32 * nt + li;
     const float bias = M.c2b[co];
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int row = 32 * w + 8 * (r >> 2) + 4 * kh + (r & 3);
-      if (row < 100) h2s[co * 100 + row] = fmaxf(acc[n][r] + bias, 0.0f);
+      if (row < 100) h2s[co * 100 + row] = fmaxf(acc[nt][r] + bias, 0.0f);
     }
   }
   __syncthreads();
-  // dense 6400 -> 16: 16 lanes per output
-  {
-    const int o = t >> 4, sl = t & 15;
-    const float* fw = M.fw + (long long)o * 6400;
-    float s = 0.0f;
-    for (int k = sl; k < 6400; k += 16) s = fmaf(fw[k], h2s[k], s);
+  float* dst = h2out + h * 6400;
+  for (int k = t; k < 6400; k += 256) dst[k] = h2s[k];
+}
+
+// z[h][o] = fb[o] + sum_k h2[h][k] fw[o][k]: one wave per 32 histograms on
+// v_mfma_f32_32x32x2f32 (columns 16..31 are zero); lane half kq holds k = 8c + 4kq .. + 3
+// of both operands, one 16-byte load each.
+__global__ __launch_bounds__(256) void k_conv_fc(const float* h2, long long n, const float* fw, const float* fb,
+                                                 float* z) {
+  const int t = threadIdx.x, w = t >> 6, l = t & 63, li = l & 31, kq = l >> 5;
+  const long long r0 = ((long long)blockIdx.x * 4 + w) * 32;
+  if (r0 >= n) return;
+  const long long row = min(r0 + li, n - 1);
+  const f32x4* a = (const f32x4*)(h2 + row * 6400 + 4 * kq);
+  const f32x4* b = (const f32x4*)(fw + (long long)min(li, 15) * 6400 + 4 * kq);
+  const bool bon = li < 16;
+  f32x16 acc;
 #pragma unroll
-    for (int m = 8; m >= 1; m >>= 1) s += __shfl_xor(s, m, 16);
-    if (sl == 0) z[h * kLatent + o] = s + M.fb[o];
+  for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
+  f32x4 an = a[0], bn = b[0];
+  for (int c = 0; c < 800; ++c) {
+    const f32x4 av = an, bv = bn;
+    if (c + 1 < 800) {
+      an = a[2 * (c + 1)];
+      bn = b[2 * (c + 1)];
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av[s], bon ? bv[s] : 0.0f, acc, 0, 0, 0);
+  }
+  if (li < 16) {
+    const float bias = fb[li];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const long long hr = r0 + 8 * (r >> 2) + 4 * kq + (r & 3);
+      if (hr < n) z[hr * kLatent + li] = acc[r] + bias;
+    }
   }
 }
 
-__global__ __launch_bounds__(256, 2) void k_conv_dec(ModelDev M, const uint8_t* codes, const float* centroids,
-                                                     int kcb, float* fhat) {
+// Decoder hidden layer: hd[h][k] = bf16(relu(db[k] + sum_d zhat[h][d] dw[k][d])) as the
+// FP32 chain over d = 0..15.  A workgroup takes 256 values of k (one per thread, its dw
+// row in registers) for 64 histograms.
+__global__ __launch_bounds__(256) void k_conv_hidden(ModelDev M, const uint8_t* codes, const float* centroids,
+                                                     int kcb, long long n, __bf16* hd) {
+  __shared__ float zs[64 * kLatent];
+  const int t = threadIdx.x;
+  const long long h0 = (long long)blockIdx.y * 64;
+  for (int q = t; q < 64 * kLatent; q += 256) {
+    const long long hh = h0 + q / kLatent;
+    const int d = q % kLatent;
+    zs[q] = hh < n ? centroids[d * kcb + min((int)codes[hh * kLatent + d], kcb - 1)] : 0.0f;
+  }
+  __syncthreads();
+  const int k = blockIdx.x * 256 + t;
+  if (k >= 6400) return;
+  float wv[kLatent];
+  const f32x4* dw = (const f32x4*)(M.dw + (long long)k * kLatent);
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const f32x4 q4 = dw[u];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) wv[4 * u + e] = q4[e];
+  }
+  const float b = M.db[k];
+  const int m = (int)min((long long)64, n - h0);
+  for (int r = 0; r < m; ++r) {
+    float s = b;
+#pragma unroll
+    for (int d = 0; d < kLatent; ++d) s = fmaf(zs[r * kLatent + d], wv[d], s);
+    hd[(h0 + r) * 6400 + k] = (__bf16)fmaxf(s, 0.0f);
+  }
+}
+
+// A workgroup loops over histograms like the encoder.  The transposed conv1 weights of a
+// parity class (up to 4 taps x 4 channel steps per lane) are loaded together before the
+// class's matrix-core steps.
+__global__ __launch_bounds__(256, 2) void k_conv_dec(ModelDev M, const __bf16* hd, long long n, float* fhat) {
   __shared__ __attribute__((aligned(16))) __bf16 hdp[11 * 11 * kCPD];
   __shared__ __attribute__((aligned(16))) float h3s[20 * 20 * kCP3];
-  __shared__ float zs[kLatent];
   __shared__ float t2s[32 * 9];
   const int t = threadIdx.x, w = t >> 6, l = t & 63;
-  const long long h = blockIdx.x;
-  if (t < kLatent) zs[t] = centroids[t * kcb + min((int)codes[h * kLatent + t], kcb - 1)];
-  for (int q = t; q < 32 * 9; q += 256) t2s[q] = M.t2w[q];
-  // zero row 10 and column 10 of the padded hidden layout
+  const int li = l & 31, kh = l >> 5;
+  {
+    const float a = M.t2w[t], b = t < 32 ? M.t2w[256 + t] : 0.0f;
+    t2s[t] = a;
+    if (t < 32) t2s[256 + t] = b;
+  }
+  // zero row 10 and column 10 of the padded hidden layout (never written afterwards)
   for (int q = t; q < 21 * 64; q += 256) {
     const int cell = q >> 6, c = q & 63;
     const int y = cell < 11 ? 10 : cell - 11, x = cell < 11 ? cell : 10;
     hdp[(y * 11 + x) * kCPD + c] = (__bf16)0.0f;
   }
-  __syncthreads();
-  // dense 16 -> 6400 as the FP32 chain over d = 0..15, ReLU, bfloat16
-  for (int k = t; k < 6400; k += 256) {
-    const f32x4* dw = (const f32x4*)(M.dw + (long long)k * kLatent);
-    float s = M.db[k];
+  const __bf16* T1 = (const __bf16*)M.t1w;
+  const float bias1 = M.t1b[li];
+  const float b2 = M.t2b[0];
+  for (long long h = blockIdx.x; h < n; h += gridDim.x) {
+  __syncthreads();          // the previous histogram is done with hdp and h3s
+  // the hidden layer (k = channel * 100 + y * 10 + x) into [y][x][channel]: 16-byte
+  // loads, all issued before the scatter into LDS
+  {
+    const bf16x8* src = (const bf16x8*)(hd + h * 6400);
+    bf16x8 v[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const f32x4 wv = dw[u];
+    for (int r = 0; r < 4; ++r) v[r] = src[min(t + 256 * r, 799)];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) s = fmaf(zs[4 * u + e], wv[e], s);
+    for (int r = 0; r < 4; ++r) {
+      const int m = t + 256 * r;
+      if (m >= 800) continue;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int k = 8 * m + e;
+        const int c = k / 100, p = k - 100 * c, y = p / 10, x = p - 10 * y;
+        hdp[(y * 11 + x) * kCPD + c] = v[r][e];
+      }
     }
-    const int c = k / 100, p = k - 100 * c, y = p / 10, x = p - 10 * y;
-    hdp[(y * 11 + x) * kCPD + c] = (__bf16)fmaxf(s, 0.0f);
   }
   __syncthreads();
   // transposed conv1 on matrix cores, one parity class (cy, cx) at a time; wave w owns
   // the class's positions 32 w .. 32 w + 31 (of 100)
-  const int li = l & 31, kh = l >> 5;
   const int q = min(32 * w + li, 99);
   const int py = q / 10, px = q - 10 * py;
-  const __bf16* T1 = (const __bf16*)M.t1w;
-  const float bias1 = M.t1b[li];
 #pragma unroll
   for (int cls = 0; cls < 4; ++cls) {
     const int cy = cls >> 1, cx = cls & 1;
     f32x16 acc;
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
+    bf16x8 bc[4][4];
+#pragma unroll
+    for (int ty = 0; ty < 1 + cy; ++ty)
+#pragma unroll
+      for (int tx = 0; tx < 1 + cx; ++tx) {
+        const int ky = cy ? (ty == 0 ? 0 : 2) : 1, kx = cx ? (tx == 0 ? 0 : 2) : 1;
+#pragma unroll
+        for (int c4 = 0; c4 < 4; ++c4)
+          bc[2 * ty + tx][c4] = *(const bf16x8*)(T1 + ((long long)((ky * 3 + kx) * 32 + li)) * 64 + 16 * c4 + 8 * kh);
+      }
     // taps: even output -> k = 1 from input p; odd output -> k = 0 from p + 1, k = 2 from p
 #pragma unroll
     for (int ty = 0; ty < 1 + cy; ++ty) {
@@ -182,12 +278,9 @@ __global__ __launch_bounds__(256, 2) void k_conv_dec(ModelDev M, const uint8_t* 
         const int kx = cx ? (tx == 0 ? 0 : 2) : 1;
         const int ix = cx ? (tx == 0 ? px + 1 : px) : px;
         const __bf16* arow = &hdp[(iy * 11 + ix) * kCPD];
-        const __bf16* brow = T1 + ((long long)((ky * 3 + kx) * 32 + li)) * 64;
 #pragma unroll
-        for (int c4 = 0; c4 < 4; ++c4) {
-          const int ci0 = 16 * c4 + 8 * kh;
-          acc = mfma_bf16c(*(const bf16x8*)(arow + ci0), *(const bf16x8*)(brow + ci0), acc);
-        }
+        for (int c4 = 0; c4 < 4; ++c4)
+          acc = mfma_bf16c(*(const bf16x8*)(arow + 16 * c4 + 8 * kh), bc[2 * ty + tx][c4], acc);
       }
     }
     // D layout: lane holds output channel li for 16 of the wave's 32 positions
@@ -204,15 +297,14 @@ __global__ __launch_bounds__(256, 2) void k_conv_dec(ModelDev M, const uint8_t* 
   __syncthreads();
   // transposed conv2 (32 -> 1) on the vector ALUs: output (oy, ox) takes input
   // (iy, ix) = ((oy + 1 - ky) / 2, (ox + 1 - kx) / 2) where that is whole and in range
-  const float b2 = M.t2b[0];
   for (int o = t; o < 1521; o += 256) {
     const int oy = o / 39, ox = o - 39 * oy;
     float s = 0.0f;
-#pragma unroll
+#pragma unroll 1
     for (int ky = 0; ky < 3; ++ky) {
       const int ny = oy + 1 - ky;
       if (ny < 0 || (ny & 1) || (ny >> 1) >= 20) continue;
-#pragma unroll
+#pragma unroll 1
       for (int kx = 0; kx < 3; ++kx) {
         const int nx = ox + 1 - kx;
         if (nx < 0 || (nx & 1) || (nx >> 1) >= 20) continue;
@@ -223,23 +315,42 @@ __global__ __launch_bounds__(256, 2) void k_conv_dec(ModelDev M, const uint8_t* 
     }
     fhat[h * 1521 + o] = fmaf(M.sd[o], s + b2, M.mu[o]);
   }
+  }
 }
 
+// Both directions run in chunks of at most kConvChunk histograms through the model's
+// scratch buffer (conv2 output, FP32; the decoder's hidden layer, bfloat16).
 hipError_t launch_conv_encode(const ModelDev& M, const void* hist, int dtype, long long H, long long hs,
                               long long rs, float* z, hipStream_t st) {
-  if (H <= 0) return hipSuccess;
-  if (dtype == HCZ_F32)
-    hipLaunchKernelGGL(k_conv_enc<float>, dim3((unsigned)H), dim3(256), 0, st, M, (const float*)hist, hs, rs, z);
-  else
-    hipLaunchKernelGGL(k_conv_enc<double>, dim3((unsigned)H), dim3(256), 0, st, M, (const double*)hist, hs, rs, z);
-  return hipGetLastError();
+  for (long long c0 = 0; c0 < H; c0 += kConvChunk) {
+    const long long n = std::min((long long)kConvChunk, H - c0);
+    if (dtype == HCZ_F32)
+      hipLaunchKernelGGL(k_conv_enc<float>, dim3((unsigned)n), dim3(256), 0, st, M, (const float*)hist + c0 * hs,
+                         hs, rs, M.scratch);
+    else
+      hipLaunchKernelGGL(k_conv_enc<double>, dim3((unsigned)n), dim3(256), 0, st, M, (const double*)hist + c0 * hs,
+                         hs, rs, M.scratch);
+    hipLaunchKernelGGL(k_conv_fc, dim3((unsigned)((n + 127) / 128)), dim3(256), 0, st, (const float*)M.scratch, n,
+                       M.fw, M.fb, z + c0 * kLatent);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_conv_decode(const ModelDev& M, const uint8_t* codes, const float* centroids, int bits,
                               long long H, float* fhat, hipStream_t st) {
-  if (H <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_conv_dec, dim3((unsigned)H), dim3(256), 0, st, M, codes, centroids, 1 << bits, fhat);
-  return hipGetLastError();
+  __bf16* hd = (__bf16*)M.scratch;
+  for (long long c0 = 0; c0 < H; c0 += kConvChunk) {
+    const long long n = std::min((long long)kConvChunk, H - c0);
+    hipLaunchKernelGGL(k_conv_hidden, dim3(25, (unsigned)((n + 63) / 64)), dim3(256), 0, st, M,
+                       codes + c0 * kLatent, centroids, 1 << bits, n, hd);
+    hipLaunchKernelGGL(k_conv_dec, dim3((unsigned)std::min(n, (long long)kConvGrid)), dim3(256), 0, st, M,
+                       (const __bf16*)hd, n, fhat + c0 * 1521);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 }  // namespace hcz

@@ -60,9 +60,10 @@ __device__ double recompose_err(const GridDev& G, double* buf, double* red, cons
 // then hold sum A_k |x| for k = 0, 2, 3 and v[4] sum |A_1| |x|, the stopping rule's scales.
 constexpr int kNv = 19;
 // ft: the reconstruction f^ + r^ in LDS, natural order; thread t takes cells t, t + NT, ...
+// kl: the KL reading, x = max(ft, 0) exp(-A^T lam), Hessian weights x, v[15] = sum_j x_j.
 template <int NT>
 __device__ void newton_pass(const GridDev& G, const double* ft, const double (&lam)[4], double (&v)[kNv],
-                            double* red, bool pos) {
+                            double* red, bool pos, bool kl = false) {
 #pragma unroll
   for (int k = 0; k < kNv; ++k) v[k] = 0.0;
   int i = (int)threadIdx.x % G.n_par, j = (int)threadIdx.x / G.n_par;
@@ -73,8 +74,13 @@ __device__ void newton_pass(const GridDev& G, const double* ft, const double (&l
     i += di;
     j += dj;
     if (i >= G.n_par) { i -= G.n_par; ++j; }
-    const double y = fte - correction(A, lam);
-    const double x = pos ? fmax(0.0, y) : y;
+    double x;
+    if (kl) {
+      x = fte > 0.0 ? fte * exp(-correction(A, lam)) : 0.0;
+    } else {
+      const double y = fte - correction(A, lam);
+      x = pos ? fmax(0.0, y) : y;
+    }
     const double xa = fabs(x);
     v[0] = fma(A.a0, x, v[0]);
     v[1] = fma(A.a1, x, v[1]);
@@ -84,7 +90,19 @@ __device__ void newton_pass(const GridDev& G, const double* ft, const double (&l
     v[16] = fma(A.a0, xa, v[16]);
     v[17] = fma(A.a2, xa, v[17]);
     v[18] = fma(A.a3, xa, v[18]);
-    if (!pos || x > 0.0) {
+    if (kl) {
+      const double p0 = x * A.a0, p1 = x * A.a1, p2 = x * A.a2, p3 = x * A.a3;
+      v[5] = fma(p0, A.a0, v[5]);
+      v[6] = fma(p0, A.a1, v[6]);
+      v[7] = fma(p0, A.a2, v[7]);
+      v[8] = fma(p0, A.a3, v[8]);
+      v[9] = fma(p1, A.a1, v[9]);
+      v[10] = fma(p1, A.a2, v[10]);
+      v[11] = fma(p1, A.a3, v[11]);
+      v[12] = fma(p2, A.a2, v[12]);
+      v[13] = fma(p2, A.a3, v[13]);
+      v[14] = fma(p3, A.a3, v[14]);
+    } else if (!pos || x > 0.0) {
       v[5] = fma(A.a0, A.a0, v[5]);
       v[6] = fma(A.a0, A.a1, v[6]);
       v[7] = fma(A.a0, A.a2, v[7]);
@@ -96,8 +114,12 @@ __device__ void newton_pass(const GridDev& G, const double* ft, const double (&l
       v[13] = fma(A.a2, A.a3, v[13]);
       v[14] = fma(A.a3, A.a3, v[14]);
     }
-    const double dx = x - fte;
-    v[15] = fma(dx, dx, v[15]);
+    if (kl) {
+      v[15] += x;
+    } else {
+      const double dx = x - fte;
+      v[15] = fma(dx, dx, v[15]);
+    }
   }
   block_sum<NT, kNv>(v, red);
 }
@@ -110,9 +132,16 @@ __device__ __forceinline__ void pass_scales(const double (&v)[kNv], bool pos, do
   sc[3] = pos ? v[3] : v[18];
 }
 
-// theta(lam) = 1/2 ||x - ft||^2 + lam^T (A x - b) from a pass's statistics.
+// theta(lam) = 1/2 ||x - ft||^2 + lam^T (A x - b) from a pass's statistics; in the KL
+// reading the dual D(lam) = -sum_j x_j - lam^T b.  Both are concave with gradient A x - b.
 __device__ __forceinline__ double theta_of(const double (&v)[kNv], const double (&lam)[4],
-                                           const double (&b)[4]) {
+                                           const double (&b)[4], bool kl = false) {
+  if (kl) {
+    double t = -v[15];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) t = t - lam[k] * b[k];
+    return t;
+  }
   double t = 0.5 * v[15];
 #pragma unroll
   for (int k = 0; k < 4; ++k) t = t + lam[k] * (v[k] - b[k]);
@@ -167,10 +196,11 @@ __device__ __forceinline__ bool chol_solve4(const double (&v)[kNv], const double
 // Returns true when the stopping rule holds; *upd counts the updates made.
 template <int NT>
 __device__ bool newton_round(const GridDev& G, const double* ft, const double (&b)[4], double (&lam)[4],
-                             double s, int max_iter, bool armijo, double* red, int* upd, bool pos) {
+                             double s, int max_iter, bool armijo, double* red, int* upd, bool pos,
+                             bool kl = false) {
   double v[kNv];
   for (int it = 0; it <= max_iter; ++it) {
-    newton_pass<NT>(G, ft, lam, v, red, pos);
+    newton_pass<NT>(G, ft, lam, v, red, pos, kl);
     double g[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) g[k] = v[k] - b[k];
@@ -188,7 +218,7 @@ __device__ bool newton_round(const GridDev& G, const double* ft, const double (&
 #pragma unroll
       for (int k = 0; k < 4; ++k) lam[k] = lam[k] + s * d[k];
     } else {
-      const double t0 = theta_of(v, lam, b);
+      const double t0 = theta_of(v, lam, b, kl);
       const double gd = ((g[0] * d[0] + g[1] * d[1]) + g[2] * d[2]) + g[3] * d[3];
       double step = 1.0;
       bool ok = false;
@@ -197,8 +227,8 @@ __device__ bool newton_round(const GridDev& G, const double* ft, const double (&
 #pragma unroll
         for (int k = 0; k < 4; ++k) cand[k] = lam[k] + step * d[k];
         double w[kNv];
-        newton_pass<NT>(G, ft, cand, w, red, pos);
-        if (theta_of(w, cand, b) >= t0 + kArmijoC * step * gd) { ok = true; break; }
+        newton_pass<NT>(G, ft, cand, w, red, pos, kl);
+        if (theta_of(w, cand, b, kl) >= t0 + kArmijoC * step * gd) { ok = true; break; }
         step *= 0.5;
       }
       if (!ok) return false;
@@ -454,9 +484,45 @@ __global__ __launch_bounds__(NT) void k_residual(GridDev G, ResidualArgs a) {
         flags |= HCZ_FLAG_WARM_REJECTED;
       }
     }
+    bool kl_kept = false;
+    if (a.kl) {
+      // KL reading first; kept only where it keeps the bound ||f - x|| <= thr (the KL
+      // correction is not non-expansive), otherwise the L2 projection below
+      double lk[4] = {0.0, 0.0, 0.0, 0.0};
+      int k1 = 0, k2 = 0;
+      bool okk = newton_round<NT>(G, ft, b, lk, a.newton_s, a.max_iter, false, red, &k1, true, true);
+      const bool kl_r2 = !okk;
+      if (!okk) {
+        const bool paper = a.fallback == HCZ_FALLBACK_PAPER;
+        okk = newton_round<NT>(G, ft, b, lk, paper ? 0.01 : 1.0, a.max_iter2, !paper, red, &k2, true, true);
+      }
+      total_upd = k1 + k2;
+      if (okk) {
+        double e2[1] = {0.0};
+        int i = t % G.n_par, j = t / G.n_par;
+        const int di = NT % G.n_par, dj = NT / G.n_par;
+        for (int e = t; e < N; e += NT) {
+          const Aphi A = make_aphi(G, e, i, j);
+          const double fte = ft[e];
+          const double x = fte > 0.0 ? fte * exp(-correction(A, lk)) : 0.0;
+          const double d = to_d(f[(long long)j * a.rs + i]) - x;
+          e2[0] = fma(d, d, e2[0]);
+          i += di;
+          j += dj;
+          if (i >= G.n_par) { i -= G.n_par; ++j; }
+        }
+        block_sum<NT, 1>(e2, red);
+        if (e2[0] <= thr2) {
+          kl_kept = true;
+          if (kl_r2) flags |= HCZ_FLAG_ROUND2;
+#pragma unroll
+          for (int k = 0; k < 4; ++k) lam[k] = lk[k];
+        }
+      }
+    }
     int u1 = 0;
-    bool ok = newton_round<NT>(G, ft, b, lam, a.newton_s, a.max_iter, false, red, &u1, !a.no_positivity);
-    total_upd = u1;
+    bool ok = kl_kept || newton_round<NT>(G, ft, b, lam, a.newton_s, a.max_iter, false, red, &u1, !a.no_positivity);
+    if (!kl_kept) total_upd = u1;
     if (!ok) {
       flags |= HCZ_FLAG_ROUND2;
       int u2 = 0;
@@ -466,6 +532,7 @@ __global__ __launch_bounds__(NT) void k_residual(GridDev G, ResidualArgs a) {
       if (!ok) raw = true;
     }
     if (!raw && a.no_positivity) flags |= HCZ_FLAG_NOCLIP;
+    if (!raw && kl_kept) flags |= HCZ_FLAG_KL;
   }
 
   uint64_t size = 0;
@@ -607,6 +674,7 @@ __global__ __launch_bounds__(NT) void k_decompress(GridDev G, DecompressArgs a) 
   for (int k = 0; k < 4; ++k)
     lam[k] = a.lambda_fp32 ? (double)((const float*)a.lambda)[h * 4 + k] : ((const double*)a.lambda)[h * 4 + k];
   const bool clip = (fl & HCZ_FLAG_NOCLIP) == 0;
+  const bool kl = (fl & HCZ_FLAG_KL) != 0;
   int em[NPT], gm[NPT];
   Interp cm[NPT];
   double dq[NPT], ym[NPT];
@@ -659,8 +727,12 @@ __global__ __launch_bounds__(NT) void k_decompress(GridDev G, DecompressArgs a) 
     const float fv = fhp ? fhp[e] : 0.0f;
     const double ft = (double)fv + ym[m];
     const Aphi A = make_aphi(G, e, i, j);
-    const double y = ft - correction(A, lam);
-    ym[m] = clip ? fmax(0.0, y) : y;
+    if (kl) {
+      ym[m] = ft > 0.0 ? ft * exp(-correction(A, lam)) : 0.0;
+    } else {
+      const double y = ft - correction(A, lam);
+      ym[m] = clip ? fmax(0.0, y) : y;
+    }
   }
   __syncthreads();
 #pragma unroll
@@ -675,7 +747,7 @@ static int pick_nt(int N) { return N <= 1536 ? 256 : (N <= 3072 ? 512 : 1024); }
 
 hipError_t launch_residual(const GridDev& G, const ResidualArgs& a, hipStream_t st) {
   if (a.H <= 0) return hipSuccess;
-  if (wave_path(G)) return launch_residual_w(G, a, st);
+  if (wave_path(G) && !a.kl) return launch_residual_w(G, a, st);
   // nodes per thread: 256 x 6 up to 1536 nodes, then 512 x 5 (2560) and 512 x 9 (4608)
   const int nt = G.N <= 1536 ? 256 : 512;
   const size_t lds = (size_t)G.N * 8 + (size_t)((G.N + 1) / 2) * 8 + (size_t)(nt / 64) * kNv * 8;

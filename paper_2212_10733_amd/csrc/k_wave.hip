@@ -1130,6 +1130,7 @@ __global__ __launch_bounds__(256, 2) void k_decompress_w(GridDev G, DecompressAr
   for (int k = 0; k < 4; ++k)
     lam[k] = a.lambda_fp32 ? (double)((const float*)a.lambda)[h * 4 + k] : ((const double*)a.lambda)[h * 4 + k];
   const bool clip = (fl & HCZ_FLAG_NOCLIP) == 0;
+  const bool kl = (fl & HCZ_FLAG_KL) != 0;
   double pa = 0.0;
   for_columns_pre(
       G,
@@ -1142,8 +1143,9 @@ __global__ __launch_bounds__(256, 2) void k_decompress_w(GridDev G, DecompressAr
         const double hv = (double)h;
         const double ft = coded ? hv + ldy(L.yb, off) : hv;
         const double w = UVOL ? G.vol0 : G.vol[j * G.n_par + i];
-        const double y = ft - w * fma(lam[2], L.s_cc[2 * j], pa);
-        out[j * G.n_par + i] = (TOut)(clip ? fmax(0.0, y) : y);
+        const double corr = w * fma(lam[2], L.s_cc[2 * j], pa);
+        const double y = ft - corr;
+        out[j * G.n_par + i] = (TOut)(kl ? (ft > 0.0 ? ft * exp(-corr) : 0.0) : (clip ? fmax(0.0, y) : y));
       },
       [](int) {});
 }

@@ -21,7 +21,7 @@ CONV_KEYS = ("c1w", "c1b", "c2w", "c2b", "fw", "fb", "dw", "db", "t1w", "t1b", "
 COMPUTE_FP32, COMPUTE_BF16 = 0, 1
 TAU_REL_L2, TAU_NRMSE = 0, 1
 FALLBACK_BACKTRACK, FALLBACK_PAPER = 0, 1
-FLAG_CODED, FLAG_ROUND2, FLAG_RAW, FLAG_WARM_REJECTED = 1, 2, 4, 8
+FLAG_CODED, FLAG_ROUND2, FLAG_RAW, FLAG_WARM_REJECTED, FLAG_NOCLIP, FLAG_KL = 1, 2, 4, 8, 16, 32
 WARM_COLD, WARM_MLP = 0, 1
 HIDDEN, LATENT = 128, 16
 
@@ -56,7 +56,7 @@ class Params(C.Structure):
                 ("newton_max_iter", C.c_int32), ("newton_max_iter2", C.c_int32),
                 ("fallback", C.c_int32), ("fit_codebook", C.c_int32), ("sample_every", C.c_int32),
                 ("warm_start", C.c_int32), ("mlp", C.c_void_p), ("lambda_fp32", C.c_int32),
-                ("no_positivity", C.c_int32), ("tau_hist", C.c_void_p)]
+                ("no_positivity", C.c_int32), ("tau_hist", C.c_void_p), ("kl", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -280,7 +280,7 @@ class Model:
 
 def params(tau=1e-3, tau_mode=TAU_REL_L2, newton_s=1.0, newton_max_iter=50, newton_max_iter2=400,
            fallback=FALLBACK_BACKTRACK, fit_codebook=False, sample_every=16, mlp=None, lambda_fp32=False,
-           no_positivity=False, tau_hist: torch.Tensor | None = None) -> Params:
+           no_positivity=False, tau_hist: torch.Tensor | None = None, kl=False) -> Params:
     """tau_hist: optional per-histogram bounds (device, float64, one per histogram), used in
     place of tau."""
     if tau_hist is not None and (tau_hist.dtype != torch.float64 or not tau_hist.is_cuda
@@ -289,7 +289,7 @@ def params(tau=1e-3, tau_mode=TAU_REL_L2, newton_s=1.0, newton_max_iter=50, newt
     p = Params(tau, tau_mode, newton_s, newton_max_iter, newton_max_iter2, fallback,
                int(fit_codebook), sample_every, WARM_MLP if mlp is not None else WARM_COLD,
                None if mlp is None else mlp.h, int(lambda_fp32), int(no_positivity),
-               None if tau_hist is None else tau_hist.data_ptr())
+               None if tau_hist is None else tau_hist.data_ptr(), int(kl))
     p._mlp = mlp          # keep the network and the bounds alive as long as the parameters
     p._tau_hist = tau_hist
     return p

@@ -42,11 +42,13 @@ def absconv(x, w, b):
     return conv.conv2d_s2(np.abs(x), np.abs(np.asarray(w, np.float64)), np.abs(np.asarray(b, np.float64)))
 
 
-@pytest.mark.parametrize("Hn,dtype,pad", [(200, np.float32, 0), (77, np.float64, 0), (50, np.float32, 5)])
+@pytest.mark.parametrize("Hn,dtype,pad", [(200, np.float32, 0), (77, np.float64, 0), (50, np.float32, 5),
+                                          (16384 + 37, np.float32, 0)])
 def test_conv_encode_parity(H, ctx, Hn, dtype, pad):
     """conv1 and its bfloat16 rounding are the oracle's bit for bit (same FP32 chain), so z
     differs only by FP32 accumulation: at most ~25 roundings of conv2's running sums (18
-    matrix-core steps plus the instruction's own) and ~410 in the dense layer."""
+    matrix-core steps plus the instruction's own) and ~3,200 in the dense layer (a
+    matrix-core accumulation over K = 6400 in steps of two)."""
     say("conv encode", Hn, dtype.__name__, pad)
     plan = H.Plan(ctx)
     F = synth.histograms(Hn, seed=60, dtype=dtype)
@@ -65,7 +67,7 @@ def test_conv_encode_parity(H, ctx, Hn, dtype, pad):
     s2 = absconv(h1b, w2b, W["c2b"]).reshape(Hn, 6400)
     h2 = np.maximum(conv.conv2d_s2(h1b, w2b, W["c2b"]), 0).reshape(Hn, 6400)
     fw = np.abs(W["fw"].astype(np.float64))
-    bound = 30 * EPS * (s2 @ fw.T) + 420 * EPS * (np.abs(h2) @ fw.T + np.abs(W["fb"]))
+    bound = 30 * EPS * (s2 @ fw.T) + 3300 * EPS * (np.abs(h2) @ fw.T + np.abs(W["fb"]))
     err = np.abs(z - zo)
     assert np.all(err <= bound), (err / bound).max()
 

@@ -240,3 +240,46 @@ def test_full_scale_batch(H, ctx, with_model):
         near = near_tie_codes(zs, Co, Cg, tol)
         diff = codes != codes_o
         assert not np.any(diff & ~near)
+
+
+@pytest.mark.parametrize("shape,tau", [((39, 39), 1e-2), ((39, 39), 1e-3), ((33, 37), 1e-2)])
+def test_kl_correction_end_to_end(H, ctx, shape, tau):
+    """The KL reading of Stage 5 (kept where it keeps the bound, the L2 projection
+    elsewhere), coder-only: records byte-exact, flags equal to the oracle's wherever the
+    KL bound decision is not a near-tie, multipliers to 1e-7, the bound, the QoIs and
+    non-negativity on the GPU's own output."""
+    n_perp, n_par = shape
+    say("kl", shape, tau)
+    g = grid.make_grid(n_par, n_perp)
+    Hn = 400
+    F = synth.histograms(Hn, n_par, n_perp, seed=44, dtype=np.float32)
+    plan = H.Plan(ctx, n_par, n_perp)
+    cz = H.Compressor(plan, None, Hn, H.params(tau=tau, kl=True))
+    comp = cz.compress(torch.from_numpy(F).cuda())
+    out = cz.decompress(comp, Hn).cpu().numpy()
+    flags = comp.flags.cpu().numpy()
+    ref = pipeline.compress(F, g, None, None, pipeline.Params(tau=tau, kl=True))
+    assert comp.stream_bytes() == ref["stream"]
+    # where the oracle's KL result sits within 1e-9 of the bound the decision may differ
+    F64 = F.astype(np.float64)
+    th = pipeline.tau_h(F64, pipeline.Params(tau=tau))
+    A = g.A()
+    near = np.zeros(Hn, bool)
+    for h in range(Hn):
+        if ref["flags"][h] & 4:
+            continue
+        ft = ref["ft"][h].reshape(-1)
+        r = oracle.newton.project_kl(ft.reshape(n_perp, n_par), A @ F64[h].reshape(-1), g)
+        if r["status"] < 2:
+            d = np.sqrt(((F64[h].reshape(-1) - r["x"].reshape(-1)) ** 2).sum())
+            near[h] = abs(d - (1 - 2.0 ** -20) * th[h]) <= 1e-9 * th[h]
+    same = flags == ref["flags"]
+    assert np.all(same | near), np.nonzero(~same & ~near)[0][:5]
+    kl = (flags & 32) != 0
+    assert kl.any() and not kl.all()
+    ok = same & ((flags & 4) == 0)
+    lam = comp.lam.cpu().numpy()
+    assert np.allclose(lam[ok], ref["lam"][ok], rtol=1e-7, atol=1e-9 * np.abs(ref["lam"][ok]).max())
+    check_roundtrip(F, out, flags, tau, g)
+    assert np.all(out[kl] >= 0)
+    assert np.allclose(out[ok], ref["fc"][ok], rtol=1e-10, atol=1e-13 * np.abs(F).max())

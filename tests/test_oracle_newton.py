@@ -184,3 +184,65 @@ def test_projection_without_positivity():
     pos = newton.project(ft, b, g)
     assert np.all(lin["x"] > 0)
     assert np.allclose(lin["lam"], pos["lam"], rtol=1e-10, atol=1e-14)
+
+
+def test_kl_reading_recovers_a_planted_solution():
+    """Plant the answer: for any f >= 0 and lam*, ft = f exp(+A^T lam*) projects (KL) onto
+    {A x = A f} at x = f with multipliers lam* (x = ft exp(-A^T lam) satisfies the
+    constraints at lam = lam*, and the minimiser is unique)."""
+    g = grid.make_grid()
+    A = g.A()
+    rng = np.random.default_rng(70)
+    for s in range(4):
+        f = synth.histograms(1, seed=70 + s, dtype=np.float64)[0].reshape(-1)
+        lam_star = rng.normal(0, 0.05, 4) / np.abs(A).max(axis=1)
+        ft = f * np.exp(A.T @ lam_star)
+        res = newton.project_kl(ft.reshape(39, 39), A @ f, g)
+        assert res["status"] == 0
+        assert np.allclose(res["lam"], lam_star, rtol=1e-9, atol=1e-12 * np.abs(lam_star).max())
+        assert np.allclose(res["x"].reshape(-1), f, rtol=1e-10, atol=1e-13 * f.max())
+        assert np.array_equal(res["x"].reshape(-1) == 0, f == 0)     # support is kept
+
+
+def test_kl_reading_matches_a_general_solver_on_3x3():
+    """The KL projection on a 3 x 3 grid against SLSQP minimising the I-divergence under
+    the four moment constraints (a library optimiser on the plain definition)."""
+    from scipy.optimize import minimize
+    g = grid.make_grid(3, 3)
+    A = g.A()
+    rng = np.random.default_rng(71)
+    for _ in range(3):
+        f = rng.uniform(0.2, 1.0, 9)
+        ft = f * rng.uniform(0.9, 1.1, 9)
+        b = A @ f
+        res = newton.project_kl(ft.reshape(3, 3), b, g)
+        assert res["status"] == 0
+        obj = lambda x: float(np.sum(x * np.log(x / ft) - x + ft))
+        jac = lambda x: np.log(x / ft)
+        sol = minimize(obj, ft, jac=jac, method="SLSQP", bounds=[(1e-12, None)] * 9,
+                       constraints=[dict(type="eq", fun=lambda x: A @ x - b, jac=lambda x: A)],
+                       options=dict(ftol=1e-15, maxiter=500))
+        assert sol.success
+        assert np.allclose(res["x"].reshape(-1), sol.x, rtol=1e-6, atol=1e-9)
+        assert np.allclose(A @ res["x"].reshape(-1), b, rtol=1e-13, atol=1e-15)
+
+
+def test_kl_pipeline_keeps_the_bound_and_qois():
+    """KL where it keeps the bound (flag bit 5), the L2 projection elsewhere: the bound,
+    the QoIs and non-negativity hold on every histogram."""
+    from oracle import pipeline
+    g = grid.make_grid()
+    F = synth.histograms(16, seed=72, dtype=np.float64)
+    p = pipeline.Params(tau=1e-2, kl=True)
+    comp = pipeline.compress(F, g, None, None, p)
+    raw = (comp["flags"] & pipeline.FLAG_RAW) != 0
+    kl = (comp["flags"] & pipeline.FLAG_KL) != 0
+    assert not raw.any() and 0 < kl.sum() < 16
+    out = pipeline.decompress(comp, g, None, None, 16, np.float64)
+    assert np.allclose(out, comp["fc"], rtol=1e-15, atol=0)
+    th = pipeline.tau_h(F, p)
+    dist = np.sqrt(((out - F) ** 2).reshape(16, -1).sum(1))
+    assert np.all(dist[~raw] <= th[~raw])
+    assert np.all(out >= 0)
+    err = moments.qoi_rel_error(moments.qoi(F, g), moments.qoi(out, g), g)[~raw]
+    assert err.max() < 1e-11
