@@ -149,10 +149,39 @@ def tau_sweep(hcz, plan, model, x, args) -> dict:
     return out
 
 
-def bf16_form(hcz, plan, ctx, x, W, args) -> dict:
-    """The plain workload with the autoencoder's two large products on bfloat16 operands
-    (FP32 accumulation): throughput, per-stage times with the encoder's and decoder's HBM
-    rates (4N bytes read, resp. written, per histogram), p, stream size, QoI error, bound."""
+def stage5_form(hcz, plan, x, args) -> dict:
+    """The coder-only pipeline at tau with each reading of the correction: FP32 multipliers,
+    no positivity (orthogonal projection onto A x = b), and the KL correction (kept where it
+    keeps the bound, the L2 projection elsewhere; it runs on the workgroup kernel)."""
+    import torch
+    H = x.shape[0]
+    _, q0, n0 = hcz.qoi(plan, x)
+    den = torch.stack([q0[:, 0].abs(), torch.maximum(q0[:, 1].abs(), q0[:, 3].abs().sqrt()),
+                       q0[:, 2].abs(), q0[:, 3].abs()], 1)
+    out = {}
+    for name, kw in (("fp32_lambda", dict(lambda_fp32=True)), ("no_positivity", dict(no_positivity=True)),
+                     ("kl", dict(kl=True))):
+        cz = hcz.Compressor(plan, None, H, hcz.params(tau=args.tau, **kw))
+        dt, comp = time_compress(cz, x, 2)
+        s = comp.stats()
+        o = cz.decompress(comp, H)
+        _, q1, _ = hcz.qoi(plan, o)
+        ok = (comp.flags & 4) == 0
+        out[name] = {"value": H / dt, "ms_per_step": dt * 1e3, "raw": s["n_raw"],
+                     "kl_kept": int(((comp.flags & 32) != 0).sum().item()),
+                     "negative_cells": int((o < 0).sum().item()),
+                     "max_qoi_rel_err": ((q1 - q0).abs() / den)[ok].max().item(),
+                     "max_err_over_tau_h": ((o - x.double()).reshape(H, -1).norm(dim=1)[ok]
+                                            / (args.tau * n0[ok])).max().item()}
+        del cz, comp, o
+    return out
+
+
+def bf16_form(hcz, plan, ctx, x, W, args, arch="dense") -> dict:
+    """The plain workload with the autoencoder's large products on bfloat16 operands
+    (FP32 accumulation), dense or convolutional: throughput, per-stage times with the
+    encoder's and decoder's HBM rates (4N bytes read, resp. written, per histogram) and
+    matrix-core rates, p, stream size, QoI error, bound."""
     import torch
     H, N = x.shape[0], plan.N
     xf = x.reshape(H, -1).double()
@@ -160,7 +189,7 @@ def bf16_form(hcz, plan, ctx, x, W, args) -> dict:
     sd = torch.clamp(sd, min=1e-12 * sd.max().item())
     mu, sd = mu.float().cpu().numpy(), sd.float().cpu().numpy()
     del xf
-    model = hcz.Model(plan, W, mu, sd, compute="bf16")
+    model = hcz.Model(plan, W, mu, sd, compute="bf16", arch=arch)
     cz = hcz.Compressor(plan, model, H, hcz.params(tau=args.tau, fit_codebook=True, sample_every=16))
     cz.compress(x)
     torch.cuda.synchronize()
@@ -183,9 +212,13 @@ def bf16_form(hcz, plan, ctx, x, W, args) -> dict:
            "max_qoi_rel_err": ((q1 - q0).abs() / den)[ok].max().item(),
            "max_err_over_tau_h": ((o - x.double()).reshape(H, -1).norm(dim=1)[ok] / (args.tau * n0[ok])).max().item(),
            "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()}}
+    # FLOP per histogram and direction: dense 2 (N 128 + 128 16); convolutional 2 (conv1
+    # 115,200 + conv2 1,843,200 + dense 102,400) multiply-adds, the decoder mirroring it
+    flop = 2 * (N * 128 + 128 * 16) if arch == "dense" else 2 * (115200 + 1843200 + 102400)
     for k in ("encode", "decode"):
         if k in stage_ms:
             res[f"{k}_hbm_GBps"] = H * 4 * N / (stage_ms[k] / 1e3) / 1e9
+            res[f"{k}_TFLOPs"] = H * flop / (stage_ms[k] / 1e3) / 1e12
     del cz, comp, o, model
     return res
 
@@ -302,6 +335,12 @@ def other_forms(hcz, plan, ctx, x, F, W, args, plain_value, plain_stats) -> dict
     if "bf16" in args.forms:
         log("form: BF16 autoencoder")
         out["bf16_ae"] = bf16_form(hcz, plan, ctx, x, W, args)
+    if "stage5" in args.forms:
+        log("form: Stage-5 variants")
+        out["stage5_variants"] = stage5_form(hcz, plan, x, args)
+    if "conv" in args.forms:
+        log("form: convolutional autoencoder (BF16)")
+        out["conv_ae"] = bf16_form(hcz, plan, ctx, x, synth.conv_ae_weights(), args, arch="conv")
     if "batched" in args.forms:
         log("form: batched uneven subdomains")
         out["batched"] = batched_form(hcz, ctx, args)
@@ -375,9 +414,11 @@ def main() -> int:
     ap.add_argument("--cpu-sample", type=int, default=8192)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the coder-only and learned forms")
-    ap.add_argument("--forms", default="tau,coder,bf16,batched,incremental,learned",
+    ap.add_argument("--forms", default="tau,coder,stage5,bf16,conv,batched,incremental,learned",
                     help="comma list of the other forms to run: tau (sweep), coder (coder-only), "
-                         "bf16 (BF16 autoencoder), batched (uneven subdomains on four grids), "
+                         "stage5 (FP32 multipliers, no positivity, KL correction), "
+                         "bf16 (BF16 autoencoder), conv (convolutional BF16 autoencoder), "
+                         "batched (uneven subdomains on four grids), "
                          "incremental (training series), learned")
     ap.add_argument("--train-hist", type=int, default=262144)
     ap.add_argument("--epochs", type=int, default=20)
