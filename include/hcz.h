@@ -318,6 +318,65 @@ hcz_status hcz_timestamp(uint64_t* dst, hcz_stream_t stream);
 /* Ticks per second of the device wall clock of HIP device `device`. */
 hcz_status hcz_wall_clock_hz(int device, double* hz);
 
+/* ---- output container and entropy coding (host) ------------------------------------
+ * The buffer of one compressed batch in the order the paper gives (Section III, end of
+ * Stage 5): a 44-byte header (scheme, sizes, byte boundaries, total size), the autoencoder
+ * weights with the z-score statistics, the quantized codes, the PQ table, the residual
+ * bytes (flags, record sizes, records) and the Lagrange multipliers.  entropy = 1 codes
+ * the codes and the residual bytes with an order-0 byte-wise rANS coder (12-bit
+ * frequencies, one table per section).  Every pointer here is a host pointer; the caller
+ * copies the device arrays of hcz_compressed to the host first.  Unpacking checks every
+ * size against the buffer and fails with HCZ_EINVAL on a malformed or truncated buffer,
+ * without reading past it. */
+typedef struct {
+  int64_t H;
+  int32_t n_par, n_perp;
+  int32_t arch;            /* 0: no model (coder-only), HCZ_ARCH_DENSE or HCZ_ARCH_CONV */
+  int32_t compute;         /* HCZ_COMPUTE_* of the model */
+  int32_t latent, bits;    /* codes per histogram and bits per code (model only) */
+  int32_t lambda_fp32;     /* multipliers stored as FP32 */
+  int32_t entropy;         /* 1: rANS-coded codes and residual bytes */
+  int64_t n_weights;       /* floats in the weight blob of hcz_model_desc */
+  uint64_t res_bytes;      /* residual record bytes (read_info output) */
+  uint64_t total_bytes;    /* container size (read_info output) */
+} hcz_container_info;
+
+typedef struct {
+  hcz_container_info info;
+  const float* weights;       /* [n_weights] (the hcz_model_desc blob) */
+  const float* norm_mean;     /* [N] */
+  const float* norm_std;      /* [N] */
+  const uint8_t* codes;       /* [H][latent] */
+  const float* centroids;     /* [latent][1 << bits] */
+  const uint8_t* flags;       /* [H] */
+  const uint64_t* res_offset; /* [H+1] exclusive scan of record sizes */
+  const uint8_t* res_bytes;   /* [res_offset[H]] */
+  const void* lambda;         /* [H][4] FP64, or FP32 when lambda_fp32 */
+} hcz_container_in;
+
+typedef struct {              /* arrays of the sizes hcz_container_read_info implies */
+  float* weights;
+  float* norm_mean;
+  float* norm_std;
+  uint8_t* codes;
+  float* centroids;
+  uint8_t* flags;
+  uint64_t* res_offset;       /* [H+1] */
+  uint8_t* res_bytes;
+  void* lambda;
+} hcz_container_out;
+
+/* Upper bound of the packed size, then the packing itself (*written = the size). */
+hcz_status hcz_container_bound(const hcz_container_in* c, size_t* bytes);
+hcz_status hcz_container_pack(const hcz_container_in* c, void* out, size_t capacity, size_t* written);
+/* Header fields, the residual byte count and the total size of a packed buffer. */
+hcz_status hcz_container_read_info(const void* buf, size_t n, hcz_container_info* info);
+hcz_status hcz_container_unpack(const void* buf, size_t n, const hcz_container_out* out);
+/* The rANS coder on its own: a block of n bytes needs at most hcz_rans_bound(n) bytes. */
+hcz_status hcz_rans_bound(size_t n, size_t* bytes);
+hcz_status hcz_rans_encode(const void* in, size_t n, void* out, size_t capacity, size_t* written);
+hcz_status hcz_rans_decode(const void* in, size_t avail, void* out, size_t n);
+
 /* ---- autoencoder training (Section III Stage 2, Eq. 5; Section IV-B) -------------------
  * The dense model of hcz_model_desc, trained with these kernels from torch.autograd.
  * params / grad: FP32 device vectors in the hcz_model_desc weights layout

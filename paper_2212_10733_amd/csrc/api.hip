@@ -30,6 +30,14 @@ hcz_status hip_fail(hipError_t e, const char* what) {
   return fail(HCZ_EHIP, "%s: %s", what, hipGetErrorString(e));
 }
 
+}  // namespace
+
+namespace hcz {
+hcz_status set_error(hcz_status s, const char* msg) { return fail(s, "%s", msg); }
+}  // namespace hcz
+
+namespace {
+
 #define HCZ_TRY(expr, what)                       \
   do {                                            \
     hipError_t e_ = (expr);                       \

@@ -327,6 +327,9 @@ size_t scan_partial_elems(long long H);
 hipError_t launch_compact(const uint8_t* slots, long long slot_stride, const uint64_t* offsets,
                           const uint64_t* sizes, long long H, uint8_t* out, uint64_t capacity,
                           hipStream_t st);
+// Records msg as the calling thread's last error and returns s.
+hcz_status set_error(hcz_status s, const char* msg);
+
 hipError_t launch_segment_tau(const int64_t* start, const double* tau, int nseg, long long H, double* out,
                               hipStream_t st);
 hipError_t launch_segment_max(const int64_t* start, int nseg, long long H, const uint64_t* t, uint64_t* out,

@@ -47,6 +47,25 @@ class ModelDesc(C.Structure):
                 ("norm_std", C.POINTER(C.c_float)), ("compute", C.c_int32)]
 
 
+class ContainerInfo(C.Structure):
+    _fields_ = [("H", C.c_int64), ("n_par", C.c_int32), ("n_perp", C.c_int32), ("arch", C.c_int32),
+                ("compute", C.c_int32), ("latent", C.c_int32), ("bits", C.c_int32), ("lambda_fp32", C.c_int32),
+                ("entropy", C.c_int32), ("n_weights", C.c_int64), ("res_bytes", C.c_uint64),
+                ("total_bytes", C.c_uint64)]
+
+
+class ContainerIn(C.Structure):
+    _fields_ = [("info", ContainerInfo), ("weights", C.c_void_p), ("norm_mean", C.c_void_p),
+                ("norm_std", C.c_void_p), ("codes", C.c_void_p), ("centroids", C.c_void_p), ("flags", C.c_void_p),
+                ("res_offset", C.c_void_p), ("res_bytes", C.c_void_p), ("lambda_", C.c_void_p)]
+
+
+class ContainerOut(C.Structure):
+    _fields_ = [("weights", C.c_void_p), ("norm_mean", C.c_void_p), ("norm_std", C.c_void_p),
+                ("codes", C.c_void_p), ("centroids", C.c_void_p), ("flags", C.c_void_p),
+                ("res_offset", C.c_void_p), ("res_bytes", C.c_void_p), ("lambda_", C.c_void_p)]
+
+
 class Codebook(C.Structure):
     _fields_ = [("bits", C.c_int32), ("centroids", C.c_void_p)]
 
@@ -125,6 +144,13 @@ def _load() -> C.CDLL:
         "hcz_segment_max": [vp, i32, i64, vp, vp, vp],
         "hcz_timestamp": [vp, vp],
         "hcz_wall_clock_hz": [C.c_int, C.POINTER(C.c_double)],
+        "hcz_container_bound": [C.POINTER(ContainerIn), C.POINTER(sz)],
+        "hcz_container_pack": [C.POINTER(ContainerIn), vp, sz, C.POINTER(sz)],
+        "hcz_container_read_info": [vp, sz, C.POINTER(ContainerInfo)],
+        "hcz_container_unpack": [vp, sz, C.POINTER(ContainerOut)],
+        "hcz_rans_bound": [sz, C.POINTER(sz)],
+        "hcz_rans_encode": [vp, sz, vp, sz, C.POINTER(sz)],
+        "hcz_rans_decode": [vp, sz, vp, sz],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -150,7 +176,9 @@ EXPORTS = ["hcz_create", "hcz_destroy", "hcz_last_error", "hcz_version", "hcz_pl
            "hcz_mse_workspace", "hcz_mse", "hcz_adam_step", "hcz_norm_stats_workspace", "hcz_norm_stats",
            "hcz_mlp_load", "hcz_mlp_free", "hcz_mlp_param_count", "hcz_mlp_saved_bytes", "hcz_mlp_forward",
            "hcz_mlp_backward", "hcz_dequantize", "hcz_mlp_predict", "hcz_segment_tau", "hcz_segment_max",
-           "hcz_timestamp", "hcz_wall_clock_hz"]
+           "hcz_timestamp", "hcz_wall_clock_hz", "hcz_container_bound", "hcz_container_pack",
+           "hcz_container_read_info", "hcz_container_unpack", "hcz_rans_bound", "hcz_rans_encode",
+           "hcz_rans_decode"]
 
 STAGES = ["encode", "codebook", "quantize", "decode", "residual", "scan", "compact", "stats", "decompress",
           "warmstart"]
@@ -238,9 +266,24 @@ class Plan:
             self.h = None
 
 
+DENSE_KEYS = ("W1", "b1", "W2", "b2", "W3", "b3", "W4", "b4")
+
+
 def pack_dense_weights(W: dict) -> np.ndarray:
-    return np.concatenate([np.ascontiguousarray(W[k], np.float32).ravel()
-                           for k in ("W1", "b1", "W2", "b2", "W3", "b3", "W4", "b4")])
+    return np.concatenate([np.ascontiguousarray(W[k], np.float32).ravel() for k in DENSE_KEYS])
+
+
+def unpack_dense_weights(blob: np.ndarray, N: int) -> dict:
+    shapes = dict(W1=(HIDDEN, N), b1=(HIDDEN,), W2=(LATENT, HIDDEN), b2=(LATENT,), W3=(HIDDEN, LATENT),
+                  b3=(HIDDEN,), W4=(N, HIDDEN), b4=(N,))
+    out, o = {}, 0
+    for k in DENSE_KEYS:
+        n = int(np.prod(shapes[k]))
+        out[k] = np.asarray(blob[o:o + n], np.float32).reshape(shapes[k])
+        o += n
+    if o != blob.size:
+        raise ValueError("weight blob size does not match the dense model of this grid")
+    return out
 
 
 class Model:
@@ -539,3 +582,90 @@ def wall_clock_hz(device: int = 0) -> float:
     hz = C.c_double()
     _check(LIB.hcz_wall_clock_hz(device, C.byref(hz)))
     return hz.value
+
+
+# ---- output container and rANS (host) ----------------------------------------------------
+
+def _np_ptr(a):
+    return None if a is None else C.c_void_p(a.ctypes.data)
+
+
+def rans_encode(data: bytes | np.ndarray) -> bytes:
+    a = np.frombuffer(bytes(data), np.uint8) if not isinstance(data, np.ndarray) else np.ascontiguousarray(data, np.uint8)
+    nb = C.c_size_t()
+    _check(LIB.hcz_rans_bound(a.size, C.byref(nb)))
+    out = np.empty(nb.value, np.uint8)
+    w = C.c_size_t()
+    _check(LIB.hcz_rans_encode(_np_ptr(a) if a.size else C.c_void_p(out.ctypes.data), a.size, _np_ptr(out), out.size,
+                               C.byref(w)))
+    return out[:w.value].tobytes()
+
+
+def rans_decode(block: bytes, n: int) -> np.ndarray:
+    b = np.frombuffer(block, np.uint8)
+    out = np.empty(max(n, 1), np.uint8)
+    _check(LIB.hcz_rans_decode(_np_ptr(b), b.size, _np_ptr(out), n))
+    return out[:n]
+
+
+def container_pack(n_par: int, n_perp: int, flags, res_offset, res_bytes, lam, codes=None, centroids=None,
+                   weights=None, norm_mean=None, norm_std=None, arch: str | None = None, compute: str = "fp32",
+                   entropy: bool = False) -> bytes:
+    """Pack host (numpy) arrays of one compressed batch into the container (see hcz.h)."""
+    flags = np.ascontiguousarray(flags, np.uint8)
+    H = flags.size
+    res_offset = np.ascontiguousarray(res_offset, np.uint64)
+    res_bytes = np.ascontiguousarray(res_bytes, np.uint8)
+    lam = np.ascontiguousarray(lam)
+    info = ContainerInfo(H, n_par, n_perp, 0 if arch is None else (ARCH_CONV if arch == "conv" else ARCH_DENSE),
+                         COMPUTE_BF16 if compute == "bf16" else COMPUTE_FP32, 0, 0, int(lam.dtype == np.float32),
+                         int(entropy), 0, 0, 0)
+    keep = [flags, res_offset, res_bytes, lam]
+    cin = ContainerIn(info, None, None, None, None, None, _np_ptr(flags), _np_ptr(res_offset),
+                      _np_ptr(res_bytes) if res_bytes.size else None, _np_ptr(lam))
+    if arch is not None:
+        codes = np.ascontiguousarray(codes, np.uint8)
+        centroids = np.ascontiguousarray(centroids, np.float32)
+        weights = np.ascontiguousarray(weights, np.float32)
+        norm_mean = np.ascontiguousarray(norm_mean, np.float32)
+        norm_std = np.ascontiguousarray(norm_std, np.float32)
+        keep += [codes, centroids, weights, norm_mean, norm_std]
+        cin.info.latent = codes.shape[1]
+        cin.info.bits = int(np.log2(centroids.shape[1]))
+        cin.info.n_weights = weights.size
+        cin.weights, cin.norm_mean, cin.norm_std = _np_ptr(weights), _np_ptr(norm_mean), _np_ptr(norm_std)
+        cin.codes, cin.centroids = _np_ptr(codes), _np_ptr(centroids)
+    nb = C.c_size_t()
+    _check(LIB.hcz_container_bound(C.byref(cin), C.byref(nb)))
+    out = np.empty(nb.value, np.uint8)
+    w = C.c_size_t()
+    _check(LIB.hcz_container_pack(C.byref(cin), _np_ptr(out), out.size, C.byref(w)))
+    del keep
+    return out[:w.value].tobytes()
+
+
+def container_unpack(buf: bytes) -> dict:
+    """The arrays of a packed container (numpy) and its header fields."""
+    b = np.frombuffer(buf, np.uint8)
+    info = ContainerInfo()
+    _check(LIB.hcz_container_read_info(_np_ptr(b), b.size, C.byref(info)))
+    H, N = info.H, info.n_par * info.n_perp
+    d = dict(H=H, n_par=info.n_par, n_perp=info.n_perp, entropy=bool(info.entropy),
+             flags=np.empty(H, np.uint8), res_offset=np.empty(H + 1, np.uint64),
+             res_bytes=np.empty(max(int(info.res_bytes), 1), np.uint8),
+             lam=np.empty((H, 4), np.float32 if info.lambda_fp32 else np.float64))
+    out = ContainerOut(None, None, None, None, None, _np_ptr(d["flags"]), _np_ptr(d["res_offset"]),
+                       _np_ptr(d["res_bytes"]), _np_ptr(d["lam"]))
+    if info.arch:
+        d.update(arch="conv" if info.arch == ARCH_CONV else "dense",
+                 compute="bf16" if info.compute == COMPUTE_BF16 else "fp32",
+                 weights=np.empty(info.n_weights, np.float32), norm_mean=np.empty(N, np.float32),
+                 norm_std=np.empty(N, np.float32), codes=np.empty((H, info.latent), np.uint8),
+                 centroids=np.empty((info.latent, 1 << info.bits), np.float32))
+        out.weights, out.norm_mean, out.norm_std = _np_ptr(d["weights"]), _np_ptr(d["norm_mean"]), _np_ptr(d["norm_std"])
+        out.codes, out.centroids = _np_ptr(d["codes"]), _np_ptr(d["centroids"])
+    else:
+        d["arch"] = None
+    _check(LIB.hcz_container_unpack(_np_ptr(b), b.size, C.byref(out)))
+    d["res_bytes"] = d["res_bytes"][:int(info.res_bytes)]
+    return d

@@ -283,3 +283,46 @@ def test_kl_correction_end_to_end(H, ctx, shape, tau):
     check_roundtrip(F, out, flags, tau, g)
     assert np.all(out[kl] >= 0)
     assert np.allclose(out[ok], ref["fc"][ok], rtol=1e-10, atol=1e-13 * np.abs(F).max())
+
+
+@pytest.mark.parametrize("with_model", [False, True])
+def test_container_round_trip_through_decompression(H, ctx, with_model):
+    """Compress, copy to the host, pack the container with rANS, unpack, copy back and
+    decompress: the same histograms bit for bit as decompressing the original arrays."""
+    say("container", with_model)
+    Hn = 2000
+    F = synth.histograms(Hn, seed=45, dtype=np.float32)
+    plan = H.Plan(ctx)
+    model, kw = None, {}
+    if with_model:
+        W = synth.dense_ae_weights()
+        mu, sd = oracle.ae.norm_stats(F)
+        mu, sd = mu.astype(np.float32), sd.astype(np.float32)
+        model = H.Model(plan, W, mu, sd)
+        kw = dict(weights=H.pack_dense_weights(W), norm_mean=mu, norm_std=sd, arch="dense", compute="fp32")
+    cz = H.Compressor(plan, model, Hn, H.params(tau=1e-3, fit_codebook=with_model, sample_every=4))
+    comp = cz.compress(torch.from_numpy(F).cuda())
+    ref = cz.decompress(comp, Hn).cpu().numpy()
+    off = comp.offsets.cpu().numpy().astype(np.uint64)
+    if with_model:
+        kw.update(codes=comp.codes.cpu().numpy(), centroids=cz.centroids.cpu().numpy())
+    buf = H.container_pack(39, 39, comp.flags.cpu().numpy(), off, np.frombuffer(comp.stream_bytes(), np.uint8),
+                           comp.lam.cpu().numpy(), entropy=True, **kw)
+    plain = H.container_pack(39, 39, comp.flags.cpu().numpy(), off, np.frombuffer(comp.stream_bytes(), np.uint8),
+                             comp.lam.cpu().numpy(), entropy=False, **kw)
+    assert len(buf) < len(plain)
+    d = H.container_unpack(buf)
+    back = H.alloc_compressed(Hn, plan.N, "cuda")
+    back.flags.copy_(torch.from_numpy(d["flags"]))
+    back.offsets.copy_(torch.from_numpy(d["res_offset"].astype(np.int64)))
+    back.stream[:d["res_bytes"].size].copy_(torch.from_numpy(d["res_bytes"]))
+    back.lam.copy_(torch.from_numpy(d["lam"]))
+    if with_model:
+        back.codes.copy_(torch.from_numpy(d["codes"]))
+        m2 = H.Model(plan, H.unpack_dense_weights(d["weights"], plan.N), d["norm_mean"], d["norm_std"])
+        cz2 = H.Compressor(plan, m2, Hn, H.params(tau=1e-3))
+        cz2.centroids.copy_(torch.from_numpy(d["centroids"]))
+    else:
+        cz2 = cz
+    out = cz2.decompress(back, Hn).cpu().numpy()
+    assert np.array_equal(out, ref)
