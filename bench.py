@@ -149,6 +149,41 @@ def tau_sweep(hcz, plan, model, x, args) -> dict:
     return out
 
 
+def container_form(hcz, plan, x, W, args, n=131072) -> dict:
+    """The output container of the plain form on the first n histograms: bytes without and
+    with the rANS coding of codes and residual bytes, and the host pack / unpack rates
+    (single thread) including the device-to-host copies."""
+    import torch
+    xs = x[:n]
+    xf = xs.reshape(n, -1).double()
+    mu = xf.mean(0).float().cpu().numpy()
+    sd = torch.clamp(xf.std(0, unbiased=False), min=1e-12).float().cpu().numpy()
+    del xf
+    model = hcz.Model(plan, W, mu, sd)
+    cz = hcz.Compressor(plan, model, n, hcz.params(tau=args.tau, fit_codebook=True, sample_every=16))
+    comp = cz.compress(xs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    arrays = dict(flags=comp.flags.cpu().numpy(), res_offset=comp.offsets.cpu().numpy().astype(np.uint64),
+                  res_bytes=np.frombuffer(comp.stream_bytes(), np.uint8), lam=comp.lam.cpu().numpy(),
+                  codes=comp.codes.cpu().numpy(), centroids=cz.centroids.cpu().numpy(),
+                  weights=hcz.pack_dense_weights(W), norm_mean=mu, norm_std=sd, arch="dense")
+    t_copy = time.perf_counter() - t0
+    res = {"histograms": n, "input_bytes": n * plan.N * 4, "d2h_seconds": t_copy}
+    for ent in (False, True):
+        t0 = time.perf_counter()
+        buf = hcz.container_pack(plan.n_par, plan.n_perp, entropy=ent, **arrays)
+        t1 = time.perf_counter()
+        d = hcz.container_unpack(buf)
+        t2 = time.perf_counter()
+        assert np.array_equal(d["res_bytes"], arrays["res_bytes"])
+        res["rans" if ent else "plain"] = {"bytes": len(buf), "ratio": n * plan.N * 4 / len(buf),
+                                           "pack_MBps": len(buf) / (t1 - t0) / 1e6,
+                                           "unpack_MBps": len(buf) / (t2 - t1) / 1e6}
+    del cz, comp, model
+    return res
+
+
 def stage5_form(hcz, plan, x, args) -> dict:
     """The coder-only pipeline at tau with each reading of the correction: FP32 multipliers,
     no positivity (orthogonal projection onto A x = b), and the KL correction (kept where it
@@ -338,6 +373,9 @@ def other_forms(hcz, plan, ctx, x, F, W, args, plain_value, plain_stats) -> dict
     if "stage5" in args.forms:
         log("form: Stage-5 variants")
         out["stage5_variants"] = stage5_form(hcz, plan, x, args)
+    if "container" in args.forms:
+        log("form: container")
+        out["container"] = container_form(hcz, plan, x, W, args)
     if "conv" in args.forms:
         log("form: convolutional autoencoder (BF16)")
         out["conv_ae"] = bf16_form(hcz, plan, ctx, x, synth.conv_ae_weights(), args, arch="conv")
@@ -414,9 +452,10 @@ def main() -> int:
     ap.add_argument("--cpu-sample", type=int, default=8192)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the coder-only and learned forms")
-    ap.add_argument("--forms", default="tau,coder,stage5,bf16,conv,batched,incremental,learned",
+    ap.add_argument("--forms", default="tau,coder,stage5,container,bf16,conv,batched,incremental,learned",
                     help="comma list of the other forms to run: tau (sweep), coder (coder-only), "
-                         "stage5 (FP32 multipliers, no positivity, KL correction), "
+                         "stage5 (FP32 multipliers, no positivity, KL correction), container (packed "
+                         "output with and without rANS), "
                          "bf16 (BF16 autoencoder), conv (convolutional BF16 autoencoder), "
                          "batched (uneven subdomains on four grids), "
                          "incremental (training series), learned")
