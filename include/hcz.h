@@ -150,6 +150,11 @@ typedef struct {
  *                  where ||f - f_c|| <= (1 - 2^-20) tau_h; elsewhere the histogram gets the
  *                  L2 projection.  Runs on the workgroup-per-histogram kernel for every grid.
  *                  Not combined with no_positivity or a warm start (HCZ_EINVAL).
+ * lambda_bits      0: multipliers stored as computed; 1..52: rounded (nearest, ties to
+ *                  even) to that many mantissa bits before storage, the truncation of the
+ *                  multipliers the paper allows to raise the compression level (Section I);
+ *                  the QoI error grows like 2^-lambda_bits, and the PD bound holds up to
+ *                  the change the rounding makes to f_c.  At most 23 with lambda_fp32.
  * tau_hist         NULL: every histogram uses tau.  Otherwise (device, FP64, [H]) histogram
  *                  h uses tau_hist[h] in place of tau (tau is then not read): per-subdomain
  *                  bounds in one call, see hcz_segment_tau.  A negative, infinite or NaN
@@ -169,6 +174,7 @@ typedef struct {
   int32_t no_positivity;
   const double* tau_hist;
   int32_t kl;
+  int32_t lambda_bits;
 } hcz_params;
 
 /* Run statistics, written to device memory by compress and read with hcz_stats_read. */
@@ -323,8 +329,8 @@ hcz_status hcz_wall_clock_hz(int device, double* hz);
  * Stage 5): a 44-byte header (scheme, sizes, byte boundaries, total size), the autoencoder
  * weights with the z-score statistics, the quantized codes, the PQ table, the residual
  * bytes (flags, record sizes, records) and the Lagrange multipliers.  entropy = 1 codes
- * the codes and the residual bytes with an order-0 byte-wise rANS coder (12-bit
- * frequencies, one table per section).  Every pointer here is a host pointer; the caller
+ * the codes, the residual bytes and the multipliers with an order-0 byte-wise rANS coder
+ * (12-bit frequencies, one table per section).  Every pointer here is a host pointer; the caller
  * copies the device arrays of hcz_compressed to the host first.  Unpacking checks every
  * size against the buffer and fails with HCZ_EINVAL on a malformed or truncated buffer,
  * without reading past it. */

@@ -43,6 +43,19 @@ class Params:
     lambda_fp32: bool = False       # store the multipliers as FP32
     positivity: bool = True         # False: projection onto {A x = b} only
     kl: bool = False                # True: the KL / I-divergence correction (multiplicative)
+    lambda_bits: int = 0            # > 0: multipliers rounded to this many mantissa bits
+
+
+def round_mantissa(v: np.ndarray, bits: int) -> np.ndarray:
+    """Round FP64 values to `bits` explicit mantissa bits, nearest with ties to even
+    (bits = 0 or >= 52 keeps them): the truncation of the multipliers (Section I)."""
+    v = np.ascontiguousarray(v, np.float64)
+    if bits <= 0 or bits >= 52:
+        return v.copy()
+    u = v.view(np.uint64)
+    drop = np.uint64(52 - bits)
+    half = (np.uint64(1) << (drop - np.uint64(1))) - np.uint64(1) + ((u >> drop) & np.uint64(1))
+    return ((u + half) & ~((np.uint64(1) << drop) - np.uint64(1))).view(np.float64)
 
 
 def tau_of(H: int, p: Params) -> np.ndarray:
@@ -182,6 +195,7 @@ def compress(F: np.ndarray, g: Grid, model: dict | None, C: np.ndarray | None, p
     sizes = np.array([len(x) for x in records], np.uint64)
     offsets = np.zeros(H + 1, np.uint64)
     offsets[1:] = np.cumsum(sizes)
+    lam = round_mantissa(lam, p.lambda_bits)
     if p.lambda_fp32:
         lam = lam.astype(np.float32)
     return dict(codes=codes, lam=lam, flags=flags, stream=b"".join(records), offsets=offsets,

@@ -405,6 +405,8 @@ hcz_status check_params(const hcz_params* p) {
   if (p->lambda_fp32 != 0 && p->lambda_fp32 != 1) return fail(HCZ_EINVAL, "lambda_fp32 must be 0 or 1");
   if (p->no_positivity != 0 && p->no_positivity != 1) return fail(HCZ_EINVAL, "no_positivity must be 0 or 1");
   if (p->kl != 0 && p->kl != 1) return fail(HCZ_EINVAL, "kl must be 0 or 1");
+  if (p->lambda_bits < 0 || p->lambda_bits > 52 || (p->lambda_fp32 && p->lambda_bits > 23))
+    return fail(HCZ_EINVAL, "lambda_bits must be in [0, 52] ([0, 23] with FP32 multipliers)");
   if (p->kl && (p->no_positivity || p->warm_start != HCZ_WARM_COLD))
     return fail(HCZ_EINVAL, "kl is not combined with no_positivity or a warm start");
   return HCZ_OK;
@@ -864,6 +866,7 @@ static hcz_status residual_impl(const hcz_plan* plan, const hcz_params* p, const
   a.lambda_fp32 = p->lambda_fp32;
   a.no_positivity = p->no_positivity;
   a.kl = p->kl;
+  a.lambda_bits = p->lambda_bits;
   a.flags = out->flags;
   a.sizes = (uint64_t*)(ws + L.sizes);
   a.slots = ws + L.slots;

@@ -1,7 +1,8 @@
 // The output buffer of one compressed batch (Section III, end of Stage 5): a 44-byte
 // header, the autoencoder weights (with the z-score statistics), the quantized codes, the
 // PQ table, the residual bytes and the Lagrange multipliers, in that order; plus an
-// optional order-0 rANS coding of the codes and of the residual bytes.  Host code only.
+// optional order-0 rANS coding of the codes, the residual bytes and the multipliers.  Host
+// code only.
 //
 // Header (little-endian): magic "HCZ1"; u16 scheme (bits 0-1 architecture: 0 none,
 // 1 dense, 2 convolutional; bit 2 BF16 compute; bit 3 FP32 multipliers; bit 4 entropy
@@ -9,7 +10,8 @@
 // u64 end of the residual section; u64 total size; u32 FNV-1a checksum of the first 40
 // header bytes.  Sections start at multiples of 8: weights (FP32 weights, mean, std),
 // codes [H][latent] (raw or rANS), PQ table [latent][2^bits] FP32, residual (flags [H],
-// record sizes [H] u32, the records back to back, raw or rANS), multipliers [H][4].
+// record sizes [H] u32, the records back to back, raw or rANS), multipliers [H][4] (raw or
+// rANS).
 //
 // rANS (Duda's asymmetric numeral systems, range variant, byte-wise renormalisation):
 // 32-bit state kept in [2^23, 2^31), symbol frequencies quantised to 12 bits.  A coded
@@ -203,7 +205,8 @@ hcz_status hcz_container_bound(const hcz_container_in* c, size_t* bytes) {
   const size_t rb = (size_t)c->res_offset[c->info.H];
   const size_t codes = c->info.entropy ? rans_bound(z.codes_raw) : z.codes_raw;
   const size_t res = c->info.entropy ? rans_bound(rb) : rb;
-  *bytes = up8(kHeader) + up8(z.weights) + up8(codes) + up8(z.pq) + up8(z.flags + z.recs + res) + up8(z.lam);
+  const size_t lam = c->info.entropy ? rans_bound(z.lam) : z.lam;
+  *bytes = up8(kHeader) + up8(z.weights) + up8(codes) + up8(z.pq) + up8(z.flags + z.recs + res) + up8(lam);
   return HCZ_OK;
 }
 
@@ -257,8 +260,11 @@ hcz_status hcz_container_pack(const hcz_container_in* c, void* out, size_t capac
   const uint64_t res_end = o;
   o = up8(o);
   (void)res0;
-  std::memcpy(b + o, c->lambda, z.lam);
-  o += up8(z.lam);
+  if (i.entropy) o += up8(rans_encode((const uint8_t*)c->lambda, z.lam, b + o));
+  else {
+    std::memcpy(b + o, c->lambda, z.lam);
+    o += up8(z.lam);
+  }
   // header
   const uint16_t scheme = (uint16_t)(i.arch | (i.compute == HCZ_COMPUTE_BF16 ? 4 : 0) | (i.lambda_fp32 ? 8 : 0) |
                                      (i.entropy ? 16 : 0));
@@ -396,8 +402,14 @@ hcz_status hcz_container_unpack(const void* buf, size_t n, const hcz_container_o
     if (i.res_bytes) std::memcpy(out->res_bytes, b + o, i.res_bytes);
   }
   o = up8(res_end);
-  if (o + z.lam > tot) return set_error(HCZ_EINVAL, "container multipliers truncated");
-  std::memcpy(out->lambda, b + o, z.lam);
+  if (i.entropy) {
+    size_t used = 0;
+    if (o > tot || !rans_decode(b + o, tot - o, (uint8_t*)out->lambda, z.lam, &used))
+      return set_error(HCZ_EINVAL, "malformed multiplier section");
+  } else {
+    if (o + z.lam > tot) return set_error(HCZ_EINVAL, "container multipliers truncated");
+    std::memcpy(out->lambda, b + o, z.lam);
+  }
   return HCZ_OK;
 }
 

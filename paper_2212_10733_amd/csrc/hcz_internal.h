@@ -111,6 +111,7 @@ struct ResidualArgs {
   int lambda_fp32;
   int no_positivity;           // 1: projection onto {A x = b} only (flag HCZ_FLAG_NOCLIP)
   int kl;                      // 1: KL correction where it keeps the bound (flag HCZ_FLAG_KL)
+  int lambda_bits;             // 0, or stored multipliers rounded to this many mantissa bits
   uint8_t* flags;              // [H]
   uint64_t* sizes;             // [H] record bytes
   uint8_t* slots;              // [H][slot_stride] staging
@@ -135,6 +136,19 @@ struct DecompressArgs {
   int out_dtype;
   uint64_t capacity;           // bytes of `stream`; records ending past it decode to NaN
 };
+
+// v rounded to `bits` explicit mantissa bits (nearest, ties to even); bits = 0 or >= 52
+// keeps v.  A carry out of the mantissa moves into the exponent, as it should.
+__host__ __device__ inline double round_mantissa(double v, int bits) {
+  if (bits <= 0 || bits >= 52) return v;
+  unsigned long long u;
+  __builtin_memcpy(&u, &v, 8);
+  const int drop = 52 - bits;
+  const unsigned long long half = (1ull << (drop - 1)) - 1ull + ((u >> drop) & 1ull);
+  u = (u + half) & ~((1ull << drop) - 1ull);
+  __builtin_memcpy(&v, &u, 8);
+  return v;
+}
 
 // Quantised coefficient Dk * q, q = rint(d / Dk) taken as an integer: rint of a small
 // negative value is -0, which the integer turns into +0.

@@ -556,7 +556,7 @@ __global__ __launch_bounds__(NT) void k_residual(GridDev G, ResidualArgs a) {
   if (t == 0) {
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      const double lv = raw ? 0.0 : lam[k];
+      const double lv = raw ? 0.0 : round_mantissa(lam[k], a.lambda_bits);
       if (a.lambda_fp32) ((float*)a.lambda)[h * 4 + k] = (float)lv;
       else ((double*)a.lambda)[h * 4 + k] = lv;
     }

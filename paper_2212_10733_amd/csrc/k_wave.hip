@@ -1025,7 +1025,7 @@ __global__ __launch_bounds__(256, 2) void k_residual_w(GridDev G, ResidualArgs a
   if (lane == 0) {
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      const double lv = raw ? 0.0 : lam[k];
+      const double lv = raw ? 0.0 : round_mantissa(lam[k], a.lambda_bits);
       if (a.lambda_fp32) ((float*)a.lambda)[h * 4 + k] = (float)lv;
       else ((double*)a.lambda)[h * 4 + k] = lv;
     }

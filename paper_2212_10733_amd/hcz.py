@@ -75,7 +75,8 @@ class Params(C.Structure):
                 ("newton_max_iter", C.c_int32), ("newton_max_iter2", C.c_int32),
                 ("fallback", C.c_int32), ("fit_codebook", C.c_int32), ("sample_every", C.c_int32),
                 ("warm_start", C.c_int32), ("mlp", C.c_void_p), ("lambda_fp32", C.c_int32),
-                ("no_positivity", C.c_int32), ("tau_hist", C.c_void_p), ("kl", C.c_int32)]
+                ("no_positivity", C.c_int32), ("tau_hist", C.c_void_p), ("kl", C.c_int32),
+                ("lambda_bits", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -323,7 +324,7 @@ class Model:
 
 def params(tau=1e-3, tau_mode=TAU_REL_L2, newton_s=1.0, newton_max_iter=50, newton_max_iter2=400,
            fallback=FALLBACK_BACKTRACK, fit_codebook=False, sample_every=16, mlp=None, lambda_fp32=False,
-           no_positivity=False, tau_hist: torch.Tensor | None = None, kl=False) -> Params:
+           no_positivity=False, tau_hist: torch.Tensor | None = None, kl=False, lambda_bits: int = 0) -> Params:
     """tau_hist: optional per-histogram bounds (device, float64, one per histogram), used in
     place of tau."""
     if tau_hist is not None and (tau_hist.dtype != torch.float64 or not tau_hist.is_cuda
@@ -332,7 +333,7 @@ def params(tau=1e-3, tau_mode=TAU_REL_L2, newton_s=1.0, newton_max_iter=50, newt
     p = Params(tau, tau_mode, newton_s, newton_max_iter, newton_max_iter2, fallback,
                int(fit_codebook), sample_every, WARM_MLP if mlp is not None else WARM_COLD,
                None if mlp is None else mlp.h, int(lambda_fp32), int(no_positivity),
-               None if tau_hist is None else tau_hist.data_ptr(), int(kl))
+               None if tau_hist is None else tau_hist.data_ptr(), int(kl), int(lambda_bits))
     p._mlp = mlp          # keep the network and the bounds alive as long as the parameters
     p._tau_hist = tau_hist
     return p

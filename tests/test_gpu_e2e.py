@@ -326,3 +326,27 @@ def test_container_round_trip_through_decompression(H, ctx, with_model):
         cz2 = cz
     out = cz2.decompress(back, Hn).cpu().numpy()
     assert np.array_equal(out, ref)
+
+
+@pytest.mark.parametrize("bits", [12, 30])
+def test_multiplier_truncation(H, ctx, bits):
+    """Multipliers rounded to `bits` mantissa bits: at most that many bits set, equal to the
+    oracle's rounded multipliers up to the Newton tolerance and one unit in the last kept
+    place, records byte-exact, QoI error of the order of 2^-bits."""
+    say("lambda bits", bits)
+    g = grid.make_grid()
+    F = synth.histograms(500, seed=46, dtype=np.float32)
+    cz = H.Compressor(H.Plan(ctx), None, 500, H.params(tau=1e-3, lambda_bits=bits))
+    comp = cz.compress(torch.from_numpy(F).cuda())
+    lam = comp.lam.cpu().numpy()
+    assert np.all((lam.view(np.uint64) & np.uint64((1 << (52 - bits)) - 1)) == 0)
+    ref = pipeline.compress(F, g, None, None, pipeline.Params(tau=1e-3, lambda_bits=bits))
+    assert comp.stream_bytes() == ref["stream"]
+    ok = (ref["flags"] & 4) == 0
+    # the unrounded multipliers agree to the Newton tolerance (1e-7 relative, 1e-9 of the
+    # largest), the rounding adds at most one unit in the last kept place
+    scale = np.abs(ref["lam"][ok]).max()
+    assert np.all(np.abs(lam[ok] - ref["lam"][ok]) <= (2.0 ** -bits + 1e-7) * np.abs(ref["lam"][ok]) + 1e-9 * scale)
+    out = cz.decompress(comp, 500).cpu().numpy()
+    err = moments.qoi_rel_error(moments.qoi(F.astype(np.float64), g), moments.qoi(out, g), g)[ok]
+    assert 2.0 ** -(bits + 12) < err.max() < 2.0 ** -(bits - 10)

@@ -196,3 +196,27 @@ def test_conv_model_roundtrip():
     out = pipeline.decompress(comp, g, model, comp["codebook"], 10, np.float32)
     check_bound_and_qoi(F, out, comp, g, 1e-3)
     assert np.array_equal(out, comp["fc"])
+
+
+def test_multiplier_truncation():
+    """Rounding to m mantissa bits is nearest-even (at m = 23 it equals the FP32 conversion
+    for normal values); the QoI error of the decompressed data grows like 2^-m while the
+    bound still holds."""
+    rng = np.random.default_rng(30)
+    v = rng.standard_normal(10000) * 10.0 ** rng.integers(-30, 30, 10000)
+    assert np.array_equal(pipeline.round_mantissa(v, 23), v.astype(np.float32).astype(np.float64))
+    assert np.array_equal(pipeline.round_mantissa(v, 0), v)
+    # ties: 1 + 2^-11 at 10 bits goes to the even 1, 1 + 3 * 2^-11 up to 1 + 2^-9
+    t = np.array([1 + 2.0 ** -11, 1 + 3 * 2.0 ** -11])
+    assert np.array_equal(pipeline.round_mantissa(t, 10), np.array([1.0, 1 + 2.0 ** -9]))
+    g = grid.make_grid()
+    F = synth.histograms(12, seed=31, dtype=np.float64)
+    errs = []
+    for bits in (0, 30, 12):
+        p = pipeline.Params(tau=1e-3, lambda_bits=bits)
+        comp = pipeline.compress(F, g, None, None, p)
+        out = pipeline.decompress(comp, g, None, None, 12, np.float64)
+        dist = np.sqrt(((out - F) ** 2).reshape(12, -1).sum(1))
+        assert np.all(dist <= 1.0001 * pipeline.tau_h(F, p))
+        errs.append(moments.qoi_rel_error(moments.qoi(F, g), moments.qoi(out, g), g).max())
+    assert errs[0] < 1e-11 and errs[0] < errs[1] < errs[2] < 1e-2
