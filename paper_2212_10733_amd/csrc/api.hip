@@ -706,7 +706,18 @@ hcz_status hcz_model_load(hcz_plan* plan, const hcz_model_desc* d, hcz_model** o
       for (int k = 0; k < N; ++k) W1b[(size_t)r * kpad + k] = bf16_rne(W1[(size_t)r * N + k]);
     for (int c = 0; c < N; ++c)
       for (int k = 0; k < Hd; ++k) W4b[(size_t)c * Hd + k] = bf16_rne(W4[(size_t)c * Hd + k]);
-    if ((s = upload(m->allocs, W1b, &M.W1b)) || (s = upload(m->allocs, W4b, &M.W4b))) {
+    // operand order of the encoder: [k-step t][column tile n][lane l][8]: column 32 n + l % 32,
+    // k = 16 t + 8 (l / 32) + e; zero beyond N
+    std::vector<uint16_t> W1m((size_t)(kpad / 16) * 4 * 64 * 8, 0);
+    for (int tt = 0; tt < kpad / 16; ++tt)
+      for (int n = 0; n < 4; ++n)
+        for (int l = 0; l < 64; ++l)
+          for (int e = 0; e < 8; ++e) {
+            const int col = 32 * n + (l & 31), k = 16 * tt + 8 * (l >> 5) + e;
+            W1m[(((size_t)tt * 4 + n) * 64 + l) * 8 + e] = k < N ? bf16_rne(W1[(size_t)col * N + k]) : 0;
+          }
+    if ((s = upload(m->allocs, W1b, &M.W1b)) || (s = upload(m->allocs, W4b, &M.W4b)) ||
+        (s = upload(m->allocs, W1m, &M.W1m))) {
       free_all(m->allocs);
       delete m;
       return s;

@@ -523,6 +523,143 @@ __global__ __launch_bounds__(256, 2) void k_encode_b(ModelDev M, const TIn* hist
   }
 }
 
+// BF16 encoder for FP32 input with contiguous rows.  Each wave owns 32 histograms and all
+// 128 hidden units (four 32-column tiles).  Per K chunk of 32 a load instruction covers 8
+// whole 128-byte row segments (lane l: row 8 i + l / 8, floats 4 (l % 8) .. + 3), the
+// normalised bfloat16 values pass through a wave-private LDS tile into the matrix-core
+// row layout, and the weights come pre-arranged in operand order (W1m: one contiguous
+// 1 KB load per k-step and column tile).  The next chunk's loads are in flight while the
+// current one is multiplied; no workgroup barrier inside the K loop.
+constexpr int kSP = 40;   // LDS pitch (bfloat16) of a staged row of 32 k
+__global__ __launch_bounds__(256, 2) void k_encode_b2(ModelDev M, const float* hist, long long H, long long hs,
+                                                      float* z) {
+  __shared__ __attribute__((aligned(16))) float smem[kTile * kHPitch];   // mu / rsd / staging, then H1
+  __shared__ __attribute__((aligned(16))) float W2t[kHidden * kLatent];
+  const int t = threadIdx.x, w = t >> 6, l = t & 63;
+  const long long h0 = (long long)blockIdx.x * kTile;
+  const int li = l & 31, kh = l >> 5;
+  const int N = M.N, kpad = M.kpad;
+  float* s_mu = smem;
+  float* s_rsd = smem + kpad;
+  __bf16* stg = (__bf16*)(smem + 2 * kpad) + w * 32 * kSP;
+  for (int k = t; k < kpad; k += 256) {
+    s_mu[k] = k < N ? M.mu[k] : 0.0f;
+    s_rsd[k] = k < N ? M.rsd[k] : 0.0f;
+  }
+  for (int q = t; q < kHidden * kLatent; q += 256) {
+    const int o = q / kHidden, c = q % kHidden;
+    W2t[c * kLatent + o] = M.W2[q];
+  }
+  __syncthreads();
+  const int kq = l & 7, rsub = l >> 3;
+  const float* arow[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const long long r = min(h0 + 32 * w + 8 * i + rsub, H - 1);
+    arow[i] = hist + r * hs + 4 * kq;
+  }
+  const bf16x8* Wm = (const bf16x8*)M.W1m + l;
+  f32x16 acc[4];
+#pragma unroll
+  for (int n = 0; n < 4; ++n)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[n][r] = 0.0f;
+  const int nfull = N / kKc, nchunk = kpad / kKc;
+  f32x4u ra[4];
+  bf16x8 rb[2][4];
+  auto aload = [&](int c) {
+    if (c < nfull) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) ra[i] = *(const f32x4u*)(arow[i] + c * kKc);
+    } else {
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) ra[i][e] = (c * kKc + 4 * kq + e < N) ? arow[i][c * kKc + e] : 0.0f;
+    }
+  };
+  auto bload = [&](int c) {
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+      for (int n = 0; n < 4; ++n) rb[s][n] = Wm[((2 * c + s) * 4 + n) * 64];
+  };
+  aload(0);
+  bload(0);
+  for (int c = 0; c < nchunk; ++c) {
+    const f32x4 mu4 = *(const f32x4*)(s_mu + c * kKc + 4 * kq);
+    const f32x4 rs4 = *(const f32x4*)(s_rsd + c * kKc + 4 * kq);
+    // normalise this chunk and stage it as bfloat16 rows
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+      bf16x4 v;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        float fv = ra[i][e];
+        if (!isfinite(fv)) fv = 0.0f;
+        v[e] = (__bf16)((fv - mu4[e]) * rs4[e]);
+      }
+      *(bf16x4*)(stg + (8 * i + rsub) * kSP + 4 * kq) = v;
+    }
+    bf16x8 b8[2][4];
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+      for (int n = 0; n < 4; ++n) b8[s][n] = rb[s][n];
+    if (c + 1 < nchunk) {
+      aload(c + 1);
+      bload(c + 1);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    bf16x8 a8[2];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) a8[s] = *(const bf16x8*)(stg + li * kSP + 16 * s + 8 * kh);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+      for (int n = 0; n < 4; ++n) acc[n] = mfma_bf16(a8[s], b8[s][n], acc[n]);
+  }
+  __syncthreads();
+  // epilogue 1: H1 = relu(acc + b1) into LDS (rows of this wave)
+  float* H1 = smem;
+#pragma unroll
+  for (int n = 0; n < 4; ++n) {
+    const int col = 32 * n + li;
+    const float bias = M.b1[col];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int row = 32 * w + 8 * (r >> 2) + 4 * kh + (r & 3);
+      H1[row * kHPitch + col] = fmaxf(acc[n][r] + bias, 0.0f);
+    }
+  }
+  __syncthreads();
+  const int row = t >> 1, o0 = (t & 1) * 8;
+  float sacc[8];
+#pragma unroll
+  for (int o = 0; o < 8; ++o) sacc[o] = M.b2[o0 + o];
+  for (int c = 0; c < kHidden; ++c) {
+    const float hv = H1[row * kHPitch + c];
+    const f32x4 w0 = *(const f32x4*)&W2t[c * kLatent + o0];
+    const f32x4 w1 = *(const f32x4*)&W2t[c * kLatent + o0 + 4];
+#pragma unroll
+    for (int o = 0; o < 4; ++o) {
+      sacc[o] = fmaf(hv, w0[o], sacc[o]);
+      sacc[o + 4] = fmaf(hv, w1[o], sacc[o + 4]);
+    }
+  }
+  const long long h = h0 + row;
+  if (h < H) {
+#pragma unroll
+    for (int o = 0; o < 8; ++o) z[h * kLatent + o0 + o] = sacc[o];
+  }
+}
+
 // Decoder of the BF16 form: H3 in LDS as bfloat16 rows in natural k order, W4 as
 // bfloat16 [npad][hidden] in device memory; K = 128 in two halves of four instructions,
 // the next half's weights loaded while the current half is multiplied.
@@ -639,7 +776,7 @@ hipError_t launch_encode(const ModelDev& M, const void* hist, int dtype, long lo
   dim3 grid((unsigned)((H + kTile - 1) / kTile)), block(256);
   if (M.bf16) {
     if (dtype == HCZ_F32 && contig)
-      hipLaunchKernelGGL((k_encode_b<float, true>), grid, block, 0, st, M, (const float*)hist, H, hs, rs, n_par, z);
+      hipLaunchKernelGGL(k_encode_b2, grid, block, 0, st, M, (const float*)hist, H, hs, z);
     else if (dtype == HCZ_F32)
       hipLaunchKernelGGL((k_encode_b<float, false>), grid, block, 0, st, M, (const float*)hist, H, hs, rs, n_par, z);
     else
