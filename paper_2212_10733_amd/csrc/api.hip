@@ -716,8 +716,20 @@ hcz_status hcz_model_load(hcz_plan* plan, const hcz_model_desc* d, hcz_model** o
             const int col = 32 * n + (l & 31), k = 16 * tt + 8 * (l >> 5) + e;
             W1m[(((size_t)tt * 4 + n) * 64 + l) * 8 + e] = k < N ? bf16_rne(W1[(size_t)col * N + k]) : 0;
           }
+    // decoder operand order: [64-column block][tile n][k-step t][lane l][8]: column
+    // 64 b + 32 n + l % 32, k = 16 t + 8 (l / 32) + e; zero for columns >= N
+    std::vector<uint16_t> W4m((size_t)(npad / 64) * 2 * 8 * 64 * 8, 0);
+    for (int b = 0; b < npad / 64; ++b)
+      for (int n = 0; n < 2; ++n)
+        for (int tt = 0; tt < 8; ++tt)
+          for (int l = 0; l < 64; ++l)
+            for (int e = 0; e < 8; ++e) {
+              const int col = 64 * b + 32 * n + (l & 31), k = 16 * tt + 8 * (l >> 5) + e;
+              W4m[((((size_t)b * 2 + n) * 8 + tt) * 64 + l) * 8 + e] =
+                  col < N ? bf16_rne(W4[(size_t)col * Hd + k]) : 0;
+            }
     if ((s = upload(m->allocs, W1b, &M.W1b)) || (s = upload(m->allocs, W4b, &M.W4b)) ||
-        (s = upload(m->allocs, W1m, &M.W1m))) {
+        (s = upload(m->allocs, W1m, &M.W1m)) || (s = upload(m->allocs, W4m, &M.W4m))) {
       free_all(m->allocs);
       delete m;
       return s;

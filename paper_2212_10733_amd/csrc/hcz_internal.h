@@ -81,6 +81,7 @@ struct ModelDev {
   const uint16_t* W1b;             // [hidden][kpad] bfloat16 of W1, zero padded
   const uint16_t* W4b;             // [npad][hidden] bfloat16 of W4, rows >= N zero
   const uint16_t* W1m;             // bfloat16 of W1 in matrix-core operand order (see k_encode_b2)
+  const uint16_t* W4m;             // bfloat16 of W4 in matrix-core operand order (see k_decode_b2)
   // convolutional model (39 x 39 grids), arch == HCZ_ARCH_CONV
   int arch;
   const float* c1w;                // [32][9]

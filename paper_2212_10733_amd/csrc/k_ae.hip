@@ -565,17 +565,18 @@ __global__ __launch_bounds__(256, 2) void k_encode_b2(ModelDev M, const float* h
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc[n][r] = 0.0f;
   const int nfull = N / kKc, nchunk = kpad / kKc;
-  f32x4u ra[4];
+  // two chunks of input in flight: ra holds chunk c, rn chunk c + 1
+  f32x4u ra[4], rn[4];
   bf16x8 rb[2][4];
-  auto aload = [&](int c) {
+  auto aload = [&](int c, f32x4u (&dst)[4]) {
     if (c < nfull) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i) ra[i] = *(const f32x4u*)(arow[i] + c * kKc);
+      for (int i = 0; i < 4; ++i) dst[i] = *(const f32x4u*)(arow[i] + c * kKc);
     } else {
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int e = 0; e < 4; ++e) ra[i][e] = (c * kKc + 4 * kq + e < N) ? arow[i][c * kKc + e] : 0.0f;
+        for (int e = 0; e < 4; ++e) dst[i][e] = (c * kKc + 4 * kq + e < N) ? arow[i][c * kKc + e] : 0.0f;
     }
   };
   auto bload = [&](int c) {
@@ -584,7 +585,8 @@ __global__ __launch_bounds__(256, 2) void k_encode_b2(ModelDev M, const float* h
 #pragma unroll
       for (int n = 0; n < 4; ++n) rb[s][n] = Wm[((2 * c + s) * 4 + n) * 64];
   };
-  aload(0);
+  aload(0, ra);
+  if (nchunk > 1) aload(1, rn);
   bload(0);
   for (int c = 0; c < nchunk; ++c) {
     const f32x4 mu4 = *(const f32x4*)(s_mu + c * kKc + 4 * kq);
@@ -607,10 +609,10 @@ __global__ __launch_bounds__(256, 2) void k_encode_b2(ModelDev M, const float* h
     for (int s = 0; s < 2; ++s)
 #pragma unroll
       for (int n = 0; n < 4; ++n) b8[s][n] = rb[s][n];
-    if (c + 1 < nchunk) {
-      aload(c + 1);
-      bload(c + 1);
-    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) ra[i] = rn[i];
+    if (c + 2 < nchunk) aload(c + 2, rn);
+    if (c + 1 < nchunk) bload(c + 1);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -750,6 +752,109 @@ __global__ __launch_bounds__(256, 2) void k_decode_b(ModelDev M, const uint8_t* 
   }
 }
 
+// BF16 decoder with row-contiguous stores: each wave owns 32 histograms and keeps their
+// eight bfloat16 h3 operands in registers; per block of 64 output columns the weights come
+// pre-arranged in operand order (W4m, 1 KB per load instruction, the next block in flight)
+// and the results pass through a wave-private LDS tile so that each store instruction
+// writes four 256-byte row segments.
+constexpr int kOP = 68;   // LDS pitch (floats) of the output tile
+__global__ __launch_bounds__(256, 2) void k_decode_b2(ModelDev M, const uint8_t* codes, const float* centroids,
+                                                      int kcb, long long H, float* fhat) {
+  __shared__ __attribute__((aligned(16))) __bf16 H3[kTile * kBPitch];
+  __shared__ __attribute__((aligned(16))) float outs[4 * 32 * kOP];
+  __shared__ float Zh[kTile * kLatent];
+  const int t = threadIdx.x, w = t >> 6, l = t & 63;
+  const long long h0 = (long long)blockIdx.x * kTile;
+  const int li = l & 31, kh = l >> 5;
+  const int N = M.N;
+  for (int q = t; q < kTile * kLatent; q += 256) {
+    const int row = q / kLatent, d = q % kLatent;
+    const long long h = h0 + row;
+    Zh[q] = (h < H) ? centroids[d * kcb + min((int)codes[h * kLatent + d], kcb - 1)] : 0.0f;
+  }
+  __syncthreads();
+  {
+    const int c = t & 127;
+    float w3[kLatent];
+#pragma unroll
+    for (int d = 0; d < kLatent; ++d) w3[d] = M.W3[c * kLatent + d];
+    const float b3 = M.b3[c];
+    for (int row = t >> 7; row < kTile; row += 2) {
+      float s = b3;
+#pragma unroll
+      for (int d = 0; d < kLatent; ++d) s = fmaf(Zh[row * kLatent + d], w3[d], s);
+      H3[row * kBPitch + c] = (__bf16)fmaxf(s, 0.0f);
+    }
+  }
+  __syncthreads();
+  bf16x8 a8[8];
+#pragma unroll
+  for (int s = 0; s < 8; ++s) a8[s] = *(const bf16x8*)&H3[(32 * w + li) * kBPitch + 16 * s + 8 * kh];
+  float* ot = outs + w * 32 * kOP;
+  const bf16x8* Wm = (const bf16x8*)M.W4m + l;
+  const int nblk = M.npad / 64;
+  bf16x8 bv[2][8], bn[2][8];
+  auto bload = [&](int nb, bf16x8 (&B)[2][8]) {
+#pragma unroll
+    for (int n = 0; n < 2; ++n)
+#pragma unroll
+      for (int s = 0; s < 8; ++s) B[n][s] = Wm[((nb * 2 + n) * 8 + s) * 64];
+  };
+  bload(0, bv);
+  // store mapping: lane -> row 4 i + l / 16 (i = 0..7), columns 4 (l % 16) .. + 3 of the block
+  const int srow = l >> 4, scol = 4 * (l & 15);
+  for (int nb = 0; nb < nblk; ++nb) {
+    if (nb + 1 < nblk) bload(nb + 1, bn);
+    f32x16 acc[2];
+#pragma unroll
+    for (int n = 0; n < 2; ++n)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[n][r] = 0.0f;
+#pragma unroll
+    for (int s = 0; s < 8; ++s)
+#pragma unroll
+      for (int n = 0; n < 2; ++n) acc[n] = mfma_bf16(a8[s], bv[n][s], acc[n]);
+#pragma unroll
+    for (int n = 0; n < 2; ++n) {
+      const int col = 64 * nb + 32 * n + li;
+      const int cc = min(col, N - 1);
+      const float b4 = M.b4[cc], sd = M.sd[cc], mu = M.mu[cc];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = 8 * (r >> 2) + 4 * kh + (r & 3);
+        ot[row * kOP + 32 * n + li] = fmaf(sd, acc[n][r] + b4, mu);
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int c0 = 64 * nb + scol;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int row = 4 * i + srow;
+      const long long h = h0 + 32 * w + row;
+      const f32x4 v = *(const f32x4*)(ot + row * kOP + scol);
+      if (h < H) {
+        float* dst = fhat + h * N + c0;
+        if (c0 + 3 < N) {
+          *(f32x4u*)dst = v;
+        } else {
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            if (c0 + e < N) dst[e] = v[e];
+        }
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+    for (int n = 0; n < 2; ++n)
+#pragma unroll
+      for (int s = 0; s < 8; ++s) bv[n][s] = bn[n][s];
+  }
+}
+
 // code = #{c : (C_c + C_{c+1}) / 2 < z} with the midpoints in FP64: a lower bound search.
 __global__ __launch_bounds__(256) void k_quantize(const float* z, long long n, int latent,
                                                   const float* centroids, int kcb, uint8_t* codes) {
@@ -798,7 +903,7 @@ hipError_t launch_decode(const ModelDev& M, const uint8_t* codes, const float* c
   if (H <= 0) return hipSuccess;
   if (M.arch == HCZ_ARCH_CONV) return launch_conv_decode(M, codes, centroids, bits, H, fhat, st);
   dim3 grid((unsigned)((H + kTile - 1) / kTile)), block(256);
-  if (M.bf16) hipLaunchKernelGGL(k_decode_b, grid, block, 0, st, M, codes, centroids, 1 << bits, H, fhat);
+  if (M.bf16) hipLaunchKernelGGL(k_decode_b2, grid, block, 0, st, M, codes, centroids, 1 << bits, H, fhat);
   else hipLaunchKernelGGL(k_decode, grid, block, 0, st, M, codes, centroids, 1 << bits, H, fhat);
   return hipGetLastError();
 }
