@@ -101,3 +101,69 @@ def decode_bf16(Zh: np.ndarray, W: dict, mu, sd) -> np.ndarray:
     h3 = relu(conv_t2d_s2(hd, bf16(W["t1w"]).astype(np.float64), W["t1b"], 20))
     y = conv_t2d_s2(h3, np.asarray(W["t2w"], np.float64), W["t2b"], 39).reshape(H, 1521)
     return np.asarray(sd, np.float64) * y + np.asarray(mu, np.float64)
+
+
+# ---- training (FP64): the FP64 model throughout (no bfloat16), MSE loss (Eq. 5) -------------
+
+def forward_train(X: np.ndarray, W: dict) -> dict:
+    """Forward pass of the FP64 model on z-scored rows X (B, 1521), keeping what the
+    backward pass needs."""
+    B = X.shape[0]
+    x = np.asarray(X, np.float64).reshape(B, 1, 39, 39)
+    w = {k: np.asarray(v, np.float64) for k, v in W.items()}
+    a1 = conv2d_s2(x, w["c1w"], w["c1b"])
+    h1 = relu(a1)
+    a2 = conv2d_s2(h1, w["c2w"], w["c2b"])
+    h2 = relu(a2).reshape(B, 6400)
+    z = h2 @ w["fw"].T + w["fb"]
+    a4 = z @ w["dw"].T + w["db"]
+    h4 = relu(a4).reshape(B, 64, 10, 10)
+    a5 = conv_t2d_s2(h4, w["t1w"], w["t1b"], 20)
+    h5 = relu(a5)
+    xh = conv_t2d_s2(h5, w["t2w"], w["t2b"], 39).reshape(B, 1521)
+    return dict(x=x, a1=a1, h1=h1, a2=a2, h2=h2, z=z, a4=a4, h4=h4, a5=a5, h5=h5, xh=xh)
+
+
+def _wgrad(coarse: np.ndarray, fine: np.ndarray) -> np.ndarray:
+    """G[cc, cf, ky, kx] = sum_b sum_(p) coarse[b, cc, py, px] fine[b, cf, 2py-1+ky, 2px-1+kx]
+    (zero outside the fine grid): the weight gradient of a stride-2, padding-1 layer."""
+    B, Cc, m, _ = coarse.shape
+    Cf, n = fine.shape[1], fine.shape[2]
+    fp = np.zeros((B, Cf, max(n + 2, 2 * m + 1), max(n + 2, 2 * m + 1)))
+    fp[:, :, 1:n + 1, 1:n + 1] = fine
+    G = np.zeros((Cc, Cf, 3, 3))
+    for ky in range(3):
+        for kx in range(3):
+            patch = fp[:, :, ky:ky + 2 * m - 1:2, kx:kx + 2 * m - 1:2]
+            G[:, :, ky, kx] = np.einsum('bcij,bfij->cf', coarse, patch, optimize=True)
+    return G
+
+
+def backward(cache: dict, W: dict, dxh: np.ndarray, dz: np.ndarray | None = None) -> dict:
+    """Gradients of every parameter for dL/dxhat = dxh (B, 1521) (plus dL/dz = dz)."""
+    B = dxh.shape[0]
+    w = {k: np.asarray(v, np.float64) for k, v in W.items()}
+    g = {}
+    d = np.asarray(dxh, np.float64).reshape(B, 1, 39, 39)
+    g["t2w"] = _wgrad(cache["h5"], d)
+    g["t2b"] = d.sum(axis=(0, 2, 3))
+    d5 = conv2d_s2(d, w["t2w"], np.zeros(32)) * (cache["a5"] > 0)
+    g["t1w"] = _wgrad(cache["h4"], d5)
+    g["t1b"] = d5.sum(axis=(0, 2, 3))
+    d4 = conv2d_s2(d5, w["t1w"], np.zeros(64)).reshape(B, 6400) * (cache["a4"] > 0)
+    g["dw"] = d4.T @ cache["z"]
+    g["db"] = d4.sum(axis=0)
+    dzt = d4 @ w["dw"] + (0.0 if dz is None else np.asarray(dz, np.float64))
+    g["fw"] = dzt.T @ cache["h2"]
+    g["fb"] = dzt.sum(axis=0)
+    d2 = (dzt @ w["fw"]).reshape(B, 64, 10, 10) * (cache["a2"] > 0)
+    g["c2w"] = _wgrad(d2, cache["h1"])
+    g["c2b"] = d2.sum(axis=(0, 2, 3))
+    d1 = conv_t2d_s2(d2, w["c2w"], np.zeros(32), 20) * (cache["a1"] > 0)
+    g["c1w"] = _wgrad(d1, cache["x"])
+    g["c1b"] = d1.sum(axis=(0, 2, 3))
+    return g
+
+
+def loss(X: np.ndarray, W: dict) -> float:
+    return float(np.mean((forward_train(X, W)["xh"] - np.asarray(X, np.float64)) ** 2))

@@ -97,3 +97,43 @@ def test_bf16_form_is_close_to_the_fp64_model():
     f64 = sd32.astype(np.float64) * y + mu32
     rel = np.abs(fh - f64).max() / np.abs(f64 - mu32).max()
     assert 1e-6 < rel < 3e-2, rel
+
+
+def test_training_gradients_match_torch_autograd():
+    """Forward and backward of the FP64 convolutional model against torch autograd (CPU,
+    FP64) on the same weights, with an extra dL/dz; and central differences on samples."""
+    rng = np.random.default_rng(53)
+    W = synth.conv_ae_weights(3)
+    for k in ("c1b", "c2b", "fb", "db", "t1b", "t2b"):
+        W[k] = rng.normal(0, 0.05, W[k].shape).astype(np.float32)
+    B = 5
+    X = rng.standard_normal((B, 1521))
+    cache = conv.forward_train(X, W)
+    dxh = 2 * (cache["xh"] - X) / X.size
+    dz = rng.standard_normal((B, 16)) * 1e-3
+    g = conv.backward(cache, W, dxh, dz)
+    t = {k: torch.tensor(np.asarray(v, np.float64), requires_grad=True) for k, v in W.items()}
+    xt = t64(X.reshape(B, 1, 39, 39))
+    h1 = torch.relu(Fn.conv2d(xt, t["c1w"], t["c1b"], stride=2, padding=1))
+    h2 = torch.relu(Fn.conv2d(h1, t["c2w"], t["c2b"], stride=2, padding=1)).reshape(B, -1)
+    zt = h2 @ t["fw"].T + t["fb"]
+    h4 = torch.relu(zt @ t["dw"].T + t["db"]).reshape(B, 64, 10, 10)
+    h5 = torch.relu(Fn.conv_transpose2d(h4, t["t1w"], t["t1b"], stride=2, padding=1, output_padding=1))
+    xht = Fn.conv_transpose2d(h5, t["t2w"], t["t2b"], stride=2, padding=1).reshape(B, -1)
+    assert np.allclose(cache["xh"], xht.detach().numpy(), rtol=1e-12, atol=1e-12)
+    (((xht - t64(X)) ** 2).mean() + (zt * t64(dz)).sum()).backward()
+    for k in W:
+        ref = t[k].grad.numpy()
+        assert np.allclose(g[k], ref, rtol=1e-9, atol=1e-12 * (np.abs(ref).max() + 1e-30)), k
+    # central differences of the FP64 loss (without the dz term) at a few coordinates
+    g0 = conv.backward(cache, W, dxh)
+    W64 = {k: v.astype(np.float64) for k, v in W.items()}
+    for k in ("c1w", "c2w", "fw", "t1w", "t2b"):
+        idx = tuple(rng.integers(0, s) for s in W64[k].shape)
+        Wp = {kk: vv.copy() for kk, vv in W64.items()}
+        Wm = {kk: vv.copy() for kk, vv in W64.items()}
+        hstep = 1e-6
+        Wp[k][idx] += hstep
+        Wm[k][idx] -= hstep
+        fd = (conv.loss(X, Wp) - conv.loss(X, Wm)) / (2 * hstep)
+        assert abs(g0[k][idx] - fd) <= 1e-4 * max(abs(fd), 1e-8) + 1e-11, (k, g0[k][idx], fd)   # ReLU kinks
