@@ -399,6 +399,18 @@ hcz_status hcz_ae_forward(int32_t N, const float* params, const float* x, int64_
 hcz_status hcz_ae_backward(int32_t N, const float* params, const float* x, int64_t B,
                            const float* dz, const float* dxhat, void* saved, size_t saved_bytes,
                            float* grad, float* dx, hcz_stream_t stream);
+/* Convolutional model (39 x 39; the parameter blob in the hcz_model_desc order, 248,785
+ * floats), FP32 throughout: forward writes z [B][16] and xhat [B][1521] for z-scored
+ * x [B][1521] and keeps the pre-activations in `saved`; backward accumulates nothing: it
+ * writes grad [248,785] (dL/dparams for dL/dxhat = dxhat and, if dz is not NULL, an extra
+ * dL/dz) from the same saved buffer.  Sizes: hcz_conv_ae_saved_bytes. */
+hcz_status hcz_conv_ae_param_count(int64_t* count);
+hcz_status hcz_conv_ae_saved_bytes(int64_t B, size_t* bytes);
+hcz_status hcz_conv_ae_forward(const float* params, const float* x, int64_t B, float* z, float* xhat,
+                               void* saved, size_t saved_bytes, hcz_stream_t stream);
+hcz_status hcz_conv_ae_backward(const float* params, const float* x, int64_t B, const float* dz,
+                                const float* dxhat, void* saved, size_t saved_bytes, float* grad,
+                                hcz_stream_t stream);
 /* MSE of Eq. 5: *loss (device) = mean((xhat - x)^2) over n values; dxhat (or NULL) =
  * 2 (xhat - x) / n.  Workspace: hcz_mse_workspace bytes. */
 hcz_status hcz_mse_workspace(size_t* bytes);

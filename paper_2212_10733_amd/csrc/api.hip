@@ -1096,6 +1096,110 @@ hcz_status hcz_ae_forward(int32_t N, const float* params, const float* x, int64_
   return HCZ_OK;
 }
 
+// ---- convolutional model training ----------------------------------------------------------
+namespace {
+struct ConvOff {
+  static constexpr size_t c1w = 0, c1b = 288, c2w = 320, c2b = 18752, fw = 18816, fb = 121216, dw = 121232,
+                          db = 223632, t1w = 230032, t1b = 248464, t2w = 248496, t2b = 248784, total = 248785;
+};
+// saved floats per sample: a1 12800 | a2 6400 | h2 6400 | z 16 | a4 6400 | a5 12800 | T1 12800 | T2 6400 | dz 16
+constexpr size_t kConvSaved = 12800 + 6400 + 6400 + 16 + 6400 + 12800 + 12800 + 6400 + 16;
+struct ConvSaved {
+  float *a1, *a2, *h2, *z, *a4, *a5, *T1, *T2, *dz;
+  ConvSaved(void* base, int64_t B) {
+    float* p = (float*)base;
+    a1 = p; p += (size_t)B * 12800;
+    a2 = p; p += (size_t)B * 6400;
+    h2 = p; p += (size_t)B * 6400;
+    z = p; p += (size_t)B * 16;
+    a4 = p; p += (size_t)B * 6400;
+    a5 = p; p += (size_t)B * 12800;
+    T1 = p; p += (size_t)B * 12800;
+    T2 = p; p += (size_t)B * 6400;
+    dz = p;
+  }
+};
+}  // namespace
+
+hcz_status hcz_conv_ae_param_count(int64_t* count) {
+  if (!count) return fail(HCZ_EINVAL, "NULL argument");
+  *count = (int64_t)ConvOff::total;
+  return HCZ_OK;
+}
+
+hcz_status hcz_conv_ae_saved_bytes(int64_t B, size_t* bytes) {
+  if (!bytes || B < 0) return fail(HCZ_EINVAL, "bad argument");
+  *bytes = std::max<size_t>((size_t)B * kConvSaved * sizeof(float), 256);
+  return HCZ_OK;
+}
+
+hcz_status hcz_conv_ae_forward(const float* params, const float* x, int64_t B, float* z, float* xhat, void* saved,
+                               size_t saved_bytes, hcz_stream_t stream) {
+  if (B < 0) return fail(HCZ_EINVAL, "bad size");
+  if (B == 0) return HCZ_OK;
+  if (!params || !x || !z || !xhat || !saved) return fail(HCZ_EINVAL, "NULL buffer");
+  if (saved_bytes < (size_t)B * kConvSaved * sizeof(float)) return fail(HCZ_EWORKSPACE, "saved buffer too small");
+  hipStream_t st = (hipStream_t)stream;
+  ConvSaved S(saved, B);
+  const float* P = params;
+  using O = ConvOff;
+  HCZ_TRY(launch_cv_fwd(x, 1, 39, 0, P + O::c1w, P + O::c1b, S.a1, 32, 20, B, st), "conv1");
+  HCZ_TRY(launch_cv_fwd(S.a1, 32, 20, 1, P + O::c2w, P + O::c2b, S.a2, 64, 10, B, st), "conv2");
+  HCZ_TRY(launch_relu_copy(S.a2, S.h2, (long long)B * 6400, st), "relu");
+  HCZ_TRY(launch_gemm(S.h2, 6400, 1, P + O::fw, 1, 6400, S.z, 16, B, 16, 6400, 1.f, 0.f, P + O::fb, 0, st), "fc");
+  HCZ_TRY(hipMemcpyAsync(z, S.z, (size_t)B * 16 * sizeof(float), hipMemcpyDeviceToDevice, st), "copy z");
+  HCZ_TRY(launch_gemm(S.z, 16, 1, P + O::dw, 1, 16, S.a4, 6400, B, 6400, 16, 1.f, 0.f, P + O::db, 0, st), "dfc");
+  HCZ_TRY(launch_cvt_fwd(S.a4, 64, 10, 1, P + O::t1w, P + O::t1b, S.a5, 32, 20, B, st), "convT1");
+  HCZ_TRY(launch_cvt_fwd(S.a5, 32, 20, 1, P + O::t2w, P + O::t2b, xhat, 1, 39, B, st), "convT2");
+  return HCZ_OK;
+}
+
+hcz_status hcz_conv_ae_backward(const float* params, const float* x, int64_t B, const float* dz_in,
+                                const float* dxh, void* saved, size_t saved_bytes, float* grad, hcz_stream_t stream) {
+  if (B < 0) return fail(HCZ_EINVAL, "bad size");
+  if (!params || !grad) return fail(HCZ_EINVAL, "NULL buffer");
+  if (B > 0 && (!x || !dxh || !saved)) return fail(HCZ_EINVAL, "NULL buffer");
+  if (saved_bytes < (size_t)B * kConvSaved * sizeof(float)) return fail(HCZ_EWORKSPACE, "saved buffer too small");
+  hipStream_t st = (hipStream_t)stream;
+  ConvSaved S(saved, B);
+  const float* P = params;
+  float* G = grad;
+  using O = ConvOff;
+  // transposed conv2 (32 -> 1)
+  HCZ_TRY(launch_cv_fwd(dxh, 1, 39, 0, P + O::t2w, nullptr, S.T1, 32, 20, B, st), "dh5");
+  HCZ_TRY(launch_cv_wgrad(S.a5, 32, 20, 1, dxh, 1, 39, 0, B, G + O::t2w, st), "dt2w");
+  HCZ_TRY(launch_chsum(dxh, 1, 1521, B, G + O::t2b, st), "dt2b");
+  HCZ_TRY(launch_relu_mask(S.T1, S.a5, (long long)B * 12800, st), "relu mask");
+  // transposed conv1 (64 -> 32)
+  HCZ_TRY(launch_cv_wgrad(S.a4, 64, 10, 1, S.T1, 32, 20, 0, B, G + O::t1w, st), "dt1w");
+  HCZ_TRY(launch_chsum(S.T1, 32, 400, B, G + O::t1b, st), "dt1b");
+  HCZ_TRY(launch_cv_fwd(S.T1, 32, 20, 0, P + O::t1w, nullptr, S.T2, 64, 10, B, st), "dh4");
+  HCZ_TRY(launch_relu_mask(S.T2, S.a4, (long long)B * 6400, st), "relu mask");
+  // decoder dense layer (16 -> 6400)
+  HCZ_TRY(launch_gemm(S.T2, 1, 6400, S.z, 16, 1, G + O::dw, 16, 6400, 16, B, 1.f, 0.f, nullptr, 0, st), "ddw");
+  HCZ_TRY(launch_colsum(S.T2, B, 6400, G + O::db, st), "ddb");
+  if (dz_in) {
+    HCZ_TRY(hipMemcpyAsync(S.dz, dz_in, (size_t)B * 16 * sizeof(float), hipMemcpyDeviceToDevice, st), "copy dz");
+    HCZ_TRY(launch_gemm(S.T2, 6400, 1, P + O::dw, 16, 1, S.dz, 16, B, 16, 6400, 1.f, 1.f, nullptr, 0, st), "dz");
+  } else {
+    HCZ_TRY(launch_gemm(S.T2, 6400, 1, P + O::dw, 16, 1, S.dz, 16, B, 16, 6400, 1.f, 0.f, nullptr, 0, st), "dz");
+  }
+  // encoder dense layer (6400 -> 16)
+  HCZ_TRY(launch_gemm(S.dz, 1, 16, S.h2, 6400, 1, G + O::fw, 6400, 16, 6400, B, 1.f, 0.f, nullptr, 0, st), "dfw");
+  HCZ_TRY(launch_colsum(S.dz, B, 16, G + O::fb, st), "dfb");
+  HCZ_TRY(launch_gemm(S.dz, 16, 1, P + O::fw, 6400, 1, S.T2, 6400, B, 6400, 16, 1.f, 0.f, nullptr, 0, st), "dh2");
+  HCZ_TRY(launch_relu_mask(S.T2, S.a2, (long long)B * 6400, st), "relu mask");
+  // conv2 (32 -> 64)
+  HCZ_TRY(launch_cv_wgrad(S.T2, 64, 10, 0, S.a1, 32, 20, 1, B, G + O::c2w, st), "dc2w");
+  HCZ_TRY(launch_chsum(S.T2, 64, 100, B, G + O::c2b, st), "dc2b");
+  HCZ_TRY(launch_cvt_fwd(S.T2, 64, 10, 0, P + O::c2w, nullptr, S.T1, 32, 20, B, st), "dh1");
+  HCZ_TRY(launch_relu_mask(S.T1, S.a1, (long long)B * 12800, st), "relu mask");
+  // conv1 (1 -> 32)
+  HCZ_TRY(launch_cv_wgrad(S.T1, 32, 20, 0, x, 1, 39, 0, B, G + O::c1w, st), "dc1w");
+  HCZ_TRY(launch_chsum(S.T1, 32, 400, B, G + O::c1b, st), "dc1b");
+  return HCZ_OK;
+}
+
 hcz_status hcz_ae_backward(int32_t N, const float* params, const float* x, int64_t B,
                            const float* dz_in, const float* dxh, void* saved, size_t saved_bytes,
                            float* grad, float* dx, hcz_stream_t stream) {

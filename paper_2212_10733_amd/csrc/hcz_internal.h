@@ -362,6 +362,14 @@ hipError_t launch_conv_encode(const ModelDev& M, const void* hist, int dtype, lo
                               long long rs, float* z, hipStream_t st);
 hipError_t launch_conv_decode(const ModelDev& M, const uint8_t* codes, const float* centroids, int bits,
                               long long H, float* fhat, hipStream_t st);
+hipError_t launch_cv_fwd(const float* in, int C, int n, int relu_in, const float* w, const float* bias, float* out,
+                         int O, int m, long long B, hipStream_t st);
+hipError_t launch_cvt_fwd(const float* in, int C, int n, int relu_in, const float* w, const float* bias, float* out,
+                          int O, int m, long long B, hipStream_t st);
+hipError_t launch_cv_wgrad(const float* coarse, int Cc, int m, int relu_c, const float* fine, int Cf, int n,
+                           int relu_f, long long B, float* G, hipStream_t st);
+hipError_t launch_chsum(const float* d, int C, int P, long long B, float* out, hipStream_t st);
+hipError_t launch_relu_copy(const float* a, float* h, long long n, hipStream_t st);
 hipError_t launch_quantize(const float* z, long long n, int latent, const float* centroids,
                            int bits, uint8_t* codes, hipStream_t st);
 size_t codebook_ws_bytes(long long n, int latent, long long every);

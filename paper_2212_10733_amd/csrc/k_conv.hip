@@ -353,4 +353,163 @@ hipError_t launch_conv_decode(const ModelDev& M, const uint8_t* codes, const flo
   return hipSuccess;
 }
 
+
+// ---- training of the convolutional model (FP32, Section III Stage 2, Eq. 5) ------------------
+// Generic batched layers, one thread per output value, FP32 fused multiply-adds; the
+// training path favours plainness over speed.  Layout [b][channel][y][x].
+
+// 3x3 convolution, stride 2, padding 1: out[b][o][oy][ox] = bias[o] + sum over c and the
+// in-range taps of in'[b][c][2oy-1+ky][2ox-1+kx] w[o][c][ky][kx]; in' = relu(in) if relu_in.
+__global__ __launch_bounds__(256) void k_cv_fwd(const float* in, int C, int n, int relu_in, const float* w,
+                                                const float* bias, float* out, int O, int m, long long B) {
+  const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (q >= B * O * m * m) return;
+  const int ox = (int)(q % m), oy = (int)((q / m) % m), o = (int)((q / ((long long)m * m)) % O);
+  const long long b = q / ((long long)m * m * O);
+  float s = bias ? bias[o] : 0.0f;
+  for (int c = 0; c < C; ++c) {
+    const float* ip = in + ((b * C + c) * n) * n;
+    const float* wp = w + (o * C + c) * 9;
+    for (int ky = 0; ky < 3; ++ky) {
+      const int iy = 2 * oy - 1 + ky;
+      if (iy < 0 || iy >= n) continue;
+      for (int kx = 0; kx < 3; ++kx) {
+        const int ix = 2 * ox - 1 + kx;
+        if (ix < 0 || ix >= n) continue;
+        float v = ip[iy * n + ix];
+        if (relu_in) v = fmaxf(v, 0.0f);
+        s = fmaf(v, wp[ky * 3 + kx], s);
+      }
+    }
+  }
+  out[q] = s;
+}
+
+// 3x3 transposed convolution, stride 2, padding 1, output m x m: out[b][o][oy][ox] =
+// bias[o] + sum over c and the taps with oy = 2 iy - 1 + ky (iy in range) of in'[b][c][iy][ix] w[c][o][ky][kx].
+__global__ __launch_bounds__(256) void k_cvt_fwd(const float* in, int C, int n, int relu_in, const float* w,
+                                                 const float* bias, float* out, int O, int m, long long B) {
+  const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (q >= B * O * m * m) return;
+  const int ox = (int)(q % m), oy = (int)((q / m) % m), o = (int)((q / ((long long)m * m)) % O);
+  const long long b = q / ((long long)m * m * O);
+  float s = bias ? bias[o] : 0.0f;
+  for (int c = 0; c < C; ++c) {
+    const float* ip = in + ((b * C + c) * n) * n;
+    const float* wp = w + (c * O + o) * 9;
+    for (int ky = 0; ky < 3; ++ky) {
+      const int ny = oy + 1 - ky;
+      if (ny < 0 || (ny & 1) || (ny >> 1) >= n) continue;
+      for (int kx = 0; kx < 3; ++kx) {
+        const int nx = ox + 1 - kx;
+        if (nx < 0 || (nx & 1) || (nx >> 1) >= n) continue;
+        float v = ip[(ny >> 1) * n + (nx >> 1)];
+        if (relu_in) v = fmaxf(v, 0.0f);
+        s = fmaf(v, wp[ky * 3 + kx], s);
+      }
+    }
+  }
+  out[q] = s;
+}
+
+// Weight gradient of a stride-2 3x3 layer: G[cc][cf][ky][kx] = sum over b and coarse cells
+// (py, px) of coarse'[b][cc][py][px] fine'[b][cf][2py-1+ky][2px-1+kx] (in-range cells).
+// For a convolution coarse = dL/d(output), fine = its input; for a transposed one coarse =
+// its input, fine = dL/d(output).  One workgroup per (cc, cf), FP64 partial sums.
+__global__ __launch_bounds__(256) void k_cv_wgrad(const float* coarse, int Cc, int m, int relu_c, const float* fine,
+                                                  int Cf, int n, int relu_f, long long B, float* G) {
+  __shared__ double red[9][256];
+  const int cc = blockIdx.x / Cf, cf = blockIdx.x % Cf, t = threadIdx.x;
+  double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  const long long tot = B * m * m;
+  for (long long q = t; q < tot; q += 256) {
+    const int px = (int)(q % m), py = (int)((q / m) % m);
+    const long long b = q / ((long long)m * m);
+    float cv = coarse[((b * Cc + cc) * m + py) * m + px];
+    if (relu_c) cv = fmaxf(cv, 0.0f);
+    if (cv == 0.0f) continue;
+    const float* fp = fine + ((b * Cf + cf) * n) * n;
+#pragma unroll
+    for (int ky = 0; ky < 3; ++ky) {
+      const int iy = 2 * py - 1 + ky;
+      if (iy < 0 || iy >= n) continue;
+#pragma unroll
+      for (int kx = 0; kx < 3; ++kx) {
+        const int ix = 2 * px - 1 + kx;
+        if (ix < 0 || ix >= n) continue;
+        float fv = fp[iy * n + ix];
+        if (relu_f) fv = fmaxf(fv, 0.0f);
+        acc[ky * 3 + kx] += (double)cv * (double)fv;
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 9; ++k) red[k][t] = acc[k];
+  __syncthreads();
+  for (int wdt = 128; wdt > 0; wdt >>= 1) {
+    if (t < wdt)
+#pragma unroll
+      for (int k = 0; k < 9; ++k) red[k][t] += red[k][t + wdt];
+    __syncthreads();
+  }
+  if (t < 9) G[(cc * Cf + cf) * 9 + t] = (float)red[t][0];
+}
+
+// out[c] = sum over b and p of d[b][c][p] (P cells per channel), FP64; one workgroup per c.
+__global__ __launch_bounds__(256) void k_chsum(const float* d, int C, int P, long long B, float* out) {
+  __shared__ double red[256];
+  const int c = blockIdx.x, t = threadIdx.x;
+  double s = 0.0;
+  for (long long q = t; q < B * P; q += 256) {
+    const long long b = q / P;
+    s += (double)d[(b * C + c) * P + q % P];
+  }
+  red[t] = s;
+  __syncthreads();
+  for (int wdt = 128; wdt > 0; wdt >>= 1) {
+    if (t < wdt) red[t] += red[t + wdt];
+    __syncthreads();
+  }
+  if (t == 0) out[c] = (float)red[0];
+}
+
+__global__ __launch_bounds__(256) void k_relu_copy(const float* a, float* h, long long n) {
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) h[i] = fmaxf(a[i], 0.0f);
+}
+
+static unsigned nblk(long long n) { return (unsigned)((n + 255) / 256); }
+
+hipError_t launch_cv_fwd(const float* in, int C, int n, int relu_in, const float* w, const float* bias, float* out,
+                         int O, int m, long long B, hipStream_t st) {
+  if (B <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_cv_fwd, dim3(nblk(B * O * m * m)), dim3(256), 0, st, in, C, n, relu_in, w, bias, out, O, m, B);
+  return hipGetLastError();
+}
+
+hipError_t launch_cvt_fwd(const float* in, int C, int n, int relu_in, const float* w, const float* bias, float* out,
+                          int O, int m, long long B, hipStream_t st) {
+  if (B <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_cvt_fwd, dim3(nblk(B * O * m * m)), dim3(256), 0, st, in, C, n, relu_in, w, bias, out, O, m, B);
+  return hipGetLastError();
+}
+
+hipError_t launch_cv_wgrad(const float* coarse, int Cc, int m, int relu_c, const float* fine, int Cf, int n,
+                           int relu_f, long long B, float* G, hipStream_t st) {
+  hipLaunchKernelGGL(k_cv_wgrad, dim3((unsigned)(Cc * Cf)), dim3(256), 0, st, coarse, Cc, m, relu_c, fine, Cf, n,
+                     relu_f, B, G);
+  return hipGetLastError();
+}
+
+hipError_t launch_chsum(const float* d, int C, int P, long long B, float* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_chsum, dim3((unsigned)C), dim3(256), 0, st, d, C, P, B, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_relu_copy(const float* a, float* h, long long n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_relu_copy, dim3(nblk(n)), dim3(256), 0, st, a, h, n);
+  return hipGetLastError();
+}
+
 }  // namespace hcz

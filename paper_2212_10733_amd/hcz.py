@@ -145,6 +145,10 @@ def _load() -> C.CDLL:
         "hcz_segment_max": [vp, i32, i64, vp, vp, vp],
         "hcz_timestamp": [vp, vp],
         "hcz_wall_clock_hz": [C.c_int, C.POINTER(C.c_double)],
+        "hcz_conv_ae_param_count": [C.POINTER(i64)],
+        "hcz_conv_ae_saved_bytes": [i64, C.POINTER(sz)],
+        "hcz_conv_ae_forward": [vp, vp, i64, vp, vp, vp, sz, vp],
+        "hcz_conv_ae_backward": [vp, vp, i64, vp, vp, vp, sz, vp, vp],
         "hcz_container_bound": [C.POINTER(ContainerIn), C.POINTER(sz)],
         "hcz_container_pack": [C.POINTER(ContainerIn), vp, sz, C.POINTER(sz)],
         "hcz_container_read_info": [vp, sz, C.POINTER(ContainerInfo)],
@@ -179,7 +183,8 @@ EXPORTS = ["hcz_create", "hcz_destroy", "hcz_last_error", "hcz_version", "hcz_pl
            "hcz_mlp_backward", "hcz_dequantize", "hcz_mlp_predict", "hcz_segment_tau", "hcz_segment_max",
            "hcz_timestamp", "hcz_wall_clock_hz", "hcz_container_bound", "hcz_container_pack",
            "hcz_container_read_info", "hcz_container_unpack", "hcz_rans_bound", "hcz_rans_encode",
-           "hcz_rans_decode"]
+           "hcz_rans_decode", "hcz_conv_ae_param_count", "hcz_conv_ae_saved_bytes", "hcz_conv_ae_forward",
+           "hcz_conv_ae_backward"]
 
 STAGES = ["encode", "codebook", "quantize", "decode", "residual", "scan", "compact", "stats", "decompress",
           "warmstart"]

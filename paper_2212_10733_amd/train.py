@@ -73,6 +73,54 @@ class DenseAE(torch.autograd.Function):
         return dx, grad
 
 
+def pack_conv(W: dict, device="cuda") -> torch.Tensor:
+    """The convolutional model's parameters in the hcz_model_desc order (hcz.CONV_KEYS)."""
+    return torch.from_numpy(np.concatenate([np.ascontiguousarray(W[k], np.float32).ravel()
+                                            for k in hcz.CONV_KEYS])).to(device)
+
+
+def unpack_conv(p: torch.Tensor) -> dict:
+    from .synth import CONV_SHAPES
+    out, o = {}, 0
+    flat = p.detach().cpu().numpy()
+    for k in hcz.CONV_KEYS:
+        s = CONV_SHAPES[k]
+        n = int(np.prod(s))
+        out[k] = flat[o:o + n].reshape(s).copy()
+        o += n
+    return out
+
+
+class ConvAE(torch.autograd.Function):
+    """The convolutional model (39 x 39) in FP32: hcz_conv_ae_forward / backward."""
+
+    @staticmethod
+    def forward(ctx, x: torch.Tensor, params: torch.Tensor):
+        x = x.contiguous()
+        B = x.shape[0]
+        nbytes = C.c_size_t()
+        _check(LIB.hcz_conv_ae_saved_bytes(B, C.byref(nbytes)))
+        saved = torch.empty(max(nbytes.value, 4) // 4, dtype=torch.float32, device=x.device)
+        z = torch.empty((B, hcz.LATENT), dtype=torch.float32, device=x.device)
+        xh = torch.empty((B, 1521), dtype=torch.float32, device=x.device)
+        _check(LIB.hcz_conv_ae_forward(_ptr(params), _ptr(x), B, _ptr(z), _ptr(xh), _ptr(saved), saved.numel() * 4,
+                                       _stream()))
+        ctx.save_for_backward(x, params, saved)
+        return z, xh
+
+    @staticmethod
+    def backward(ctx, dz, dxh):
+        x, params, saved = ctx.saved_tensors
+        B = x.shape[0]
+        grad = torch.empty_like(params)
+        dz = None if dz is None else dz.contiguous()
+        if dxh is None:
+            dxh = torch.zeros_like(x)
+        _check(LIB.hcz_conv_ae_backward(_ptr(params), _ptr(x), B, _ptr(dz), _ptr(dxh.contiguous()), _ptr(saved),
+                                        saved.numel() * 4, _ptr(grad), _stream()))
+        return None, grad
+
+
 class MSE(torch.autograd.Function):
     @staticmethod
     def forward(ctx, xh: torch.Tensor, x: torch.Tensor):
@@ -99,7 +147,8 @@ def mse(xh, x):
 class Trainer:
     """Adam on the packed parameter vector with hcz_adam_step (FP32 master weights)."""
 
-    def __init__(self, params: torch.Tensor, lr=1e-3, betas=(0.9, 0.999), eps=1e-8):
+    def __init__(self, params: torch.Tensor, lr=1e-3, betas=(0.9, 0.999), eps=1e-8, arch: str = "dense"):
+        self.arch = arch
         self.p = params.detach().clone().contiguous()
         self.m = torch.zeros_like(self.p)
         self.v = torch.zeros_like(self.p)
@@ -114,7 +163,7 @@ class Trainer:
 
     def train_step(self, xb: torch.Tensor) -> torch.Tensor:
         p = self.p.detach().requires_grad_(True)
-        _, xh = DenseAE.apply(xb, p)
+        _, xh = (ConvAE if self.arch == "conv" else DenseAE).apply(xb, p)
         loss = mse(xh, xb)
         loss.backward()
         self.step(p.grad)

@@ -280,3 +280,41 @@ def test_incremental_training(T):
         # the step is lr g / (|g| + eps): within 0.5 % of lr where the sign is sure
         tol = 5e-6 + 4 * np.finfo(np.float32).eps * np.abs(W64[k][sure])
         assert np.all(d <= tol), (k, (d / tol).max())
+
+
+def test_conv_model_forward_backward_and_training(T):
+    """The convolutional model's FP32 training kernels against the oracle's FP64 forward and
+    backward (plus an extra dL/dz), and a few epochs of training lower the loss."""
+    hcz, train = T
+    say("conv training")
+    from oracle import conv as oconv
+    rng = np.random.default_rng(90)
+    W = synth.conv_ae_weights(4)
+    for k in ("c1b", "c2b", "fb", "db", "t1b", "t2b"):
+        W[k] = rng.normal(0, 0.05, W[k].shape).astype(np.float32)
+    B = 96
+    X = inputs(B, 1521, seed=91)
+    p = train.pack_conv(W).requires_grad_(True)
+    x = torch.from_numpy(X).cuda()
+    z, xh = train.ConvAE.apply(x, p)
+    dz = torch.from_numpy(rng.standard_normal((B, 16)).astype(np.float32) * 1e-3).cuda()
+    loss = train.mse(xh, x)
+    (loss + (z * dz).sum()).backward()
+    torch.cuda.synchronize()
+    cache = oconv.forward_train(X.astype(np.float64), W)
+    assert np.allclose(z.detach().cpu().numpy(), cache["z"], rtol=1e-4, atol=1e-4 * np.abs(cache["z"]).max())
+    assert np.allclose(xh.detach().cpu().numpy(), cache["xh"], rtol=1e-4, atol=1e-4 * np.abs(cache["xh"]).max())
+    dxh = 2 * (cache["xh"] - X.astype(np.float64)) / X.size
+    g_or = oconv.backward(cache, W, dxh, dz.cpu().numpy().astype(np.float64))
+    g = train.unpack_conv(p.grad)
+    for k in hcz.CONV_KEYS:
+        scale = np.abs(g_or[k]).max() + 1e-30
+        err = np.abs(g[k] - g_or[k]).max() / scale
+        assert err < 2e-4, (k, err)
+    # training on 2,048 z-scored histograms lowers the loss
+    F = synth.histograms(2048, seed=92, dtype=np.float32).reshape(2048, -1)
+    mu, sd = oracle.ae.norm_stats(F)
+    Xt = torch.from_numpy(((F - mu) / sd).astype(np.float32)).cuda()
+    tr = train.Trainer(train.pack_conv(synth.conv_ae_weights()), lr=1e-3, arch="conv")
+    losses = tr.fit(Xt, epochs=6, batch=256)
+    assert losses[-1] < 0.7 * losses[0], losses
