@@ -184,6 +184,31 @@ def container_form(hcz, plan, x, W, args, n=131072) -> dict:
     return res
 
 
+def conv_train_form(hcz, plan, ctx, x, args, rows=32768, epochs=5) -> dict:
+    """The convolutional model trained by the library's FP32 kernels (Adam, lr 1e-3, batch
+    1024) on `rows` held-apart histograms, then used in its BF16 form on the benchmark
+    batch: training time and loss, and the step with the trained model."""
+    import torch
+
+    from paper_2212_10733_amd import synth, train
+    Ftr = torch.from_numpy(synth.histograms(rows, seed=synth.SEED_TRAIN, dtype=np.float32)).cuda()
+    mu, sd = hcz.norm_stats(plan, Ftr)
+    X = ((Ftr.reshape(rows, -1) - mu) / sd).contiguous()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tr = train.Trainer(train.pack_conv(synth.conv_ae_weights()), lr=1e-3, arch="conv")
+    losses = tr.fit(X, epochs=epochs, batch=1024)
+    torch.cuda.synchronize()
+    dt_train = time.perf_counter() - t0
+    del X, Ftr
+    res = bf16_form(hcz, plan, ctx, x, train.unpack_conv(tr.p), args, arch="conv",
+                    stats=(mu.cpu().numpy(), sd.cpu().numpy()))
+    return {"train_rows": rows, "epochs": epochs, "train_seconds": dt_train,
+            "train_samples_per_s": rows * epochs / dt_train, "loss_first_last": [losses[0], losses[-1]],
+            "value": res["value"], "ms_per_step": res["ms_per_step"], "stream_bytes": res["stream_bytes"],
+            "max_qoi_rel_err": res["max_qoi_rel_err"], "max_err_over_tau_h": res["max_err_over_tau_h"]}
+
+
 def stage5_form(hcz, plan, x, args) -> dict:
     """The coder-only pipeline at tau with each reading of the correction: FP32 multipliers,
     no positivity (orthogonal projection onto A x = b), and the KL correction (kept where it
@@ -212,17 +237,20 @@ def stage5_form(hcz, plan, x, args) -> dict:
     return out
 
 
-def bf16_form(hcz, plan, ctx, x, W, args, arch="dense") -> dict:
+def bf16_form(hcz, plan, ctx, x, W, args, arch="dense", stats=None) -> dict:
     """The plain workload with the autoencoder's large products on bfloat16 operands
     (FP32 accumulation), dense or convolutional: throughput, per-stage times with the
     encoder's and decoder's HBM rates (4N bytes read, resp. written, per histogram) and
     matrix-core rates, p, stream size, QoI error, bound."""
     import torch
     H, N = x.shape[0], plan.N
-    xf = x.reshape(H, -1).double()
-    mu, sd = xf.mean(0), xf.std(0, unbiased=False)
-    sd = torch.clamp(sd, min=1e-12 * sd.max().item())
-    mu, sd = mu.float().cpu().numpy(), sd.float().cpu().numpy()
+    xf = x.reshape(H, -1).double() if stats is None else None
+    if stats is None:
+        mu, sd = xf.mean(0), xf.std(0, unbiased=False)
+        sd = torch.clamp(sd, min=1e-12 * sd.max().item())
+        mu, sd = mu.float().cpu().numpy(), sd.float().cpu().numpy()
+    else:
+        mu, sd = stats
     del xf
     model = hcz.Model(plan, W, mu, sd, compute="bf16", arch=arch)
     cz = hcz.Compressor(plan, model, H, hcz.params(tau=args.tau, fit_codebook=True, sample_every=16))
@@ -379,6 +407,8 @@ def other_forms(hcz, plan, ctx, x, F, W, args, plain_value, plain_stats) -> dict
     if "conv" in args.forms:
         log("form: convolutional autoencoder (BF16)")
         out["conv_ae"] = bf16_form(hcz, plan, ctx, x, synth.conv_ae_weights(), args, arch="conv")
+        log("form: convolutional autoencoder trained")
+        out["conv_ae_trained"] = conv_train_form(hcz, plan, ctx, x, args)
     if "batched" in args.forms:
         log("form: batched uneven subdomains")
         out["batched"] = batched_form(hcz, ctx, args)
