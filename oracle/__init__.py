@@ -9,7 +9,7 @@ FP64 (plus `math.fsum` for correctly rounded moment sums), written from the pape
   moments   true moments b = A f and the four QoIs                (Eq. 1-4)
   ae        dense / tied-linear autoencoder forward+backward, MSE, Adam, z-score
                                                                   (Section III Stage 2-3, Eq. 5;
-                                                                   Section IV-B)
+                                                                   Section IV-C)
   conv      convolutional autoencoder for 39 x 39 grids, BF16 form (Section III Stage 2)
   pq        per-dimension product-quantizer fit (1-D k-means) and encode
                                                                   (Section III Stage 3, IV-E)

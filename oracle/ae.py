@@ -1,9 +1,9 @@
-"""Autoencoder evaluation and training in FP64 (Section III Stages 2-3, Eq. 5; Section IV-B).
+"""Autoencoder evaluation and training in FP64 (Section III Stages 2-3, Eq. 5; Section IV-C).
 
-Dense model:  x = (f - mu) / sigma  (z-score per pixel, Section IV-C)
+Dense model:  x = (f - mu) / sigma  (z-score per pixel, Section IV-D)
               z = W2 relu(W1 x + b1) + b2                       (encoder, linear latent)
               xhat = W4 relu(W3 z + b3) + b4,  fhat = sigma xhat + mu
-Tied linear model (the paper's own, Section IV-B): z = W x,  xhat = W^T z.
+Tied linear model (the paper's own, Section IV-C): z = W x,  xhat = W^T z.
 Loss: MSE(X, Xhat), the mean over batch and pixels (Eq. 5).  Optimizer: Adam.
 Weights are stored [out][in] (y = x @ W.T + b).
 """
@@ -49,14 +49,23 @@ def denormalize(Xh, mu, sd):
     return sd * Xh + mu
 
 
-def dense_forward_train(X: np.ndarray, W: dict):
-    """Full forward pass with the values the backward pass needs."""
-    a1 = X @ _w(W, "W1").T + _w(W, "b1")
+def _mm(A, B, rnd):
+    """A @ B in FP64; with rnd (the BF16 training form) both operands are rounded first."""
+    if rnd is None:
+        return A @ B
+    return rnd(A).astype(np.float64) @ rnd(B).astype(np.float64)
+
+
+def dense_forward_train(X: np.ndarray, W: dict, rnd=None):
+    """Full forward pass with the values the backward pass needs.  rnd: None (FP64), or a
+    rounding applied to both operands of every product (`bf16`: the BF16 training form,
+    bfloat16 operands, exact products, FP32 master weights; biases and ReLU unrounded)."""
+    a1 = _mm(X, _w(W, "W1").T, rnd) + _w(W, "b1")
     h1 = relu(a1)
-    z = h1 @ _w(W, "W2").T + _w(W, "b2")
-    a3 = z @ _w(W, "W3").T + _w(W, "b3")
+    z = _mm(h1, _w(W, "W2").T, rnd) + _w(W, "b2")
+    a3 = _mm(z, _w(W, "W3").T, rnd) + _w(W, "b3")
     h3 = relu(a3)
-    xh = h3 @ _w(W, "W4").T + _w(W, "b4")
+    xh = _mm(h3, _w(W, "W4").T, rnd) + _w(W, "b4")
     return dict(X=X, a1=a1, h1=h1, z=z, a3=a3, h3=h3, xh=xh)
 
 
@@ -64,24 +73,28 @@ def mse(xh: np.ndarray, X: np.ndarray) -> float:
     return float(np.mean((xh - X) ** 2))
 
 
-def dense_backward(cache: dict, W: dict) -> dict:
-    """Gradients of MSE(xhat, X) (mean over all B*N terms) w.r.t. every parameter."""
+def dense_backward(cache: dict, W: dict, rnd=None, dz_extra=None) -> dict:
+    """Gradients of MSE(xhat, X) (mean over all B*N terms) w.r.t. every parameter, by the
+    chain rule layer by layer; rnd as in `dense_forward_train` (both operands of every
+    product of the backward pass rounded).  dz_extra: an extra dL/dz added at the latent."""
     X, h1, z, h3, xh = cache["X"], cache["h1"], cache["z"], cache["h3"], cache["xh"]
     B, N = X.shape
     dxh = 2.0 * (xh - X) / (B * N)
     g = {}
-    g["W4"] = dxh.T @ h3
+    g["W4"] = _mm(dxh.T, h3, rnd)
     g["b4"] = dxh.sum(axis=0)
-    dh3 = dxh @ _w(W, "W4")
+    dh3 = _mm(dxh, _w(W, "W4"), rnd)
     da3 = dh3 * (cache["a3"] > 0)
-    g["W3"] = da3.T @ z
+    g["W3"] = _mm(da3.T, z, rnd)
     g["b3"] = da3.sum(axis=0)
-    dz = da3 @ _w(W, "W3")
-    g["W2"] = dz.T @ h1
+    dz = _mm(da3, _w(W, "W3"), rnd)
+    if dz_extra is not None:
+        dz = dz + dz_extra
+    g["W2"] = _mm(dz.T, h1, rnd)
     g["b2"] = dz.sum(axis=0)
-    dh1 = dz @ _w(W, "W2")
+    dh1 = _mm(dz, _w(W, "W2"), rnd)
     da1 = dh1 * (cache["a1"] > 0)
-    g["W1"] = da1.T @ X
+    g["W1"] = _mm(da1.T, X, rnd)
     g["b1"] = da1.sum(axis=0)
     return g
 

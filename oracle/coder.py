@@ -23,7 +23,9 @@ Delta_0 = 2 (1 - 2^-19) tau_h / (sqrt(N) (L+1)); q = rint(d / Delta_k) (round ha
 even, via multiplication by 1/Delta_k).  Level 0 always meets the bound, since each
 recomposition level adds at most Delta/2 to a convex combination of coarser errors.
 feasible(k): sum (r - T^-1(Delta_k q))^2 <= thr^2, thr = (1 - 2^-20) tau_h.
-The bound search is a bisection over k in [0, 41): lo = 0, hi = 41, mid = (lo+hi) >> 1.
+The bound search is a bisection over k in [0, 41): lo = 0, hi = 41, mid = (lo+hi) >> 1
+(the paper's 'ab'); with a user-specified step ('ub') the ladder index is given and there is
+no search (Section IV-F).
 
 Record: header = Delta_k* (f64 LE), k* (u8), nlev = L+1 (u8), one bit width per
 coefficient group (u8), zero padded to a multiple of 8 bytes; payload = the zigzag
@@ -218,6 +220,15 @@ def bisect(r: np.ndarray, d: np.ndarray, d0: np.ndarray, thr: np.ndarray, lay: L
     q = quantize(d, ladder(d0, lo))
     rh = reconstruct(q, ladder(d0, lo), lay)
     return lo, q, rh
+
+
+def at_level(d: np.ndarray, d0: np.ndarray, k: int, lay: Layout):
+    """The user-specified step ('ub', Section IV-F): every histogram quantised with ladder
+    step k, without a search; returns (k*, q, rhat) like `bisect`."""
+    ks = np.full(d.shape[0], int(k), np.int64)
+    Delta = ladder(d0, ks)
+    q = quantize(d, Delta)
+    return ks, q, reconstruct(q, Delta, lay)
 
 
 def zigzag(q: int) -> int:

@@ -44,6 +44,7 @@ class Params:
     positivity: bool = True         # False: projection onto {A x = b} only
     kl: bool = False                # True: the KL / I-divergence correction (multiplicative)
     lambda_bits: int = 0            # > 0: multipliers rounded to this many mantissa bits
+    ub_level: int | None = None     # None: searched coder step ('ab'); 0..40: the user's step ('ub')
 
 
 def round_mantissa(v: np.ndarray, bits: int) -> np.ndarray:
@@ -143,7 +144,10 @@ def compress(F: np.ndarray, g: Grid, model: dict | None, C: np.ndarray | None, p
         act = coded & ~raw
         keep = ~big
         if keep.any():
-            ks, qs, rh = coder.bisect(r[act], d[keep], d0[act], thr[act], lay)
+            if p.ub_level is None:
+                ks, qs, rh = coder.bisect(r[act], d[keep], d0[act], thr[act], lay)
+            else:
+                ks, qs, rh = coder.at_level(d[keep], d0[act], p.ub_level, lay)
             kstar[act], q[act], rhat[act] = ks, qs, rh
     ft = fhat + rhat
     lam = np.zeros((H, 4))

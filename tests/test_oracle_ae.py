@@ -167,3 +167,34 @@ def test_bf16_form_is_close_to_the_fp64_model():
     xb = ae.bf16_encode_input(F.reshape(64, -1), mu32, rsd32)
     zb = ae.dense_encode_bf16(F, mu32, rsd32, Wb32)
     assert np.allclose(zb, ae.dense_encode(xb.astype(np.float64), Wb), rtol=1e-12, atol=1e-12)
+
+
+def test_bf16_training_form():
+    """The BF16 training form rounds both operands of every product to bfloat16 (FP32
+    master weights, exact products, FP64 sums here).  Pinned against torch's own bfloat16
+    conversion: each product, and the whole forward pass written with torch.nn.functional.
+    The backward pass has the FP64 pass's structure (pinned by autograd and finite
+    differences) and must stay within the bfloat16 operand error of it, without being
+    equal to it."""
+    import torch
+    rng = np.random.default_rng(5)
+    A = rng.normal(size=(7, 33)).astype(np.float32)
+    B = rng.normal(size=(33, 5)).astype(np.float32)
+    bft = lambda a: torch.from_numpy(np.asarray(a, np.float32)).to(torch.bfloat16).to(torch.float64)
+    assert np.allclose(ae._mm(A, B, ae.bf16), (bft(A) @ bft(B)).numpy(), rtol=1e-14, atol=1e-14)
+    W = {k: v.astype(np.float32) for k, v in small_weights().items()}
+    X = rng.normal(size=(6, 50)).astype(np.float32)
+    c = ae.dense_forward_train(X, W, rnd=ae.bf16)
+    lin = lambda x, w, b: bft(x.numpy()) @ bft(w).T + torch.from_numpy(W[b]).double()
+    h1 = torch.relu(lin(torch.from_numpy(X), W["W1"], "b1"))
+    z = lin(h1, W["W2"], "b2")
+    h3 = torch.relu(lin(z, W["W3"], "b3"))
+    xh = lin(h3, W["W4"], "b4")
+    for k, v in (("h1", h1), ("z", z), ("h3", h3), ("xh", xh)):
+        assert np.allclose(c[k], v.numpy(), rtol=1e-13, atol=1e-13), k
+    W64 = {k: v.astype(np.float64) for k, v in W.items()}
+    g64 = ae.dense_backward(ae.dense_forward_train(X.astype(np.float64), W64), W64)
+    g16 = ae.dense_backward(c, W, rnd=ae.bf16)
+    for k in W:
+        rel = np.linalg.norm(g16[k] - g64[k]) / np.linalg.norm(g64[k])
+        assert 1e-5 < rel < 3e-2, (k, rel)

@@ -220,3 +220,47 @@ def test_multiplier_truncation():
         assert np.all(dist <= 1.0001 * pipeline.tau_h(F, p))
         errs.append(moments.qoi_rel_error(moments.qoi(F, g), moments.qoi(out, g), g).max())
     assert errs[0] < 1e-11 and errs[0] < errs[1] < errs[2] < 1e-2
+
+
+def _records(comp, H):
+    off = comp["offsets"].astype(np.int64)
+    return [comp["stream"][off[h]:off[h + 1]] for h in range(H)]
+
+
+def test_user_specified_step():
+    """The 'ub' setting (Section IV-F): the coder's step is given, not searched.
+    * level 0 keeps the bound: every cell's coder error is at most (L+1) Delta_0 / 2 (each
+      level adds at most Delta/2 to a convex combination of coarser errors), so
+      ||f - f~|| <= sqrt(N) (L+1) Delta_0 / 2 < tau_h, and the projection only shrinks it;
+    * on histograms where the bisection chose k, the step k given by the user gives the
+      same record byte for byte;
+    * a finer step never gives a shorter record (|rint(d / Delta)| is non-increasing in
+      Delta, so is every group's bit width)."""
+    g = grid.make_grid()
+    H = 16
+    F = synth.histograms(H, seed=41, dtype=np.float64)
+    lay = coder.layout(g.n_par, g.n_perp)
+    ab = pipeline.compress(F, g, None, None, pipeline.Params(tau=1e-3))
+    ub0 = pipeline.compress(F, g, None, None, pipeline.Params(tau=1e-3, ub_level=0))
+    coded = (ab["flags"] & pipeline.FLAG_CODED) != 0
+    assert coded.all() and np.array_equal(ub0["flags"] & pipeline.FLAG_CODED, ab["flags"] & pipeline.FLAG_CODED)
+    assert np.all(ub0["kstar"][coded] == 0)
+    d0 = coder.delta0(ub0["tau_h"], lay)
+    cell = np.abs((F - ub0["ft"]).reshape(H, -1)).max(axis=1)
+    assert np.all(cell <= (lay.L + 1) * d0 / 2 * (1 + 1e-12))
+    out = pipeline.decompress(ub0, g, None, None, H, np.float64)
+    check_bound_and_qoi(F, out, ub0, g, 1e-3)
+    ra, r0 = _records(ab, H), _records(ub0, H)
+    assert all(len(x) >= len(y) for x, y in zip(r0, ra))
+    assert sum(map(len, r0)) > sum(map(len, ra))
+    for k in np.unique(ab["kstar"][coded]):
+        uk = pipeline.compress(F, g, None, None, pipeline.Params(tau=1e-3, ub_level=int(k)))
+        rk = _records(uk, H)
+        for h in np.nonzero(coded & (ab["kstar"] == k))[0]:
+            assert rk[h] == ra[h]
+            assert np.array_equal(uk["lam"][h], ab["lam"][h])
+        assert np.all(uk["kstar"][coded] == k)
+    # a step far above the search's choice loses the bound on the primary data
+    big = pipeline.compress(F, g, None, None, pipeline.Params(tau=1e-3, ub_level=40))
+    dist = np.sqrt(((big["ft"] - F) ** 2).reshape(H, -1).sum(1))
+    assert np.any(dist > big["tau_h"])
