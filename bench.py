@@ -119,33 +119,58 @@ def time_compress(cz, x, steps):
     return (time.perf_counter() - t0) / steps, comp
 
 
-def tau_sweep(hcz, plan, model, x, args) -> dict:
-    """The plain form at the other bounds of the workload's tau set: throughput, coded
-    fraction p, stream size, compression ratio, QoI error and the bound on the batch."""
+def _qoi_refs(hcz, plan, x):
     import torch
-    H = x.shape[0]
-    N = plan.N
-    out = {}
     _, q0, n0 = hcz.qoi(plan, x)
     den = torch.stack([q0[:, 0].abs(), torch.maximum(q0[:, 1].abs(), q0[:, 3].abs().sqrt()),
                        q0[:, 2].abs(), q0[:, 3].abs()], 1)
+    return q0, n0, den
+
+
+def _plain_run(hcz, plan, model, x, hp, tau, refs, steps=3) -> dict:
+    """Time one configuration of the full pipeline and report throughput, coded fraction p,
+    stream size, compression ratio, QoI error and the bound on the batch."""
+    H = x.shape[0]
+    q0, n0, den = refs
+    cz = hcz.Compressor(plan, model, H, hp)
+    dt, comp = time_compress(cz, x, steps)
+    s = comp.stats()
+    o = cz.decompress(comp, H)
+    _, q1, _ = hcz.qoi(plan, o)
+    ok = (comp.flags & 4) == 0
+    stored = H * 16 + H * 32 + H + s["stream_bytes"] + 395265 * 4 + 16 * 256 * 4 + 44
+    over = (o - x.double()).reshape(H, -1).norm(dim=1)[ok] / (tau * n0[ok])
+    r = {"value": H / dt, "ms_per_step": dt * 1e3, "coded_frac": s["n_coded"] / H, "raw": s["n_raw"],
+         "stream_bytes": s["stream_bytes"], "compression_ratio": H * plan.N * 4 / stored,
+         "newton_mean_updates": s["newton_iters_total"] / max(1, H - s["n_raw"]),
+         "max_qoi_rel_err": ((q1 - q0).abs() / den)[ok].max().item(),
+         "max_err_over_tau_h": over.max().item(), "over_bound": int((over > 1).sum().item())}
+    del cz, comp, o
+    return r
+
+
+def tau_sweep(hcz, plan, model, x, args) -> dict:
+    """The plain form at the other bounds of the workload's tau set."""
+    refs = _qoi_refs(hcz, plan, x)
+    out = {}
     for tau in (1e-2, 1e-4):
         log(f"tau sweep: {tau}")
-        cz = hcz.Compressor(plan, model, H, hcz.params(tau=tau, fit_codebook=True, sample_every=16))
-        dt, comp = time_compress(cz, x, 3)
-        s = comp.stats()
-        o = cz.decompress(comp, H)
-        _, q1, _ = hcz.qoi(plan, o)
-        ok = (comp.flags & 4) == 0
-        stored = H * 16 + H * 32 + H + s["stream_bytes"] + 395265 * 4 + 16 * 256 * 4 + 44
-        out[f"{tau:g}"] = {
-            "value": H / dt, "ms_per_step": dt * 1e3, "coded_frac": s["n_coded"] / H, "raw": s["n_raw"],
-            "stream_bytes": s["stream_bytes"], "compression_ratio": H * N * 4 / stored,
-            "newton_mean_updates": s["newton_iters_total"] / max(1, H - s["n_raw"]),
-            "max_qoi_rel_err": ((q1 - q0).abs() / den)[ok].max().item(),
-            "max_err_over_tau_h": ((o - x.double()).reshape(H, -1).norm(dim=1)[ok] / (tau * n0[ok])).max().item(),
-        }
-        del cz, comp, o
+        out[f"{tau:g}"] = _plain_run(hcz, plan, model, x, hcz.params(tau=tau, fit_codebook=True, sample_every=16),
+                                     tau, refs)
+    return out
+
+
+def ub_form(hcz, plan, model, x, args) -> dict:
+    """The plain form with the coder's step given instead of searched (the paper's 'ub'
+    against its 'ab'): level 0 is the step whose a-priori estimate keeps the bound, level 4
+    doubles it and lets the bound go."""
+    refs = _qoi_refs(hcz, plan, x)
+    out = {}
+    for level in (0, 4):
+        log(f"ub form: level {level}")
+        out[f"level_{level}"] = _plain_run(hcz, plan, model, x,
+                                           hcz.params(tau=args.tau, fit_codebook=True, sample_every=16,
+                                                      ub_level=level), args.tau, refs)
     return out
 
 
@@ -335,7 +360,7 @@ def batched_form(hcz, ctx, args, n_sub=512, reps=3) -> dict:
 
 
 def incremental_form(hcz, plan, H, W, args, steps=4, planes=8) -> dict:
-    """Incremental training (Section IV-C) on a drifting synthetic series: at every step a
+    """Incremental training (Section IV-D) on a drifting synthetic series: at every step a
     batch of planes x nodes = H / 4 histograms (262,144 at H = 2^20), training rows chosen
     one per node (column-random-index: 32,768), the model of step 0 trained from
     scratch for --epochs, every later step either continued from the previous model for 2
@@ -426,6 +451,12 @@ def other_forms(hcz, plan, ctx, x, F, W, args, plain_value, plain_stats) -> dict
     losses = tr.fit(X, epochs=args.epochs, batch=1024)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
+    log("form: learned, bf16 training")
+    t0 = time.perf_counter()
+    tr16 = train.Trainer(train.pack(W), lr=1e-3, compute="bf16")
+    losses16 = tr16.fit(X, epochs=args.epochs, batch=1024)
+    torch.cuda.synchronize()
+    t_train16 = time.perf_counter() - t0
     del X
     Wt = train.unpack(tr.p, plan.N)
     model = hcz.Model(plan, Wt, mu.cpu().numpy(), sd.cpu().numpy())
@@ -464,7 +495,14 @@ def other_forms(hcz, plan, ctx, x, F, W, args, plain_value, plain_stats) -> dict
                                                / (args.tau * n0[okk])).max().item()
             del o
         del cz, comp
+    # the BF16-trained model compressing in the BF16 dense form
+    model16 = hcz.Model(plan, train.unpack(tr16.p, plan.N), mu.cpu().numpy(), sd.cpu().numpy(), compute="bf16")
+    bf16_run = _plain_run(hcz, plan, model16, x, hcz.params(tau=args.tau, fit_codebook=True, sample_every=16),
+                          args.tau, _qoi_refs(hcz, plan, x))
+    del model16
     out["learned"] = {"train_seconds": t_train, "train_loss_first_last": [losses[0], losses[-1]],
+                      "bf16_train_seconds": t_train16, "bf16_train_loss_first_last": [losses16[0], losses16[-1]],
+                      "bf16_trained_bf16_form": bf16_run,
                       "mlp_train_seconds": t_mlp, "mlp_loss_first_last": [mlosses[0], mlosses[-1]],
                       "cold_start": res["cold"], "warm_start": res["warm"],
                       "untrained_plain": {"value": plain_value, "coded_frac": plain_stats["n_coded"] / H,
@@ -482,10 +520,10 @@ def main() -> int:
     ap.add_argument("--cpu-sample", type=int, default=8192)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the coder-only and learned forms")
-    ap.add_argument("--forms", default="tau,coder,stage5,container,bf16,conv,batched,incremental,learned",
+    ap.add_argument("--forms", default="tau,ub,coder,stage5,container,bf16,conv,batched,incremental,learned",
                     help="comma list of the other forms to run: tau (sweep), coder (coder-only), "
                          "stage5 (FP32 multipliers, no positivity, KL correction), container (packed "
-                         "output with and without rANS), "
+                         "output with and without rANS), ub (the coder step given, not searched), "
                          "bf16 (BF16 autoencoder), conv (convolutional BF16 autoencoder), "
                          "batched (uneven subdomains on four grids), "
                          "incremental (training series), learned")
@@ -605,6 +643,8 @@ def main() -> int:
     if not args.no_forms:
         if "tau" in args.forms:
             forms["tau_sweep"] = tau_sweep(hcz, plan, model, x, args)
+        if "ub" in args.forms:
+            forms["ub"] = ub_form(hcz, plan, model, x, args)
         forms.update(other_forms(hcz, plan, ctx, x, F, W, args, value, st))
 
     cpu = None

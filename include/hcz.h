@@ -57,6 +57,7 @@ enum { HCZ_ARCH_DENSE = 1, HCZ_ARCH_CONV = 2 };           /* autoencoder archite
 enum { HCZ_COMPUTE_FP32 = 0, HCZ_COMPUTE_BF16 = 1 };      /* autoencoder arithmetic */
 enum { HCZ_TAU_REL_L2 = 0, HCZ_TAU_NRMSE = 1 };          /* tau_h = tau ||f||, tau sqrt(N)(max-min) */
 enum { HCZ_FALLBACK_BACKTRACK = 0, HCZ_FALLBACK_PAPER = 1 };
+enum { HCZ_BOUND_AB = 0, HCZ_BOUND_UB = 1 };                /* coder step: searched, user-specified */
 enum { HCZ_FLAG_CODED = 1, HCZ_FLAG_ROUND2 = 2, HCZ_FLAG_RAW = 4, HCZ_FLAG_WARM_REJECTED = 8,
        HCZ_FLAG_NOCLIP = 16, HCZ_FLAG_KL = 32 };
 enum { HCZ_WARM_COLD = 0, HCZ_WARM_MLP = 1 };
@@ -81,7 +82,7 @@ typedef struct {
  * linear latent and output (Stage 2).  weights (host, FP32, copied) holds
  * W1[hidden][N], b1[hidden], W2[latent][hidden], b2[latent], W3[hidden][latent],
  * b3[hidden], W4[N][hidden], b4[N] back to back (y = x W^T + b).  norm_mean and
- * norm_std (host, [N]) are the per-pixel z-score statistics (Section IV-C).
+ * norm_std (host, [N]) are the per-pixel z-score statistics (Section IV-D).
  * Supported: hidden = 128, latent = 16.
  * compute: HCZ_COMPUTE_FP32 evaluates both products on FP32 matrix cores.
  *   HCZ_COMPUTE_BF16 (an arithmetic form of this library, not the paper's) gives the two
@@ -158,7 +159,17 @@ typedef struct {
  * tau_hist         NULL: every histogram uses tau.  Otherwise (device, FP64, [H]) histogram
  *                  h uses tau_hist[h] in place of tau (tau is then not read): per-subdomain
  *                  bounds in one call, see hcz_segment_tau.  A negative, infinite or NaN
- *                  entry makes that histogram a verbatim record. */
+ *                  entry makes that histogram a verbatim record.
+ * bound_mode       HCZ_BOUND_AB (0): the coder's step is searched per histogram by the
+ *                  bisection over the ladder (the paper's 'ab', automatic error-bound
+ *                  determination, Section IV-F).  HCZ_BOUND_UB (1): the step is the user's
+ *                  ('ub', user-specified error bound): every coded histogram is quantised
+ *                  with ladder step ub_level, without a search.  ub_level 0 is the step
+ *                  whose a-priori error estimate ((L+1) Delta / 2 per cell) meets tau_h, so
+ *                  the bound still holds; a larger ub_level trades the bound for ratio and
+ *                  nothing checks ||f - f~|| against tau_h.  The selection (coded iff
+ *                  ||r|| > (1 - 2^-20) tau_h) is the same in both modes.
+ * ub_level         0..40, read only with HCZ_BOUND_UB. */
 typedef struct {
   double tau;
   int32_t tau_mode;
@@ -175,6 +186,8 @@ typedef struct {
   const double* tau_hist;
   int32_t kl;
   int32_t lambda_bits;
+  int32_t bound_mode;
+  int32_t ub_level;
 } hcz_params;
 
 /* Run statistics, written to device memory by compress and read with hcz_stats_read. */
@@ -383,20 +396,25 @@ hcz_status hcz_rans_bound(size_t n, size_t* bytes);
 hcz_status hcz_rans_encode(const void* in, size_t n, void* out, size_t capacity, size_t* written);
 hcz_status hcz_rans_decode(const void* in, size_t avail, void* out, size_t n);
 
-/* ---- autoencoder training (Section III Stage 2, Eq. 5; Section IV-B) -------------------
+/* ---- autoencoder training (Section III Stage 2, Eq. 5; Section IV-C) -------------------
  * The dense model of hcz_model_desc, trained with these kernels from torch.autograd.
  * params / grad: FP32 device vectors in the hcz_model_desc weights layout
  * (hcz_ae_param_count elements).  x: z-scored inputs [B][N] (device, FP32).
  * hcz_ae_forward writes z [B][latent], xhat [B][N] and the activations the backward
  * pass needs into `saved` (hcz_ae_saved_bytes; also the backward's scratch).
  * hcz_ae_backward takes dL/dz (or NULL for 0) and dL/dxhat and writes dL/dparams to
- * grad and, if dx is not NULL, dL/dx [B][N].  Every product runs on FP32 matrix cores
- * with a fixed reduction order (no atomics). */
+ * grad and, if dx is not NULL, dL/dx [B][N].  compute: HCZ_COMPUTE_FP32, every product on
+ * FP32 matrix cores; HCZ_COMPUTE_BF16, both operands of every product (forward and
+ * backward) rounded to the nearest bfloat16 and multiplied on BF16 matrix cores with FP32
+ * accumulation, while parameters, gradients, biases, ReLU and the loss stay FP32 (FP32
+ * master weights under hcz_adam_step).  Fixed reduction order (no atomics); any other
+ * compute value is HCZ_EINVAL.  saved layout (FP32): h1 [B][128], h3 [B][128], then the
+ * backward's dL/da3 [B][128], dL/da1 [B][128] and dL/dz [B][latent]. */
 hcz_status hcz_ae_param_count(int32_t N, int64_t* count);
 hcz_status hcz_ae_saved_bytes(int32_t N, int64_t B, size_t* bytes);
-hcz_status hcz_ae_forward(int32_t N, const float* params, const float* x, int64_t B, float* z,
-                          float* xhat, void* saved, size_t saved_bytes, hcz_stream_t stream);
-hcz_status hcz_ae_backward(int32_t N, const float* params, const float* x, int64_t B,
+hcz_status hcz_ae_forward(int32_t N, int32_t compute, const float* params, const float* x, int64_t B,
+                          float* z, float* xhat, void* saved, size_t saved_bytes, hcz_stream_t stream);
+hcz_status hcz_ae_backward(int32_t N, int32_t compute, const float* params, const float* x, int64_t B,
                            const float* dz, const float* dxhat, void* saved, size_t saved_bytes,
                            float* grad, float* dx, hcz_stream_t stream);
 /* Convolutional model (39 x 39; the parameter blob in the hcz_model_desc order, 248,785
@@ -420,7 +438,7 @@ hcz_status hcz_mse(const float* xhat, const float* x, int64_t n, float* loss, fl
 hcz_status hcz_adam_step(float* params, const float* grad, float* m, float* v, int64_t n,
                          double lr, double beta1, double beta2, double eps, int64_t step,
                          hcz_stream_t stream);
-/* Per-pixel z-score statistics (Section IV-C): mean and population std over H
+/* Per-pixel z-score statistics (Section IV-D): mean and population std over H
  * histograms (FP64 two-pass), std floored at 1e-12 * max std; written as FP32 [N]. */
 hcz_status hcz_norm_stats_workspace(const hcz_plan* plan, int64_t H, size_t* bytes);
 hcz_status hcz_norm_stats(const hcz_plan* plan, const void* hist, int32_t dtype, int64_t H,

@@ -409,6 +409,9 @@ hcz_status check_params(const hcz_params* p) {
     return fail(HCZ_EINVAL, "lambda_bits must be in [0, 52] ([0, 23] with FP32 multipliers)");
   if (p->kl && (p->no_positivity || p->warm_start != HCZ_WARM_COLD))
     return fail(HCZ_EINVAL, "kl is not combined with no_positivity or a warm start");
+  if (p->bound_mode != HCZ_BOUND_AB && p->bound_mode != HCZ_BOUND_UB) return fail(HCZ_EINVAL, "bound_mode");
+  if (p->bound_mode == HCZ_BOUND_UB && (p->ub_level < 0 || p->ub_level > 40))
+    return fail(HCZ_EINVAL, "ub_level must be in [0, 40]");
   return HCZ_OK;
 }
 
@@ -890,6 +893,7 @@ static hcz_status residual_impl(const hcz_plan* plan, const hcz_params* p, const
   a.no_positivity = p->no_positivity;
   a.kl = p->kl;
   a.lambda_bits = p->lambda_bits;
+  a.ub_k = p->bound_mode == HCZ_BOUND_UB ? p->ub_level : -1;
   a.flags = out->flags;
   a.sizes = (uint64_t*)(ws + L.sizes);
   a.slots = ws + L.slots;
@@ -1078,9 +1082,10 @@ hcz_status hcz_ae_saved_bytes(int32_t N, int64_t B, size_t* bytes) {
   return HCZ_OK;
 }
 
-hcz_status hcz_ae_forward(int32_t N, const float* params, const float* x, int64_t B, float* z,
+hcz_status hcz_ae_forward(int32_t N, int32_t compute, const float* params, const float* x, int64_t B, float* z,
                           float* xhat, void* saved, size_t saved_bytes, hcz_stream_t stream) {
   if (N < 1 || N > kMaxN || B < 0) return fail(HCZ_EINVAL, "bad size");
+  if (compute != HCZ_COMPUTE_FP32 && compute != HCZ_COMPUTE_BF16) return fail(HCZ_EINVAL, "compute");
   if (B == 0) return HCZ_OK;
   if (!params || !x || !z || !xhat || !saved) return fail(HCZ_EINVAL, "NULL buffer");
   if (saved_bytes < ae_saved_floats(B) * sizeof(float)) return fail(HCZ_EWORKSPACE, "saved buffer too small");
@@ -1089,10 +1094,11 @@ hcz_status hcz_ae_forward(int32_t N, const float* params, const float* x, int64_
   float* h1 = (float*)saved;
   float* h3 = h1 + (size_t)B * kHidden;
   const int Hd = kHidden, Ld = kLatent;
-  HCZ_TRY(launch_gemm(x, N, 1, params + o.W1, 1, N, h1, Hd, B, Hd, N, 1.f, 0.f, params + o.b1, 1, st), "gemm");
-  HCZ_TRY(launch_gemm(h1, Hd, 1, params + o.W2, 1, Hd, z, Ld, B, Ld, Hd, 1.f, 0.f, params + o.b2, 0, st), "gemm");
-  HCZ_TRY(launch_gemm(z, Ld, 1, params + o.W3, 1, Ld, h3, Hd, B, Hd, Ld, 1.f, 0.f, params + o.b3, 1, st), "gemm");
-  HCZ_TRY(launch_gemm(h3, Hd, 1, params + o.W4, 1, Hd, xhat, N, B, N, Hd, 1.f, 0.f, params + o.b4, 0, st), "gemm");
+  const int bf = compute == HCZ_COMPUTE_BF16;
+  HCZ_TRY(launch_gemm(x, N, 1, params + o.W1, 1, N, h1, Hd, B, Hd, N, 1.f, 0.f, params + o.b1, 1, st, bf), "gemm");
+  HCZ_TRY(launch_gemm(h1, Hd, 1, params + o.W2, 1, Hd, z, Ld, B, Ld, Hd, 1.f, 0.f, params + o.b2, 0, st, bf), "gemm");
+  HCZ_TRY(launch_gemm(z, Ld, 1, params + o.W3, 1, Ld, h3, Hd, B, Hd, Ld, 1.f, 0.f, params + o.b3, 1, st, bf), "gemm");
+  HCZ_TRY(launch_gemm(h3, Hd, 1, params + o.W4, 1, Hd, xhat, N, B, N, Hd, 1.f, 0.f, params + o.b4, 0, st, bf), "gemm");
   return HCZ_OK;
 }
 
@@ -1200,47 +1206,49 @@ hcz_status hcz_conv_ae_backward(const float* params, const float* x, int64_t B, 
   return HCZ_OK;
 }
 
-hcz_status hcz_ae_backward(int32_t N, const float* params, const float* x, int64_t B,
+hcz_status hcz_ae_backward(int32_t N, int32_t compute, const float* params, const float* x, int64_t B,
                            const float* dz_in, const float* dxh, void* saved, size_t saved_bytes,
                            float* grad, float* dx, hcz_stream_t stream) {
   if (N < 1 || N > kMaxN || B < 0) return fail(HCZ_EINVAL, "bad size");
+  if (compute != HCZ_COMPUTE_FP32 && compute != HCZ_COMPUTE_BF16) return fail(HCZ_EINVAL, "compute");
   if (!params || !grad) return fail(HCZ_EINVAL, "NULL buffer");
   if (B > 0 && (!x || !dxh || !saved)) return fail(HCZ_EINVAL, "NULL buffer");
   if (saved_bytes < ae_saved_floats(B) * sizeof(float)) return fail(HCZ_EWORKSPACE, "saved buffer too small");
   const AeOffsets o = ae_offsets(N);
   hipStream_t st = (hipStream_t)stream;
   const int Hd = kHidden, Ld = kLatent;
+  const int bf = compute == HCZ_COMPUTE_BF16;
   float* h1 = (float*)saved;
   float* h3 = h1 + (size_t)B * Hd;
   float* d3 = h3 + (size_t)B * Hd;      // dL/d(pre-activation 3), [B][Hd]
   float* d1 = d3 + (size_t)B * Hd;      // dL/d(pre-activation 1), [B][Hd]
   float* dz = d1 + (size_t)B * Hd;      // dL/dz, [B][Ld]
   // z is needed for dW3: recompute it from h1 (cheap) into dz's slot first
-  HCZ_TRY(launch_gemm(h1, Hd, 1, params + o.W2, 1, Hd, dz, Ld, B, Ld, Hd, 1.f, 0.f, params + o.b2, 0, st), "gemm");
+  HCZ_TRY(launch_gemm(h1, Hd, 1, params + o.W2, 1, Hd, dz, Ld, B, Ld, Hd, 1.f, 0.f, params + o.b2, 0, st, bf), "gemm");
   // output layer
-  HCZ_TRY(launch_gemm(dxh, 1, N, h3, Hd, 1, grad + o.W4, Hd, N, Hd, B, 1.f, 0.f, nullptr, 0, st), "gemm dW4");
+  HCZ_TRY(launch_gemm(dxh, 1, N, h3, Hd, 1, grad + o.W4, Hd, N, Hd, B, 1.f, 0.f, nullptr, 0, st, bf), "gemm dW4");
   HCZ_TRY(launch_colsum(dxh, B, N, grad + o.b4, st), "colsum");
-  HCZ_TRY(launch_gemm(dxh, N, 1, params + o.W4, Hd, 1, d3, Hd, B, Hd, N, 1.f, 0.f, nullptr, 0, st), "gemm dh3");
+  HCZ_TRY(launch_gemm(dxh, N, 1, params + o.W4, Hd, 1, d3, Hd, B, Hd, N, 1.f, 0.f, nullptr, 0, st, bf), "gemm dh3");
   HCZ_TRY(launch_relu_mask(d3, h3, (long long)B * Hd, st), "relu mask");
   // decoder input layer: dW3 = d3^T z
-  HCZ_TRY(launch_gemm(d3, 1, Hd, dz, Ld, 1, grad + o.W3, Ld, Hd, Ld, B, 1.f, 0.f, nullptr, 0, st), "gemm dW3");
+  HCZ_TRY(launch_gemm(d3, 1, Hd, dz, Ld, 1, grad + o.W3, Ld, Hd, Ld, B, 1.f, 0.f, nullptr, 0, st, bf), "gemm dW3");
   HCZ_TRY(launch_colsum(d3, B, Hd, grad + o.b3, st), "colsum");
   // dz = d3 W3 (+ dz_in)
   if (dz_in) {
     HCZ_TRY(hipMemcpyAsync(dz, dz_in, (size_t)B * Ld * sizeof(float), hipMemcpyDeviceToDevice, st), "copy dz");
-    HCZ_TRY(launch_gemm(d3, Hd, 1, params + o.W3, Ld, 1, dz, Ld, B, Ld, Hd, 1.f, 1.f, nullptr, 0, st), "gemm dz");
+    HCZ_TRY(launch_gemm(d3, Hd, 1, params + o.W3, Ld, 1, dz, Ld, B, Ld, Hd, 1.f, 1.f, nullptr, 0, st, bf), "gemm dz");
   } else {
-    HCZ_TRY(launch_gemm(d3, Hd, 1, params + o.W3, Ld, 1, dz, Ld, B, Ld, Hd, 1.f, 0.f, nullptr, 0, st), "gemm dz");
+    HCZ_TRY(launch_gemm(d3, Hd, 1, params + o.W3, Ld, 1, dz, Ld, B, Ld, Hd, 1.f, 0.f, nullptr, 0, st, bf), "gemm dz");
   }
   // encoder output layer
-  HCZ_TRY(launch_gemm(dz, 1, Ld, h1, Hd, 1, grad + o.W2, Hd, Ld, Hd, B, 1.f, 0.f, nullptr, 0, st), "gemm dW2");
+  HCZ_TRY(launch_gemm(dz, 1, Ld, h1, Hd, 1, grad + o.W2, Hd, Ld, Hd, B, 1.f, 0.f, nullptr, 0, st, bf), "gemm dW2");
   HCZ_TRY(launch_colsum(dz, B, Ld, grad + o.b2, st), "colsum");
-  HCZ_TRY(launch_gemm(dz, Ld, 1, params + o.W2, Hd, 1, d1, Hd, B, Hd, Ld, 1.f, 0.f, nullptr, 0, st), "gemm dh1");
+  HCZ_TRY(launch_gemm(dz, Ld, 1, params + o.W2, Hd, 1, d1, Hd, B, Hd, Ld, 1.f, 0.f, nullptr, 0, st, bf), "gemm dh1");
   HCZ_TRY(launch_relu_mask(d1, h1, (long long)B * Hd, st), "relu mask");
   // encoder input layer
-  HCZ_TRY(launch_gemm(d1, 1, Hd, x, N, 1, grad + o.W1, N, Hd, N, B, 1.f, 0.f, nullptr, 0, st), "gemm dW1");
+  HCZ_TRY(launch_gemm(d1, 1, Hd, x, N, 1, grad + o.W1, N, Hd, N, B, 1.f, 0.f, nullptr, 0, st, bf), "gemm dW1");
   HCZ_TRY(launch_colsum(d1, B, Hd, grad + o.b1, st), "colsum");
-  if (dx) HCZ_TRY(launch_gemm(d1, Hd, 1, params + o.W1, N, 1, dx, N, B, N, Hd, 1.f, 0.f, nullptr, 0, st), "gemm dx");
+  if (dx) HCZ_TRY(launch_gemm(d1, Hd, 1, params + o.W1, N, 1, dx, N, B, N, Hd, 1.f, 0.f, nullptr, 0, st, bf), "gemm dx");
   return HCZ_OK;
 }
 

@@ -114,6 +114,7 @@ struct ResidualArgs {
   int no_positivity;           // 1: projection onto {A x = b} only (flag HCZ_FLAG_NOCLIP)
   int kl;                      // 1: KL correction where it keeps the bound (flag HCZ_FLAG_KL)
   int lambda_bits;             // 0, or stored multipliers rounded to this many mantissa bits
+  int ub_k;                    // -1: bisection over the ladder; 0..40: this ladder step, no search
   uint8_t* flags;              // [H]
   uint64_t* sizes;             // [H] record bytes
   uint8_t* slots;              // [H][slot_stride] staging
@@ -375,7 +376,7 @@ hipError_t launch_quantize(const float* z, long long n, int latent, const float*
 size_t codebook_ws_bytes(long long n, int latent, long long every);
 hipError_t launch_gemm(const float* A, long long sam, long long sak, const float* B, long long sbk,
                        long long sbn, float* C, long long scm, long long M, long long Nc, long long K,
-                       float alpha, float beta, const float* bias, int relu, hipStream_t st);
+                       float alpha, float beta, const float* bias, int relu, hipStream_t st, int bf16 = 0);
 hipError_t launch_relu_mask(float* d, const float* h, long long n, hipStream_t st);
 hipError_t launch_colsum(const float* D, long long M, long long Nc, float* out, hipStream_t st);
 size_t mse_ws_bytes();

@@ -1,7 +1,7 @@
-// Autoencoder training kernels (Section III Stage 2, Eq. 5; Section IV-B): a strided FP32
-// matrix-core GEMM used for every forward and backward product of the dense model, ReLU
+// Autoencoder training kernels (Section III Stage 2, Eq. 5; Section IV-C): a strided FP32 or
+// BF16 matrix-core GEMM used for every forward and backward product of the dense model, ReLU
 // masks, column sums for bias gradients, the MSE loss with its gradient, Adam, and the
-// per-pixel z-score statistics (Section IV-C).  All reductions run in a fixed order, so
+// per-pixel z-score statistics (Section IV-D).  All reductions run in a fixed order, so
 // a training step is bitwise repeatable.
 #include "hcz_internal.h"
 
@@ -14,15 +14,25 @@ constexpr int kGT = 64;      // GEMM tile (M and N)
 constexpr int kGK = 32;      // K chunk
 constexpr int kGP = 36;      // LDS pitch
 
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+constexpr int kGPB = 40;     // LDS pitch (bfloat16 elements) of the BF16 tiles
+
 // C[m][n] = alpha * sum_k A(m,k) B(k,n) + beta * C[m][n] (+ bias[n]) (relu), with
 // A(m,k) = A[m*sam + k*sak], B(k,n) = B[k*sbk + n*sbn], C[m*scm + n].
+// BF = false: FP32 operands on v_mfma_f32_32x32x2f32.  BF = true: both operands rounded to
+// the nearest bfloat16 (ties to even) as they are staged, products on
+// v_mfma_f32_32x32x16_bf16 (exact products, FP32 accumulation); alpha, beta, bias and the
+// ReLU stay FP32.
+template <bool BF>
 __global__ __launch_bounds__(256) void k_gemm(const float* A, long long sam, long long sak,
                                               const float* B, long long sbk, long long sbn,
                                               float* C, long long scm, long long M, long long Nc,
                                               long long K, float alpha, float beta,
                                               const float* bias, int relu) {
-  __shared__ __attribute__((aligned(16))) float As[kGT * kGP];
-  __shared__ __attribute__((aligned(16))) float Bs[kGT * kGP];
+  __shared__ __attribute__((aligned(16))) float As[BF ? 1 : kGT * kGP];
+  __shared__ __attribute__((aligned(16))) float Bs[BF ? 1 : kGT * kGP];
+  __shared__ __attribute__((aligned(16))) __bf16 Ab[BF ? kGT * kGPB : 8];
+  __shared__ __attribute__((aligned(16))) __bf16 Bb[BF ? kGT * kGPB : 8];
   const int t = threadIdx.x, w = t >> 6, l = t & 63, li = l & 31, lh = l >> 5;
   const long long m0 = (long long)blockIdx.x * kGT, n0 = (long long)blockIdx.y * kGT;
   const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
@@ -37,21 +47,38 @@ __global__ __launch_bounds__(256) void k_gemm(const float* A, long long sam, lon
       int mm, kk;
       if (ak) { mm = idx >> 5; kk = idx & 31; } else { mm = idx & 63; kk = idx >> 6; }
       const long long gm = m0 + mm, gk = k0 + kk;
-      As[mm * kGP + (kk & 1) * 16 + (kk >> 1)] = (gm < M && gk < K) ? A[gm * sam + gk * sak] : 0.0f;
+      const float av = (gm < M && gk < K) ? A[gm * sam + gk * sak] : 0.0f;
       int nn, kb;
       if (bk) { nn = idx >> 5; kb = idx & 31; } else { nn = idx & 63; kb = idx >> 6; }
       const long long gn = n0 + nn, gkb = k0 + kb;
-      Bs[nn * kGP + (kb & 1) * 16 + (kb >> 1)] = (gn < Nc && gkb < K) ? B[gkb * sbk + gn * sbn] : 0.0f;
+      const float bv = (gn < Nc && gkb < K) ? B[gkb * sbk + gn * sbn] : 0.0f;
+      if constexpr (BF) {
+        Ab[mm * kGPB + kk] = (__bf16)av;
+        Bb[nn * kGPB + kb] = (__bf16)bv;
+      } else {
+        As[mm * kGP + (kk & 1) * 16 + (kk >> 1)] = av;
+        Bs[nn * kGP + (kb & 1) * 16 + (kb >> 1)] = bv;
+      }
     }
     __syncthreads();
-    const f32x4* pa = (const f32x4*)&As[(wm + li) * kGP + lh * 16];
-    const f32x4* pb = (const f32x4*)&Bs[(wn + li) * kGP + lh * 16];
-    f32x4 av[4], bv[4];
+    if constexpr (BF) {
+      // lane l: row (col) l % 32 of the wave's tile, k = 16 s + 8 (l / 32) + e
 #pragma unroll
-    for (int u = 0; u < 4; ++u) { av[u] = pa[u]; bv[u] = pb[u]; }
+      for (int s = 0; s < 2; ++s) {
+        const bf16x8 a = *(const bf16x8*)&Ab[(wm + li) * kGPB + 16 * s + 8 * lh];
+        const bf16x8 b = *(const bf16x8*)&Bb[(wn + li) * kGPB + 16 * s + 8 * lh];
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+      }
+    } else {
+      const f32x4* pa = (const f32x4*)&As[(wm + li) * kGP + lh * 16];
+      const f32x4* pb = (const f32x4*)&Bs[(wn + li) * kGP + lh * 16];
+      f32x4 av[4], bv[4];
 #pragma unroll
-    for (int s = 0; s < 16; ++s)
-      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av[s >> 2][s & 3], bv[s >> 2][s & 3], acc, 0, 0, 0);
+      for (int u = 0; u < 4; ++u) { av[u] = pa[u]; bv[u] = pb[u]; }
+#pragma unroll
+      for (int s = 0; s < 16; ++s)
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av[s >> 2][s & 3], bv[s >> 2][s & 3], acc, 0, 0, 0);
+    }
     __syncthreads();
   }
 #pragma unroll
@@ -170,11 +197,15 @@ __global__ __launch_bounds__(1024) void k_stat_final(const double* mean, const d
 
 hipError_t launch_gemm(const float* A, long long sam, long long sak, const float* B, long long sbk,
                        long long sbn, float* C, long long scm, long long M, long long Nc, long long K,
-                       float alpha, float beta, const float* bias, int relu, hipStream_t st) {
+                       float alpha, float beta, const float* bias, int relu, hipStream_t st, int bf16) {
   if (M <= 0 || Nc <= 0) return hipSuccess;
   dim3 grid((unsigned)((M + kGT - 1) / kGT), (unsigned)((Nc + kGT - 1) / kGT));
-  hipLaunchKernelGGL(k_gemm, grid, dim3(256), 0, st, A, sam, sak, B, sbk, sbn, C, scm, M, Nc, K, alpha,
-                     beta, bias, relu);
+  if (bf16)
+    hipLaunchKernelGGL(k_gemm<true>, grid, dim3(256), 0, st, A, sam, sak, B, sbk, sbn, C, scm, M, Nc, K, alpha,
+                       beta, bias, relu);
+  else
+    hipLaunchKernelGGL(k_gemm<false>, grid, dim3(256), 0, st, A, sam, sak, B, sbk, sbn, C, scm, M, Nc, K, alpha,
+                       beta, bias, relu);
   return hipGetLastError();
 }
 

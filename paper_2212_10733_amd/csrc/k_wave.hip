@@ -857,7 +857,8 @@ __global__ __launch_bounds__(256, 2) void k_residual_w(GridDev G, ResidualArgs a
     const double d0 = (kLadderMargin * tau_h) / G.den;
     if (mx * (1.0 / d0) >= kQMax) raw = true;
     if (!raw) {
-      int lo = 0, hi = kLadder;
+      // bisection over the ladder, or the user's step (an empty search)
+      int lo = a.ub_k < 0 ? 0 : a.ub_k, hi = a.ub_k < 0 ? kLadder : a.ub_k + 1;
       while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
         const double Dk = ladder(d0, mid);

@@ -1,5 +1,5 @@
 """Training of the dense autoencoder with the library's own kernels (Section III Stage 2,
-Eq. 5; Section IV-B: Adam, z-scored inputs, a random sampler).
+Eq. 5; Sections IV-C and IV-D: Adam, z-scored inputs, a random sampler).
 
 `DenseAE.apply(x, params)` is a torch.autograd.Function whose forward and backward are
 hcz_ae_forward / hcz_ae_backward; `mse` wraps hcz_mse; `Trainer` runs Adam
@@ -45,8 +45,11 @@ def unpack(p: torch.Tensor, N: int) -> dict:
 
 
 class DenseAE(torch.autograd.Function):
+    """apply(x, params, compute=hcz.COMPUTE_FP32): with hcz.COMPUTE_BF16 every product of the
+    forward and backward pass takes bfloat16 operands (FP32 accumulation and master weights)."""
+
     @staticmethod
-    def forward(ctx, x: torch.Tensor, params: torch.Tensor):
+    def forward(ctx, x: torch.Tensor, params: torch.Tensor, compute: int = hcz.COMPUTE_FP32):
         x = x.contiguous()
         B, N = x.shape
         nbytes = C.c_size_t()
@@ -54,9 +57,10 @@ class DenseAE(torch.autograd.Function):
         saved = torch.empty(max(nbytes.value, 4) // 4, dtype=torch.float32, device=x.device)
         z = torch.empty((B, hcz.LATENT), dtype=torch.float32, device=x.device)
         xh = torch.empty((B, N), dtype=torch.float32, device=x.device)
-        _check(LIB.hcz_ae_forward(N, _ptr(params), _ptr(x), B, _ptr(z), _ptr(xh), _ptr(saved),
+        _check(LIB.hcz_ae_forward(N, compute, _ptr(params), _ptr(x), B, _ptr(z), _ptr(xh), _ptr(saved),
                                   saved.numel() * 4, _stream()))
         ctx.save_for_backward(x, params, saved)
+        ctx.compute = compute
         return z, xh
 
     @staticmethod
@@ -68,9 +72,9 @@ class DenseAE(torch.autograd.Function):
         dz = None if dz is None else dz.contiguous()
         if dxh is None:
             dxh = torch.zeros_like(x)
-        _check(LIB.hcz_ae_backward(N, _ptr(params), _ptr(x), B, _ptr(dz), _ptr(dxh.contiguous()), _ptr(saved),
-                                   saved.numel() * 4, _ptr(grad), _ptr(dx), _stream()))
-        return dx, grad
+        _check(LIB.hcz_ae_backward(N, ctx.compute, _ptr(params), _ptr(x), B, _ptr(dz), _ptr(dxh.contiguous()),
+                                   _ptr(saved), saved.numel() * 4, _ptr(grad), _ptr(dx), _stream()))
+        return dx, grad, None
 
 
 def pack_conv(W: dict, device="cuda") -> torch.Tensor:
@@ -147,8 +151,14 @@ def mse(xh, x):
 class Trainer:
     """Adam on the packed parameter vector with hcz_adam_step (FP32 master weights)."""
 
-    def __init__(self, params: torch.Tensor, lr=1e-3, betas=(0.9, 0.999), eps=1e-8, arch: str = "dense"):
+    def __init__(self, params: torch.Tensor, lr=1e-3, betas=(0.9, 0.999), eps=1e-8, arch: str = "dense",
+                 compute: str = "fp32"):
+        """compute: "fp32", or "bf16" (dense model only): bfloat16 operands in every product,
+        FP32 accumulation, FP32 master weights and Adam state."""
+        if compute not in ("fp32", "bf16") or (compute == "bf16" and arch != "dense"):
+            raise ValueError("compute must be 'fp32', or 'bf16' with the dense model")
         self.arch = arch
+        self.compute = hcz.COMPUTE_BF16 if compute == "bf16" else hcz.COMPUTE_FP32
         self.p = params.detach().clone().contiguous()
         self.m = torch.zeros_like(self.p)
         self.v = torch.zeros_like(self.p)
@@ -163,7 +173,7 @@ class Trainer:
 
     def train_step(self, xb: torch.Tensor) -> torch.Tensor:
         p = self.p.detach().requires_grad_(True)
-        _, xh = (ConvAE if self.arch == "conv" else DenseAE).apply(xb, p)
+        _, xh = ConvAE.apply(xb, p) if self.arch == "conv" else DenseAE.apply(xb, p, self.compute)
         loss = mse(xh, xb)
         loss.backward()
         self.step(p.grad)
@@ -188,10 +198,10 @@ class Trainer:
         return losses
 
 
-# ---- data selection and incremental training (Section IV-C) --------------------------------
+# ---- data selection and incremental training (Section IV-D) --------------------------------
 
 def colrandind(planes: int, nodes: int, seed: int = 0) -> np.ndarray:
-    """Training rows chosen like the paper's column-random-index scheme (Section IV-C,
+    """Training rows chosen like the paper's column-random-index scheme (Section IV-D,
     Fig. 5): the batch holds planes x nodes histograms (row r * nodes + m); for every mesh
     node m one plane r_m is drawn uniformly, giving `nodes` rows, one per node, in node
     order.  The draw is NumPy PCG64 with the given seed."""
@@ -202,11 +212,11 @@ def colrandind(planes: int, nodes: int, seed: int = 0) -> np.ndarray:
 
 
 def incremental(params: torch.Tensor, X: torch.Tensor, epochs: int = 2, batch: int = 1024, lr: float = 1e-3,
-                seed: int = 0) -> tuple:
-    """Incremental training (Section IV-C): continue a model trained on an earlier batch
+                seed: int = 0, compute: str = "fp32") -> tuple:
+    """Incremental training (Section IV-D): continue a model trained on an earlier batch
     with `epochs` passes over the current batch's z-scored rows X, with fresh Adam moments.
     Returns (Trainer, per-epoch losses)."""
-    tr = Trainer(params, lr=lr)
+    tr = Trainer(params, lr=lr, compute=compute)
     return tr, tr.fit(X, epochs=epochs, batch=batch, seed=seed)
 
 

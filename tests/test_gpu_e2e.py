@@ -350,3 +350,31 @@ def test_multiplier_truncation(H, ctx, bits):
     out = cz.decompress(comp, 500).cpu().numpy()
     err = moments.qoi_rel_error(moments.qoi(F.astype(np.float64), g), moments.qoi(out, g), g)[ok]
     assert 2.0 ** -(bits + 12) < err.max() < 2.0 ** -(bits - 10)
+
+
+@pytest.mark.parametrize("shape,level", [((39, 39), 0), ((39, 39), 7), ((39, 39), 40), ((33, 37), 3),
+                                         ((65, 65), 0), ((65, 65), 9)])
+def test_user_specified_step_end_to_end(H, ctx, shape, level):
+    """The 'ub' setting (the coder's step given, no search) on the compiled 39 x 39 wave
+    kernel, the run-time-table wave kernel (33 x 37) and the workgroup kernel (65 x 65),
+    coder-only: records and flags byte-exact against the oracle, k* equal to the level on
+    every coded histogram, decompressed data equal to the oracle's, and at level 0 the
+    bound and the QoIs on the GPU's own output."""
+    n_perp, n_par = shape
+    say("ub", shape, level)
+    g = grid.make_grid(n_par, n_perp)
+    Hn = 300
+    F = synth.histograms(Hn, n_par, n_perp, seed=47, dtype=np.float32)
+    cz = H.Compressor(H.Plan(ctx, n_par, n_perp), None, Hn, H.params(tau=1e-3, ub_level=level))
+    comp = cz.compress(torch.from_numpy(F).cuda())
+    ref = pipeline.compress(F, g, None, None, pipeline.Params(tau=1e-3, ub_level=level))
+    flags = comp.flags.cpu().numpy()
+    assert comp.stream_bytes() == ref["stream"]
+    assert np.array_equal(flags, ref["flags"])
+    coded = (flags & 5) == 1
+    assert coded.any() and np.all(ref["kstar"][coded] == level)
+    out = cz.decompress(comp, Hn).cpu().numpy()
+    refout = pipeline.decompress(ref, g, None, None, Hn)
+    assert np.allclose(out, refout, rtol=1e-10, atol=1e-13 * np.abs(F).max())
+    if level == 0:
+        check_roundtrip(F, out, flags, 1e-3, g)

@@ -234,7 +234,7 @@ def test_warm_start_network_cuts_newton_iterations(T):
 
 
 def test_incremental_training(T):
-    """Incremental training (Section IV-C) on a drifting series: a model trained on step 0
+    """Incremental training (Section IV-D) on a drifting series: a model trained on step 0
     and continued for 2 epochs on step 1 (rows chosen one per mesh node, column-random-
     index style) fits step 1 better than before the update and better than 2 epochs from
     scratch; its first update is the oracle's Adam step from the same weights."""
@@ -318,3 +318,128 @@ def test_conv_model_forward_backward_and_training(T):
     tr = train.Trainer(train.pack_conv(synth.conv_ae_weights()), lr=1e-3, arch="conv")
     losses = tr.fit(Xt, epochs=6, batch=256)
     assert losses[-1] < 0.7 * losses[0], losses
+
+
+def _bf(a):
+    return oracle.ae.bf16(np.asarray(a, np.float32)).astype(np.float64)
+
+
+def _product_ok(got, A, B, add=None, what=""):
+    """got (the kernel's FP32 result) against bf16(A) @ bf16(B) (+ add) in FP64.  The matrix
+    cores multiply bfloat16 operands exactly and only the FP32 sums round: at most one
+    rounding of 2^-24 of the running sum per term of the K-long sum, so
+    |got - exact| <= K 2^-24 (|bf16 A| @ |bf16 B|), plus one rounding of the result."""
+    a, b = _bf(A), _bf(B)
+    exact = a @ b + (0.0 if add is None else add)
+    K = a.shape[1]
+    tol = K * 2.0 ** -23 * (np.abs(a) @ np.abs(b)) + 2.0 ** -22 * np.abs(exact) + 1e-30
+    err = np.abs(got.astype(np.float64) - exact)
+    assert np.all(err <= tol), (what, float((err / tol).max()))
+    return exact
+
+
+def test_bf16_training_products_stage_exact(T):
+    """BF16 training form, stage by stage through the C-ABI: every product of the forward
+    and backward pass is checked against the oracle's bfloat16-operand product of the
+    kernel's own inputs (exact in FP64) within the FP32 summation bound; bias gradients
+    against FP64 column sums."""
+    hcz, train = T
+    N, B, Hd, Ld = 1521, 200, 128, 16
+    say("bf16 training products", B)
+    C = train.C
+    W = weights(N, seed=13)
+    X = inputs(B, N, seed=14)
+    rng = np.random.default_rng(15)
+    dxh = (rng.normal(size=(B, N)) * 1e-3).astype(np.float32)
+    dz_in = (rng.normal(size=(B, Ld)) * 1e-2).astype(np.float32)
+    p = train.pack(W)
+    x = torch.from_numpy(X).cuda()
+    nbytes = C.c_size_t()
+    train._check(train.LIB.hcz_ae_saved_bytes(N, B, C.byref(nbytes)))
+    saved = torch.zeros(nbytes.value // 4, dtype=torch.float32, device="cuda")
+    z = torch.empty((B, Ld), dtype=torch.float32, device="cuda")
+    xh = torch.empty((B, N), dtype=torch.float32, device="cuda")
+    train._check(train.LIB.hcz_ae_forward(N, hcz.COMPUTE_BF16, train._ptr(p), train._ptr(x), B, train._ptr(z),
+                                          train._ptr(xh), train._ptr(saved), nbytes.value, None))
+    torch.cuda.synchronize()
+    s = saved.cpu().numpy()
+    h1, h3 = s[:B * Hd].reshape(B, Hd), s[B * Hd:2 * B * Hd].reshape(B, Hd)
+    zg, xhg = z.cpu().numpy(), xh.cpu().numpy()
+    # h1 = relu(.): compare the pre-activation where it is positive, zero elsewhere
+    ex1 = _bf(X) @ _bf(W["W1"].T) + W["b1"]
+    tol1 = N * 2.0 ** -23 * (np.abs(_bf(X)) @ np.abs(_bf(W["W1"].T))) + 2.0 ** -22 * np.abs(ex1)
+    assert np.all(np.abs(h1 - np.maximum(ex1, 0)) <= tol1)
+    _product_ok(zg, h1, W["W2"].T, W["b2"], "z")
+    ex3 = _bf(zg) @ _bf(W["W3"].T) + W["b3"]
+    tol3 = Ld * 2.0 ** -23 * (np.abs(_bf(zg)) @ np.abs(_bf(W["W3"].T))) + 2.0 ** -22 * np.abs(ex3)
+    assert np.all(np.abs(h3 - np.maximum(ex3, 0)) <= tol3)
+    _product_ok(xhg, h3, W["W4"].T, W["b4"], "xhat")
+    # backward with dL/dxhat = dxh and an extra dL/dz = dz_in
+    grad = torch.empty_like(p)
+    dx = torch.empty_like(x)
+    dxh_d, dz_d = torch.from_numpy(dxh).cuda(), torch.from_numpy(dz_in).cuda()
+    train._check(train.LIB.hcz_ae_backward(N, hcz.COMPUTE_BF16, train._ptr(p), train._ptr(x), B, train._ptr(dz_d),
+                                           train._ptr(dxh_d), train._ptr(saved), nbytes.value, train._ptr(grad),
+                                           train._ptr(dx), None))
+    torch.cuda.synchronize()
+    s = saved.cpu().numpy()
+    d3 = s[2 * B * Hd:3 * B * Hd].reshape(B, Hd)
+    d1 = s[3 * B * Hd:4 * B * Hd].reshape(B, Hd)
+    dz = s[4 * B * Hd:4 * B * Hd + B * Ld].reshape(B, Ld)
+    g = train.unpack(grad, N)
+    _product_ok(g["W4"], dxh.T, h3, None, "dW4")
+    assert np.allclose(g["b4"], dxh.astype(np.float64).sum(0), rtol=2.0 ** -23, atol=1e-30)
+    mask3 = h3 > 0
+    ed3 = _bf(dxh) @ _bf(W["W4"])
+    td3 = N * 2.0 ** -23 * (np.abs(_bf(dxh)) @ np.abs(_bf(W["W4"])))
+    assert np.all(np.abs(d3 - ed3 * mask3) <= td3 + 1e-30)
+    _product_ok(g["W3"], d3.T, zg, None, "dW3")
+    _product_ok(dz, d3, W["W3"], dz_in, "dz")
+    _product_ok(g["W2"], dz.T, h1, None, "dW2")
+    assert np.allclose(g["b2"], dz.astype(np.float64).sum(0), rtol=2.0 ** -23, atol=1e-30)
+    ed1 = _bf(dz) @ _bf(W["W2"])
+    td1 = Ld * 2.0 ** -23 * (np.abs(_bf(dz)) @ np.abs(_bf(W["W2"])))
+    assert np.all(np.abs(d1 - ed1 * (h1 > 0)) <= td1 + 1e-30)
+    _product_ok(g["W1"], d1.T, X, None, "dW1")
+    assert np.allclose(g["b1"], d1.astype(np.float64).sum(0), rtol=2.0 ** -23, atol=1e-30)
+    _product_ok(dx.cpu().numpy(), d1, W["W1"], None, "dx")
+
+
+def test_bf16_training_end_to_end(T):
+    """BF16 training against the oracle: the gradients of one step agree with the oracle's
+    BF16 form (FP64 sums; its own rounding decisions) to 1e-2 in norm and with the FP64
+    gradients to 3e-2, and training with bfloat16 operands follows FP32 training."""
+    hcz, train = T
+    N, B = 1521, 256
+    say("bf16 training end to end")
+    W = weights(N, seed=16)
+    X = inputs(B, N, seed=17)
+    x = torch.from_numpy(X).cuda()
+    p = train.pack(W).requires_grad_(True)
+    _, xh = train.DenseAE.apply(x, p, hcz.COMPUTE_BF16)
+    loss = train.mse(xh, x)
+    loss.backward()
+    g = train.unpack(p.grad, N)
+    c16 = oracle.ae.dense_forward_train(X, W, rnd=oracle.ae.bf16)
+    g16 = oracle.ae.dense_backward(c16, W, rnd=oracle.ae.bf16)
+    W64 = {k: v.astype(np.float64) for k, v in W.items()}
+    g64 = oracle.ae.dense_backward(oracle.ae.dense_forward_train(X.astype(np.float64), W64), W64)
+    assert loss.item() == pytest.approx(oracle.ae.mse(c16["xh"], X.astype(np.float64)), rel=1e-4)
+    for k in train.KEYS:
+        n16 = np.linalg.norm(g[k] - g16[k]) / np.linalg.norm(g16[k])
+        n64 = np.linalg.norm(g[k] - g64[k]) / np.linalg.norm(g64[k])
+        assert n16 < 1e-2 and n64 < 3e-2, (k, n16, n64)
+    say("bf16 training run")
+    ctx = hcz.Context(0)
+    plan = hcz.Plan(ctx)
+    Ftr = torch.from_numpy(synth.histograms(8192, seed=synth.SEED_TRAIN, dtype=np.float32)).cuda()
+    mu, sd = hcz.norm_stats(plan, Ftr)
+    Xt = ((Ftr.reshape(8192, -1) - mu) / sd).contiguous()
+    W0 = synth.dense_ae_weights()
+    l32 = train.Trainer(train.pack(W0), lr=1e-3).fit(Xt, epochs=8, batch=512)
+    l16 = train.Trainer(train.pack(W0), lr=1e-3, compute="bf16").fit(Xt, epochs=8, batch=512)
+    say("losses fp32", l32, "bf16", l16)
+    assert l16[-1] < 0.6 * l16[0]
+    assert abs(l16[-1] - l32[-1]) < 0.15 * l32[-1], (l16, l32)
+    with pytest.raises(ValueError):
+        train.Trainer(train.pack(W0), compute="bf16", arch="conv")

@@ -1,4 +1,4 @@
-"""Host logic of incremental training (Section IV-C): the column-random-index selection
+"""Host logic of incremental training (Section IV-D): the column-random-index selection
 of training rows and the drifting synthetic series (CPU)."""
 import numpy as np
 import pytest
