@@ -13,7 +13,7 @@ FP64 (plus `math.fsum` for correctly rounded moment sums), written from the pape
   conv      convolutional autoencoder for 39 x 39 grids, BF16 form (Section III Stage 2)
   pq        per-dimension product-quantizer fit (1-D k-means) and encode
                                                                   (Section III Stage 3, IV-E)
-  coder     multilevel residual coder with bound bisection        (Section III Stage 4)
+  coder     multilevel residual coder with its bound search       (Section III Stage 4)
   newton    Lagrange / Newton projection restoring the moments    (Section III Stage 5, Eq. 6)
   pipeline  compress / decompress of a batch                      (Section III, Fig. 1)
   metrics   NRMSE and compression ratio                           (Eq. 7, Section IV-A)

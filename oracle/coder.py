@@ -23,8 +23,10 @@ Delta_0 = 2 (1 - 2^-19) tau_h / (sqrt(N) (L+1)); q = rint(d / Delta_k) (round ha
 even, via multiplication by 1/Delta_k).  Level 0 always meets the bound, since each
 recomposition level adds at most Delta/2 to a convex combination of coarser errors.
 feasible(k): sum (r - T^-1(Delta_k q))^2 <= thr^2, thr = (1 - 2^-20) tau_h.
-The bound search is a bisection over k in [0, 41): lo = 0, hi = 41, mid = (lo+hi) >> 1
-(the paper's 'ab'); with a user-specified step ('ub') the ladder index is given and there is
+The bound search (the paper's 'ab', a binary search): by default an exponential search from
+the predicted index round(4 log2(L+1)) that brackets the feasibility boundary, then a
+bisection of the bracket; optionally the bisection over k in [0, 41) alone: lo = 0, hi = 41,
+mid = (lo+hi) >> 1.  With a user-specified step ('ub') the ladder index is given and there is
 no search (Section IV-F).
 
 Record: header = Delta_k* (f64 LE), k* (u8), nlev = L+1 (u8), one bit width per
@@ -217,6 +219,77 @@ def bisect(r: np.ndarray, d: np.ndarray, d0: np.ndarray, thr: np.ndarray, lay: L
         idx = np.nonzero(act)[0]
         lo[idx[ok]] = mid[idx[ok]]
         hi[idx[~ok]] = mid[idx[~ok]]
+    q = quantize(d, ladder(d0, lo))
+    rh = reconstruct(q, ladder(d0, lo), lay)
+    return lo, q, rh
+
+
+def search_start(lay: Layout) -> int:
+    """Ladder index where the guided search starts: round(4 log2(L+1)).  Independent uniform
+    quantisation errors have variance Delta^2/12 per coefficient; the recomposition adds the
+    coarser levels' interpolated errors, about three times that per cell, so the error
+    estimate N Delta^2 / 4 meets tau_h^2 at Delta = 2 tau_h / sqrt(N) = (L+1) Delta_0,
+    i.e. k = 4 log2(L+1) (margins ignored)."""
+    return int(min(NLADDER - 1, math.floor(4.0 * math.log2(lay.L + 1) + 0.5)))
+
+
+def search(r: np.ndarray, d: np.ndarray, d0: np.ndarray, thr: np.ndarray, lay: Layout,
+           start: int | None = None, feasible_at=None):
+    """Bound search over the ladder for a batch; returns (k*, q, rhat).
+
+    start None: bisection over [0, 41) (lo = 0, hi = 41, mid = (lo+hi) >> 1).
+    start k_g: exponential search from a predicted index (Bentley and Yao), then the same
+    bisection: probe k_g; if it is feasible, probe k_g+1, k_g+3, k_g+7, ... (steps doubling)
+    until one is infeasible or past 40; otherwise probe k_g-1, k_g-3, ... until one is
+    feasible or at most 0 (index 0 is feasible by construction).  The last feasible and the
+    first infeasible probe bracket the bisection.  Either way k* is feasible and k*+1 is
+    infeasible or 41.  feasible_at(rows, k) replaces the feasibility test (for checking the
+    search alone)."""
+    H = r.shape[0] if r is not None else d.shape[0]
+    if feasible_at is None:
+        def feasible_at(rows, k):
+            ok, _, _ = feasible(r[rows], d[rows], ladder(d0[rows], k), thr[rows], lay)
+            return ok
+    lo = np.zeros(H, np.int64)
+    hi = np.full(H, NLADDER, np.int64)
+    step = np.ones(H, np.int64)
+    # phase 0: first probe, 1: climbing, 2: descending, 3: bisection
+    phase = np.full(H, 3 if start is None else 0, np.int64)
+    kg = 0 if start is None else int(min(max(start, 0), NLADDER - 1))
+    while True:
+        up = (phase == 1) & (lo + step >= NLADDER)
+        phase[up] = 3
+        down = (phase == 2) & (hi - step <= 0)
+        lo[down] = 0
+        phase[down] = 3
+        act = (phase != 3) | (hi - lo > 1)
+        if not act.any():
+            break
+        t = np.where(phase == 0, kg, np.where(phase == 1, lo + step,
+                     np.where(phase == 2, hi - step, (lo + hi) >> 1)))
+        rows = np.nonzero(act)[0]
+        ok = np.zeros(H, bool)
+        ok[rows] = feasible_at(rows, t[rows])
+        p0, p1, p2, p3 = (act & (phase == i) for i in range(4))
+        # first probe
+        lo[p0 & ok] = kg
+        hi[p0 & ~ok] = kg
+        phase[p0] = np.where(ok[p0], 1, 2)
+        # climbing: a feasible probe moves lo and doubles the step, an infeasible one brackets
+        lo[p1 & ok] = t[p1 & ok]
+        step[p1 & ok] *= 2
+        hi[p1 & ~ok] = t[p1 & ~ok]
+        phase[p1 & ~ok] = 3
+        # descending: an infeasible probe moves hi and doubles the step, a feasible one brackets
+        hi[p2 & ~ok] = t[p2 & ~ok]
+        step[p2 & ~ok] *= 2
+        lo[p2 & ok] = t[p2 & ok]
+        phase[p2 & ok] = 3
+        # bisection
+        lo[p3 & ok] = t[p3 & ok]
+        hi[p3 & ~ok] = t[p3 & ~ok]
+    if r is None:
+        return lo
     q = quantize(d, ladder(d0, lo))
     rh = reconstruct(q, ladder(d0, lo), lay)
     return lo, q, rh

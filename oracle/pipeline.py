@@ -7,7 +7,7 @@ Compress, per histogram (FP64):
   4. z = encoder(f), codes = PQ(z), fhat = decoder(codebook[codes]) (Stages 2-3);
      without a model fhat = 0 (the MGARD-only pipeline the paper compares against);
   5. r = f - fhat; coded iff ||r||^2 > thr^2, thr = (1 - 2^-20) tau_h (Stage 4 selection);
-  6. coded: multilevel coefficients, bound bisection, record (Stage 4);
+  6. coded: multilevel coefficients, bound search, record (Stage 4);
   7. ft = fhat + rhat; Newton projection onto A x = b, x >= 0 (Stage 5);
   8. outputs: codes, multipliers, flags, residual records.
 Decompress: fhat from the codes, rhat from the record, ft = fhat + rhat,
@@ -45,6 +45,7 @@ class Params:
     kl: bool = False                # True: the KL / I-divergence correction (multiplicative)
     lambda_bits: int = 0            # > 0: multipliers rounded to this many mantissa bits
     ub_level: int | None = None     # None: searched coder step ('ab'); 0..40: the user's step ('ub')
+    search: str = "guided"          # 'ab' search: "guided" (from the predicted index) or "bisect"
 
 
 def round_mantissa(v: np.ndarray, bits: int) -> np.ndarray:
@@ -145,7 +146,8 @@ def compress(F: np.ndarray, g: Grid, model: dict | None, C: np.ndarray | None, p
         keep = ~big
         if keep.any():
             if p.ub_level is None:
-                ks, qs, rh = coder.bisect(r[act], d[keep], d0[act], thr[act], lay)
+                start = coder.search_start(lay) if p.search == "guided" else None
+                ks, qs, rh = coder.search(r[act], d[keep], d0[act], thr[act], lay, start)
             else:
                 ks, qs, rh = coder.at_level(d[keep], d0[act], p.ub_level, lay)
             kstar[act], q[act], rhat[act] = ks, qs, rh

@@ -129,3 +129,72 @@ def test_pack_unpack_identity_and_size(shape):
     assert widths[0] == 0
     assert len(rec) == coder.record_size(widths, lay)
     assert len(rec) % 4 == 0 and lay.header_bytes % 8 == 0
+
+
+def test_guided_search_against_brute_force():
+    """The exponential search from a predicted index followed by bisection, on its own with
+    made-up feasibility: for every monotone boundary b (0..40 feasible up to b) and every
+    start, it returns b; for arbitrary non-monotone patterns (index 0 always feasible) it
+    returns a feasible k whose successor is infeasible or 41, and without a start it is the
+    plain bisection."""
+    K = coder.NLADDER
+    for start in range(K):
+        b = np.arange(K)
+        got = coder.search(None, np.zeros((K, 1, 1)), None, None, None, start,
+                           feasible_at=lambda rows, k: k <= b[rows])
+        assert np.array_equal(got, b), start
+    rng = np.random.default_rng(9)
+    pat = rng.random((500, K)) < rng.random((500, 1))
+    pat[:, 0] = True
+    for start in (None, 0, 5, 11, 40):
+        got = coder.search(None, np.zeros((500, 1, 1)), None, None, None, start,
+                           feasible_at=lambda rows, k: pat[rows, k])
+        assert np.all(pat[np.arange(500), got])
+        nxt = np.minimum(got + 1, K - 1)
+        assert np.all((got == K - 1) | ~pat[np.arange(500), nxt])
+        if start is None:
+            for h in range(500):
+                lo, hi = 0, K
+                while hi - lo > 1:
+                    mid = (lo + hi) // 2
+                    lo, hi = (mid, hi) if pat[h, mid] else (lo, mid)
+                assert got[h] == lo
+
+
+def test_guided_search_start_and_agreement_on_residuals():
+    """The start index round(4 log2(L+1)) for the grids in use, and on real residuals the
+    guided search lands where the bisection does (feasibility is monotone there)."""
+    assert coder.search_start(coder.layout(39, 39)) == 11       # L = 6
+    assert coder.search_start(coder.layout(3, 3)) == 4          # L = 1
+    assert coder.search_start(coder.layout(65, 65)) == 11       # L = 6
+    assert coder.search_start(coder.layout(12, 12)) == 9        # L = 4
+    lay = coder.layout(39, 39)
+    from paper_2212_10733_amd import synth
+    F = synth.histograms(40, seed=8, dtype=np.float64)
+    rng = np.random.default_rng(4)
+    r = F - F.mean(axis=0) + rng.normal(size=F.shape) * 1e-3 * F.max()
+    th = np.geomspace(1e-4, 0.5, 40) * np.sqrt((r * r).sum((1, 2)))
+    thr = coder.SEL_MARGIN * th
+    d = coder.decompose(r, lay)
+    d0 = coder.delta0(th, lay)
+    kb, qb, rb = coder.bisect(r, d, d0, thr, lay)
+    probes = np.zeros(40, np.int64)
+
+    def counted(rows, k):
+        probes[rows] += 1
+        ok, _, _ = coder.feasible(r[rows], d[rows], coder.ladder(d0[rows], k), thr[rows], lay)
+        return ok
+
+    kg = coder.search(None, d, d0, thr, lay, coder.search_start(lay), feasible_at=counted)
+    _, qg, rg = coder.search(r, d, d0, thr, lay, coder.search_start(lay))
+    assert len(np.unique(kb)) > 5
+    # the exit property on real residuals; k* equals the bisection's on most histograms
+    # (where feasibility is not monotone each may stop at a different boundary)
+    for k in (kg, kb):
+        ok, _, _ = coder.feasible(r, d, coder.ladder(d0, k), thr, lay)
+        assert ok.all()
+        ok1, _, _ = coder.feasible(r, d, coder.ladder(d0, np.minimum(k + 1, 40)), thr, lay)
+        assert np.all((k == 40) | ~ok1)
+    assert (kg == kb).mean() >= 0.6
+    assert np.array_equal(qg, coder.quantize(d, coder.ladder(d0, kg)))
+    assert probes.mean() < 4.5
