@@ -41,19 +41,39 @@ def residual_flops(N: int, H: int, coded: int, steps_per_coded: float, newton_pa
     return per_cell * N
 
 
-def bisection_steps(kstar_hist) -> float:
-    """Mean number of bound evaluations of the bisection over the 41-step ladder: each
-    final step k* has exactly one search path."""
+def search_steps(kstar_hist, start: int | None = 11) -> float:
+    """Mean number of bound evaluations of the ladder search for the measured k*
+    distribution, counted on a ladder whose feasibility is monotone (k feasible iff k <= k*):
+    the exponential search from `start` (the default search; 11 = round(4 log2(L+1)) for
+    the 39 x 39 grid, L = 6) followed by bisection, or with start None the bisection over
+    the 41-step ladder alone."""
     def steps(k):
-        lo, hi, n = 0, 41, 0
-        while hi - lo > 1:
-            mid = (lo + hi) >> 1
+        lo, hi, step, n = 0, 41, 1, 0
+        phase = 3 if start is None else 0
+        while True:
+            if phase == 1 and lo + step >= 41:
+                phase = 3
+            if phase == 2 and hi - step <= 0:
+                lo, phase = 0, 3
+            if phase == 3 and hi - lo <= 1:
+                return n
+            t = start if phase == 0 else lo + step if phase == 1 else hi - step if phase == 2 else (lo + hi) >> 1
+            ok = t <= k
             n += 1
-            if mid <= k:
-                lo = mid
+            if phase == 0:
+                lo, hi, phase = (t, hi, 1) if ok else (lo, t, 2)
+            elif phase == 1:
+                if ok:
+                    lo, step = t, step * 2
+                else:
+                    hi, phase = t, 3
+            elif phase == 2:
+                if ok:
+                    lo, phase = t, 3
+                else:
+                    hi, step = t, step * 2
             else:
-                hi = mid
-        return n
+                lo, hi = (t, hi) if ok else (lo, t)
     tot = sum(kstar_hist)
     return sum(c * steps(k) for k, c in enumerate(kstar_hist)) / tot if tot else 0.0
 
@@ -597,7 +617,7 @@ def main() -> int:
     stage_ms = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in prof.items() if v[1]}
     N = plan.N
     coded = st["n_coded"]
-    steps_coded = bisection_steps(st["kstar_hist"])
+    steps_coded = search_steps(st["kstar_hist"])
     passes = st["newton_iters_total"] + (H - st["n_raw"])
     ae_flops = 2.0 * H * N * 128 + 2.0 * H * 128 * 16
     cands = {

@@ -58,6 +58,7 @@ enum { HCZ_COMPUTE_FP32 = 0, HCZ_COMPUTE_BF16 = 1 };      /* autoencoder arithme
 enum { HCZ_TAU_REL_L2 = 0, HCZ_TAU_NRMSE = 1 };          /* tau_h = tau ||f||, tau sqrt(N)(max-min) */
 enum { HCZ_FALLBACK_BACKTRACK = 0, HCZ_FALLBACK_PAPER = 1 };
 enum { HCZ_BOUND_AB = 0, HCZ_BOUND_UB = 1 };                /* coder step: searched, user-specified */
+enum { HCZ_SEARCH_GUIDED = 0, HCZ_SEARCH_BISECT = 1 };      /* how the coder step is searched */
 enum { HCZ_FLAG_CODED = 1, HCZ_FLAG_ROUND2 = 2, HCZ_FLAG_RAW = 4, HCZ_FLAG_WARM_REJECTED = 8,
        HCZ_FLAG_NOCLIP = 16, HCZ_FLAG_KL = 32 };
 enum { HCZ_WARM_COLD = 0, HCZ_WARM_MLP = 1 };
@@ -169,7 +170,15 @@ typedef struct {
  *                  the bound still holds; a larger ub_level trades the bound for ratio and
  *                  nothing checks ||f - f~|| against tau_h.  The selection (coded iff
  *                  ||r|| > (1 - 2^-20) tau_h) is the same in both modes.
- * ub_level         0..40, read only with HCZ_BOUND_UB. */
+ * ub_level         0..40, read only with HCZ_BOUND_UB.
+ * search           how HCZ_BOUND_AB searches the ladder.  HCZ_SEARCH_GUIDED (0): an
+ *                  exponential search from the predicted index round(4 log2(L+1)) (where an
+ *                  estimate of independent quantisation errors meets tau_h): probe it, then
+ *                  climb (+1, +3, +7, ...) while feasible or descend (-1, -3, ...) while
+ *                  infeasible, and bisect the bracket; about half the probes of a plain
+ *                  bisection on smooth data.  HCZ_SEARCH_BISECT (1): bisection over [0, 41).
+ *                  Both end on a feasible k* whose successor is infeasible (or k* = 40);
+ *                  where feasibility is not monotone in k they may end on different k*. */
 typedef struct {
   double tau;
   int32_t tau_mode;
@@ -188,6 +197,7 @@ typedef struct {
   int32_t lambda_bits;
   int32_t bound_mode;
   int32_t ub_level;
+  int32_t search;
 } hcz_params;
 
 /* Run statistics, written to device memory by compress and read with hcz_stats_read. */

@@ -412,6 +412,7 @@ hcz_status check_params(const hcz_params* p) {
   if (p->bound_mode != HCZ_BOUND_AB && p->bound_mode != HCZ_BOUND_UB) return fail(HCZ_EINVAL, "bound_mode");
   if (p->bound_mode == HCZ_BOUND_UB && (p->ub_level < 0 || p->ub_level > 40))
     return fail(HCZ_EINVAL, "ub_level must be in [0, 40]");
+  if (p->search != HCZ_SEARCH_GUIDED && p->search != HCZ_SEARCH_BISECT) return fail(HCZ_EINVAL, "search");
   return HCZ_OK;
 }
 
@@ -894,6 +895,7 @@ static hcz_status residual_impl(const hcz_plan* plan, const hcz_params* p, const
   a.kl = p->kl;
   a.lambda_bits = p->lambda_bits;
   a.ub_k = p->bound_mode == HCZ_BOUND_UB ? p->ub_level : -1;
+  a.k_start = p->search == HCZ_SEARCH_BISECT ? -1 : std::min(kLadder - 1, (int)std::floor(4.0 * std::log2(G.L + 1.0) + 0.5));
   a.flags = out->flags;
   a.sizes = (uint64_t*)(ws + L.sizes);
   a.slots = ws + L.slots;

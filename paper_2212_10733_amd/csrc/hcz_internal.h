@@ -114,7 +114,8 @@ struct ResidualArgs {
   int no_positivity;           // 1: projection onto {A x = b} only (flag HCZ_FLAG_NOCLIP)
   int kl;                      // 1: KL correction where it keeps the bound (flag HCZ_FLAG_KL)
   int lambda_bits;             // 0, or stored multipliers rounded to this many mantissa bits
-  int ub_k;                    // -1: bisection over the ladder; 0..40: this ladder step, no search
+  int ub_k;                    // -1: search the ladder; 0..40: this ladder step, no search
+  int k_start;                 // -1: bisection over [0, 41); else the exponential search's first probe
   uint8_t* flags;              // [H]
   uint64_t* sizes;             // [H] record bytes
   uint8_t* slots;              // [H][slot_stride] staging
@@ -308,6 +309,41 @@ __device__ __forceinline__ double ladder_c(int m) {
 __device__ __forceinline__ double ladder(double d0, int k) {
   return __dmul_rn(ldexp(d0, k >> 2), ladder_c(k & 3));
 }
+
+// The bound search over the ladder, uniform across the threads that run it: a bisection
+// of [lo, hi), optionally preceded by an exponential search from k_start that brackets the
+// feasibility boundary (probe k_start; climb +1, +3, +7, ... while feasible, or descend
+// -1, -3, ... while infeasible).  next() gives the next probe or -1 when k* = lo is found.
+struct LadderSearch {
+  int lo, hi, step, phase, k0;   // phase 0: first probe, 1: climbing, 2: descending, 3: bisection
+  __device__ __forceinline__ void init(int ub_k, int k_start) {
+    step = 1;
+    k0 = k_start;
+    lo = 0;
+    hi = kLadder;
+    phase = k_start < 0 ? 3 : 0;
+    if (ub_k >= 0) { lo = ub_k; hi = ub_k + 1; phase = 3; }
+  }
+  __device__ __forceinline__ int next() {
+    if (phase == 1 && lo + step >= kLadder) phase = 3;
+    if (phase == 2 && hi - step <= 0) { lo = 0; phase = 3; }
+    if (phase == 0) return k0;
+    if (phase == 1) return lo + step;
+    if (phase == 2) return hi - step;
+    return hi - lo > 1 ? (lo + hi) >> 1 : -1;
+  }
+  __device__ __forceinline__ void result(int t, bool ok) {
+    if (phase == 0) {
+      if (ok) { lo = t; phase = 1; } else { hi = t; phase = 2; }
+    } else if (phase == 1) {
+      if (ok) { lo = t; step <<= 1; } else { hi = t; phase = 3; }
+    } else if (phase == 2) {
+      if (ok) { lo = t; phase = 3; } else { hi = t; step <<= 1; }
+    } else {
+      if (ok) lo = t; else hi = t;
+    }
+  }
+};
 
 // Per-cell constraint coefficients vol * phi_k and the correction A^T lambda, in one
 // fixed order shared by compression and decompression.

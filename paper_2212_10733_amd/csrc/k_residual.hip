@@ -348,17 +348,17 @@ __global__ __launch_bounds__(NT) void k_residual(GridDev G, ResidualArgs a) {
     const double d0 = (kLadderMargin * tau_h) / G.den;
     if (mx * (1.0 / d0) >= kQMax) raw = true;
     if (!raw) {
-      // bisection over the ladder, or the user's step (an empty search)
-      int lo = a.ub_k < 0 ? 0 : a.ub_k, hi = a.ub_k < 0 ? kLadder : a.ub_k + 1, at = -1;
-      while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        const double Dk = ladder(d0, mid);
+      // the bound search over the ladder, or the user's step (an empty search)
+      LadderSearch S;
+      S.init(a.ub_k, a.k_start);
+      int at = -1;
+      for (int t = S.next(); t >= 0; t = S.next()) {
+        const double Dk = ladder(d0, t);
         const double e2 = recompose_err<NT, NPT>(G, buf, red, gm, em, cm, dm, rm, Dk, 1.0 / Dk);
-        at = mid;
-        if (e2 <= thr2) lo = mid;
-        else hi = mid;
+        at = t;
+        S.result(t, e2 <= thr2);
       }
-      kst = lo;
+      kst = S.lo;
       if (at != kst) {
         const double Dk = ladder(d0, kst);
         recompose_err<NT, NPT>(G, buf, red, gm, em, cm, dm, rm, Dk, 1.0 / Dk);

@@ -857,17 +857,16 @@ __global__ __launch_bounds__(256, 2) void k_residual_w(GridDev G, ResidualArgs a
     const double d0 = (kLadderMargin * tau_h) / G.den;
     if (mx * (1.0 / d0) >= kQMax) raw = true;
     if (!raw) {
-      // bisection over the ladder, or the user's step (an empty search)
-      int lo = a.ub_k < 0 ? 0 : a.ub_k, hi = a.ub_k < 0 ? kLadder : a.ub_k + 1;
-      while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        const double Dk = ladder(d0, mid);
+      // the bound search over the ladder, or the user's step (an empty search)
+      LadderSearch S;
+      S.init(a.ub_k, a.k_start);
+      for (int t = S.next(); t >= 0; t = S.next()) {
+        const double Dk = ladder(d0, t);
         const double inv = 1.0 / Dk;
         const double e2 = recompose_w<SH, false>(G, L, R, rm, [&](int s) { return __dmul_rn(Dk, rint(__dmul_rn(dm[s], inv))); });
-        if (e2 <= thr2) lo = mid;
-        else hi = mid;
+        S.result(t, e2 <= thr2);
       }
-      kst = lo;
+      kst = S.lo;
       const double Dk = ladder(d0, kst);
       const double inv = 1.0 / Dk;
       // zigzag integers and per-group widths (wave-uniform, in registers); the payload

@@ -24,6 +24,7 @@ FALLBACK_BACKTRACK, FALLBACK_PAPER = 0, 1
 FLAG_CODED, FLAG_ROUND2, FLAG_RAW, FLAG_WARM_REJECTED, FLAG_NOCLIP, FLAG_KL = 1, 2, 4, 8, 16, 32
 WARM_COLD, WARM_MLP = 0, 1
 BOUND_AB, BOUND_UB = 0, 1
+SEARCH_GUIDED, SEARCH_BISECT = 0, 1
 HIDDEN, LATENT = 128, 16
 
 STATUS = {0: "HCZ_OK", -1: "HCZ_EINVAL", -2: "HCZ_ENOMEM", -3: "HCZ_EHIP",
@@ -77,7 +78,8 @@ class Params(C.Structure):
                 ("fallback", C.c_int32), ("fit_codebook", C.c_int32), ("sample_every", C.c_int32),
                 ("warm_start", C.c_int32), ("mlp", C.c_void_p), ("lambda_fp32", C.c_int32),
                 ("no_positivity", C.c_int32), ("tau_hist", C.c_void_p), ("kl", C.c_int32),
-                ("lambda_bits", C.c_int32), ("bound_mode", C.c_int32), ("ub_level", C.c_int32)]
+                ("lambda_bits", C.c_int32), ("bound_mode", C.c_int32), ("ub_level", C.c_int32),
+                ("search", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -331,10 +333,14 @@ class Model:
 def params(tau=1e-3, tau_mode=TAU_REL_L2, newton_s=1.0, newton_max_iter=50, newton_max_iter2=400,
            fallback=FALLBACK_BACKTRACK, fit_codebook=False, sample_every=16, mlp=None, lambda_fp32=False,
            no_positivity=False, tau_hist: torch.Tensor | None = None, kl=False, lambda_bits: int = 0,
-           ub_level: int | None = None) -> Params:
+           ub_level: int | None = None, search: str = "guided") -> Params:
     """tau_hist: optional per-histogram bounds (device, float64, one per histogram), used in
     place of tau.  ub_level: None searches the coder's step per histogram ('ab'); an
-    integer 0..40 quantises every coded histogram with that ladder step ('ub')."""
+    integer 0..40 quantises every coded histogram with that ladder step ('ub').  search:
+    "guided" (exponential search from the predicted ladder index, then bisection) or
+    "bisect" (bisection over the whole ladder)."""
+    if search not in ("guided", "bisect"):
+        raise ValueError("search must be 'guided' or 'bisect'")
     if tau_hist is not None and (tau_hist.dtype != torch.float64 or not tau_hist.is_cuda
                                  or not tau_hist.is_contiguous()):
         raise ValueError("tau_hist must be a contiguous float64 device tensor")
@@ -342,7 +348,8 @@ def params(tau=1e-3, tau_mode=TAU_REL_L2, newton_s=1.0, newton_max_iter=50, newt
                int(fit_codebook), sample_every, WARM_MLP if mlp is not None else WARM_COLD,
                None if mlp is None else mlp.h, int(lambda_fp32), int(no_positivity),
                None if tau_hist is None else tau_hist.data_ptr(), int(kl), int(lambda_bits),
-               BOUND_AB if ub_level is None else BOUND_UB, 0 if ub_level is None else int(ub_level))
+               BOUND_AB if ub_level is None else BOUND_UB, 0 if ub_level is None else int(ub_level),
+               SEARCH_BISECT if search == "bisect" else SEARCH_GUIDED)
     p._mlp = mlp          # keep the network and the bounds alive as long as the parameters
     p._tau_hist = tau_hist
     return p

@@ -378,3 +378,25 @@ def test_user_specified_step_end_to_end(H, ctx, shape, level):
     assert np.allclose(out, refout, rtol=1e-10, atol=1e-13 * np.abs(F).max())
     if level == 0:
         check_roundtrip(F, out, flags, 1e-3, g)
+
+
+@pytest.mark.parametrize("shape,search", [((39, 39), "bisect"), ((39, 39), "guided"), ((33, 37), "bisect"),
+                                          ((65, 65), "bisect"), ((65, 65), "guided")])
+def test_search_modes_end_to_end(H, ctx, shape, search):
+    """Both ways of searching the coder's step (exponential search from the predicted index,
+    or bisection over the whole ladder) on the three kernel paths, coder-only, at a tight
+    and a loose bound: records, offsets and flags byte-exact against the oracle's same
+    search, the bound and the QoIs on the GPU's own output."""
+    n_perp, n_par = shape
+    g = grid.make_grid(n_par, n_perp)
+    Hn = 300
+    F = synth.histograms(Hn, n_par, n_perp, seed=48, dtype=np.float32)
+    for tau in (1e-4, 3e-2):
+        say("search", shape, search, tau)
+        cz = H.Compressor(H.Plan(ctx, n_par, n_perp), None, Hn, H.params(tau=tau, search=search))
+        comp = cz.compress(torch.from_numpy(F).cuda())
+        ref = pipeline.compress(F, g, None, None, pipeline.Params(tau=tau, search=search))
+        assert comp.stream_bytes() == ref["stream"]
+        assert np.array_equal(comp.offsets.cpu().numpy().astype(np.uint64), ref["offsets"])
+        assert np.array_equal(comp.flags.cpu().numpy(), ref["flags"])
+        check_roundtrip(F, cz.decompress(comp, Hn).cpu().numpy(), comp.flags.cpu().numpy(), tau, g)

@@ -230,20 +230,24 @@ def oracle_residual(F, fhat, g, p, lam0=None):
             if np.abs(d).max() * (1.0 / d0[h]) >= coder.QMAX:
                 raw[h] = True
             else:
-                ks, q, rh = coder.bisect(r[h:h + 1], d, d0[h:h + 1], thr[h:h + 1], lay)
+                # the search, recording the distance of every feasibility decision on its path
+                # from the threshold
+                margins = [abs(rr[h] - thr[h] ** 2) / thr[h] ** 2]
+
+                def probe(rows, k, h=h, d=d):
+                    Dk = coder.ladder(d0[h:h + 1], np.asarray(k))
+                    e2 = coder.sumsq(r[h:h + 1] - coder.reconstruct(coder.quantize(d, Dk), Dk, lay))[0]
+                    margins.append(abs(e2 - thr[h] ** 2) / thr[h] ** 2)
+                    return np.array([e2 <= thr[h] ** 2])
+
+                start = coder.search_start(lay) if p.search == "guided" else None
+                ks = coder.search(None, d, d0[h:h + 1], thr[h:h + 1], lay, start, feasible_at=probe)
+                Dk = coder.ladder(d0[h:h + 1], ks)
+                q = coder.quantize(d, Dk)
+                rh = coder.reconstruct(q, Dk, lay)
                 out["kstar"][h] = ks[0]
-                rec = coder.pack(q[0], coder.ladder(d0[h:h + 1], ks)[0], int(ks[0]), lay)
-                # distance of every feasibility decision on the search path from its threshold
-                m = abs(rr[h] - thr[h] ** 2) / thr[h] ** 2
-                lo, hi = 0, coder.NLADDER
-                while hi - lo > 1:
-                    mid = (lo + hi) // 2
-                    Dk = coder.ladder(d0[h:h + 1], np.array([mid]))
-                    qq = coder.quantize(d, Dk)
-                    e2 = coder.sumsq(r[h:h + 1] - coder.reconstruct(qq, Dk, lay))[0]
-                    m = min(m, abs(e2 - thr[h] ** 2) / thr[h] ** 2)
-                    lo, hi = (mid, hi) if e2 <= thr[h] ** 2 else (lo, mid)
-                out["margin"][h] = m
+                rec = coder.pack(q[0], Dk[0], int(ks[0]), lay)
+                out["margin"][h] = min(margins)
                 fh[h] = fh[h] + rh[0]
         elif not raw[h]:
             out["margin"][h] = abs(rr[h] - thr[h] ** 2) / max(thr[h] ** 2, 1e-300)
