@@ -195,8 +195,9 @@ def ub_form(hcz, plan, model, x, args) -> dict:
 
 
 def container_form(hcz, plan, x, W, args, n=131072) -> dict:
-    """The output container of the plain form on the first n histograms: bytes without and
-    with the rANS coding of codes and residual bytes, and the host pack / unpack rates
+    """The output container of the plain form on the first n histograms: bytes without
+    entropy coding, with the byte-wise rANS of codes, residual bytes and multipliers, and
+    with the residual records coded by their integers, and the host pack / unpack rates
     (single thread) including the device-to-host copies."""
     import torch
     xs = x[:n]
@@ -215,14 +216,14 @@ def container_form(hcz, plan, x, W, args, n=131072) -> dict:
                   weights=hcz.pack_dense_weights(W), norm_mean=mu, norm_std=sd, arch="dense")
     t_copy = time.perf_counter() - t0
     res = {"histograms": n, "input_bytes": n * plan.N * 4, "d2h_seconds": t_copy}
-    for ent in (False, True):
+    for ent, name in ((0, "plain"), (1, "rans"), (2, "rans_integers")):
         t0 = time.perf_counter()
         buf = hcz.container_pack(plan.n_par, plan.n_perp, entropy=ent, **arrays)
         t1 = time.perf_counter()
         d = hcz.container_unpack(buf)
         t2 = time.perf_counter()
         assert np.array_equal(d["res_bytes"], arrays["res_bytes"])
-        res["rans" if ent else "plain"] = {"bytes": len(buf), "ratio": n * plan.N * 4 / len(buf),
+        res[name] = {"bytes": len(buf), "ratio": n * plan.N * 4 / len(buf),
                                            "pack_MBps": len(buf) / (t1 - t0) / 1e6,
                                            "unpack_MBps": len(buf) / (t2 - t1) / 1e6}
     del cz, comp, model
@@ -363,9 +364,37 @@ def batched_form(hcz, ctx, args, n_sub=512, reps=3) -> dict:
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / reps
     done = sb.completion_seconds()
-    live = np.array([c > 0 for _, c, _ in layout])
     st = {k: c.stats() for k, c in comps.items()}
+    # the launch variant of every grid's residual stage from the autotuner, then the whole
+    # batch as one HIP graph
+    import tempfile
+    from paper_2212_10733_amd import autotune
+    tuned = {}
+    with tempfile.TemporaryDirectory() as td:
+        for n in synth.BATCH_GRIDS:
+            v = autotune.apply(plans[n], os.path.join(td, "tune.json"), H=16384, reps=3)
+            tuned[f"{n}x{n}"] = {"variant": v, "ms_per_16384": autotune.load(os.path.join(td, "tune.json"))[
+                autotune.plan_key(plans[n])]["ms"]}
+    sb.compress(inputs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        sb.compress(inputs)
+    torch.cuda.synchronize()
+    dt_tuned = (time.perf_counter() - t0) / reps
+    sb.capture(inputs)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        sb.replay()
+    torch.cuda.synchronize()
+    dt_graph = (time.perf_counter() - t0) / reps
+    small = _small_batch_graph(hcz, batched, synth, plans, torch)
+    for n in synth.BATCH_GRIDS:
+        plans[n].set_variant("auto")
+    live = np.array([c > 0 for _, c, _ in layout])
     res = {"subdomains": n_sub, "histograms": Htot, "input_bytes": nbytes, "value": Htot / dt,
+           "tuned": {"variants": tuned, "value": Htot / dt_tuned, "ms_per_step": dt_tuned * 1e3},
+           "graph": {"value": Htot / dt_graph, "ms_per_step": dt_graph * 1e3}, "small_batch": small,
            "unit": "histograms/s", "ms_per_step": dt * 1e3, "input_GBps": nbytes / dt / 1e9,
            "completion_ms_p50": float(np.percentile(done[live], 50) * 1e3),
            "completion_ms_p99": float(np.percentile(done[live], 99) * 1e3),
@@ -377,6 +406,33 @@ def batched_form(hcz, ctx, args, n_sub=512, reps=3) -> dict:
     del sb, comps, inputs, models, plans
     torch.cuda.empty_cache()
     return res
+
+
+def _small_batch_graph(hcz, batched, synth, plans, torch, n_sub=64, reps=20) -> dict:
+    """64 small subdomains (50..500 histograms, coder-only) on the four grids: eager calls
+    against replays of the captured batch, where launch overhead is a visible share."""
+    layout = synth.subdomains(n_sub, seed=55, count_range=(50, 500))
+    inputs = {}
+    for n in synth.BATCH_GRIDS:
+        Hn = sum(c for g, c, _ in layout if g == n)
+        inputs[n] = torch.from_numpy(synth.histograms(max(Hn, 1), n, n, seed=56 + n, dtype=np.float32)[:Hn]).cuda()
+    sb = batched.SubdomainBatch(plans, {}, layout)
+    Htot = sum(c for _, c, _ in layout)
+    sb.compress(inputs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        sb.compress(inputs)
+    torch.cuda.synchronize()
+    dt_e = (time.perf_counter() - t0) / reps
+    sb.capture(inputs)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        sb.replay()
+    torch.cuda.synchronize()
+    dt_g = (time.perf_counter() - t0) / reps
+    return {"subdomains": n_sub, "histograms": Htot, "eager_ms": dt_e * 1e3, "graph_ms": dt_g * 1e3,
+            "eager_value": Htot / dt_e, "graph_value": Htot / dt_g}
 
 
 def incremental_form(hcz, plan, H, W, args, steps=4, planes=8) -> dict:
@@ -657,8 +713,29 @@ def main() -> int:
     bound_ratio = (dist[ok] / (args.tau * n0[ok])).max().item()
     extra["max_qoi_rel_err"] = qerr
     extra["max_err_over_tau_h"] = bound_ratio
+    # decompression (dequantize + decode + residual records + correction) on its own, into
+    # the same FP64 output: reads codes, multipliers, flags, offsets and records, writes 8N
+    ctx.profile(True)
+    ctx.profile_read()
+    reps = 3
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        cz.decompress_into(comp, H, out, in_dtype=torch.float32)
+    e1.record()
+    e1.synchronize()
+    dms = e0.elapsed_time(e1) / reps
+    dprof = ctx.profile_read()
+    ctx.profile(False)
+    dbytes = H * (16 + 32 + 1 + 8 + 8 * N) + stream_bytes
+    extra["decompress"] = {"value": H / (dms / 1e3), "unit": "histograms/s", "ms": dms,
+                           "stage_ms": {k: round(v[0] / v[1], 4) for k, v in dprof.items() if v[1]},
+                           "alg_bytes": dbytes, "GB/s": dbytes / (dms / 1e3) / 1e9,
+                           "hbm_frac": dbytes / (dms / 1e3) / 1e9 / PEAK_HBM_GBS}
     del out
 
+    log("measured ceilings")
+    extra["ceilings"] = hcz.ceilings()
     forms = {}
     if not args.no_forms:
         if "tau" in args.forms:

@@ -249,10 +249,35 @@ void hcz_plan_destroy(hcz_plan* plan);
    HCZ_PATH_BLOCK one workgroup per histogram (grids too large for one wave),
    HCZ_PATH_WAVE one wave per histogram with the slot structure read at run time,
    HCZ_PATH_WAVE_FIXED one wave per histogram with a slot structure compiled in
-   (the 39 x 39 grid with uniform cell volumes).  Results are identical on every path.
+   (the 39 x 39 grid with uniform cell volumes).  Records and flags are identical on every
+   path; multipliers agree to the Newton stopping rule.
    Errors: HCZ_EINVAL for a NULL argument. */
 enum { HCZ_PATH_BLOCK = 0, HCZ_PATH_WAVE = 1, HCZ_PATH_WAVE_FIXED = 2 };
 hcz_status hcz_plan_path(const hcz_plan* plan, int32_t* path);
+
+/* Launch variants of the residual stage (hcz_compress, hcz_residual) for tuning: the
+ * kernel family and its shape, i.e. waves per histogram and nodes per thread.
+ *   HCZ_VARIANT_AUTO          the default choice of hcz_plan_path (and 256 x 6, 512 x 5 or
+ *                             512 x 9 threads x nodes per thread on the workgroup kernel,
+ *                             the smallest that holds the grid);
+ *   HCZ_VARIANT_WAVE_FIXED    one wave per histogram, slot structure compiled in (the 39 x 39
+ *                             grid with uniform cell volumes only);
+ *   HCZ_VARIANT_WAVE          one wave per histogram, slot structure read at run time
+ *                             (grids whose nodes fit 26 slots of 64);
+ *   HCZ_VARIANT_BLOCK_256x6, _512x5, _512x9   the workgroup kernel with that many threads and
+ *                             nodes per thread (N at most 1,536, 2,560, 4,608).
+ * Every variant gives the same records, offsets and flags; the multipliers agree to the
+ * Newton stopping rule (the kernel families sum in different orders, so their last bits
+ * may differ).  The KL reading always runs on the workgroup kernel
+ * (a wave variant then means AUTO).  hcz_plan_variants writes the variants valid for the
+ * plan's grid (at most 8) to list (host) and their count to *n; hcz_plan_set_variant makes
+ * one of them the plan's choice for later calls (not thread-safe against calls in flight
+ * on other threads).  Errors: HCZ_EINVAL for a NULL argument, HCZ_EUNSUPPORTED for a
+ * variant the grid does not allow. */
+enum { HCZ_VARIANT_AUTO = 0, HCZ_VARIANT_WAVE_FIXED = 1, HCZ_VARIANT_WAVE = 2, HCZ_VARIANT_BLOCK_256x6 = 3,
+       HCZ_VARIANT_BLOCK_512x5 = 4, HCZ_VARIANT_BLOCK_512x9 = 5 };
+hcz_status hcz_plan_variants(const hcz_plan* plan, int32_t* list, int32_t* n);
+hcz_status hcz_plan_set_variant(hcz_plan* plan, int32_t variant);
 
 /* Copy an autoencoder to the device for `plan`'s grid (N = n_par * n_perp). */
 hcz_status hcz_model_load(hcz_plan* plan, const hcz_model_desc* desc, hcz_model** out);
@@ -353,7 +378,12 @@ hcz_status hcz_wall_clock_hz(int device, double* hz);
  * weights with the z-score statistics, the quantized codes, the PQ table, the residual
  * bytes (flags, record sizes, records) and the Lagrange multipliers.  entropy = 1 codes
  * the codes, the residual bytes and the multipliers with an order-0 byte-wise rANS coder
- * (12-bit frequencies, one table per section).  Every pointer here is a host pointer; the caller
+ * (12-bit frequencies, one table per section); entropy = 2 codes the residual records
+ * by their integers instead: the headers and verbatim records as one byte stream, every
+ * zigzag integer's bit length as a byte symbol in the stream of its coefficient group
+ * (each stream with its own rANS table) and its bits below the leading one raw; unpacking
+ * re-packs the integers with the records' widths, byte for byte (packing refuses a coded
+ * record not in the coder's format).  Every pointer here is a host pointer; the caller
  * copies the device arrays of hcz_compressed to the host first.  Unpacking checks every
  * size against the buffer and fails with HCZ_EINVAL on a malformed or truncated buffer,
  * without reading past it. */
@@ -364,7 +394,9 @@ typedef struct {
   int32_t compute;         /* HCZ_COMPUTE_* of the model */
   int32_t latent, bits;    /* codes per histogram and bits per code (model only) */
   int32_t lambda_fp32;     /* multipliers stored as FP32 */
-  int32_t entropy;         /* 1: rANS-coded codes and residual bytes */
+  int32_t entropy;         /* 0: none; 1: rANS-coded codes, residual bytes and multipliers;
+                              2: as 1, with the residual records coded by their integers
+                              (per-group magnitude classes plus raw low bits) */
   int64_t n_weights;       /* floats in the weight blob of hcz_model_desc */
   uint64_t res_bytes;      /* residual record bytes (read_info output) */
   uint64_t total_bytes;    /* container size (read_info output) */
@@ -475,6 +507,21 @@ hcz_status hcz_dequantize(const uint8_t* codes, int64_t n, int32_t latent, const
 /* Warm-start multipliers lam0 [H][4] (FP64) of the network for codes [H][16]. */
 hcz_status hcz_mlp_predict(const hcz_mlp* mlp, const uint8_t* codes, const hcz_codebook* cb, int64_t H,
                            double* lam0, hcz_stream_t stream);
+
+/* ---- measured ceilings (measurement infrastructure, not part of compression) ----------
+ * hcz_probe_copy: a streaming device-to-device copy of `bytes` (a multiple of 16, both
+ * pointers 16-byte aligned; device), for the practical HBM rate.  hcz_probe_compute: a
+ * launch of 2,048 workgroups of 256 threads whose loops keep every SIMD busy with
+ * independent FP64 fused multiply-adds (8 chains per lane), FP32 matrix-core operations
+ * (v_mfma_f32_32x32x2f32, 4 chains per wave) or BF16 matrix-core operations
+ * (v_mfma_f32_32x32x16_bf16), `iters` times; *flops (host) receives the launch's operation
+ * count (FMA = 2).  sink: device scratch of hcz_probe_sink_bytes bytes; its contents are
+ * meaningless.  Errors: HCZ_EINVAL for NULL, misaligned or negative arguments or an unknown
+ * kind, HCZ_EHIP when the launch fails. */
+enum { HCZ_PROBE_FP64_FMA = 0, HCZ_PROBE_FP32_MFMA = 1, HCZ_PROBE_BF16_MFMA = 2 };
+hcz_status hcz_probe_sink_bytes(size_t* bytes);
+hcz_status hcz_probe_copy(const void* src, void* dst, size_t bytes, hcz_stream_t stream);
+hcz_status hcz_probe_compute(int32_t kind, int64_t iters, void* sink, double* flops, hcz_stream_t stream);
 
 /* ---- stage timing ---------------------------------------------------------------------
  * With profiling on, hcz_compress and hcz_decompress record a HIP event pair around every

@@ -7,7 +7,9 @@ hcz_compress call with per-histogram bounds (hcz_segment_tau expands the per-sub
 tau); every grid size has its own plan, model and codebook.  The residual stage stamps the
 device wall clock as each histogram finishes, and hcz_segment_max turns those stamps into
 per-subdomain completion times.  Allocation happens at construction; compress() only
-launches.
+launches, so the whole batch (every grid size) can be recorded once into a HIP graph
+(capture) and rerun with a single launch (replay).  With a tuning cache, each grid's
+residual launch variant comes from the autotuner.
 """
 from __future__ import annotations
 
@@ -19,10 +21,17 @@ from . import hcz
 
 class SubdomainBatch:
     def __init__(self, plans: dict, models: dict, layout: list, bits: int = 8, sample_every: int = 16,
-                 device="cuda", **param_kw):
+                 device="cuda", tune_cache: str | None = None, **param_kw):
         """plans / models: grid key -> Plan / Model (or None: the coder-only pipeline);
-        layout: [(grid key, count, tau)] in batch order."""
+        layout: [(grid key, count, tau)] in batch order; tune_cache: a JSON file of the
+        autotuner (read, and extended on a miss) to choose each plan's launch variant."""
         self.layout = list(layout)
+        if tune_cache is not None:
+            from . import autotune
+            for k in plans:
+                if any(g == k for g, _, _ in self.layout):
+                    autotune.apply(plans[k], tune_cache)
+        self.graph = None
         self.keys = [k for k in plans if any(g == k for g, _, _ in self.layout)]
         self.groups = {}
         for k in self.keys:
@@ -58,6 +67,25 @@ class SubdomainBatch:
             self.done[k] = hcz.segment_max(g["start"], comp.t_done)
             out[k] = comp
         return out
+
+    def capture(self, inputs: dict) -> dict:
+        """Record compress(inputs) into a HIP graph (torch.cuda.CUDAGraph, default stream
+        priority) after one eager call; returns the graph's outputs, which replay()
+        refreshes.  The inputs must stay at the same device addresses."""
+        self.compress(inputs)
+        torch.cuda.synchronize()
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            self.graph_out = self.compress(inputs)
+        torch.cuda.synchronize()
+        return self.graph_out
+
+    def replay(self) -> dict:
+        """Rerun the captured batch (asynchronous); the outputs are those capture() returned."""
+        if self.graph is None:
+            raise RuntimeError("capture() first")
+        self.graph.replay()
+        return self.graph_out
 
     def completion_seconds(self) -> np.ndarray:
         """Seconds from the start of the last compress() to each subdomain's last histogram

@@ -121,6 +121,7 @@ struct hcz_plan {
   hcz_ctx* ctx;
   GridDev G;
   std::vector<void*> allocs;
+  int variant = HCZ_VARIANT_AUTO;
 };
 
 struct hcz_model {
@@ -579,6 +580,32 @@ hcz_status hcz_plan_create(hcz_ctx* ctx, const hcz_grid* g, hcz_plan** out) {
   return HCZ_OK;
 }
 
+hcz_status hcz_plan_variants(const hcz_plan* plan, int32_t* list, int32_t* n) {
+  if (!plan || !list || !n) return fail(HCZ_EINVAL, "NULL argument");
+  const GridDev& G = plan->G;
+  int k = 0;
+  list[k++] = HCZ_VARIANT_AUTO;
+  if (wave_fixed_path(G)) list[k++] = HCZ_VARIANT_WAVE_FIXED;
+  if (wave_path(G)) list[k++] = HCZ_VARIANT_WAVE;
+  if (G.N <= 256 * 6) list[k++] = HCZ_VARIANT_BLOCK_256x6;
+  if (G.N <= 512 * 5) list[k++] = HCZ_VARIANT_BLOCK_512x5;
+  if (G.N <= 512 * 9) list[k++] = HCZ_VARIANT_BLOCK_512x9;
+  *n = k;
+  return HCZ_OK;
+}
+
+hcz_status hcz_plan_set_variant(hcz_plan* plan, int32_t variant) {
+  if (!plan) return fail(HCZ_EINVAL, "NULL argument");
+  int32_t list[8], n = 0;
+  hcz_plan_variants(plan, list, &n);
+  for (int i = 0; i < n; ++i)
+    if (list[i] == variant) {
+      plan->variant = variant;
+      return HCZ_OK;
+    }
+  return fail(HCZ_EUNSUPPORTED, "variant %d is not valid for this grid", variant);
+}
+
 hcz_status hcz_plan_path(const hcz_plan* plan, int32_t* path) {
   if (!plan || !path) return fail(HCZ_EINVAL, "NULL argument");
   *path = wave_fixed_path(plan->G) ? HCZ_PATH_WAVE_FIXED : wave_path(plan->G) ? HCZ_PATH_WAVE : HCZ_PATH_BLOCK;
@@ -895,6 +922,7 @@ static hcz_status residual_impl(const hcz_plan* plan, const hcz_params* p, const
   a.kl = p->kl;
   a.lambda_bits = p->lambda_bits;
   a.ub_k = p->bound_mode == HCZ_BOUND_UB ? p->ub_level : -1;
+  a.variant = plan->variant;
   a.k_start = p->search == HCZ_SEARCH_BISECT ? -1 : std::min(kLadder - 1, (int)std::floor(4.0 * std::log2(G.L + 1.0) + 0.5));
   a.flags = out->flags;
   a.sizes = (uint64_t*)(ws + L.sizes);

@@ -10,12 +10,14 @@
 // u64 end of the residual section; u64 total size; u32 FNV-1a checksum of the first 40
 // header bytes.  Sections start at multiples of 8: weights (FP32 weights, mean, std),
 // codes [H][latent] (raw or rANS), PQ table [latent][2^bits] FP32, residual (flags [H],
-// record sizes [H] u32, the records back to back, raw or rANS), multipliers [H][4] (raw or
-// rANS).
+// record sizes [H] u32, the records back to back, raw or rANS, or with entropy = 2 (scheme
+// bit 5) split into headers and per-group integer symbols, see below), multipliers [H][4]
+// (raw or rANS).
 //
 // rANS (Duda's asymmetric numeral systems, range variant, byte-wise renormalisation):
 // 32-bit state kept in [2^23, 2^31), symbol frequencies quantised to 12 bits.  A coded
 // block is u64 n, u16 freq[256], u64 m, m bytes.
+#include <algorithm>
 #include <cstring>
 #include <vector>
 
@@ -149,6 +151,194 @@ bool rans_decode(const uint8_t* in, size_t avail, uint8_t* out, uint64_t n_expec
   return p == end && x == kL;
 }
 
+// ---- integer model of the residual records (entropy = 2) ----------------------------
+// A coded record is a header (Delta, k*, nlev, one bit width per coefficient group, zero
+// padding to 8 bytes) and the zigzag integers of the groups, coarsest first, each with its
+// group's width, packed LSB first.  Here the headers and the verbatim records go to one
+// byte stream; every integer u becomes its magnitude class c = bit length of u (0 for
+// u = 0) as a byte symbol in its group's stream, and the c - 1 bits of u below its leading
+// one go to a raw bit stream (LSB first).  The byte streams are rANS coded, each with its
+// own table.  Unpacking re-packs the integers with the header's widths, so the records
+// come back byte for byte.  The group sizes follow from the grid: with
+// G_l(n) = {i : i mod 2^l = 0} U {n - 1} and L = max over both axes of ceil(log2(n - 1)),
+// group 0 is G_L x G_L and group L - l + 1 is G_(l-1)^2 minus G_l^2.
+
+size_t set_1d(int n, int l) {
+  if (n <= 1) return 1;
+  const size_t m = (size_t)(n - 1);
+  return (m >> l) + 1 + ((m & (((size_t)1 << l) - 1)) ? 1 : 0);
+}
+
+std::vector<size_t> group_counts(int n_par, int n_perp) {
+  auto lev = [](int n) { int L = 0; while (n > 1 && (1 << L) < n - 1) ++L; return L; };
+  const int L = std::max(lev(n_par), lev(n_perp));
+  std::vector<size_t> g;
+  g.push_back(set_1d(n_par, L) * set_1d(n_perp, L));
+  for (int l = L; l >= 1; --l) g.push_back(set_1d(n_par, l - 1) * set_1d(n_perp, l - 1) - set_1d(n_par, l) * set_1d(n_perp, l));
+  return g;
+}
+
+struct IntStreams {
+  std::vector<uint8_t> side;                 // coded-record headers, verbatim records
+  std::vector<std::vector<uint8_t>> sym;     // per group, the magnitude class of each integer
+  std::vector<uint8_t> bits;                 // bits below the leading one, LSB first
+  uint64_t nbits = 0;
+  void put(uint32_t v, int n) {              // append the n low bits of v
+    for (int k = 0; k < n; ++k, ++nbits) {
+      if ((nbits & 7) == 0) bits.push_back(0);
+      bits.back() |= (uint8_t)(((v >> k) & 1u) << (nbits & 7));
+    }
+  }
+};
+
+int bit_length(uint32_t u) { return u ? 32 - __builtin_clz(u) : 0; }
+
+// Split the records of a batch into the streams; false if a coded record is not in the
+// coder's canonical form (nlev, widths <= 32, size, zero padding bits).
+bool split_records(int n_par, int n_perp, int64_t H, const uint8_t* flags, const uint64_t* off,
+                   const uint8_t* rec, IntStreams* s) {
+  const std::vector<size_t> cnt = group_counts(n_par, n_perp);
+  const size_t nlev = cnt.size(), hdr = (10 + nlev + 7) / 8 * 8;
+  s->sym.assign(nlev, {});
+  for (int64_t h = 0; h < H; ++h) {
+    const size_t size = (size_t)(off[h + 1] - off[h]);
+    if (!size) continue;
+    const uint8_t* r = rec + off[h];
+    if (flags[h] & HCZ_FLAG_RAW) {
+      s->side.insert(s->side.end(), r, r + size);
+      continue;
+    }
+    if (size < hdr || r[9] != nlev) return false;
+    size_t bits = 0;
+    for (size_t g = 0; g < nlev; ++g) {
+      if (r[10 + g] > 32) return false;
+      bits += cnt[g] * r[10 + g];
+    }
+    const size_t pay = 4 * ((bits + 31) / 32);
+    if (size != hdr + pay) return false;
+    s->side.insert(s->side.end(), r, r + hdr);
+    const uint8_t* p = r + hdr;
+    size_t pos = 0;
+    for (size_t g = 0; g < nlev; ++g) {
+      const int w = r[10 + g];
+      for (size_t k = 0; k < cnt[g]; ++k) {
+        uint64_t win = 0;
+        if (w) {
+          const size_t b0 = pos >> 3;
+          for (size_t j = 0; j < 8 && b0 + j < pay; ++j) win |= (uint64_t)p[b0 + j] << (8 * j);
+          win = (win >> (pos & 7)) & ((w == 32) ? 0xffffffffull : ((1ull << w) - 1));
+        }
+        pos += (size_t)w;
+        const uint32_t u = (uint32_t)win;
+        const int c = bit_length(u);
+        s->sym[g].push_back((uint8_t)c);
+        if (c > 1) s->put(u, c - 1);
+      }
+    }
+    // the padding after the last integer must be zero for an exact round trip
+    for (size_t q = pos; q < 8 * pay; ++q)
+      if ((p[q >> 3] >> (q & 7)) & 1) return false;
+  }
+  return true;
+}
+
+size_t int_streams_bound(const IntStreams& s) {
+  size_t b = rans_bound(s.side.size()) + 8 + s.bits.size();
+  for (const auto& v : s.sym) b += rans_bound(v.size());
+  return b;
+}
+
+size_t int_streams_write(const IntStreams& s, uint8_t* out) {
+  size_t o = rans_encode(s.side.data(), s.side.size(), out);
+  for (const auto& v : s.sym) o += rans_encode(v.data(), v.size(), out + o);
+  std::memcpy(out + o, &s.nbits, 8);
+  o += 8;
+  if (!s.bits.empty()) std::memcpy(out + o, s.bits.data(), s.bits.size());
+  return o + s.bits.size();
+}
+
+// Rebuild the records from the streams at in[0, avail); sizes and flags from the container.
+bool int_streams_read(int n_par, int n_perp, int64_t H, const uint8_t* flags, const uint64_t* off,
+                      const uint8_t* in, size_t avail, uint8_t* rec, size_t* used) {
+  const std::vector<size_t> cnt = group_counts(n_par, n_perp);
+  const size_t nlev = cnt.size(), hdr = (10 + nlev + 7) / 8 * 8;
+  // stream lengths: the side bytes and the symbols of each group follow from the records
+  size_t side_n = 0;
+  std::vector<size_t> sym_n(nlev, 0);
+  for (int64_t h = 0; h < H; ++h) {
+    const size_t size = (size_t)(off[h + 1] - off[h]);
+    if (!size) continue;
+    if (flags[h] & HCZ_FLAG_RAW) side_n += size;
+    else {
+      if (size < hdr) return false;
+      side_n += hdr;
+      for (size_t g = 0; g < nlev; ++g) sym_n[g] += cnt[g];
+    }
+  }
+  std::vector<uint8_t> side(side_n);
+  std::vector<std::vector<uint8_t>> sym(nlev);
+  size_t o = 0, u = 0;
+  if (!rans_decode(in, avail, side.data(), side_n, &u)) return false;
+  o += u;
+  for (size_t g = 0; g < nlev; ++g) {
+    sym[g].resize(sym_n[g]);
+    if (!rans_decode(in + o, avail - o, sym[g].data(), sym_n[g], &u)) return false;
+    o += u;
+  }
+  if (avail - o < 8) return false;
+  uint64_t nbits;
+  std::memcpy(&nbits, in + o, 8);
+  o += 8;
+  if (nbits / 8 > avail - o || (nbits + 7) / 8 > avail - o) return false;
+  const uint8_t* bits = in + o;
+  o += (size_t)((nbits + 7) / 8);
+  uint64_t bp = 0;
+  size_t si = 0;
+  std::vector<size_t> gi(nlev, 0);
+  for (int64_t h = 0; h < H; ++h) {
+    const size_t size = (size_t)(off[h + 1] - off[h]);
+    if (!size) continue;
+    uint8_t* r = rec + off[h];
+    if (flags[h] & HCZ_FLAG_RAW) {
+      std::memcpy(r, side.data() + si, size);
+      si += size;
+      continue;
+    }
+    std::memcpy(r, side.data() + si, hdr);
+    si += hdr;
+    if (r[9] != nlev) return false;
+    size_t nb = 0;
+    for (size_t g = 0; g < nlev; ++g) {
+      if (r[10 + g] > 32) return false;
+      nb += cnt[g] * r[10 + g];
+    }
+    const size_t pay = 4 * ((nb + 31) / 32);
+    if (size != hdr + pay) return false;
+    uint8_t* p = r + hdr;
+    std::memset(p, 0, pay);
+    size_t pos = 0;
+    for (size_t g = 0; g < nlev; ++g) {
+      const int w = r[10 + g];
+      for (size_t k = 0; k < cnt[g]; ++k) {
+        const int c = sym[g][gi[g]++];
+        if (c > w) return false;
+        uint32_t v = 0;
+        if (c > 0) {
+          if (bp + (uint64_t)(c - 1) > nbits) return false;
+          v = 1u << (c - 1);
+          for (int q = 0; q < c - 1; ++q, ++bp) v |= (uint32_t)((bits[bp >> 3] >> (bp & 7)) & 1u) << q;
+        }
+        uint64_t win = (uint64_t)v << (pos & 7);
+        for (size_t j = 0; win && j < 8; ++j, win >>= 8) p[(pos >> 3) + j] |= (uint8_t)(win & 0xff);
+        pos += (size_t)w;
+      }
+    }
+  }
+  if (bp != nbits) return false;
+  *used = o;
+  return true;
+}
+
 struct Sizes {
   size_t N, weights, codes_raw, pq, flags, recs, lam;
 };
@@ -202,9 +392,17 @@ hcz_status hcz_container_bound(const hcz_container_in* c, size_t* bytes) {
   Sizes z;
   if (!sizes_of(c->info, &z)) return set_error(HCZ_EINVAL, "bad container description");
   if (!c->res_offset) return set_error(HCZ_EINVAL, "res_offset is NULL");
+  if (c->info.entropy < 0 || c->info.entropy > 2) return set_error(HCZ_EINVAL, "entropy must be 0, 1 or 2");
   const size_t rb = (size_t)c->res_offset[c->info.H];
   const size_t codes = c->info.entropy ? rans_bound(z.codes_raw) : z.codes_raw;
-  const size_t res = c->info.entropy ? rans_bound(rb) : rb;
+  size_t res = c->info.entropy ? rans_bound(rb) : rb;
+  if (c->info.entropy == 2) {
+    if (c->info.H && (!c->flags || (rb && !c->res_bytes))) return set_error(HCZ_EINVAL, "NULL section");
+    IntStreams s;
+    if (!split_records(c->info.n_par, c->info.n_perp, c->info.H, c->flags, c->res_offset, c->res_bytes, &s))
+      return set_error(HCZ_EINVAL, "a coded residual record is not in the coder's format");
+    res = int_streams_bound(s);
+  }
   const size_t lam = c->info.entropy ? rans_bound(z.lam) : z.lam;
   *bytes = up8(kHeader) + up8(z.weights) + up8(codes) + up8(z.pq) + up8(z.flags + z.recs + res) + up8(lam);
   return HCZ_OK;
@@ -252,8 +450,13 @@ hcz_status hcz_container_pack(const hcz_container_in* c, void* out, size_t capac
   }
   o += z.recs;
   const size_t rb = (size_t)c->res_offset[H];
-  if (i.entropy) o += rans_encode(c->res_bytes, rb, b + o);
-  else {
+  if (i.entropy == 2) {
+    IntStreams s;
+    split_records(i.n_par, i.n_perp, H, c->flags, c->res_offset, c->res_bytes, &s);
+    o += int_streams_write(s, b + o);
+  } else if (i.entropy) {
+    o += rans_encode(c->res_bytes, rb, b + o);
+  } else {
     if (rb) std::memcpy(b + o, c->res_bytes, rb);
     o += rb;
   }
@@ -267,7 +470,7 @@ hcz_status hcz_container_pack(const hcz_container_in* c, void* out, size_t capac
   }
   // header
   const uint16_t scheme = (uint16_t)(i.arch | (i.compute == HCZ_COMPUTE_BF16 ? 4 : 0) | (i.lambda_fp32 ? 8 : 0) |
-                                     (i.entropy ? 16 : 0));
+                                     (i.entropy ? 16 : 0) | (i.entropy == 2 ? 32 : 0));
   const uint8_t lat = (uint8_t)(i.arch ? i.latent : 0), bits = (uint8_t)(i.arch ? i.bits : 0);
   const uint64_t HH = (uint64_t)H, tot = o;
   const uint16_t np = (uint16_t)i.n_par, nq = (uint16_t)i.n_perp;
@@ -313,7 +516,7 @@ hcz_status hcz_container_read_info(const void* buf, size_t n, hcz_container_info
   i.arch = scheme & 3;
   i.compute = (scheme & 4) ? HCZ_COMPUTE_BF16 : HCZ_COMPUTE_FP32;
   i.lambda_fp32 = (scheme & 8) ? 1 : 0;
-  i.entropy = (scheme & 16) ? 1 : 0;
+  i.entropy = (scheme & 32) ? 2 : ((scheme & 16) ? 1 : 0);
   i.latent = b[6];
   i.bits = b[7];
   const size_t N = (size_t)np * nq;
@@ -393,7 +596,12 @@ hcz_status hcz_container_unpack(const void* buf, size_t n, const hcz_container_o
     out->res_offset[h + 1] = out->res_offset[h] + r;
   }
   o += z.recs;
-  if (i.entropy) {
+  if (i.entropy == 2) {
+    size_t used = 0;
+    if (!int_streams_read(i.n_par, i.n_perp, i.H, out->flags, out->res_offset, b + o, res_end - o,
+                          out->res_bytes, &used) || o + used != res_end)
+      return set_error(HCZ_EINVAL, "malformed residual section");
+  } else if (i.entropy) {
     size_t used = 0;
     if (!rans_decode(b + o, res_end - o, out->res_bytes, i.res_bytes, &used) || o + used != res_end)
       return set_error(HCZ_EINVAL, "malformed residual section");

@@ -116,6 +116,7 @@ struct ResidualArgs {
   int lambda_bits;             // 0, or stored multipliers rounded to this many mantissa bits
   int ub_k;                    // -1: search the ladder; 0..40: this ladder step, no search
   int k_start;                 // -1: bisection over [0, 41); else the exponential search's first probe
+  int variant;                 // HCZ_VARIANT_*: kernel family and shape of the launch
   uint8_t* flags;              // [H]
   uint64_t* sizes;             // [H] record bytes
   uint8_t* slots;              // [H][slot_stride] staging

@@ -748,17 +748,26 @@ static int pick_nt(int N) { return N <= 1536 ? 256 : (N <= 3072 ? 512 : 1024); }
 
 hipError_t launch_residual(const GridDev& G, const ResidualArgs& a, hipStream_t st) {
   if (a.H <= 0) return hipSuccess;
-  if (wave_path(G) && !a.kl) return launch_residual_w(G, a, st);
-  // nodes per thread: 256 x 6 up to 1536 nodes, then 512 x 5 (2560) and 512 x 9 (4608)
-  const int nt = G.N <= 1536 ? 256 : 512;
+  const int v = a.variant;
+  const bool wave_v = v == HCZ_VARIANT_AUTO || v == HCZ_VARIANT_WAVE_FIXED || v == HCZ_VARIANT_WAVE;
+  if (wave_path(G) && !a.kl && wave_v) return launch_residual_w(G, a, st);
+  // threads x nodes per thread: the variant's, else the smallest that holds the grid
+  // (256 x 6 up to 1536 nodes, then 512 x 5 (2560) and 512 x 9 (4608))
+  int shape = v;
+  if (wave_v) shape = G.N <= 1536 ? HCZ_VARIANT_BLOCK_256x6 : (G.N <= 2560 ? HCZ_VARIANT_BLOCK_512x5 : HCZ_VARIANT_BLOCK_512x9);
+  const int nt = shape == HCZ_VARIANT_BLOCK_256x6 ? 256 : 512;
   const size_t lds = (size_t)G.N * 8 + (size_t)((G.N + 1) / 2) * 8 + (size_t)(nt / 64) * kNv * 8;
   dim3 grid((unsigned)a.H), block(nt);
 #define HCZ_RES(NT, NPT, T) hipLaunchKernelGGL((k_residual<NT, NPT, T>), grid, block, lds, st, G, a)
-  if (a.dtype == HCZ_F32) {
-    if (G.N <= 1536) HCZ_RES(256, 6, float); else if (G.N <= 2560) HCZ_RES(512, 5, float); else HCZ_RES(512, 9, float);
-  } else {
-    if (G.N <= 1536) HCZ_RES(256, 6, double); else if (G.N <= 2560) HCZ_RES(512, 5, double); else HCZ_RES(512, 9, double);
-  }
+#define HCZ_RES_T(T)                                                      \
+  do {                                                                    \
+    if (shape == HCZ_VARIANT_BLOCK_256x6) HCZ_RES(256, 6, T);             \
+    else if (shape == HCZ_VARIANT_BLOCK_512x5) HCZ_RES(512, 5, T);        \
+    else HCZ_RES(512, 9, T);                                              \
+  } while (0)
+  if (a.dtype == HCZ_F32) HCZ_RES_T(float);
+  else HCZ_RES_T(double);
+#undef HCZ_RES_T
 #undef HCZ_RES
   return hipGetLastError();
 }

@@ -1157,7 +1157,7 @@ bool wave_fixed_path(const GridDev& G) { return wave_path(G) && G.uniform_vol &&
 
 hipError_t launch_residual_w(const GridDev& G, const ResidualArgs& a, hipStream_t st) {
   if (a.H <= 0) return hipSuccess;
-  const bool s39 = wave_fixed_path(G);
+  const bool s39 = wave_fixed_path(G) && a.variant != HCZ_VARIANT_WAVE;
   dim3 grid((unsigned)((a.H + kWPB - 1) / kWPB)), block(64 * kWPB);
   const size_t lds = lds_bytes_w(G);
 #define HCZ_RW(T, U, SH) hipLaunchKernelGGL((k_residual_w<T, U, SH>), grid, block, lds, st, G, a)

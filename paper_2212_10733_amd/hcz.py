@@ -142,6 +142,11 @@ def _load() -> C.CDLL:
         "hcz_norm_stats_workspace": [vp, i64, C.POINTER(sz)],
         "hcz_norm_stats": [vp, vp, i32, i64, i64, i64, vp, vp, vp, sz, vp],
         "hcz_plan_path": [vp, C.POINTER(i32)],
+        "hcz_plan_variants": [vp, C.POINTER(i32), C.POINTER(i32)],
+        "hcz_probe_sink_bytes": [C.POINTER(sz)],
+        "hcz_probe_copy": [vp, vp, sz, vp],
+        "hcz_probe_compute": [i32, i64, vp, C.POINTER(C.c_double), vp],
+        "hcz_plan_set_variant": [vp, i32],
         "hcz_profile_enable": [vp, C.c_int],
         "hcz_profile_read": [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)],
         "hcz_segment_tau": [vp, vp, i32, i64, vp, vp],
@@ -176,7 +181,7 @@ LIB = _load()
 
 # Every symbol the C header declares (checked by the CPU tests).
 EXPORTS = ["hcz_create", "hcz_destroy", "hcz_last_error", "hcz_version", "hcz_plan_create",
-           "hcz_plan_destroy", "hcz_plan_path", "hcz_model_load", "hcz_model_free", "hcz_qoi", "hcz_encode",
+           "hcz_plan_destroy", "hcz_plan_path", "hcz_plan_variants", "hcz_plan_set_variant", "hcz_probe_sink_bytes", "hcz_probe_copy", "hcz_probe_compute", "hcz_model_load", "hcz_model_free", "hcz_qoi", "hcz_encode",
            "hcz_codebook_fit_workspace", "hcz_codebook_fit", "hcz_quantize", "hcz_decode",
            "hcz_residual", "hcz_compress_workspace", "hcz_decompress_workspace", "hcz_compress",
            "hcz_decompress", "hcz_stats_read", "hcz_profile_enable", "hcz_profile_read",
@@ -259,6 +264,7 @@ class Plan:
         h = C.c_void_p()
         _check(LIB.hcz_plan_create(ctx.h, C.byref(g), C.byref(h)))
         self.h = h
+        self.variant = "auto"
 
     PATHS = {0: "block", 1: "wave", 2: "wave_fixed"}
 
@@ -268,6 +274,20 @@ class Plan:
         v = C.c_int32()
         _check(LIB.hcz_plan_path(self.h, C.byref(v)))
         return self.PATHS[v.value]
+
+    VARIANTS = ("auto", "wave_fixed", "wave", "block_256x6", "block_512x5", "block_512x9")
+
+    def variants(self) -> list:
+        """Launch variants of the residual stage valid for this grid (names of VARIANTS)."""
+        buf = (C.c_int32 * 8)()
+        n = C.c_int32()
+        _check(LIB.hcz_plan_variants(self.h, buf, C.byref(n)))
+        return [self.VARIANTS[buf[i]] for i in range(n.value)]
+
+    def set_variant(self, name: str) -> None:
+        """Make a variant (a name of VARIANTS) this plan's residual launch for later calls."""
+        _check(LIB.hcz_plan_set_variant(self.h, self.VARIANTS.index(name)))
+        self.variant = name
 
     def __del__(self):
         if getattr(self, "h", None):
@@ -568,6 +588,43 @@ def norm_stats(plan: Plan, hist: torch.Tensor):
 
 # ---- batches of subdomains --------------------------------------------------------------
 
+PROBE_FP64_FMA, PROBE_FP32_MFMA, PROBE_BF16_MFMA = 0, 1, 2
+
+
+def ceilings(copy_bytes: int = 1 << 31, reps: int = 5, iters: dict | None = None) -> dict:
+    """Measured ceilings of the current device: streaming-copy rate (bytes read + written
+    per second) and FP64 FMA, FP32 and BF16 matrix-core rates of the probe kernels, each the
+    best of `reps` launches timed with events on the current stream."""
+    iters = iters or {PROBE_FP64_FMA: 100000, PROBE_FP32_MFMA: 10000, PROBE_BF16_MFMA: 10000}
+    src = torch.empty(copy_bytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+
+    def best(fn):
+        t = []
+        for _ in range(reps + 1):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            e1.synchronize()
+            t.append(e0.elapsed_time(e1) / 1e3)
+        return min(t[1:])
+
+    out = {"copy_bytes": copy_bytes,
+           "hbm_copy_GBps": 2 * copy_bytes / best(lambda: _check(LIB.hcz_probe_copy(_ptr(src), _ptr(dst), copy_bytes,
+                                                                                     _stream()))) / 1e9}
+    del src, dst
+    nb = C.c_size_t()
+    _check(LIB.hcz_probe_sink_bytes(C.byref(nb)))
+    sink = torch.empty(nb.value, dtype=torch.uint8, device="cuda")
+    fl = C.c_double()
+    for kind, name in ((PROBE_FP64_FMA, "fp64_fma_TFLOPs"), (PROBE_FP32_MFMA, "fp32_mfma_TFLOPs"),
+                       (PROBE_BF16_MFMA, "bf16_mfma_TFLOPs")):
+        dt = best(lambda: _check(LIB.hcz_probe_compute(kind, iters[kind], _ptr(sink), C.byref(fl), _stream())))
+        out[name] = fl.value / dt / 1e12
+    return out
+
+
 def segment_tau(seg_start: torch.Tensor, seg_tau: torch.Tensor, H: int) -> torch.Tensor:
     """Per-histogram bounds of a batch of subdomains: histogram h of subdomain s (rows
     seg_start[s] .. seg_start[s+1]-1) gets seg_tau[s]."""
@@ -627,8 +684,9 @@ def rans_decode(block: bytes, n: int) -> np.ndarray:
 
 def container_pack(n_par: int, n_perp: int, flags, res_offset, res_bytes, lam, codes=None, centroids=None,
                    weights=None, norm_mean=None, norm_std=None, arch: str | None = None, compute: str = "fp32",
-                   entropy: bool = False) -> bytes:
-    """Pack host (numpy) arrays of one compressed batch into the container (see hcz.h)."""
+                   entropy: int = 0) -> bytes:
+    """Pack host (numpy) arrays of one compressed batch into the container (see hcz.h);
+    entropy 0 (none), 1 (byte-wise rANS) or 2 (rANS of the residual integers by group)."""
     flags = np.ascontiguousarray(flags, np.uint8)
     H = flags.size
     res_offset = np.ascontiguousarray(res_offset, np.uint64)
@@ -667,7 +725,7 @@ def container_unpack(buf: bytes) -> dict:
     info = ContainerInfo()
     _check(LIB.hcz_container_read_info(_np_ptr(b), b.size, C.byref(info)))
     H, N = info.H, info.n_par * info.n_perp
-    d = dict(H=H, n_par=info.n_par, n_perp=info.n_perp, entropy=bool(info.entropy),
+    d = dict(H=H, n_par=info.n_par, n_perp=info.n_perp, entropy=int(info.entropy),
              flags=np.empty(H, np.uint8), res_offset=np.empty(H + 1, np.uint64),
              res_bytes=np.empty(max(int(info.res_bytes), 1), np.uint8),
              lam=np.empty((H, 4), np.float32 if info.lambda_fp32 else np.float64))

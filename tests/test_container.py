@@ -113,3 +113,42 @@ def test_container_rejects_damage(H):
     bad[48 + 50 + 1] ^= 0xff                             # a record size (after 50 flags): sizes inconsistent
     with pytest.raises(RuntimeError):
         H.container_unpack(bytes(bad))
+
+
+@pytest.mark.parametrize("shape", [(39, 39), (33, 37), (65, 65)])
+def test_integer_model_of_residual_records(H, shape):
+    """entropy = 2: the coder's records (the oracle's, with a verbatim record for a histogram
+    holding a NaN) split into headers and per-group integer symbols and rebuilt byte for
+    byte; smaller than the byte-wise rANS of the same records; a record that is not in the
+    coder's format (wrong level count, nonzero padding bits) is refused."""
+    from oracle import grid, pipeline
+    n_perp, n_par = shape
+    g = grid.make_grid(n_par, n_perp)
+    F = synth.histograms(120, n_par, n_perp, seed=84, dtype=np.float32)
+    F[5, 3, 4] = np.nan
+    comp = pipeline.compress(F, g, None, None, pipeline.Params(tau=1e-3))
+    stream = np.frombuffer(comp["stream"], np.uint8).copy()
+    flags = comp["flags"]
+    assert flags[5] & 4 and (flags & 1).sum() > 100
+    b = dict(flags=flags, res_offset=comp["offsets"], res_bytes=stream, lam=comp["lam"])
+    buf2 = H.container_pack(n_par, n_perp, entropy=2, **b)
+    buf1 = H.container_pack(n_par, n_perp, entropy=1, **b)
+    d = H.container_unpack(buf2)
+    assert d["entropy"] == 2
+    for k in ("flags", "res_offset", "res_bytes", "lam"):
+        assert np.array_equal(d[k], b[k]), k
+    assert len(buf2) < len(buf1)
+    h = int(np.nonzero((flags & 5) == 1)[0][0])
+    o, e = int(comp["offsets"][h]), int(comp["offsets"][h + 1])
+    bad = stream.copy()
+    bad[o + 9] ^= 1                                      # nlev
+    with pytest.raises(RuntimeError):
+        H.container_pack(n_par, n_perp, entropy=2, **dict(b, res_bytes=bad))
+    from oracle import coder
+    nbits = sum(len(J) * int(w) for (J, _), w in zip(coder.layout(n_par, n_perp).groups(),
+                                                     stream[o + 10:o + 10 + int(stream[o + 9])]))
+    if nbits % 32:
+        bad = stream.copy()
+        bad[e - 1] |= 0x80                               # a padding bit after the last integer
+        with pytest.raises(RuntimeError):
+            H.container_pack(n_par, n_perp, entropy=2, **dict(b, res_bytes=bad))

@@ -120,3 +120,91 @@ def test_subdomain_batch_round_trip(H, ctx):
         ia = [i for i in sb.groups[a]["index"] if layout[i][1] > 0]
         ib = [i for i in sb.groups[b]["index"] if layout[i][1] > 0]
         assert tdone[ia].max() <= tdone[ib].min()
+
+
+def _snapshot(comps):
+    snap = {}
+    for n, c in comps.items():
+        end = int(c.offsets[-1].item())
+        snap[n] = (c.flags.clone(), c.lam.clone(), c.codes.clone(), c.offsets.clone(), c.stream[:end].clone())
+    return snap
+
+
+def test_subdomain_batch_graph_replay(H, ctx):
+    """The whole batch (three grid sizes, a model on one, per-subdomain bounds) recorded
+    into one HIP graph: four replays, with eager work and synchronisations between them,
+    each give the eager call's outputs bit for bit, and the completion stamps move on."""
+    from paper_2212_10733_amd import batched
+    say("batch graph replay")
+    layout = [(n, c, t) for n, c, t in synth.subdomains(18, seed=52, count_range=(20, 400)) if n != 65]
+    plans = {n: H.Plan(ctx, n, n) for n in (33, 39, 49)}
+    inputs = {}
+    for n in plans:
+        Hn = sum(c for g_, c, _ in layout if g_ == n)
+        inputs[n] = torch.from_numpy(synth.histograms(max(Hn, 1), n, n, seed=53 + n, dtype=np.float32)[:Hn]).cuda()
+    F39 = inputs[39].cpu().numpy().astype(np.float64)
+    mu, sd = oracle.ae.norm_stats(F39)
+    models = {39: H.Model(plans[39], synth.dense_ae_weights(1521), mu.astype(np.float32), sd.astype(np.float32))}
+    sb = batched.SubdomainBatch(plans, models, layout)
+    eager = _snapshot(sb.compress(inputs))
+    t_eager = sb.completion_seconds()
+    outs = sb.capture(inputs)
+    scratch = torch.zeros(1 << 20, device="cuda")
+    last = None
+    for rep in range(4):
+        scratch.add_(1.0)                     # eager work between replays
+        torch.cuda.synchronize()
+        sb.replay()
+        torch.cuda.synchronize()
+        got = _snapshot(outs)
+        for n in eager:
+            for a, b in zip(eager[n], got[n]):
+                assert torch.equal(a, b), (rep, n)
+        t = sb.completion_seconds()
+        assert np.all(t > 0) and np.all(np.isfinite(t))
+        stamp = int(sb.t0.item())
+        assert last is None or stamp > last
+        last = stamp
+    assert t_eager.shape == t.shape
+
+
+def test_launch_variants_and_autotuner(H, ctx, tmp_path):
+    """Every launch variant of the residual stage gives the default's records, offsets and
+    flags byte for byte and its multipliers to the Newton tolerance on the compiled 39 x 39,
+    run-time-table 33 x 37 and
+    workgroup 49 x 49 paths; the autotuner times every valid variant, caches its choice
+    under the architecture / grid / dtype key and applies it."""
+    from paper_2212_10733_amd import autotune
+    for n_perp, n_par in ((39, 39), (33, 37), (49, 49)):
+        plan = H.Plan(ctx, n_par, n_perp)
+        vs = plan.variants()
+        say("variants", n_perp, n_par, vs)
+        assert vs[0] == "auto" and len(vs) >= 2
+        F = torch.from_numpy(synth.histograms(400, n_par, n_perp, seed=61, dtype=np.float32)).cuda()
+        ref = None
+        for v in vs:
+            plan.set_variant(v)
+            cz = H.Compressor(plan, None, 400, H.params(tau=1e-3))
+            c = cz.compress(F)
+            got = (c.stream_bytes(), c.offsets.cpu().numpy(), c.flags.cpu().numpy(), c.lam.cpu().numpy())
+            if ref is None:
+                ref = got
+            else:
+                assert got[0] == ref[0] and np.array_equal(got[1], ref[1]) and np.array_equal(got[2], ref[2])
+                # Newton's sums run in another order on the workgroup kernel: the
+                # multipliers agree to the stopping rule, not bit for bit
+                assert np.allclose(got[3], ref[3], rtol=1e-9, atol=1e-12 * np.abs(ref[3]).max()), v
+        bad = [v for v in H.Plan.VARIANTS if v not in vs]
+        if bad:
+            with pytest.raises(H.HczError):
+                plan.set_variant(bad[0])
+    plan = H.Plan(ctx, 39, 39)
+    cache = str(tmp_path / "tune.json")
+    v = autotune.apply(plan, cache, H=4096, reps=2)
+    data = autotune.load(cache)
+    k = autotune.plan_key(plan)
+    assert k.startswith("gfx950|39x39|f32|uniform")
+    assert data[k]["variant"] == v == plan.variant and set(data[k]["ms"]) == set(plan.variants())
+    assert v == autotune.best(data[k]["ms"])
+    plan2 = H.Plan(ctx, 39, 39)
+    assert autotune.apply(plan2, cache) == v         # served from the cache
