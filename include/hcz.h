@@ -54,7 +54,7 @@ typedef enum {
 
 enum { HCZ_F32 = 0, HCZ_F64 = 1 };                       /* element types */
 enum { HCZ_ARCH_DENSE = 1, HCZ_ARCH_CONV = 2 };           /* autoencoder architectures */
-enum { HCZ_COMPUTE_FP32 = 0, HCZ_COMPUTE_BF16 = 1 };      /* autoencoder arithmetic */
+enum { HCZ_COMPUTE_FP32 = 0, HCZ_COMPUTE_BF16 = 1, HCZ_COMPUTE_FP64 = 2 };  /* autoencoder arithmetic */
 enum { HCZ_TAU_REL_L2 = 0, HCZ_TAU_NRMSE = 1 };          /* tau_h = tau ||f||, tau sqrt(N)(max-min) */
 enum { HCZ_FALLBACK_BACKTRACK = 0, HCZ_FALLBACK_PAPER = 1 };
 enum { HCZ_BOUND_AB = 0, HCZ_BOUND_UB = 1 };                /* coder step: searched, user-specified */
@@ -91,8 +91,14 @@ typedef struct {
  *   formed in FP32 (FP64 input rounded to FP32 first) and rounded to nearest-even
  *   bfloat16 against W1 rounded at load; h3 = relu(b3 + sum_d zhat_d W3[:, d]) as FP32
  *   fused multiply-adds in order d = 0..15, rounded likewise, against W4 rounded at load.
- *   The 128 -> latent and latent -> 128 layers stay FP32.  Compression and decompression
- *   evaluate the decoder with the same kernel, so they agree bit for bit either way.
+ *   The 128 -> latent and latent -> 128 layers stay FP32.
+ *   HCZ_COMPUTE_FP64 (a checking form, one workgroup per histogram on the vector ALUs)
+ *   evaluates every layer in FP64 with the weights and statistics widened exactly:
+ *   x = (f - mean) / std (non-finite inputs as 0), every sum in index order with fused
+ *   multiply-adds, fhat = std y + mean; z and fhat are stored rounded to FP32 where the
+ *   other forms store them, so the quantiser and the residual stage see FP32 values.
+ *   Compression and decompression evaluate the decoder with the same kernel, so they
+ *   agree bit for bit in every form.
  * arch = HCZ_ARCH_CONV: the convolutional autoencoder of 39 x 39 grids (latent 16,
  *   compute = HCZ_COMPUTE_BF16; hidden is ignored).  weights (host, FP32) holds, back to
  *   back: c1w[32][1][3][3], c1b[32], c2w[64][32][3][3], c2b[64], fw[16][6400], fb[16],

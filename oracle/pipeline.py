@@ -81,6 +81,17 @@ def _bf16(model: dict) -> bool:
     return model.get("compute", "fp64") == "bf16"
 
 
+def _staged(model: dict) -> bool:
+    """model["compute"] == "fp64_staged": the FP64 model whose latent z and reconstruction
+    fhat are stored as FP32 (rounded to nearest) before the quantiser and the residual
+    stage read them, as the library's FP64 form stores them."""
+    return model.get("compute", "fp64") == "fp64_staged"
+
+
+def _f32(a: np.ndarray) -> np.ndarray:
+    return np.asarray(a, np.float64).astype(np.float32).astype(np.float64)
+
+
 def encode_ae(F64: np.ndarray, model: dict) -> np.ndarray:
     if model.get("arch", "dense") == "conv":
         sd32 = np.asarray(model["sd"], np.float32)
@@ -90,7 +101,8 @@ def encode_ae(F64: np.ndarray, model: dict) -> np.ndarray:
         sd32 = np.asarray(model["sd"], np.float32)
         return ae.dense_encode_bf16(F64.astype(np.float32), np.asarray(model["mu"], np.float32),
                                     np.float32(1) / sd32, model["W"])
-    return ae.dense_encode(ae.normalize(F64, model["mu"], model["sd"]), model["W"])
+    Z = ae.dense_encode(ae.normalize(F64, model["mu"], model["sd"]), model["W"])
+    return _f32(Z) if _staged(model) else Z
 
 
 def reconstruct_ae(codes: np.ndarray, C: np.ndarray, model: dict, shape) -> np.ndarray:
@@ -102,7 +114,8 @@ def reconstruct_ae(codes: np.ndarray, C: np.ndarray, model: dict, shape) -> np.n
         return ae.dense_decode_bf16(Zh, model["W"], np.asarray(model["mu"], np.float32),
                                     np.asarray(model["sd"], np.float32)).reshape(shape)
     Xh = ae.dense_decode(Zh, model["W"])
-    return ae.denormalize(Xh, model["mu"], model["sd"]).reshape(shape)
+    fhat = ae.denormalize(Xh, model["mu"], model["sd"])
+    return (_f32(fhat) if _staged(model) else fhat).reshape(shape)
 
 
 def compress(F: np.ndarray, g: Grid, model: dict | None, C: np.ndarray | None, p: Params,

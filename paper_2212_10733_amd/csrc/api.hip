@@ -698,7 +698,7 @@ hcz_status hcz_model_load(hcz_plan* plan, const hcz_model_desc* d, hcz_model** o
   if (d->hidden != kHidden || d->latent != kLatent)
     return fail(HCZ_EUNSUPPORTED, "dense model must be hidden %d, latent %d", kHidden, kLatent);
   if (!d->weights || !d->norm_mean || !d->norm_std) return fail(HCZ_EINVAL, "weights or norm stats NULL");
-  if (d->compute != HCZ_COMPUTE_FP32 && d->compute != HCZ_COMPUTE_BF16)
+  if (d->compute != HCZ_COMPUTE_FP32 && d->compute != HCZ_COMPUTE_BF16 && d->compute != HCZ_COMPUTE_FP64)
     return fail(HCZ_EINVAL, "compute %d", d->compute);
   hcz_status s = set_device(plan->ctx);
   if (s) return s;
@@ -761,6 +761,26 @@ hcz_status hcz_model_load(hcz_plan* plan, const hcz_model_desc* d, hcz_model** o
             }
     if ((s = upload(m->allocs, W1b, &M.W1b)) || (s = upload(m->allocs, W4b, &M.W4b)) ||
         (s = upload(m->allocs, W1m, &M.W1m)) || (s = upload(m->allocs, W4m, &M.W4m))) {
+      free_all(m->allocs);
+      delete m;
+      return s;
+    }
+  }
+  M.fp64 = d->compute == HCZ_COMPUTE_FP64;
+  if (M.fp64) {
+    // FP64 form: exact widenings, W1 and W4 transposed so that a thread's reads coalesce
+    std::vector<double> W1t((size_t)N * Hd), W4t((size_t)Hd * N), db1(b1, b1 + Hd), dW2(W2, W2 + Ld * Hd),
+        db2(b2, b2 + Ld), dW3(W3, W3 + Hd * Ld), db3(b3, b3 + Hd), db4(b4, b4 + N), dmu(mu.begin(), mu.end()),
+        dsd(sd.begin(), sd.end());
+    for (int r = 0; r < Hd; ++r)
+      for (int k = 0; k < N; ++k) W1t[(size_t)k * Hd + r] = W1[(size_t)r * N + k];
+    for (int n = 0; n < N; ++n)
+      for (int c = 0; c < Hd; ++c) W4t[(size_t)c * N + n] = W4[(size_t)n * Hd + c];
+    if ((s = upload(m->allocs, W1t, &M.W1t)) || (s = upload(m->allocs, db1, &M.b1d)) ||
+        (s = upload(m->allocs, dW2, &M.W2d)) || (s = upload(m->allocs, db2, &M.b2d)) ||
+        (s = upload(m->allocs, dW3, &M.W3d)) || (s = upload(m->allocs, db3, &M.b3d)) ||
+        (s = upload(m->allocs, W4t, &M.W4t)) || (s = upload(m->allocs, db4, &M.b4d)) ||
+        (s = upload(m->allocs, dmu, &M.mud)) || (s = upload(m->allocs, dsd, &M.sdd))) {
       free_all(m->allocs);
       delete m;
       return s;

@@ -6,8 +6,8 @@
 //
 // Header (little-endian): magic "HCZ1"; u16 scheme (bits 0-1 architecture: 0 none,
 // 1 dense, 2 convolutional; bit 2 BF16 compute; bit 3 FP32 multipliers; bit 4 entropy
-// coded); u8 latent; u8 bits; u64 H; u16 n_par; u16 n_perp; u32 weight-section bytes;
-// u64 end of the residual section; u64 total size; u32 FNV-1a checksum of the first 40
+// coded; bit 5 residual integers coded; bit 6 FP64 compute); u8 latent; u8 bits; u64 H;
+// u16 n_par; u16 n_perp; u32 weight-section bytes; u64 end of the residual section; u64 total size; u32 FNV-1a checksum of the first 40
 // header bytes.  Sections start at multiples of 8: weights (FP32 weights, mean, std),
 // codes [H][latent] (raw or rANS), PQ table [latent][2^bits] FP32, residual (flags [H],
 // record sizes [H] u32, the records back to back, raw or rANS, or with entropy = 2 (scheme
@@ -469,7 +469,8 @@ hcz_status hcz_container_pack(const hcz_container_in* c, void* out, size_t capac
     o += up8(z.lam);
   }
   // header
-  const uint16_t scheme = (uint16_t)(i.arch | (i.compute == HCZ_COMPUTE_BF16 ? 4 : 0) | (i.lambda_fp32 ? 8 : 0) |
+  const uint16_t scheme = (uint16_t)(i.arch | (i.compute == HCZ_COMPUTE_BF16 ? 4 : 0) |
+                                     (i.compute == HCZ_COMPUTE_FP64 ? 64 : 0) | (i.lambda_fp32 ? 8 : 0) |
                                      (i.entropy ? 16 : 0) | (i.entropy == 2 ? 32 : 0));
   const uint8_t lat = (uint8_t)(i.arch ? i.latent : 0), bits = (uint8_t)(i.arch ? i.bits : 0);
   const uint64_t HH = (uint64_t)H, tot = o;
@@ -514,7 +515,7 @@ hcz_status hcz_container_read_info(const void* buf, size_t n, hcz_container_info
   i.n_par = np;
   i.n_perp = nq;
   i.arch = scheme & 3;
-  i.compute = (scheme & 4) ? HCZ_COMPUTE_BF16 : HCZ_COMPUTE_FP32;
+  i.compute = (scheme & 64) ? HCZ_COMPUTE_FP64 : ((scheme & 4) ? HCZ_COMPUTE_BF16 : HCZ_COMPUTE_FP32);
   i.lambda_fp32 = (scheme & 8) ? 1 : 0;
   i.entropy = (scheme & 32) ? 2 : ((scheme & 16) ? 1 : 0);
   i.latent = b[6];

@@ -82,6 +82,17 @@ struct ModelDev {
   const uint16_t* W4b;             // [npad][hidden] bfloat16 of W4, rows >= N zero
   const uint16_t* W1m;             // bfloat16 of W1 in matrix-core operand order (see k_encode_b2)
   const uint16_t* W4m;             // bfloat16 of W4 in matrix-core operand order (see k_decode_b2)
+  int fp64;                        // 1: the FP64 form (the FP64 copies below)
+  const double* W1t;               // [N][hidden], W1 transposed
+  const double* b1d;
+  const double* W2d;               // [latent][hidden]
+  const double* b2d;
+  const double* W3d;               // [hidden][latent]
+  const double* b3d;
+  const double* W4t;               // [hidden][N], W4 transposed
+  const double* b4d;
+  const double* mud;               // [N]
+  const double* sdd;               // [N]
   // convolutional model (39 x 39 grids), arch == HCZ_ARCH_CONV
   int arch;
   const float* c1w;                // [32][9]

@@ -873,10 +873,70 @@ __global__ __launch_bounds__(256) void k_quantize(const float* z, long long n, i
   codes[q] = (uint8_t)lo;
 }
 
+// ---- FP64 form: every layer in FP64 on the vector ALUs, one workgroup per histogram ----
+// Encoder: x = (f - mu) / sigma (non-finite inputs as 0) staged in LDS; thread c sums
+// W1[c][k] x_k over k = 0..N-1 with fused multiply-adds, h1_c = max(0, sum + b1_c);
+// threads o < latent sum W2[o][c] h1_c over c = 0..127, plus b2_o; z stored as FP32.
+template <typename TIn>
+__global__ __launch_bounds__(128) void k_encode64(ModelDev M, const TIn* hist, long long H, long long hs,
+                                                  long long rs, int n_par, float* z) {
+  extern __shared__ double xs[];          // x [N], then h1 [128]
+  const long long h = blockIdx.x;
+  const int t = threadIdx.x, N = M.N;
+  const TIn* f = hist + h * hs;
+  for (int e = t; e < N; e += 128) {
+    const int j = e / n_par, i = e - j * n_par;
+    double v = (double)f[(long long)j * rs + i];
+    if (!isfinite(v)) v = 0.0;
+    xs[e] = (v - M.mud[e]) / M.sdd[e];
+  }
+  __syncthreads();
+  double s = 0.0;
+  for (int k = 0; k < N; ++k) s = fma(M.W1t[(long long)k * kHidden + t], xs[k], s);
+  double* h1 = xs + N;
+  h1[t] = fmax(s + M.b1d[t], 0.0);
+  __syncthreads();
+  if (t < kLatent) {
+    double a = 0.0;
+    for (int c = 0; c < kHidden; ++c) a = fma(M.W2d[t * kHidden + c], h1[c], a);
+    z[h * kLatent + t] = (float)(a + M.b2d[t]);
+  }
+}
+
+// Decoder: zhat_d = C[d][code_d]; h3_c = max(0, sum_d W3[c][d] zhat_d + b3_c) over
+// d = 0..15; fhat_n = sigma_n (sum_c W4[n][c] h3_c + b4_n) + mu_n over c = 0..127, stored
+// as FP32.
+__global__ __launch_bounds__(128) void k_decode64(ModelDev M, const uint8_t* codes, const float* centroids,
+                                                  int kcb, long long H, float* fhat) {
+  __shared__ double zh[kLatent], h3[kHidden];
+  const long long h = blockIdx.x;
+  const int t = threadIdx.x, N = M.N;
+  if (t < kLatent) zh[t] = (double)centroids[t * kcb + min((int)codes[h * kLatent + t], kcb - 1)];
+  __syncthreads();
+  double s = 0.0;
+  for (int d = 0; d < kLatent; ++d) s = fma(M.W3d[t * kLatent + d], zh[d], s);
+  h3[t] = fmax(s + M.b3d[t], 0.0);
+  __syncthreads();
+  for (int n = t; n < N; n += 128) {
+    double y = 0.0;
+    for (int c = 0; c < kHidden; ++c) y = fma(M.W4t[(long long)c * N + n], h3[c], y);
+    y = y + M.b4d[n];
+    fhat[h * N + n] = (float)(M.sdd[n] * y + M.mud[n]);
+  }
+}
+
 hipError_t launch_encode(const ModelDev& M, const void* hist, int dtype, long long H, long long hs,
                          long long rs, int n_par, float* z, hipStream_t st) {
   if (H <= 0) return hipSuccess;
   if (M.arch == HCZ_ARCH_CONV) return launch_conv_encode(M, hist, dtype, H, hs, rs, z, st);
+  if (M.fp64) {
+    const size_t lds = ((size_t)M.N + kHidden) * sizeof(double);
+    if (dtype == HCZ_F32)
+      hipLaunchKernelGGL(k_encode64<float>, dim3((unsigned)H), dim3(128), lds, st, M, (const float*)hist, H, hs, rs, n_par, z);
+    else
+      hipLaunchKernelGGL(k_encode64<double>, dim3((unsigned)H), dim3(128), lds, st, M, (const double*)hist, H, hs, rs, n_par, z);
+    return hipGetLastError();
+  }
   const bool contig = rs == n_par;
   dim3 grid((unsigned)((H + kTile - 1) / kTile)), block(256);
   if (M.bf16) {
@@ -902,6 +962,10 @@ hipError_t launch_decode(const ModelDev& M, const uint8_t* codes, const float* c
                          long long H, float* fhat, hipStream_t st) {
   if (H <= 0) return hipSuccess;
   if (M.arch == HCZ_ARCH_CONV) return launch_conv_decode(M, codes, centroids, bits, H, fhat, st);
+  if (M.fp64) {
+    hipLaunchKernelGGL(k_decode64, dim3((unsigned)H), dim3(128), 0, st, M, codes, centroids, 1 << bits, H, fhat);
+    return hipGetLastError();
+  }
   dim3 grid((unsigned)((H + kTile - 1) / kTile)), block(256);
   if (M.bf16) hipLaunchKernelGGL(k_decode_b2, grid, block, 0, st, M, codes, centroids, 1 << bits, H, fhat);
   else hipLaunchKernelGGL(k_decode, grid, block, 0, st, M, codes, centroids, 1 << bits, H, fhat);

@@ -18,7 +18,8 @@ LIB_PATH = os.path.join(_HERE, "libhcz.so")
 F32, F64 = 0, 1
 ARCH_DENSE, ARCH_CONV = 1, 2
 CONV_KEYS = ("c1w", "c1b", "c2w", "c2b", "fw", "fb", "dw", "db", "t1w", "t1b", "t2w", "t2b")
-COMPUTE_FP32, COMPUTE_BF16 = 0, 1
+COMPUTE_FP32, COMPUTE_BF16, COMPUTE_FP64 = 0, 1, 2
+_COMPUTE = {"fp32": COMPUTE_FP32, "bf16": COMPUTE_BF16, "fp64": COMPUTE_FP64}
 TAU_REL_L2, TAU_NRMSE = 0, 1
 FALLBACK_BACKTRACK, FALLBACK_PAPER = 0, 1
 FLAG_CODED, FLAG_ROUND2, FLAG_RAW, FLAG_WARM_REJECTED, FLAG_NOCLIP, FLAG_KL = 1, 2, 4, 8, 16, 32
@@ -321,9 +322,10 @@ class Model:
     def __init__(self, plan: Plan, W: dict, mu: np.ndarray, sd: np.ndarray, compute: str = "fp32",
                  arch: str = "dense"):
         """arch "dense" (W1..b4) or "conv" (the convolutional model of 39 x 39 grids, keys
-        CONV_KEYS, compute "bf16" only)."""
-        if compute not in ("fp32", "bf16"):
-            raise ValueError(f"compute must be 'fp32' or 'bf16', not {compute!r}")
+        CONV_KEYS, compute "bf16" only); compute "fp32", "bf16" or "fp64" (dense: every
+        layer in FP64, z and fhat stored as FP32)."""
+        if compute not in ("fp32", "bf16", "fp64"):
+            raise ValueError(f"compute must be 'fp32', 'bf16' or 'fp64', not {compute!r}")
         if arch not in ("dense", "conv"):
             raise ValueError(f"arch must be 'dense' or 'conv', not {arch!r}")
         self.plan = plan
@@ -338,7 +340,7 @@ class Model:
         fp = C.POINTER(C.c_float)
         d = ModelDesc(ARCH_CONV if arch == "conv" else ARCH_DENSE, LATENT, HIDDEN, blob.ctypes.data_as(fp),
                       mu.ctypes.data_as(fp),
-                      sd.ctypes.data_as(fp), COMPUTE_BF16 if compute == "bf16" else COMPUTE_FP32)
+                      sd.ctypes.data_as(fp), _COMPUTE[compute])
         h = C.c_void_p()
         _check(LIB.hcz_model_load(plan.h, C.byref(d), C.byref(h)))
         self.h = h
@@ -693,7 +695,7 @@ def container_pack(n_par: int, n_perp: int, flags, res_offset, res_bytes, lam, c
     res_bytes = np.ascontiguousarray(res_bytes, np.uint8)
     lam = np.ascontiguousarray(lam)
     info = ContainerInfo(H, n_par, n_perp, 0 if arch is None else (ARCH_CONV if arch == "conv" else ARCH_DENSE),
-                         COMPUTE_BF16 if compute == "bf16" else COMPUTE_FP32, 0, 0, int(lam.dtype == np.float32),
+                         _COMPUTE[compute], 0, 0, int(lam.dtype == np.float32),
                          int(entropy), 0, 0, 0)
     keep = [flags, res_offset, res_bytes, lam]
     cin = ContainerIn(info, None, None, None, None, None, _np_ptr(flags), _np_ptr(res_offset),
@@ -733,7 +735,7 @@ def container_unpack(buf: bytes) -> dict:
                        _np_ptr(d["res_bytes"]), _np_ptr(d["lam"]))
     if info.arch:
         d.update(arch="conv" if info.arch == ARCH_CONV else "dense",
-                 compute="bf16" if info.compute == COMPUTE_BF16 else "fp32",
+                 compute={v: k for k, v in _COMPUTE.items()}[info.compute],
                  weights=np.empty(info.n_weights, np.float32), norm_mean=np.empty(N, np.float32),
                  norm_std=np.empty(N, np.float32), codes=np.empty((H, info.latent), np.uint8),
                  centroids=np.empty((info.latent, 1 << info.bits), np.float32))

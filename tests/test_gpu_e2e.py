@@ -400,3 +400,54 @@ def test_search_modes_end_to_end(H, ctx, shape, search):
         assert np.array_equal(comp.offsets.cpu().numpy().astype(np.uint64), ref["offsets"])
         assert np.array_equal(comp.flags.cpu().numpy(), ref["flags"])
         check_roundtrip(F, cz.decompress(comp, Hn).cpu().numpy(), comp.flags.cpu().numpy(), tau, g)
+
+
+@pytest.mark.parametrize("Hn,dtype,every", [(256, np.float64, 1), (1000, np.float32, 4)])
+def test_fp64_form_end_to_end(H, ctx, Hn, dtype, every):
+    """The FP64 form of the autoencoder (every layer in FP64, z and fhat stored as FP32)
+    against the oracle's FP64 model with the same FP32 staging: the two sum in different
+    orders, so a stored value may differ in its last FP32 place only where the FP64 sums
+    straddle a rounding boundary.  Where z agrees everywhere (the expected case) the
+    codebook, every code, every flag and every record byte must agree; the bound and the
+    QoIs hold on the GPU's own output."""
+    say("e2e fp64 form", Hn, dtype.__name__, every)
+    g = grid.make_grid()
+    F = synth.histograms(Hn, seed=synth.SEED_PLAIN_SMALL, dtype=dtype)
+    W = synth.dense_ae_weights()
+    mu, sd = oracle.ae.norm_stats(F)
+    mu, sd = mu.astype(np.float32), sd.astype(np.float32)
+    plan = H.Plan(ctx)
+    model = H.Model(plan, W, mu, sd, compute="fp64")
+    model_o = dict(W=W, mu=mu.astype(np.float64), sd=sd.astype(np.float64), compute="fp64_staged")
+    tdt = torch.float64 if dtype == np.float64 else torch.float32
+    x = torch.from_numpy(F).cuda()
+    z = H.encode(model, x).cpu().numpy().astype(np.float64)
+    z_o = pipeline.encode_ae(F.astype(np.float64), model_o)
+    zdiff = z != z_o
+    assert zdiff.sum() <= 2
+    assert np.all(np.abs(z - z_o)[zdiff] <= np.spacing(np.abs(z_o[zdiff]).astype(np.float32)))
+    cz = H.Compressor(plan, model, Hn, H.params(tau=1e-3, fit_codebook=True, sample_every=every), in_dtype=tdt)
+    comp = cz.compress(x)
+    out = cz.decompress(comp, Hn, in_dtype=tdt).cpu().numpy()
+    flags = comp.flags.cpu().numpy()
+    check_roundtrip(F, out, flags, 1e-3, g)
+    ref = pipeline.compress(F, g, model_o, None, pipeline.Params(tau=1e-3), fit_codebook=True, bits=8,
+                            sample_every=every)
+    Cg = cz.centroids.cpu().numpy()
+    codes = comp.codes.cpu().numpy()
+    if not zdiff.any():
+        assert np.array_equal(Cg, ref["codebook"].astype(np.float32))
+        assert np.array_equal(codes, ref["codes"])
+        # the decoder's FP32 fhat may also differ in a last place where the FP64 sums
+        # straddle a rounding boundary; every histogram whose fhat agrees must agree byte
+        # for byte
+        fh = H.decode(model, comp.codes, cz.centroids).cpu().numpy().astype(np.float64)
+        same = (fh.reshape(Hn, -1) == ref["fhat"].reshape(Hn, -1)).all(axis=1)
+        assert same.mean() >= 0.99
+        assert np.array_equal(flags[same], ref["flags"][same])
+        off_g, off_o = comp.offsets.cpu().numpy().astype(np.int64), ref["offsets"].astype(np.int64)
+        st_g, st_o = comp.stream_bytes(), ref["stream"]
+        for h in np.nonzero(same)[0]:
+            assert st_g[off_g[h]:off_g[h + 1]] == st_o[off_o[h]:off_o[h + 1]], h
+        if same.all():
+            assert st_g == st_o

@@ -264,3 +264,25 @@ def test_user_specified_step():
     big = pipeline.compress(F, g, None, None, pipeline.Params(tau=1e-3, ub_level=40))
     dist = np.sqrt(((big["ft"] - F) ** 2).reshape(H, -1).sum(1))
     assert np.any(dist > big["tau_h"])
+
+
+def test_fp64_staged_form():
+    """The library's FP64 form stores z and fhat as FP32: the oracle's staged form equals
+    torch's float32 rounding of the FP64 model's z and fhat, and the pipeline keeps the
+    bound and the QoIs with it."""
+    import torch
+    g = grid.make_grid()
+    F = synth.histograms(10, seed=33, dtype=np.float64)
+    model = make_model(F)
+    model["mu"] = model["mu"].astype(np.float32).astype(np.float64)
+    model["sd"] = model["sd"].astype(np.float32).astype(np.float64)
+    staged = dict(model, compute="fp64_staged")
+    z64 = pipeline.encode_ae(F, model)
+    z32 = pipeline.encode_ae(F, staged)
+    assert np.array_equal(z32, torch.from_numpy(z64).float().double().numpy())
+    assert not np.array_equal(z32, z64)
+    comp = pipeline.compress(F, g, staged, None, pipeline.Params(tau=1e-3), fit_codebook=True, sample_every=1)
+    f64 = pipeline.reconstruct_ae(comp["codes"], comp["codebook"], model, F.shape)
+    assert np.array_equal(comp["fhat"], torch.from_numpy(f64).float().double().numpy())
+    out = pipeline.decompress(comp, g, staged, comp["codebook"], 10, np.float64)
+    check_bound_and_qoi(F, out, comp, g, 1e-3)
