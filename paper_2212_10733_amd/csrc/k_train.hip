@@ -15,6 +15,7 @@ constexpr int kGK = 32;      // K chunk
 constexpr int kGP = 36;      // LDS pitch
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 constexpr int kGPB = 40;     // LDS pitch (bfloat16 elements) of the BF16 tiles
 
 // C[m][n] = alpha * sum_k A(m,k) B(k,n) + beta * C[m][n] (+ bias[n]) (relu), with
@@ -41,23 +42,36 @@ __global__ __launch_bounds__(256) void k_gemm(const float* A, long long sam, lon
   for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
   const bool ak = sak == 1, bk = sbk == 1;
   for (long long k0 = 0; k0 < K; k0 += kGK) {
+    if constexpr (BF) {
+      // pairs of k per thread, packed into one 32-bit LDS store
 #pragma unroll
-    for (int it = 0; it < 8; ++it) {
-      const int idx = t + 256 * it;
-      int mm, kk;
-      if (ak) { mm = idx >> 5; kk = idx & 31; } else { mm = idx & 63; kk = idx >> 6; }
-      const long long gm = m0 + mm, gk = k0 + kk;
-      const float av = (gm < M && gk < K) ? A[gm * sam + gk * sak] : 0.0f;
-      int nn, kb;
-      if (bk) { nn = idx >> 5; kb = idx & 31; } else { nn = idx & 63; kb = idx >> 6; }
-      const long long gn = n0 + nn, gkb = k0 + kb;
-      const float bv = (gn < Nc && gkb < K) ? B[gkb * sbk + gn * sbn] : 0.0f;
-      if constexpr (BF) {
-        Ab[mm * kGPB + kk] = (__bf16)av;
-        Bb[nn * kGPB + kb] = (__bf16)bv;
-      } else {
-        As[mm * kGP + (kk & 1) * 16 + (kk >> 1)] = av;
-        Bs[nn * kGP + (kb & 1) * 16 + (kb >> 1)] = bv;
+      for (int it = 0; it < 4; ++it) {
+        const int idx = t + 256 * it;
+        int mm, kp;
+        if (ak) { mm = idx >> 4; kp = idx & 15; } else { mm = idx & 63; kp = idx >> 6; }
+        const long long gm = m0 + mm, gk = k0 + 2 * kp;
+        const float a0 = (gm < M && gk < K) ? A[gm * sam + gk * sak] : 0.0f;
+        const float a1 = (gm < M && gk + 1 < K) ? A[gm * sam + (gk + 1) * sak] : 0.0f;
+        int nn, kq;
+        if (bk) { nn = idx >> 4; kq = idx & 15; } else { nn = idx & 63; kq = idx >> 6; }
+        const long long gn = n0 + nn, gkb = k0 + 2 * kq;
+        const float b0 = (gn < Nc && gkb < K) ? B[gkb * sbk + gn * sbn] : 0.0f;
+        const float b1 = (gn < Nc && gkb + 1 < K) ? B[(gkb + 1) * sbk + gn * sbn] : 0.0f;
+        *(bf16x2*)&Ab[mm * kGPB + 2 * kp] = bf16x2{(__bf16)a0, (__bf16)a1};
+        *(bf16x2*)&Bb[nn * kGPB + 2 * kq] = bf16x2{(__bf16)b0, (__bf16)b1};
+      }
+    } else {
+#pragma unroll
+      for (int it = 0; it < 8; ++it) {
+        const int idx = t + 256 * it;
+        int mm, kk;
+        if (ak) { mm = idx >> 5; kk = idx & 31; } else { mm = idx & 63; kk = idx >> 6; }
+        const long long gm = m0 + mm, gk = k0 + kk;
+        As[mm * kGP + (kk & 1) * 16 + (kk >> 1)] = (gm < M && gk < K) ? A[gm * sam + gk * sak] : 0.0f;
+        int nn, kb;
+        if (bk) { nn = idx >> 5; kb = idx & 31; } else { nn = idx & 63; kb = idx >> 6; }
+        const long long gn = n0 + nn, gkb = k0 + kb;
+        Bs[nn * kGP + (kb & 1) * 16 + (kb >> 1)] = (gn < Nc && gkb < K) ? B[gkb * sbk + gn * sbn] : 0.0f;
       }
     }
     __syncthreads();
@@ -101,13 +115,24 @@ __global__ void k_relu_mask(float* d, const float* h, long long n) {
   if (i < n && !(h[i] > 0.0f)) d[i] = 0.0f;
 }
 
-// out[n] = sum_m D[m][n] (rows in order), FP64 accumulation.
-__global__ void k_colsum(const float* D, long long M, long long Nc, float* out) {
-  const long long n = (long long)blockIdx.x * 256 + threadIdx.x;
-  if (n >= Nc) return;
+// out[n] = sum_m D[m][n], FP64 accumulation in a fixed order: a workgroup takes 32
+// columns; its 8 row groups g sum rows m = g, g + 8, ... in order, then the 8 partial sums
+// are added in order g = 0..7.
+__global__ __launch_bounds__(256) void k_colsum(const float* D, long long M, long long Nc, float* out) {
+  __shared__ double part[8][32];
+  const int c = threadIdx.x & 31, g = threadIdx.x >> 5;
+  const long long n = (long long)blockIdx.x * 32 + c;
   double s = 0.0;
-  for (long long m = 0; m < M; ++m) s += (double)D[m * Nc + n];
-  out[n] = (float)s;
+  if (n < Nc)
+    for (long long m = g; m < M; m += 8) s += (double)D[m * Nc + n];
+  part[g][c] = s;
+  __syncthreads();
+  if (g == 0 && n < Nc) {
+    double t = part[0][c];
+#pragma unroll
+    for (int q = 1; q < 8; ++q) t += part[q][c];
+    out[n] = (float)t;
+  }
 }
 
 // dxh = 2 (xh - x) / n and per-block partial sums of (xh - x)^2.
@@ -127,12 +152,20 @@ __global__ __launch_bounds__(256) void k_mse_partial(const float* xh, const floa
   if (threadIdx.x == 0) partial[blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
 }
 
-__global__ void k_mse_final(const double* partial, int nb, long long n, float* loss) {
-  if (threadIdx.x == 0) {
-    double s = 0.0;
-    for (int i = 0; i < nb; ++i) s += partial[i];
-    *loss = (float)(s / (double)n);
+// loss = (sum of the partials) / n: 256 threads sum strided partials in order, then a
+// fixed pairwise tree.
+__global__ __launch_bounds__(256) void k_mse_final(const double* partial, int nb, long long n, float* loss) {
+  __shared__ double red[256];
+  const int t = threadIdx.x;
+  double s = 0.0;
+  for (int i = t; i < nb; i += 256) s += partial[i];
+  red[t] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) red[t] += red[t + w];
+    __syncthreads();
   }
+  if (t == 0) *loss = (float)(red[0] / (double)n);
 }
 
 // Adam (Kingma & Ba) with bias corrections c1 = 1 - b1^t, c2 = 1 - b2^t.
@@ -217,7 +250,7 @@ hipError_t launch_relu_mask(float* d, const float* h, long long n, hipStream_t s
 
 hipError_t launch_colsum(const float* D, long long M, long long Nc, float* out, hipStream_t st) {
   if (Nc <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_colsum, dim3((unsigned)((Nc + 255) / 256)), dim3(256), 0, st, D, M, Nc, out);
+  hipLaunchKernelGGL(k_colsum, dim3((unsigned)((Nc + 31) / 32)), dim3(256), 0, st, D, M, Nc, out);
   return hipGetLastError();
 }
 
@@ -227,7 +260,7 @@ hipError_t launch_mse(const float* xh, const float* x, long long n, float* loss,
                       hipStream_t st) {
   const int nb = (int)std::max<long long>(1, std::min<long long>(1024, (n + 255) / 256));
   hipLaunchKernelGGL(k_mse_partial, dim3(nb), dim3(256), 0, st, xh, x, n, dxh, (double*)ws);
-  hipLaunchKernelGGL(k_mse_final, dim3(1), dim3(64), 0, st, (const double*)ws, nb, n, loss);
+  hipLaunchKernelGGL(k_mse_final, dim3(1), dim3(256), 0, st, (const double*)ws, nb, n, loss);
   return hipGetLastError();
 }
 
