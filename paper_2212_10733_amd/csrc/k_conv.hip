@@ -421,26 +421,35 @@ __global__ __launch_bounds__(256) void k_cv_wgrad(const float* coarse, int Cc, i
   __shared__ double red[9][256];
   const int cc = blockIdx.x / Cf, cf = blockIdx.x % Cf, t = threadIdx.x;
   double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-  const long long tot = B * m * m;
-  for (long long q = t; q < tot; q += 256) {
-    const int px = (int)(q % m), py = (int)((q / m) % m);
-    const long long b = q / ((long long)m * m);
-    float cv = coarse[((b * Cc + cc) * m + py) * m + px];
+  const int mm = m * m;
+  // thread t takes the flattened (sample, coarse pixel) indices t, t + 256, ...; the sample
+  // and pixel advance incrementally instead of by 64-bit division
+  long long b = t / mm;
+  int pix = t - (int)b * mm;
+  for (; b < B;) {
+    const int py = pix / m, px = pix - py * m;
+    float cv = coarse[(b * Cc + cc) * mm + pix];
     if (relu_c) cv = fmaxf(cv, 0.0f);
-    if (cv == 0.0f) continue;
-    const float* fp = fine + ((b * Cf + cf) * n) * n;
+    if (cv != 0.0f) {
+      const float* fp = fine + ((b * Cf + cf) * n) * n;
 #pragma unroll
-    for (int ky = 0; ky < 3; ++ky) {
-      const int iy = 2 * py - 1 + ky;
-      if (iy < 0 || iy >= n) continue;
+      for (int ky = 0; ky < 3; ++ky) {
+        const int iy = 2 * py - 1 + ky;
+        if (iy < 0 || iy >= n) continue;
 #pragma unroll
-      for (int kx = 0; kx < 3; ++kx) {
-        const int ix = 2 * px - 1 + kx;
-        if (ix < 0 || ix >= n) continue;
-        float fv = fp[iy * n + ix];
-        if (relu_f) fv = fmaxf(fv, 0.0f);
-        acc[ky * 3 + kx] += (double)cv * (double)fv;
+        for (int kx = 0; kx < 3; ++kx) {
+          const int ix = 2 * px - 1 + kx;
+          if (ix < 0 || ix >= n) continue;
+          float fv = fp[iy * n + ix];
+          if (relu_f) fv = fmaxf(fv, 0.0f);
+          acc[ky * 3 + kx] += (double)cv * (double)fv;
+        }
       }
+    }
+    pix += 256;
+    while (pix >= mm) {
+      pix -= mm;
+      ++b;
     }
   }
 #pragma unroll
@@ -460,9 +469,16 @@ __global__ __launch_bounds__(256) void k_chsum(const float* d, int C, int P, lon
   __shared__ double red[256];
   const int c = blockIdx.x, t = threadIdx.x;
   double s = 0.0;
-  for (long long q = t; q < B * P; q += 256) {
-    const long long b = q / P;
-    s += (double)d[(b * C + c) * P + q % P];
+  // flattened (sample, cell) indices t, t + 256, ..., advanced without 64-bit division
+  long long b = t / P;
+  int i = t - (int)b * P;
+  for (; b < B;) {
+    s += (double)d[(b * C + c) * P + i];
+    i += 256;
+    while (i >= P) {
+      i -= P;
+      ++b;
+    }
   }
   red[t] = s;
   __syncthreads();

@@ -1096,7 +1096,13 @@ __global__ __launch_bounds__(256, 2) void k_decompress_w(GridDev G, DecompressAr
       for (int e = lane; e < N; e += 64) out[e] = (TOut)NAN;
       return;
     }
+    // the payload words, staged through the wave's buffer with whole-wave loads (at most
+    // 4N bytes, below the zero cell at 8N), then read per node from LDS
     const uint8_t* payload = rec + G.hdr_bytes;
+    const uint32_t nwords = (nb + 31u) >> 5;
+    uint32_t* pw = (uint32_t*)L.yb;
+    for (uint32_t k = lane; k < nwords; k += 64) pw[k] = ld32w(payload + 4 * k);
+    wave_sync();
     const uint32_t zero_off = (uint32_t)N * 8u;
     SlotRegs<NS> R;
     load_slot_regs<SH>(G, L, R);
@@ -1114,8 +1120,8 @@ __global__ __launch_bounds__(256, 2) void k_decompress_w(GridDev G, DecompressAr
           if (wdt) {
             const uint32_t pos = base + (uint32_t)L.rk[s * 64 + lane] * wdt;
             const uint32_t wi = pos >> 5, sh = pos & 31u;
-            uint64_t v = ld32w(payload + 4 * wi);
-            if (sh + wdt > 32u) v |= (uint64_t)ld32w(payload + 4 * (wi + 1)) << 32;
+            uint64_t v = pw[wi];
+            if (sh + wdt > 32u) v |= (uint64_t)pw[wi + 1] << 32;
             u = (uint32_t)((v >> sh) & ((wdt == 32u) ? 0xffffffffull : ((1ull << wdt) - 1ull)));
           }
           const int q = (int)((u >> 1) ^ (0u - (u & 1u)));
@@ -1123,6 +1129,7 @@ __global__ __launch_bounds__(256, 2) void k_decompress_w(GridDev G, DecompressAr
         }
       }
     }
+    wave_sync();      // every lane has read its words before the recomposition writes the buffer
     recompose_w<SH, true>(G, L, R, rm, [&](int s) { return dq[s]; });
   }
   double lam[4];
