@@ -7,7 +7,7 @@ tau = 1e-3, FP64 residual coder and Newton QoI correction.  One step = one hcz_c
 call (encode, codebook fit, quantize, decode, residual coding, Newton, stream assembly)
 with the input already resident in HBM.
 
-Prints one JSON line.  `--gpus N` with N > 1 is refused: this build runs on one GPU.
+Prints one JSON line.  `--gpus N` with N > 1 is refused: the program runs on one GPU.
 """
 from __future__ import annotations
 
@@ -621,7 +621,7 @@ def main() -> int:
         return 0
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on exactly one GPU: the per-histogram path needs no communication, "
-              "and multi-GPU runs are not part of this build.", file=sys.stderr)
+              "and this program does not run on several GPUs.", file=sys.stderr)
         return 2
 
     import torch

@@ -47,7 +47,7 @@ typedef enum {
   HCZ_EINVAL = -1,        /* bad argument (null pointer, size, mode, shape mismatch) */
   HCZ_ENOMEM = -2,        /* library-owned allocation failed */
   HCZ_EHIP = -3,          /* a HIP runtime call failed */
-  HCZ_EUNSUPPORTED = -4,  /* valid request this build does not implement */
+  HCZ_EUNSUPPORTED = -4,  /* valid request the library does not implement */
   HCZ_ECAPACITY = -5,     /* residual stream larger than the caller's capacity */
   HCZ_EWORKSPACE = -6     /* workspace smaller than the size query returned */
 } hcz_status;

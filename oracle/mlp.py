@@ -4,7 +4,7 @@ A 16 -> 64 -> 64 -> 4 ReLU network maps the dequantised latent of a histogram to
 guess of its four multipliers, in units of a per-component scale stored with the network:
 lam0 = scale * (W3 relu(W2 relu(W1 zhat + b1) + b2) + b3).  Trained by MSE against the
 multipliers the cold-start Newton solve produces (targets divided by the scale).
-Cold start stays the fallback and the judge (see newton.project).
+Cold start stays the fallback and the reference result (see newton.project).
 """
 from __future__ import annotations
 
