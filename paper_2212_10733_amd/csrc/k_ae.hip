@@ -186,57 +186,67 @@ __global__ __launch_bounds__(256, 2) void k_encode_d(ModelDev M, const float* hi
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.0f;
   const int nfull = N / kKc, nchunk = kpad / kKc;
-  f32x4u ra[2][4], rb[2][4];
-  auto gload = [&](int c) {
-#pragma unroll
-    for (int q = 0; q < 2; ++q)
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        ra[q][u] = *(const f32x4u*)(arow[q] + c * kKc + 4 * u);
-        rb[q][u] = *(const f32x4u*)(brow[q] + c * kKc + 4 * u);
-      }
+  // two raw operand buffers: chunk c + 1 is loaded while chunk c is normalised and
+  // multiplied (the loop takes chunks in pairs, so the buffers alternate by name)
+  struct Raw {
+    f32x4u a[2][4], b[2][4];
   };
-  auto gload_tail = [&](int c) {            // k may reach N: element by element
+  auto gload = [&](int c, Raw& R) {
+    if (c < nfull) {
 #pragma unroll
-    for (int q = 0; q < 2; ++q)
+      for (int q = 0; q < 2; ++q)
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int k = c * kKc + kh * 16 + 4 * u + e;
-          ra[q][u][e] = k < N ? arow[q][c * kKc + 4 * u + e] : 0.0f;
+        for (int u = 0; u < 4; ++u) {
+          R.a[q][u] = *(const f32x4u*)(arow[q] + c * kKc + 4 * u);
+          R.b[q][u] = *(const f32x4u*)(brow[q] + c * kKc + 4 * u);
         }
-        rb[q][u] = *(const f32x4u*)(brow[q] + c * kKc + 4 * u);
-      }
+    } else {                              // k may reach N: element by element
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int k = c * kKc + kh * 16 + 4 * u + e;
+            R.a[q][u][e] = k < N ? arow[q][c * kKc + 4 * u + e] : 0.0f;
+          }
+          R.b[q][u] = *(const f32x4u*)(brow[q] + c * kKc + 4 * u);
+        }
+    }
   };
-  if (nfull > 0) gload(0);
-  else gload_tail(0);
-  for (int c = 0; c < nchunk; ++c) {
-    // normalise this chunk's A operands: (f - mu) / sigma, non-finite inputs as 0
-    float av[2][16], bv[2][16];
+  // (f - mu) / sigma with non-finite inputs as 0, formed right before the matrix core
+  // takes it; the products and their order are those of a fully normalised chunk
+  auto mma = [&](int c, const Raw& R) {
     const f32x4* pm = (const f32x4*)(s_mu + c * kKc + kh * 16);
     const f32x4* pr = (const f32x4*)(s_rsd + c * kKc + kh * 16);
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const f32x4 mu4 = pm[u], rs4 = pr[u];
 #pragma unroll
-      for (int e = 0; e < 4; ++e)
+      for (int e = 0; e < 4; ++e) {
+        float av[2];
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
-          float fv = ra[q][u][e];
+          float fv = R.a[q][u][e];
           if (!isfinite(fv)) fv = 0.0f;
-          av[q][4 * u + e] = (fv - mu4[e]) * rs4[e];
-          bv[q][4 * u + e] = rb[q][u][e];
+          av[q] = (fv - mu4[e]) * rs4[e];
         }
+#pragma unroll
+        for (int qa = 0; qa < 2; ++qa)
+#pragma unroll
+          for (int qb = 0; qb < 2; ++qb) acc[qa][qb] = mfma32(av[qa], R.b[qb][u][e], acc[qa][qb]);
+      }
     }
-    if (c + 1 < nfull) gload(c + 1);
-    else if (c + 1 < nchunk) gload_tail(c + 1);
-#pragma unroll
-    for (int s2 = 0; s2 < 16; ++s2)
-#pragma unroll
-      for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b) acc[a][b] = mfma32(av[a][s2], bv[b][s2], acc[a][b]);
+  };
+  Raw R0, R1;
+  gload(0, R0);
+  for (int c = 0; c < nchunk; c += 2) {
+    if (c + 1 < nchunk) gload(c + 1, R1);
+    mma(c, R0);
+    if (c + 1 < nchunk) {
+      if (c + 2 < nchunk) gload(c + 2, R0);
+      mma(c + 1, R1);
+    }
   }
   __syncthreads();
   // epilogue 1: H1 = relu(acc + b1) into LDS
