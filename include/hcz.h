@@ -10,7 +10,7 @@
  *   quantize codes = PQ(z)               (Stage 3, Section IV-E)
  *   decode fhat = sigma decoder(C[codes]) + mu
  *   residual r = f - fhat, coded under a per-histogram bound tau_h by a multilevel coder
- *   with a bisection over its quantisation ladder (Stage 4)
+ *   with a binary search over its quantisation ladder (Stage 4)
  *   Newton projection of ft = fhat + rhat onto {A x = b, x >= 0}; 4 multipliers lambda
  *   per histogram (Stage 5, Eq. 6)
  * Decompress rebuilds ft and applies f_c = max(0, ft - A^T lambda).
@@ -168,7 +168,7 @@ typedef struct {
  *                  bounds in one call, see hcz_segment_tau.  A negative, infinite or NaN
  *                  entry makes that histogram a verbatim record.
  * bound_mode       HCZ_BOUND_AB (0): the coder's step is searched per histogram by the
- *                  bisection over the ladder (the paper's 'ab', automatic error-bound
+ *                  search over the ladder below (the paper's 'ab', automatic error-bound
  *                  determination, Section IV-F).  HCZ_BOUND_UB (1): the step is the user's
  *                  ('ub', user-specified error bound): every coded histogram is quantised
  *                  with ladder step ub_level, without a search.  ub_level 0 is the step

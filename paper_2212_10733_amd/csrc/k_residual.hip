@@ -1,5 +1,5 @@
 // Per-histogram FP64 kernels: moments/QoIs (Eq. 1-4), residual selection and the
-// multilevel coder with its bound bisection (Section III Stage 4), the Newton projection
+// multilevel coder with its bound search (Section III Stage 4), the Newton projection
 // restoring the four moments (Stage 5, Eq. 6), and decompression (Section III, end).
 //
 // One workgroup of NT threads owns one histogram.  A first pass streams the histogram
