@@ -32,13 +32,23 @@ def log(*a):
 
 
 def residual_flops(N: int, H: int, coded: int, steps_per_coded: float, newton_passes: float) -> float:
-    """FP64 operations the residual stage's method needs, FMA counted as 2, per grid cell:
+    """FP64 operations the residual kernel itself executes, FMA counted as 2, per grid cell:
     13 for the load pass (residual, two squared norms, four moments), per coded histogram
     5 for the decomposition, 12 per bisection step (quantise, interpolate, add, error),
     2 for packing and 10 for the final recomposition with ft = fhat + rhat, and 10 per
     Newton pass (correction, clip, two moment sums, Hessian terms on active cells)."""
     per_cell = 13.0 * H + coded * (5.0 + 12.0 * steps_per_coded + 2.0 + 10.0) + 10.0 * newton_passes
     return per_cell * N
+
+
+def residual_flops_survey(N: int, H: int, coded: int, probes_per_coded: float, passes: float,
+                          hessians: float) -> float:
+    """FP64 operations of the residual stage as the method's algorithmic count gives them
+    (FMA = 2 operations), per grid cell: the four moments, 4 FMA; each Newton pass, 8 FMA
+    (correction, clip, gradient sums); each Hessian, 5 masked adds; each coded histogram,
+    7 operations per coder step, the steps being the forward decomposition plus one per
+    bound evaluation of the ladder search.  passes and hessians are totals over the batch."""
+    return N * (8.0 * H + 16.0 * passes + 5.0 * hessians + 7.0 * coded * (1.0 + probes_per_coded))
 
 
 def search_steps(kstar_hist, start: int | None = 11) -> float:
@@ -110,22 +120,93 @@ def residual_traffic(H: int):
     return per_hist * H
 
 
-def cpu_baseline(F: np.ndarray, W: dict, mu, sd, tau: float, n: int) -> dict:
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def _oracle_compress_timed(F, W, mu, sd, tau, threads=1):
+    """Time the oracle's full compress (encode, codebook fit on every 16th latent, quantize,
+    decode, coder, Newton) of the histograms F with `threads` BLAS threads; returns seconds."""
     from threadpoolctl import threadpool_limits
 
-    import oracle
     from oracle import grid, pipeline
-    g = grid.make_grid()
-    model = dict(W=W, mu=mu.astype(np.float64), sd=sd.astype(np.float64))
-    sample = F[:n]
-    with threadpool_limits(limits=1):
+    g = grid.make_grid(F.shape[2], F.shape[1])
+    model = dict(W=W, mu=np.asarray(mu, np.float64), sd=np.asarray(sd, np.float64))
+    with threadpool_limits(limits=threads):
         t0 = time.perf_counter()
-        pipeline.compress(sample, g, model, None, pipeline.Params(tau=tau), fit_codebook=True,
-                          bits=8, sample_every=16)
-        dt = time.perf_counter() - t0
-    return {"value": n / dt, "unit": "histograms/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {n} histograms of the same batch, full compress (encode, codebook fit on "
-                      f"every 16th, quantize, decode, coder, Newton), NumPy FP64, 1 thread, {dt:.1f} s"}
+        pipeline.compress(F, g, model, None, pipeline.Params(tau=tau), fit_codebook=True, bits=8, sample_every=16)
+        return time.perf_counter() - t0
+
+
+def _oracle_worker(a):
+    return _oracle_compress_timed(*a)
+
+
+def cpu_baseline(F: np.ndarray, W: dict, mu, sd, tau: float, n: int, gpu_check=None) -> dict:
+    """The FP64 oracle timed on this host's cores on samples of the same workload: every
+    sample runs the whole compress.  Headline: all cores, one worker process per core (at
+    most 16), each on its own n/4 histograms with one BLAS thread.  Beside it: one thread on
+    n histograms at tau and on n/4 at 1e-2 and 1e-4, the same with every BLAS thread (the
+    oracle's products are the only multithreaded part), and the 256-histogram FP64 case.
+    gpu_check: (b, q_in, q_out) of the GPU on the first histograms of the batch (moments
+    of f, QoIs of f and of the decompressed f_c), compared here with the oracle's moments."""
+    import multiprocessing as mp
+
+    from oracle import grid, moments
+    from paper_2212_10733_amd import synth
+    cores = os.cpu_count() or 1
+    workers = max(1, min(16, cores))
+    res = {"cpu_model": _cpu_model(), "host_cores": cores, "kind": "oracle", "unit": "histograms/s"}
+    dt = _oracle_compress_timed(F[:n], W, mu, sd, tau, 1)
+    res["one_thread"] = {"value": n / dt, "histograms": n, "tau": tau, "seconds": dt}
+    for t in (1e-2, 1e-4):
+        m = max(256, n // 4)
+        d = _oracle_compress_timed(F[:m], W, mu, sd, t, 1)
+        res[f"one_thread_tau_{t:g}"] = {"value": m / d, "histograms": m, "seconds": d}
+    m = max(256, n // 2)
+    d = _oracle_compress_timed(F[:m], W, mu, sd, tau, cores)
+    res["blas_all_threads"] = {"value": m / d, "histograms": m, "threads": cores, "seconds": d}
+    F1 = synth.histograms(256, seed=synth.SEED_PLAIN_SMALL, dtype=np.float64)
+    from oracle import ae
+    m1, s1 = ae.norm_stats(F1)                  # the 256-histogram case's own z-score statistics
+    d = _oracle_compress_timed(F1, W, m1, s1, tau, 1)
+    res["c1_256_fp64_one_thread"] = {"value": 256 / d, "seconds": d}
+    per = max(64, n // 4)
+    per = min(per, len(F) // workers)
+    chunks = [(np.ascontiguousarray(F[k * per:(k + 1) * per]), W, mu, sd, tau, 1) for k in range(workers)]
+    with mp.get_context("spawn").Pool(workers) as pool:
+        pool.map(_oracle_worker, [(c[0][:64], W, mu, sd, tau, 1) for c in chunks])      # import and warm up
+        t0 = time.perf_counter()
+        secs = pool.map(_oracle_worker, chunks)
+        wall = time.perf_counter() - t0
+    res["value"] = workers * per / wall
+    res["cores"] = workers
+    res["all_cores"] = {"value": workers * per / wall, "workers": workers, "histograms": workers * per,
+                        "wall_seconds": wall, "max_worker_seconds": max(secs)}
+    res["sample"] = (f"histograms of the same 2^20 batch, full compress (encode, codebook fit on every 16th, "
+                     f"quantize, decode, coder, Newton), NumPy FP64: headline {workers} worker processes x {per} "
+                     f"histograms, one BLAS thread each; see one_thread, blas_all_threads, c1_256_fp64_one_thread")
+    if gpu_check is not None:
+        b_gpu, q_in, q_out, fc = gpu_check
+        k = len(b_gpu)
+        g = grid.make_grid()
+        bo = moments.moments(F[:k], g)
+        qo_in = moments.qoi(F[:k], g)
+        qo_out = moments.qoi(fc, g)
+        res["gpu_crosscheck"] = {
+            "histograms": k,
+            "moments_max_rel_diff": float((np.abs(b_gpu - bo) / np.abs(bo).max(axis=0)).max()),
+            "qoi_in_max_rel_err": float(moments.qoi_rel_error(qo_in, q_in, g).max()),
+            "qoi_out_vs_oracle_input_max_rel_err": float(moments.qoi_rel_error(qo_in, qo_out, g).max()),
+        }
+    return res
 
 
 def time_compress(cz, x, steps):
@@ -165,6 +246,9 @@ def _plain_run(hcz, plan, model, x, hp, tau, refs, steps=3) -> dict:
          "newton_mean_updates": s["newton_iters_total"] / max(1, H - s["n_raw"]),
          "max_qoi_rel_err": ((q1 - q0).abs() / den)[ok].max().item(),
          "max_err_over_tau_h": over.max().item(), "over_bound": int((over > 1).sum().item())}
+    alg = H * (4 * plan.N + 16 + 32 + 1 + 8) + s["stream_bytes"]
+    r["hbm_alg_bytes"] = alg
+    r["hbm_frac"] = alg / dt / 1e9 / PEAK_HBM_GBS
     del cz, comp, o
     return r
 
@@ -201,10 +285,8 @@ def container_form(hcz, plan, x, W, args, n=131072) -> dict:
     (single thread) including the device-to-host copies."""
     import torch
     xs = x[:n]
-    xf = xs.reshape(n, -1).double()
-    mu = xf.mean(0).float().cpu().numpy()
-    sd = torch.clamp(xf.std(0, unbiased=False), min=1e-12).float().cpu().numpy()
-    del xf
+    mu, sd = hcz.norm_stats(plan, xs)
+    mu, sd = mu.cpu().numpy(), sd.cpu().numpy()
     model = hcz.Model(plan, W, mu, sd)
     cz = hcz.Compressor(plan, model, n, hcz.params(tau=args.tau, fit_codebook=True, sample_every=16))
     comp = cz.compress(xs)
@@ -239,7 +321,7 @@ def conv_train_form(hcz, plan, ctx, x, args, rows=32768, epochs=5) -> dict:
     from paper_2212_10733_amd import synth, train
     Ftr = torch.from_numpy(synth.histograms(rows, seed=synth.SEED_TRAIN, dtype=np.float32)).cuda()
     mu, sd = hcz.norm_stats(plan, Ftr)
-    X = ((Ftr.reshape(rows, -1) - mu) / sd).contiguous()
+    X = hcz.column_normalize(Ftr, mu, sd)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     tr = train.Trainer(train.pack_conv(synth.conv_ae_weights()), lr=1e-3, arch="conv")
@@ -290,14 +372,11 @@ def bf16_form(hcz, plan, ctx, x, W, args, arch="dense", stats=None) -> dict:
     matrix-core rates, p, stream size, QoI error, bound."""
     import torch
     H, N = x.shape[0], plan.N
-    xf = x.reshape(H, -1).double() if stats is None else None
     if stats is None:
-        mu, sd = xf.mean(0), xf.std(0, unbiased=False)
-        sd = torch.clamp(sd, min=1e-12 * sd.max().item())
-        mu, sd = mu.float().cpu().numpy(), sd.float().cpu().numpy()
+        mu, sd = hcz.norm_stats(plan, x)
+        mu, sd = mu.cpu().numpy(), sd.cpu().numpy()
     else:
         mu, sd = stats
-    del xf
     model = hcz.Model(plan, W, mu, sd, compute="bf16", arch=arch)
     cz = hcz.Compressor(plan, model, H, hcz.params(tau=args.tau, fit_codebook=True, sample_every=16))
     cz.compress(x)
@@ -454,7 +533,7 @@ def incremental_form(hcz, plan, H, W, args, steps=4, planes=8) -> dict:
         sel = torch.from_numpy(train.colrandind(planes, nodes, seed=t)).cuda()
         Fs = F.reshape(n, -1)[sel]
         mu, sd = hcz.norm_stats(plan, Fs.reshape(nodes, plan.n_perp, plan.n_par))
-        X = ((Fs - mu) / sd).contiguous()
+        X = hcz.column_normalize(Fs, mu, sd)
         row = {"step": t}
         runs = [("scratch", train.pack(W), args.epochs)]
         if prev is not None:
@@ -521,7 +600,7 @@ def other_forms(hcz, plan, ctx, x, F, W, args, plain_value, plain_stats) -> dict
     log(f"form: learned (train {args.epochs} epochs on {args.train_hist})")
     Ftr = torch.from_numpy(synth.histograms(args.train_hist, seed=synth.SEED_TRAIN, dtype=np.float32)).cuda()
     mu, sd = hcz.norm_stats(plan, Ftr)
-    X = ((Ftr.reshape(args.train_hist, -1) - mu) / sd).contiguous()
+    X = hcz.column_normalize(Ftr, mu, sd)
     t0 = time.perf_counter()
     tr = train.Trainer(train.pack(W), lr=1e-3)
     losses = tr.fit(X, epochs=args.epochs, batch=1024)
@@ -540,9 +619,11 @@ def other_forms(hcz, plan, ctx, x, F, W, args, plain_value, plain_stats) -> dict
     czt = hcz.Compressor(plan, model, args.train_hist, hcz.params(tau=args.tau, fit_codebook=True, sample_every=16))
     ct = czt.compress(Ftr)
     ok = (ct.flags & 4) == 0
-    scale = ct.lam[ok].std(dim=0).clamp_min(1e-30)
+    lam_ok = ct.lam[ok]
+    _, scale = hcz.column_stats(lam_ok)
     Z = hcz.dequantize(ct.codes, czt.centroids)[ok]
-    T = (ct.lam[ok] / scale).float()
+    T = hcz.column_normalize(lam_ok, None, scale)
+    scale = scale.double()
     t0 = time.perf_counter()
     pm, mlosses = train.fit_mlp(Z, T, synth.mlp_weights(), epochs=10, batch=512, lr=3e-3)
     torch.cuda.synchronize()
@@ -593,7 +674,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--H", type=int, default=1 << 20)
     ap.add_argument("--tau", type=float, default=1e-3)
-    ap.add_argument("--cpu-sample", type=int, default=8192)
+    ap.add_argument("--cpu-sample", type=int, default=4096)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the coder-only and learned forms")
     ap.add_argument("--forms", default="tau,ub,coder,stage5,container,bf16,conv,batched,incremental,learned",
@@ -635,16 +716,11 @@ def main() -> int:
     W = synth.dense_ae_weights()
     log(f"generated in {time.perf_counter() - t0:.1f} s")
     x = torch.from_numpy(F).cuda()
-    # model preparation (outside the hot path): z-score statistics of the batch
-    xf = x.reshape(H, -1).double()
-    mu = xf.mean(0)
-    sd = xf.std(0, unbiased=False)
-    sd = torch.clamp(sd, min=1e-12 * sd.max().item())
-    mu, sd = mu.float().cpu().numpy(), sd.float().cpu().numpy()
-    del xf
-
     ctx = hcz.Context(0)
     plan = hcz.Plan(ctx)
+    # model preparation (outside the hot path): z-score statistics of the batch
+    mu, sd = hcz.norm_stats(plan, x)
+    mu, sd = mu.cpu().numpy(), sd.cpu().numpy()
     model = hcz.Model(plan, W, mu, sd)
     p = hcz.params(tau=args.tau, fit_codebook=True, sample_every=16)
     cz = hcz.Compressor(plan, model, H, p, bits=8)
@@ -676,10 +752,11 @@ def main() -> int:
     steps_coded = search_steps(st["kstar_hist"])
     passes = st["newton_iters_total"] + (H - st["n_raw"])
     ae_flops = 2.0 * H * N * 128 + 2.0 * H * 128 * 16
+    survey_flops = residual_flops_survey(N, H, coded, steps_coded, passes, st["newton_iters_total"])
     cands = {
         "encode": ("mfma", ae_flops / 1e12, PEAK_FP32_MFMA_TFLOPS, "TFLOP/s"),
         "decode": ("mfma", ae_flops / 1e12, PEAK_FP32_MFMA_TFLOPS, "TFLOP/s"),
-        "residual": ("alu", residual_flops(N, H, coded, steps_coded, passes) / 1e12, PEAK_FP64_VALU_TFLOPS, "TFLOP/s"),
+        "residual": ("alu", survey_flops / 1e12, PEAK_FP64_VALU_TFLOPS, "TFLOP/s"),
     }
     dom = max(cands, key=lambda k: stage_ms.get(k, 0.0))
     bound, work, peak, unit = cands[dom]
@@ -688,10 +765,18 @@ def main() -> int:
                 "frac": achieved / peak, "traffic": residual_traffic(H) if dom == "residual" else None}
     stream_bytes = st["stream_bytes"]
     alg_bytes = H * (4 * N + 16 + 32 + 1 + 8) + stream_bytes
+    kernel_flops = residual_flops(N, H, coded, steps_coded, passes)
     extra = {
         "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
         "stage_roofline": {k: {"bound": c[0], "achieved": c[1] / (stage_ms[k] / 1e3), "peak": c[2],
                                "frac": c[1] / (stage_ms[k] / 1e3) / c[2]} for k, c in cands.items() if k in stage_ms},
+        "residual_flop_counts": {
+            "method_count_per_cell": survey_flops / (H * N), "kernel_count_per_cell": kernel_flops / (H * N),
+            "kernel_count_frac": kernel_flops / (stage_ms["residual"] / 1e3) / 1e12 / PEAK_FP64_VALU_TFLOPS,
+            "search_probes_per_coded": steps_coded, "newton_passes": passes,
+            "hbm_alg_bytes": H * (4 * N + 16 + 32 + 1 + 8) + stream_bytes,
+            "hbm_frac_of_alg_bytes": (H * (4 * N + 16 + 32 + 1 + 8) + stream_bytes)
+                                     / (stage_ms["residual"] / 1e3) / 1e9 / PEAK_HBM_GBS},
         "hbm_whole_step": {"alg_bytes": alg_bytes, "GB/s": alg_bytes / (dt / args.steps) / 1e9,
                            "frac": alg_bytes / (dt / args.steps) / 1e9 / PEAK_HBM_GBS},
         "coded_frac": coded / H, "raw": st["n_raw"], "round2": st["n_round2"],
@@ -713,6 +798,19 @@ def main() -> int:
     bound_ratio = (dist[ok] / (args.tau * n0[ok])).max().item()
     extra["max_qoi_rel_err"] = qerr
     extra["max_err_over_tau_h"] = bound_ratio
+    # Eq. 7 applied to each QoI over the batch: u = the QoI of the inputs, f = of the output
+    rng_q = (q0[ok].max(0).values - q0[ok].min(0).values)
+    nr = ((q1[ok] - q0[ok]) ** 2).mean(0).sqrt() / rng_q
+    extra["qoi_nrmse"] = {k: nr[i].item() for i, k in enumerate(("n", "u_par", "T_perp", "T_par"))}
+    extra["pd_nrmse"] = ((dist[ok] ** 2).sum() / (int(ok.sum().item()) * N)).sqrt().item() / (x.max() - x.min()).item()
+    valid = bool(qerr <= 1e-10 and bound_ratio <= 1.0)
+    extra["valid"] = valid
+    if not valid:
+        log(f"INVALID: max QoI relative error {qerr:.3e} (limit 1e-10) or max ||f-f_c||/tau_h {bound_ratio:.4f} > 1")
+    kchk = min(4096, H)
+    bchk, qin_chk, _ = hcz.qoi(plan, x[:kchk])
+    _, qout_chk, _ = hcz.qoi(plan, out[:kchk])
+    gpu_check = (bchk.cpu().numpy(), qin_chk.cpu().numpy(), qout_chk.cpu().numpy(), out[:kchk].cpu().numpy())
     # decompression (dequantize + decode + residual records + correction) on its own, into
     # the same FP64 output: reads codes, multipliers, flags, offsets and records, writes 8N
     ctx.profile(True)
@@ -747,7 +845,7 @@ def main() -> int:
     cpu = None
     if not args.no_cpu:
         log(f"cpu baseline on {args.cpu_sample} histograms")
-        cpu = cpu_baseline(F, W, mu, sd, args.tau, args.cpu_sample)
+        cpu = cpu_baseline(F, W, mu, sd, args.tau, args.cpu_sample, gpu_check)
 
     line = {
         "metric": "histograms/s (compress+QoI-correct)", "value": value, "unit": "histograms/s",
@@ -761,7 +859,7 @@ def main() -> int:
         "roofline": roofline, "cpu_baseline": cpu, **extra, "forms": forms,
     }
     print(json.dumps(line), flush=True)
-    return 0
+    return 0 if valid else 3
 
 
 if __name__ == "__main__":

@@ -493,6 +493,21 @@ hcz_status hcz_norm_stats(const hcz_plan* plan, const void* hist, int32_t dtype,
                           int64_t hist_stride, int64_t row_stride, float* mean, float* std,
                           void* ws, size_t ws_bytes, hcz_stream_t stream);
 
+/* The same statistics for any matrix x [rows][cols] (row stride ld >= cols elements, FP32
+ * or FP64): per-column mean and population std (FP64 two-pass), std floored at 1e-12 times
+ * the largest std, written as FP32 [cols]; e.g. the scales of the warm-start targets.
+ * Workspace: hcz_column_stats_workspace bytes.  Errors: HCZ_EINVAL for NULL pointers, an
+ * unknown dtype or a bad shape, HCZ_EWORKSPACE for a short workspace. */
+hcz_status hcz_column_stats_workspace(int64_t rows, int64_t cols, size_t* bytes);
+hcz_status hcz_column_stats(const void* x, int32_t dtype, int64_t rows, int64_t cols, int64_t ld, float* mean,
+                            float* std, void* ws, size_t ws_bytes, hcz_stream_t stream);
+/* z-scoring of training rows (Section IV-D: inputs are normalised before training):
+ * out[r][c] = (x[r][c] - mean[c]) / std[c] (out dense [rows][cols], FP32), x rounded to FP32
+ * first, then one FP32 subtraction and one FP32 division (round to nearest); mean NULL
+ * means 0 (pure scaling).  x may be FP32 or FP64 with row stride ld.  Errors: HCZ_EINVAL. */
+hcz_status hcz_column_normalize(const void* x, int32_t dtype, int64_t rows, int64_t cols, int64_t ld,
+                                const float* mean, const float* std, float* out, hcz_stream_t stream);
+
 /* ---- warm-start network (learned addition to Section III Stage 5) ----------------------
  * lam0 = scale * (W3 relu(W2 relu(W1 zhat + b1) + b2) + b3), 16 -> 64 -> 64 -> 4, with
  * zhat the dequantised latent.  params (host for hcz_mlp_load, device for training):

@@ -97,6 +97,6 @@ class SubdomainBatch:
             res[self.groups[k]["index"]] = (d.cpu().numpy() - t0) / hz
         return res
 
-    def decompress(self, comps: dict, in_dtype=torch.float32) -> dict:
+    def decompress(self, comps: dict, in_dtype=None) -> dict:
         return {k: self.groups[k]["cz"].decompress(c, self.groups[k]["H"], in_dtype=in_dtype)
                 for k, c in comps.items()}

@@ -1346,6 +1346,33 @@ hcz_status hcz_norm_stats(const hcz_plan* plan, const void* hist, int32_t dtype,
   return HCZ_OK;
 }
 
+hcz_status hcz_column_stats_workspace(int64_t rows, int64_t cols, size_t* bytes) {
+  if (!bytes || rows < 1 || cols < 1 || cols > INT32_MAX) return fail(HCZ_EINVAL, "bad argument");
+  *bytes = norm_stats_ws_bytes(rows, (int)cols);
+  return HCZ_OK;
+}
+
+hcz_status hcz_column_stats(const void* x, int32_t dtype, int64_t rows, int64_t cols, int64_t ld, float* mean,
+                            float* sd, void* ws, size_t ws_bytes, hcz_stream_t stream) {
+  if (!x || !mean || !sd) return fail(HCZ_EINVAL, "NULL argument");
+  if (dtype != HCZ_F32 && dtype != HCZ_F64) return fail(HCZ_EINVAL, "dtype");
+  if (rows < 1 || cols < 1 || cols > INT32_MAX || ld < cols) return fail(HCZ_EINVAL, "bad shape");
+  if (!ws || ws_bytes < norm_stats_ws_bytes(rows, (int)cols)) return fail(HCZ_EWORKSPACE, "workspace too small");
+  // one row of `cols` elements per "histogram": the statistics kernel's (n_par = N = cols) case
+  HCZ_TRY(launch_norm_stats(x, dtype, rows, ld, cols, (int)cols, (int)cols, mean, sd, ws, (hipStream_t)stream),
+          "column stats");
+  return HCZ_OK;
+}
+
+hcz_status hcz_column_normalize(const void* x, int32_t dtype, int64_t rows, int64_t cols, int64_t ld,
+                                const float* mean, const float* sd, float* out, hcz_stream_t stream) {
+  if (rows < 0 || cols < 0 || ld < cols) return fail(HCZ_EINVAL, "bad shape");
+  if (dtype != HCZ_F32 && dtype != HCZ_F64) return fail(HCZ_EINVAL, "dtype");
+  if (rows * cols > 0 && (!x || !sd || !out)) return fail(HCZ_EINVAL, "NULL argument");
+  HCZ_TRY(launch_col_normalize(x, dtype, rows, cols, ld, mean, sd, out, (hipStream_t)stream), "column normalize");
+  return HCZ_OK;
+}
+
 // ---- warm-start network -------------------------------------------------------------
 namespace {
 constexpr int kMH = 64, kMI = 16, kMO = 4;

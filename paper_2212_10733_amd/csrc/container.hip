@@ -193,6 +193,25 @@ struct IntStreams {
 
 int bit_length(uint32_t u) { return u ? 32 - __builtin_clz(u) : 0; }
 
+// Record sizes the residual kernels write: a verbatim record holds the N input values (4N
+// or 8N bytes), a coded one at least its header, any other histogram none.
+bool record_sizes_valid(int n_par, int n_perp, int64_t H, const uint8_t* flags, const uint64_t* off) {
+  const size_t N = (size_t)n_par * n_perp;
+  const size_t nlev = group_counts(n_par, n_perp).size(), hdr = (10 + nlev + 7) / 8 * 8;
+  for (int64_t h = 0; h < H; ++h) {
+    if (off[h + 1] < off[h]) return false;
+    const size_t size = (size_t)(off[h + 1] - off[h]);
+    if (flags[h] & HCZ_FLAG_RAW) {
+      if (size != 4 * N && size != 8 * N) return false;
+    } else if (flags[h] & HCZ_FLAG_CODED) {
+      if (size < hdr) return false;
+    } else if (size) {
+      return false;
+    }
+  }
+  return true;
+}
+
 // Split the records of a batch into the streams; false if a coded record is not in the
 // coder's canonical form (nlev, widths <= 32, size, zero padding bits).
 bool split_records(int n_par, int n_perp, int64_t H, const uint8_t* flags, const uint64_t* off,
@@ -393,6 +412,9 @@ hcz_status hcz_container_bound(const hcz_container_in* c, size_t* bytes) {
   if (!sizes_of(c->info, &z)) return set_error(HCZ_EINVAL, "bad container description");
   if (!c->res_offset) return set_error(HCZ_EINVAL, "res_offset is NULL");
   if (c->info.entropy < 0 || c->info.entropy > 2) return set_error(HCZ_EINVAL, "entropy must be 0, 1 or 2");
+  if (c->info.H && !c->flags) return set_error(HCZ_EINVAL, "flags is NULL");
+  if (!record_sizes_valid(c->info.n_par, c->info.n_perp, c->info.H, c->flags, c->res_offset))
+    return set_error(HCZ_EINVAL, "a residual record's size does not fit its flags");
   const size_t rb = (size_t)c->res_offset[c->info.H];
   const size_t codes = c->info.entropy ? rans_bound(z.codes_raw) : z.codes_raw;
   size_t res = c->info.entropy ? rans_bound(rb) : rb;
@@ -597,6 +619,8 @@ hcz_status hcz_container_unpack(const void* buf, size_t n, const hcz_container_o
     out->res_offset[h + 1] = out->res_offset[h] + r;
   }
   o += z.recs;
+  if (!record_sizes_valid(i.n_par, i.n_perp, i.H, out->flags, out->res_offset))
+    return set_error(HCZ_EINVAL, "a residual record's size does not fit its flags");
   if (i.entropy == 2) {
     size_t used = 0;
     if (!int_streams_read(i.n_par, i.n_perp, i.H, out->flags, out->res_offset, b + o, res_end - o,

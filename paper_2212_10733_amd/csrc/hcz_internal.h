@@ -438,6 +438,8 @@ hipError_t launch_mlp_infer(const float* params, const double* scale, const uint
 hipError_t launch_dequant(const uint8_t* codes, long long n, int latent, const float* centroids, int bits,
                           float* z, hipStream_t st);
 size_t norm_stats_ws_bytes(long long H, int N);
+hipError_t launch_col_normalize(const void* x, int dtype, long long rows, long long cols, long long ld,
+                                const float* mean, const float* sd, float* out, hipStream_t st);
 hipError_t launch_norm_stats(const void* hist, int dtype, long long H, long long hs, long long rs, int n_par,
                              int N, float* mean, float* sd, void* ws, hipStream_t st);
 hipError_t launch_codebook_fit(const float* z, long long n, int latent, long long every, int bits,

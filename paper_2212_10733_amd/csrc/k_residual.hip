@@ -631,6 +631,11 @@ __global__ __launch_bounds__(NT) void k_decompress(GridDev G, DecompressArgs a) 
     return;
   }
   if (fl & HCZ_FLAG_RAW) {
+    // a verbatim record holds exactly the N input values; any other size decodes to NaN
+    if (a.offsets[h + 1] - a.offsets[h] != (uint64_t)N * sizeof(TIn)) {
+      for (int e = t; e < N; e += NT) out[e] = (TOut)NAN;
+      return;
+    }
     const TIn* src = (const TIn*)rec;   // records start 4-byte aligned
     if (sizeof(TIn) == 8) {
       const uint32_t* s32 = (const uint32_t*)rec;

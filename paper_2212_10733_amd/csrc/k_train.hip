@@ -273,6 +273,33 @@ hipError_t launch_adam(float* p, const float* g, float* m, float* v, long long n
   return hipGetLastError();
 }
 
+// out[r][c] = (x[r][c] - mean[c]) / sd[c] in FP32 (x rounded to FP32 first; mean NULL = 0):
+// one thread per element, rows of ld elements.
+template <typename T>
+__global__ __launch_bounds__(256) void k_col_normalize(const T* x, long long rows, long long cols, long long ld,
+                                                       const float* mean, const float* sd, float* out) {
+  const long long n = rows * cols;
+  for (long long e = (long long)blockIdx.x * 256 + threadIdx.x; e < n; e += (long long)gridDim.x * 256) {
+    const long long r = e / cols, c = e - r * cols;
+    const float v = (float)x[r * ld + c];
+    out[e] = __fdiv_rn(mean ? __fsub_rn(v, mean[c]) : v, sd[c]);
+  }
+}
+
+hipError_t launch_col_normalize(const void* x, int dtype, long long rows, long long cols, long long ld,
+                                const float* mean, const float* sd, float* out, hipStream_t st) {
+  if (rows <= 0 || cols <= 0) return hipSuccess;
+  const long long n = rows * cols;
+  const unsigned nb = (unsigned)std::min<long long>((n + 255) / 256, 65536);
+  if (dtype == HCZ_F32)
+    hipLaunchKernelGGL(k_col_normalize<float>, dim3(nb), dim3(256), 0, st, (const float*)x, rows, cols, ld, mean,
+                       sd, out);
+  else
+    hipLaunchKernelGGL(k_col_normalize<double>, dim3(nb), dim3(256), 0, st, (const double*)x, rows, cols, ld,
+                       mean, sd, out);
+  return hipGetLastError();
+}
+
 size_t norm_stats_ws_bytes(long long H, int N) {
   const long long nb = (H + kStatRows - 1) / kStatRows;
   return (size_t)(nb * N + 2 * N) * sizeof(double);

@@ -1061,6 +1061,12 @@ __global__ __launch_bounds__(256, 2) void k_decompress_w(GridDev G, DecompressAr
     return;
   }
   if (fl & HCZ_FLAG_RAW) {
+    // a verbatim record holds exactly the N input values; any other size (a damaged
+    // stream, or records of the other input type) decodes to NaN instead of being read
+    if (a.offsets[h + 1] - a.offsets[h] != (uint64_t)N * sizeof(TIn)) {
+      for (int e = lane; e < N; e += 64) out[e] = (TOut)NAN;
+      return;
+    }
     if (sizeof(TIn) == 8) {
       const uint32_t* s32 = (const uint32_t*)rec;
       for (int e = lane; e < N; e += 64) {

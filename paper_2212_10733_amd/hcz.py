@@ -142,6 +142,9 @@ def _load() -> C.CDLL:
         "hcz_adam_step": [vp, vp, vp, vp, i64, C.c_double, C.c_double, C.c_double, C.c_double, i64, vp],
         "hcz_norm_stats_workspace": [vp, i64, C.POINTER(sz)],
         "hcz_norm_stats": [vp, vp, i32, i64, i64, i64, vp, vp, vp, sz, vp],
+        "hcz_column_stats_workspace": [i64, i64, C.POINTER(sz)],
+        "hcz_column_stats": [vp, i32, i64, i64, i64, vp, vp, vp, sz, vp],
+        "hcz_column_normalize": [vp, i32, i64, i64, i64, vp, vp, vp, vp],
         "hcz_plan_path": [vp, C.POINTER(i32)],
         "hcz_plan_variants": [vp, C.POINTER(i32), C.POINTER(i32)],
         "hcz_probe_sink_bytes": [C.POINTER(sz)],
@@ -193,7 +196,7 @@ EXPORTS = ["hcz_create", "hcz_destroy", "hcz_last_error", "hcz_version", "hcz_pl
            "hcz_timestamp", "hcz_wall_clock_hz", "hcz_container_bound", "hcz_container_pack",
            "hcz_container_read_info", "hcz_container_unpack", "hcz_rans_bound", "hcz_rans_encode",
            "hcz_rans_decode", "hcz_conv_ae_param_count", "hcz_conv_ae_saved_bytes", "hcz_conv_ae_forward",
-           "hcz_conv_ae_backward"]
+           "hcz_conv_ae_backward", "hcz_column_stats_workspace", "hcz_column_stats", "hcz_column_normalize"]
 
 STAGES = ["encode", "codebook", "quantize", "decode", "residual", "scan", "compact", "stats", "decompress",
           "warmstart"]
@@ -418,6 +421,7 @@ class Compressed:
     stream: torch.Tensor       # (capacity,) uint8
     stats_dev: torch.Tensor    # sizeof(hcz_stats) bytes
     t_done: torch.Tensor | None = None   # (H,) int64 (u64 bits): wall clock per histogram
+    in_dtype: torch.dtype | None = None  # element type the batch was compressed from
 
     def cstruct(self) -> CompressedC:
         return CompressedC(self.codes.data_ptr(), self.lam.data_ptr(), self.flags.data_ptr(),
@@ -521,6 +525,7 @@ def residual(plan: Plan, p: Params, hist: torch.Tensor, fhat: torch.Tensor | Non
     ws = workspace(nbytes.value, hist.device)
     out = alloc_compressed(H, plan.N, hist.device, capacity=capacity, in_bytes=hist.element_size(),
                            lambda_fp32=bool(p.lambda_fp32))
+    out.in_dtype = hist.dtype
     cs = out.cstruct()
     fh = None if fhat is None else fhat.contiguous()
     l0 = None if lam0 is None else lam0.contiguous()
@@ -549,11 +554,16 @@ class Compressor:
                                     lambda_fp32=bool(p.lambda_fp32), timestamps=timestamps)
         self.centroids = torch.zeros((LATENT, 1 << bits), dtype=torch.float32, device=device)
         self.bits = bits
+        self.in_dtype = in_dtype
 
     def compress(self, hist: torch.Tensor) -> Compressed:
         H, hs, rs = _strides(hist)
         if H > self.H:
             raise ValueError("batch larger than the compressor was sized for")
+        if hist.dtype == torch.float64 and self.in_dtype != torch.float64:
+            raise ValueError("FP64 input needs a compressor built with in_dtype=torch.float64 "
+                             "(its verbatim records take 8N bytes)")
+        self.out.in_dtype = hist.dtype
         cb = Codebook(self.bits, self.centroids.data_ptr())
         cs = self.out.cstruct()
         _check(LIB.hcz_compress(self.plan.h, None if self.model is None else self.model.h, C.byref(cb),
@@ -561,12 +571,19 @@ class Compressor:
                                 _ptr(self.ws), self.ws.numel(), _stream()))
         return self.out
 
-    def decompress(self, comp: Compressed, H: int, in_dtype=torch.float32,
+    def decompress(self, comp: Compressed, H: int, in_dtype=None,
                    out_dtype=torch.float64) -> torch.Tensor:
         out = torch.empty((H, self.plan.n_perp, self.plan.n_par), dtype=out_dtype, device=comp.lam.device)
         return self.decompress_into(comp, H, out, in_dtype)
 
-    def decompress_into(self, comp: Compressed, H: int, out: torch.Tensor, in_dtype=torch.float32):
+    def decompress_into(self, comp: Compressed, H: int, out: torch.Tensor, in_dtype=None):
+        """in_dtype: the element type the batch was compressed from (its verbatim records);
+        by default the one the batch records, else the compressor's.  A value that
+        contradicts the batch's own is refused."""
+        if in_dtype is None:
+            in_dtype = comp.in_dtype if comp.in_dtype is not None else self.in_dtype
+        elif comp.in_dtype is not None and in_dtype != comp.in_dtype:
+            raise ValueError(f"batch was compressed from {comp.in_dtype}, not {in_dtype}")
         cb = Codebook(self.bits, self.centroids.data_ptr())
         cs = comp.cstruct()
         _check(LIB.hcz_decompress(self.plan.h, None if self.model is None else self.model.h, C.byref(cb),
@@ -586,6 +603,42 @@ def norm_stats(plan: Plan, hist: torch.Tensor):
     _check(LIB.hcz_norm_stats(plan.h, _ptr(hist), _dtype_code(hist), H, hs, rs, _ptr(mu), _ptr(sd),
                               _ptr(ws), ws.numel(), _stream()))
     return mu, sd
+
+
+def _matrix(x: torch.Tensor):
+    """(rows, cols, row stride) of a 2-D view whose columns are contiguous (any trailing
+    dimensions of a contiguous tensor are flattened into the columns)."""
+    if x.dim() != 2:
+        x = x.reshape(x.shape[0], -1)
+    if x.stride(1) != 1:
+        raise ValueError("columns must be contiguous")
+    return x, x.shape[0], x.shape[1], x.stride(0)
+
+
+def column_stats(x: torch.Tensor):
+    """Per-column mean and population std (std floored at 1e-12 of the largest) of a matrix
+    (rows x cols, FP32 or FP64), as FP32 device tensors."""
+    x, rows, cols, ld = _matrix(x)
+    nbytes = C.c_size_t()
+    _check(LIB.hcz_column_stats_workspace(rows, cols, C.byref(nbytes)))
+    ws = workspace(nbytes.value, x.device)
+    mu = torch.empty(cols, dtype=torch.float32, device=x.device)
+    sd = torch.empty(cols, dtype=torch.float32, device=x.device)
+    _check(LIB.hcz_column_stats(_ptr(x), _dtype_code(x), rows, cols, ld, _ptr(mu), _ptr(sd), _ptr(ws), ws.numel(),
+                                _stream()))
+    return mu, sd
+
+
+def column_normalize(x: torch.Tensor, mean: torch.Tensor | None, std: torch.Tensor) -> torch.Tensor:
+    """(x - mean) / std per column in FP32 (mean None: x / std), as a dense FP32 matrix of
+    x's rows; histograms (H, n_perp, n_par) are taken as rows of N values."""
+    x, rows, cols, ld = _matrix(x)
+    out = torch.empty((rows, cols), dtype=torch.float32, device=x.device)
+    m = None if mean is None else mean.contiguous().float()
+    sd = std.contiguous().float()
+    _check(LIB.hcz_column_normalize(_ptr(x), _dtype_code(x), rows, cols, ld, _ptr(m), _ptr(sd), _ptr(out),
+                                    _stream()))
+    return out
 
 
 # ---- batches of subdomains --------------------------------------------------------------

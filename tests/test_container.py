@@ -55,11 +55,17 @@ def test_rans_rejects_malformed_blocks(H):
 
 
 def fake_batch(Hn, N, rng, lam_dtype=np.float64):
-    sizes = rng.integers(0, 300, Hn).astype(np.uint64)
-    sizes[rng.random(Hn) < 0.2] = 0
+    """Random flags with record sizes that fit them: a verbatim record holds the N input
+    values (FP32 here), a coded one at least its 24-byte header, the others nothing."""
+    flags = rng.integers(0, 32, Hn).astype(np.uint8)
+    flags[rng.random(Hn) < 0.9] &= ~np.uint8(4)
+    flags[Hn // 2] |= 4
+    sizes = rng.integers(24, 300, Hn).astype(np.uint64)
+    sizes[(flags & 1) == 0] = 0
+    sizes[(flags & 4) != 0] = 4 * N
     off = np.zeros(Hn + 1, np.uint64)
     off[1:] = np.cumsum(sizes)
-    return dict(flags=rng.integers(0, 32, Hn).astype(np.uint8), res_offset=off,
+    return dict(flags=flags, res_offset=off,
                 res_bytes=rng.geometric(0.1, int(off[-1])).clip(0, 255).astype(np.uint8),
                 lam=rng.standard_normal((Hn, 4)).astype(lam_dtype))
 
@@ -152,3 +158,41 @@ def test_integer_model_of_residual_records(H, shape):
         bad[e - 1] |= 0x80                               # a padding bit after the last integer
         with pytest.raises(RuntimeError):
             H.container_pack(n_par, n_perp, entropy=2, **dict(b, res_bytes=bad))
+
+
+def test_container_refuses_record_sizes_that_do_not_fit_their_flags(H):
+    """A verbatim record must hold exactly 4N or 8N bytes, a coded one at least its header,
+    any other histogram no bytes: packing refuses other sizes, and so does unpacking of a
+    buffer whose record-size table was altered (the header checksum does not cover it)."""
+    rng = np.random.default_rng(85)
+    Hn, N = 40, 1521
+    b = fake_batch(Hn, N, rng)
+    h = int(np.nonzero(b["flags"] & 4)[0][0])
+    for delta in (-4, 4):                                # a verbatim record one word short / long
+        sizes = np.diff(b["res_offset"]).astype(np.int64)
+        sizes[h] += delta
+        off = np.zeros(Hn + 1, np.uint64)
+        off[1:] = np.cumsum(sizes)
+        bytes_ = rng.integers(0, 256, int(off[-1]), dtype=np.uint8)
+        with pytest.raises(RuntimeError):
+            H.container_pack(39, 39, entropy=0, **dict(b, res_offset=off, res_bytes=bytes_))
+    # 8N is accepted (records of FP64 input)
+    sizes = np.diff(b["res_offset"]).astype(np.int64)
+    sizes[h] = 8 * N
+    off = np.zeros(Hn + 1, np.uint64)
+    off[1:] = np.cumsum(sizes)
+    ok = dict(b, res_offset=off, res_bytes=rng.integers(0, 256, int(off[-1]), dtype=np.uint8))
+    d = H.container_unpack(H.container_pack(39, 39, entropy=0, **ok))
+    assert np.array_equal(d["res_offset"], off)
+    # unpacking: move 4 bytes from the verbatim record's size to its neighbour's
+    buf = bytearray(H.container_pack(39, 39, entropy=0, **b))
+    table = 48 + Hn                                      # after the header (padded) and the flags
+    j = h + 1 if h + 1 < Hn else h - 1
+    sz = np.frombuffer(bytes(buf[table:table + 4 * Hn]), np.uint32).copy()
+    if not b["flags"][j] & 5:
+        j = int(np.nonzero((b["flags"] & 5) == 1)[0][0])
+    sz[h] -= 4
+    sz[j] += 4
+    buf[table:table + 4 * Hn] = sz.tobytes()
+    with pytest.raises(RuntimeError):
+        H.container_unpack(bytes(buf))

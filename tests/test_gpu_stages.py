@@ -472,6 +472,71 @@ def test_decompress_rejects_corrupt_headers(H, ctx, shape):
 
 
 @pytest.mark.parametrize("shape", [(39, 39), (49, 49)])
+def test_decompress_rejects_raw_records_of_wrong_size(H, ctx, shape):
+    """A verbatim record must hold exactly the N input values: the last histogram's record
+    cut 4 bytes short (ending at the stream's capacity) decodes to NaN instead of being read
+    past its end, and FP32 records decoded as FP64 input decode to NaN; coded records around
+    them decode as before (wave and workgroup kernels)."""
+    n = shape[0]
+    say("raw record sizes", shape)
+    g = grid.make_grid(n, n)
+    plan = H.Plan(ctx, n, n)
+    F = synth.histograms(6, n, n, seed=41, dtype=np.float32)
+    F[2, 1, 1] = np.nan
+    F[5, 2, 3] = np.nan
+    comp = pipeline.compress(F, g, None, None, pipeline.Params(tau=1e-3))
+    assert comp["flags"][2] & 4 and comp["flags"][5] & 4
+    ref = pipeline.decompress(comp, g, None, None, 6)
+    off = comp["offsets"].astype(np.int64).copy()
+    off[6] -= 4
+    stream = bytearray(comp["stream"][:off[6]])
+
+    def run(offsets, data, in_dtype):
+        c = H.alloc_compressed(6, plan.N, "cuda", capacity=len(data))
+        c.flags.copy_(torch.from_numpy(comp["flags"]))
+        c.lam.copy_(torch.from_numpy(comp["lam"]))
+        c.offsets.copy_(torch.from_numpy(offsets))
+        c.stream[:len(data)].copy_(torch.frombuffer(data, dtype=torch.uint8))
+        return H.Compressor(plan, None, 6, H.params()).decompress(c, 6, in_dtype=in_dtype).cpu().numpy()
+
+    out = run(off, stream, torch.float32)
+    assert np.all(np.isnan(out[5]))
+    ok = [0, 1, 3, 4]
+    assert np.allclose(out[ok], ref[ok], rtol=1e-13, atol=1e-15 * np.nanmax(np.abs(ref)))
+    assert np.array_equal(np.isnan(out[2]), np.isnan(ref[2]))
+    assert np.array_equal(out[2][~np.isnan(out[2])], ref[2][~np.isnan(ref[2])])
+    full = bytearray(comp["stream"])
+    out = run(comp["offsets"].astype(np.int64), full, torch.float64)
+    assert np.all(np.isnan(out[[2, 5]]))
+    assert np.allclose(out[ok], ref[ok], rtol=1e-13, atol=1e-15 * np.nanmax(np.abs(ref)))
+
+
+def test_fp64_round_trip_with_default_arguments(H, ctx):
+    """A compressor built for FP64 input decompresses with its own element type by default:
+    verbatim FP64 records come back bit for bit, the rest within the bound; asking for the
+    other type than the batch was compressed from is refused."""
+    say("fp64 default in_dtype")
+    plan = H.Plan(ctx)
+    F = synth.histograms(64, seed=42, dtype=np.float64)
+    F[9, 4, 4] = np.nan
+    cz = H.Compressor(plan, None, 64, H.params(tau=1e-3), in_dtype=torch.float64)
+    comp = cz.compress(to_dev(F))
+    out = cz.decompress(comp, 64).cpu().numpy()
+    flags = comp.flags.cpu().numpy()
+    assert flags[9] & 4
+    assert np.array_equal(np.isnan(out[9]), np.isnan(F[9]))
+    assert np.array_equal(out[9][~np.isnan(F[9])].view(np.uint64), F[9][~np.isnan(F[9])].view(np.uint64))
+    ok = (flags & 4) == 0
+    th = pipeline.tau_h(F[ok], pipeline.Params(tau=1e-3))
+    dist = np.sqrt(((out[ok] - F[ok]) ** 2).sum(axis=(1, 2)))
+    assert np.all(dist <= th)
+    with pytest.raises(ValueError):
+        cz.decompress(comp, 64, in_dtype=torch.float32)
+    with pytest.raises(ValueError):
+        H.Compressor(plan, None, 64, H.params(tau=1e-3)).compress(to_dev(F))
+
+
+@pytest.mark.parametrize("shape", [(39, 39), (49, 49)])
 def test_residual_warm_start(H, ctx, shape):
     """Warm starts near the solution, garbage and NaN: flags (incl. rejection), records and
     multipliers match the oracle given the same warm starts."""

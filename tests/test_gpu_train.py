@@ -123,6 +123,36 @@ def test_adam_and_norm_stats(T):
     assert np.allclose(sd.cpu().numpy(), so, rtol=1e-5, atol=1e-18)
 
 
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_column_stats_and_normalize(T, dtype):
+    """Column statistics of a strided matrix against the oracle's z-score statistics, and
+    the FP32 z-scoring of training rows bit for bit against NumPy's FP32 subtraction and
+    division (both IEEE round to nearest)."""
+    hcz, train = T
+    say("column stats / normalize", dtype.__name__)
+    rng = np.random.default_rng(13)
+    X = (rng.standard_normal((3000, 37)) * rng.random(37) * 5 + rng.standard_normal(37)).astype(dtype)
+    X[:, 4] = 1.5                                          # constant column: floored std
+    pad = np.zeros((3000, 40), dtype)
+    pad[:, :37] = X
+    xd = torch.from_numpy(pad).cuda()[:, :37]              # row stride 40
+    mu, sd = hcz.column_stats(xd)
+    mo, so = oracle.ae.norm_stats(X)
+    assert np.allclose(mu.cpu().numpy(), mo, rtol=1e-6, atol=1e-7)
+    assert np.allclose(sd.cpu().numpy(), so, rtol=1e-5, atol=1e-18)
+    out = hcz.column_normalize(xd, mu, sd).cpu().numpy()
+    m32, s32 = mu.cpu().numpy(), sd.cpu().numpy()
+    want = (X.astype(np.float32) - m32) / s32
+    assert out.dtype == np.float32 and np.array_equal(out, want)
+    out = hcz.column_normalize(xd, None, sd).cpu().numpy()
+    assert np.array_equal(out, X.astype(np.float32) / s32)
+    F = synth.histograms(50, seed=14, dtype=np.float32)
+    x = torch.from_numpy(F).cuda()
+    m, s = hcz.column_stats(x)
+    assert np.array_equal(hcz.column_normalize(x, m, s).cpu().numpy(),
+                          (F.reshape(50, -1) - m.cpu().numpy()) / s.cpu().numpy())
+
+
 def test_training_reduces_loss_and_residuals(T):
     hcz, train = T
     say("training")
