@@ -348,6 +348,25 @@ hcz_status hcz_compress(const hcz_plan* plan, const hcz_model* model, hcz_codebo
                         int64_t hist_stride, int64_t row_stride, hcz_compressed* out,
                         void* ws, size_t ws_bytes, hcz_stream_t stream);
 
+/* Compression that allocates nothing, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Same arguments, kernels and results as hcz_compress, without the workspace: the
+ * workspace is a scratch array of HCZ_STATIC_SCRATCH_BYTES (64 MiB) that the library holds
+ * on every device it has a context on, from hcz_create until the process ends.  A batch is
+ * accepted while the workspace hcz_compress would need for it (the layout for this dtype,
+ * model and codebook fit) fits that array: about 5,000 FP32 or 3,500 FP64 histograms of
+ * 39 x 39 with a model; larger batches return HCZ_EWORKSPACE, before any launch, with the
+ * largest batch that fits in the message.  Every call on a device shares that device's
+ * array and the array keeps the last call's contents (nothing in it needs to start at
+ * zero): calls that overlap on one device, e.g. on two streams, race and give undefined
+ * results; calls ordered on one stream are fine.  The caller still owns and passes the
+ * input and every output buffer.  Errors: as hcz_compress. */
+#define HCZ_STATIC_SCRATCH_BYTES (64u << 20)
+hcz_status hcz_compress_static(const hcz_plan* plan, const hcz_model* model, hcz_codebook* cb,
+                               const hcz_params* params, const void* hist, int32_t dtype, int64_t H,
+                               int64_t hist_stride, int64_t row_stride, hcz_compressed* out,
+                               hcz_stream_t stream);
+
 /* Decompress (Section III, last paragraph): out[H][N] in out_dtype, row-major.
  * in_dtype is the element type the batch was compressed from (verbatim records).
  * A histogram whose record ends past in->res_capacity decodes to NaN. */

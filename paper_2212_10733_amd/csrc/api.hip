@@ -62,8 +62,15 @@ struct ProfSet {
   bool live;
 };
 
+// Workspace of hcz_compress_static: a file-scope device array, one copy per device, held
+// until the process ends.  Host code never passes the array's name to a kernel (on the host
+// it only stands for the symbol); it uses the device address hipGetSymbolAddress gives for
+// the context's device, kept in hcz_ctx::scratch.
+static __device__ __align__(256) uint8_t scratch[HCZ_STATIC_SCRATCH_BYTES];
+
 struct hcz_ctx {
   int device;
+  uint8_t* scratch = nullptr;   // this device's address of `scratch`
   bool prof = false;
   std::vector<ProfSet> ring;
   int head = 0;
@@ -468,7 +475,11 @@ hcz_status hcz_create(int device, hcz_ctx** out) {
   HCZ_TRY(hipGetDeviceCount(&n), "hipGetDeviceCount");
   if (device < 0 || device >= n) return fail(HCZ_EINVAL, "device %d of %d", device, n);
   HCZ_TRY(hipSetDevice(device), "hipSetDevice");
-  *out = new hcz_ctx{device};
+  void* sp = nullptr;
+  HCZ_TRY(hipGetSymbolAddress(&sp, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+  hcz_ctx* c = new hcz_ctx{device};
+  c->scratch = (uint8_t*)sp;
+  *out = c;
   return HCZ_OK;
 }
 
@@ -1002,10 +1013,52 @@ hcz_status hcz_residual(const hcz_plan* plan, const hcz_params* params, const vo
                        (uint8_t*)ws, L, (hipStream_t)stream);
 }
 
+static hcz_status compress_impl(const hcz_plan* plan, const hcz_model* model, hcz_codebook* cb,
+                                const hcz_params* params, const void* hist, int32_t dtype, int64_t H,
+                                int64_t hist_stride, int64_t row_stride, hcz_compressed* out, void* ws,
+                                size_t ws_bytes, hcz_stream_t stream);
+
 hcz_status hcz_compress(const hcz_plan* plan, const hcz_model* model, hcz_codebook* cb,
                         const hcz_params* params, const void* hist, int32_t dtype, int64_t H,
                         int64_t hist_stride, int64_t row_stride, hcz_compressed* out, void* ws,
                         size_t ws_bytes, hcz_stream_t stream) {
+  return compress_impl(plan, model, cb, params, hist, dtype, H, hist_stride, row_stride, out, ws, ws_bytes,
+                       stream);
+}
+
+hcz_status hcz_compress_static(const hcz_plan* plan, const hcz_model* model, hcz_codebook* cb,
+                               const hcz_params* params, const void* hist, int32_t dtype, int64_t H,
+                               int64_t hist_stride, int64_t row_stride, hcz_compressed* out,
+                               hcz_stream_t stream) {
+  if (!plan) return fail(HCZ_EINVAL, "plan is NULL");
+  if (!plan->ctx->scratch) return fail(HCZ_EHIP, "no scratch address for device %d", plan->ctx->device);
+  if (params && H >= 0 && (dtype == HCZ_F32 || dtype == HCZ_F64)) {
+    const bool fit = model && params->fit_codebook;
+    const size_t need = ws_layout(plan->G, model != nullptr, H, dtype, fit, std::max(params->sample_every, 1)).total;
+    if (need > (size_t)HCZ_STATIC_SCRATCH_BYTES) {
+      int64_t lo = 0, hi = H;   // largest batch whose workspace fits, for the message
+      while (lo < hi) {
+        const int64_t mid = lo + (hi - lo + 1) / 2;
+        if (ws_layout(plan->G, model != nullptr, mid, dtype, fit, std::max(params->sample_every, 1)).total <=
+            (size_t)HCZ_STATIC_SCRATCH_BYTES)
+          lo = mid;
+        else
+          hi = mid - 1;
+      }
+      return fail(HCZ_EWORKSPACE,
+                  "hcz_compress_static: %lld histograms need %zu bytes of workspace, more than the %u-byte "
+                  "static scratch; at most %lld histograms of this grid, model and dtype fit",
+                  (long long)H, need, (unsigned)HCZ_STATIC_SCRATCH_BYTES, (long long)lo);
+    }
+  }
+  return compress_impl(plan, model, cb, params, hist, dtype, H, hist_stride, row_stride, out, plan->ctx->scratch,
+                       (size_t)HCZ_STATIC_SCRATCH_BYTES, stream);
+}
+
+static hcz_status compress_impl(const hcz_plan* plan, const hcz_model* model, hcz_codebook* cb,
+                                const hcz_params* params, const void* hist, int32_t dtype, int64_t H,
+                                int64_t hist_stride, int64_t row_stride, hcz_compressed* out, void* ws,
+                                size_t ws_bytes, hcz_stream_t stream) {
   if (!plan) return fail(HCZ_EINVAL, "plan is NULL");
   if (model && model->plan->G.N != plan->G.N) return fail(HCZ_EINVAL, "model was loaded for another grid");
   hcz_status s;

@@ -131,6 +131,8 @@ def _load() -> C.CDLL:
         "hcz_decompress_workspace": [vp, vp, i64, C.POINTER(sz)],
         "hcz_compress": [vp, vp, C.POINTER(Codebook), C.POINTER(Params), vp, i32, i64, i64, i64,
                          C.POINTER(CompressedC), vp, sz, vp],
+        "hcz_compress_static": [vp, vp, C.POINTER(Codebook), C.POINTER(Params), vp, i32, i64, i64, i64,
+                                C.POINTER(CompressedC), vp],
         "hcz_decompress": [vp, vp, C.POINTER(Codebook), C.POINTER(CompressedC), i32, i64, vp, i32, vp, sz, vp],
         "hcz_stats_read": [vp, C.POINTER(Stats), vp],
         "hcz_ae_param_count": [i32, C.POINTER(i64)],
@@ -196,7 +198,8 @@ EXPORTS = ["hcz_create", "hcz_destroy", "hcz_last_error", "hcz_version", "hcz_pl
            "hcz_timestamp", "hcz_wall_clock_hz", "hcz_container_bound", "hcz_container_pack",
            "hcz_container_read_info", "hcz_container_unpack", "hcz_rans_bound", "hcz_rans_encode",
            "hcz_rans_decode", "hcz_conv_ae_param_count", "hcz_conv_ae_saved_bytes", "hcz_conv_ae_forward",
-           "hcz_conv_ae_backward", "hcz_column_stats_workspace", "hcz_column_stats", "hcz_column_normalize"]
+           "hcz_conv_ae_backward", "hcz_column_stats_workspace", "hcz_column_stats", "hcz_column_normalize",
+           "hcz_compress_static"]
 
 STAGES = ["encode", "codebook", "quantize", "decode", "residual", "scan", "compact", "stats", "decompress",
           "warmstart"]
