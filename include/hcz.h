@@ -61,7 +61,7 @@ enum { HCZ_BOUND_AB = 0, HCZ_BOUND_UB = 1 };                /* coder step: searc
 enum { HCZ_SEARCH_GUIDED = 0, HCZ_SEARCH_BISECT = 1 };      /* how the coder step is searched */
 enum { HCZ_FLAG_CODED = 1, HCZ_FLAG_ROUND2 = 2, HCZ_FLAG_RAW = 4, HCZ_FLAG_WARM_REJECTED = 8,
        HCZ_FLAG_NOCLIP = 16, HCZ_FLAG_KL = 32 };
-enum { HCZ_WARM_COLD = 0, HCZ_WARM_MLP = 1 };
+enum { HCZ_WARM_COLD = 0, HCZ_WARM_MLP = 1, HCZ_WARM_ANALYTIC = 2 };
 
 typedef struct hcz_ctx hcz_ctx;
 typedef struct hcz_plan hcz_plan;
@@ -144,6 +144,12 @@ typedef struct {
  *                  network's multipliers (hcz_compress with a model only); the start is
  *                  rejected, and the solve restarts cold, if its first Newton step makes
  *                  max_k |g_k| / sum_j |A_kj| x_j grow (flag HCZ_FLAG_WARM_REJECTED).
+ *                  HCZ_WARM_ANALYTIC: round 1 starts from the multipliers of the projection
+ *                  without positivity, lam0 = (A A^T)^-1 (A f~ - b), computed in the kernel
+ *                  by one Newton step at lam = 0 over every cell; under the same acceptance
+ *                  rule (and the same flag when it is dropped).  Exact when no cell of
+ *                  f~ - A^T lam0 is negative.  mlp is not read.  Not combined with
+ *                  no_positivity or kl (HCZ_EINVAL).
  * lambda_fp32      1: store the multipliers as FP32 (the paper's float multipliers,
  *                  Section I and Fig. 7: QoIs to about 1e-8 instead of 1e-14); the
  *                  compressed batch's lambda_fp32 must say the same.
@@ -324,8 +330,8 @@ hcz_status hcz_decode(const hcz_model* model, const uint8_t* codes, const hcz_co
 
 /* Residual coding + QoI correction of H histograms against a given reconstruction
  * (Stages 4-5): fhat [H][N] FP32 row-major, or NULL for fhat = 0 (the coder-only
- * pipeline); lam0 [H][4] (FP64) warm-start multipliers or NULL (params->warm_start is
- * not used here).  Fills out->lambda, flags, res_offset, res_bytes, stats (codes
+ * pipeline); lam0 [H][4] (FP64) warm-start multipliers or NULL (params->warm_start
+ * HCZ_WARM_MLP is not used here; HCZ_WARM_ANALYTIC is, and then lam0 must be NULL).  Fills out->lambda, flags, res_offset, res_bytes, stats (codes
  * untouched).  Workspace: hcz_compress_workspace. */
 hcz_status hcz_residual(const hcz_plan* plan, const hcz_params* params, const void* hist,
                         int32_t dtype, int64_t H, int64_t hist_stride, int64_t row_stride,
@@ -485,17 +491,23 @@ hcz_status hcz_ae_backward(int32_t N, int32_t compute, const float* params, cons
                            const float* dz, const float* dxhat, void* saved, size_t saved_bytes,
                            float* grad, float* dx, hcz_stream_t stream);
 /* Convolutional model (39 x 39; the parameter blob in the hcz_model_desc order, 248,785
- * floats), FP32 throughout: forward writes z [B][16] and xhat [B][1521] for z-scored
- * x [B][1521] and keeps the pre-activations in `saved`; backward accumulates nothing: it
- * writes grad [248,785] (dL/dparams for dL/dxhat = dxhat and, if dz is not NULL, an extra
- * dL/dz) from the same saved buffer.  Sizes: hcz_conv_ae_saved_bytes. */
+ * floats): forward writes z [B][16] and xhat [B][1521] for z-scored x [B][1521] and keeps
+ * the pre-activations in `saved`; backward accumulates nothing: it writes grad [248,785]
+ * (dL/dparams for dL/dxhat = dxhat and, if dz is not NULL, an extra dL/dz) from the same
+ * saved buffer.  Sizes: hcz_conv_ae_saved_bytes.  compute HCZ_COMPUTE_FP32: FP32
+ * operands; HCZ_COMPUTE_BF16: both operands of every product of both passes (convolutions,
+ * transposed convolutions, dense layers, weight gradients) rounded to the nearest bfloat16,
+ * exact products, FP32 accumulation (FP64 in the convolution weight gradients); biases,
+ * ReLU, bias gradients, the loss and Adam stay FP32 on FP32 master weights (Section III
+ * Stage 2 trains the autoencoder; reduced precision is this library's option).  Both
+ * passes of one step take the same compute. */
 hcz_status hcz_conv_ae_param_count(int64_t* count);
 hcz_status hcz_conv_ae_saved_bytes(int64_t B, size_t* bytes);
-hcz_status hcz_conv_ae_forward(const float* params, const float* x, int64_t B, float* z, float* xhat,
-                               void* saved, size_t saved_bytes, hcz_stream_t stream);
-hcz_status hcz_conv_ae_backward(const float* params, const float* x, int64_t B, const float* dz,
-                                const float* dxhat, void* saved, size_t saved_bytes, float* grad,
-                                hcz_stream_t stream);
+hcz_status hcz_conv_ae_forward(int32_t compute, const float* params, const float* x, int64_t B, float* z,
+                               float* xhat, void* saved, size_t saved_bytes, hcz_stream_t stream);
+hcz_status hcz_conv_ae_backward(int32_t compute, const float* params, const float* x, int64_t B,
+                                const float* dz, const float* dxhat, void* saved, size_t saved_bytes,
+                                float* grad, hcz_stream_t stream);
 /* MSE of Eq. 5: *loss (device) = mean((xhat - x)^2) over n values; dxhat (or NULL) =
  * 2 (xhat - x) / n.  Workspace: hcz_mse_workspace bytes. */
 hcz_status hcz_mse_workspace(size_t* bytes);

@@ -10,6 +10,8 @@ Decoder:  hd = relu(dw zhat + db)   16 -> 6400, viewed as 64 x 10 x 10
                                     output padding 1 -> 20 x 20
           y  = convT2(h3)           transposed 3x3, 32 -> 1, stride 2, padding 1 -> 39 x 39
           fhat = sigma y + mu
+The plain FP64 model (encode64 / decode64) evaluates the same layers in FP64 throughout;
+it is the reference the BF16 form's error is stated against.
 BF16 form: the operands of conv2 and convT1 (h1, hd and their weights) are rounded to
 nearest-even bfloat16.  Both rounded activations come from FP32 fused multiply-add chains
 that the oracle reproduces exactly: h1 = b1 + sum over the window's in-range taps in
@@ -103,24 +105,55 @@ def decode_bf16(Zh: np.ndarray, W: dict, mu, sd) -> np.ndarray:
     return np.asarray(sd, np.float64) * y + np.asarray(mu, np.float64)
 
 
-# ---- training (FP64): the FP64 model throughout (no bfloat16), MSE loss (Eq. 5) -------------
+# ---- the plain FP64 model (no bfloat16, no FP32 chains) ----------------------------------
 
-def forward_train(X: np.ndarray, W: dict) -> dict:
-    """Forward pass of the FP64 model on z-scored rows X (B, 1521), keeping what the
-    backward pass needs."""
+def encode64(F64: np.ndarray, mu, sd, W: dict) -> np.ndarray:
+    """Latents z (H, 16) of the plain FP64 model: x = (f - mu) / sigma, then conv1, ReLU,
+    conv2, ReLU and the dense layer, every value and product in FP64 with the stored
+    weights widened exactly.  The reference the BF16 form's error is stated against."""
+    H = F64.shape[0]
+    x = ((np.asarray(F64, np.float64).reshape(H, 1521) - np.asarray(mu, np.float64))
+         / np.asarray(sd, np.float64)).reshape(H, 1, 39, 39)
+    w = {k: np.asarray(v, np.float64) for k, v in W.items()}
+    h1 = relu(conv2d_s2(x, w["c1w"], w["c1b"]))
+    h2 = relu(conv2d_s2(h1, w["c2w"], w["c2b"])).reshape(H, 6400)
+    return h2 @ w["fw"].T + w["fb"]
+
+
+def decode64(Zh: np.ndarray, W: dict, mu, sd) -> np.ndarray:
+    """fhat (H, 1521) of the plain FP64 model from dequantised latents."""
+    H = Zh.shape[0]
+    w = {k: np.asarray(v, np.float64) for k, v in W.items()}
+    hd = relu(np.asarray(Zh, np.float64) @ w["dw"].T + w["db"]).reshape(H, 64, 10, 10)
+    h3 = relu(conv_t2d_s2(hd, w["t1w"], w["t1b"], 20))
+    y = conv_t2d_s2(h3, w["t2w"], w["t2b"], 39).reshape(H, 1521)
+    return np.asarray(sd, np.float64) * y + np.asarray(mu, np.float64)
+
+
+# ---- training (FP64): MSE loss (Eq. 5); rnd = None is the FP64 model throughout, rnd = bf16
+# the BF16 training form (both operands of every product rounded, products exact, sums in
+# FP64 here; biases, ReLU and the bias gradients unrounded) ------------------------------
+
+def _r(a, rnd):
+    return a if rnd is None else rnd(a).astype(np.float64)
+
+
+def forward_train(X: np.ndarray, W: dict, rnd=None) -> dict:
+    """Forward pass on z-scored rows X (B, 1521), keeping what the backward pass needs."""
     B = X.shape[0]
     x = np.asarray(X, np.float64).reshape(B, 1, 39, 39)
     w = {k: np.asarray(v, np.float64) for k, v in W.items()}
-    a1 = conv2d_s2(x, w["c1w"], w["c1b"])
+    r = lambda a: _r(a, rnd)          # noqa: E731
+    a1 = conv2d_s2(r(x), r(w["c1w"]), w["c1b"])
     h1 = relu(a1)
-    a2 = conv2d_s2(h1, w["c2w"], w["c2b"])
+    a2 = conv2d_s2(r(h1), r(w["c2w"]), w["c2b"])
     h2 = relu(a2).reshape(B, 6400)
-    z = h2 @ w["fw"].T + w["fb"]
-    a4 = z @ w["dw"].T + w["db"]
+    z = r(h2) @ r(w["fw"]).T + w["fb"]
+    a4 = r(z) @ r(w["dw"]).T + w["db"]
     h4 = relu(a4).reshape(B, 64, 10, 10)
-    a5 = conv_t2d_s2(h4, w["t1w"], w["t1b"], 20)
+    a5 = conv_t2d_s2(r(h4), r(w["t1w"]), w["t1b"], 20)
     h5 = relu(a5)
-    xh = conv_t2d_s2(h5, w["t2w"], w["t2b"], 39).reshape(B, 1521)
+    xh = conv_t2d_s2(r(h5), r(w["t2w"]), w["t2b"], 39).reshape(B, 1521)
     return dict(x=x, a1=a1, h1=h1, a2=a2, h2=h2, z=z, a4=a4, h4=h4, a5=a5, h5=h5, xh=xh)
 
 
@@ -139,28 +172,30 @@ def _wgrad(coarse: np.ndarray, fine: np.ndarray) -> np.ndarray:
     return G
 
 
-def backward(cache: dict, W: dict, dxh: np.ndarray, dz: np.ndarray | None = None) -> dict:
-    """Gradients of every parameter for dL/dxhat = dxh (B, 1521) (plus dL/dz = dz)."""
+def backward(cache: dict, W: dict, dxh: np.ndarray, dz: np.ndarray | None = None, rnd=None) -> dict:
+    """Gradients of every parameter for dL/dxhat = dxh (B, 1521) (plus dL/dz = dz); rnd as in
+    `forward_train` (both operands of every product of the backward pass rounded)."""
     B = dxh.shape[0]
     w = {k: np.asarray(v, np.float64) for k, v in W.items()}
+    r = lambda a: _r(a, rnd)          # noqa: E731
     g = {}
     d = np.asarray(dxh, np.float64).reshape(B, 1, 39, 39)
-    g["t2w"] = _wgrad(cache["h5"], d)
+    g["t2w"] = _wgrad(r(cache["h5"]), r(d))
     g["t2b"] = d.sum(axis=(0, 2, 3))
-    d5 = conv2d_s2(d, w["t2w"], np.zeros(32)) * (cache["a5"] > 0)
-    g["t1w"] = _wgrad(cache["h4"], d5)
+    d5 = conv2d_s2(r(d), r(w["t2w"]), np.zeros(32)) * (cache["a5"] > 0)
+    g["t1w"] = _wgrad(r(cache["h4"]), r(d5))
     g["t1b"] = d5.sum(axis=(0, 2, 3))
-    d4 = conv2d_s2(d5, w["t1w"], np.zeros(64)).reshape(B, 6400) * (cache["a4"] > 0)
-    g["dw"] = d4.T @ cache["z"]
+    d4 = conv2d_s2(r(d5), r(w["t1w"]), np.zeros(64)).reshape(B, 6400) * (cache["a4"] > 0)
+    g["dw"] = r(d4).T @ r(cache["z"])
     g["db"] = d4.sum(axis=0)
-    dzt = d4 @ w["dw"] + (0.0 if dz is None else np.asarray(dz, np.float64))
-    g["fw"] = dzt.T @ cache["h2"]
+    dzt = r(d4) @ r(w["dw"]) + (0.0 if dz is None else np.asarray(dz, np.float64))
+    g["fw"] = r(dzt).T @ r(cache["h2"])
     g["fb"] = dzt.sum(axis=0)
-    d2 = (dzt @ w["fw"]).reshape(B, 64, 10, 10) * (cache["a2"] > 0)
-    g["c2w"] = _wgrad(d2, cache["h1"])
+    d2 = (r(dzt) @ r(w["fw"])).reshape(B, 64, 10, 10) * (cache["a2"] > 0)
+    g["c2w"] = _wgrad(r(d2), r(cache["h1"]))
     g["c2b"] = d2.sum(axis=(0, 2, 3))
-    d1 = conv_t2d_s2(d2, w["c2w"], np.zeros(32), 20) * (cache["a1"] > 0)
-    g["c1w"] = _wgrad(d1, cache["x"])
+    d1 = conv_t2d_s2(r(d2), r(w["c2w"]), np.zeros(32), 20) * (cache["a1"] > 0)
+    g["c1w"] = _wgrad(r(d1), r(cache["x"]))
     g["c1b"] = d1.sum(axis=(0, 2, 3))
     return g
 

@@ -116,6 +116,15 @@ def warm_ok(ft, A, b, lam0, s) -> bool:
     return scaled_residual(ft, A, b, lam0 + s * d) <= scaled_residual(ft, A, b, lam0)
 
 
+def analytic_start(ft: np.ndarray, b: np.ndarray, g: Grid) -> np.ndarray:
+    """The analytic-linear warm start: the multipliers of the projection without the
+    positivity constraint, lam0 = (A A^T)^-1 (A ft - b).  Exact whenever no cell of
+    ft - A^T lam0 is negative (then it is the Stage-5 solution itself); otherwise Newton
+    continues from it under the warm-start acceptance rule of `project`."""
+    A = g.A()
+    return np.linalg.solve(A @ A.T, A @ np.asarray(ft, np.float64).reshape(-1) - b)
+
+
 def project_linear(ft: np.ndarray, b: np.ndarray, g: Grid):
     """Reading without positivity: the orthogonal projection of ft onto {A x = b},
     x = ft - A^T lam with (A A^T) lam = A ft - b (the plain definition, one solve)."""

@@ -46,6 +46,7 @@ class Params:
     lambda_bits: int = 0            # > 0: multipliers rounded to this many mantissa bits
     ub_level: int | None = None     # None: searched coder step ('ab'); 0..40: the user's step ('ub')
     search: str = "guided"          # 'ab' search: "guided" (from the predicted index) or "bisect"
+    analytic_start: bool = False    # Newton starts from (A A^T)^-1 (A ft - b) (not with a network)
 
 
 def round_mantissa(v: np.ndarray, bits: int) -> np.ndarray:
@@ -92,7 +93,15 @@ def _f32(a: np.ndarray) -> np.ndarray:
     return np.asarray(a, np.float64).astype(np.float32).astype(np.float64)
 
 
+def _conv_plain(model: dict) -> bool:
+    """The convolutional model runs in its BF16 form unless model["compute"] == "fp64"
+    asks for the plain FP64 model (the reference for the BF16 form's error)."""
+    return model.get("arch", "dense") == "conv" and model.get("compute") == "fp64"
+
+
 def encode_ae(F64: np.ndarray, model: dict) -> np.ndarray:
+    if _conv_plain(model):
+        return conv.encode64(F64, model["mu"], model["sd"], model["W"])
     if model.get("arch", "dense") == "conv":
         sd32 = np.asarray(model["sd"], np.float32)
         return conv.encode_bf16(F64.astype(np.float32), np.asarray(model["mu"], np.float32),
@@ -107,6 +116,8 @@ def encode_ae(F64: np.ndarray, model: dict) -> np.ndarray:
 
 def reconstruct_ae(codes: np.ndarray, C: np.ndarray, model: dict, shape) -> np.ndarray:
     Zh = pq.decode(codes, C)
+    if _conv_plain(model):
+        return conv.decode64(Zh, model["W"], model["mu"], model["sd"]).reshape(shape)
     if model.get("arch", "dense") == "conv":
         return conv.decode_bf16(Zh, model["W"], np.asarray(model["mu"], np.float32),
                                 np.asarray(model["sd"], np.float32)).reshape(shape)
@@ -172,6 +183,13 @@ def compress(F: np.ndarray, g: Grid, model: dict | None, C: np.ndarray | None, p
     lam0 = None
     if warm is not None and model is not None:
         lam0 = mlp_net.predict(pq.decode(codes, C), warm[0], warm[1])
+    if p.analytic_start:
+        if lam0 is not None:
+            raise ValueError("the analytic start and a warm-start network exclude each other")
+        if not p.positivity or p.kl:
+            raise ValueError("the analytic start belongs to the projection with positivity")
+        lam0 = np.array([newton.analytic_start(ft[h], b[h], g) if not raw[h] else np.zeros(4)
+                         for h in range(H)]).reshape(H, 4)
     for h in range(H):
         if raw[h]:
             continue

@@ -408,7 +408,10 @@ hcz_status check_params(const hcz_params* p) {
   if (p->newton_max_iter < 0 || p->newton_max_iter2 < 0) return fail(HCZ_EINVAL, "newton iteration caps must be >= 0");
   if (p->fallback != HCZ_FALLBACK_BACKTRACK && p->fallback != HCZ_FALLBACK_PAPER) return fail(HCZ_EINVAL, "fallback");
   if (p->fit_codebook && p->sample_every < 1) return fail(HCZ_EINVAL, "sample_every must be >= 1");
-  if (p->warm_start != HCZ_WARM_COLD && p->warm_start != HCZ_WARM_MLP) return fail(HCZ_EINVAL, "warm_start");
+  if (p->warm_start != HCZ_WARM_COLD && p->warm_start != HCZ_WARM_MLP && p->warm_start != HCZ_WARM_ANALYTIC)
+    return fail(HCZ_EINVAL, "warm_start");
+  if (p->warm_start == HCZ_WARM_ANALYTIC && p->no_positivity)
+    return fail(HCZ_EINVAL, "the analytic start belongs to the projection with positivity");
   if (p->warm_start == HCZ_WARM_MLP && !p->mlp) return fail(HCZ_EINVAL, "warm_start needs an mlp");
   if (p->lambda_fp32 != 0 && p->lambda_fp32 != 1) return fail(HCZ_EINVAL, "lambda_fp32 must be 0 or 1");
   if (p->no_positivity != 0 && p->no_positivity != 1) return fail(HCZ_EINVAL, "no_positivity must be 0 or 1");
@@ -962,6 +965,7 @@ static hcz_status residual_impl(const hcz_plan* plan, const hcz_params* p, const
   a.kstar = ws + L.kstar;
   a.iters = (uint16_t*)(ws + L.iters);
   a.lam0 = lam0;
+  a.analytic = p->warm_start == HCZ_WARM_ANALYTIC;
   a.t_done = (unsigned long long*)out->t_done;
   hcz_ctx* c = plan->ctx;
   {
@@ -1005,6 +1009,8 @@ hcz_status hcz_residual(const hcz_plan* plan, const hcz_params* params, const vo
       (s = check_out(out, H, false)))
     return s;
   if (out->lambda_fp32 != params->lambda_fp32) return fail(HCZ_EINVAL, "out->lambda_fp32 differs from params");
+  if (lam0 && params->warm_start == HCZ_WARM_ANALYTIC)
+    return fail(HCZ_EINVAL, "lam0 is not given with the analytic start");
   const WsLayout L = ws_layout(plan->G, false, H, dtype, false, 1);
   if (!ws || ws_bytes < L.total) return fail(HCZ_EWORKSPACE, "workspace %zu < %zu", ws_bytes, L.total);
   if ((s = set_device(plan->ctx))) return s;
@@ -1242,9 +1248,11 @@ hcz_status hcz_conv_ae_saved_bytes(int64_t B, size_t* bytes) {
   return HCZ_OK;
 }
 
-hcz_status hcz_conv_ae_forward(const float* params, const float* x, int64_t B, float* z, float* xhat, void* saved,
-                               size_t saved_bytes, hcz_stream_t stream) {
+hcz_status hcz_conv_ae_forward(int32_t compute, const float* params, const float* x, int64_t B, float* z,
+                               float* xhat, void* saved, size_t saved_bytes, hcz_stream_t stream) {
   if (B < 0) return fail(HCZ_EINVAL, "bad size");
+  if (compute != HCZ_COMPUTE_FP32 && compute != HCZ_COMPUTE_BF16) return fail(HCZ_EINVAL, "compute");
+  const int bf = compute == HCZ_COMPUTE_BF16;
   if (B == 0) return HCZ_OK;
   if (!params || !x || !z || !xhat || !saved) return fail(HCZ_EINVAL, "NULL buffer");
   if (saved_bytes < (size_t)B * kConvSaved * sizeof(float)) return fail(HCZ_EWORKSPACE, "saved buffer too small");
@@ -1252,20 +1260,23 @@ hcz_status hcz_conv_ae_forward(const float* params, const float* x, int64_t B, f
   ConvSaved S(saved, B);
   const float* P = params;
   using O = ConvOff;
-  HCZ_TRY(launch_cv_fwd(x, 1, 39, 0, P + O::c1w, P + O::c1b, S.a1, 32, 20, B, st), "conv1");
-  HCZ_TRY(launch_cv_fwd(S.a1, 32, 20, 1, P + O::c2w, P + O::c2b, S.a2, 64, 10, B, st), "conv2");
+  HCZ_TRY(launch_cv_fwd(x, 1, 39, 0, P + O::c1w, P + O::c1b, S.a1, 32, 20, B, st, bf), "conv1");
+  HCZ_TRY(launch_cv_fwd(S.a1, 32, 20, 1, P + O::c2w, P + O::c2b, S.a2, 64, 10, B, st, bf), "conv2");
   HCZ_TRY(launch_relu_copy(S.a2, S.h2, (long long)B * 6400, st), "relu");
-  HCZ_TRY(launch_gemm(S.h2, 6400, 1, P + O::fw, 1, 6400, S.z, 16, B, 16, 6400, 1.f, 0.f, P + O::fb, 0, st), "fc");
+  HCZ_TRY(launch_gemm(S.h2, 6400, 1, P + O::fw, 1, 6400, S.z, 16, B, 16, 6400, 1.f, 0.f, P + O::fb, 0, st, bf), "fc");
   HCZ_TRY(hipMemcpyAsync(z, S.z, (size_t)B * 16 * sizeof(float), hipMemcpyDeviceToDevice, st), "copy z");
-  HCZ_TRY(launch_gemm(S.z, 16, 1, P + O::dw, 1, 16, S.a4, 6400, B, 6400, 16, 1.f, 0.f, P + O::db, 0, st), "dfc");
-  HCZ_TRY(launch_cvt_fwd(S.a4, 64, 10, 1, P + O::t1w, P + O::t1b, S.a5, 32, 20, B, st), "convT1");
-  HCZ_TRY(launch_cvt_fwd(S.a5, 32, 20, 1, P + O::t2w, P + O::t2b, xhat, 1, 39, B, st), "convT2");
+  HCZ_TRY(launch_gemm(S.z, 16, 1, P + O::dw, 1, 16, S.a4, 6400, B, 6400, 16, 1.f, 0.f, P + O::db, 0, st, bf), "dfc");
+  HCZ_TRY(launch_cvt_fwd(S.a4, 64, 10, 1, P + O::t1w, P + O::t1b, S.a5, 32, 20, B, st, bf), "convT1");
+  HCZ_TRY(launch_cvt_fwd(S.a5, 32, 20, 1, P + O::t2w, P + O::t2b, xhat, 1, 39, B, st, bf), "convT2");
   return HCZ_OK;
 }
 
-hcz_status hcz_conv_ae_backward(const float* params, const float* x, int64_t B, const float* dz_in,
-                                const float* dxh, void* saved, size_t saved_bytes, float* grad, hcz_stream_t stream) {
+hcz_status hcz_conv_ae_backward(int32_t compute, const float* params, const float* x, int64_t B,
+                                const float* dz_in, const float* dxh, void* saved, size_t saved_bytes, float* grad,
+                                hcz_stream_t stream) {
   if (B < 0) return fail(HCZ_EINVAL, "bad size");
+  if (compute != HCZ_COMPUTE_FP32 && compute != HCZ_COMPUTE_BF16) return fail(HCZ_EINVAL, "compute");
+  const int bf = compute == HCZ_COMPUTE_BF16;
   if (!params || !grad) return fail(HCZ_EINVAL, "NULL buffer");
   if (B > 0 && (!x || !dxh || !saved)) return fail(HCZ_EINVAL, "NULL buffer");
   if (saved_bytes < (size_t)B * kConvSaved * sizeof(float)) return fail(HCZ_EWORKSPACE, "saved buffer too small");
@@ -1275,36 +1286,36 @@ hcz_status hcz_conv_ae_backward(const float* params, const float* x, int64_t B, 
   float* G = grad;
   using O = ConvOff;
   // transposed conv2 (32 -> 1)
-  HCZ_TRY(launch_cv_fwd(dxh, 1, 39, 0, P + O::t2w, nullptr, S.T1, 32, 20, B, st), "dh5");
-  HCZ_TRY(launch_cv_wgrad(S.a5, 32, 20, 1, dxh, 1, 39, 0, B, G + O::t2w, st), "dt2w");
+  HCZ_TRY(launch_cv_fwd(dxh, 1, 39, 0, P + O::t2w, nullptr, S.T1, 32, 20, B, st, bf), "dh5");
+  HCZ_TRY(launch_cv_wgrad(S.a5, 32, 20, 1, dxh, 1, 39, 0, B, G + O::t2w, st, bf), "dt2w");
   HCZ_TRY(launch_chsum(dxh, 1, 1521, B, G + O::t2b, st), "dt2b");
   HCZ_TRY(launch_relu_mask(S.T1, S.a5, (long long)B * 12800, st), "relu mask");
   // transposed conv1 (64 -> 32)
-  HCZ_TRY(launch_cv_wgrad(S.a4, 64, 10, 1, S.T1, 32, 20, 0, B, G + O::t1w, st), "dt1w");
+  HCZ_TRY(launch_cv_wgrad(S.a4, 64, 10, 1, S.T1, 32, 20, 0, B, G + O::t1w, st, bf), "dt1w");
   HCZ_TRY(launch_chsum(S.T1, 32, 400, B, G + O::t1b, st), "dt1b");
-  HCZ_TRY(launch_cv_fwd(S.T1, 32, 20, 0, P + O::t1w, nullptr, S.T2, 64, 10, B, st), "dh4");
+  HCZ_TRY(launch_cv_fwd(S.T1, 32, 20, 0, P + O::t1w, nullptr, S.T2, 64, 10, B, st, bf), "dh4");
   HCZ_TRY(launch_relu_mask(S.T2, S.a4, (long long)B * 6400, st), "relu mask");
   // decoder dense layer (16 -> 6400)
-  HCZ_TRY(launch_gemm(S.T2, 1, 6400, S.z, 16, 1, G + O::dw, 16, 6400, 16, B, 1.f, 0.f, nullptr, 0, st), "ddw");
+  HCZ_TRY(launch_gemm(S.T2, 1, 6400, S.z, 16, 1, G + O::dw, 16, 6400, 16, B, 1.f, 0.f, nullptr, 0, st, bf), "ddw");
   HCZ_TRY(launch_colsum(S.T2, B, 6400, G + O::db, st), "ddb");
   if (dz_in) {
     HCZ_TRY(hipMemcpyAsync(S.dz, dz_in, (size_t)B * 16 * sizeof(float), hipMemcpyDeviceToDevice, st), "copy dz");
-    HCZ_TRY(launch_gemm(S.T2, 6400, 1, P + O::dw, 16, 1, S.dz, 16, B, 16, 6400, 1.f, 1.f, nullptr, 0, st), "dz");
+    HCZ_TRY(launch_gemm(S.T2, 6400, 1, P + O::dw, 16, 1, S.dz, 16, B, 16, 6400, 1.f, 1.f, nullptr, 0, st, bf), "dz");
   } else {
-    HCZ_TRY(launch_gemm(S.T2, 6400, 1, P + O::dw, 16, 1, S.dz, 16, B, 16, 6400, 1.f, 0.f, nullptr, 0, st), "dz");
+    HCZ_TRY(launch_gemm(S.T2, 6400, 1, P + O::dw, 16, 1, S.dz, 16, B, 16, 6400, 1.f, 0.f, nullptr, 0, st, bf), "dz");
   }
   // encoder dense layer (6400 -> 16)
-  HCZ_TRY(launch_gemm(S.dz, 1, 16, S.h2, 6400, 1, G + O::fw, 6400, 16, 6400, B, 1.f, 0.f, nullptr, 0, st), "dfw");
+  HCZ_TRY(launch_gemm(S.dz, 1, 16, S.h2, 6400, 1, G + O::fw, 6400, 16, 6400, B, 1.f, 0.f, nullptr, 0, st, bf), "dfw");
   HCZ_TRY(launch_colsum(S.dz, B, 16, G + O::fb, st), "dfb");
-  HCZ_TRY(launch_gemm(S.dz, 16, 1, P + O::fw, 6400, 1, S.T2, 6400, B, 6400, 16, 1.f, 0.f, nullptr, 0, st), "dh2");
+  HCZ_TRY(launch_gemm(S.dz, 16, 1, P + O::fw, 6400, 1, S.T2, 6400, B, 6400, 16, 1.f, 0.f, nullptr, 0, st, bf), "dh2");
   HCZ_TRY(launch_relu_mask(S.T2, S.a2, (long long)B * 6400, st), "relu mask");
   // conv2 (32 -> 64)
-  HCZ_TRY(launch_cv_wgrad(S.T2, 64, 10, 0, S.a1, 32, 20, 1, B, G + O::c2w, st), "dc2w");
+  HCZ_TRY(launch_cv_wgrad(S.T2, 64, 10, 0, S.a1, 32, 20, 1, B, G + O::c2w, st, bf), "dc2w");
   HCZ_TRY(launch_chsum(S.T2, 64, 100, B, G + O::c2b, st), "dc2b");
-  HCZ_TRY(launch_cvt_fwd(S.T2, 64, 10, 0, P + O::c2w, nullptr, S.T1, 32, 20, B, st), "dh1");
+  HCZ_TRY(launch_cvt_fwd(S.T2, 64, 10, 0, P + O::c2w, nullptr, S.T1, 32, 20, B, st, bf), "dh1");
   HCZ_TRY(launch_relu_mask(S.T1, S.a1, (long long)B * 12800, st), "relu mask");
   // conv1 (1 -> 32)
-  HCZ_TRY(launch_cv_wgrad(S.T1, 32, 20, 0, x, 1, 39, 0, B, G + O::c1w, st), "dc1w");
+  HCZ_TRY(launch_cv_wgrad(S.T1, 32, 20, 0, x, 1, 39, 0, B, G + O::c1w, st, bf), "dc1w");
   HCZ_TRY(launch_chsum(S.T1, 32, 400, B, G + O::c1b, st), "dc1b");
   return HCZ_OK;
 }

@@ -135,6 +135,7 @@ struct ResidualArgs {
   uint8_t* kstar;              // [H] 0xff if not coded
   uint16_t* iters;             // [H]
   const double* lam0;          // [H][4] warm start or null
+  int analytic;                // 1: warm start (A A^T)^-1 (A ft - b), formed in the kernel
   const double* tau_hist;      // [H] per-histogram tau, or null (tau for all)
   unsigned long long* t_done;  // [H] wall clock at the end of each histogram, or null
 };
@@ -412,11 +413,11 @@ hipError_t launch_conv_encode(const ModelDev& M, const void* hist, int dtype, lo
 hipError_t launch_conv_decode(const ModelDev& M, const uint8_t* codes, const float* centroids, int bits,
                               long long H, float* fhat, hipStream_t st);
 hipError_t launch_cv_fwd(const float* in, int C, int n, int relu_in, const float* w, const float* bias, float* out,
-                         int O, int m, long long B, hipStream_t st);
+                         int O, int m, long long B, hipStream_t st, int bf);
 hipError_t launch_cvt_fwd(const float* in, int C, int n, int relu_in, const float* w, const float* bias, float* out,
-                          int O, int m, long long B, hipStream_t st);
+                          int O, int m, long long B, hipStream_t st, int bf);
 hipError_t launch_cv_wgrad(const float* coarse, int Cc, int m, int relu_c, const float* fine, int Cf, int n,
-                           int relu_f, long long B, float* G, hipStream_t st);
+                           int relu_f, long long B, float* G, hipStream_t st, int bf);
 hipError_t launch_chsum(const float* d, int C, int P, long long B, float* out, hipStream_t st);
 hipError_t launch_relu_copy(const float* a, float* h, long long n, hipStream_t st);
 hipError_t launch_quantize(const float* z, long long n, int latent, const float* centroids,

@@ -354,12 +354,22 @@ hipError_t launch_conv_decode(const ModelDev& M, const uint8_t* codes, const flo
 }
 
 
-// ---- training of the convolutional model (FP32, Section III Stage 2, Eq. 5) ------------------
+// ---- training of the convolutional model (Section III Stage 2, Eq. 5) -----------------------
 // Generic batched layers, one thread per output value, FP32 fused multiply-adds; the
-// training path favours plainness over speed.  Layout [b][channel][y][x].
+// training path favours plainness over speed.  Layout [b][channel][y][x].  BF = true is
+// the BF16 training form: both operands of every product are rounded to the nearest
+// bfloat16 (ties to even) before the multiply, whose result is then exact in FP32, and
+// the sums stay FP32 (FP64 in the weight gradients); biases are not rounded.
+
+template <bool BF>
+__device__ __forceinline__ float opnd(float v) {
+  if constexpr (BF) return (float)(__bf16)v;
+  else return v;
+}
 
 // 3x3 convolution, stride 2, padding 1: out[b][o][oy][ox] = bias[o] + sum over c and the
 // in-range taps of in'[b][c][2oy-1+ky][2ox-1+kx] w[o][c][ky][kx]; in' = relu(in) if relu_in.
+template <bool BF>
 __global__ __launch_bounds__(256) void k_cv_fwd(const float* in, int C, int n, int relu_in, const float* w,
                                                 const float* bias, float* out, int O, int m, long long B) {
   const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
@@ -378,7 +388,7 @@ __global__ __launch_bounds__(256) void k_cv_fwd(const float* in, int C, int n, i
         if (ix < 0 || ix >= n) continue;
         float v = ip[iy * n + ix];
         if (relu_in) v = fmaxf(v, 0.0f);
-        s = fmaf(v, wp[ky * 3 + kx], s);
+        s = fmaf(opnd<BF>(v), opnd<BF>(wp[ky * 3 + kx]), s);
       }
     }
   }
@@ -387,6 +397,7 @@ __global__ __launch_bounds__(256) void k_cv_fwd(const float* in, int C, int n, i
 
 // 3x3 transposed convolution, stride 2, padding 1, output m x m: out[b][o][oy][ox] =
 // bias[o] + sum over c and the taps with oy = 2 iy - 1 + ky (iy in range) of in'[b][c][iy][ix] w[c][o][ky][kx].
+template <bool BF>
 __global__ __launch_bounds__(256) void k_cvt_fwd(const float* in, int C, int n, int relu_in, const float* w,
                                                  const float* bias, float* out, int O, int m, long long B) {
   const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
@@ -405,7 +416,7 @@ __global__ __launch_bounds__(256) void k_cvt_fwd(const float* in, int C, int n, 
         if (nx < 0 || (nx & 1) || (nx >> 1) >= n) continue;
         float v = ip[(ny >> 1) * n + (nx >> 1)];
         if (relu_in) v = fmaxf(v, 0.0f);
-        s = fmaf(v, wp[ky * 3 + kx], s);
+        s = fmaf(opnd<BF>(v), opnd<BF>(wp[ky * 3 + kx]), s);
       }
     }
   }
@@ -416,6 +427,7 @@ __global__ __launch_bounds__(256) void k_cvt_fwd(const float* in, int C, int n, 
 // (py, px) of coarse'[b][cc][py][px] fine'[b][cf][2py-1+ky][2px-1+kx] (in-range cells).
 // For a convolution coarse = dL/d(output), fine = its input; for a transposed one coarse =
 // its input, fine = dL/d(output).  One workgroup per (cc, cf), FP64 partial sums.
+template <bool BF>
 __global__ __launch_bounds__(256) void k_cv_wgrad(const float* coarse, int Cc, int m, int relu_c, const float* fine,
                                                   int Cf, int n, int relu_f, long long B, float* G) {
   __shared__ double red[9][256];
@@ -430,6 +442,7 @@ __global__ __launch_bounds__(256) void k_cv_wgrad(const float* coarse, int Cc, i
     const int py = pix / m, px = pix - py * m;
     float cv = coarse[(b * Cc + cc) * mm + pix];
     if (relu_c) cv = fmaxf(cv, 0.0f);
+    cv = opnd<BF>(cv);
     if (cv != 0.0f) {
       const float* fp = fine + ((b * Cf + cf) * n) * n;
 #pragma unroll
@@ -442,7 +455,7 @@ __global__ __launch_bounds__(256) void k_cv_wgrad(const float* coarse, int Cc, i
           if (ix < 0 || ix >= n) continue;
           float fv = fp[iy * n + ix];
           if (relu_f) fv = fmaxf(fv, 0.0f);
-          acc[ky * 3 + kx] += (double)cv * (double)fv;
+          acc[ky * 3 + kx] += (double)cv * (double)opnd<BF>(fv);
         }
       }
     }
@@ -497,23 +510,37 @@ __global__ __launch_bounds__(256) void k_relu_copy(const float* a, float* h, lon
 static unsigned nblk(long long n) { return (unsigned)((n + 255) / 256); }
 
 hipError_t launch_cv_fwd(const float* in, int C, int n, int relu_in, const float* w, const float* bias, float* out,
-                         int O, int m, long long B, hipStream_t st) {
+                         int O, int m, long long B, hipStream_t st, int bf) {
   if (B <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_cv_fwd, dim3(nblk(B * O * m * m)), dim3(256), 0, st, in, C, n, relu_in, w, bias, out, O, m, B);
+  if (bf)
+    hipLaunchKernelGGL(k_cv_fwd<true>, dim3(nblk(B * O * m * m)), dim3(256), 0, st, in, C, n, relu_in, w, bias, out, O,
+                       m, B);
+  else
+    hipLaunchKernelGGL(k_cv_fwd<false>, dim3(nblk(B * O * m * m)), dim3(256), 0, st, in, C, n, relu_in, w, bias, out,
+                       O, m, B);
   return hipGetLastError();
 }
 
 hipError_t launch_cvt_fwd(const float* in, int C, int n, int relu_in, const float* w, const float* bias, float* out,
-                          int O, int m, long long B, hipStream_t st) {
+                          int O, int m, long long B, hipStream_t st, int bf) {
   if (B <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_cvt_fwd, dim3(nblk(B * O * m * m)), dim3(256), 0, st, in, C, n, relu_in, w, bias, out, O, m, B);
+  if (bf)
+    hipLaunchKernelGGL(k_cvt_fwd<true>, dim3(nblk(B * O * m * m)), dim3(256), 0, st, in, C, n, relu_in, w, bias, out,
+                       O, m, B);
+  else
+    hipLaunchKernelGGL(k_cvt_fwd<false>, dim3(nblk(B * O * m * m)), dim3(256), 0, st, in, C, n, relu_in, w, bias, out,
+                       O, m, B);
   return hipGetLastError();
 }
 
 hipError_t launch_cv_wgrad(const float* coarse, int Cc, int m, int relu_c, const float* fine, int Cf, int n,
-                           int relu_f, long long B, float* G, hipStream_t st) {
-  hipLaunchKernelGGL(k_cv_wgrad, dim3((unsigned)(Cc * Cf)), dim3(256), 0, st, coarse, Cc, m, relu_c, fine, Cf, n,
-                     relu_f, B, G);
+                           int relu_f, long long B, float* G, hipStream_t st, int bf) {
+  if (bf)
+    hipLaunchKernelGGL(k_cv_wgrad<true>, dim3((unsigned)(Cc * Cf)), dim3(256), 0, st, coarse, Cc, m, relu_c, fine, Cf,
+                       n, relu_f, B, G);
+  else
+    hipLaunchKernelGGL(k_cv_wgrad<false>, dim3((unsigned)(Cc * Cf)), dim3(256), 0, st, coarse, Cc, m, relu_c, fine,
+                       Cf, n, relu_f, B, G);
   return hipGetLastError();
 }
 

@@ -442,14 +442,28 @@ __global__ __launch_bounds__(NT) void k_residual(GridDev G, ResidualArgs a) {
   int flags = 0, total_upd = 0;
   if (!raw) {
     const double* ft = buf;
-    if (a.lam0) {
+    if (a.lam0 || a.analytic) {
       // warm start: keep it unless round 1 allows no update, its Cholesky step fails, or
       // that step makes max_k |g_k| / s_k grow
       double l0[4], v[kNv], g[4], d[4];
       const bool pos = !a.no_positivity;
       bool ok0 = a.max_iter >= 1;
+      if (a.analytic) {
+        // (A A^T)^-1 (A ft - b): one Newton step at lam = 0 with every cell active
+        const double zero[4] = {0.0, 0.0, 0.0, 0.0};
+        newton_pass<NT>(G, ft, zero, v, red, false);
 #pragma unroll
-      for (int k = 0; k < 4; ++k) { l0[k] = a.lam0[h * 4 + k]; ok0 = ok0 && isfinite(l0[k]); }
+        for (int k = 0; k < 4; ++k) g[k] = v[k] - b[k];
+        if (!chol_solve4(v, g, l0)) {
+#pragma unroll
+          for (int k = 0; k < 4; ++k) l0[k] = NAN;
+        }
+      } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) l0[k] = a.lam0[h * 4 + k];
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) ok0 = ok0 && isfinite(l0[k]);
       if (ok0) {
         newton_pass<NT>(G, ft, l0, v, red, pos);
         double r0 = 0.0;

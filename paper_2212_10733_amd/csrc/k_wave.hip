@@ -996,13 +996,26 @@ __global__ __launch_bounds__(256, 2) void k_residual_w(GridDev G, ResidualArgs a
     if (a.lam0) {
 #pragma unroll
       for (int k = 0; k < 4; ++k) l0[k] = a.lam0[h * 4 + k];
+    } else if (a.analytic) {
+      // the analytic start (A A^T)^-1 (A ft - b): one Newton step at lam = 0 with every
+      // cell active; a failed factorisation leaves a non-finite start, which is rejected
+      double v[16], sc[4], hh[9], g[4];
+      newton_pass_w<SH, UVOL, false, false>(G, L, l0, v, sc, hh);
+      hess_reduce<UVOL>(G, hh, v);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) g[k] = v[k] - b[k];
+      if (!chol4(v, g, l0)) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) l0[k] = NAN;
+      }
     }
+    const bool have_l0 = a.lam0 != nullptr || a.analytic;
     bool rejected = false;
     const int st = a.no_positivity
                        ? newton_w<SH, UVOL, false>(G, L, b, lam, a.newton_s, a.max_iter, paper ? 0.01 : 1.0,
-                                                   a.max_iter2, !paper, &total_upd, a.lam0 != nullptr, l0, &rejected)
+                                                   a.max_iter2, !paper, &total_upd, have_l0, l0, &rejected)
                        : newton_w<SH, UVOL, true>(G, L, b, lam, a.newton_s, a.max_iter, paper ? 0.01 : 1.0,
-                                                  a.max_iter2, !paper, &total_upd, a.lam0 != nullptr, l0, &rejected);
+                                                  a.max_iter2, !paper, &total_upd, have_l0, l0, &rejected);
     if (rejected) flags |= HCZ_FLAG_WARM_REJECTED;
     if (st >= 1) flags |= HCZ_FLAG_ROUND2;
     if (st == 2) raw = true;

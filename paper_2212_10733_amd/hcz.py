@@ -23,7 +23,7 @@ _COMPUTE = {"fp32": COMPUTE_FP32, "bf16": COMPUTE_BF16, "fp64": COMPUTE_FP64}
 TAU_REL_L2, TAU_NRMSE = 0, 1
 FALLBACK_BACKTRACK, FALLBACK_PAPER = 0, 1
 FLAG_CODED, FLAG_ROUND2, FLAG_RAW, FLAG_WARM_REJECTED, FLAG_NOCLIP, FLAG_KL = 1, 2, 4, 8, 16, 32
-WARM_COLD, WARM_MLP = 0, 1
+WARM_COLD, WARM_MLP, WARM_ANALYTIC = 0, 1, 2
 BOUND_AB, BOUND_UB = 0, 1
 SEARCH_GUIDED, SEARCH_BISECT = 0, 1
 HIDDEN, LATENT = 128, 16
@@ -161,8 +161,8 @@ def _load() -> C.CDLL:
         "hcz_wall_clock_hz": [C.c_int, C.POINTER(C.c_double)],
         "hcz_conv_ae_param_count": [C.POINTER(i64)],
         "hcz_conv_ae_saved_bytes": [i64, C.POINTER(sz)],
-        "hcz_conv_ae_forward": [vp, vp, i64, vp, vp, vp, sz, vp],
-        "hcz_conv_ae_backward": [vp, vp, i64, vp, vp, vp, sz, vp, vp],
+        "hcz_conv_ae_forward": [i32, vp, vp, i64, vp, vp, vp, sz, vp],
+        "hcz_conv_ae_backward": [i32, vp, vp, i64, vp, vp, vp, sz, vp, vp],
         "hcz_container_bound": [C.POINTER(ContainerIn), C.POINTER(sz)],
         "hcz_container_pack": [C.POINTER(ContainerIn), vp, sz, C.POINTER(sz)],
         "hcz_container_read_info": [vp, sz, C.POINTER(ContainerInfo)],
@@ -361,19 +361,23 @@ class Model:
 def params(tau=1e-3, tau_mode=TAU_REL_L2, newton_s=1.0, newton_max_iter=50, newton_max_iter2=400,
            fallback=FALLBACK_BACKTRACK, fit_codebook=False, sample_every=16, mlp=None, lambda_fp32=False,
            no_positivity=False, tau_hist: torch.Tensor | None = None, kl=False, lambda_bits: int = 0,
-           ub_level: int | None = None, search: str = "guided") -> Params:
+           ub_level: int | None = None, search: str = "guided", analytic_start: bool = False) -> Params:
     """tau_hist: optional per-histogram bounds (device, float64, one per histogram), used in
     place of tau.  ub_level: None searches the coder's step per histogram ('ab'); an
     integer 0..40 quantises every coded histogram with that ladder step ('ub').  search:
     "guided" (exponential search from the predicted ladder index, then bisection) or
-    "bisect" (bisection over the whole ladder)."""
+    "bisect" (bisection over the whole ladder).  analytic_start: Newton starts from
+    (A A^T)^-1 (A f~ - b) under the warm-start acceptance rule (not with mlp)."""
+    if analytic_start and mlp is not None:
+        raise ValueError("analytic_start and a warm-start network exclude each other")
     if search not in ("guided", "bisect"):
         raise ValueError("search must be 'guided' or 'bisect'")
     if tau_hist is not None and (tau_hist.dtype != torch.float64 or not tau_hist.is_cuda
                                  or not tau_hist.is_contiguous()):
         raise ValueError("tau_hist must be a contiguous float64 device tensor")
     p = Params(tau, tau_mode, newton_s, newton_max_iter, newton_max_iter2, fallback,
-               int(fit_codebook), sample_every, WARM_MLP if mlp is not None else WARM_COLD,
+               int(fit_codebook), sample_every,
+               WARM_MLP if mlp is not None else WARM_ANALYTIC if analytic_start else WARM_COLD,
                None if mlp is None else mlp.h, int(lambda_fp32), int(no_positivity),
                None if tau_hist is None else tau_hist.data_ptr(), int(kl), int(lambda_bits),
                BOUND_AB if ub_level is None else BOUND_UB, 0 if ub_level is None else int(ub_level),

@@ -96,10 +96,12 @@ def unpack_conv(p: torch.Tensor) -> dict:
 
 
 class ConvAE(torch.autograd.Function):
-    """The convolutional model (39 x 39) in FP32: hcz_conv_ae_forward / backward."""
+    """The convolutional model (39 x 39): hcz_conv_ae_forward / backward.  apply(x, params,
+    compute=hcz.COMPUTE_FP32); with hcz.COMPUTE_BF16 every product of both passes takes
+    bfloat16 operands (FP32 accumulation and master weights)."""
 
     @staticmethod
-    def forward(ctx, x: torch.Tensor, params: torch.Tensor):
+    def forward(ctx, x: torch.Tensor, params: torch.Tensor, compute: int = hcz.COMPUTE_FP32):
         x = x.contiguous()
         B = x.shape[0]
         nbytes = C.c_size_t()
@@ -107,9 +109,10 @@ class ConvAE(torch.autograd.Function):
         saved = torch.empty(max(nbytes.value, 4) // 4, dtype=torch.float32, device=x.device)
         z = torch.empty((B, hcz.LATENT), dtype=torch.float32, device=x.device)
         xh = torch.empty((B, 1521), dtype=torch.float32, device=x.device)
-        _check(LIB.hcz_conv_ae_forward(_ptr(params), _ptr(x), B, _ptr(z), _ptr(xh), _ptr(saved), saved.numel() * 4,
-                                       _stream()))
+        _check(LIB.hcz_conv_ae_forward(compute, _ptr(params), _ptr(x), B, _ptr(z), _ptr(xh), _ptr(saved),
+                                       saved.numel() * 4, _stream()))
         ctx.save_for_backward(x, params, saved)
+        ctx.compute = compute
         return z, xh
 
     @staticmethod
@@ -120,9 +123,9 @@ class ConvAE(torch.autograd.Function):
         dz = None if dz is None else dz.contiguous()
         if dxh is None:
             dxh = torch.zeros_like(x)
-        _check(LIB.hcz_conv_ae_backward(_ptr(params), _ptr(x), B, _ptr(dz), _ptr(dxh.contiguous()), _ptr(saved),
-                                        saved.numel() * 4, _ptr(grad), _stream()))
-        return None, grad
+        _check(LIB.hcz_conv_ae_backward(ctx.compute, _ptr(params), _ptr(x), B, _ptr(dz), _ptr(dxh.contiguous()),
+                                        _ptr(saved), saved.numel() * 4, _ptr(grad), _stream()))
+        return None, grad, None
 
 
 class MSE(torch.autograd.Function):
@@ -153,10 +156,10 @@ class Trainer:
 
     def __init__(self, params: torch.Tensor, lr=1e-3, betas=(0.9, 0.999), eps=1e-8, arch: str = "dense",
                  compute: str = "fp32"):
-        """compute: "fp32", or "bf16" (dense model only): bfloat16 operands in every product,
-        FP32 accumulation, FP32 master weights and Adam state."""
-        if compute not in ("fp32", "bf16") or (compute == "bf16" and arch != "dense"):
-            raise ValueError("compute must be 'fp32', or 'bf16' with the dense model")
+        """compute: "fp32", or "bf16": bfloat16 operands in every product, FP32 accumulation,
+        FP32 master weights and Adam state (dense and convolutional models)."""
+        if compute not in ("fp32", "bf16") or arch not in ("dense", "conv"):
+            raise ValueError("compute must be 'fp32' or 'bf16', arch 'dense' or 'conv'")
         self.arch = arch
         self.compute = hcz.COMPUTE_BF16 if compute == "bf16" else hcz.COMPUTE_FP32
         self.p = params.detach().clone().contiguous()
@@ -173,7 +176,7 @@ class Trainer:
 
     def train_step(self, xb: torch.Tensor) -> torch.Tensor:
         p = self.p.detach().requires_grad_(True)
-        _, xh = ConvAE.apply(xb, p) if self.arch == "conv" else DenseAE.apply(xb, p, self.compute)
+        _, xh = ConvAE.apply(xb, p, self.compute) if self.arch == "conv" else DenseAE.apply(xb, p, self.compute)
         loss = mse(xh, xb)
         loss.backward()
         self.step(p.grad)

@@ -204,7 +204,8 @@ def test_decode_parity_bf16(H, ctx, Hn, shape):
 # ---- residual coder + Newton -------------------------------------------------------------------
 
 def oracle_residual(F, fhat, g, p, lam0=None):
-    """Oracle compress with a given reconstruction (the coder-only pipeline when fhat is None)."""
+    """Oracle compress with a given reconstruction (the coder-only pipeline when fhat is None);
+    p.analytic_start seeds Newton with the oracle's own analytic start."""
     class _M:   # pipeline hook: a fixed reconstruction instead of the autoencoder
         pass
     Hn = F.shape[0]
@@ -253,8 +254,10 @@ def oracle_residual(F, fhat, g, p, lam0=None):
             out["margin"][h] = abs(rr[h] - thr[h] ** 2) / max(thr[h] ** 2, 1e-300)
         flag = 0
         if not raw[h]:
+            l0 = oracle.newton.analytic_start(fh[h], b[h], g) if p.analytic_start else \
+                None if lam0 is None else lam0[h]
             res = oracle.newton.project(fh[h], b[h], g, p.newton_s, p.newton_max_iter, p.newton_max_iter2, p.fallback,
-                                        lam0=None if lam0 is None else lam0[h], positivity=p.positivity)
+                                        lam0=l0, positivity=p.positivity)
             out["iters"][h] = res["iters"]
             if res.get("warm_rejected"):
                 flag |= 8
@@ -278,7 +281,7 @@ def oracle_residual(F, fhat, g, p, lam0=None):
     return out
 
 
-def compare_residual(H, plan, g, F, fhat, p, hp, near_tie=1e-9, lam0=None):
+def compare_residual(H, plan, g, F, fhat, p, hp, near_tie=1e-9, lam0=None, flag_mask=0xff):
     Hn = F.shape[0]
     comp = H.residual(plan, hp, to_dev(F), None if fhat is None else to_dev(fhat),
                       lam0=None if lam0 is None else to_dev(lam0))
@@ -290,7 +293,7 @@ def compare_residual(H, plan, g, F, fhat, p, hp, near_tie=1e-9, lam0=None):
     st = comp.stats()
     ref = oracle_residual(F, fhat, g, p, lam0=lam0)
     sure = ref["margin"] > near_tie          # decisions that rounding order cannot flip
-    assert np.array_equal(flags[sure], ref["flags"][sure])
+    assert np.array_equal(flags[sure] & flag_mask, ref["flags"][sure] & flag_mask)
     assert (~sure).sum() <= max(1, Hn // 1000)
     nrec_equal = 0
     for h in np.nonzero(sure)[0]:
@@ -559,3 +562,31 @@ def test_residual_warm_start(H, ctx, shape):
     assert acc.sum() > 50
     st = comp.stats()
     assert st["newton_iters_total"] < cold["iters"].sum()
+
+
+@pytest.mark.parametrize("shape", [(39, 39), (33, 33), (65, 65)])
+def test_residual_analytic_start(H, ctx, shape):
+    """The analytic-linear start (A A^T)^-1 (A f~ - b), formed in the kernel from its own f~:
+    records and flags equal to the oracle seeded with its own analytic start, multipliers
+    to the Newton tolerance, the acceptance decision (flag bit 3) on all but near-ties, and
+    the same projection as the cold start; on the compiled 39x39, run-time-table and
+    workgroup kernels."""
+    n = shape[0]
+    say("analytic start", shape)
+    g = grid.make_grid(n, n)
+    plan = H.Plan(ctx, n, n)
+    F = synth.histograms(128, n, n, seed=41, dtype=np.float32)
+    fhat = synth.perturbed(F, np.geomspace(1e-4, 3e-2, 128), seed=42)
+    p = pipeline.Params(tau=1e-3, analytic_start=True)
+    comp, ref, _ = compare_residual(H, plan, g, F, fhat, p, H.params(tau=1e-3, analytic_start=True),
+                                    flag_mask=0xff & ~8)
+    flags = comp.flags.cpu().numpy()
+    agree = ((flags & 8) == (ref["flags"] & 8)).mean()
+    assert agree >= 0.98, agree
+    cold = H.residual(plan, H.params(tau=1e-3), to_dev(F), to_dev(fhat))
+    lam_c, lam_a = cold.lam.cpu().numpy(), comp.lam.cpu().numpy()
+    ok = (flags & 4) == 0
+    assert np.allclose(lam_a[ok], lam_c[ok], rtol=1e-7, atol=1e-9 * np.abs(lam_c[ok]).max())
+    assert cold.stream_bytes() == comp.stream_bytes()
+    with pytest.raises(Exception):
+        H.residual(plan, H.params(tau=1e-3, analytic_start=True, no_positivity=True), to_dev(F), to_dev(fhat))

@@ -472,4 +472,49 @@ def test_bf16_training_end_to_end(T):
     assert l16[-1] < 0.6 * l16[0]
     assert abs(l16[-1] - l32[-1]) < 0.15 * l32[-1], (l16, l32)
     with pytest.raises(ValueError):
-        train.Trainer(train.pack(W0), compute="bf16", arch="conv")
+        train.Trainer(train.pack(W0), compute="fp16")
+
+
+def test_conv_bf16_training(T):
+    """BF16 training of the convolutional model: one step's gradients (with an extra dL/dz)
+    against the oracle's BF16 form (bfloat16 operands of every product, its own rounding
+    decisions on FP64 activations) within 2e-2 in norm and against the FP64 gradients
+    within 1e-1, the loss against the oracle's BF16 forward, and a short training run in
+    BF16 that follows the FP32 run."""
+    hcz, train = T
+    say("conv bf16 training")
+    from oracle import conv as oconv
+    rng = np.random.default_rng(93)
+    W = synth.conv_ae_weights(6)
+    for k in ("c1b", "c2b", "fb", "db", "t1b", "t2b"):
+        W[k] = rng.normal(0, 0.05, W[k].shape).astype(np.float32)
+    B = 96
+    X = inputs(B, 1521, seed=94)
+    p = train.pack_conv(W).requires_grad_(True)
+    x = torch.from_numpy(X).cuda()
+    z, xh = train.ConvAE.apply(x, p, hcz.COMPUTE_BF16)
+    dz = torch.from_numpy(rng.standard_normal((B, 16)).astype(np.float32) * 1e-3).cuda()
+    loss = train.mse(xh, x)
+    (loss + (z * dz).sum()).backward()
+    torch.cuda.synchronize()
+    X64 = X.astype(np.float64)
+    c16 = oconv.forward_train(X64, W, rnd=oracle.ae.bf16)
+    assert loss.item() == pytest.approx(float(np.mean((c16["xh"] - X64) ** 2)), rel=1e-3)
+    dz64 = dz.cpu().numpy().astype(np.float64)
+    g16 = oconv.backward(c16, W, 2 * (c16["xh"] - X64) / X.size, dz64, rnd=oracle.ae.bf16)
+    c64 = oconv.forward_train(X64, W)
+    g64 = oconv.backward(c64, W, 2 * (c64["xh"] - X64) / X.size, dz64)
+    g = train.unpack_conv(p.grad)
+    for k in hcz.CONV_KEYS:
+        n16 = np.linalg.norm(g[k] - g16[k]) / np.linalg.norm(g16[k])
+        n64 = np.linalg.norm(g[k] - g64[k]) / np.linalg.norm(g64[k])
+        assert n16 < 2e-2 and n64 < 1e-1, (k, n16, n64)
+    F = synth.histograms(2048, seed=95, dtype=np.float32).reshape(2048, -1)
+    mu, sd = oracle.ae.norm_stats(F)
+    Xt = torch.from_numpy(((F - mu) / sd).astype(np.float32)).cuda()
+    W0 = synth.conv_ae_weights()
+    l32 = train.Trainer(train.pack_conv(W0), lr=1e-3, arch="conv").fit(Xt, epochs=6, batch=256)
+    l16 = train.Trainer(train.pack_conv(W0), lr=1e-3, arch="conv", compute="bf16").fit(Xt, epochs=6, batch=256)
+    say("conv losses fp32", l32, "bf16", l16)
+    assert l16[-1] < 0.7 * l16[0]
+    assert abs(l16[-1] - l32[-1]) < 0.15 * l32[-1], (l16, l32)

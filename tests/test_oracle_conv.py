@@ -137,3 +137,68 @@ def test_training_gradients_match_torch_autograd():
         Wm[k][idx] -= hstep
         fd = (conv.loss(X, Wp) - conv.loss(X, Wm)) / (2 * hstep)
         assert abs(g0[k][idx] - fd) <= 1e-4 * max(abs(fd), 1e-8) + 1e-11, (k, g0[k][idx], fd)   # ReLU kinks
+
+
+def test_plain_fp64_model_matches_torch_and_training_forward():
+    """encode64 / decode64 (the reference the BF16 form's error is stated against) against
+    torch's CPU FP64 layers on the same weights, and against the training forward pass on
+    the same z-scored rows; the z-scoring divides by sigma in FP64."""
+    F = synth.histograms(5, seed=54, dtype=np.float64)
+    W = synth.conv_ae_weights()
+    rng = np.random.default_rng(54)
+    for k in ("c1b", "c2b", "fb", "db", "t1b", "t2b"):
+        W[k] = rng.normal(0, 0.05, W[k].shape).astype(np.float32)
+    mu, sd = oracle.ae.norm_stats(F)
+    z = conv.encode64(F, mu, sd, W)
+    X = (F.reshape(5, -1) - mu) / sd
+    Wt = {k: t64(v) for k, v in W.items()}
+    h1 = torch.relu(Fn.conv2d(t64(X.reshape(5, 1, 39, 39)), Wt["c1w"], Wt["c1b"], stride=2, padding=1))
+    h2 = torch.relu(Fn.conv2d(h1, Wt["c2w"], Wt["c2b"], stride=2, padding=1))
+    zt = (h2.reshape(5, -1) @ Wt["fw"].T + Wt["fb"]).numpy()
+    assert np.allclose(z, zt, rtol=1e-12, atol=1e-12 * np.abs(zt).max())
+    cache = conv.forward_train(X, W)
+    assert np.allclose(z, cache["z"], rtol=1e-13, atol=1e-13 * np.abs(zt).max())
+    fh = conv.decode64(cache["z"], W, mu, sd)
+    assert np.allclose(fh, sd * cache["xh"] + mu, rtol=1e-12, atol=1e-12 * np.abs(fh).max())
+    # the decoder's z -> y part against torch directly
+    hd = torch.relu(t64(cache["z"]) @ Wt["dw"].T + Wt["db"]).reshape(5, 64, 10, 10)
+    h3 = torch.relu(Fn.conv_transpose2d(hd, Wt["t1w"], Wt["t1b"], stride=2, padding=1, output_padding=1))
+    y = Fn.conv_transpose2d(h3, Wt["t2w"], Wt["t2b"], stride=2, padding=1).reshape(5, -1).numpy()
+    assert np.allclose((fh - mu) / sd, y, rtol=1e-10, atol=1e-11 * np.abs(y).max())
+
+
+def test_bf16_training_form():
+    """The BF16 training form of the convolutional model: its forward pass against torch's
+    CPU FP64 layers fed torch's own bfloat16 conversion of both operands of every product
+    (biases unrounded); an identity rounding gives the FP64 model bit for bit; its gradients
+    are close to the FP64 gradients (bfloat16 operands: about 2^-9 relative per operand, and
+    ReLU masks that flip where a pre-activation's sign does) but not equal."""
+    rng = np.random.default_rng(55)
+    W = synth.conv_ae_weights(5)
+    for k in ("c1b", "c2b", "fb", "db", "t1b", "t2b"):
+        W[k] = rng.normal(0, 0.05, W[k].shape).astype(np.float32)
+    B = 4
+    X = rng.standard_normal((B, 1521))
+    c16 = conv.forward_train(X, W, rnd=oracle.ae.bf16)
+
+    def tb(a):
+        return torch.from_numpy(np.asarray(a, np.float64)).to(torch.bfloat16).to(torch.float64)
+
+    Wt = {k: t64(v) for k, v in W.items()}
+    h1 = torch.relu(Fn.conv2d(tb(X.reshape(B, 1, 39, 39)), tb(W["c1w"]), Wt["c1b"], stride=2, padding=1))
+    h2 = torch.relu(Fn.conv2d(tb(h1), tb(W["c2w"]), Wt["c2b"], stride=2, padding=1)).reshape(B, -1)
+    z = tb(h2) @ tb(W["fw"]).T + Wt["fb"]
+    h4 = torch.relu(tb(z) @ tb(W["dw"]).T + Wt["db"]).reshape(B, 64, 10, 10)
+    h5 = torch.relu(Fn.conv_transpose2d(tb(h4), tb(W["t1w"]), Wt["t1b"], stride=2, padding=1, output_padding=1))
+    xh = Fn.conv_transpose2d(tb(h5), tb(W["t2w"]), Wt["t2b"], stride=2, padding=1).reshape(B, -1).numpy()
+    assert np.allclose(c16["z"], z.numpy(), rtol=1e-12, atol=1e-12 * np.abs(z.numpy()).max())
+    assert np.allclose(c16["xh"], xh, rtol=1e-10, atol=1e-10 * np.abs(xh).max())
+    c64 = conv.forward_train(X, W)
+    same = conv.forward_train(X, W, rnd=lambda a: np.asarray(a, np.float64))
+    assert np.array_equal(same["xh"], c64["xh"])
+    dxh = 2 * (c64["xh"] - X) / X.size
+    g64 = conv.backward(c64, W, dxh)
+    g16 = conv.backward(c16, W, 2 * (c16["xh"] - X) / X.size, rnd=oracle.ae.bf16)
+    for k in g64:
+        rel = np.linalg.norm(g16[k] - g64[k]) / np.linalg.norm(g64[k])
+        assert 1e-6 < rel < 1e-1, (k, rel)

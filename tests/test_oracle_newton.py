@@ -136,6 +136,49 @@ def test_warm_start_rules():
     assert nan["warm_rejected"] and nan["iters"] == cold["iters"]
 
 
+def test_analytic_start():
+    """The analytic-linear start (A A^T)^-1 (A ft - b): with no active positivity constraint
+    it is the solution itself (0 updates, the least-norm closed form solved independently
+    by least squares on the constraint system); it scales with (f, ft); on histograms whose
+    tails clip it reaches the same unique projection as the cold start; and the pipeline
+    applies it per histogram."""
+    g, f, ft = positive_case(seed=9)
+    A = g.A()
+    b = moments.moments(f, g)
+    lam0 = newton.analytic_start(ft, b, g)
+    # least-norm correction: the minimum-norm solution of A^T lam ~ (ft - x) with A x = b is
+    # the lstsq solution of A^T lam = ft - x*, x* = ft - A^T lam; check it via the normal
+    # equations' alternative route, an SVD of A
+    U, S, Vt = np.linalg.svd(A, full_matrices=False)
+    lam_svd = U @ ((U.T @ (A @ ft.ravel() - b)) / S ** 2)
+    assert np.allclose(lam0, lam_svd, rtol=1e-10, atol=1e-13 * np.abs(lam_svd).max())
+    res = newton.project(ft, b, g, lam0=lam0)
+    assert res["iters"] == 0 and not res["warm_rejected"]
+    assert np.allclose(moments.moments(res["x"], g), b, rtol=1e-13)
+    assert np.allclose(newton.analytic_start(3.0 * ft, 3.0 * b, g), 3.0 * lam0, rtol=1e-12)
+    G = grid.make_grid()
+    F = synth.histograms(6, seed=12, dtype=np.float64)
+    rng = np.random.default_rng(12)
+    clipped = 0
+    for fh in F:
+        fth = fh + 0.01 * fh.max() * rng.normal(size=fh.shape)
+        bh = moments.moments(fh, G)
+        cold = newton.project(fth, bh, G)
+        warm = newton.project(fth, bh, G, lam0=newton.analytic_start(fth, bh, G))
+        assert cold["status"] == 0 and warm["status"] == 0
+        assert np.allclose(warm["x"], cold["x"], rtol=0, atol=1e-12 * fh.max())
+        clipped += int((cold["x"] == 0).sum())
+    assert clipped > 0
+    from oracle import pipeline
+    Fs = synth.histograms(4, seed=13, dtype=np.float64)
+    pc = pipeline.compress(Fs, G, None, None, pipeline.Params(tau=1e-2))
+    pa = pipeline.compress(Fs, G, None, None, pipeline.Params(tau=1e-2, analytic_start=True))
+    assert pc["stream"] == pa["stream"] and np.array_equal(pc["kstar"], pa["kstar"])
+    assert np.allclose(pa["fc"], pc["fc"], rtol=0, atol=1e-12 * Fs.max())
+    with pytest.raises(ValueError):
+        pipeline.compress(Fs, G, None, None, pipeline.Params(tau=1e-2, analytic_start=True, positivity=False))
+
+
 def test_mlp_backward_matches_autograd():
     import torch
     from oracle import mlp
