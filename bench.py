@@ -149,14 +149,17 @@ def _oracle_worker(a):
     return _oracle_compress_timed(*a)
 
 
-def cpu_baseline(F: np.ndarray, W: dict, mu, sd, tau: float, n: int, gpu_check=None) -> dict:
+def cpu_baseline(F: np.ndarray, W: dict, mu, sd, tau: float, n: int, gpu_check=None, precision=None) -> dict:
     """The FP64 oracle timed on this host's cores on samples of the same workload: every
     sample runs the whole compress.  Headline: all cores, one worker process per core (at
-    most 16), each on its own n/4 histograms with one BLAS thread.  Beside it: one thread on
-    n histograms at tau and on n/4 at 1e-2 and 1e-4, the same with every BLAS thread (the
-    oracle's products are the only multithreaded part), and the 256-histogram FP64 case.
-    gpu_check: (b, q_in, q_out) of the GPU on the first histograms of the batch (moments
-    of f, QoIs of f and of the decompressed f_c), compared here with the oracle's moments."""
+    most 16), each on its own n histograms with one BLAS thread (16 n histograms, 65,536 at
+    the default n), at tau; the same at 1e-2 and 1e-4.  Beside it: one thread on n
+    histograms, every BLAS thread on n/2 (the oracle's products are the only multithreaded
+    part), and the 256-histogram FP64 case.
+    gpu_check: (b, q_in, q_out, f_c) of the GPU on the first histograms of the batch
+    (moments of f, QoIs of f and of the decompressed f_c), compared here with the oracle's.
+    precision: the GPU's per-stage outputs of the precision forms on a sample
+    (precision_sample), compared here with the plain FP64 model."""
     import multiprocessing as mp
 
     from oracle import grid, moments
@@ -166,10 +169,6 @@ def cpu_baseline(F: np.ndarray, W: dict, mu, sd, tau: float, n: int, gpu_check=N
     res = {"cpu_model": _cpu_model(), "host_cores": cores, "kind": "oracle", "unit": "histograms/s"}
     dt = _oracle_compress_timed(F[:n], W, mu, sd, tau, 1)
     res["one_thread"] = {"value": n / dt, "histograms": n, "tau": tau, "seconds": dt}
-    for t in (1e-2, 1e-4):
-        m = max(256, n // 4)
-        d = _oracle_compress_timed(F[:m], W, mu, sd, t, 1)
-        res[f"one_thread_tau_{t:g}"] = {"value": m / d, "histograms": m, "seconds": d}
     m = max(256, n // 2)
     d = _oracle_compress_timed(F[:m], W, mu, sd, tau, cores)
     res["blas_all_threads"] = {"value": m / d, "histograms": m, "threads": cores, "seconds": d}
@@ -178,21 +177,27 @@ def cpu_baseline(F: np.ndarray, W: dict, mu, sd, tau: float, n: int, gpu_check=N
     m1, s1 = ae.norm_stats(F1)                  # the 256-histogram case's own z-score statistics
     d = _oracle_compress_timed(F1, W, m1, s1, tau, 1)
     res["c1_256_fp64_one_thread"] = {"value": 256 / d, "seconds": d}
-    per = max(64, n // 4)
-    per = min(per, len(F) // workers)
-    chunks = [(np.ascontiguousarray(F[k * per:(k + 1) * per]), W, mu, sd, tau, 1) for k in range(workers)]
+    per = min(n, len(F) // workers)
+    chunks = [np.ascontiguousarray(F[k * per:(k + 1) * per]) for k in range(workers)]
     with mp.get_context("spawn").Pool(workers) as pool:
-        pool.map(_oracle_worker, [(c[0][:64], W, mu, sd, tau, 1) for c in chunks])      # import and warm up
-        t0 = time.perf_counter()
-        secs = pool.map(_oracle_worker, chunks)
-        wall = time.perf_counter() - t0
-    res["value"] = workers * per / wall
-    res["cores"] = workers
-    res["all_cores"] = {"value": workers * per / wall, "workers": workers, "histograms": workers * per,
-                        "wall_seconds": wall, "max_worker_seconds": max(secs)}
+        pool.map(_oracle_worker, [(c[:64], W, mu, sd, tau, 1) for c in chunks])      # import and warm up
+        for t in dict.fromkeys((tau, 1e-2, 1e-4)):
+            t0 = time.perf_counter()
+            secs = pool.map(_oracle_worker, [(c, W, mu, sd, t, 1) for c in chunks])
+            wall = time.perf_counter() - t0
+            r = {"value": workers * per / wall, "workers": workers, "histograms": workers * per, "tau": t,
+                 "wall_seconds": wall, "max_worker_seconds": max(secs)}
+            if t == tau:
+                res["value"] = r["value"]
+                res["cores"] = workers
+                res["all_cores"] = r
+            else:
+                res[f"all_cores_tau_{t:g}"] = r
+            log(f"cpu baseline: all cores at tau {t:g}: {r['value']:.0f} histograms/s")
     res["sample"] = (f"histograms of the same 2^20 batch, full compress (encode, codebook fit on every 16th, "
                      f"quantize, decode, coder, Newton), NumPy FP64: headline {workers} worker processes x {per} "
-                     f"histograms, one BLAS thread each; see one_thread, blas_all_threads, c1_256_fp64_one_thread")
+                     f"histograms at tau {tau:g}, one BLAS thread each; all_cores_tau_* the same at the other "
+                     f"bounds; see one_thread, blas_all_threads, c1_256_fp64_one_thread")
     if gpu_check is not None:
         b_gpu, q_in, q_out, fc = gpu_check
         k = len(b_gpu)
@@ -205,6 +210,84 @@ def cpu_baseline(F: np.ndarray, W: dict, mu, sd, tau: float, n: int, gpu_check=N
             "moments_max_rel_diff": float((np.abs(b_gpu - bo) / np.abs(bo).max(axis=0)).max()),
             "qoi_in_max_rel_err": float(moments.qoi_rel_error(qo_in, q_in, g).max()),
             "qoi_out_vs_oracle_input_max_rel_err": float(moments.qoi_rel_error(qo_in, qo_out, g).max()),
+        }
+    if precision is not None:
+        log("cpu baseline: per-stage error of the precision forms against the FP64 model")
+        res["precision_vs_fp64"] = precision_errors(F, precision, tau)
+    return res
+
+
+def precision_sample(hcz, plan, x, forms, tau: float, K: int) -> dict:
+    """GPU outputs of each precision form on the first K histograms of the batch, for the
+    per-stage comparison with the plain FP64 model (codebook fitted on all K latents, the
+    sample's own z-score statistics): z, codebook, codes, fhat, flags, multipliers, record
+    sizes and the decompressed FP64 histograms.  forms: name -> (weights, arch, compute)."""
+    import torch
+    xs = x[:K].contiguous()
+    mu, sd = hcz.norm_stats(plan, xs)
+    mu, sd = mu.cpu().numpy(), sd.cpu().numpy()
+    out = {}
+    for name, (W, arch, compute) in forms.items():
+        model = hcz.Model(plan, W, mu, sd, compute=compute, arch=arch)
+        cz = hcz.Compressor(plan, model, K, hcz.params(tau=tau, fit_codebook=True, sample_every=1))
+        comp = cz.compress(xs)
+        z = hcz.encode(model, xs)
+        fh = hcz.decode(model, comp.codes, cz.centroids)
+        fc = cz.decompress(comp, K)
+        torch.cuda.synchronize()
+        off = comp.offsets.cpu().numpy().astype(np.int64)
+        out[name] = {"arch": arch, "compute": compute, "W": W, "z": z.cpu().numpy().astype(np.float64),
+                     "centroids": cz.centroids.cpu().numpy().astype(np.float64),
+                     "codes": comp.codes.cpu().numpy(), "fhat": fh.cpu().numpy().astype(np.float64).reshape(K, -1),
+                     "flags": comp.flags.cpu().numpy(), "lam": comp.lam.cpu().numpy().astype(np.float64),
+                     "stream_bytes": int(off[-1]), "fc": fc.cpu().numpy().reshape(K, -1)}
+        del model, cz, comp, fc
+    return out
+
+
+def precision_errors(F: np.ndarray, gpu: dict, tau: float) -> dict:
+    """Per-stage error of each precision form's GPU outputs against the plain FP64 model run
+    by the oracle on the same K histograms (its own z-score statistics and codebook fit):
+    latent, codebook, code flip rate, fhat, coded fraction p, stream bytes, multipliers,
+    QoI error of each side's output and the final histograms."""
+    from oracle import ae, grid, moments, pipeline
+    K = next(iter(gpu.values()))["z"].shape[0]
+    F64 = np.asarray(F[:K], np.float64)
+    g = grid.make_grid()
+    mu, sd = ae.norm_stats(F64)
+    q_in = moments.qoi(F64, g)
+    th = pipeline.tau_h(F64, pipeline.Params(tau=tau))
+    res = {"histograms": K, "tau": tau}
+    for name, d in gpu.items():
+        model = dict(arch=d["arch"], W=d["W"], mu=mu, sd=sd, compute="fp64")
+        t0 = time.perf_counter()
+        o = pipeline.compress(F64, g, model, None, pipeline.Params(tau=tau), fit_codebook=True, bits=8, sample_every=1)
+        t_or = time.perf_counter() - t0
+        zo, fo = o["z"], o["fhat"].reshape(K, -1)
+        ok = ((d["flags"] & 4) == 0) & ((o["flags"] & 4) == 0)
+        lam_o = np.asarray(o["lam"], np.float64)
+        lam_rel = np.linalg.norm(d["lam"] - lam_o, axis=1) / np.maximum(np.linalg.norm(lam_o, axis=1), 1e-300)
+        fc_o = o["fc"].reshape(K, -1)
+        qg = moments.qoi(d["fc"].reshape(F64.shape), g)
+        qo = moments.qoi(fc_o.reshape(F64.shape), g)
+        span = d["centroids"].max() - d["centroids"].min()
+        res[name] = {
+            "oracle_seconds": t_or,
+            "z_rel_l2": float(np.linalg.norm(d["z"] - zo) / np.linalg.norm(zo)),
+            "z_max_abs_over_range": float(np.abs(d["z"] - zo).max() / (zo.max() - zo.min())),
+            "codebook_max_abs_over_range": float(np.abs(d["centroids"] - o["codebook"]).max() / span),
+            "code_flip_rate": float((d["codes"] != o["codes"]).mean()),
+            "fhat_rel_l2": float(np.linalg.norm(d["fhat"] - fo) / np.linalg.norm(fo)),
+            "fhat_diff_over_tau_h_median": float(np.median(np.linalg.norm(d["fhat"] - fo, axis=1) / th)),
+            "coded_frac": {"gpu": float((d["flags"] & 1).mean()), "oracle": float((o["flags"] & 1).mean())},
+            "stream_bytes": {"gpu": d["stream_bytes"], "oracle": len(o["stream"])},
+            "lambda_rel_diff_median": float(np.median(lam_rel[ok])), "lambda_rel_diff_max": float(lam_rel[ok].max()),
+            "qoi_rel_err_max": {"gpu": float(moments.qoi_rel_error(q_in[ok], qg[ok], g).max()),
+                                "oracle": float(moments.qoi_rel_error(q_in[ok], qo[ok], g).max())},
+            "final_diff_over_tau_h_max": float((np.linalg.norm(d["fc"] - fc_o, axis=1)[ok] / th[ok]).max()),
+            "err_over_tau_h_max": {"gpu": float((np.linalg.norm(d["fc"] - F64.reshape(K, -1), axis=1)[ok] / th[ok]).max()),
+                                   "oracle": float((np.linalg.norm(fc_o - F64.reshape(K, -1), axis=1)[ok]
+                                                    / th[ok]).max())},
         }
     return res
 
@@ -228,9 +311,28 @@ def _qoi_refs(hcz, plan, x):
     return q0, n0, den
 
 
-def _plain_run(hcz, plan, model, x, hp, tau, refs, steps=3) -> dict:
+def newton_stats(s: dict, H: int) -> dict:
+    """Newton updates per histogram from the device histogram of update counts (its last
+    bin holds 63 or more): mean over the non-verbatim histograms, median, 99th percentile
+    and maximum."""
+    hist = np.asarray(s["newton_iter_hist"], np.int64)
+    cum = np.cumsum(hist)
+    n = int(cum[-1])
+
+    def pct(q):
+        return int(np.searchsorted(cum, q * n)) if n else 0
+    return {"mean": s["newton_iters_total"] / max(1, H - s["n_raw"]), "p50": pct(0.5), "p99": pct(0.99),
+            "max": int(s["newton_max_iters"])}
+
+
+DENSE_PARAMS, CONV_PARAMS = 395265, 248785
+
+
+def _plain_run(hcz, plan, model, x, hp, tau, refs, steps=3, model_floats=DENSE_PARAMS) -> dict:
     """Time one configuration of the full pipeline and report throughput, coded fraction p,
-    stream size, compression ratio, QoI error and the bound on the batch."""
+    stream size, compression ratio (codes, FP64 multipliers, flags, residual stream, model,
+    codebook and header against the FP32 input), Newton updates, QoI error and the bound on
+    the batch."""
     H = x.shape[0]
     q0, n0, den = refs
     cz = hcz.Compressor(plan, model, H, hp)
@@ -239,11 +341,13 @@ def _plain_run(hcz, plan, model, x, hp, tau, refs, steps=3) -> dict:
     o = cz.decompress(comp, H)
     _, q1, _ = hcz.qoi(plan, o)
     ok = (comp.flags & 4) == 0
-    stored = H * 16 + H * 32 + H + s["stream_bytes"] + 395265 * 4 + 16 * 256 * 4 + 44
+    stored = H * 16 + H * 32 + H + s["stream_bytes"] + model_floats * 4 + 16 * 256 * 4 + 44
     over = (o - x.double()).reshape(H, -1).norm(dim=1)[ok] / (tau * n0[ok])
     r = {"value": H / dt, "ms_per_step": dt * 1e3, "coded_frac": s["n_coded"] / H, "raw": s["n_raw"],
          "stream_bytes": s["stream_bytes"], "compression_ratio": H * plan.N * 4 / stored,
          "newton_mean_updates": s["newton_iters_total"] / max(1, H - s["n_raw"]),
+         "newton": newton_stats(s, H), "round2": s["n_round2"],
+         "warm_rejected": int(((comp.flags & 8) != 0).sum().item()),
          "max_qoi_rel_err": ((q1 - q0).abs() / den)[ok].max().item(),
          "max_err_over_tau_h": over.max().item(), "over_bound": int((over > 1).sum().item())}
     alg = H * (4 * plan.N + 16 + 32 + 1 + 8) + s["stream_bytes"]
@@ -310,31 +414,6 @@ def container_form(hcz, plan, x, W, args, n=131072) -> dict:
                                            "unpack_MBps": len(buf) / (t2 - t1) / 1e6}
     del cz, comp, model
     return res
-
-
-def conv_train_form(hcz, plan, ctx, x, args, rows=32768, epochs=5) -> dict:
-    """The convolutional model trained by the library's FP32 kernels (Adam, lr 1e-3, batch
-    1024) on `rows` held-apart histograms, then used in its BF16 form on the benchmark
-    batch: training time and loss, and the step with the trained model."""
-    import torch
-
-    from paper_2212_10733_amd import synth, train
-    Ftr = torch.from_numpy(synth.histograms(rows, seed=synth.SEED_TRAIN, dtype=np.float32)).cuda()
-    mu, sd = hcz.norm_stats(plan, Ftr)
-    X = hcz.column_normalize(Ftr, mu, sd)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    tr = train.Trainer(train.pack_conv(synth.conv_ae_weights()), lr=1e-3, arch="conv")
-    losses = tr.fit(X, epochs=epochs, batch=1024)
-    torch.cuda.synchronize()
-    dt_train = time.perf_counter() - t0
-    del X, Ftr
-    res = bf16_form(hcz, plan, ctx, x, train.unpack_conv(tr.p), args, arch="conv",
-                    stats=(mu.cpu().numpy(), sd.cpu().numpy()))
-    return {"train_rows": rows, "epochs": epochs, "train_seconds": dt_train,
-            "train_samples_per_s": rows * epochs / dt_train, "loss_first_last": [losses[0], losses[-1]],
-            "value": res["value"], "ms_per_step": res["ms_per_step"], "stream_bytes": res["stream_bytes"],
-            "max_qoi_rel_err": res["max_qoi_rel_err"], "max_err_over_tau_h": res["max_err_over_tau_h"]}
 
 
 def stage5_form(hcz, plan, x, args) -> dict:
@@ -587,84 +666,98 @@ def other_forms(hcz, plan, ctx, x, F, W, args, plain_value, plain_stats) -> dict
     if "conv" in args.forms:
         log("form: convolutional autoencoder (BF16)")
         out["conv_ae"] = bf16_form(hcz, plan, ctx, x, synth.conv_ae_weights(), args, arch="conv")
-        log("form: convolutional autoencoder trained")
-        out["conv_ae_trained"] = conv_train_form(hcz, plan, ctx, x, args)
     if "batched" in args.forms:
         log("form: batched uneven subdomains")
         out["batched"] = batched_form(hcz, ctx, args)
     if "incremental" in args.forms:
         log("form: incremental training series")
         out["incremental"] = incremental_form(hcz, plan, x.shape[0], W, args)
-    if "learned" not in args.forms:
-        return out
-    log(f"form: learned (train {args.epochs} epochs on {args.train_hist})")
+    if "learned" in args.forms:
+        log(f"form: learned, dense (train {args.epochs} epochs on {args.train_hist})")
+        out["learned"] = learned_form(hcz, plan, ctx, W, args, "dense", plain_value, plain_stats, H)
+    if "c4" in args.forms:
+        log(f"form: learned, convolutional BF16 (train {args.epochs} epochs on {args.train_hist})")
+        out["learned_conv"] = learned_form(hcz, plan, ctx, synth.conv_ae_weights(), args, "conv", plain_value,
+                                           plain_stats, H)
+    return out
+
+
+def learned_form(hcz, plan, ctx, W0, args, arch, plain_value, plain_stats, H) -> dict:
+    """The learned form: the autoencoder trained by the library's kernels (Adam, lr 1e-3,
+    batch 1024, `args.epochs` epochs on `args.train_hist` histograms of the training seed,
+    z-scored with their own statistics), a warm-start network per bound trained on the
+    training batch's cold multipliers, then evaluated on a held-out batch of H histograms
+    (held-out seed) at tau = 1e-3 and 1e-2: the untrained model (its z-score statistics from
+    the held-out batch), the trained model with cold, analytic-linear and network starts
+    (Newton updates mean / p50 / p99 / max, QoI error, bound, p, ratio).  Dense: trained in
+    FP32 and, separately, in BF16 (evaluated in the BF16 form, the benchmark spec's HBM-target
+    form).  Convolutional: trained in BF16, evaluated in its BF16 form."""
+    import torch
+
+    from paper_2212_10733_amd import synth, train
+    conv = arch == "conv"
+    mf = CONV_PARAMS if conv else DENSE_PARAMS
     Ftr = torch.from_numpy(synth.histograms(args.train_hist, seed=synth.SEED_TRAIN, dtype=np.float32)).cuda()
     mu, sd = hcz.norm_stats(plan, Ftr)
+    mu_np, sd_np = mu.cpu().numpy(), sd.cpu().numpy()
     X = hcz.column_normalize(Ftr, mu, sd)
-    t0 = time.perf_counter()
-    tr = train.Trainer(train.pack(W), lr=1e-3)
-    losses = tr.fit(X, epochs=args.epochs, batch=1024)
-    torch.cuda.synchronize()
-    t_train = time.perf_counter() - t0
-    log("form: learned, bf16 training")
-    t0 = time.perf_counter()
-    tr16 = train.Trainer(train.pack(W), lr=1e-3, compute="bf16")
-    losses16 = tr16.fit(X, epochs=args.epochs, batch=1024)
-    torch.cuda.synchronize()
-    t_train16 = time.perf_counter() - t0
+    res = {"train_histograms": args.train_hist, "epochs": args.epochs, "batch": 1024}
+    pack = train.pack_conv if conv else train.pack
+    unpack = train.unpack_conv if conv else (lambda p: train.unpack(p, plan.N))
+    runs = [("bf16", "bf16")] if conv else [("fp32", "fp32"), ("bf16", "bf16")]
+    trained = {}
+    for name, compute in runs:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        tr = train.Trainer(pack(W0), lr=1e-3, arch=arch, compute=compute)
+        losses = tr.fit(X, epochs=args.epochs, batch=1024, log=log if conv else None)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        res[f"train_{name}"] = {"seconds": dt, "samples_per_s": args.train_hist * args.epochs / dt,
+                                "loss_first_last": [losses[0], losses[-1]]}
+        log(f"  trained {arch} in {name}: {dt:.1f} s, loss {losses[0]:.4f} -> {losses[-1]:.4f}")
+        trained[name] = unpack(tr.p)
+        del tr
     del X
-    Wt = train.unpack(tr.p, plan.N)
-    model = hcz.Model(plan, Wt, mu.cpu().numpy(), sd.cpu().numpy())
-    # warm-start network: targets are the training batch's cold multipliers
-    czt = hcz.Compressor(plan, model, args.train_hist, hcz.params(tau=args.tau, fit_codebook=True, sample_every=16))
-    ct = czt.compress(Ftr)
-    ok = (ct.flags & 4) == 0
-    lam_ok = ct.lam[ok]
-    _, scale = hcz.column_stats(lam_ok)
-    Z = hcz.dequantize(ct.codes, czt.centroids)[ok]
-    T = hcz.column_normalize(lam_ok, None, scale)
-    scale = scale.double()
-    t0 = time.perf_counter()
-    pm, mlosses = train.fit_mlp(Z, T, synth.mlp_weights(), epochs=10, batch=512, lr=3e-3)
-    torch.cuda.synchronize()
-    t_mlp = time.perf_counter() - t0
-    net = hcz.Mlp(ctx, pm.cpu().numpy(), scale.cpu().numpy())
-    del czt, ct, Ftr, Z, T
-    res = {}
-    for name, p in (("cold", hcz.params(tau=args.tau, fit_codebook=True, sample_every=16)),
-                    ("warm", hcz.params(tau=args.tau, fit_codebook=True, sample_every=16, mlp=net))):
-        cz = hcz.Compressor(plan, model, H, p)
-        dt, comp = time_compress(cz, x, 3)
-        s = comp.stats()
-        res[name] = {"value": H / dt, "ms_per_step": dt * 1e3, "coded_frac": s["n_coded"] / H,
-                     "stream_bytes": s["stream_bytes"], "newton_mean_updates": s["newton_iters_total"] / H,
-                     "newton_max_updates": s["newton_max_iters"], "raw": s["n_raw"],
-                     "warm_rejected": int(((comp.flags & 8) != 0).sum().item())}
-        if name == "warm":
-            o = cz.decompress(comp, H)
-            _, q0, n0 = hcz.qoi(plan, x)
-            _, q1, _ = hcz.qoi(plan, o)
-            okk = (comp.flags & 4) == 0
-            den = torch.stack([q0[:, 0].abs(), torch.maximum(q0[:, 1].abs(), q0[:, 3].abs().sqrt()),
-                               q0[:, 2].abs(), q0[:, 3].abs()], 1)
-            res[name]["max_qoi_rel_err"] = ((q1 - q0).abs() / den)[okk].max().item()
-            res[name]["max_err_over_tau_h"] = ((o - x.double()).reshape(H, -1).norm(dim=1)[okk]
-                                               / (args.tau * n0[okk])).max().item()
-            del o
-        del cz, comp
-    # the BF16-trained model compressing in the BF16 dense form
-    model16 = hcz.Model(plan, train.unpack(tr16.p, plan.N), mu.cpu().numpy(), sd.cpu().numpy(), compute="bf16")
-    bf16_run = _plain_run(hcz, plan, model16, x, hcz.params(tau=args.tau, fit_codebook=True, sample_every=16),
-                          args.tau, _qoi_refs(hcz, plan, x))
-    del model16
-    out["learned"] = {"train_seconds": t_train, "train_loss_first_last": [losses[0], losses[-1]],
-                      "bf16_train_seconds": t_train16, "bf16_train_loss_first_last": [losses16[0], losses16[-1]],
-                      "bf16_trained_bf16_form": bf16_run,
-                      "mlp_train_seconds": t_mlp, "mlp_loss_first_last": [mlosses[0], mlosses[-1]],
-                      "cold_start": res["cold"], "warm_start": res["warm"],
-                      "untrained_plain": {"value": plain_value, "coded_frac": plain_stats["n_coded"] / H,
-                                          "stream_bytes": plain_stats["stream_bytes"]}}
-    return out
+    # the evaluation model: conv and the BF16-trained dense model in their BF16 forms
+    main = "bf16" if conv else "fp32"
+    model = hcz.Model(plan, trained[main], mu_np, sd_np, compute="bf16" if conv else "fp32", arch=arch)
+    model16 = None if conv else hcz.Model(plan, trained["bf16"], mu_np, sd_np, compute="bf16")
+    xe = torch.from_numpy(synth.histograms(H, seed=synth.SEED_HELDOUT, dtype=np.float32)).cuda()
+    refs = _qoi_refs(hcz, plan, xe)
+    mue, sde = hcz.norm_stats(plan, xe)
+    untrained = hcz.Model(plan, W0, mue.cpu().numpy(), sde.cpu().numpy(), compute="bf16" if conv else "fp32",
+                          arch=arch)
+    for tau in (1e-3, 1e-2):
+        log(f"  held-out evaluation at tau {tau:g}")
+        # warm-start network: targets are the training batch's cold multipliers at this tau
+        czt = hcz.Compressor(plan, model, args.train_hist, hcz.params(tau=tau, fit_codebook=True, sample_every=16))
+        ct = czt.compress(Ftr)
+        ok = (ct.flags & 4) == 0
+        lam_ok = ct.lam[ok]
+        _, scale = hcz.column_stats(lam_ok)
+        Z = hcz.dequantize(ct.codes, czt.centroids)[ok]
+        T = hcz.column_normalize(lam_ok, None, scale)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pm, mlosses = train.fit_mlp(Z, T, synth.mlp_weights(), epochs=10, batch=512, lr=3e-3)
+        torch.cuda.synchronize()
+        t_mlp = time.perf_counter() - t0
+        net = hcz.Mlp(ctx, pm.cpu().numpy(), scale.double().cpu().numpy())
+        del czt, ct, Z, T
+        r = {"mlp_train_seconds": t_mlp, "mlp_loss_first_last": [mlosses[0], mlosses[-1]]}
+        base = dict(tau=tau, fit_codebook=True, sample_every=16)
+        r["untrained"] = _plain_run(hcz, plan, untrained, xe, hcz.params(**base), tau, refs, 2, mf)
+        for start, kw in (("cold", {}), ("analytic", {"analytic_start": True}), ("mlp", {"mlp": net})):
+            r[f"trained_{start}"] = _plain_run(hcz, plan, model, xe, hcz.params(**base, **kw), tau, refs, 2, mf)
+        if model16 is not None:
+            r["bf16_trained_bf16_form"] = _plain_run(hcz, plan, model16, xe, hcz.params(**base), tau, refs, 3, mf)
+        res[f"tau_{tau:g}"] = r
+        del net
+    res["benchmark_batch_untrained_plain"] = {"value": plain_value, "coded_frac": plain_stats["n_coded"] / H,
+                                              "stream_bytes": plain_stats["stream_bytes"]}
+    del xe, Ftr, model, model16, untrained
+    return res
 
 
 def main() -> int:
@@ -674,16 +767,21 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--H", type=int, default=1 << 20)
     ap.add_argument("--tau", type=float, default=1e-3)
-    ap.add_argument("--cpu-sample", type=int, default=4096)
+    ap.add_argument("--cpu-sample", type=int, default=4096,
+                    help="histograms per oracle worker (16 workers at most) and of the one-thread run")
+    ap.add_argument("--precision-sample", type=int, default=2048,
+                    help="histograms of the per-stage comparison of the precision forms with the FP64 model")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the coder-only and learned forms")
-    ap.add_argument("--forms", default="tau,ub,coder,stage5,container,bf16,conv,batched,incremental,learned",
+    ap.add_argument("--forms", default="tau,ub,coder,stage5,container,bf16,conv,batched,incremental,learned,c4",
                     help="comma list of the other forms to run: tau (sweep), coder (coder-only), "
                          "stage5 (FP32 multipliers, no positivity, KL correction), container (packed "
                          "output with and without rANS), ub (the coder step given, not searched), "
                          "bf16 (BF16 autoencoder), conv (convolutional BF16 autoencoder), "
                          "batched (uneven subdomains on four grids), "
-                         "incremental (training series), learned")
+                         "incremental (training series), learned (dense model trained in FP32 and "
+                         "BF16, held-out evaluation with cold / analytic / network starts), c4 (the "
+                         "convolutional model trained in BF16, the same evaluation)")
     ap.add_argument("--train-hist", type=int, default=262144)
     ap.add_argument("--epochs", type=int, default=20)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -844,9 +942,19 @@ def main() -> int:
 
     cpu = None
     if not args.no_cpu:
-        log(f"cpu baseline on {args.cpu_sample} histograms")
-        cpu = cpu_baseline(F, W, mu, sd, args.tau, args.cpu_sample, gpu_check)
+        log(f"precision forms on {args.precision_sample} histograms")
+        prec = precision_sample(hcz, plan, x, {"fp32_dense": (W, "dense", "fp32"), "bf16_dense": (W, "dense", "bf16"),
+                                               "bf16_conv": (synth.conv_ae_weights(), "conv", "bf16")},
+                                args.tau, args.precision_sample)
+        log(f"cpu baseline on {args.cpu_sample} histograms per worker")
+        cpu = cpu_baseline(F, W, mu, sd, args.tau, args.cpu_sample, gpu_check, prec)
 
+    lf = forms.get("learned", {}).get(f"tau_{args.tau:g}", {}).get("bf16_trained_bf16_form")
+    if lf:
+        # the benchmark spec's HBM-target form: the BF16-trained dense model in its BF16 form,
+        # on the held-out batch, algorithmic bytes (f read once, outputs, stream) per step
+        extra["hbm_frac_bf16_dense_trained"] = {"value": lf["value"], "hbm_frac": lf["hbm_frac"],
+                                                "GB/s": lf["hbm_frac"] * PEAK_HBM_GBS}
     line = {
         "metric": "histograms/s (compress+QoI-correct)", "value": value, "unit": "histograms/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
