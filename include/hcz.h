@@ -258,26 +258,32 @@ hcz_status hcz_plan_create(hcz_ctx* ctx, const hcz_grid* grid, hcz_plan** out);
 void hcz_plan_destroy(hcz_plan* plan);
 
 /* Which per-histogram kernels serve `plan`'s grid (host only, no GPU work):
-   HCZ_PATH_BLOCK one workgroup per histogram (grids too large for one wave),
+   HCZ_PATH_BLOCK one workgroup per histogram (the generic kernel; the KL reading),
    HCZ_PATH_WAVE one wave per histogram with the slot structure read at run time,
    HCZ_PATH_WAVE_FIXED one wave per histogram with a slot structure compiled in
-   (the 39 x 39 grid with uniform cell volumes).  Records and flags are identical on every
+   (the 39 x 39 grid with uniform cell volumes),
+   HCZ_PATH_TEAM2 / HCZ_PATH_TEAM4 a team of two / four waves per histogram (grids too
+   large for one wave whose nodes fit the team's slots, e.g. 49 x 49 / 65 x 65).  Records and flags are identical on every
    path; multipliers agree to the Newton stopping rule.
    Errors: HCZ_EINVAL for a NULL argument. */
-enum { HCZ_PATH_BLOCK = 0, HCZ_PATH_WAVE = 1, HCZ_PATH_WAVE_FIXED = 2 };
+enum { HCZ_PATH_BLOCK = 0, HCZ_PATH_WAVE = 1, HCZ_PATH_WAVE_FIXED = 2, HCZ_PATH_TEAM2 = 3, HCZ_PATH_TEAM4 = 4 };
 hcz_status hcz_plan_path(const hcz_plan* plan, int32_t* path);
 
 /* Launch variants of the residual stage (hcz_compress, hcz_residual) for tuning: the
  * kernel family and its shape, i.e. waves per histogram and nodes per thread.
- *   HCZ_VARIANT_AUTO          the default choice of hcz_plan_path (and 256 x 6, 512 x 5 or
- *                             512 x 9 threads x nodes per thread on the workgroup kernel,
- *                             the smallest that holds the grid);
+ *   HCZ_VARIANT_AUTO          the default choice of hcz_plan_path (on the workgroup kernel
+ *                             256 x 6, 512 x 5 or 512 x 9 threads x nodes per thread, the
+ *                             smallest that holds the grid);
  *   HCZ_VARIANT_WAVE_FIXED    one wave per histogram, slot structure compiled in (the 39 x 39
  *                             grid with uniform cell volumes only);
  *   HCZ_VARIANT_WAVE          one wave per histogram, slot structure read at run time
  *                             (grids whose nodes fit 26 slots of 64);
  *   HCZ_VARIANT_BLOCK_256x6, _512x5, _512x9   the workgroup kernel with that many threads and
- *                             nodes per thread (N at most 1,536, 2,560, 4,608).
+ *                             nodes per thread (N at most 1,536, 2,560, 4,608);
+ *   HCZ_VARIANT_TEAM2, _TEAM4 a team of two or four waves per histogram with the wave
+ *                             kernels' slot layout widened to 128 or 256 lanes (grids whose
+ *                             nodes fit 22 slots of 128, resp. 20 slots of 256, e.g. 49 x 49
+ *                             and 65 x 65).
  * Every variant gives the same records, offsets and flags; the multipliers agree to the
  * Newton stopping rule (the kernel families sum in different orders, so their last bits
  * may differ).  The KL reading always runs on the workgroup kernel
@@ -287,7 +293,7 @@ hcz_status hcz_plan_path(const hcz_plan* plan, int32_t* path);
  * on other threads).  Errors: HCZ_EINVAL for a NULL argument, HCZ_EUNSUPPORTED for a
  * variant the grid does not allow. */
 enum { HCZ_VARIANT_AUTO = 0, HCZ_VARIANT_WAVE_FIXED = 1, HCZ_VARIANT_WAVE = 2, HCZ_VARIANT_BLOCK_256x6 = 3,
-       HCZ_VARIANT_BLOCK_512x5 = 4, HCZ_VARIANT_BLOCK_512x9 = 5 };
+       HCZ_VARIANT_BLOCK_512x5 = 4, HCZ_VARIANT_BLOCK_512x9 = 5, HCZ_VARIANT_TEAM2 = 6, HCZ_VARIANT_TEAM4 = 7 };
 hcz_status hcz_plan_variants(const hcz_plan* plan, int32_t* list, int32_t* n);
 hcz_status hcz_plan_set_variant(hcz_plan* plan, int32_t variant);
 

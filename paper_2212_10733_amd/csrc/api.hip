@@ -231,8 +231,10 @@ struct SlotTables {
 
 constexpr uint32_t kPadGroup = 15;
 
+// lanes: nodes per slot, 64 for one wave per histogram, 64 W for a team of W waves; a
+// layout needing more than max_slots slots is not built (nslots = 0).
 SlotTables make_slots(int np, int nq, int L, const std::vector<uint32_t>& node, const std::vector<int>& gstart,
-                      const DimTables& dp, const DimTables& dq) {
+                      const DimTables& dp, const DimTables& dq, int lanes = 64, int max_slots = kWaveSlots) {
   SlotTables T;
   const int nlev = L + 1;
   const uint32_t zero = (uint32_t)(np * nq) * 8u;
@@ -285,14 +287,14 @@ SlotTables make_slots(int np, int nq, int L, const std::vector<uint32_t>& node, 
     w[1] = c10 | c01 << 16;
     w[2] = c11 | wi << 16 | ti << 22 | (uint32_t)g << 28;
   };
-  // slot 0: the coarsest groups while they fit in 64 lanes
+  // slot 0: the coarsest groups while they fit in one slot
   int g = 0, cnt = 0;
-  while (g < nlev && cnt + (gstart[g + 1] - gstart[g]) <= 64) { cnt += gstart[g + 1] - gstart[g]; ++g; }
+  while (g < nlev && cnt + (gstart[g + 1] - gstart[g]) <= lanes) { cnt += gstart[g + 1] - gstart[g]; ++g; }
   if (g == 0) return T;                           // coarsest group alone exceeds a slot
   T.ncoarse = g;
-  std::vector<uint32_t> slot(64 * 3);
-  std::vector<uint16_t> spos(64);
-  for (int l = 0; l < 64; ++l) pad(&slot[3 * l]);
+  std::vector<uint32_t> slot((size_t)lanes * 3);
+  std::vector<uint16_t> spos(lanes);
+  for (int l = 0; l < lanes; ++l) pad(&slot[3 * l]);
   std::fill(spos.begin(), spos.end(), (uint16_t)0);
   for (int p = 0; p < cnt; ++p) {
     int gg = 0;
@@ -310,10 +312,10 @@ SlotTables make_slots(int np, int nq, int L, const std::vector<uint32_t>& node, 
     for (int p = gstart[g]; p < gstart[g + 1]; ++p) (kind(p, g) == 3 ? bil : lin).push_back(p);
     const size_t nlin = lin.size();
     lin.insert(lin.end(), bil.begin(), bil.end());
-    for (size_t k = 0; k < lin.size(); k += 64) {
-      const size_t kend = std::min(lin.size(), k + 64);
+    for (size_t k = 0; k < lin.size(); k += lanes) {
+      const size_t kend = std::min(lin.size(), k + lanes);
       const bool f4 = kend > nlin;                // the slot holds a bilinear node
-      for (int l = 0; l < 64; ++l) pad(&slot[3 * l]);
+      for (int l = 0; l < lanes; ++l) pad(&slot[3 * l]);
       std::fill(spos.begin(), spos.end(), (uint16_t)0);
       for (size_t q = k; q < kend; ++q) {
         entry(lin[q], g, f4, &slot[3 * (q - k)]);
@@ -326,7 +328,7 @@ SlotTables make_slots(int np, int nq, int L, const std::vector<uint32_t>& node, 
     }
   }
   T.nslots = (int)T.group.size();
-  if (T.nslots > kWaveSlots || T.wtab.size() > 64 || np * nq * 8 + 8 > 65535) {
+  if (T.nslots > max_slots || T.wtab.size() > 64 || np * nq * 8 + 8 > 65535) {
     T.nslots = 0;
     return T;
   }
@@ -334,8 +336,8 @@ SlotTables make_slots(int np, int nq, int L, const std::vector<uint32_t>& node, 
     // every node of the slot interpolates with weight(s) exactly 1/2 (padding lanes read
     // the zero cell, where any weight gives 0)
     bool half = true;
-    for (int l = 0; l < 64; ++l) {
-      const uint32_t* w = &T.meta[(size_t)(k * 64 + l) * 3];
+    for (int l = 0; l < lanes; ++l) {
+      const uint32_t* w = &T.meta[((size_t)k * lanes + l) * 3];
       if ((w[0] & 0xffffu) == zero || (w[2] >> 28) == 0) continue;
       half = half && T.wtab[(w[2] >> 16) & 63] == 0.5 && (!four[k] || T.wtab[(w[2] >> 22) & 63] == 0.5);
     }
@@ -352,17 +354,17 @@ SlotTables make_slots(int np, int nq, int L, const std::vector<uint32_t>& node, 
 // the zero cell) and in strictly coarser groups, weight indices inside wtab, packing
 // positions inside the node's group.
 bool slots_valid(const SlotTables& T, int np, int nq, int N, int nlev, const std::vector<uint32_t>& node,
-                 const std::vector<int>& gstart) {
+                 const std::vector<int>& gstart, int lanes = 64) {
   if (T.nslots == 0) return true;
-  if (T.meta.size() != (size_t)T.nslots * 192 || T.pos.size() != (size_t)T.nslots * 64) return false;
+  if (T.meta.size() != (size_t)T.nslots * lanes * 3 || T.pos.size() != (size_t)T.nslots * lanes) return false;
   const uint32_t zero = (uint32_t)N * 8u;
   std::vector<int> grp(N + 1, -1);
   for (int g = 0; g < nlev; ++g)
     for (int p = gstart[g]; p < gstart[g + 1]; ++p) grp[(node[p] >> 16) * np + (node[p] & 0xffff)] = g;
   std::vector<uint8_t> seen(N, 0);
   for (int s = 0; s < T.nslots; ++s)
-    for (int l = 0; l < 64; ++l) {
-      const uint32_t* w = &T.meta[(size_t)(s * 64 + l) * 3];
+    for (int l = 0; l < lanes; ++l) {
+      const uint32_t* w = &T.meta[((size_t)s * lanes + l) * 3];
       const uint32_t oe = w[0] & 0xffff, o[4] = {w[0] >> 16, w[1] & 0xffff, w[1] >> 16, w[2] & 0xffff};
       const uint32_t wi = (w[2] >> 16) & 63, ti = (w[2] >> 22) & 63, g = w[2] >> 28;
       for (uint32_t v : {oe, o[0], o[1], o[2], o[3]})
@@ -376,7 +378,7 @@ bool slots_valid(const SlotTables& T, int np, int nq, int N, int nlev, const std
       if (seen[e] || (int)g >= nlev || grp[e] != (int)g) return false;
       if (s == 0 ? (int)g >= T.ncoarse : (int)g != T.group[s]) return false;
       seen[e] = 1;
-      const int p = T.pos[(size_t)s * 64 + l];
+      const int p = T.pos[(size_t)s * lanes + l];
       if (p < gstart[g] || p >= gstart[g + 1] || (int)((node[p] >> 16) * np + (node[p] & 0xffff)) != e) return false;
       for (uint32_t v : o)
         if (v != zero && grp[v / 8] >= (int)g) return false;
@@ -547,6 +549,12 @@ hcz_status hcz_plan_create(hcz_ctx* ctx, const hcz_grid* g, hcz_plan** out) {
   SlotTables slots = make_slots(np, nq, L, node, gstart, dp, dq);
   if (!slots_valid(slots, np, nq, N, nlev, node, gstart))
     return fail(HCZ_EINVAL, "internal: slot tables for %dx%d failed their check", np, nq);
+  // the wave-team layouts: slots of 128 (two waves) and 256 nodes (four waves)
+  SlotTables team[2] = {make_slots(np, nq, L, node, gstart, dp, dq, 128, kTeamSlots2),
+                        make_slots(np, nq, L, node, gstart, dp, dq, 256, kTeamSlots4)};
+  for (int k = 0; k < 2; ++k)
+    if (!slots_valid(team[k], np, nq, N, nlev, node, gstart, k == 0 ? 128 : 256))
+      return fail(HCZ_EINVAL, "internal: team slot tables for %dx%d failed their check", np, nq);
   hcz_plan* P = new hcz_plan();
   P->ctx = ctx;
   GridDev& G = P->G;
@@ -578,6 +586,24 @@ hcz_status hcz_plan_create(hcz_ctx* ctx, const hcz_grid* g, hcz_plan** out) {
   G.slot_sync = slots.sync;
   G.slot_keep = slots.keep;
   G.slot_half = slots.half;
+  std::vector<uint16_t> trank[2];
+  for (int k = 0; k < 2; ++k) {
+    const SlotTables& T = team[k];
+    G.tnslots[k] = T.nslots;
+    G.tncoarse[k] = T.ncoarse;
+    G.tnw[k] = (int)T.wtab.size();
+    G.tslot_bil[k] = T.bil;
+    G.tslot_sync[k] = T.sync;
+    G.tslot_keep[k] = T.keep;
+    G.tslot_meta[k] = nullptr;
+    G.tslot_rank[k] = nullptr;
+    G.twtab[k] = nullptr;
+    trank[k].assign(T.pos.size(), 0);
+    for (size_t q = 0; q < trank[k].size(); ++q) {
+      const uint32_t w0 = T.meta[3 * q], w2 = T.meta[3 * q + 2];
+      if ((w0 & 0xffffu) != (uint32_t)N * 8u) trank[k][q] = (uint16_t)(T.pos[q] - gstart[w2 >> 28]);
+    }
+  }
   if ((s = upload(P->allocs, vol, &G.vol)) || (s = upload(P->allocs, apar, &G.apar)) ||
       (s = upload(P->allocs, cperp, &G.cperp)) || (s = upload(P->allocs, node, &G.node_ij)) ||
       (s = upload(P->allocs, dp.lev, &G.lev_par)) || (s = upload(P->allocs, dp.a, &G.a_par)) ||
@@ -585,7 +611,13 @@ hcz_status hcz_plan_create(hcz_ctx* ctx, const hcz_grid* g, hcz_plan** out) {
       (s = upload(P->allocs, dq.lev, &G.lev_perp)) || (s = upload(P->allocs, dq.a, &G.a_perp)) ||
       (s = upload(P->allocs, dq.b, &G.b_perp)) || (s = upload(P->allocs, dq.s, &G.s_perp)) ||
       (s = upload(P->allocs, slots.meta, &G.slot_meta)) || (s = upload(P->allocs, rank, &G.slot_rank)) ||
-      (s = upload(P->allocs, slots.wtab, &G.wtab))) {
+      (s = upload(P->allocs, slots.wtab, &G.wtab)) ||
+      (team[0].nslots > 0 && ((s = upload(P->allocs, team[0].meta, &G.tslot_meta[0])) ||
+                              (s = upload(P->allocs, trank[0], &G.tslot_rank[0])) ||
+                              (s = upload(P->allocs, team[0].wtab, &G.twtab[0])))) ||
+      (team[1].nslots > 0 && ((s = upload(P->allocs, team[1].meta, &G.tslot_meta[1])) ||
+                              (s = upload(P->allocs, trank[1], &G.tslot_rank[1])) ||
+                              (s = upload(P->allocs, team[1].wtab, &G.twtab[1]))))) {
     free_all(P->allocs);
     delete P;
     return s;
@@ -604,6 +636,8 @@ hcz_status hcz_plan_variants(const hcz_plan* plan, int32_t* list, int32_t* n) {
   if (G.N <= 256 * 6) list[k++] = HCZ_VARIANT_BLOCK_256x6;
   if (G.N <= 512 * 5) list[k++] = HCZ_VARIANT_BLOCK_512x5;
   if (G.N <= 512 * 9) list[k++] = HCZ_VARIANT_BLOCK_512x9;
+  if (team_path(G, 2)) list[k++] = HCZ_VARIANT_TEAM2;
+  if (team_path(G, 4)) list[k++] = HCZ_VARIANT_TEAM4;
   *n = k;
   return HCZ_OK;
 }
@@ -622,7 +656,12 @@ hcz_status hcz_plan_set_variant(hcz_plan* plan, int32_t variant) {
 
 hcz_status hcz_plan_path(const hcz_plan* plan, int32_t* path) {
   if (!plan || !path) return fail(HCZ_EINVAL, "NULL argument");
-  *path = wave_fixed_path(plan->G) ? HCZ_PATH_WAVE_FIXED : wave_path(plan->G) ? HCZ_PATH_WAVE : HCZ_PATH_BLOCK;
+  const GridDev& G = plan->G;
+  *path = wave_fixed_path(G) ? HCZ_PATH_WAVE_FIXED
+          : wave_path(G)     ? HCZ_PATH_WAVE
+          : team_path(G, 2)  ? HCZ_PATH_TEAM2
+          : team_path(G, 4)  ? HCZ_PATH_TEAM4
+                             : HCZ_PATH_BLOCK;
   return HCZ_OK;
 }
 

@@ -16,6 +16,8 @@ constexpr int kMaxN = 4608;         // largest n_par * n_perp (keeps per-block L
 constexpr int kMaxLev = 9;          // L + 1 for n <= 128 is at most 8
 constexpr int kLadder = 41;         // quantisation ladder k = 0..40
 constexpr int kWaveSlots = 26;     // slots of 64 nodes a wave-per-histogram kernel holds
+constexpr int kTeamSlots2 = 22;    // slots of 128 nodes a team of two waves holds
+constexpr int kTeamSlots4 = 20;    // slots of 256 nodes a team of four waves holds
 constexpr int kHidden = 128;
 constexpr int kLatent = 16;
 
@@ -61,6 +63,14 @@ struct GridDev {
   const uint32_t* slot_meta;         // [nslots * 64][3], see make_slots()
   const uint16_t* slot_rank;         // [nslots * 64] packing rank of each entry within its group
   const double* wtab;                // [nw] distinct interpolation weights, wtab[0] = 0
+  // Wave-team layout (a team of W waves per histogram, for grids beyond one wave): the same
+  // scheme with slots of 64 W nodes, index 0 for W = 2 and 1 for W = 4; tnslots[k] = 0
+  // where the grid does not fit that team.
+  int tnslots[2], tncoarse[2], tnw[2];
+  uint32_t tslot_bil[2], tslot_sync[2], tslot_keep[2];
+  const uint32_t* tslot_meta[2];     // [tnslots * 64 W][3]
+  const uint16_t* tslot_rank[2];     // [tnslots * 64 W]
+  const double* twtab[2];            // [tnw]
 };
 
 struct ModelDev {
@@ -412,6 +422,8 @@ hipError_t launch_conv_encode(const ModelDev& M, const void* hist, int dtype, lo
                               long long rs, float* z, hipStream_t st);
 hipError_t launch_conv_decode(const ModelDev& M, const uint8_t* codes, const float* centroids, int bits,
                               long long H, float* fhat, hipStream_t st);
+hipError_t launch_residual_t(const GridDev& G, const ResidualArgs& a, int W, hipStream_t st);
+bool team_path(const GridDev& G, int W);
 hipError_t launch_cv_fwd(const float* in, int C, int n, int relu_in, const float* w, const float* bias, float* out,
                          int O, int m, long long B, hipStream_t st, int bf);
 hipError_t launch_cvt_fwd(const float* in, int C, int n, int relu_in, const float* w, const float* bias, float* out,

@@ -770,6 +770,10 @@ hipError_t launch_residual(const GridDev& G, const ResidualArgs& a, hipStream_t 
   const int v = a.variant;
   const bool wave_v = v == HCZ_VARIANT_AUTO || v == HCZ_VARIANT_WAVE_FIXED || v == HCZ_VARIANT_WAVE;
   if (wave_path(G) && !a.kl && wave_v) return launch_residual_w(G, a, st);
+  if ((v == HCZ_VARIANT_TEAM2 || v == HCZ_VARIANT_TEAM4) && !a.kl)
+    return launch_residual_t(G, a, v == HCZ_VARIANT_TEAM2 ? 2 : 4, st);
+  if (v == HCZ_VARIANT_AUTO && !a.kl && !wave_path(G) && (team_path(G, 2) || team_path(G, 4)))
+    return launch_residual_t(G, a, team_path(G, 2) ? 2 : 4, st);
   // threads x nodes per thread: the variant's, else the smallest that holds the grid
   // (256 x 6 up to 1536 nodes, then 512 x 5 (2560) and 512 x 9 (4608))
   int shape = v;

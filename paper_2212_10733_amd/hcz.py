@@ -273,16 +273,16 @@ class Plan:
         self.h = h
         self.variant = "auto"
 
-    PATHS = {0: "block", 1: "wave", 2: "wave_fixed"}
+    PATHS = {0: "block", 1: "wave", 2: "wave_fixed", 3: "team2", 4: "team4"}
 
     @property
     def path(self) -> str:
-        """Kernel family serving this grid: 'block', 'wave' or 'wave_fixed'."""
+        """Kernel family serving this grid: 'block', 'wave', 'wave_fixed', 'team2' or 'team4'."""
         v = C.c_int32()
         _check(LIB.hcz_plan_path(self.h, C.byref(v)))
         return self.PATHS[v.value]
 
-    VARIANTS = ("auto", "wave_fixed", "wave", "block_256x6", "block_512x5", "block_512x9")
+    VARIANTS = ("auto", "wave_fixed", "wave", "block_256x6", "block_512x5", "block_512x9", "team2", "team4")
 
     def variants(self) -> list:
         """Launch variants of the residual stage valid for this grid (names of VARIANTS)."""
