@@ -28,25 +28,41 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 constexpr int kCP1 = 40;   // LDS pitch (bfloat16) of a conv1 output cell (32 channels)
 constexpr int kCPD = 72;   // LDS pitch (bfloat16) of a decoder hidden cell (64 channels)
-constexpr int kCP3 = 33;   // LDS pitch (floats) of a transposed-conv1 output cell (32 channels)
+constexpr int kCP3 = 36;   // LDS pitch (floats) of a transposed-conv1 output cell (32 channels, 16-byte rows)
 constexpr int kConvGrid = 1024;  // workgroups of the looping decoder kernel
+constexpr int kConvEncGrid = 512; // workgroups of the looping encoder kernel (two per CU)
 
 __device__ __forceinline__ f32x16 mfma_bf16c(bf16x8 a, bf16x8 b, f32x16 c) {
   return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
 }
 
-// One workgroup per histogram (an LDS footprint of 41 KB lets three share a CU).
+// A workgroup loops over histograms (h = blockIdx.x, + gridDim.x, ...) with conv2's
+// weights staged once in LDS; 78 KB of LDS lets two share a CU.
 template <typename TIn>
-__global__ __launch_bounds__(256, 2) void k_conv_enc(ModelDev M, const TIn* hist, long long hs, long long rs,
-                                                     float* h2out) {
+__global__ __launch_bounds__(256, 2) void k_conv_enc(ModelDev M, const TIn* hist, long long n, long long hs,
+                                                     long long rs, float* h2out) {
   __shared__ float xs[39 * 39];
   __shared__ __attribute__((aligned(16))) __bf16 h1p[21 * 21 * kCP1];   // later: h2 (6400 floats)
+  __shared__ __attribute__((aligned(16))) __bf16 w2s[9 * 64 * 32];      // conv2 weights [tap][out][in]
   float* h2s = (float*)h1p;
   const int t = threadIdx.x, w = t >> 6, l = t & 63;
   const int li = l & 31, kh = l >> 5;
-  const __bf16* W2 = (const __bf16*)M.c2w;
-  const long long h = blockIdx.x;
+  {
+    const bf16x8* src = (const bf16x8*)M.c2w;
+    for (int q = t; q < 9 * 64 * 32 / 8; q += 256) ((bf16x8*)w2s)[q] = src[q];
+  }
+  // conv1's weights: thread -> channels 4 cg .. 4 cg + 3
+  const int cg = t & 7;
+  float wv1[4][9], bv1[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) wv1[c][k] = M.c1w[(4 * cg + c) * 9 + k];
+    bv1[c] = M.c1b[4 * cg + c];
+  }
+  for (long long h = blockIdx.x; h < n; h += gridDim.x) {
   const TIn* f = hist + h * hs;
+  __syncthreads();          // the previous histogram is done with xs and h2s
   {
     // all loads first (6 per thread), then the stores: one memory round trip
     float fv[6], mv[6], rv[6];
@@ -71,16 +87,12 @@ __global__ __launch_bounds__(256, 2) void k_conv_enc(ModelDev M, const TIn* hist
     h1p[(cy * 21 + cx) * kCP1 + c] = (__bf16)0.0f;
   }
   __syncthreads();
-  // conv1: thread -> channel c = t % 32, positions p = t / 32 + 8 q
+  // conv1: thread -> channels 4 cg .. 4 cg + 3, positions p = t / 8 + 32 q; each input value
+  // read once for the four channels, every channel's chain in the same tap order
   {
-    const int c = t & 31;
-    float wv[9];
-#pragma unroll
-    for (int k = 0; k < 9; ++k) wv[k] = M.c1w[c * 9 + k];
-    const float bv = M.c1b[c];
-    for (int p = t >> 5; p < 400; p += 8) {
+    for (int p = t >> 3; p < 400; p += 32) {
       const int oy = p / 20, ox = p - 20 * oy;
-      float s = bv;
+      float s[4] = {bv1[0], bv1[1], bv1[2], bv1[3]};
 #pragma unroll
       for (int ky = 0; ky < 3; ++ky) {
         const int iy = 2 * oy - 1 + ky;
@@ -89,10 +101,14 @@ __global__ __launch_bounds__(256, 2) void k_conv_enc(ModelDev M, const TIn* hist
         for (int kx = 0; kx < 3; ++kx) {
           const int ix = 2 * ox - 1 + kx;
           if (ix < 0 || ix >= 39) continue;
-          s = fmaf(xs[iy * 39 + ix], wv[ky * 3 + kx], s);
+          const float xv = xs[iy * 39 + ix];
+#pragma unroll
+          for (int c = 0; c < 4; ++c) s[c] = fmaf(xv, wv1[c][ky * 3 + kx], s[c]);
         }
       }
-      h1p[((oy + 1) * 21 + (ox + 1)) * kCP1 + c] = (__bf16)fmaxf(s, 0.0f);
+      __bf16* dst = &h1p[((oy + 1) * 21 + (ox + 1)) * kCP1 + 4 * cg];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) dst[c] = (__bf16)fmaxf(s[c], 0.0f);
     }
   }
   __syncthreads();
@@ -113,7 +129,7 @@ __global__ __launch_bounds__(256, 2) void k_conv_enc(ModelDev M, const TIn* hist
       const bf16x8 a = *(const bf16x8*)(arow + 16 * half + 8 * kh);
 #pragma unroll
       for (int nt = 0; nt < 2; ++nt)
-        acc[nt] = mfma_bf16c(a, *(const bf16x8*)(W2 + ((long long)(tap * 64 + 32 * nt + li)) * 32 + 16 * half + 8 * kh),
+        acc[nt] = mfma_bf16c(a, *(const bf16x8*)(w2s + (tap * 64 + 32 * nt + li) * 32 + 16 * half + 8 * kh),
                              acc[nt]);
     }
   }
@@ -129,49 +145,65 @@ __global__ __launch_bounds__(256, 2) void k_conv_enc(ModelDev M, const TIn* hist
     }
   }
   __syncthreads();
-  float* dst = h2out + h * 6400;
-  for (int k = t; k < 6400; k += 256) dst[k] = h2s[k];
+  float4* dst = (float4*)(h2out + h * 6400);
+  for (int k = t; k < 1600; k += 256) dst[k] = ((const float4*)h2s)[k];
+  }
 }
 
-// z[h][o] = fb[o] + sum_k h2[h][k] fw[o][k]: one wave per 32 histograms on
-// v_mfma_f32_32x32x2f32 (columns 16..31 are zero); lane half kq holds k = 8c + 4kq .. + 3
-// of both operands, one 16-byte load each.
+// z[h][o] = fb[o] + sum_k h2[h][k] fw[o][k] on v_mfma_f32_16x16x4f32: a workgroup takes 16
+// histograms, its four waves a quarter of K = 6400 each.  Per 16-wide k step lane l holds
+// k = 16 c + 4 (l / 16) .. + 3 of row l % 16 of both operands (one 16-byte load each; the
+// products are summed in this lane order, which the two operands share), and the four
+// partial tiles are added in wave order.
 __global__ __launch_bounds__(256) void k_conv_fc(const float* h2, long long n, const float* fw, const float* fb,
                                                  float* z) {
-  const int t = threadIdx.x, w = t >> 6, l = t & 63, li = l & 31, kq = l >> 5;
-  const long long r0 = ((long long)blockIdx.x * 4 + w) * 32;
-  if (r0 >= n) return;
-  const long long row = min(r0 + li, n - 1);
-  const f32x4* a = (const f32x4*)(h2 + row * 6400 + 4 * kq);
-  const f32x4* b = (const f32x4*)(fw + (long long)min(li, 15) * 6400 + 4 * kq);
-  const bool bon = li < 16;
-  f32x16 acc;
+  __shared__ float part[4][16 * 16];
+  const int t = threadIdx.x, w = t >> 6, l = t & 63, lr = l & 15, lq = l >> 4;
+  const long long r0 = (long long)blockIdx.x * 16;
+  const long long row = min(r0 + lr, n - 1);
+  constexpr int kSteps = 6400 / 16 / 4;          // 16-wide k steps per wave
+  const f32x4* a = (const f32x4*)(h2 + row * 6400 + (long long)w * (6400 / 4) + 4 * lq);
+  const f32x4* b = (const f32x4*)(fw + (long long)lr * 6400 + w * (6400 / 4) + 4 * lq);
+  f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+  f32x4 an[4], bn[4];
 #pragma unroll
-  for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
-  f32x4 an = a[0], bn = b[0];
-  for (int c = 0; c < 800; ++c) {
-    const f32x4 av = an, bv = bn;
-    if (c + 1 < 800) {
-      an = a[2 * (c + 1)];
-      bn = b[2 * (c + 1)];
+  for (int u = 0; u < 4; ++u) {
+    an[u] = a[4 * u];
+    bn[u] = b[4 * u];
+  }
+  for (int c = 0; c < kSteps; c += 4) {
+    f32x4 av[4], bv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      av[u] = an[u];
+      bv[u] = bn[u];
+    }
+    if (c + 4 < kSteps) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        an[u] = a[4 * (c + 4 + u)];
+        bn[u] = b[4 * (c + 4 + u)];
+      }
     }
 #pragma unroll
-    for (int s = 0; s < 4; ++s)
-      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av[s], bon ? bv[s] : 0.0f, acc, 0, 0, 0);
-  }
-  if (li < 16) {
-    const float bias = fb[li];
+    for (int u = 0; u < 4; ++u)
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const long long hr = r0 + 8 * (r >> 2) + 4 * kq + (r & 3);
-      if (hr < n) z[hr * kLatent + li] = acc[r] + bias;
-    }
+      for (int e = 0; e < 4; ++e) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[u][e], bv[u][e], acc, 0, 0, 0);
   }
+  // D layout: lane l holds rows 4 (l / 16) + r, column l % 16
+#pragma unroll
+  for (int r = 0; r < 4; ++r) part[w][(4 * lq + r) * 16 + lr] = acc[r];
+  __syncthreads();
+  const int q = t;                               // 256 outputs: row q / 16, column q % 16
+  const long long hr = r0 + q / 16;
+  if (hr < n) z[hr * kLatent + (q & 15)] = fb[q & 15] + (((part[0][q] + part[1][q]) + part[2][q]) + part[3][q]);
 }
 
-// Decoder hidden layer: hd[h][k] = bf16(relu(db[k] + sum_d zhat[h][d] dw[k][d])) as the
-// FP32 chain over d = 0..15.  A workgroup takes 256 values of k (one per thread, its dw
-// row in registers) for 64 histograms.
+// Decoder hidden layer: hd = bf16(relu(db[k] + sum_d zhat[h][d] dw[k][d])) as the FP32
+// chain over d = 0..15, for unit k = channel * 100 + position, stored position-major:
+// hd[h][position * 64 + channel] (the layout the decoder stages into LDS).  A workgroup
+// takes 256 consecutive stored units (one per thread, its dw row in registers) for 64
+// histograms, so its stores are contiguous.
 __global__ __launch_bounds__(256) void k_conv_hidden(ModelDev M, const uint8_t* codes, const float* centroids,
                                                      int kcb, long long n, __bf16* hd) {
   __shared__ float zs[64 * kLatent];
@@ -183,8 +215,9 @@ __global__ __launch_bounds__(256) void k_conv_hidden(ModelDev M, const uint8_t* 
     zs[q] = hh < n ? centroids[d * kcb + min((int)codes[hh * kLatent + d], kcb - 1)] : 0.0f;
   }
   __syncthreads();
-  const int k = blockIdx.x * 256 + t;
-  if (k >= 6400) return;
+  const int ks = blockIdx.x * 256 + t;           // stored index: position * 64 + channel
+  if (ks >= 6400) return;
+  const int k = (ks & 63) * 100 + (ks >> 6);     // unit: channel * 100 + position
   float wv[kLatent];
   const f32x4* dw = (const f32x4*)(M.dw + (long long)k * kLatent);
 #pragma unroll
@@ -199,7 +232,7 @@ __global__ __launch_bounds__(256) void k_conv_hidden(ModelDev M, const uint8_t* 
     float s = b;
 #pragma unroll
     for (int d = 0; d < kLatent; ++d) s = fmaf(zs[r * kLatent + d], wv[d], s);
-    hd[(h0 + r) * 6400 + k] = (__bf16)fmaxf(s, 0.0f);
+    hd[(h0 + r) * 6400 + ks] = (__bf16)fmaxf(s, 0.0f);
   }
 }
 
@@ -209,14 +242,10 @@ __global__ __launch_bounds__(256) void k_conv_hidden(ModelDev M, const uint8_t* 
 __global__ __launch_bounds__(256, 2) void k_conv_dec(ModelDev M, const __bf16* hd, long long n, float* fhat) {
   __shared__ __attribute__((aligned(16))) __bf16 hdp[11 * 11 * kCPD];
   __shared__ __attribute__((aligned(16))) float h3s[20 * 20 * kCP3];
-  __shared__ float t2s[32 * 9];
+  __shared__ __attribute__((aligned(16))) float t2v[9 * 32];     // transposed conv2 weights [tap][channel]
   const int t = threadIdx.x, w = t >> 6, l = t & 63;
   const int li = l & 31, kh = l >> 5;
-  {
-    const float a = M.t2w[t], b = t < 32 ? M.t2w[256 + t] : 0.0f;
-    t2s[t] = a;
-    if (t < 32) t2s[256 + t] = b;
-  }
+  for (int q = t; q < 9 * 32; q += 256) t2v[(q % 9) * 32 + q / 9] = M.t2w[q];   // t2w[ci][tap]
   // zero row 10 and column 10 of the padded hidden layout (never written afterwards)
   for (int q = t; q < 21 * 64; q += 256) {
     const int cell = q >> 6, c = q & 63;
@@ -228,8 +257,8 @@ __global__ __launch_bounds__(256, 2) void k_conv_dec(ModelDev M, const __bf16* h
   const float b2 = M.t2b[0];
   for (long long h = blockIdx.x; h < n; h += gridDim.x) {
   __syncthreads();          // the previous histogram is done with hdp and h3s
-  // the hidden layer (k = channel * 100 + y * 10 + x) into [y][x][channel]: 16-byte
-  // loads, all issued before the scatter into LDS
+  // the hidden layer ([position][channel], 8 channels per 16-byte chunk) into
+  // [y][x][channel]: all loads issued before the stores
   {
     const bf16x8* src = (const bf16x8*)(hd + h * 6400);
     bf16x8 v[4];
@@ -239,12 +268,8 @@ __global__ __launch_bounds__(256, 2) void k_conv_dec(ModelDev M, const __bf16* h
     for (int r = 0; r < 4; ++r) {
       const int m = t + 256 * r;
       if (m >= 800) continue;
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int k = 8 * m + e;
-        const int c = k / 100, p = k - 100 * c, y = p / 10, x = p - 10 * y;
-        hdp[(y * 11 + x) * kCPD + c] = v[r][e];
-      }
+      const int p = m >> 3, y = p / 10, x = p - 10 * y;
+      *(bf16x8*)&hdp[(y * 11 + x) * kCPD + 8 * (m & 7)] = v[r];
     }
   }
   __syncthreads();
@@ -295,25 +320,57 @@ __global__ __launch_bounds__(256, 2) void k_conv_dec(ModelDev M, const __bf16* h
     }
   }
   __syncthreads();
-  // transposed conv2 (32 -> 1) on the vector ALUs: output (oy, ox) takes input
-  // (iy, ix) = ((oy + 1 - ky) / 2, (ox + 1 - kx) / 2) where that is whole and in range
-  for (int o = t; o < 1521; o += 256) {
-    const int oy = o / 39, ox = o - 39 * oy;
-    float s = 0.0f;
-#pragma unroll 1
-    for (int ky = 0; ky < 3; ++ky) {
-      const int ny = oy + 1 - ky;
-      if (ny < 0 || (ny & 1) || (ny >> 1) >= 20) continue;
-#pragma unroll 1
-      for (int kx = 0; kx < 3; ++kx) {
-        const int nx = ox + 1 - kx;
-        if (nx < 0 || (nx & 1) || (nx >> 1) >= 20) continue;
-        const float* cell = &h3s[((ny >> 1) * 20 + (nx >> 1)) * kCP3];
-#pragma unroll 8
-        for (int ci = 0; ci < 32; ++ci) s = fmaf(cell[ci], t2s[ci * 9 + ky * 3 + kx], s);
+  // transposed conv2 (32 -> 1) on the vector ALUs, one 2 x 2 output block per task: output
+  // (2m + a, 2n + b) takes input cells (m, n), (m, n + 1), (m + 1, n), (m + 1, n + 1) with
+  // taps ky = 1 (a = 0) or ky = 0 from row m + 1 and ky = 2 from row m (a = 1), likewise
+  // kx; the four cells are read once for the block's nine taps.  Row and column 39 do
+  // not exist, so cells past 19 are never needed (clamped reads, outputs skipped).
+  for (int task = t; task < 400; task += 256) {
+    const int m = task / 20, nn = task - 20 * m;
+    const int m1 = min(m + 1, 19), n1 = min(nn + 1, 19);
+    const float4* a00 = (const float4*)&h3s[(m * 20 + nn) * kCP3];
+    const float4* a01 = (const float4*)&h3s[(m * 20 + n1) * kCP3];
+    const float4* a10 = (const float4*)&h3s[(m1 * 20 + nn) * kCP3];
+    const float4* a11 = (const float4*)&h3s[(m1 * 20 + n1) * kCP3];
+    const float4* wt = (const float4*)t2v;       // wt[tap * 8 + channel / 4]
+    float see = 0.0f, seo = 0.0f, soe = 0.0f, soo = 0.0f;
+#pragma unroll 2
+    for (int q = 0; q < 8; ++q) {
+      const float4 c00 = a00[q], c01 = a01[q], c10 = a10[q], c11 = a11[q];
+      const float4 w00 = wt[0 * 8 + q], w01 = wt[1 * 8 + q], w02 = wt[2 * 8 + q];
+      const float4 w10 = wt[3 * 8 + q], w11 = wt[4 * 8 + q], w12 = wt[5 * 8 + q];
+      const float4 w20 = wt[6 * 8 + q], w21 = wt[7 * 8 + q], w22 = wt[8 * 8 + q];
+#define HCZ_T2(E)                                  \
+      see = fmaf(c00.E, w11.E, see);                \
+      seo = fmaf(c01.E, w10.E, seo);                \
+      seo = fmaf(c00.E, w12.E, seo);                \
+      soe = fmaf(c10.E, w01.E, soe);                \
+      soe = fmaf(c00.E, w21.E, soe);                \
+      soo = fmaf(c11.E, w00.E, soo);                \
+      soo = fmaf(c10.E, w02.E, soo);                \
+      soo = fmaf(c01.E, w20.E, soo);                \
+      soo = fmaf(c00.E, w22.E, soo);
+      HCZ_T2(x) HCZ_T2(y) HCZ_T2(z) HCZ_T2(w)
+#undef HCZ_T2
+    }
+    const int oy = 2 * m, ox = 2 * nn;
+    float* out = fhat + h * 1521;
+    {
+      const int o = oy * 39 + ox;
+      out[o] = fmaf(M.sd[o], see + b2, M.mu[o]);
+    }
+    if (ox + 1 < 39) {
+      const int o = oy * 39 + ox + 1;
+      out[o] = fmaf(M.sd[o], seo + b2, M.mu[o]);
+    }
+    if (oy + 1 < 39) {
+      const int o = (oy + 1) * 39 + ox;
+      out[o] = fmaf(M.sd[o], soe + b2, M.mu[o]);
+      if (ox + 1 < 39) {
+        const int o2 = o + 1;
+        out[o2] = fmaf(M.sd[o2], soo + b2, M.mu[o2]);
       }
     }
-    fhat[h * 1521 + o] = fmaf(M.sd[o], s + b2, M.mu[o]);
   }
   }
 }
@@ -324,13 +381,14 @@ hipError_t launch_conv_encode(const ModelDev& M, const void* hist, int dtype, lo
                               long long rs, float* z, hipStream_t st) {
   for (long long c0 = 0; c0 < H; c0 += kConvChunk) {
     const long long n = std::min((long long)kConvChunk, H - c0);
+    const dim3 eg((unsigned)std::min(n, (long long)kConvEncGrid));
     if (dtype == HCZ_F32)
-      hipLaunchKernelGGL(k_conv_enc<float>, dim3((unsigned)n), dim3(256), 0, st, M, (const float*)hist + c0 * hs,
-                         hs, rs, M.scratch);
+      hipLaunchKernelGGL(k_conv_enc<float>, eg, dim3(256), 0, st, M, (const float*)hist + c0 * hs, n, hs, rs,
+                         M.scratch);
     else
-      hipLaunchKernelGGL(k_conv_enc<double>, dim3((unsigned)n), dim3(256), 0, st, M, (const double*)hist + c0 * hs,
-                         hs, rs, M.scratch);
-    hipLaunchKernelGGL(k_conv_fc, dim3((unsigned)((n + 127) / 128)), dim3(256), 0, st, (const float*)M.scratch, n,
+      hipLaunchKernelGGL(k_conv_enc<double>, eg, dim3(256), 0, st, M, (const double*)hist + c0 * hs, n, hs, rs,
+                         M.scratch);
+    hipLaunchKernelGGL(k_conv_fc, dim3((unsigned)((n + 15) / 16)), dim3(256), 0, st, (const float*)M.scratch, n,
                        M.fw, M.fb, z + c0 * kLatent);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
