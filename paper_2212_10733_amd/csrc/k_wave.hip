@@ -325,16 +325,17 @@ __device__ __forceinline__ void for_columns(const GridDev& G, BEGIN begin, BODY 
 
 // One Newton pass at lam (Section III Stage 5): v[0..3] = A x, v[4] = sum |A_1| x and,
 // when THETA, v[15] = ||x - ft||^2, with x = max(0, ft - A^T lam) and ft in the wave
-// buffer.  The Hessian A diag(x > 0) A^T is left as this lane's share in hh[10] (upper
-// triangle, row-major, without the duplicate (1,1) = (0,3) entry); hess_reduce() sums it
-// only when a step is taken.  Per column the row sums of w x, c w x and, on active
+// buffer; hs the Hessian A diag(x > 0) A^T (upper triangle, row-major, without the
+// duplicate (1,1) = (0,3) entry), all reduced together by one transposed butterfly.  Per
+// column the row sums of w x, c w x and, on active
 // cells, w^2, w^2 c, w^2 c^2 come first and are then weighted by the column's powers of
 // a.  The correction per cell is vol * ((lam3 a + lam1) a + lam0 + lam2 c), one fixed
 // order for compression and decompression.
 template <class SH, bool UVOL, bool THETA, bool POS>
 __device__ __forceinline__ void newton_pass_w(const GridDev& G, const WaveLds& L, const double (&lam)[4],
-                                              double (&v)[16], double (&sc)[4], double (&hh)[9]) {
+                                              double (&v)[16], double (&sc)[4], double (&hs)[9]) {
   double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0, v4 = 0.0, v15 = 0.0, c0 = 0.0, c2 = 0.0, c3 = 0.0;
+  double hh[9];
 #pragma unroll
   for (int k = 0; k < 9; ++k) hh[k] = 0.0;
   double sx, sxc, sxa, sxca, h0, hc, hcc, s2;
@@ -404,12 +405,26 @@ __device__ __forceinline__ void newton_pass_w(const GridDev& G, const WaveLds& L
   } else {
     for_columns(G, begin, body, fold);
   }
-  v[0] = wsum(v0);
-  v[1] = wsum(v1);
-  v[2] = wsum(v2);
-  v[3] = wsum(v3);
-  v[4] = wsum(v4);
-  v[15] = THETA ? wsum(v15) : 0.0;
+  const double s2v = UVOL ? G.vol0 * G.vol0 : 1.0;
+  if constexpr (POS) {
+    const double r[16] = {v0, v1, v2, v3, v4, v15, hh[0], hh[1], hh[2], hh[3], hh[4], hh[5], hh[6], hh[7], hh[8], 0.0};
+    double o[16];
+    wsum16(r, o);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) v[k] = o[k];
+    v[15] = THETA ? o[5] : 0.0;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) hs[k] = o[6 + k] * s2v;
+  } else {
+    v[0] = wsum(v0);
+    v[1] = wsum(v1);
+    v[2] = wsum(v2);
+    v[3] = wsum(v3);
+    v[4] = wsum(v4);
+    v[15] = THETA ? wsum(v15) : 0.0;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) hs[k] = wsum(hh[k]) * s2v;
+  }
   if (UVOL) {
 #pragma unroll
     for (int k = 0; k < 5; ++k) v[k] *= G.vol0;
@@ -429,13 +444,11 @@ __device__ __forceinline__ void newton_pass_w(const GridDev& G, const WaveLds& L
   }
 }
 
-// The pass's Hessian shares summed into v[5..14].
-template <bool UVOL>
-__device__ __forceinline__ void hess_reduce(const GridDev& G, const double (&hh)[9], double (&v)[16]) {
-  const double s2v = UVOL ? G.vol0 * G.vol0 : 1.0;
+// The pass's reduced Hessian into v[5..14].
+__device__ __forceinline__ void hess_fill(const double (&hs)[9], double (&v)[16]) {
   constexpr int dst[9] = {5, 6, 7, 8, 10, 11, 12, 13, 14};
 #pragma unroll
-  for (int k = 0; k < 9; ++k) v[dst[k]] = wsum(hh[k]) * s2v;
+  for (int k = 0; k < 9; ++k) v[dst[k]] = hs[k];
   v[9] = v[8];
 }
 
@@ -449,7 +462,7 @@ __device__ __forceinline__ int newton_w(const GridDev& G, const WaveLds& L, cons
     if (theta) newton_pass_w<SH, UVOL, true, POS>(G, L, cand, v, sc, hh);
     else newton_pass_w<SH, UVOL, false, POS>(G, L, cand, v, sc, hh);
   };
-  auto hess = [&](double (&v)[16]) { hess_reduce<UVOL>(G, hh, v); };
+  auto hess = [&](double (&v)[16]) { hess_fill(hh, v); };
   return newton_core(pass, hess, b, lam, s1, max1, s2, max2, armijo2, upd, have_init, lam_init, rejected);
 }
 
@@ -760,7 +773,7 @@ __global__ __launch_bounds__(256, 2) void k_residual_w(GridDev G, ResidualArgs a
       // cell active; a failed factorisation leaves a non-finite start, which is rejected
       double v[16], sc[4], hh[9], g[4];
       newton_pass_w<SH, UVOL, false, false>(G, L, l0, v, sc, hh);
-      hess_reduce<UVOL>(G, hh, v);
+      hess_fill(hh, v);
 #pragma unroll
       for (int k = 0; k < 4; ++k) g[k] = v[k] - b[k];
       if (!chol4(v, g, l0)) {

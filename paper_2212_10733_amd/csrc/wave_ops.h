@@ -88,6 +88,51 @@ __device__ __forceinline__ dd wdd(dd v) {
   return dd{lane63(v.hi), lane63(v.lo)};
 }
 
+// Sixteen wave sums at once, by a transposed butterfly: each step pairs every value a lane
+// carries with a partner lane and keeps half of the values, so the lanes end with one
+// total each instead of sixteen.  Steps: lanes l, l ^ 32 (permlane32 swap; values k and
+// k + 8), l, l ^ 16 (permlane16 swap; k and k + 4), l, l ^ 15 (row_mirror; k and k + 2,
+// by bit 3), l, l ^ 7 (row_half_mirror; k and k + 1, by bit 2), then l ^ 1 and l ^ 2.  Lane
+// 4 i .. 4 i + 3 ends with the total of v[i]; every lane reads all sixteen from those lanes,
+// so all hold the same bits.
+__device__ __forceinline__ double swap_add32(double p, double q) {
+  const auto rl = __builtin_amdgcn_permlane32_swap((unsigned)__double2loint(p), (unsigned)__double2loint(q), false,
+                                                   false);
+  const auto rh = __builtin_amdgcn_permlane32_swap((unsigned)__double2hiint(p), (unsigned)__double2hiint(q), false,
+                                                   false);
+  return __hiloint2double((int)rh[0], (int)rl[0]) + __hiloint2double((int)rh[1], (int)rl[1]);
+}
+__device__ __forceinline__ double swap_add16(double p, double q) {
+  const auto rl = __builtin_amdgcn_permlane16_swap((unsigned)__double2loint(p), (unsigned)__double2loint(q), false,
+                                                   false);
+  const auto rh = __builtin_amdgcn_permlane16_swap((unsigned)__double2hiint(p), (unsigned)__double2hiint(q), false,
+                                                   false);
+  return __hiloint2double((int)rh[0], (int)rl[0]) + __hiloint2double((int)rh[1], (int)rl[1]);
+}
+__device__ __forceinline__ void wsum16(const double (&v)[16], double (&out)[16]) {
+  const int lane = threadIdx.x & 63;
+  double u[8], w[4], z[2];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) u[k] = swap_add32(v[k], v[k + 8]);       // lane half: k + 8 b5
+#pragma unroll
+  for (int k = 0; k < 4; ++k) w[k] = swap_add16(u[k], u[k + 4]);       // row parity: + 4 b4
+  const bool b3 = (lane & 8) != 0, b2 = (lane & 4) != 0;
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const double keep = b3 ? w[k + 2] : w[k], send = b3 ? w[k] : w[k + 2];
+    z[k] = keep + dpp_d<0x140, 0xF>(send);                                 // + 2 b3
+  }
+  double t;
+  {
+    const double keep = b2 ? z[1] : z[0], send = b2 ? z[0] : z[1];
+    t = keep + dpp_d<0x141, 0xF>(send);                                    // + b2
+  }
+  t = t + dpp_d<0xB1, 0xF>(t);
+  t = t + dpp_d<0x4E, 0xF>(t);
+#pragma unroll
+  for (int i = 0; i < 16; ++i) out[i] = lane_d(t, 4 * i);
+}
+
 __device__ __forceinline__ double theta_w(const double (&v)[16], const double (&lam)[4], const double (&b)[4]) {
   double t = 0.5 * v[15];
 #pragma unroll
