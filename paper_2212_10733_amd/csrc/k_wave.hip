@@ -393,14 +393,25 @@ __device__ __forceinline__ void newton_pass_w(const GridDev& G, const WaveLds& L
     hh[7] = fma(a2, hc, hh[7]);
     hh[8] = fma(a2 * a2, h0, hh[8]);
   };
-  if constexpr (SH::fixed && SH::NP <= 64) {
-    // one column per lane, every row offset a compile-time constant
-    const int i = threadIdx.x & 63;
-    if (i < SH::NP) {
-      begin(i);
+  if constexpr (SH::fixed && SH::NP <= 64 && SH::NQ <= 64) {
+    // an 8 x 8 grid of lane blocks: lane (bx, by) = (l % 8, l / 8) takes columns
+    // BX bx .. BX bx + BX - 1 and rows BY by .. BY by + BY - 1 (39 x 39: 5 x 5 cells, 25
+    // per lane instead of a 39-row column on 39 of the 64 lanes), folding per column
+    constexpr int BX = (SH::NP + 7) / 8, BY = (SH::NQ + 7) / 8;
+    const int lane = threadIdx.x & 63;
+    const int i0 = (lane & 7) * BX, j0 = (lane >> 3) * BY;
 #pragma unroll
-      for (int j = 0; j < SH::NQ; ++j) body(i, j, (uint32_t)(j * SH::NP + i) * 8u);
-      fold(i);
+    for (int ci = 0; ci < BX; ++ci) {
+      const int i = i0 + ci;
+      if (i < SH::NP) {
+        begin(i);
+#pragma unroll
+        for (int cj = 0; cj < BY; ++cj) {
+          const int j = j0 + cj;
+          if (j < SH::NQ) body(i, j, (uint32_t)(j * SH::NP + i) * 8u);
+        }
+        fold(i);
+      }
     }
   } else {
     for_columns(G, begin, body, fold);
