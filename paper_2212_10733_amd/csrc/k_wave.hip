@@ -77,11 +77,11 @@ struct SlotRegs {
 };
 // Entry words hidden from loop-invariant code motion: otherwise every slot's decoded
 // addresses are hoisted out of the bisection loop and the registers spill.
-__device__ __forceinline__ uint2 opaque2(uint2 m) {
-  asm volatile("" : "+v"(m.x), "+v"(m.y));
+__device__ __forceinline__ uint2 opaque2(uint2& m) {
+  asm volatile("" : "+v"(m.x), "+v"(m.y));     // in place: no copy of the register
   return m;
 }
-__device__ __forceinline__ uint32_t opaque1(uint32_t m) {
+__device__ __forceinline__ uint32_t opaque1(uint32_t& m) {
   asm volatile("" : "+v"(m));
   return m;
 }
@@ -196,7 +196,7 @@ constexpr int batch_end(int s) {
 // Slots [S, E) of one group: every entry and corner read first, then values, stores
 // and errors.  Nothing in the batch reads what the batch writes.
 template <class SH, int S, int E, bool STORE_ALL, typename DQ>
-__device__ __forceinline__ void batch_fixed(const WaveLds& L, const SlotRegs<SH::NS>& R, const double (&rm)[SH::NS],
+__device__ __forceinline__ void batch_fixed(const WaveLds& L, SlotRegs<SH::NS>& R, const double (&rm)[SH::NS],
                                             DQ& dqf, double& acc) {
   constexpr int B = E - S;
   double v[B], r[B];
@@ -219,7 +219,7 @@ __device__ __forceinline__ void batch_fixed(const WaveLds& L, const SlotRegs<SH:
 }
 
 template <class SH, int S, bool STORE_ALL, typename DQ>
-__device__ __forceinline__ void slots_fixed(const WaveLds& L, const SlotRegs<SH::NS>& R, const double (&rm)[SH::NS],
+__device__ __forceinline__ void slots_fixed(const WaveLds& L, SlotRegs<SH::NS>& R, const double (&rm)[SH::NS],
                                             DQ& dqf, double& acc) {
   if constexpr (S < SH::NS) {
     constexpr int E = batch_end<SH>(S);
@@ -233,7 +233,7 @@ __device__ __forceinline__ void slots_fixed(const WaveLds& L, const SlotRegs<SH:
 // group only when STORE_ALL) and return sum (rm - y)^2 over the histogram.  DQ(s) gives
 // the lane's quantised coefficient of slot s.
 template <class SH, bool STORE_ALL, typename DQ>
-__device__ __forceinline__ double recompose_w(const GridDev& G, const WaveLds& L, const SlotRegs<SH::NS>& R,
+__device__ __forceinline__ double recompose_w(const GridDev& G, const WaveLds& L, SlotRegs<SH::NS>& R,
                                               const double (&rm)[SH::NS], DQ dqf) {
   constexpr int NS = SH::NS;
   const SlotMasks sm = slot_masks(G);
