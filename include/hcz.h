@@ -409,6 +409,45 @@ hcz_status hcz_timestamp(uint64_t* dst, hcz_stream_t stream);
 /* Ticks per second of the device wall clock of HIP device `device`. */
 hcz_status hcz_wall_clock_hz(int device, double* hz);
 
+/* ---- one launch for the subdomains of several grids ----------------------------------
+ * Compresses nseg batches whose grids may differ (a rank's subdomains at several
+ * resolutions: Section III-A compresses every subdomain's histograms on their own) with
+ * one launch of the residual stage (Stages 4-5) for all of them.  Segment k holds the
+ * arguments of one hcz_compress call, with their meaning there (ws: that segment's
+ * hcz_compress_workspace).  The model stages of the segments run first, in order, on
+ * `stream`; then one persistent launch of as many workgroups as stay resident takes the
+ * segments' histograms from one work list (four histograms of a grid whose nodes fit 26
+ * slots of 64 lanes per item, one wave each; one histogram of a grid that fits 20 slots of
+ * 256 lanes per item, a team of four waves), so the histograms of a small grid and of a
+ * large one share the device instead of running launch after launch; then each segment's
+ * records are compacted as hcz_compress compacts them.  Every segment gets the records,
+ * offsets, flags, multipliers and stats that hcz_compress gives it with the variant
+ * HCZ_VARIANT_WAVE (resp. HCZ_VARIANT_TEAM4), byte for byte; params->variant is not read.
+ * batch_ws: device memory of at least HCZ_BATCH_WORKSPACE_BYTES bytes for the work counter,
+ * reset by the call itself on `stream` (calls that overlap on one batch_ws race).
+ * Errors: HCZ_EINVAL for nseg outside [1, HCZ_BATCH_MAX_SEGMENTS], plans of different
+ * contexts or different dtypes; HCZ_EUNSUPPORTED for a batch mixing uniform and
+ * non-uniform cell volumes, the KL reading, or a grid that fits neither layout;
+ * HCZ_EWORKSPACE for a short batch_ws; otherwise as hcz_compress.  Every segment is checked
+ * before the first launch.  With profiling on, a batch call times its residual launch only
+ * (HCZ_STAGE_RESIDUAL). */
+#define HCZ_BATCH_MAX_SEGMENTS 4
+#define HCZ_BATCH_WORKSPACE_BYTES 256
+typedef struct {
+  const hcz_plan* plan;
+  const hcz_model* model;     /* NULL: coder-only, as in hcz_compress */
+  hcz_codebook* codebook;
+  const hcz_params* params;
+  const void* hist;           /* device */
+  int32_t dtype;
+  int64_t H, hist_stride, row_stride;
+  hcz_compressed* out;
+  void* ws;                   /* device, hcz_compress_workspace bytes for this segment */
+  size_t ws_bytes;
+} hcz_batch_segment;
+hcz_status hcz_compress_batch(const hcz_batch_segment* seg, int32_t nseg, void* batch_ws, size_t batch_ws_bytes,
+                              hcz_stream_t stream);
+
 /* ---- output container and entropy coding (host) ------------------------------------
  * The buffer of one compressed batch in the order the paper gives (Section III, end of
  * Stage 5): a 44-byte header (scheme, sizes, byte boundaries, total size), the autoencoder

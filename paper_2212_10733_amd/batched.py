@@ -9,7 +9,9 @@ device wall clock as each histogram finishes, and hcz_segment_max turns those st
 per-subdomain completion times.  Allocation happens at construction; compress() only
 launches, so the whole batch (every grid size) can be recorded once into a HIP graph
 (capture) and rerun with a single launch (replay).  With a tuning cache, each grid's
-residual launch variant comes from the autotuner.
+residual launch variant comes from the autotuner.  With persistent=True the residual
+stage of every grid size runs as one persistent launch (hcz_compress_batch) that serves
+the histograms of all grids from one work list, instead of one launch per grid.
 """
 from __future__ import annotations
 
@@ -21,11 +23,14 @@ from . import hcz
 
 class SubdomainBatch:
     def __init__(self, plans: dict, models: dict, layout: list, bits: int = 8, sample_every: int = 16,
-                 device="cuda", tune_cache: str | None = None, **param_kw):
+                 device="cuda", tune_cache: str | None = None, persistent: bool = False, **param_kw):
         """plans / models: grid key -> Plan / Model (or None: the coder-only pipeline);
         layout: [(grid key, count, tau)] in batch order; tune_cache: a JSON file of the
-        autotuner (read, and extended on a miss) to choose each plan's launch variant."""
+        autotuner (read, and extended on a miss) to choose each plan's launch variant;
+        persistent: one residual launch for every grid (at most hcz.BATCH_MAX_SEGMENTS grid
+        sizes; the launch variants are then those of the batch kernel, not the tuner's)."""
         self.layout = list(layout)
+        self.persistent = persistent
         if tune_cache is not None:
             from . import autotune
             for k in plans:
@@ -49,6 +54,9 @@ class SubdomainBatch:
                 tau_buf=tau_buf, params=p,
                 cz=hcz.Compressor(plans[k], models.get(k), max(H, 1), p, bits=bits, device=device,
                                   timestamps=True))
+        if persistent and len(self.keys) > hcz.BATCH_MAX_SEGMENTS:
+            raise ValueError(f"a persistent batch holds at most {hcz.BATCH_MAX_SEGMENTS} grid sizes")
+        self.batch_ws = torch.zeros(hcz.BATCH_WORKSPACE_BYTES, dtype=torch.uint8, device=device)
         self.t0 = torch.zeros(1, dtype=torch.int64, device=device)
         self.done = {}
 
@@ -57,6 +65,18 @@ class SubdomainBatch:
         back in layout order.  Returns grid key -> Compressed (the compressor's buffers)."""
         out = {}
         hcz._check(hcz.LIB.hcz_timestamp(hcz._ptr(self.t0), hcz._stream()))
+        if self.persistent:
+            keys = [k for k in self.keys if self.groups[k]["H"] > 0]
+            for k in keys:
+                g = self.groups[k]
+                hcz._check(hcz.LIB.hcz_segment_tau(hcz._ptr(g["start"]), hcz._ptr(g["tau"]), len(g["index"]),
+                                                   g["H"], hcz._ptr(g["tau_buf"]), hcz._stream()))
+            comps = hcz.compress_batch([self.groups[k]["cz"] for k in keys], [inputs[k] for k in keys],
+                                       self.batch_ws)
+            for k, comp in zip(keys, comps):
+                self.done[k] = hcz.segment_max(self.groups[k]["start"], comp.t_done)
+                out[k] = comp
+            return out
         for k in self.keys:
             g = self.groups[k]
             if g["H"] == 0:

@@ -970,10 +970,9 @@ hcz_status hcz_decompress_workspace(const hcz_plan* plan, const hcz_model* model
   return HCZ_OK;
 }
 
-static hcz_status residual_impl(const hcz_plan* plan, const hcz_params* p, const void* hist,
-                                int32_t dtype, int64_t H, int64_t hs, int64_t rs, const float* fhat,
-                                const double* lam0, hcz_compressed* out, uint8_t* ws, const WsLayout& L,
-                                hipStream_t st) {
+static ResidualArgs residual_args(const hcz_plan* plan, const hcz_params* p, const void* hist, int32_t dtype,
+                                  int64_t H, int64_t hs, int64_t rs, const float* fhat, const double* lam0,
+                                  hcz_compressed* out, uint8_t* ws, const WsLayout& L) {
   const GridDev& G = plan->G;
   ResidualArgs a{};
   a.hist = hist;
@@ -1006,11 +1005,14 @@ static hcz_status residual_impl(const hcz_plan* plan, const hcz_params* p, const
   a.lam0 = lam0;
   a.analytic = p->warm_start == HCZ_WARM_ANALYTIC;
   a.t_done = (unsigned long long*)out->t_done;
+  return a;
+}
+
+// After the residual kernel: exclusive scan of the record sizes, compaction into the
+// stream, statistics.
+static hcz_status residual_finish(const hcz_plan* plan, const ResidualArgs& a, int64_t H, hcz_compressed* out,
+                                  uint8_t* ws, const WsLayout& L, hipStream_t st) {
   hcz_ctx* c = plan->ctx;
-  {
-    StageTimer tm(c, HCZ_STAGE_RESIDUAL, st);
-    HCZ_TRY(launch_residual(G, a, st), "residual launch");
-  }
   {
     StageTimer tm(c, HCZ_STAGE_SCAN, st);
     HCZ_TRY(launch_scan(a.sizes, out->res_offset, H, (uint64_t*)(ws + L.partial), st), "scan launch");
@@ -1026,6 +1028,18 @@ static hcz_status residual_impl(const hcz_plan* plan, const hcz_params* p, const
             "stats launch");
   }
   return HCZ_OK;
+}
+
+static hcz_status residual_impl(const hcz_plan* plan, const hcz_params* p, const void* hist,
+                                int32_t dtype, int64_t H, int64_t hs, int64_t rs, const float* fhat,
+                                const double* lam0, hcz_compressed* out, uint8_t* ws, const WsLayout& L,
+                                hipStream_t st) {
+  const ResidualArgs a = residual_args(plan, p, hist, dtype, H, hs, rs, fhat, lam0, out, ws, L);
+  {
+    StageTimer tm(plan->ctx, HCZ_STAGE_RESIDUAL, st);
+    HCZ_TRY(launch_residual(plan->G, a, st), "residual launch");
+  }
+  return residual_finish(plan, a, H, out, ws, L, st);
 }
 
 static hcz_status check_out(const hcz_compressed* out, int64_t H, bool codes) {
@@ -1100,10 +1114,11 @@ hcz_status hcz_compress_static(const hcz_plan* plan, const hcz_model* model, hcz
                        (size_t)HCZ_STATIC_SCRATCH_BYTES, stream);
 }
 
-static hcz_status compress_impl(const hcz_plan* plan, const hcz_model* model, hcz_codebook* cb,
-                                const hcz_params* params, const void* hist, int32_t dtype, int64_t H,
-                                int64_t hist_stride, int64_t row_stride, hcz_compressed* out, void* ws,
-                                size_t ws_bytes, hcz_stream_t stream) {
+// The argument checks of hcz_compress; on success *L_out is the workspace layout.
+static hcz_status compress_check(const hcz_plan* plan, const hcz_model* model, hcz_codebook* cb,
+                                 const hcz_params* params, const void* hist, int32_t dtype, int64_t H,
+                                 int64_t hist_stride, int64_t row_stride, hcz_compressed* out, void* ws,
+                                 size_t ws_bytes, WsLayout* L_out) {
   if (!plan) return fail(HCZ_EINVAL, "plan is NULL");
   if (model && model->plan->G.N != plan->G.N) return fail(HCZ_EINVAL, "model was loaded for another grid");
   hcz_status s;
@@ -1115,12 +1130,21 @@ static hcz_status compress_impl(const hcz_plan* plan, const hcz_model* model, hc
   const bool fit = model && params->fit_codebook;
   const WsLayout L = ws_layout(plan->G, model != nullptr, H, dtype, fit, params->sample_every);
   if (!ws || ws_bytes < L.total) return fail(HCZ_EWORKSPACE, "workspace %zu < %zu", ws_bytes, L.total);
-  if ((s = set_device(plan->ctx))) return s;
-  hipStream_t st = (hipStream_t)stream;
-  uint8_t* w = (uint8_t*)ws;
+  *L_out = L;
+  return HCZ_OK;
+}
+
+// The model stages of hcz_compress (encode, codebook fit, quantise, decode, warm start) on
+// checked arguments, the device already current: *fhat and *lam0 are what the residual
+// stage reads.
+static hcz_status compress_model_stages(const hcz_plan* plan, const hcz_model* model, hcz_codebook* cb,
+                                        const hcz_params* params, const void* hist, int32_t dtype, int64_t H,
+                                        int64_t hist_stride, int64_t row_stride, hcz_compressed* out,
+                                        uint8_t* w, const WsLayout& L, hipStream_t st, const float** fhat_out,
+                                        const double** lam0_out) {
+  const bool fit = model && params->fit_codebook;
   const float* fhat = nullptr;
   hcz_ctx* c = plan->ctx;
-  prof_begin(c);
   const double* lam0 = nullptr;
   if (model && H > 0) {
     float* z = (float*)(w + L.z);
@@ -1150,7 +1174,84 @@ static hcz_status compress_impl(const hcz_plan* plan, const hcz_model* model, hc
                                (double*)(w + L.lam0), st), "warm start launch");
     }
   }
-  return residual_impl(plan, params, hist, dtype, H, hist_stride, row_stride, fhat, lam0, out, w, L, st);
+  *fhat_out = fhat;
+  *lam0_out = lam0;
+  return HCZ_OK;
+}
+
+static hcz_status compress_impl(const hcz_plan* plan, const hcz_model* model, hcz_codebook* cb,
+                                const hcz_params* params, const void* hist, int32_t dtype, int64_t H,
+                                int64_t hist_stride, int64_t row_stride, hcz_compressed* out, void* ws,
+                                size_t ws_bytes, hcz_stream_t stream) {
+  hipStream_t st = (hipStream_t)stream;
+  WsLayout L{};
+  hcz_status s = compress_check(plan, model, cb, params, hist, dtype, H, hist_stride, row_stride, out, ws, ws_bytes, &L);
+  if (s || (s = set_device(plan->ctx))) return s;
+  prof_begin(plan->ctx);
+  const float* fhat = nullptr;
+  const double* lam0 = nullptr;
+  if ((s = compress_model_stages(plan, model, cb, params, hist, dtype, H, hist_stride, row_stride, out, (uint8_t*)ws,
+                                 L, st, &fhat, &lam0)))
+    return s;
+  return residual_impl(plan, params, hist, dtype, H, hist_stride, row_stride, fhat, lam0, out, (uint8_t*)ws, L, st);
+}
+
+hcz_status hcz_compress_batch(const hcz_batch_segment* seg, int32_t nseg, void* batch_ws, size_t batch_ws_bytes,
+                              hcz_stream_t stream) {
+  if (!seg) return fail(HCZ_EINVAL, "seg is NULL");
+  if (nseg < 1 || nseg > HCZ_BATCH_MAX_SEGMENTS) return fail(HCZ_EINVAL, "nseg %d not in [1, %d]", nseg, HCZ_BATCH_MAX_SEGMENTS);
+  if (!batch_ws || batch_ws_bytes < HCZ_BATCH_WORKSPACE_BYTES)
+    return fail(HCZ_EWORKSPACE, "batch workspace %zu < %d", batch_ws_bytes, HCZ_BATCH_WORKSPACE_BYTES);
+  static_assert(kBatchSeg == HCZ_BATCH_MAX_SEGMENTS, "segment count of the batch launch");
+  WsLayout L[kBatchSeg];
+  BatchArgs B{};
+  hcz_status s;
+  // every check before the first launch
+  for (int k = 0; k < nseg; ++k) {
+    const hcz_batch_segment& q = seg[k];
+    if ((s = compress_check(q.plan, q.model, q.codebook, q.params, q.hist, q.dtype, q.H, q.hist_stride, q.row_stride,
+                            q.out, q.ws, q.ws_bytes, &L[k])))
+      return s;
+    const GridDev& G = q.plan->G;
+    if (q.plan->ctx != seg[0].plan->ctx) return fail(HCZ_EINVAL, "segment %d: plan of another context", k);
+    if (q.dtype != seg[0].dtype) return fail(HCZ_EINVAL, "segment %d: dtype differs from segment 0", k);
+    if (G.uniform_vol != seg[0].plan->G.uniform_vol)
+      return fail(HCZ_EUNSUPPORTED, "segment %d: uniform and non-uniform cell volumes in one batch", k);
+    if (q.params->kl) return fail(HCZ_EUNSUPPORTED, "segment %d: the KL reading is not batched", k);
+    if (!wave_path(G) && !team_path(G, 4))
+      return fail(HCZ_EUNSUPPORTED, "segment %d: grid %d x %d fits neither one wave nor a team of four", k, G.n_par,
+                  G.n_perp);
+  }
+  hcz_ctx* c = seg[0].plan->ctx;
+  if ((s = set_device(c))) return s;
+  hipStream_t st = (hipStream_t)stream;
+  prof_begin(c);
+  ProfSet* prof = c->cur;
+  c->cur = nullptr;            // only the batch's residual launch is timed
+  for (int k = 0; k < nseg; ++k) {
+    const hcz_batch_segment& q = seg[k];
+    const float* fhat = nullptr;
+    const double* lam0 = nullptr;
+    uint8_t* w = (uint8_t*)q.ws;
+    if ((s = compress_model_stages(q.plan, q.model, q.codebook, q.params, q.hist, q.dtype, q.H, q.hist_stride,
+                                   q.row_stride, q.out, w, L[k], st, &fhat, &lam0)))
+      return s;
+    BatchSeg& S = B.s[k];
+    S.G = q.plan->G;
+    S.a = residual_args(q.plan, q.params, q.hist, q.dtype, q.H, q.hist_stride, q.row_stride, fhat, lam0, q.out, w, L[k]);
+    S.kind = wave_path(S.G) ? kBatchWave : kBatchTeam4;
+  }
+  B.nseg = nseg;
+  B.counter = (unsigned long long*)batch_ws;
+  {
+    c->cur = prof;
+    StageTimer tm(c, HCZ_STAGE_RESIDUAL, st);
+    HCZ_TRY(launch_residual_batch(B, seg[0].dtype, seg[0].plan->G.uniform_vol != 0, 0, st), "batch residual launch");
+  }
+  c->cur = nullptr;
+  for (int k = 0; k < nseg; ++k)
+    if ((s = residual_finish(seg[k].plan, B.s[k].a, seg[k].H, seg[k].out, (uint8_t*)seg[k].ws, L[k], st))) return s;
+  return HCZ_OK;
 }
 
 hcz_status hcz_decompress(const hcz_plan* plan, const hcz_model* model, const hcz_codebook* cb,

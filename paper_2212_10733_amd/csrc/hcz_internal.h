@@ -150,6 +150,22 @@ struct ResidualArgs {
   unsigned long long* t_done;  // [H] wall clock at the end of each histogram, or null
 };
 
+// One grid's share of the persistent batch launch of the residual stage.
+constexpr int kBatchSeg = 4;                   // grids per batch launch
+enum { kBatchWave = 0, kBatchTeam4 = 1 };
+struct BatchSeg {
+  GridDev G;
+  ResidualArgs a;
+  int kind;                    // kBatchWave (4 histograms per item), kBatchTeam4 (1)
+  long long item0;             // first work item of the segment in the batch's list
+};
+struct BatchArgs {
+  BatchSeg s[kBatchSeg];
+  int nseg;
+  long long nitems;
+  unsigned long long* counter; // the work counter (device), zeroed by the launch itself
+};
+
 struct DecompressArgs {
   const uint8_t* flags;
   const void* lambda;          // FP64, or FP32 when lambda_fp32
@@ -423,6 +439,9 @@ hipError_t launch_conv_encode(const ModelDev& M, const void* hist, int dtype, lo
 hipError_t launch_conv_decode(const ModelDev& M, const uint8_t* codes, const float* centroids, int bits,
                               long long H, float* fhat, hipStream_t st);
 hipError_t launch_residual_t(const GridDev& G, const ResidualArgs& a, int W, hipStream_t st);
+// Fills B's item0 and nitems from the segments' kinds and H; grid <= 0: as many workgroups
+// as stay resident on the device.
+hipError_t launch_residual_batch(BatchArgs B, int dtype, bool uvol, int grid, hipStream_t st);
 bool team_path(const GridDev& G, int W);
 hipError_t launch_cv_fwd(const float* in, int C, int n, int relu_in, const float* w, const float* bias, float* out,
                          int O, int m, long long B, hipStream_t st, int bf);

@@ -392,18 +392,15 @@ __device__ __forceinline__ int newton_t(const GridDev& G, Team<W>& T, const Task
 template <int W>
 constexpr int team_slots() { return W == 2 ? kTeamSlots2 : kTeamSlots4; }
 
+// Histogram h (< a.H) on the first 64 W threads of the workgroup, the team's LDS set up.
 template <typename TIn, bool UVOL, int W>
-__global__ __launch_bounds__(64 * W, 2) void k_residual_t(GridDev G, ResidualArgs a) {
+__device__ __forceinline__ void residual_t_hist(const GridDev& G, const ResidualArgs& a, Team<W>& T, long long h) {
   constexpr int NS = team_slots<W>();
   constexpr int NT = Team<W>::NT;
-  extern __shared__ double smem[];
   const int N = G.N;
   const int t = threadIdx.x;
-  const long long h = blockIdx.x;
-  Team<W> T = setup_team<W>(G, smem);
   const TeamTabs tb = team_tabs<W>(G);
   const TaskSplit S = task_split<W>(G);
-  T.sync();
   const TIn* f = (const TIn*)a.hist + h * a.hs;
   const float* fhp = a.fhat ? a.fhat + h * (long long)N : nullptr;
   uint32_t* words = (uint32_t*)T.yb;     // payload words borrow the buffer before the last recomposition
@@ -697,6 +694,14 @@ __global__ __launch_bounds__(64 * W, 2) void k_residual_t(GridDev G, ResidualArg
     __syncthreads();            // the histogram is done when every wave of its team is
     if (t == 0) a.t_done[h] = wall_clock64();
   }
+}
+
+template <typename TIn, bool UVOL, int W>
+__global__ __launch_bounds__(64 * W, 2) void k_residual_t(GridDev G, ResidualArgs a) {
+  extern __shared__ double smem[];
+  Team<W> T = setup_team<W>(G, smem);
+  T.sync();
+  residual_t_hist<TIn, UVOL, W>(G, a, T, (long long)blockIdx.x);
 }
 
 // ---- launcher ---------------------------------------------------------------------------

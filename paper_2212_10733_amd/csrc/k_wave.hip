@@ -503,20 +503,14 @@ __device__ __forceinline__ void pre_load(PreRows<TIn, SH>& P, const GridDev& G, 
   }
 }
 
-// One wave per histogram.  With a fixed shape the wave's column of the histogram is
-// loaded before the workgroup stages its tables, so both latencies overlap.
+// Histogram h (< a.H) on this wave, with the grid's tables staged in LDS and, for a fixed
+// shape, the wave's column already loaded into P.
 template <typename TIn, bool UVOL, class SH>
-__global__ __launch_bounds__(256, 2) void k_residual_w(GridDev G, ResidualArgs a) {
+__device__ __forceinline__ void residual_w_hist(const GridDev& G, const ResidualArgs& a, const WaveLds& L,
+                                                long long h, const PreRows<TIn, SH>& P) {
   constexpr int NS = SH::NS;
-  extern __shared__ double smem[];
   const int N = G.N;
-  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const long long h = (long long)blockIdx.x * kWPB + wv;
-  PreRows<TIn, SH> P;
-  if constexpr (SH::fixed) pre_load(P, G, a, h);
-  const WaveLds L = setup_lds(G, smem, wv);
-  __syncthreads();
-  if (h >= a.H) return;
+  const int lane = threadIdx.x & 63;
   const TIn* f = (const TIn*)a.hist + h * a.hs;
   const float* fhp = a.fhat ? a.fhat + h * (long long)N : nullptr;
   uint32_t* words = (uint32_t*)L.yb;     // payload words borrow the buffer before the last recomposition
@@ -831,6 +825,21 @@ __global__ __launch_bounds__(256, 2) void k_residual_w(GridDev G, ResidualArgs a
     a.iters[h] = (uint16_t)min(total_upd, 65535);
     if (a.t_done) a.t_done[h] = wall_clock64();
   }
+}
+
+// One wave per histogram.  With a fixed shape the wave's column of the histogram is
+// loaded before the workgroup stages its tables, so both latencies overlap.
+template <typename TIn, bool UVOL, class SH>
+__global__ __launch_bounds__(256, 2) void k_residual_w(GridDev G, ResidualArgs a) {
+  extern __shared__ double smem[];
+  const int wv = threadIdx.x >> 6;
+  const long long h = (long long)blockIdx.x * kWPB + wv;
+  PreRows<TIn, SH> P;
+  if constexpr (SH::fixed) pre_load(P, G, a, h);
+  const WaveLds L = setup_lds(G, smem, wv);
+  __syncthreads();
+  if (h >= a.H) return;
+  residual_w_hist<TIn, UVOL, SH>(G, a, L, h, P);
 }
 
 // ---- decompression ----------------------------------------------------------------------

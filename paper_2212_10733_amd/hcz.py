@@ -103,6 +103,17 @@ class CompressedC(C.Structure):
                 ("t_done", C.c_void_p)]
 
 
+class BatchSegmentC(C.Structure):
+    _fields_ = [("plan", C.c_void_p), ("model", C.c_void_p), ("codebook", C.POINTER(Codebook)),
+                ("params", C.POINTER(Params)), ("hist", C.c_void_p), ("dtype", C.c_int32), ("H", C.c_int64),
+                ("hist_stride", C.c_int64), ("row_stride", C.c_int64), ("out", C.POINTER(CompressedC)),
+                ("ws", C.c_void_p), ("ws_bytes", C.c_size_t)]
+
+
+BATCH_MAX_SEGMENTS = 4
+BATCH_WORKSPACE_BYTES = 256
+
+
 def _load() -> C.CDLL:
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2212_10733_amd.build` "
@@ -133,6 +144,7 @@ def _load() -> C.CDLL:
                          C.POINTER(CompressedC), vp, sz, vp],
         "hcz_compress_static": [vp, vp, C.POINTER(Codebook), C.POINTER(Params), vp, i32, i64, i64, i64,
                                 C.POINTER(CompressedC), vp],
+        "hcz_compress_batch": [C.POINTER(BatchSegmentC), i32, vp, sz, vp],
         "hcz_decompress": [vp, vp, C.POINTER(Codebook), C.POINTER(CompressedC), i32, i64, vp, i32, vp, sz, vp],
         "hcz_stats_read": [vp, C.POINTER(Stats), vp],
         "hcz_ae_param_count": [i32, C.POINTER(i64)],
@@ -199,7 +211,7 @@ EXPORTS = ["hcz_create", "hcz_destroy", "hcz_last_error", "hcz_version", "hcz_pl
            "hcz_container_read_info", "hcz_container_unpack", "hcz_rans_bound", "hcz_rans_encode",
            "hcz_rans_decode", "hcz_conv_ae_param_count", "hcz_conv_ae_saved_bytes", "hcz_conv_ae_forward",
            "hcz_conv_ae_backward", "hcz_column_stats_workspace", "hcz_column_stats", "hcz_column_normalize",
-           "hcz_compress_static"]
+           "hcz_compress_static", "hcz_compress_batch"]
 
 STAGES = ["encode", "codebook", "quantize", "decode", "residual", "scan", "compact", "stats", "decompress",
           "warmstart"]
@@ -229,6 +241,8 @@ def _dtype_code(t: torch.Tensor) -> int:
 def _strides(hist: torch.Tensor):
     if hist.dim() != 3:
         raise ValueError("hist must be (H, n_perp, n_par)")
+    if hist.numel() == 0:                 # an empty batch has no layout of its own
+        return hist.shape[0], hist.shape[1] * hist.shape[2], hist.shape[2]
     if hist.stride(2) != 1:
         raise ValueError("the v_par axis must be contiguous")
     return hist.shape[0], hist.stride(0), hist.stride(1)
@@ -597,6 +611,35 @@ class Compressor:
                                   C.byref(cs), F32 if in_dtype == torch.float32 else F64, H, _ptr(out),
                                   _dtype_code(out), _ptr(self.dws), self.dws.numel(), _stream()))
         return out
+
+
+def compress_batch(compressors: list, hists: list, batch_ws: torch.Tensor | None = None) -> list:
+    """hcz_compress_batch: compressors[k] compresses hists[k] (grids may differ), with one
+    persistent launch of the residual stage for all of them; returns each compressor's
+    Compressed.  batch_ws: a device buffer of BATCH_WORKSPACE_BYTES (allocated here if None)."""
+    if len(compressors) != len(hists):
+        raise ValueError("one input per compressor")
+    n = len(compressors)
+    segs = (BatchSegmentC * max(n, 1))()
+    keep = []
+    for k, (cz, hist) in enumerate(zip(compressors, hists)):
+        H, hs, rs = _strides(hist)
+        if H > cz.H:
+            raise ValueError("batch larger than the compressor was sized for")
+        if hist.dtype == torch.float64 and cz.in_dtype != torch.float64:
+            raise ValueError("FP64 input needs a compressor built with in_dtype=torch.float64")
+        cz.out.in_dtype = hist.dtype
+        cb = Codebook(cz.bits, cz.centroids.data_ptr())
+        cs = cz.out.cstruct()
+        keep += [cb, cs]
+        segs[k] = BatchSegmentC(cz.plan.h, None if cz.model is None else cz.model.h, C.pointer(cb),
+                                C.pointer(cz.p), hist.data_ptr(), _dtype_code(hist), H, hs, rs, C.pointer(cs),
+                                cz.ws.data_ptr(), cz.ws.numel())
+    if batch_ws is None:
+        dev = hists[0].device if hists else torch.device("cuda")
+        batch_ws = torch.empty(BATCH_WORKSPACE_BYTES, dtype=torch.uint8, device=dev)
+    _check(LIB.hcz_compress_batch(segs, n, _ptr(batch_ws), batch_ws.numel(), _stream()))
+    return [cz.out for cz in compressors]
 
 
 def norm_stats(plan: Plan, hist: torch.Tensor):

@@ -130,12 +130,14 @@ def _snapshot(comps):
     return snap
 
 
-def test_subdomain_batch_graph_replay(H, ctx):
+@pytest.mark.parametrize("persistent", [False, True])
+def test_subdomain_batch_graph_replay(H, ctx, persistent):
     """The whole batch (three grid sizes, a model on one, per-subdomain bounds) recorded
-    into one HIP graph: four replays, with eager work and synchronisations between them,
-    each give the eager call's outputs bit for bit, and the completion stamps move on."""
+    into one HIP graph, per grid or as one persistent residual launch: four replays, with
+    eager work and synchronisations between them, each give the eager call's outputs bit
+    for bit, and the completion stamps move on."""
     from paper_2212_10733_amd import batched
-    say("batch graph replay")
+    say("batch graph replay", persistent)
     layout = [(n, c, t) for n, c, t in synth.subdomains(18, seed=52, count_range=(20, 400)) if n != 65]
     plans = {n: H.Plan(ctx, n, n) for n in (33, 39, 49)}
     inputs = {}
@@ -145,7 +147,7 @@ def test_subdomain_batch_graph_replay(H, ctx):
     F39 = inputs[39].cpu().numpy().astype(np.float64)
     mu, sd = oracle.ae.norm_stats(F39)
     models = {39: H.Model(plans[39], synth.dense_ae_weights(1521), mu.astype(np.float32), sd.astype(np.float32))}
-    sb = batched.SubdomainBatch(plans, models, layout)
+    sb = batched.SubdomainBatch(plans, models, layout, persistent=persistent)
     eager = _snapshot(sb.compress(inputs))
     t_eager = sb.completion_seconds()
     outs = sb.capture(inputs)
@@ -208,3 +210,86 @@ def test_launch_variants_and_autotuner(H, ctx, tmp_path):
     assert v == autotune.best(data[k]["ms"])
     plan2 = H.Plan(ctx, 39, 39)
     assert autotune.apply(plan2, cache) == v         # served from the cache
+
+
+def _batch_case(H, ctx, n_perp, n_par, vol, Hn, seed, model, in_dtype, variant, tau_hist=None):
+    """Two compressors of one grid (one for the batch call, one for hcz_compress with the
+    variant the batch kernel's body corresponds to) and the input."""
+    g = grid.make_grid(n_par, n_perp, vol=vol)
+    plan = H.Plan(ctx, n_par, n_perp, vol=None if vol is None else g.vol)
+    plan.set_variant(variant)
+    F = synth.histograms(max(Hn, 1), n_par, n_perp, seed=seed, dtype=np.float32)[:Hn].astype(in_dtype)
+    m = None
+    if model:
+        mu, sd = oracle.ae.norm_stats(F.astype(np.float64))
+        m = H.Model(plan, synth.dense_ae_weights(n_par * n_perp), mu.astype(np.float32), sd.astype(np.float32))
+    tdt = torch.float64 if in_dtype == np.float64 else torch.float32
+    kw = dict(tau=1e-3, fit_codebook=model, sample_every=4)
+    if tau_hist is not None:
+        kw["tau_hist"] = torch.from_numpy(tau_hist).cuda()
+    czb = H.Compressor(plan, m, max(Hn, 1), H.params(**kw), in_dtype=tdt, timestamps=True)
+    czr = H.Compressor(plan, m, max(Hn, 1), H.params(**kw), in_dtype=tdt)
+    return czb, czr, torch.from_numpy(np.ascontiguousarray(F)).cuda()
+
+
+def _same_compressed(a, b, what):
+    for name in ("flags", "codes", "offsets"):
+        assert torch.equal(getattr(a, name), getattr(b, name)), (what, name)
+    assert a.stream_bytes() == b.stream_bytes(), what
+    # the same arithmetic in the same order: the multipliers bit for bit
+    assert torch.equal(a.lam.view(torch.int64) if a.lam.dtype == torch.float64 else a.lam.view(torch.int32),
+                       b.lam.view(torch.int64) if b.lam.dtype == torch.float64 else b.lam.view(torch.int32)), what
+    assert a.stats() == b.stats(), what
+
+
+@pytest.mark.parametrize("vol", [None, "jacobian"])
+def test_persistent_batch_matches_per_grid(H, ctx, vol):
+    """hcz_compress_batch over four grid sizes (two on the one-wave body, two on the team of
+    four waves; models on two; per-histogram bounds with NaN and negative entries on one)
+    gives every segment hcz_compress's outputs byte for byte; segment sizes ragged against
+    the four histograms of a work item, one of a single histogram; then FP64 input with an
+    empty segment and a non-square grid."""
+    rng = np.random.default_rng(70)
+    th = rng.uniform(1e-4, 1e-2, 517)
+    th[[3, 100]] = np.nan
+    th[7] = -1.0
+    cases = [((33, 33), 517, False, "wave", th), ((39, 39), 1001, True, "wave", None),
+             ((49, 49), 203, True, "team4", None), ((65, 65), 1, False, "team4", None)]
+    for in_dtype, cs in ((np.float32, cases),
+                         (np.float64, [((39, 39), 0, False, "wave", None), ((37, 33), 130, False, "wave", None),
+                                       ((65, 65), 77, False, "team4", None)])):
+        say("persistent batch", vol, in_dtype.__name__, [(c[0], c[1]) for c in cs])
+        made = [_batch_case(H, ctx, s[0], s[1], vol, n, 71 + k, m, in_dtype, v, t)
+                for k, (s, n, m, v, t) in enumerate(cs)]
+        got = H.compress_batch([c[0] for c in made], [c[2] for c in made])
+        for (czb, czr, F), (s, n, _, v, _), comp in zip(made, cs, got):
+            ref = czr.compress(F)
+            torch.cuda.synchronize()
+            _same_compressed(comp, ref, (s, n, v))
+            if n:
+                assert bool((comp.t_done[:n] > 0).all())
+
+
+def test_persistent_batch_errors(H, ctx):
+    """Requests the batch refuses before any launch."""
+    say("persistent batch errors")
+    cz, _, F = _batch_case(H, ctx, 39, 39, None, 8, 80, False, np.float32, "auto")
+    czj, _, Fj = _batch_case(H, ctx, 39, 39, "jacobian", 8, 81, False, np.float32, "auto")
+    cz64, _, F64 = _batch_case(H, ctx, 33, 33, None, 8, 82, False, np.float64, "auto")
+    kl = H.Compressor(cz.plan, None, 8, H.params(tau=1e-3, kl=1))
+    bad = [([cz] * 5, [F] * 5), ([cz, czj], [F, Fj]), ([cz64, cz64], [F64, F64.float()]), ([cz, kl], [F, F])]
+    # a grid only the workgroup kernel serves
+    for n_perp, n_par in ((67, 67), (48, 96), (36, 128)):
+        big = H.Plan(ctx, n_par, n_perp)
+        if "wave" not in big.variants() and "team4" not in big.variants():
+            czbig = H.Compressor(big, None, 4, H.params(tau=1e-3))
+            Fbig = torch.from_numpy(synth.histograms(4, n_par, n_perp, seed=83, dtype=np.float32)).cuda()
+            bad.append(([cz, czbig], [F, Fbig]))
+            break
+    for czs, hs in bad:
+        with pytest.raises(H.HczError):
+            H.compress_batch(czs, hs)
+    with pytest.raises(H.HczError):
+        H.compress_batch([cz], [F], torch.zeros(64, dtype=torch.uint8, device="cuda"))
+    # nothing launched: the outputs are untouched
+    assert int(cz.out.offsets[-1].item()) == 0
