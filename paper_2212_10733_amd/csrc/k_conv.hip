@@ -37,11 +37,15 @@ __device__ __forceinline__ f32x16 mfma_bf16c(bf16x8 a, bf16x8 b, f32x16 c) {
 }
 
 // A workgroup loops over histograms (h = blockIdx.x, + gridDim.x, ...) with conv2's
-// weights staged once in LDS; 78 KB of LDS lets two share a CU.
+// weights staged once in LDS; 77 KB of LDS lets two share a CU.  The input is staged with
+// a zero border, so every tap of conv1 reads a value: a padding tap adds a zero product,
+// which leaves the chain's value as skipping it would (only the sign of an exact-zero
+// sum can differ, and ReLU makes it a zero either way).  Each histogram's input is loaded while the
+// previous one is convolved.
 template <typename TIn>
 __global__ __launch_bounds__(256, 2) void k_conv_enc(ModelDev M, const TIn* hist, long long n, long long hs,
                                                      long long rs, float* h2out) {
-  __shared__ float xs[39 * 39];
+  __shared__ float xs[41 * 41];                                        // x at (iy + 1, ix + 1)
   __shared__ __attribute__((aligned(16))) __bf16 h1p[21 * 21 * kCP1];   // later: h2 (6400 floats)
   __shared__ __attribute__((aligned(16))) __bf16 w2s[9 * 64 * 32];      // conv2 weights [tap][out][in]
   float* h2s = (float*)h1p;
@@ -51,35 +55,51 @@ __global__ __launch_bounds__(256, 2) void k_conv_enc(ModelDev M, const TIn* hist
     const bf16x8* src = (const bf16x8*)M.c2w;
     for (int q = t; q < 9 * 64 * 32 / 8; q += 256) ((bf16x8*)w2s)[q] = src[q];
   }
-  // conv1's weights: thread -> channels 4 cg .. 4 cg + 3
-  const int cg = t & 7;
-  float wv1[4][9], bv1[4];
-#pragma unroll
-  for (int c = 0; c < 4; ++c) {
-#pragma unroll
-    for (int k = 0; k < 9; ++k) wv1[c][k] = M.c1w[(4 * cg + c) * 9 + k];
-    bv1[c] = M.c1b[4 * cg + c];
+  for (int q = t; q < 41 * 41; q += 256) {
+    const int y = q / 41, x = q - 41 * y;
+    if (y == 0 || y == 40 || x == 0 || x == 40) xs[q] = 0.0f;
   }
-  for (long long h = blockIdx.x; h < n; h += gridDim.x) {
-  const TIn* f = hist + h * hs;
-  __syncthreads();          // the previous histogram is done with xs and h2s
-  {
-    // all loads first (6 per thread), then the stores: one memory round trip
-    float fv[6], mv[6], rv[6];
+  // conv1's weights: thread -> channels 8 cg .. 8 cg + 7
+  const int cg = t & 3;
+  float wv1[8][9], bv1[8];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) wv1[c][k] = M.c1w[(8 * cg + c) * 9 + k];
+    bv1[c] = M.c1b[8 * cg + c];
+  }
+  // the thread's six input cells: z-score factors and padded LDS index
+  float mv[6], rv[6];
+  int xo[6];
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    const int e = min(t + 256 * q, 1520);
+    const int j = e / 39, i = e - 39 * j;
+    mv[q] = M.mu[e];
+    rv[q] = M.rsd[e];
+    xo[q] = (j + 1) * 41 + i + 1;
+  }
+  TIn fv[6];
+  auto load_f = [&](long long hh) {
+    const TIn* f = hist + hh * hs;
 #pragma unroll
     for (int q = 0; q < 6; ++q) {
       const int e = min(t + 256 * q, 1520);
       const int j = e / 39, i = e - 39 * j;
-      fv[q] = (float)f[j * rs + i];
-      mv[q] = M.mu[e];
-      rv[q] = M.rsd[e];
+      fv[q] = f[j * rs + i];
     }
+  };
+  if ((long long)blockIdx.x < n) load_f(blockIdx.x);
+  for (long long h = blockIdx.x; h < n; h += gridDim.x) {
+  __syncthreads();          // the previous histogram is done with xs and h2s
 #pragma unroll
-    for (int q = 0; q < 6; ++q) {
-      const int e = t + 256 * q;
-      if (e < 1521) xs[e] = ((isfinite(fv[q]) ? fv[q] : 0.0f) - mv[q]) * rv[q];
+  for (int q = 0; q < 6; ++q) {
+    if (t + 256 * q < 1521) {
+      const float v = (float)fv[q];
+      xs[xo[q]] = ((isfinite(v) ? v : 0.0f) - mv[q]) * rv[q];
     }
   }
+  if (h + gridDim.x < n) load_f(h + gridDim.x);
   // zero border of the conv1 output (row 0 and column 0 of the padded layout)
   for (int q = t; q < 41 * 32; q += 256) {
     const int cell = q >> 5, c = q & 31;
@@ -87,29 +107,27 @@ __global__ __launch_bounds__(256, 2) void k_conv_enc(ModelDev M, const TIn* hist
     h1p[(cy * 21 + cx) * kCP1 + c] = (__bf16)0.0f;
   }
   __syncthreads();
-  // conv1: thread -> channels 4 cg .. 4 cg + 3, positions p = t / 8 + 32 q; each input value
-  // read once for the four channels, every channel's chain in the same tap order
-  {
-    for (int p = t >> 3; p < 400; p += 32) {
-      const int oy = p / 20, ox = p - 20 * oy;
-      float s[4] = {bv1[0], bv1[1], bv1[2], bv1[3]};
+  // conv1: thread -> channels 8 cg .. 8 cg + 7 of positions p = t / 4 + 64 q; the nine
+  // taps are read first, then every channel's chain runs over them in row-major order
+  for (int p = t >> 2; p < 400; p += 64) {
+    const int oy = p / 20, ox = p - 20 * oy;
+    const float* xb = &xs[2 * oy * 41 + 2 * ox];
+    float xv[9];
 #pragma unroll
-      for (int ky = 0; ky < 3; ++ky) {
-        const int iy = 2 * oy - 1 + ky;
-        if (iy < 0 || iy >= 39) continue;
+    for (int ky = 0; ky < 3; ++ky)
 #pragma unroll
-        for (int kx = 0; kx < 3; ++kx) {
-          const int ix = 2 * ox - 1 + kx;
-          if (ix < 0 || ix >= 39) continue;
-          const float xv = xs[iy * 39 + ix];
+      for (int kx = 0; kx < 3; ++kx) xv[3 * ky + kx] = xb[ky * 41 + kx];
+    float s[8];
 #pragma unroll
-          for (int c = 0; c < 4; ++c) s[c] = fmaf(xv, wv1[c][ky * 3 + kx], s[c]);
-        }
-      }
-      __bf16* dst = &h1p[((oy + 1) * 21 + (ox + 1)) * kCP1 + 4 * cg];
+    for (int c = 0; c < 8; ++c) s[c] = bv1[c];
 #pragma unroll
-      for (int c = 0; c < 4; ++c) dst[c] = (__bf16)fmaxf(s[c], 0.0f);
-    }
+    for (int k = 0; k < 9; ++k)
+#pragma unroll
+      for (int c = 0; c < 8; ++c) s[c] = fmaf(xv[k], wv1[c][k], s[c]);
+    bf16x8 o;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) o[c] = (__bf16)fmaxf(s[c], 0.0f);
+    *(bf16x8*)&h1p[((oy + 1) * 21 + (ox + 1)) * kCP1 + 8 * cg] = o;
   }
   __syncthreads();
   // conv2 on matrix cores: wave w owns output positions 32 w .. 32 w + 31

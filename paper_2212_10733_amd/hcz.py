@@ -266,7 +266,7 @@ class Context:
         return {s: (ms[i], calls[i]) for i, s in enumerate(STAGES)}
 
     def __del__(self):
-        if getattr(self, "h", None):
+        if getattr(self, "h", None) and LIB is not None:   # LIB is None during interpreter shutdown
             LIB.hcz_destroy(self.h)
             self.h = None
 
@@ -311,7 +311,7 @@ class Plan:
         self.variant = name
 
     def __del__(self):
-        if getattr(self, "h", None):
+        if getattr(self, "h", None) and LIB is not None:   # LIB is None during interpreter shutdown
             LIB.hcz_plan_destroy(self.h)
             self.h = None
 
@@ -367,7 +367,7 @@ class Model:
         self.latent = LATENT
 
     def __del__(self):
-        if getattr(self, "h", None):
+        if getattr(self, "h", None) and LIB is not None:   # LIB is None during interpreter shutdown
             LIB.hcz_model_free(self.h)
             self.h = None
 
@@ -420,7 +420,7 @@ class Mlp:
         return out
 
     def __del__(self):
-        if getattr(self, "h", None):
+        if getattr(self, "h", None) and LIB is not None:   # LIB is None during interpreter shutdown
             LIB.hcz_mlp_free(self.h)
             self.h = None
 
