@@ -254,9 +254,70 @@ __global__ __launch_bounds__(256) void k_conv_hidden(ModelDev M, const uint8_t* 
   }
 }
 
-// A workgroup loops over histograms like the encoder.  The transposed conv1 weights of a
-// parity class (up to 4 taps x 4 channel steps per lane) are loaded together before the
-// class's matrix-core steps.
+// Lane l's float x from its quad partner: CTRL 0xB1 swaps lanes 0 <-> 1 and 2 <-> 3 of
+// every quad, 0x4E lanes 0 <-> 2 and 1 <-> 3.
+template <int CTRL>
+__device__ __forceinline__ float quad_swap(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
+}
+
+// Transposed conv1, parity class CLS = (cy, cx) = (CLS / 2, CLS % 2): an output cell of
+// that parity receives (1 + cy) (1 + cx) taps; even output -> k = 1 from input p, odd
+// output -> k = 0 from p + 1 and k = 2 from p.  Tap ty, tx of the class is ky = 1 (cy = 0)
+// or ky = 0, 2 (ty = 0, 1), likewise kx.
+template <int CLS>
+__device__ __forceinline__ void tconv1_weights(const __bf16* T1, int li, int kh, int zo,
+                                               bf16x8 (&b)[(1 + CLS / 2) * (1 + CLS % 2)][4]) {
+  constexpr int cy = CLS >> 1, cx = CLS & 1;
+#pragma unroll
+  for (int ty = 0; ty < 1 + cy; ++ty)
+#pragma unroll
+    for (int tx = 0; tx < 1 + cx; ++tx) {
+      const int ky = cy ? (ty == 0 ? 0 : 2) : 1, kx = cx ? (tx == 0 ? 0 : 2) : 1;
+#pragma unroll
+      for (int c4 = 0; c4 < 4; ++c4)
+        b[ty * (1 + cx) + tx][c4] =
+            *(const bf16x8*)(T1 + ((long long)((ky * 3 + kx) * 32 + li)) * 64 + 16 * c4 + 8 * kh + zo);
+    }
+}
+
+// The class's matrix-core steps for the wave's 32 positions (position q = (py, px) on
+// this lane's row of the A operand), then ReLU(acc + b) to h3s [y][x][channel].
+template <int CLS>
+__device__ __forceinline__ void tconv1_class(const __bf16* hdp, float* h3s,
+                                             const bf16x8 (&b)[(1 + CLS / 2) * (1 + CLS % 2)][4], int py, int px,
+                                             int w, int li, int kh, float bias1) {
+  constexpr int cy = CLS >> 1, cx = CLS & 1;
+  f32x16 acc;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
+#pragma unroll
+  for (int ty = 0; ty < 1 + cy; ++ty) {
+    const int iy = cy ? (ty == 0 ? py + 1 : py) : py;
+#pragma unroll
+    for (int tx = 0; tx < 1 + cx; ++tx) {
+      const int ix = cx ? (tx == 0 ? px + 1 : px) : px;
+      const __bf16* arow = &hdp[(iy * 11 + ix) * kCPD];
+#pragma unroll
+      for (int c4 = 0; c4 < 4; ++c4)
+        acc = mfma_bf16c(*(const bf16x8*)(arow + 16 * c4 + 8 * kh), b[ty * (1 + cx) + tx][c4], acc);
+    }
+  }
+  // D layout: lane holds output channel li for 16 of the wave's 32 positions
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int row = 32 * w + 8 * (r >> 2) + 4 * kh + (r & 3);
+    if (row < 100) {
+      const int ry = row / 10, rx = row - 10 * ry;
+      const int oy = 2 * ry + cy, ox = 2 * rx + cx;
+      h3s[(oy * 20 + ox) * kCP3 + li] = fmaxf(acc[r] + bias1, 0.0f);
+    }
+  }
+}
+
+// A workgroup loops over histograms like the encoder.  Per histogram, the transposed conv1
+// weights of each parity class are issued one class ahead of its matrix-core steps, and
+// the next histogram's hidden layer is loaded while this one is computed.
 __global__ __launch_bounds__(256, 2) void k_conv_dec(ModelDev M, const __bf16* hd, long long n, float* fhat) {
   __shared__ __attribute__((aligned(16))) __bf16 hdp[11 * 11 * kCPD];
   __shared__ __attribute__((aligned(16))) float h3s[20 * 20 * kCP3];
@@ -264,130 +325,130 @@ __global__ __launch_bounds__(256, 2) void k_conv_dec(ModelDev M, const __bf16* h
   const int t = threadIdx.x, w = t >> 6, l = t & 63;
   const int li = l & 31, kh = l >> 5;
   for (int q = t; q < 9 * 32; q += 256) t2v[(q % 9) * 32 + q / 9] = M.t2w[q];   // t2w[ci][tap]
-  // zero row 10 and column 10 of the padded hidden layout (never written afterwards)
-  for (int q = t; q < 21 * 64; q += 256) {
-    const int cell = q >> 6, c = q & 63;
-    const int y = cell < 11 ? 10 : cell - 11, x = cell < 11 ? cell : 10;
-    hdp[(y * 11 + x) * kCPD + c] = (__bf16)0.0f;
-  }
   const __bf16* T1 = (const __bf16*)M.t1w;
   const float bias1 = M.t1b[li];
-  const float b2 = M.t2b[0];
+  const float bias2 = M.t2b[0];
+  // the hidden layer of a histogram: 800 16-byte chunks ([position][channel], 8 channels each)
+  bf16x8 hv[4];
+  auto load_hd = [&](long long hh) {
+    const bf16x8* src = (const bf16x8*)(hd + hh * 6400);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) hv[r] = src[min(t + 256 * r, 799)];
+  };
+  if ((long long)blockIdx.x < n) load_hd(blockIdx.x);
+  const int q = min(32 * w + li, 99);
+  const int py = q / 10, px = q - 10 * py;
   for (long long h = blockIdx.x; h < n; h += gridDim.x) {
+  // a zero the compiler cannot see through: the weight loads below stay inside the loop
+  // instead of being hoisted (holding them across iterations would not fit the registers)
+  int zo = 0;
+  asm volatile("" : "+v"(zo));
+  // transposed conv1's weights by parity class, each class's issued one class ahead of
+  // its matrix-core steps (classes 0 and 1 before the hidden layer is staged)
+  bf16x8 wb0[1][4], wb1[2][4], wb2[2][4], wb3[4][4];
+  tconv1_weights<0>(T1, li, kh, zo, wb0);
+  tconv1_weights<1>(T1, li, kh, zo, wb1);
   __syncthreads();          // the previous histogram is done with hdp and h3s
-  // the hidden layer ([position][channel], 8 channels per 16-byte chunk) into
-  // [y][x][channel]: all loads issued before the stores
-  {
-    const bf16x8* src = (const bf16x8*)(hd + h * 6400);
-    bf16x8 v[4];
+  // the hidden layer into [y][x][channel], and zeros in row 10 and column 10 (the output
+  // of the previous histogram went over part of the buffer)
+  if (t < 21 * 8) {
+    const int cell = t >> 3;
+    const int y = cell < 11 ? 10 : cell - 11, x = cell < 11 ? cell : 10;
+    bf16x8 z;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) v[r] = src[min(t + 256 * r, 799)];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int m = t + 256 * r;
-      if (m >= 800) continue;
-      const int p = m >> 3, y = p / 10, x = p - 10 * y;
-      *(bf16x8*)&hdp[(y * 11 + x) * kCPD + 8 * (m & 7)] = v[r];
-    }
+    for (int c = 0; c < 8; ++c) z[c] = (__bf16)0.0f;
+    *(bf16x8*)&hdp[(y * 11 + x) * kCPD + 8 * (t & 7)] = z;
   }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int m = t + 256 * r;
+    if (m >= 800) continue;
+    const int p = m >> 3, y = p / 10, x = p - 10 * y;
+    *(bf16x8*)&hdp[(y * 11 + x) * kCPD + 8 * (m & 7)] = hv[r];
+  }
+  if (h + gridDim.x < n) load_hd(h + gridDim.x);
   __syncthreads();
   // transposed conv1 on matrix cores, one parity class (cy, cx) at a time; wave w owns
   // the class's positions 32 w .. 32 w + 31 (of 100)
-  const int q = min(32 * w + li, 99);
-  const int py = q / 10, px = q - 10 * py;
-#pragma unroll
-  for (int cls = 0; cls < 4; ++cls) {
-    const int cy = cls >> 1, cx = cls & 1;
-    f32x16 acc;
-#pragma unroll
-    for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
-    bf16x8 bc[4][4];
-#pragma unroll
-    for (int ty = 0; ty < 1 + cy; ++ty)
-#pragma unroll
-      for (int tx = 0; tx < 1 + cx; ++tx) {
-        const int ky = cy ? (ty == 0 ? 0 : 2) : 1, kx = cx ? (tx == 0 ? 0 : 2) : 1;
-#pragma unroll
-        for (int c4 = 0; c4 < 4; ++c4)
-          bc[2 * ty + tx][c4] = *(const bf16x8*)(T1 + ((long long)((ky * 3 + kx) * 32 + li)) * 64 + 16 * c4 + 8 * kh);
-      }
-    // taps: even output -> k = 1 from input p; odd output -> k = 0 from p + 1, k = 2 from p
-#pragma unroll
-    for (int ty = 0; ty < 1 + cy; ++ty) {
-      const int ky = cy ? (ty == 0 ? 0 : 2) : 1;
-      const int iy = cy ? (ty == 0 ? py + 1 : py) : py;
-#pragma unroll
-      for (int tx = 0; tx < 1 + cx; ++tx) {
-        const int kx = cx ? (tx == 0 ? 0 : 2) : 1;
-        const int ix = cx ? (tx == 0 ? px + 1 : px) : px;
-        const __bf16* arow = &hdp[(iy * 11 + ix) * kCPD];
-#pragma unroll
-        for (int c4 = 0; c4 < 4; ++c4)
-          acc = mfma_bf16c(*(const bf16x8*)(arow + 16 * c4 + 8 * kh), bc[2 * ty + tx][c4], acc);
-      }
-    }
-    // D layout: lane holds output channel li for 16 of the wave's 32 positions
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int row = 32 * w + 8 * (r >> 2) + 4 * kh + (r & 3);
-      if (row < 100) {
-        const int ry = row / 10, rx = row - 10 * ry;
-        const int oy = 2 * ry + cy, ox = 2 * rx + cx;
-        h3s[(oy * 20 + ox) * kCP3 + li] = fmaxf(acc[r] + bias1, 0.0f);
-      }
-    }
-  }
+  tconv1_class<0>(hdp, h3s, wb0, py, px, w, li, kh, bias1);
+  tconv1_weights<2>(T1, li, kh, zo, wb2);
+  tconv1_class<1>(hdp, h3s, wb1, py, px, w, li, kh, bias1);
+  tconv1_weights<3>(T1, li, kh, zo, wb3);
+  tconv1_class<2>(hdp, h3s, wb2, py, px, w, li, kh, bias1);
+  tconv1_class<3>(hdp, h3s, wb3, py, px, w, li, kh, bias1);
   __syncthreads();
-  // transposed conv2 (32 -> 1) on the vector ALUs, one 2 x 2 output block per task: output
-  // (2m + a, 2n + b) takes input cells (m, n), (m, n + 1), (m + 1, n), (m + 1, n + 1) with
-  // taps ky = 1 (a = 0) or ky = 0 from row m + 1 and ky = 2 from row m (a = 1), likewise
-  // kx; the four cells are read once for the block's nine taps.  Row and column 39 do
+  // transposed conv2 (32 -> 1) on the vector ALUs.  A quad of lanes takes one 2 x 2 output
+  // block, lane cq of the quad channels 8 cq .. 8 cq + 7: output (2m + a, 2n + b) takes
+  // input cells (m, n), (m, n + 1), (m + 1, n), (m + 1, n + 1) with taps ky = 1 (a = 0) or
+  // ky = 0 from row m + 1 and ky = 2 from row m (a = 1), likewise kx.  The quad then sums
+  // its four channel groups with two swaps, lane cq keeping output cq = 2a + b, which goes
+  // to LDS; sigma y + mu is written out afterwards in natural order.  Row and column 39 do
   // not exist, so cells past 19 are never needed (clamped reads, outputs skipped).
-  for (int task = t; task < 400; task += 256) {
-    const int m = task / 20, nn = task - 20 * m;
-    const int m1 = min(m + 1, 19), n1 = min(nn + 1, 19);
-    const float4* a00 = (const float4*)&h3s[(m * 20 + nn) * kCP3];
-    const float4* a01 = (const float4*)&h3s[(m * 20 + n1) * kCP3];
-    const float4* a10 = (const float4*)&h3s[(m1 * 20 + nn) * kCP3];
-    const float4* a11 = (const float4*)&h3s[(m1 * 20 + n1) * kCP3];
-    const float4* wt = (const float4*)t2v;       // wt[tap * 8 + channel / 4]
-    float see = 0.0f, seo = 0.0f, soe = 0.0f, soo = 0.0f;
-#pragma unroll 2
-    for (int q = 0; q < 8; ++q) {
-      const float4 c00 = a00[q], c01 = a01[q], c10 = a10[q], c11 = a11[q];
-      const float4 w00 = wt[0 * 8 + q], w01 = wt[1 * 8 + q], w02 = wt[2 * 8 + q];
-      const float4 w10 = wt[3 * 8 + q], w11 = wt[4 * 8 + q], w12 = wt[5 * 8 + q];
-      const float4 w20 = wt[6 * 8 + q], w21 = wt[7 * 8 + q], w22 = wt[8 * 8 + q];
-#define HCZ_T2(E)                                  \
-      see = fmaf(c00.E, w11.E, see);                \
-      seo = fmaf(c01.E, w10.E, seo);                \
-      seo = fmaf(c00.E, w12.E, seo);                \
-      soe = fmaf(c10.E, w01.E, soe);                \
-      soe = fmaf(c00.E, w21.E, soe);                \
-      soo = fmaf(c11.E, w00.E, soo);                \
-      soo = fmaf(c10.E, w02.E, soo);                \
-      soo = fmaf(c01.E, w20.E, soo);                \
-      soo = fmaf(c00.E, w22.E, soo);
-      HCZ_T2(x) HCZ_T2(y) HCZ_T2(z) HCZ_T2(w)
-#undef HCZ_T2
+  {
+    const int cq = t & 3;
+    float wt[9][8];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      const float4 u0 = *(const float4*)&t2v[k * 32 + 8 * cq + zo];
+      const float4 u1 = *(const float4*)&t2v[k * 32 + 8 * cq + 4 + zo];
+      wt[k][0] = u0.x; wt[k][1] = u0.y; wt[k][2] = u0.z; wt[k][3] = u0.w;
+      wt[k][4] = u1.x; wt[k][5] = u1.y; wt[k][6] = u1.z; wt[k][7] = u1.w;
     }
-    const int oy = 2 * m, ox = 2 * nn;
-    float* out = fhat + h * 1521;
-    {
-      const int o = oy * 39 + ox;
-      out[o] = fmaf(M.sd[o], see + b2, M.mu[o]);
+    // sigma and mu of the six outputs this thread writes at the end (o = t + 256 k)
+    float sdv[6], muv[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      const int o = min(t + 256 * k, 1520) + zo;
+      sdv[k] = M.sd[o];
+      muv[k] = M.mu[o];
     }
-    if (ox + 1 < 39) {
-      const int o = oy * 39 + ox + 1;
-      out[o] = fmaf(M.sd[o], seo + b2, M.mu[o]);
-    }
-    if (oy + 1 < 39) {
-      const int o = (oy + 1) * 39 + ox;
-      out[o] = fmaf(M.sd[o], soe + b2, M.mu[o]);
-      if (ox + 1 < 39) {
-        const int o2 = o + 1;
-        out[o2] = fmaf(M.sd[o2], soo + b2, M.mu[o2]);
+    float* ys = (float*)hdp;     // y before sigma and mu; the hidden layer is no longer read
+#pragma unroll 1
+    for (int task = t >> 2; task < 400; task += 64) {
+      const int m = task / 20, nn = task - 20 * m;
+      const int m1 = min(m + 1, 19), n1 = min(nn + 1, 19);
+      const float* c00 = &h3s[(m * 20 + nn) * kCP3 + 8 * cq];
+      const float* c01 = &h3s[(m * 20 + n1) * kCP3 + 8 * cq];
+      const float* c10 = &h3s[(m1 * 20 + nn) * kCP3 + 8 * cq];
+      const float* c11 = &h3s[(m1 * 20 + n1) * kCP3 + 8 * cq];
+      float v00[8], v01[8], v10[8], v11[8];
+#pragma unroll
+      for (int hq = 0; hq < 2; ++hq) {
+        const float4 a = *(const float4*)(c00 + 4 * hq), b = *(const float4*)(c01 + 4 * hq);
+        const float4 c = *(const float4*)(c10 + 4 * hq), d = *(const float4*)(c11 + 4 * hq);
+        v00[4 * hq] = a.x; v00[4 * hq + 1] = a.y; v00[4 * hq + 2] = a.z; v00[4 * hq + 3] = a.w;
+        v01[4 * hq] = b.x; v01[4 * hq + 1] = b.y; v01[4 * hq + 2] = b.z; v01[4 * hq + 3] = b.w;
+        v10[4 * hq] = c.x; v10[4 * hq + 1] = c.y; v10[4 * hq + 2] = c.z; v10[4 * hq + 3] = c.w;
+        v11[4 * hq] = d.x; v11[4 * hq + 1] = d.y; v11[4 * hq + 2] = d.z; v11[4 * hq + 3] = d.w;
       }
+      float see = 0.0f, seo = 0.0f, soe = 0.0f, soo = 0.0f;
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        see = fmaf(v00[c], wt[4][c], see);
+        seo = fmaf(v01[c], wt[3][c], seo);
+        seo = fmaf(v00[c], wt[5][c], seo);
+        soe = fmaf(v10[c], wt[1][c], soe);
+        soe = fmaf(v00[c], wt[7][c], soe);
+        soo = fmaf(v11[c], wt[0][c], soo);
+        soo = fmaf(v10[c], wt[2][c], soo);
+        soo = fmaf(v01[c], wt[6][c], soo);
+        soo = fmaf(v00[c], wt[8][c], soo);
+      }
+      // transposed reduction over the quad: after the first swap lane cq holds, summed over
+      // its pair, the outputs of column b = cq & 1; after the second, output cq
+      const bool odd = (cq & 1) != 0, high = (cq & 2) != 0;
+      const float r0 = (odd ? seo : see) + quad_swap<0xB1>(odd ? see : seo);
+      const float r1 = (odd ? soo : soe) + quad_swap<0xB1>(odd ? soe : soo);
+      const float v = (high ? r1 : r0) + quad_swap<0x4E>(high ? r0 : r1);
+      const int oy = 2 * m + (high ? 1 : 0), ox = 2 * nn + (odd ? 1 : 0);
+      if (oy < 39 && ox < 39) ys[oy * 39 + ox] = v;
+    }
+    __syncthreads();
+    float* out = fhat + h * 1521;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      const int o = t + 256 * k;
+      if (o < 1521) out[o] = fmaf(sdv[k], ys[o] + bias2, muv[k]);
     }
   }
   }
