@@ -99,7 +99,7 @@ __global__ __launch_bounds__(256, 2) void k_conv_enc(ModelDev M, const TIn* hist
       xs[xo[q]] = ((isfinite(v) ? v : 0.0f) - mv[q]) * rv[q];
     }
   }
-  if (h + gridDim.x < n) load_f(h + gridDim.x);
+  load_f(min(h + (long long)gridDim.x, n - 1));     // unconditional: the waits stay exact
   // zero border of the conv1 output (row 0 and column 0 of the padded layout)
   for (int q = t; q < 41 * 32; q += 256) {
     const int cell = q >> 5, c = q & 31;
@@ -168,53 +168,68 @@ __global__ __launch_bounds__(256, 2) void k_conv_enc(ModelDev M, const TIn* hist
   }
 }
 
-// z[h][o] = fb[o] + sum_k h2[h][k] fw[o][k] on v_mfma_f32_16x16x4f32: a workgroup takes 16
-// histograms, its four waves a quarter of K = 6400 each.  Per 16-wide k step lane l holds
-// k = 16 c + 4 (l / 16) .. + 3 of row l % 16 of both operands (one 16-byte load each; the
-// products are summed in this lane order, which the two operands share), and the four
-// partial tiles are added in wave order.
+// z[h][o] = fb[o] + sum_k h2[h][k] fw[o][k] on v_mfma_f32_16x16x4f32: a workgroup takes 32
+// histograms as two 16-row tiles that share every fw operand, its four waves a quarter of
+// K = 6400 each.  Per 16-wide k step lane l holds k = 16 c + 4 (l / 16) .. + 3 of row
+// l % 16 of each operand (one 16-byte load each; the products are summed in this lane
+// order, which the operands share), and the four partial tiles are added in wave order.
 __global__ __launch_bounds__(256) void k_conv_fc(const float* h2, long long n, const float* fw, const float* fb,
                                                  float* z) {
-  __shared__ float part[4][16 * 16];
+  __shared__ float part[4][2][16 * 16];
   const int t = threadIdx.x, w = t >> 6, l = t & 63, lr = l & 15, lq = l >> 4;
-  const long long r0 = (long long)blockIdx.x * 16;
-  const long long row = min(r0 + lr, n - 1);
+  const long long r0 = (long long)blockIdx.x * 32;
+  const long long row0 = min(r0 + lr, n - 1), row1 = min(r0 + 16 + lr, n - 1);
   constexpr int kSteps = 6400 / 16 / 4;          // 16-wide k steps per wave
-  const f32x4* a = (const f32x4*)(h2 + row * 6400 + (long long)w * (6400 / 4) + 4 * lq);
+  const f32x4* a0 = (const f32x4*)(h2 + row0 * 6400 + (long long)w * (6400 / 4) + 4 * lq);
+  const f32x4* a1 = (const f32x4*)(h2 + row1 * 6400 + (long long)w * (6400 / 4) + 4 * lq);
   const f32x4* b = (const f32x4*)(fw + (long long)lr * 6400 + w * (6400 / 4) + 4 * lq);
-  f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-  f32x4 an[4], bn[4];
+  f32x4 acc0 = {0.0f, 0.0f, 0.0f, 0.0f}, acc1 = {0.0f, 0.0f, 0.0f, 0.0f};
+  f32x4 an0[4], an1[4], bn[4];
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
-    an[u] = a[4 * u];
+    an0[u] = a0[4 * u];
+    an1[u] = a1[4 * u];
     bn[u] = b[4 * u];
   }
   for (int c = 0; c < kSteps; c += 4) {
-    f32x4 av[4], bv[4];
+    f32x4 av0[4], av1[4], bv[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      av[u] = an[u];
+      av0[u] = an0[u];
+      av1[u] = an1[u];
       bv[u] = bn[u];
     }
     if (c + 4 < kSteps) {
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        an[u] = a[4 * (c + 4 + u)];
+        an0[u] = a0[4 * (c + 4 + u)];
+        an1[u] = a1[4 * (c + 4 + u)];
         bn[u] = b[4 * (c + 4 + u)];
       }
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u)
 #pragma unroll
-      for (int e = 0; e < 4; ++e) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[u][e], bv[u][e], acc, 0, 0, 0);
+      for (int e = 0; e < 4; ++e) {
+        acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(av0[u][e], bv[u][e], acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(av1[u][e], bv[u][e], acc1, 0, 0, 0);
+      }
   }
   // D layout: lane l holds rows 4 (l / 16) + r, column l % 16
 #pragma unroll
-  for (int r = 0; r < 4; ++r) part[w][(4 * lq + r) * 16 + lr] = acc[r];
+  for (int r = 0; r < 4; ++r) {
+    part[w][0][(4 * lq + r) * 16 + lr] = acc0[r];
+    part[w][1][(4 * lq + r) * 16 + lr] = acc1[r];
+  }
   __syncthreads();
-  const int q = t;                               // 256 outputs: row q / 16, column q % 16
-  const long long hr = r0 + q / 16;
-  if (hr < n) z[hr * kLatent + (q & 15)] = fb[q & 15] + (((part[0][q] + part[1][q]) + part[2][q]) + part[3][q]);
+#pragma unroll
+  for (int tile = 0; tile < 2; ++tile) {
+    const int q = t;                             // 256 outputs: row q / 16, column q % 16
+    const long long hr = r0 + 16 * tile + q / 16;
+    if (hr < n)
+      z[hr * kLatent + (q & 15)] =
+          fb[q & 15] + (((part[0][tile][q] + part[1][tile][q]) + part[2][tile][q]) + part[3][tile][q]);
+  }
 }
 
 // Decoder hidden layer: hd = bf16(relu(db[k] + sum_d zhat[h][d] dw[k][d])) as the FP32
@@ -366,7 +381,7 @@ __global__ __launch_bounds__(256, 2) void k_conv_dec(ModelDev M, const __bf16* h
     const int p = m >> 3, y = p / 10, x = p - 10 * y;
     *(bf16x8*)&hdp[(y * 11 + x) * kCPD + 8 * (m & 7)] = hv[r];
   }
-  if (h + gridDim.x < n) load_hd(h + gridDim.x);
+  load_hd(min(h + (long long)gridDim.x, n - 1));    // unconditional: the waits stay exact
   __syncthreads();
   // transposed conv1 on matrix cores, one parity class (cy, cx) at a time; wave w owns
   // the class's positions 32 w .. 32 w + 31 (of 100)
@@ -467,7 +482,7 @@ hipError_t launch_conv_encode(const ModelDev& M, const void* hist, int dtype, lo
     else
       hipLaunchKernelGGL(k_conv_enc<double>, eg, dim3(256), 0, st, M, (const double*)hist + c0 * hs, n, hs, rs,
                          M.scratch);
-    hipLaunchKernelGGL(k_conv_fc, dim3((unsigned)((n + 15) / 16)), dim3(256), 0, st, (const float*)M.scratch, n,
+    hipLaunchKernelGGL(k_conv_fc, dim3((unsigned)((n + 31) / 32)), dim3(256), 0, st, (const float*)M.scratch, n,
                        M.fw, M.fb, z + c0 * kLatent);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
