@@ -745,7 +745,22 @@ __device__ __forceinline__ void residual_w_hist(const GridDev& G, const Residual
       }
       recompose_w<SH, true>(G, L, R, rm, [&](int s) { return __dmul_rn(Dk, rint(__dmul_rn(dm[s], inv))); });   // rhat at k*
       wave_sync();
-      if (pre) {
+      bool done_ft = false;
+      if constexpr (SH::fixed) {
+        static_assert(SH::NP <= 64 && SH::NQ <= kRowChunk, "the fixed shape's column fits one lane and one chunk");
+        // the fixed shape's column: every rhat read first, then the sums stored
+        if (lane < SH::NP) {
+          double rh[SH::NQ];
+#pragma unroll
+          for (int k = 0; k < SH::NQ; ++k) rh[k] = ldy(L.yb, (uint32_t)(k * SH::NP + lane) * 8u);
+#pragma unroll
+          for (int k = 0; k < SH::NQ; ++k) sty(L.yb, (uint32_t)(k * SH::NP + lane) * 8u, (double)fh[k] + rh[k]);
+        }
+        wave_sync();
+        done_ft = true;
+      }
+      if (done_ft) {
+      } else if (pre) {
         if (lane < G.n_par) {
 #pragma unroll
           for (int k = 0; k < kRowChunk; ++k) {

@@ -243,15 +243,18 @@ __device__ __forceinline__ int newton_core(PASS pass, HESS hess, const double (&
 #pragma unroll
     for (int k = 0; k < 4; ++k) g[k] = v[k] - b[k];
     bool conv = true;
-    double rs = 0.0;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      conv = conv && (fabs(g[k]) <= kGTol * (sc[k] + 1e-300));
-      rs = fmax(rs, fabs(g[k]) / (sc[k] + 1e-300));
-    }
+    for (int k = 0; k < 4; ++k) conv = conv && (fabs(g[k]) <= kGTol * (sc[k] + 1e-300));
+    // the scaled residual max_k |g_k| / s_k, formed only while a warm start is judged
+    auto scaled_res = [&]() {
+      double rs = 0.0;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) rs = fmax(rs, fabs(g[k]) / (sc[k] + 1e-300));
+      return rs;
+    };
     if (warm && round == 0 && it == 1 && total == 1) {
       warm = false;
-      if (rs > r_warm0) {          // the warm start's first step made things worse
+      if (scaled_res() > r_warm0) {          // the warm start's first step made things worse
         *rejected = true;
 #pragma unroll
         for (int k = 0; k < 4; ++k) { lam[k] = 0.0; cand[k] = 0.0; }
@@ -260,7 +263,7 @@ __device__ __forceinline__ int newton_core(PASS pass, HESS hess, const double (&
         continue;
       }
     }
-    if (warm && round == 0 && it == 0) r_warm0 = rs;
+    if (warm && round == 0 && it == 0) r_warm0 = scaled_res();
     *upd = total;
     if (conv) return round;
     const int cap = round == 0 ? max1 : max2;
