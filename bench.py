@@ -97,7 +97,8 @@ def _sha256(paths) -> str:
     return h.hexdigest()
 
 
-RESIDUAL_SOURCES = ["paper_2212_10733_amd/csrc/k_wave.hip", "paper_2212_10733_amd/csrc/hcz_internal.h"]
+RESIDUAL_SOURCES = ["paper_2212_10733_amd/csrc/k_wave.hip", "paper_2212_10733_amd/csrc/wave_ops.h",
+                    "paper_2212_10733_amd/csrc/hcz_internal.h"]
 
 
 def residual_traffic(H: int):
