@@ -162,7 +162,8 @@ typedef struct {
  *                  i.e. f_c = max(ft, 0) exp(-A^T lam), solved by the same Newton rounds on
  *                  its dual.  It is not non-expansive, so it is kept (flag HCZ_FLAG_KL) only
  *                  where ||f - f_c|| <= (1 - 2^-20) tau_h; elsewhere the histogram gets the
- *                  L2 projection.  Runs on the workgroup-per-histogram kernel for every grid.
+ *                  L2 projection.  Runs on the wave-per-histogram kernels for grids that
+ *                  fit one wave, on the workgroup-per-histogram kernel otherwise.
  *                  Not combined with no_positivity or a warm start (HCZ_EINVAL).
  * lambda_bits      0: multipliers stored as computed; 1..52: rounded (nearest, ties to
  *                  even) to that many mantissa bits before storage, the truncation of the
@@ -286,8 +287,8 @@ hcz_status hcz_plan_path(const hcz_plan* plan, int32_t* path);
  *                             and 65 x 65).
  * Every variant gives the same records, offsets and flags; the multipliers agree to the
  * Newton stopping rule (the kernel families sum in different orders, so their last bits
- * may differ).  The KL reading always runs on the workgroup kernel
- * (a wave variant then means AUTO).  hcz_plan_variants writes the variants valid for the
+ * may differ).  The KL reading runs on the wave kernels and the workgroup kernel; a
+ * team variant then means the workgroup kernel.  hcz_plan_variants writes the variants valid for the
  * plan's grid (at most 8) to list (host) and their count to *n; hcz_plan_set_variant makes
  * one of them the plan's choice for later calls (not thread-safe against calls in flight
  * on other threads).  Errors: HCZ_EINVAL for a NULL argument, HCZ_EUNSUPPORTED for a

@@ -769,7 +769,7 @@ hipError_t launch_residual(const GridDev& G, const ResidualArgs& a, hipStream_t 
   if (a.H <= 0) return hipSuccess;
   const int v = a.variant;
   const bool wave_v = v == HCZ_VARIANT_AUTO || v == HCZ_VARIANT_WAVE_FIXED || v == HCZ_VARIANT_WAVE;
-  if (wave_path(G) && !a.kl && wave_v) return launch_residual_w(G, a, st);
+  if (wave_path(G) && wave_v) return launch_residual_w(G, a, st);
   if ((v == HCZ_VARIANT_TEAM2 || v == HCZ_VARIANT_TEAM4) && !a.kl)
     return launch_residual_t(G, a, v == HCZ_VARIANT_TEAM2 ? 2 : 4, st);
   if (v == HCZ_VARIANT_AUTO && !a.kl && !wave_path(G) && (team_path(G, 2) || team_path(G, 4)))

@@ -330,10 +330,12 @@ __device__ __forceinline__ void for_columns(const GridDev& G, BEGIN begin, BODY 
 // column the row sums of w x, c w x and, on active
 // cells, w^2, w^2 c, w^2 c^2 come first and are then weighted by the column's powers of
 // a.  The correction per cell is vol * ((lam3 a + lam1) a + lam0 + lam2 c), one fixed
-// order for compression and decompression.
-template <class SH, bool UVOL, bool THETA, bool POS>
+// order for compression and decompression.  KL: the KL reading, x = max(ft, 0) exp(-corr)
+// with Hessian weights x (A diag(x) A^T) and v[15] = sum_j x_j for its dual.
+template <class SH, bool UVOL, bool THETA, bool POS, bool KL = false>
 __device__ __forceinline__ void newton_pass_w(const GridDev& G, const WaveLds& L, const double (&lam)[4],
                                               double (&v)[16], double (&sc)[4], double (&hs)[9]) {
+  static_assert(!KL || POS, "the KL reading's x is never negative");
   double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0, v4 = 0.0, v15 = 0.0, c0 = 0.0, c2 = 0.0, c3 = 0.0;
   double hh[9];
 #pragma unroll
@@ -349,8 +351,9 @@ __device__ __forceinline__ void newton_pass_w(const GridDev& G, const WaveLds& L
     const double c = L.s_cc[2 * j], c2 = L.s_cc[2 * j + 1];
     const double w = UVOL ? G.vol0 : G.vol[j * G.n_par + i];
     const double ft = ldy(L.yb, off);
-    const double y = ft - w * fma(lam[2], c, pa);
-    const double x = POS ? fmax(0.0, y) : y;
+    const double corr = w * fma(lam[2], c, pa);
+    const double y = ft - corr;
+    const double x = KL ? (ft > 0.0 ? ft * exp(-corr) : 0.0) : (POS ? fmax(0.0, y) : y);
     const double wx = UVOL ? x : w * x;
     sx += wx;
     sxc = fma(c, wx, sxc);
@@ -359,15 +362,20 @@ __device__ __forceinline__ void newton_pass_w(const GridDev& G, const WaveLds& L
       sxa += wxa;
       sxca = fma(c, wxa, sxca);
     }
-    // Hessian terms on active cells, as a 0/1 weight (exact: products with 0 or 1)
-    const double act = (!POS || x > 0.0) ? 1.0 : 0.0;
+    // Hessian terms on active cells, as a 0/1 weight (exact: products with 0 or 1); in
+    // the KL reading the weight is x itself
+    const double act = KL ? x : ((!POS || x > 0.0) ? 1.0 : 0.0);
     const double w2 = UVOL ? act : act * (w * w);
     h0 += w2;
     hc = fma(w2, c, hc);
     hcc = fma(w2, c2, hcc);
     if (THETA) {
-      const double dx = x - ft;
-      s2 = fma(dx, dx, s2);
+      if (KL) {
+        s2 += x;
+      } else {
+        const double dx = x - ft;
+        s2 = fma(dx, dx, s2);
+      }
     }
   };
   auto fold = [&](int i) {
@@ -464,17 +472,18 @@ __device__ __forceinline__ void hess_fill(const double (&hs)[9], double (&v)[16]
 }
 
 // Both Newton rounds (newton_core) on the wave's buffer.
-template <class SH, bool UVOL, bool POS>
+template <class SH, bool UVOL, bool POS, bool KL = false>
 __device__ __forceinline__ int newton_w(const GridDev& G, const WaveLds& L, const double (&b)[4], double (&lam)[4],
                                         double s1, int max1, double s2, int max2, bool armijo2, int* upd,
                                         bool have_init, const double (&lam_init)[4], bool* rejected) {
   double hh[9];
   auto pass = [&](bool theta, const double (&cand)[4], double (&v)[16], double (&sc)[4]) {
-    if (theta) newton_pass_w<SH, UVOL, true, POS>(G, L, cand, v, sc, hh);
-    else newton_pass_w<SH, UVOL, false, POS>(G, L, cand, v, sc, hh);
+    if (theta) newton_pass_w<SH, UVOL, true, POS, KL>(G, L, cand, v, sc, hh);
+    else newton_pass_w<SH, UVOL, false, POS, KL>(G, L, cand, v, sc, hh);
   };
   auto hess = [&](double (&v)[16]) { hess_fill(hh, v); };
-  return newton_core(pass, hess, b, lam, s1, max1, s2, max2, armijo2, upd, have_init, lam_init, rejected);
+  return newton_core<decltype(pass), decltype(hess), KL>(pass, hess, b, lam, s1, max1, s2, max2, armijo2, upd,
+                                                        have_init, lam_init, rejected);
 }
 
 // ---- compression ------------------------------------------------------------------------
@@ -504,8 +513,9 @@ __device__ __forceinline__ void pre_load(PreRows<TIn, SH>& P, const GridDev& G, 
 }
 
 // Histogram h (< a.H) on this wave, with the grid's tables staged in LDS and, for a fixed
-// shape, the wave's column already loaded into P.
-template <typename TIn, bool UVOL, class SH>
+// shape, the wave's column already loaded into P.  KL: the KL reading of Stage 5 first,
+// kept where it keeps the bound, the L2 projection elsewhere.
+template <typename TIn, bool UVOL, class SH, bool KL = false>
 __device__ __forceinline__ void residual_w_hist(const GridDev& G, const ResidualArgs& a, const WaveLds& L,
                                                 long long h, const PreRows<TIn, SH>& P) {
   constexpr int NS = SH::NS;
@@ -803,15 +813,52 @@ __device__ __forceinline__ void residual_w_hist(const GridDev& G, const Residual
     }
     const bool have_l0 = a.lam0 != nullptr || a.analytic;
     bool rejected = false;
-    const int st = a.no_positivity
-                       ? newton_w<SH, UVOL, false>(G, L, b, lam, a.newton_s, a.max_iter, paper ? 0.01 : 1.0,
-                                                   a.max_iter2, !paper, &total_upd, have_l0, l0, &rejected)
-                       : newton_w<SH, UVOL, true>(G, L, b, lam, a.newton_s, a.max_iter, paper ? 0.01 : 1.0,
-                                                  a.max_iter2, !paper, &total_upd, have_l0, l0, &rejected);
-    if (rejected) flags |= HCZ_FLAG_WARM_REJECTED;
-    if (st >= 1) flags |= HCZ_FLAG_ROUND2;
-    if (st == 2) raw = true;
-    if (!raw && a.no_positivity) flags |= HCZ_FLAG_NOCLIP;
+    bool kl_kept = false;
+    if constexpr (KL) {
+      // the KL reading first (cold, both rounds); kept only where ||f - x|| stays within
+      // the selection threshold (the KL correction is not non-expansive)
+      double lk[4] = {0.0, 0.0, 0.0, 0.0};
+      int ku = 0;
+      bool krej = false;
+      const int kst = newton_w<SH, UVOL, true, true>(G, L, b, lk, a.newton_s, a.max_iter, paper ? 0.01 : 1.0,
+                                                     a.max_iter2, !paper, &ku, false, lk, &krej);
+      if (kst < 2) {
+        double pa = 0.0, e2 = 0.0;
+        for_columns(
+            G,
+            [&](int i) {
+              const double av = G.apar[i];
+              pa = fma(fma(lk[3], av, lk[1]), av, lk[0]);
+            },
+            [&](int i, int j, uint32_t off) {
+              const double ft = ldy(L.yb, off);
+              const double w = UVOL ? G.vol0 : G.vol[j * G.n_par + i];
+              const double x = ft > 0.0 ? ft * exp(-(w * fma(lk[2], L.s_cc[2 * j], pa))) : 0.0;
+              const double d = (double)f[(long long)j * a.rs + i] - x;
+              e2 = fma(d, d, e2);
+            },
+            [](int) {});
+        if (wsum(e2) <= thr2) {
+          kl_kept = true;
+          total_upd = ku;
+          if (kst >= 1) flags |= HCZ_FLAG_ROUND2;
+#pragma unroll
+          for (int k = 0; k < 4; ++k) lam[k] = lk[k];
+        }
+      }
+    }
+    if (!kl_kept) {
+      const int st = a.no_positivity
+                         ? newton_w<SH, UVOL, false>(G, L, b, lam, a.newton_s, a.max_iter, paper ? 0.01 : 1.0,
+                                                     a.max_iter2, !paper, &total_upd, have_l0, l0, &rejected)
+                         : newton_w<SH, UVOL, true>(G, L, b, lam, a.newton_s, a.max_iter, paper ? 0.01 : 1.0,
+                                                    a.max_iter2, !paper, &total_upd, have_l0, l0, &rejected);
+      if (rejected) flags |= HCZ_FLAG_WARM_REJECTED;
+      if (st >= 1) flags |= HCZ_FLAG_ROUND2;
+      if (st == 2) raw = true;
+      if (!raw && a.no_positivity) flags |= HCZ_FLAG_NOCLIP;
+    }
+    if (!raw && kl_kept) flags |= HCZ_FLAG_KL;
   }
 
   uint64_t size = 0;
@@ -844,7 +891,7 @@ __device__ __forceinline__ void residual_w_hist(const GridDev& G, const Residual
 
 // One wave per histogram.  With a fixed shape the wave's column of the histogram is
 // loaded before the workgroup stages its tables, so both latencies overlap.
-template <typename TIn, bool UVOL, class SH>
+template <typename TIn, bool UVOL, class SH, bool KL = false>
 __global__ __launch_bounds__(256, 2) void k_residual_w(GridDev G, ResidualArgs a) {
   extern __shared__ double smem[];
   const int wv = threadIdx.x >> 6;
@@ -854,7 +901,7 @@ __global__ __launch_bounds__(256, 2) void k_residual_w(GridDev G, ResidualArgs a
   const WaveLds L = setup_lds(G, smem, wv);
   __syncthreads();
   if (h >= a.H) return;
-  residual_w_hist<TIn, UVOL, SH>(G, a, L, h, P);
+  residual_w_hist<TIn, UVOL, SH, KL>(G, a, L, h, P);
 }
 
 // ---- decompression ----------------------------------------------------------------------
@@ -993,15 +1040,20 @@ hipError_t launch_residual_w(const GridDev& G, const ResidualArgs& a, hipStream_
   const bool s39 = wave_fixed_path(G) && a.variant != HCZ_VARIANT_WAVE;
   dim3 grid((unsigned)((a.H + kWPB - 1) / kWPB)), block(64 * kWPB);
   const size_t lds = lds_bytes_w(G);
-#define HCZ_RW(T, U, SH) hipLaunchKernelGGL((k_residual_w<T, U, SH>), grid, block, lds, st, G, a)
-#define HCZ_RW2(T)                                     \
-  do {                                                  \
-    if (s39) HCZ_RW(T, true, Shape39);                  \
-    else if (G.uniform_vol) HCZ_RW(T, true, ShapeDyn);  \
-    else HCZ_RW(T, false, ShapeDyn);                    \
+#define HCZ_RW(T, U, SH, K) hipLaunchKernelGGL((k_residual_w<T, U, SH, K>), grid, block, lds, st, G, a)
+#define HCZ_RW2(T, K)                                     \
+  do {                                                     \
+    if (s39) HCZ_RW(T, true, Shape39, K);                  \
+    else if (G.uniform_vol) HCZ_RW(T, true, ShapeDyn, K);  \
+    else HCZ_RW(T, false, ShapeDyn, K);                    \
   } while (0)
-  if (a.dtype == HCZ_F32) HCZ_RW2(float);
-  else HCZ_RW2(double);
+  if (a.kl) {
+    if (a.dtype == HCZ_F32) HCZ_RW2(float, true);
+    else HCZ_RW2(double, true);
+  } else {
+    if (a.dtype == HCZ_F32) HCZ_RW2(float, false);
+    else HCZ_RW2(double, false);
+  }
 #undef HCZ_RW2
 #undef HCZ_RW
   return hipGetLastError();

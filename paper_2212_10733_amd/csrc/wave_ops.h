@@ -139,6 +139,14 @@ __device__ __forceinline__ double theta_w(const double (&v)[16], const double (&
   for (int k = 0; k < 4; ++k) t = t + lam[k] * (v[k] - b[k]);
   return t;
 }
+// The KL reading's dual D(lam) = -sum_j x_j - lam^T b (v[15] = sum_j x_j), concave with the
+// same gradient A x - b.
+__device__ __forceinline__ double theta_kl(const double (&v)[16], const double (&lam)[4], const double (&b)[4]) {
+  double t = -v[15];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) t = t - lam[k] * b[k];
+  return t;
+}
 
 __device__ __forceinline__ bool chol4(const double (&v)[16], const double (&g)[4], double (&d)[4]) {
   double Hm[4][4];
@@ -193,10 +201,11 @@ __device__ __forceinline__ bool chol4(const double (&v)[16], const double (&g)[4
 // pass(theta, lam, v, sc) evaluates the iterate lam: v[0..3] = A x, v[15] = ||x - ft||^2
 // when theta, sc the stopping rule's scales; hess(v) fills the Hessian entries v[5..14]
 // of the last pass.
-template <class PASS, class HESS>
+template <class PASS, class HESS, bool KL = false>
 __device__ __forceinline__ int newton_core(PASS pass, HESS hess, const double (&b)[4], double (&lam)[4], double s1,
                                            int max1, double s2, int max2, bool armijo2, int* upd, bool have_init,
                                            const double (&lam_init)[4], bool* rejected) {
+  auto theta = [&](const double (&v)[16], const double (&l)[4]) { return KL ? theta_kl(v, l, b) : theta_w(v, l, b); };
   int round = 0, it = 0, total = 0, halvings = 0;
   bool trial = false;
   // warm start: lam begins at lam_init; it is dropped (cold restart) if round 1 allows no
@@ -224,7 +233,7 @@ __device__ __forceinline__ int newton_core(PASS pass, HESS hess, const double (&
   for (;;) {
     pass(round == 1 && armijo2, cand, v, sc);
     if (trial) {
-      if (theta_w(v, cand, b) >= t0 + kArmijoC * step * gd) {
+      if (theta(v, cand) >= t0 + kArmijoC * step * gd) {
 #pragma unroll
         for (int k = 0; k < 4; ++k) lam[k] = cand[k];
         trial = false;
@@ -291,7 +300,7 @@ __device__ __forceinline__ int newton_core(PASS pass, HESS hess, const double (&
       if (!chol4(v, g, d)) break;
     }
     if (round == 1 && armijo2) {
-      t0 = theta_w(v, lam, b);
+      t0 = theta(v, lam);
       gd = ((g[0] * d[0] + g[1] * d[1]) + g[2] * d[2]) + g[3] * d[3];
       step = 1.0;
       halvings = 0;

@@ -242,18 +242,23 @@ def test_full_scale_batch(H, ctx, with_model):
         assert not np.any(diff & ~near)
 
 
-@pytest.mark.parametrize("shape,tau", [((39, 39), 1e-2), ((39, 39), 1e-3), ((33, 37), 1e-2)])
-def test_kl_correction_end_to_end(H, ctx, shape, tau):
+@pytest.mark.parametrize("shape,tau,variant,Hn", [((39, 39), 1e-2, "auto", 400), ((39, 39), 1e-3, "auto", 400),
+                                                  ((33, 37), 1e-2, "auto", 400),
+                                                  ((39, 39), 1e-2, "block_256x6", 400),
+                                                  ((49, 49), 1e-2, "auto", 120)])
+def test_kl_correction_end_to_end(H, ctx, shape, tau, variant, Hn):
     """The KL reading of Stage 5 (kept where it keeps the bound, the L2 projection
-    elsewhere), coder-only: records byte-exact, flags equal to the oracle's wherever the
-    KL bound decision is not a near-tie, multipliers to 1e-7, the bound, the QoIs and
+    elsewhere), coder-only, on the wave kernels (39 x 39 compiled, 33 x 37 run-time tables)
+    and the workgroup kernel (39 x 39 by its variant, 49 x 49, which the wave-team kernels
+    leave to it for this reading): records byte-exact, flags equal to the oracle's wherever
+    the KL bound decision is not a near-tie, multipliers to 1e-7, the bound, the QoIs and
     non-negativity on the GPU's own output."""
     n_perp, n_par = shape
-    say("kl", shape, tau)
+    say("kl", shape, tau, variant)
     g = grid.make_grid(n_par, n_perp)
-    Hn = 400
     F = synth.histograms(Hn, n_par, n_perp, seed=44, dtype=np.float32)
     plan = H.Plan(ctx, n_par, n_perp)
+    plan.set_variant(variant)
     cz = H.Compressor(plan, None, Hn, H.params(tau=tau, kl=True))
     comp = cz.compress(torch.from_numpy(F).cuda())
     out = cz.decompress(comp, Hn).cpu().numpy()
