@@ -216,6 +216,15 @@ def test_full_scale_batch(H, ctx, with_model):
     sample = np.sort(rng.choice(Hn, 128, replace=False))
     off = comp.offsets.cpu().numpy().astype(np.int64)
     flags = comp.flags.cpu().numpy()
+    # the same bound and QoIs on the sampled histograms by the oracle's own formulas (FP64,
+    # NumPy) rather than the library's moment kernel
+    Fs = F[sample].astype(np.float64)
+    outs = out[torch.from_numpy(sample).cuda()].cpu().numpy()
+    oks = (flags[sample] & 4) == 0
+    th = pipeline.tau_h(Fs, pipeline.Params(tau=1e-3))
+    d = np.sqrt(((outs - Fs) ** 2).reshape(len(sample), -1).sum(1))
+    assert np.all(d[oks] <= th[oks])
+    assert moments.qoi_rel_error(moments.qoi(Fs, g), moments.qoi(outs, g), g)[oks].max() < 1e-10
     if not with_model:
         ref = pipeline.compress(F[sample], g, None, None, pipeline.Params(tau=1e-3))
         stream = comp.stream
