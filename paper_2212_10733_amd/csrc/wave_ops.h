@@ -164,8 +164,7 @@ __device__ __forceinline__ bool chol4(const double (&v)[16], const double (&g)[4
 #pragma unroll
     for (int q = 0; q < k; ++q) piv = piv - Lm[k][q] * Lm[k][q];
     if (!(piv > kPivTol * tr)) return false;
-    Lm[k][k] = sqrt(piv);
-    rl[k] = 1.0 / Lm[k][k];
+    rl[k] = rsqrt(piv);                 // 1 / L_kk: the only form the solves use
 #pragma unroll
     for (int i = k + 1; i < 4; ++i) {
       double s = Hm[i][k];
