@@ -159,19 +159,20 @@ __device__ __forceinline__ bool chol_solve4(const double (&v)[kNv], const double
   Hm[2][1] = Hm[1][2]; Hm[3][1] = Hm[1][3]; Hm[3][2] = Hm[2][3];
   const double tr = ((Hm[0][0] + Hm[1][1]) + Hm[2][2]) + Hm[3][3];
   double Lm[4][4] = {};
+  double rl[4];                         // 1 / L_kk: the only form the solves use
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     double piv = Hm[k][k];
 #pragma unroll
     for (int q = 0; q < k; ++q) piv = piv - Lm[k][q] * Lm[k][q];
     if (!(piv > kPivTol * tr)) return false;
-    Lm[k][k] = sqrt(piv);
+    rl[k] = rsqrt(piv);
 #pragma unroll
     for (int i = k + 1; i < 4; ++i) {
       double s = Hm[i][k];
 #pragma unroll
       for (int q = 0; q < k; ++q) s = s - Lm[i][q] * Lm[k][q];
-      Lm[i][k] = s / Lm[k][k];
+      Lm[i][k] = s * rl[k];
     }
   }
   double y[4];
@@ -180,14 +181,14 @@ __device__ __forceinline__ bool chol_solve4(const double (&v)[kNv], const double
     double s = g[i];
 #pragma unroll
     for (int q = 0; q < i; ++q) s = s - Lm[i][q] * y[q];
-    y[i] = s / Lm[i][i];
+    y[i] = s * rl[i];
   }
 #pragma unroll
   for (int i = 3; i >= 0; --i) {
     double s = y[i];
 #pragma unroll
     for (int q = i + 1; q < 4; ++q) s = s - Lm[q][i] * d[q];
-    d[i] = s / Lm[i][i];
+    d[i] = s * rl[i];
   }
   return true;
 }
