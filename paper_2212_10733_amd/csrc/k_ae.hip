@@ -330,8 +330,22 @@ __global__ __launch_bounds__(256, 2) void k_decode(ModelDev M, const uint8_t* co
     }
   };
   bload(0, 0, bv);
+  // b4, sigma and mu of the wave's two column tiles, loaded one column block ahead
+  float ep[2][3], epn[2][3];
+  auto epload = [&](int nb, float (&E)[2][3]) {
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const int cc = min(nb + (w & 1) * 64 + b * 32 + li, M.N - 1);
+      E[b][0] = M.b4[cc];
+      E[b][1] = M.sd[cc];
+      E[b][2] = M.mu[cc];
+    }
+  };
+  epload(0, ep);
+  const bool full = h0 + kTile <= H;       // every row of the tile is a histogram
   for (int nb = 0; nb < M.npad; nb += 128) {
     const int wc = nb + (w & 1) * 64;
+    epload(min(nb + 128, M.npad - 128), epn);
     f32x16 acc[2][2];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
@@ -366,14 +380,18 @@ __global__ __launch_bounds__(256, 2) void k_decode(ModelDev M, const uint8_t* co
       for (int b = 0; b < 2; ++b) {
         const int col = wc + b * 32 + li;
         if (col >= M.N) continue;
-        const float b4 = M.b4[col], sd = M.sd[col], mu = M.mu[col];
+        const float b4 = ep[b][0], sd = ep[b][1], mu = ep[b][2];
+        float* dst = fhat + (h0 + wr + a * 32 + 4 * lh) * M.N + col;
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
-          const int row = wr + a * 32 + 8 * (r >> 2) + 4 * lh + (r & 3);
-          const long long h = h0 + row;
-          if (h < H) fhat[h * M.N + col] = fmaf(sd, acc[a][b][r] + b4, mu);
+          const int rr = 8 * (r >> 2) + (r & 3);        // row within the tile, less 4 lh
+          if (full || h0 + wr + a * 32 + 4 * lh + rr < H) dst[rr * M.N] = fmaf(sd, acc[a][b][r] + b4, mu);
         }
       }
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int e = 0; e < 3; ++e) ep[b][e] = epn[b][e];
   }
 }
 
