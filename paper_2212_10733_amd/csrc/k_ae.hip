@@ -829,10 +829,23 @@ __global__ __launch_bounds__(256, 2) void k_decode_b2(ModelDev M, const uint8_t*
       for (int s = 0; s < 8; ++s) B[n][s] = Wm[((nb * 2 + n) * 8 + s) * 64];
   };
   bload(0, bv);
+  // b4, sigma and mu of the lane's two columns, loaded one column block ahead
+  float ep[2][3], epn[2][3];
+  auto epload = [&](int nb, float (&E)[2][3]) {
+#pragma unroll
+    for (int n = 0; n < 2; ++n) {
+      const int cc = min(64 * nb + 32 * n + li, N - 1);
+      E[n][0] = M.b4[cc];
+      E[n][1] = M.sd[cc];
+      E[n][2] = M.mu[cc];
+    }
+  };
+  epload(0, ep);
   // store mapping: lane -> row 4 i + l / 16 (i = 0..7), columns 4 (l % 16) .. + 3 of the block
   const int srow = l >> 4, scol = 4 * (l & 15);
   for (int nb = 0; nb < nblk; ++nb) {
     if (nb + 1 < nblk) bload(nb + 1, bn);
+    epload(min(nb + 1, nblk - 1), epn);
     f32x16 acc[2];
 #pragma unroll
     for (int n = 0; n < 2; ++n)
@@ -844,9 +857,7 @@ __global__ __launch_bounds__(256, 2) void k_decode_b2(ModelDev M, const uint8_t*
       for (int n = 0; n < 2; ++n) acc[n] = mfma_bf16(a8[s], bv[n][s], acc[n]);
 #pragma unroll
     for (int n = 0; n < 2; ++n) {
-      const int col = 64 * nb + 32 * n + li;
-      const int cc = min(col, N - 1);
-      const float b4 = M.b4[cc], sd = M.sd[cc], mu = M.mu[cc];
+      const float b4 = ep[n][0], sd = ep[n][1], mu = ep[n][2];
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int row = 8 * (r >> 2) + 4 * kh + (r & 3);
@@ -880,6 +891,10 @@ __global__ __launch_bounds__(256, 2) void k_decode_b2(ModelDev M, const uint8_t*
     for (int n = 0; n < 2; ++n)
 #pragma unroll
       for (int s = 0; s < 8; ++s) bv[n][s] = bn[n][s];
+#pragma unroll
+    for (int n = 0; n < 2; ++n)
+#pragma unroll
+      for (int e = 0; e < 3; ++e) ep[n][e] = epn[n][e];
   }
 }
 
