@@ -8,8 +8,9 @@
 // border; conv2 (3x3, 32 -> 64, stride 2) as an implicit GEMM on v_mfma_f32_32x32x16_bf16:
 // rows = the 100 output positions (four 32-row tiles, one per wave), columns = 64 output
 // channels, K = 9 taps x 32 input channels, each lane's eight operands one 16-byte LDS
-// read; ReLU(acc + b) in FP32 to LDS in flattening order (channel-major); the dense
-// 6400 -> 16 layer on the vector ALUs (16 lanes per output, shuffle reduction).
+// read; ReLU(acc + b) in FP32 stored to the h2 buffer in flattening order (channel-major).
+// The dense 6400 -> 16 layer (k_conv_fc) runs over 32 histograms per workgroup on
+// v_mfma_f32_16x16x4f32.
 // Decoder (k_conv_dec): hd = relu(db + sum_d zhat_d dw[:, d]) as an FP32 chain, rounded to
 // bfloat16 into LDS as [y][x][channel] (10 x 10 plus a zero row and column); the
 // transposed conv1 (64 -> 32, stride 2, output padding 1) as an implicit GEMM per output
@@ -46,9 +47,8 @@ template <typename TIn>
 __global__ __launch_bounds__(256, 2) void k_conv_enc(ModelDev M, const TIn* hist, long long n, long long hs,
                                                      long long rs, float* h2out) {
   __shared__ float xs[41 * 41];                                        // x at (iy + 1, ix + 1)
-  __shared__ __attribute__((aligned(16))) __bf16 h1p[21 * 21 * kCP1];   // later: h2 (6400 floats)
+  __shared__ __attribute__((aligned(16))) __bf16 h1p[21 * 21 * kCP1];
   __shared__ __attribute__((aligned(16))) __bf16 w2s[9 * 64 * 32];      // conv2 weights [tap][out][in]
-  float* h2s = (float*)h1p;
   const int t = threadIdx.x, w = t >> 6, l = t & 63;
   const int li = l & 31, kh = l >> 5;
   {
@@ -58,6 +58,13 @@ __global__ __launch_bounds__(256, 2) void k_conv_enc(ModelDev M, const TIn* hist
   for (int q = t; q < 41 * 41; q += 256) {
     const int y = q / 41, x = q - 41 * y;
     if (y == 0 || y == 40 || x == 0 || x == 40) xs[q] = 0.0f;
+  }
+  // zero border of the conv1 output (row 0 and column 0 of the padded layout), which
+  // conv1 never writes
+  for (int q = t; q < 41 * 32; q += 256) {
+    const int cell = q >> 5, c = q & 31;
+    const int cy = cell < 21 ? 0 : cell - 20, cx = cell < 21 ? cell : 0;
+    h1p[(cy * 21 + cx) * kCP1 + c] = (__bf16)0.0f;
   }
   // conv1's weights: thread -> channels 8 cg .. 8 cg + 7
   const int cg = t & 3;
@@ -91,7 +98,7 @@ __global__ __launch_bounds__(256, 2) void k_conv_enc(ModelDev M, const TIn* hist
   };
   if ((long long)blockIdx.x < n) load_f(blockIdx.x);
   for (long long h = blockIdx.x; h < n; h += gridDim.x) {
-  __syncthreads();          // the previous histogram is done with xs and h2s
+  __syncthreads();          // the previous histogram is done with xs and h1p
 #pragma unroll
   for (int q = 0; q < 6; ++q) {
     if (t + 256 * q < 1521) {
@@ -100,12 +107,6 @@ __global__ __launch_bounds__(256, 2) void k_conv_enc(ModelDev M, const TIn* hist
     }
   }
   load_f(min(h + (long long)gridDim.x, n - 1));     // unconditional: the waits stay exact
-  // zero border of the conv1 output (row 0 and column 0 of the padded layout)
-  for (int q = t; q < 41 * 32; q += 256) {
-    const int cell = q >> 5, c = q & 31;
-    const int cy = cell < 21 ? 0 : cell - 20, cx = cell < 21 ? cell : 0;
-    h1p[(cy * 21 + cx) * kCP1 + c] = (__bf16)0.0f;
-  }
   __syncthreads();
   // conv1: thread -> channels 8 cg .. 8 cg + 7 of positions p = t / 4 + 64 q; the nine
   // taps are read first, then every channel's chain runs over them in row-major order
@@ -151,20 +152,27 @@ __global__ __launch_bounds__(256, 2) void k_conv_enc(ModelDev M, const TIn* hist
                              acc[nt]);
     }
   }
-  __syncthreads();          // every wave is done reading h1p before h2 overwrites it
+  // ReLU(acc + b) straight to h2 in flattening order (channel-major): the lane's four
+  // consecutive rows 8 g + 4 kh .. + 3 of channel co are one 16-byte store (100 rows per
+  // channel, so a group of four is all in range or all out)
+  float* dst = h2out + h * 6400;
 #pragma unroll
   for (int nt = 0; nt < 2; ++nt) {
     const int co = 32 * nt + li;
     const float bias = M.c2b[co];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int row = 32 * w + 8 * (r >> 2) + 4 * kh + (r & 3);
-      if (row < 100) h2s[co * 100 + row] = fmaxf(acc[nt][r] + bias, 0.0f);
+    for (int g = 0; g < 4; ++g) {
+      const int row = 32 * w + 8 * g + 4 * kh;
+      if (row < 100) {
+        float4 v;
+        v.x = fmaxf(acc[nt][4 * g] + bias, 0.0f);
+        v.y = fmaxf(acc[nt][4 * g + 1] + bias, 0.0f);
+        v.z = fmaxf(acc[nt][4 * g + 2] + bias, 0.0f);
+        v.w = fmaxf(acc[nt][4 * g + 3] + bias, 0.0f);
+        *(float4*)(dst + co * 100 + row) = v;
+      }
     }
   }
-  __syncthreads();
-  float4* dst = (float4*)(h2out + h * 6400);
-  for (int k = t; k < 1600; k += 256) dst[k] = ((const float4*)h2s)[k];
   }
 }
 
