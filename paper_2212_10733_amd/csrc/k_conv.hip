@@ -26,6 +26,7 @@ namespace hcz {
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kCP1 = 40;   // LDS pitch (bfloat16) of a conv1 output cell (32 channels)
 constexpr int kCPD = 72;   // LDS pitch (bfloat16) of a decoder hidden cell (64 channels)
@@ -243,37 +244,52 @@ __global__ __launch_bounds__(256) void k_conv_fc(const float* h2, long long n, c
 // Decoder hidden layer: hd = bf16(relu(db[k] + sum_d zhat[h][d] dw[k][d])) as the FP32
 // chain over d = 0..15, for unit k = channel * 100 + position, stored position-major:
 // hd[h][position * 64 + channel] (the layout the decoder stages into LDS).  A workgroup
-// takes 256 consecutive stored units (one per thread, its dw row in registers) for 64
-// histograms, so its stores are contiguous.
-__global__ __launch_bounds__(256) void k_conv_hidden(ModelDev M, const uint8_t* codes, const float* centroids,
-                                                     int kcb, long long n, __bf16* hd) {
-  __shared__ float zs[64 * kLatent];
+// of 320 threads takes 1,280 consecutive stored units, four per thread (their dw rows in
+// registers, one 8-byte store per histogram), for 64 histograms; five workgroups cover
+// the 6,400 units.
+constexpr int kHidThreads = 320;
+__global__ __launch_bounds__(kHidThreads) void k_conv_hidden(ModelDev M, const uint8_t* codes,
+                                                             const float* centroids, int kcb, long long n,
+                                                             __bf16* hd) {
+  __shared__ __attribute__((aligned(16))) float zs[64 * kLatent];
   const int t = threadIdx.x;
   const long long h0 = (long long)blockIdx.y * 64;
-  for (int q = t; q < 64 * kLatent; q += 256) {
+  for (int q = t; q < 64 * kLatent; q += kHidThreads) {
     const long long hh = h0 + q / kLatent;
     const int d = q % kLatent;
     zs[q] = hh < n ? centroids[d * kcb + min((int)codes[hh * kLatent + d], kcb - 1)] : 0.0f;
   }
   __syncthreads();
-  const int ks = blockIdx.x * 256 + t;           // stored index: position * 64 + channel
-  if (ks >= 6400) return;
-  const int k = (ks & 63) * 100 + (ks >> 6);     // unit: channel * 100 + position
-  float wv[kLatent];
-  const f32x4* dw = (const f32x4*)(M.dw + (long long)k * kLatent);
+  const int ks0 = 4 * (blockIdx.x * kHidThreads + t);   // stored index of the first unit
+  float wv[4][kLatent], bv[4];
 #pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const f32x4 q4 = dw[u];
+  for (int j = 0; j < 4; ++j) {
+    const int ks = ks0 + j;
+    const int k = (ks & 63) * 100 + (ks >> 6);          // unit: channel * 100 + position
+    const f32x4* dw = (const f32x4*)(M.dw + (long long)k * kLatent);
 #pragma unroll
-    for (int e = 0; e < 4; ++e) wv[4 * u + e] = q4[e];
+    for (int u = 0; u < 4; ++u) {
+      const f32x4 q4 = dw[u];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) wv[j][4 * u + e] = q4[e];
+    }
+    bv[j] = M.db[k];
   }
-  const float b = M.db[k];
   const int m = (int)min((long long)64, n - h0);
   for (int r = 0; r < m; ++r) {
-    float s = b;
+    float s[4];
 #pragma unroll
-    for (int d = 0; d < kLatent; ++d) s = fmaf(zs[r * kLatent + d], wv[d], s);
-    hd[(h0 + r) * 6400 + ks] = (__bf16)fmaxf(s, 0.0f);
+    for (int j = 0; j < 4; ++j) s[j] = bv[j];
+#pragma unroll
+    for (int d = 0; d < kLatent; ++d) {
+      const float zd = zs[r * kLatent + d];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) s[j] = fmaf(zd, wv[j][d], s[j]);
+    }
+    bf16x4 o;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) o[j] = (__bf16)fmaxf(s[j], 0.0f);
+    *(bf16x4*)&hd[(h0 + r) * 6400 + ks0] = o;
   }
 }
 
@@ -503,7 +519,8 @@ hipError_t launch_conv_decode(const ModelDev& M, const uint8_t* codes, const flo
   __bf16* hd = (__bf16*)M.scratch;
   for (long long c0 = 0; c0 < H; c0 += kConvChunk) {
     const long long n = std::min((long long)kConvChunk, H - c0);
-    hipLaunchKernelGGL(k_conv_hidden, dim3(25, (unsigned)((n + 63) / 64)), dim3(256), 0, st, M,
+    static_assert(5 * kHidThreads * 4 == 6400, "the hidden layer's workgroups cover its units exactly");
+    hipLaunchKernelGGL(k_conv_hidden, dim3(5, (unsigned)((n + 63) / 64)), dim3(kHidThreads), 0, st, M,
                        codes + c0 * kLatent, centroids, 1 << bits, n, hd);
     hipLaunchKernelGGL(k_conv_dec, dim3((unsigned)std::min(n, (long long)kConvGrid)), dim3(256), 0, st, M,
                        (const __bf16*)hd, n, fhat + c0 * 1521);
