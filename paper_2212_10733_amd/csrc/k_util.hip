@@ -112,10 +112,19 @@ __global__ __launch_bounds__(256) void k_compact(const uint8_t* slots, long long
   if (h >= H) return;
   const uint64_t sz = sizes[h], off = offsets[h];
   if (sz == 0 || off + sz > capacity) return;
-  const uint32_t* src = (const uint32_t*)(slots + h * slot_stride);
-  uint32_t* dst = (uint32_t*)(out + off);
+  const uint32_t* __restrict__ src = (const uint32_t*)(slots + h * slot_stride);
+  uint32_t* __restrict__ dst = (uint32_t*)(out + off);
   const uint64_t nw = sz >> 2;
-  for (uint64_t k = l; k < nw; k += 64) dst[k] = src[k];
+  // four words per lane in flight at a time (slot and stream never overlap)
+  uint64_t k = l;
+  for (; k + 192 < nw; k += 256) {
+    const uint32_t a = src[k], b = src[k + 64], c = src[k + 128], d = src[k + 192];
+    dst[k] = a;
+    dst[k + 64] = b;
+    dst[k + 128] = c;
+    dst[k + 192] = d;
+  }
+  for (; k < nw; k += 64) dst[k] = src[k];
 }
 
 hipError_t launch_compact(const uint8_t* slots, long long slot_stride, const uint64_t* offsets,
