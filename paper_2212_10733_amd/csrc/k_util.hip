@@ -115,16 +115,17 @@ __global__ __launch_bounds__(256) void k_compact(const uint8_t* slots, long long
   const uint32_t* __restrict__ src = (const uint32_t*)(slots + h * slot_stride);
   uint32_t* __restrict__ dst = (uint32_t*)(out + off);
   const uint64_t nw = sz >> 2;
-  // four words per lane in flight at a time (slot and stream never overlap)
-  uint64_t k = l;
-  for (; k + 192 < nw; k += 256) {
-    const uint32_t a = src[k], b = src[k + 64], c = src[k + 128], d = src[k + 192];
-    dst[k] = a;
-    dst[k + 64] = b;
-    dst[k + 128] = c;
-    dst[k + 192] = d;
+  // eight words per lane in flight at a time: the loads are clamped to the record's last
+  // word so that all of them issue together, the stores past the end are skipped (slot
+  // and stream never overlap)
+  for (uint64_t k0 = l; k0 < nw; k0 += 512) {
+    uint32_t v[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = src[min(k0 + 64 * j, nw - 1)];
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      if (k0 + 64 * j < nw) dst[k0 + 64 * j] = v[j];
   }
-  for (; k < nw; k += 64) dst[k] = src[k];
 }
 
 hipError_t launch_compact(const uint8_t* slots, long long slot_stride, const uint64_t* offsets,
