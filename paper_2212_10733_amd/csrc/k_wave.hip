@@ -488,33 +488,48 @@ __device__ __forceinline__ int newton_w(const GridDev& G, const WaveLds& L, cons
 
 // ---- compression ------------------------------------------------------------------------
 
-// One histogram's column for this lane, loaded ahead of its use (fixed shapes).
+// This lane's cells of one histogram, loaded ahead of their use (fixed shapes): an 8 x 8
+// grid of lane blocks, lane (bx, by) = (l % 8, l / 8) holding columns BX bx .. + BX - 1
+// and rows BY by .. + BY - 1 (39 x 39: 5 x 5 cells), cell (ci, cj) at index cj BX + ci.
+template <class SH>
+struct LaneBlock {
+  static constexpr int BX = SH::fixed ? (SH::NP + 7) / 8 : 1, BY = SH::fixed ? (SH::NQ + 7) / 8 : 1;
+};
 template <typename TIn, class SH>
 struct PreRows {
-  TIn f[SH::fixed ? SH::NQ : 1];
-  float h[SH::fixed ? SH::NQ : 1];
+  TIn f[LaneBlock<SH>::BX * LaneBlock<SH>::BY];
+  float h[LaneBlock<SH>::BX * LaneBlock<SH>::BY];
 };
-// Every lane loads, clamped to a valid histogram and column (the extra values are unused).
+// Every lane loads every cell of its block, clamped to a valid histogram, column and row
+// (the extra values are unused).
 template <typename TIn, class SH>
 __device__ __forceinline__ void pre_load(PreRows<TIn, SH>& P, const GridDev& G, const ResidualArgs& a, long long h) {
-  const int i = min(threadIdx.x & 63, SH::NP - 1);
+  constexpr int BX = LaneBlock<SH>::BX, BY = LaneBlock<SH>::BY;
+  const int lane = threadIdx.x & 63;
+  const int i0 = (lane & 7) * BX, j0 = (lane >> 3) * BY;
   const long long hc = min(h, a.H - 1);
   const TIn* f = (const TIn*)a.hist + hc * a.hs;
 #pragma unroll
-  for (int j = 0; j < SH::NQ; ++j) P.f[j] = f[(long long)j * a.rs + i];
+  for (int cj = 0; cj < BY; ++cj)
+#pragma unroll
+    for (int ci = 0; ci < BX; ++ci)
+      P.f[cj * BX + ci] = f[(long long)min(j0 + cj, SH::NQ - 1) * a.rs + min(i0 + ci, SH::NP - 1)];
   if (a.fhat) {
     const float* fhp = a.fhat + hc * (long long)G.N;
 #pragma unroll
-    for (int j = 0; j < SH::NQ; ++j) P.h[j] = fhp[j * SH::NP + i];
+    for (int cj = 0; cj < BY; ++cj)
+#pragma unroll
+      for (int ci = 0; ci < BX; ++ci)
+        P.h[cj * BX + ci] = fhp[min(j0 + cj, SH::NQ - 1) * SH::NP + min(i0 + ci, SH::NP - 1)];
   } else {
 #pragma unroll
-    for (int j = 0; j < SH::NQ; ++j) P.h[j] = 0.0f;
+    for (int c = 0; c < BX * BY; ++c) P.h[c] = 0.0f;
   }
 }
 
 // Histogram h (< a.H) on this wave, with the grid's tables staged in LDS and, for a fixed
-// shape, the wave's column already loaded into P.  KL: the KL reading of Stage 5 first,
-// kept where it keeps the bound, the L2 projection elsewhere.
+// shape, the lane's block of cells already loaded into P.  KL: the KL reading of Stage 5
+// first, kept where it keeps the bound, the L2 projection elsewhere.
 template <typename TIn, bool UVOL, class SH, bool KL = false>
 __device__ __forceinline__ void residual_w_hist(const GridDev& G, const ResidualArgs& a, const WaveLds& L,
                                                 long long h, const PreRows<TIn, SH>& P) {
@@ -566,10 +581,22 @@ __device__ __forceinline__ void residual_w_hist(const GridDev& G, const Residual
       m3 = fma(av * av, sf, m3);
     };
     if constexpr (SH::fixed) {
-      if (lane < SH::NP) {
+      // the lane's block, folding per column
+      constexpr int BX = LaneBlock<SH>::BX, BY = LaneBlock<SH>::BY;
+      static_assert(8 * BX >= SH::NP && 8 * BY >= SH::NQ, "the lane blocks cover the grid");
+      const int i0 = (lane & 7) * BX, j0 = (lane >> 3) * BY;
 #pragma unroll
-        for (int j = 0; j < SH::NQ; ++j) body(lane, j, (uint32_t)(j * SH::NP + lane) * 8u, FH{P.f[j], P.h[j]});
-        fold(lane);
+      for (int ci = 0; ci < BX; ++ci) {
+        const int i = i0 + ci;
+        if (i < SH::NP) {
+          sf = sfc = 0.0;
+#pragma unroll
+          for (int cj = 0; cj < BY; ++cj) {
+            const int j = j0 + cj;
+            if (j < SH::NQ) body(i, j, (uint32_t)(j * SH::NP + i) * 8u, FH{P.f[cj * BX + ci], P.h[cj * BX + ci]});
+          }
+          fold(i);
+        }
       }
     } else {
       for_columns_pre(G, [&](int) { sf = sfc = 0.0; }, load, body, fold);
@@ -889,7 +916,7 @@ __device__ __forceinline__ void residual_w_hist(const GridDev& G, const Residual
   }
 }
 
-// One wave per histogram.  With a fixed shape the wave's column of the histogram is
+// One wave per histogram.  With a fixed shape the wave's cells of the histogram are
 // loaded before the workgroup stages its tables, so both latencies overlap.
 template <typename TIn, bool UVOL, class SH, bool KL = false>
 __global__ __launch_bounds__(256, 2) void k_residual_w(GridDev G, ResidualArgs a) {
