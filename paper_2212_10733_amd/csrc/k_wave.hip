@@ -584,7 +584,11 @@ __device__ __forceinline__ void residual_w_hist(const GridDev& G, const Residual
       // the lane's block, folding per column
       constexpr int BX = LaneBlock<SH>::BX, BY = LaneBlock<SH>::BY;
       static_assert(8 * BX >= SH::NP && 8 * BY >= SH::NQ, "the lane blocks cover the grid");
-      const int i0 = (lane & 7) * BX, j0 = (lane >> 3) * BY;
+      // the block origin from a lane index the compiler cannot see through, so that it is
+      // not kept live until the Newton pass forms the same one
+      int lb = lane;
+      asm volatile("" : "+v"(lb));
+      const int i0 = (lb & 7) * BX, j0 = (lb >> 3) * BY;
 #pragma unroll
       for (int ci = 0; ci < BX; ++ci) {
         const int i = i0 + ci;
