@@ -41,7 +41,7 @@ def residual_flops(N: int, H: int, coded: int, steps_per_coded: float, newton_pa
     return per_cell * N
 
 
-def residual_flops_survey(N: int, H: int, coded: int, probes_per_coded: float, passes: float,
+def residual_flops_method(N: int, H: int, coded: int, probes_per_coded: float, passes: float,
                           hessians: float) -> float:
     """FP64 operations of the residual stage as the method's algorithmic count gives them
     (FMA = 2 operations), per grid cell: the four moments, 4 FMA; each Newton pass, 8 FMA
@@ -710,7 +710,7 @@ def other_forms(hcz, plan, ctx, x, F, W, args, plain_value, plain_stats) -> dict
     if "learned" in args.forms:
         log(f"form: learned, dense (train {args.epochs} epochs on {args.train_hist})")
         out["learned"] = learned_form(hcz, plan, ctx, W, args, "dense", plain_value, plain_stats, H)
-    if "c4" in args.forms:
+    if "learned_conv" in args.forms:
         log(f"form: learned, convolutional BF16 (train {args.epochs} epochs on {args.train_hist})")
         out["learned_conv"] = learned_form(hcz, plan, ctx, synth.conv_ae_weights(), args, "conv", plain_value,
                                            plain_stats, H)
@@ -725,8 +725,8 @@ def learned_form(hcz, plan, ctx, W0, args, arch, plain_value, plain_stats, H) ->
     (held-out seed) at tau = 1e-3 and 1e-2: the untrained model (its z-score statistics from
     the held-out batch), the trained model with cold, analytic-linear and network starts
     (Newton updates mean / p50 / p99 / max, QoI error, bound, p, ratio).  Dense: trained in
-    FP32 and, separately, in BF16 (evaluated in the BF16 form, the benchmark spec's HBM-target
-    form).  Convolutional: trained in BF16, evaluated in its BF16 form."""
+    FP32 and, separately, in BF16 (evaluated in the BF16 form, the form whose HBM rate is
+    reported as hbm_frac_bf16_dense_trained).  Convolutional: trained in BF16, evaluated in its BF16 form."""
     import torch
 
     from paper_2212_10733_amd import synth, train
@@ -808,14 +808,14 @@ def main() -> int:
                     help="histograms of the per-stage comparison of the precision forms with the FP64 model")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the coder-only and learned forms")
-    ap.add_argument("--forms", default="tau,ub,coder,stage5,container,bf16,conv,batched,incremental,learned,c4",
+    ap.add_argument("--forms", default="tau,ub,coder,stage5,container,bf16,conv,batched,incremental,learned,learned_conv",
                     help="comma list of the other forms to run: tau (sweep), coder (coder-only), "
                          "stage5 (FP32 multipliers, no positivity, KL correction), container (packed "
                          "output with and without rANS), ub (the coder step given, not searched), "
                          "bf16 (BF16 autoencoder), conv (convolutional BF16 autoencoder), "
                          "batched (uneven subdomains on four grids), "
                          "incremental (training series), learned (dense model trained in FP32 and "
-                         "BF16, held-out evaluation with cold / analytic / network starts), c4 (the "
+                         "BF16, held-out evaluation with cold / analytic / network starts), learned_conv (the "
                          "convolutional model trained in BF16, the same evaluation)")
     ap.add_argument("--train-hist", type=int, default=262144)
     ap.add_argument("--epochs", type=int, default=20)
@@ -823,6 +823,7 @@ def main() -> int:
                     help="only run a plain device-to-device copy of MIB MiB three times (the "
                          "reference kernel for scaling HBM byte counters), then exit")
     args = ap.parse_args()
+    args.forms = {f.strip() for f in args.forms.split(",") if f.strip()}
     if args.copy_calibration:
         import torch
         n = args.copy_calibration << 20
@@ -885,11 +886,11 @@ def main() -> int:
     steps_coded = search_steps(st["kstar_hist"])
     passes = st["newton_iters_total"] + (H - st["n_raw"])
     ae_flops = 2.0 * H * N * 128 + 2.0 * H * 128 * 16
-    survey_flops = residual_flops_survey(N, H, coded, steps_coded, passes, st["newton_iters_total"])
+    method_flops = residual_flops_method(N, H, coded, steps_coded, passes, st["newton_iters_total"])
     cands = {
         "encode": ("mfma", ae_flops / 1e12, PEAK_FP32_MFMA_TFLOPS, "TFLOP/s"),
         "decode": ("mfma", ae_flops / 1e12, PEAK_FP32_MFMA_TFLOPS, "TFLOP/s"),
-        "residual": ("alu", survey_flops / 1e12, PEAK_FP64_VALU_TFLOPS, "TFLOP/s"),
+        "residual": ("alu", method_flops / 1e12, PEAK_FP64_VALU_TFLOPS, "TFLOP/s"),
     }
     dom = max(cands, key=lambda k: stage_ms.get(k, 0.0))
     bound, work, peak, unit = cands[dom]
@@ -904,7 +905,7 @@ def main() -> int:
         "stage_roofline": {k: {"bound": c[0], "achieved": c[1] / (stage_ms[k] / 1e3), "peak": c[2],
                                "frac": c[1] / (stage_ms[k] / 1e3) / c[2]} for k, c in cands.items() if k in stage_ms},
         "residual_flop_counts": {
-            "method_count_per_cell": survey_flops / (H * N), "kernel_count_per_cell": kernel_flops / (H * N),
+            "method_count_per_cell": method_flops / (H * N), "kernel_count_per_cell": kernel_flops / (H * N),
             "kernel_count_frac": kernel_flops / (stage_ms["residual"] / 1e3) / 1e12 / PEAK_FP64_VALU_TFLOPS,
             "search_probes_per_coded": steps_coded, "newton_passes": passes,
             "hbm_alg_bytes": H * (4 * N + 16 + 32 + 1 + 8) + stream_bytes,
@@ -986,7 +987,7 @@ def main() -> int:
 
     lf = forms.get("learned", {}).get(f"tau_{args.tau:g}", {}).get("bf16_trained_bf16_form")
     if lf:
-        # the benchmark spec's HBM-target form: the BF16-trained dense model in its BF16 form,
+        # the HBM rate of the BF16-trained dense model in its BF16 form,
         # on the held-out batch, algorithmic bytes (f read once, outputs, stream) per step
         extra["hbm_frac_bf16_dense_trained"] = {"value": lf["value"], "hbm_frac": lf["hbm_frac"],
                                                 "GB/s": lf["hbm_frac"] * PEAK_HBM_GBS}
