@@ -123,6 +123,32 @@ def test_compress_without_model_bit_exact(H, ctx):
     check_roundtrip(F, out, comp.flags.cpu().numpy(), 1e-3, g)
 
 
+def test_verbatim_records_bit_exact(H, ctx):
+    """FP64 input with verbatim records mixed in (non-finite cells, empty histograms): the
+    12,168-byte records go through the stream compaction several 2,048-byte passes at a
+    time, and the stream, offsets and flags are the oracle's byte for byte; decompression
+    returns the verbatim histograms bit for bit."""
+    say("e2e verbatim records")
+    g = grid.make_grid()
+    n = 300
+    F = synth.histograms(n, seed=47, dtype=np.float64)
+    F[::7, 3, 5] = np.inf
+    F[1::11, 20, 2] = np.nan
+    F[5::13] = 0.0
+    plan = H.Plan(ctx)
+    cz = H.Compressor(plan, None, n, H.params(tau=1e-3), in_dtype=torch.float64)
+    comp = cz.compress(torch.from_numpy(F).cuda())
+    ref = pipeline.compress(F, g, None, None, pipeline.Params(tau=1e-3))
+    raw = (ref["flags"] & 4) != 0
+    assert raw.sum() >= 60
+    assert comp.stream_bytes() == ref["stream"]
+    assert np.array_equal(comp.offsets.cpu().numpy().astype(np.uint64), ref["offsets"])
+    assert np.array_equal(comp.flags.cpu().numpy(), ref["flags"])
+    out = cz.decompress(comp, n).cpu().numpy()
+    assert out[raw].tobytes() == F[raw].tobytes()
+    check_roundtrip(F[~raw], out[~raw], comp.flags.cpu().numpy()[~raw], 1e-3, g)
+
+
 @pytest.mark.parametrize("lambda_fp32,no_positivity", [(True, False), (False, True)])
 def test_stage5_variants_end_to_end(H, ctx, lambda_fp32, no_positivity):
     """Compress and decompress with FP32 multipliers or without positivity: the stream is
