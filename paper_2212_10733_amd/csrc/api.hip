@@ -784,12 +784,11 @@ hcz_status hcz_model_load(hcz_plan* plan, const hcz_model_desc* d, hcz_model** o
   std::vector<float> vb1(b1, b1 + Hd), vW2(W2, W2 + Ld * Hd), vb2(b2, b2 + Ld), vW3(W3, W3 + Hd * Ld),
       vb3(b3, b3 + Hd), vb4(b4, b4 + N);
   if (M.bf16) {
-    // BF16 form: W1 and W4 rounded to nearest-even bfloat16, natural k order
-    std::vector<uint16_t> W1b((size_t)Hd * kpad, 0), W4b((size_t)npad * Hd, 0);
+    // BF16 form: W1 rounded to nearest-even bfloat16 in natural k order (the strided
+    // encoder), and W1 and W4 in matrix-core operand order
+    std::vector<uint16_t> W1b((size_t)Hd * kpad, 0);
     for (int r = 0; r < Hd; ++r)
       for (int k = 0; k < N; ++k) W1b[(size_t)r * kpad + k] = bf16_rne(W1[(size_t)r * N + k]);
-    for (int c = 0; c < N; ++c)
-      for (int k = 0; k < Hd; ++k) W4b[(size_t)c * Hd + k] = bf16_rne(W4[(size_t)c * Hd + k]);
     // operand order of the encoder: [k-step t][column tile n][lane l][8]: column 32 n + l % 32,
     // k = 16 t + 8 (l / 32) + e; zero beyond N
     std::vector<uint16_t> W1m((size_t)(kpad / 16) * 4 * 64 * 8, 0);
@@ -812,8 +811,8 @@ hcz_status hcz_model_load(hcz_plan* plan, const hcz_model_desc* d, hcz_model** o
               W4m[((((size_t)b * 2 + n) * 8 + tt) * 64 + l) * 8 + e] =
                   col < N ? bf16_rne(W4[(size_t)col * Hd + k]) : 0;
             }
-    if ((s = upload(m->allocs, W1b, &M.W1b)) || (s = upload(m->allocs, W4b, &M.W4b)) ||
-        (s = upload(m->allocs, W1m, &M.W1m)) || (s = upload(m->allocs, W4m, &M.W4m))) {
+    if ((s = upload(m->allocs, W1b, &M.W1b)) || (s = upload(m->allocs, W1m, &M.W1m)) ||
+        (s = upload(m->allocs, W4m, &M.W4m))) {
       free_all(m->allocs);
       delete m;
       return s;

@@ -87,9 +87,8 @@ struct ModelDev {
   const float* rsd;                // [N] 1 / sigma (encoder side)
   const float* sd;                 // [N] sigma (decoder side)
   int npad;
-  int bf16;                        // 1: the BF16 form (W1b, W4b below)
+  int bf16;                        // 1: the BF16 form (W1b, W1m, W4m below)
   const uint16_t* W1b;             // [hidden][kpad] bfloat16 of W1, zero padded
-  const uint16_t* W4b;             // [npad][hidden] bfloat16 of W4, rows >= N zero
   const uint16_t* W1m;             // bfloat16 of W1 in matrix-core operand order (see k_encode_b2)
   const uint16_t* W4m;             // bfloat16 of W4 in matrix-core operand order (see k_decode_b2)
   int fp64;                        // 1: the FP64 form (the FP64 copies below)

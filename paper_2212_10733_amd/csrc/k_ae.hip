@@ -690,101 +690,11 @@ __global__ __launch_bounds__(256, 2) void k_encode_b2(ModelDev M, const float* h
   }
 }
 
-// Decoder of the BF16 form: H3 in LDS as bfloat16 rows in natural k order, W4 as
-// bfloat16 [npad][hidden] in device memory; K = 128 in two halves of four instructions,
-// the next half's weights loaded while the current half is multiplied.
-__global__ __launch_bounds__(256, 2) void k_decode_b(ModelDev M, const uint8_t* codes,
-                                                     const float* centroids, int kcb, long long H,
-                                                     float* fhat) {
-  __shared__ __attribute__((aligned(16))) __bf16 H3[kTile * kBPitch];
-  __shared__ float Zh[kTile * kLatent];
-  const int t = threadIdx.x, w = t >> 6, l = t & 63;
-  const long long h0 = (long long)blockIdx.x * kTile;
-  const int li = l & 31, kh = l >> 5;
-  for (int q = t; q < kTile * kLatent; q += 256) {
-    const int row = q / kLatent, d = q % kLatent;
-    const long long h = h0 + row;
-    Zh[q] = (h < H) ? centroids[d * kcb + min((int)codes[h * kLatent + d], kcb - 1)] : 0.0f;
-  }
-  __syncthreads();
-  {
-    const int c = t & 127;
-    float w3[kLatent];
-#pragma unroll
-    for (int d = 0; d < kLatent; ++d) w3[d] = M.W3[c * kLatent + d];
-    const float b3 = M.b3[c];
-    for (int row = t >> 7; row < kTile; row += 2) {
-      float s = b3;
-#pragma unroll
-      for (int d = 0; d < kLatent; ++d) s = fmaf(Zh[row * kLatent + d], w3[d], s);
-      H3[row * kBPitch + c] = (__bf16)fmaxf(s, 0.0f);
-    }
-  }
-  __syncthreads();
-  const int wr = (w >> 1) * 64;
-  const __bf16* W4b = (const __bf16*)M.W4b;
-  bf16x8 bv[2][4], bn[2][4];
-  auto bload = [&](int nb, int half, bf16x8 (&B)[2][4]) {
-    const int wc = nb + (w & 1) * 64;
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const __bf16* pb = W4b + (long long)(wc + q * 32 + li) * kHidden + half * 64 + kh * 8;
-#pragma unroll
-      for (int s = 0; s < 4; ++s) B[q][s] = *(const bf16x8*)(pb + 16 * s);
-    }
-  };
-  bload(0, 0, bv);
-  for (int nb = 0; nb < M.npad; nb += 128) {
-    const int wc = nb + (w & 1) * 64;
-    f32x16 acc[2][2];
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-      for (int b = 0; b < 2; ++b)
-#pragma unroll
-        for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.0f;
-#pragma unroll 1
-    for (int half = 0; half < 2; ++half) {
-      if (half == 0) bload(nb, 1, bn);
-      else if (nb + 128 < M.npad) bload(nb + 128, 0, bn);
-#pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        bf16x8 av[2];
-#pragma unroll
-        for (int q = 0; q < 2; ++q)
-          av[q] = *(const bf16x8*)&H3[(wr + q * 32 + li) * kBPitch + half * 64 + 16 * s + kh * 8];
-#pragma unroll
-        for (int a = 0; a < 2; ++a)
-#pragma unroll
-          for (int b = 0; b < 2; ++b) acc[a][b] = mfma_bf16(av[a], bv[b][s], acc[a][b]);
-      }
-#pragma unroll
-      for (int q = 0; q < 2; ++q)
-#pragma unroll
-        for (int s = 0; s < 4; ++s) bv[q][s] = bn[q][s];
-    }
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-      for (int b = 0; b < 2; ++b) {
-        const int col = wc + b * 32 + li;
-        if (col >= M.N) continue;
-        const float b4 = M.b4[col], sd = M.sd[col], mu = M.mu[col];
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const int row = wr + a * 32 + 8 * (r >> 2) + 4 * kh + (r & 3);
-          const long long h = h0 + row;
-          if (h < H) fhat[h * M.N + col] = fmaf(sd, acc[a][b][r] + b4, mu);
-        }
-      }
-  }
-}
-
-// BF16 decoder with row-contiguous stores: each wave owns 32 histograms and keeps their
-// eight bfloat16 h3 operands in registers; per block of 64 output columns the weights come
-// pre-arranged in operand order (W4m, 1 KB per load instruction, the next block in flight)
-// and the results pass through a wave-private LDS tile so that each store instruction
-// writes four 256-byte row segments.
+// Decoder of the BF16 form, with row-contiguous stores: each wave owns 32 histograms and
+// keeps their eight bfloat16 h3 operands in registers; per block of 64 output columns the
+// weights come pre-arranged in operand order (W4m, 1 KB per load instruction, the next
+// block in flight) and the results pass through a wave-private LDS tile so that each
+// store instruction writes four 256-byte row segments.
 constexpr int kOP = 68;   // LDS pitch (floats) of the output tile
 __global__ __launch_bounds__(256, 2) void k_decode_b2(ModelDev M, const uint8_t* codes, const float* centroids,
                                                       int kcb, long long H, float* fhat) {
