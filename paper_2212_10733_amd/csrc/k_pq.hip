@@ -81,44 +81,64 @@ __global__ __launch_bounds__(256) void k_sort_global(float* keys, long long np2,
   b[p] = c;
 }
 
-// Exclusive FP64 prefix sums of the first ns sorted keys of each dimension.
-__global__ __launch_bounds__(1024) void k_prefix(const float* keys, long long np2, long long ns,
-                                                 double* prefix) {
+// Exclusive FP64 prefix sums of the first ns sorted keys of each dimension, in two
+// passes over chunks of 1,024 keys.  k_prefix_local: each chunk's exclusive prefix sums
+// (waves by shuffles, then the chunk's 16 wave totals in order) and the chunk total;
+// k_prefix_add: each chunk adds the totals of the chunks before it, summed in order.
+__global__ __launch_bounds__(1024) void k_prefix_local(const float* keys, long long np2, long long ns,
+                                                       double* prefix, double* totals) {
   __shared__ double sw[16];
-  const int d = blockIdx.x, t = threadIdx.x, w = t >> 6, l = t & 63;
-  const float* kk = keys + (long long)d * np2;
-  double* pf = prefix + (long long)d * (ns + 1);
-  double carry = 0.0;
-  for (long long b0 = 0; b0 < ns; b0 += 1024) {
-    const long long i = b0 + t;
-    const double x = i < ns ? (double)kk[i] : 0.0;
-    double v = x;
+  const int b = blockIdx.x, d = blockIdx.y, t = threadIdx.x, w = t >> 6, l = t & 63;
+  const long long i = (long long)b * 1024 + t;
+  const double x = i < ns ? (double)keys[(long long)d * np2 + i] : 0.0;
+  double v = x;
 #pragma unroll
-    for (int k = 1; k < 64; k <<= 1) {
-      const double o = __shfl_up(v, k, 64);
-      if (l >= k) v = v + o;
-    }
-    if (l == 63) sw[w] = v;
-    __syncthreads();
-    double before = carry;
-    for (int q = 0; q < w; ++q) before = before + sw[q];
-    if (i < ns) pf[i] = before + (v - x);
-    double tot = carry;
-    for (int q = 0; q < 16; ++q) tot = tot + sw[q];
-    __syncthreads();
-    carry = tot;
+  for (int k = 1; k < 64; k <<= 1) {
+    const double o = __shfl_up(v, k, 64);
+    if (l >= k) v = v + o;
   }
-  if (t == 0) pf[ns] = carry;
+  if (l == 63) sw[w] = v;
+  __syncthreads();
+  double before = 0.0;
+  for (int q = 0; q < w; ++q) before = before + sw[q];
+  if (i < ns) prefix[(long long)d * (ns + 1) + i] = before + (v - x);
+  if (t == 1023) totals[(long long)d * gridDim.x + b] = before + v;
 }
 
-// Lloyd iterations of one dimension; thread c owns centroid c.
+__global__ __launch_bounds__(1024) void k_prefix_add(long long ns, double* prefix, const double* totals) {
+  __shared__ double off_s;
+  const int b = blockIdx.x, d = blockIdx.y, t = threadIdx.x;
+  const double* tot = totals + (long long)d * gridDim.x;
+  if (t == 0) {
+    double o = 0.0;
+    for (int q = 0; q < b; ++q) o = o + tot[q];
+    off_s = o;
+  }
+  __syncthreads();
+  const double off = off_s;
+  const long long i = (long long)b * 1024 + t;
+  double* pf = prefix + (long long)d * (ns + 1);
+  if (i < ns) pf[i] = off + pf[i];
+  if (b == (int)gridDim.x - 1 && t == 0) pf[ns] = off + tot[b];
+}
+
+// Lloyd iterations of one dimension; thread c owns centroid c.  Every stride-th sorted key
+// sits in LDS (at most kLloydSamples of them), so each run boundary's binary search takes
+// its first steps there and only the last log2(stride) in memory; the count it finds is
+// the one a search over all keys finds.
+constexpr int kLloydSamples = 8192;
 __global__ __launch_bounds__(256) void k_lloyd(const float* keys, long long np2, long long ns,
                                                const double* prefix, int kcb, float* centroids) {
   __shared__ double C[256];
   __shared__ long long ends[256];
+  __shared__ float smp[kLloydSamples];
   const int d = blockIdx.x, c = threadIdx.x;
   const float* kk = keys + (long long)d * np2;
   const double* pf = prefix + (long long)d * (ns + 1);
+  long long stride = 1;
+  while ((ns + stride - 1) / stride > kLloydSamples) stride <<= 1;
+  const int nsmp = (int)((ns + stride - 1) / stride);      // samples kk[q stride], q < nsmp
+  for (int q = c; q < nsmp; q += 256) smp[q] = kk[(long long)q * stride];
   if (c < kcb) {
     const long long idx = ((long long)(2 * c + 1) * ns) / (2LL * kcb);
     C[c] = (double)kk[idx];
@@ -130,7 +150,16 @@ __global__ __launch_bounds__(256) void k_lloyd(const float* keys, long long np2,
     long long e = ns;
     if (c < kcb - 1) {
       const double beta = (C[c] + C[c + 1]) * 0.5;
-      long long lo = 0, hi = ns;
+      // q = #{samples <= beta}: key (q - 1) stride is <= beta and key q stride (if any) is
+      // not, so the count lies in ((q - 1) stride, q stride]
+      int qlo = 0, qhi = nsmp;
+      while (qlo < qhi) {
+        const int mid = (qlo + qhi) >> 1;
+        if ((double)smp[mid] <= beta) qlo = mid + 1;
+        else qhi = mid;
+      }
+      long long lo = qlo == 0 ? 0 : (long long)(qlo - 1) * stride + 1;
+      long long hi = min((long long)qlo * stride, ns);
       while (lo < hi) {
         const long long mid = (lo + hi) >> 1;
         if ((double)kk[mid] <= beta) lo = mid + 1;
@@ -153,18 +182,25 @@ __global__ __launch_bounds__(256) void k_lloyd(const float* keys, long long np2,
   if (c < kcb) centroids[(long long)d * kcb + c] = (float)C[c];
 }
 
+// Workspace: the keys [latent][np2] (FP32), the prefix sums [latent][ns + 1] and the chunk
+// totals [latent][ceil(ns / 1024)] (FP64), each part 256-byte aligned.
+static size_t align_up256(size_t x) { return (x + 255) / 256 * 256; }
 size_t codebook_ws_bytes(long long n, int latent, long long every) {
   const long long ns = (n + every - 1) / every;
   const long long np2 = std::max<long long>(next_pow2(ns), 2);
-  return (size_t)latent * np2 * 4 + (size_t)latent * (ns + 1) * 8 + 256;
+  const long long nch = (ns + 1023) / 1024;
+  return align_up256((size_t)latent * np2 * 4) + align_up256((size_t)latent * (ns + 1) * 8) +
+         (size_t)latent * nch * 8;
 }
 
 hipError_t launch_codebook_fit(const float* z, long long n, int latent, long long every, int bits,
                                float* centroids, void* ws, hipStream_t st) {
   const long long ns = (n + every - 1) / every;
   const long long np2 = std::max<long long>(next_pow2(ns), 2);
+  const long long nch = (ns + 1023) / 1024;
   float* keys = (float*)ws;
-  double* prefix = (double*)((uint8_t*)ws + (((size_t)latent * np2 * 4 + 255) / 256) * 256);
+  double* prefix = (double*)((uint8_t*)ws + align_up256((size_t)latent * np2 * 4));
+  double* totals = (double*)((uint8_t*)prefix + align_up256((size_t)latent * (ns + 1) * 8));
   hipLaunchKernelGGL(k_gather, dim3((unsigned)((np2 + 255) / 256), latent), dim3(256), 0, st, z, n,
                      latent, every, ns, np2, keys);
   const int chunk = (int)std::min<long long>(np2, kSortChunk);
@@ -176,7 +212,8 @@ hipError_t launch_codebook_fit(const float* z, long long n, int latent, long lon
                          keys, np2, k, j);
     hipLaunchKernelGGL(k_sort_local, lgrid, dim3(kSortNT), 0, st, keys, np2, chunk, k, k);
   }
-  hipLaunchKernelGGL(k_prefix, dim3(latent), dim3(1024), 0, st, keys, np2, ns, prefix);
+  hipLaunchKernelGGL(k_prefix_local, dim3((unsigned)nch, latent), dim3(1024), 0, st, keys, np2, ns, prefix, totals);
+  hipLaunchKernelGGL(k_prefix_add, dim3((unsigned)nch, latent), dim3(1024), 0, st, ns, prefix, totals);
   hipLaunchKernelGGL(k_lloyd, dim3(latent), dim3(256), 0, st, keys, np2, ns, prefix, 1 << bits, centroids);
   return hipGetLastError();
 }
