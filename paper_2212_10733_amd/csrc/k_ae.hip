@@ -826,6 +826,39 @@ __global__ __launch_bounds__(256) void k_quantize(const float* z, long long n, i
   codes[q] = (uint8_t)lo;
 }
 
+// The same search over midpoints staged once per workgroup in LDS ([latent][kcb - 1] in
+// FP64, formed exactly as above), the workgroup striding over the latents.
+constexpr int kQuantLdsMax = 65536;   // bytes of staged midpoints this form takes
+__global__ __launch_bounds__(256) void k_quantize_lds(const float* z, long long n, int latent,
+                                                      const float* centroids, int kcb, uint8_t* codes) {
+  extern __shared__ double beta[];
+  const int nb = kcb - 1;
+  for (int q = threadIdx.x; q < latent * nb; q += 256) {
+    const int d = q / nb, c = q - d * nb;
+    const float* C = centroids + (long long)d * kcb;
+    beta[q] = ((double)C[c] + (double)C[c + 1]) * 0.5;
+  }
+  __syncthreads();
+  const long long tot = n * latent;
+  const long long stride = (long long)gridDim.x * 256;
+  long long q = (long long)blockIdx.x * 256 + threadIdx.x;
+  int d = (int)(q % latent);
+  const int dstep = (int)(stride % latent);
+  for (; q < tot; q += stride) {
+    const double* B = beta + d * nb;
+    const double zv = (double)z[q];
+    int lo = 0, hi = kcb - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (B[mid] < zv) lo = mid + 1;
+      else hi = mid;
+    }
+    codes[q] = (uint8_t)lo;
+    d += dstep;
+    if (d >= latent) d -= latent;
+  }
+}
+
 // ---- FP64 form: every layer in FP64 on the vector ALUs, one workgroup per histogram ----
 // Encoder: x = (f - mu) / sigma (non-finite inputs as 0) staged in LDS; thread c sums
 // W1[c][k] x_k over k = 0..N-1 with fused multiply-adds, h1_c = max(0, sum + b1_c);
@@ -929,8 +962,15 @@ hipError_t launch_quantize(const float* z, long long n, int latent, const float*
                            int bits, uint8_t* codes, hipStream_t st) {
   const long long tot = n * latent;
   if (tot <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_quantize, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, z, n, latent,
-                     centroids, 1 << bits, codes);
+  const int kcb = 1 << bits;
+  const size_t lds = (size_t)latent * (kcb - 1) * sizeof(double);
+  if (kcb > 1 && lds <= (size_t)kQuantLdsMax) {
+    const unsigned grid = (unsigned)std::min<long long>((tot + 255) / 256, 2048);
+    hipLaunchKernelGGL(k_quantize_lds, dim3(grid), dim3(256), lds, st, z, n, latent, centroids, kcb, codes);
+  } else {
+    hipLaunchKernelGGL(k_quantize, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, z, n, latent,
+                       centroids, kcb, codes);
+  }
   return hipGetLastError();
 }
 
