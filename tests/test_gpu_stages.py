@@ -60,11 +60,15 @@ def test_qoi_parity(H, ctx, dtype, shape, vol):
 
 # ---- quantizer -------------------------------------------------------------------------------
 
-def test_quantize_bit_exact(H, ctx):
-    say("quantize")
-    Z = synth.latents(5000, 16, seed=22)
-    C = synth.sorted_codebook(16, 8, seed=23)
-    C[3, 10] = C[3, 11]                      # duplicate centroid
+@pytest.mark.parametrize("latent,bits,n", [(16, 8, 5000), (40, 8, 3001), (7, 3, 1000)])
+def test_quantize_bit_exact(H, ctx, latent, bits, n):
+    """Codes equal the oracle's, exact midpoints, duplicates and non-finite latents
+    included; 40 x 255 midpoints exceed what the LDS-staged kernel takes, so that case
+    runs the search over the codebook in memory."""
+    say("quantize", latent, bits, n)
+    Z = synth.latents(n, latent, seed=22)
+    C = synth.sorted_codebook(latent, bits, seed=23)
+    C[3, 2] = C[3, 3]                        # duplicate centroid
     beta = (C[:, :-1].astype(np.float64) + C[:, 1:]) * 0.5
     exact = beta.astype(np.float32).astype(np.float64) == beta
     Z[:40, 5] = beta[5][exact[5]][:40].astype(np.float32) if exact[5].sum() >= 40 else Z[:40, 5]
