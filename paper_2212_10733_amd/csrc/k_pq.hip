@@ -51,15 +51,15 @@ __global__ __launch_bounds__(kSortNT) void k_sort_local(float* keys, long long n
     long long jstart = k >> 1;
     if (jstart >= chunk) jstart = chunk >> 1;
     for (long long j = jstart; j >= 1; j >>= 1) {
-      for (int i = threadIdx.x; i < chunk; i += kSortNT) {
-        const int p = i ^ (int)j;
-        if (p > i) {
-          const bool up = ((gbase + i) & k) == 0;
-          float a = s[i], b = s[p];
-          cswap(a, b, up);
-          s[i] = a;
-          s[p] = b;
-        }
+      // pair m joins keys i = 2 j (m / j) + m % j and i + j: every thread busy
+      const int jj = (int)j;
+      for (int m = threadIdx.x; m < chunk / 2; m += kSortNT) {
+        const int i = ((m & ~(jj - 1)) << 1) | (m & (jj - 1)), p = i + jj;
+        const bool up = ((gbase + i) & k) == 0;
+        float a = s[i], b = s[p];
+        cswap(a, b, up);
+        s[i] = a;
+        s[p] = b;
       }
       __syncthreads();
     }
